@@ -1,0 +1,787 @@
+/*
+ * mf_oracle.c -- plain FP64 CPU reference for the Q2 heat and linearized
+ * momentum operators of the diffuse-interface two-phase model.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg are the only users of this file.  It shares no
+ * source, header, table or helper with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * Everything is computed from its definition, not for speed:
+ *   - 1D Lagrange basis of degree 2 on the nodes {0, 1/2, 1} and its
+ *     derivative by the product formula; 3-point Gauss-Legendre rule
+ *     ((k+1) points per direction for k = 2, App. B "Numerical framework");
+ *   - every cell is mapped by a general trilinear map from its 8 vertices;
+ *     J, det J and J^{-1} are computed at every quadrature point;
+ *   - every basis function and every physical gradient is evaluated
+ *     explicitly at every quadrature point (no sum factorization);
+ *   - per-cell dense matrices by full 3x3x3 Gauss quadrature, assembled into
+ *     a global CSR matrix by summation.
+ * OpenMP is used only across cells that share no node (8-colouring by cell
+ * parity) and across matrix rows, which changes nothing but rounding order.
+ *
+ * Node numbering: Q2 node grid (2nx+1)(2ny+1)(2nz+1), id = i + NX*(j + NY*k).
+ * Vector unknowns are component-major: dof = comp * n_nodes + node.
+ * Quadrature points in a cell: q = qx + 3 qy + 9 qz; local nodes a + 3b + 9c.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    int32_t n[3];      /* cells per direction */
+    int32_t dirichlet; /* bit f: homogeneous Dirichlet on face f (x-,x+,y-,y+,z-,z+) */
+    double lo[3];
+    double hi[3];
+} orc_mesh;
+
+typedef struct {
+    int32_t heaviside; /* 0: H = clamp((1+phi)/2, 0, 1); 1: sine form of eq. heaviside */
+    int32_t pad_;
+    double eps;        /* interface thickness parameter (sine form) */
+    double alpha_m;    /* mass factor (1/dt for backward Euler) */
+    double alpha_k;    /* conduction factor (heat) */
+    double alpha_c;    /* convection factor (momentum) */
+    double alpha_v;    /* viscous factor (momentum) */
+    double k_l, k_g, rc_l, rc_g, rho_l, rho_g, mu_l, mu_g;
+} orc_coeffs;
+
+/* ------------------------------------------------------------------------ */
+/* Reference element                                                         */
+/* ------------------------------------------------------------------------ */
+
+static const double NODE1D[3] = {0.0, 0.5, 1.0};
+
+/* l_a(xi) = prod_{b != a} (xi - x_b) / (x_a - x_b) */
+static double lag1(int a, double xi)
+{
+    double v = 1.0;
+    for (int b = 0; b < 3; ++b)
+        if (b != a) v *= (xi - NODE1D[b]) / (NODE1D[a] - NODE1D[b]);
+    return v;
+}
+
+/* d l_a / d xi = sum_{m != a} 1/(x_a - x_m) prod_{b != a, m} (xi - x_b)/(x_a - x_b) */
+static double dlag1(int a, double xi)
+{
+    double s = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        if (m == a) continue;
+        double t = 1.0 / (NODE1D[a] - NODE1D[m]);
+        for (int b = 0; b < 3; ++b)
+            if (b != a && b != m) t *= (xi - NODE1D[b]) / (NODE1D[a] - NODE1D[b]);
+        s += t;
+    }
+    return s;
+}
+
+/* 3-point Gauss-Legendre rule on [-1,1] (roots 0, +-sqrt(3/5) of P3, weights
+ * 8/9 and 5/9) mapped affinely to [0,1]. */
+static void gauss3(double xi[3], double w[3])
+{
+    const double r = sqrt(0.6);
+    const double t[3] = {-r, 0.0, r};
+    const double wt[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    for (int i = 0; i < 3; ++i) {
+        xi[i] = 0.5 * (1.0 + t[i]);
+        w[i] = 0.5 * wt[i];
+    }
+}
+
+void orc_gauss3(double *xi, double *w) { gauss3(xi, w); }
+
+void orc_basis1d(double xi, double *val, double *der)
+{
+    for (int a = 0; a < 3; ++a) {
+        val[a] = lag1(a, xi);
+        der[a] = dlag1(a, xi);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry and per-quadrature-point data                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double N[27];     /* basis values */
+    double G[27][3];  /* physical gradients */
+    double W;         /* quadrature weight times |det J| */
+    double x[3];      /* physical position */
+} qp_data;
+
+/* Local shape data at reference point xi (3 coords) through the trilinear map
+ * defined by the 8 vertices X[v], v = vx + 2 vy + 4 vz. */
+static void eval_point(const double X[8][3], const double xi[3], qp_data *out, double wref)
+{
+    double J[3][3] = {{0}};
+    double pos[3] = {0, 0, 0};
+    for (int v = 0; v < 8; ++v) {
+        const int b[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
+        double L[3], dL[3];
+        for (int d = 0; d < 3; ++d) {
+            L[d] = b[d] ? xi[d] : 1.0 - xi[d];
+            dL[d] = b[d] ? 1.0 : -1.0;
+        }
+        const double Lv = L[0] * L[1] * L[2];
+        const double dLv[3] = {dL[0] * L[1] * L[2], L[0] * dL[1] * L[2], L[0] * L[1] * dL[2]};
+        for (int d = 0; d < 3; ++d) {
+            pos[d] += X[v][d] * Lv;
+            for (int k = 0; k < 3; ++k) J[d][k] += X[v][d] * dLv[k];
+        }
+    }
+    /* inverse by cofactors */
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                     - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                     + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double Ji[3][3];
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+
+    double l[3][3], dl[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int a = 0; a < 3; ++a) {
+            l[d][a] = lag1(a, xi[d]);
+            dl[d][a] = dlag1(a, xi[d]);
+        }
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                const int i = a + 3 * b + 9 * c;
+                out->N[i] = l[0][a] * l[1][b] * l[2][c];
+                const double gref[3] = {dl[0][a] * l[1][b] * l[2][c],
+                                        l[0][a] * dl[1][b] * l[2][c],
+                                        l[0][a] * l[1][b] * dl[2][c]};
+                /* grad N = J^{-T} grad_ref N : (grad N)_d = sum_k Ji[k][d] gref[k] */
+                for (int d = 0; d < 3; ++d)
+                    out->G[i][d] = Ji[0][d] * gref[0] + Ji[1][d] * gref[1] + Ji[2][d] * gref[2];
+            }
+    out->W = wref * fabs(det);
+    for (int d = 0; d < 3; ++d) out->x[d] = pos[d];
+}
+
+static void cell_qp(const double X[8][3], int q, qp_data *out)
+{
+    double xg[3], wg[3];
+    gauss3(xg, wg);
+    const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
+    const double xi[3] = {xg[qi[0]], xg[qi[1]], xg[qi[2]]};
+    eval_point(X, xi, out, wg[qi[0]] * wg[qi[1]] * wg[qi[2]]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh helpers                                                              */
+/* ------------------------------------------------------------------------ */
+
+static inline int64_t nnodes(const orc_mesh *m)
+{
+    return (int64_t)(2 * m->n[0] + 1) * (2 * m->n[1] + 1) * (2 * m->n[2] + 1);
+}
+
+static inline int64_t node_id(const orc_mesh *m, int i, int j, int k)
+{
+    return (int64_t)i + (int64_t)(2 * m->n[0] + 1) * ((int64_t)j + (int64_t)(2 * m->n[1] + 1) * k);
+}
+
+static void cell_vertices(const orc_mesh *m, int cx, int cy, int cz, double X[8][3])
+{
+    const int c[3] = {cx, cy, cz};
+    for (int v = 0; v < 8; ++v)
+        for (int d = 0; d < 3; ++d) {
+            const int b = (v >> d) & 1;
+            const double h = (m->hi[d] - m->lo[d]) / m->n[d];
+            X[v][d] = m->lo[d] + h * (c[d] + b);
+        }
+}
+
+static void cell_nodes(const orc_mesh *m, int cx, int cy, int cz, int64_t idx[27])
+{
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a)
+                idx[a + 3 * b + 9 * c] = node_id(m, 2 * cx + a, 2 * cy + b, 2 * cz + c);
+}
+
+static int node_constrained(const orc_mesh *m, int64_t id)
+{
+    const int NX = 2 * m->n[0] + 1, NY = 2 * m->n[1] + 1;
+    const int i = (int)(id % NX), j = (int)((id / NX) % NY), k = (int)(id / ((int64_t)NX * NY));
+    const int f = m->dirichlet;
+    return ((f & 1) && i == 0) || ((f & 2) && i == 2 * m->n[0]) ||
+           ((f & 4) && j == 0) || ((f & 8) && j == 2 * m->n[1]) ||
+           ((f & 16) && k == 0) || ((f & 32) && k == 2 * m->n[2]);
+}
+
+void orc_constrained_mask(const orc_mesh *m, uint8_t *mask)
+{
+    const int64_t n = nnodes(m);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) mask[i] = (uint8_t)node_constrained(m, i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coefficients (Sec. 2.3)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Smoothed Heaviside.  kind 0: H = clamp((1+phi)/2, 0, 1).  kind 1: eq.
+ * heaviside with the signed distance recovered from the tanh profile of eq.
+ * initial_phi, d = 2 eps artanh(phi).  Returns H and writes dH/dphi. */
+static double heaviside(int kind, double eps, double phi, double *dH)
+{
+    if (kind == 0) {
+        if (phi <= -1.0) { *dH = 0.0; return 0.0; }
+        if (phi >= 1.0) { *dH = 0.0; return 1.0; }
+        *dH = 0.5;
+        return 0.5 * (1.0 + phi);
+    }
+    const double lim = 1.0 - 1e-15;
+    const double p = phi < -lim ? -lim : (phi > lim ? lim : phi);
+    const double d = 2.0 * eps * atanh(p);
+    if (d <= -3.0 * eps) { *dH = 0.0; return 0.0; }
+    if (d >= 3.0 * eps) { *dH = 0.0; return 1.0; }
+    const double dH_dd = 1.0 / (6.0 * eps) + cos(M_PI * d / (3.0 * eps)) / (6.0 * eps);
+    const double dd_dphi = 2.0 * eps / (1.0 - p * p);
+    *dH = dH_dd * dd_dphi;
+    return 0.5 + d / (6.0 * eps) + sin(M_PI * d / (3.0 * eps)) / (2.0 * M_PI);
+}
+
+void orc_heaviside(int32_t kind, double eps, const double *phi, double *H, double *dH, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) H[i] = heaviside(kind, eps, phi[i], &dH[i]);
+}
+
+/* eq. muEff: arithmetic phase-fraction weighted average */
+static inline double blend_arith(double H, double a_l, double a_g) { return H * a_l + (1.0 - H) * a_g; }
+/* eq. rhoEff: reciprocal interpolation of the density */
+static inline double blend_recip(double H, double r_l, double r_g) { return 1.0 / (H / r_l + (1.0 - H) / r_g); }
+
+/* ------------------------------------------------------------------------ */
+/* Cell matrices                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Heat cell matrix, from the weak form of eq. heat_transfer (without the
+ * convective term) after one backward-Euler step:
+ *   A_e[i][j] = sum_q W_q ( alpha_m rc_q N_i N_j + alpha_k k_q grad N_i . grad N_j ).
+ * Coefficients: from nodal phi (phi27 != NULL) through H and eq. muEff, or
+ * given per quadrature point (kq27, rcq27). */
+static void heat_cell_matrix(const double X[8][3], const orc_coeffs *cf, const double *phi27,
+                             const double *kq27, const double *rcq27, double *Ae)
+{
+    memset(Ae, 0, sizeof(double) * 27 * 27);
+    qp_data Q;
+    for (int q = 0; q < 27; ++q) {
+        cell_qp(X, q, &Q);
+        double k, rc;
+        if (phi27) {
+            double phiq = 0.0, dH;
+            for (int j = 0; j < 27; ++j) phiq += Q.N[j] * phi27[j];
+            const double H = heaviside(cf->heaviside, cf->eps, phiq, &dH);
+            k = blend_arith(H, cf->k_l, cf->k_g);
+            rc = blend_arith(H, cf->rc_l, cf->rc_g);
+        } else {
+            k = kq27[q];
+            rc = rcq27[q];
+        }
+        const double cm = Q.W * cf->alpha_m * rc, ck = Q.W * cf->alpha_k * k;
+        for (int i = 0; i < 27; ++i)
+            for (int j = 0; j < 27; ++j)
+                Ae[i * 27 + j] += cm * Q.N[i] * Q.N[j] +
+                                  ck * (Q.G[i][0] * Q.G[j][0] + Q.G[i][1] * Q.G[j][1] + Q.G[i][2] * Q.G[j][2]);
+    }
+}
+
+void orc_heat_cell_matrix(const double *X24, const orc_coeffs *cf, const double *phi27,
+                          const double *kq27, const double *rcq27, double *Ae)
+{
+    double X[8][3];
+    memcpy(X, X24, sizeof(X));
+    heat_cell_matrix(X, cf, phi27, kq27, rcq27, Ae);
+}
+
+/* Linearized momentum cell matrix from eq. momentum_balance with the viscous
+ * stress 2 mu eps(u) (Sec. 2.1), backward Euler and the convective velocity
+ * frozen at u0 (Oseen form).  Local dof index c*27 + i:
+ *   A_e[(i,c),(j,c')] = sum_q W_q [ alpha_m rho N_i N_j d_cc'
+ *                                 + alpha_c rho N_i (u0_q . grad N_j) d_cc'
+ *                                 + alpha_v mu (grad N_i . grad N_j d_cc' + d_c' N_i d_c N_j) ]
+ * rho by the reciprocal blend of eq. rhoEff, mu by eq. muEff. */
+static void oseen_cell_matrix(const double X[8][3], const orc_coeffs *cf, const double *phi27,
+                              const double *u0_27x3, double *Ae)
+{
+    memset(Ae, 0, sizeof(double) * 81 * 81);
+    qp_data Q;
+    for (int q = 0; q < 27; ++q) {
+        cell_qp(X, q, &Q);
+        double phiq = 0.0, dH, u0q[3] = {0, 0, 0};
+        for (int j = 0; j < 27; ++j) {
+            phiq += Q.N[j] * phi27[j];
+            for (int c = 0; c < 3; ++c) u0q[c] += Q.N[j] * u0_27x3[c * 27 + j];
+        }
+        const double H = heaviside(cf->heaviside, cf->eps, phiq, &dH);
+        const double rho = blend_recip(H, cf->rho_l, cf->rho_g);
+        const double mu = blend_arith(H, cf->mu_l, cf->mu_g);
+        for (int i = 0; i < 27; ++i)
+            for (int j = 0; j < 27; ++j) {
+                const double mass = Q.N[i] * Q.N[j];
+                const double conv = Q.N[i] * (u0q[0] * Q.G[j][0] + u0q[1] * Q.G[j][1] + u0q[2] * Q.G[j][2]);
+                const double lap = Q.G[i][0] * Q.G[j][0] + Q.G[i][1] * Q.G[j][1] + Q.G[i][2] * Q.G[j][2];
+                const double diag = Q.W * (cf->alpha_m * rho * mass + cf->alpha_c * rho * conv + cf->alpha_v * mu * lap);
+                for (int c = 0; c < 3; ++c)
+                    for (int cp = 0; cp < 3; ++cp) {
+                        double v = Q.W * cf->alpha_v * mu * Q.G[i][cp] * Q.G[j][c];
+                        if (c == cp) v += diag;
+                        Ae[(c * 27 + i) * 81 + cp * 27 + j] += v;
+                    }
+            }
+    }
+}
+
+void orc_oseen_cell_matrix(const double *X24, const orc_coeffs *cf, const double *phi27,
+                           const double *u0_27x3, double *Ae)
+{
+    double X[8][3];
+    memcpy(X, X24, sizeof(X));
+    oseen_cell_matrix(X, cf, phi27, u0_27x3, Ae);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Global CSR pattern: row (c, i) couples to (c', j) for all components c'   */
+/* and all nodes j sharing a cell with node i.                               */
+/* ------------------------------------------------------------------------ */
+
+/* Range of node indices, along one direction, of the cells containing node t:
+ * cells c with 2c <= t <= 2c+2, clipped to [0, n-1]. */
+static void neighbor_range(int t, int n, int *lo, int *hi)
+{
+    int cmin = (t - 1) / 2; /* ceil((t-2)/2) for t >= 0 */
+    if (t < 2) cmin = 0;
+    int cmax = t / 2;
+    if (cmax > n - 1) cmax = n - 1;
+    *lo = 2 * cmin;
+    *hi = 2 * cmax + 2;
+}
+
+int64_t orc_csr_rowptr(const orc_mesh *m, int32_t ncomp, int64_t *rowptr)
+{
+    const int64_t nn = nnodes(m);
+    const int NX = 2 * m->n[0] + 1, NY = 2 * m->n[1] + 1;
+    rowptr[0] = 0;
+    for (int64_t r = 0; r < ncomp * nn; ++r) {
+        const int64_t id = r % nn;
+        const int i = (int)(id % NX), j = (int)((id / NX) % NY), k = (int)(id / ((int64_t)NX * NY));
+        int lo[3], hi[3];
+        neighbor_range(i, m->n[0], &lo[0], &hi[0]);
+        neighbor_range(j, m->n[1], &lo[1], &hi[1]);
+        neighbor_range(k, m->n[2], &lo[2], &hi[2]);
+        const int64_t len = (int64_t)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+        rowptr[r + 1] = rowptr[r] + ncomp * len;
+    }
+    return rowptr[ncomp * nn];
+}
+
+void orc_csr_cols(const orc_mesh *m, int32_t ncomp, const int64_t *rowptr, int32_t *cols)
+{
+    const int64_t nn = nnodes(m);
+    const int NX = 2 * m->n[0] + 1, NY = 2 * m->n[1] + 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < ncomp * nn; ++r) {
+        const int64_t id = r % nn;
+        const int i = (int)(id % NX), j = (int)((id / NX) % NY), k = (int)(id / ((int64_t)NX * NY));
+        int lo[3], hi[3];
+        neighbor_range(i, m->n[0], &lo[0], &hi[0]);
+        neighbor_range(j, m->n[1], &lo[1], &hi[1]);
+        neighbor_range(k, m->n[2], &lo[2], &hi[2]);
+        int64_t p = rowptr[r];
+        for (int c = 0; c < ncomp; ++c)
+            for (int kk = lo[2]; kk <= hi[2]; ++kk)
+                for (int jj = lo[1]; jj <= hi[1]; ++jj)
+                    for (int ii = lo[0]; ii <= hi[0]; ++ii)
+                        cols[p++] = (int32_t)(c * nn + node_id(m, ii, jj, kk));
+    }
+}
+
+static int64_t find_col(const int64_t *rowptr, const int32_t *cols, int64_t row, int32_t col)
+{
+    int64_t a = rowptr[row], b = rowptr[row + 1] - 1;
+    while (a <= b) {
+        const int64_t mid = (a + b) / 2;
+        if (cols[mid] == col) return mid;
+        if (cols[mid] < col) a = mid + 1; else b = mid - 1;
+    }
+    return -1;
+}
+
+/* Identity rows and removed columns for constrained dofs. */
+static void apply_dirichlet(const orc_mesh *m, int ncomp, const int64_t *rowptr, const int32_t *cols, double *vals)
+{
+    const int64_t nn = nnodes(m);
+    if (!m->dirichlet) return;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < ncomp * nn; ++r) {
+        const int rc = node_constrained(m, r % nn);
+        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+            if (rc) vals[p] = (cols[p] == r) ? 1.0 : 0.0;
+            else if (node_constrained(m, cols[p] % nn)) vals[p] = 0.0;
+        }
+    }
+}
+
+/* Assembly of the heat operator.  phi (nodal) or kq/rcq (per quadrature point,
+ * cell-major, 27 per cell) select how the coefficients are formed. */
+void orc_assemble_heat(const orc_mesh *m, const orc_coeffs *cf, const double *phi,
+                       const double *kq, const double *rcq,
+                       const int64_t *rowptr, const int32_t *cols, double *vals)
+{
+    const int64_t nnz = rowptr[nnodes(m)];
+    memset(vals, 0, sizeof(double) * nnz);
+    for (int color = 0; color < 8; ++color) {
+        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
+#pragma omp parallel for collapse(3) schedule(dynamic, 16)
+        for (int cz = pz; cz < m->n[2]; cz += 2)
+            for (int cy = py; cy < m->n[1]; cy += 2)
+                for (int cx = px; cx < m->n[0]; cx += 2) {
+                    double X[8][3], Ae[27 * 27], phi27[27];
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    if (phi) {
+                        for (int a = 0; a < 27; ++a) phi27[a] = phi[idx[a]];
+                        heat_cell_matrix(X, cf, phi27, NULL, NULL, Ae);
+                    } else {
+                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, Ae);
+                    }
+                    for (int i = 0; i < 27; ++i)
+                        for (int j = 0; j < 27; ++j) {
+                            const int64_t p = find_col(rowptr, cols, idx[i], (int32_t)idx[j]);
+                            vals[p] += Ae[i * 27 + j];
+                        }
+                }
+    }
+    apply_dirichlet(m, 1, rowptr, cols, vals);
+}
+
+void orc_assemble_oseen(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *u0,
+                        const int64_t *rowptr, const int32_t *cols, double *vals)
+{
+    const int64_t nn = nnodes(m);
+    const int64_t nnz = rowptr[3 * nn];
+    memset(vals, 0, sizeof(double) * nnz);
+    for (int color = 0; color < 8; ++color) {
+        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
+#pragma omp parallel for collapse(3) schedule(dynamic, 4)
+        for (int cz = pz; cz < m->n[2]; cz += 2)
+            for (int cy = py; cy < m->n[1]; cy += 2)
+                for (int cx = px; cx < m->n[0]; cx += 2) {
+                    double X[8][3], phi27[27], u27[81];
+                    double *Ae = (double *)malloc(sizeof(double) * 81 * 81);
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    for (int a = 0; a < 27; ++a) {
+                        phi27[a] = phi[idx[a]];
+                        for (int c = 0; c < 3; ++c) u27[c * 27 + a] = u0[c * nn + idx[a]];
+                    }
+                    oseen_cell_matrix(X, cf, phi27, u27, Ae);
+                    for (int c = 0; c < 3; ++c)
+                        for (int i = 0; i < 27; ++i)
+                            for (int cp = 0; cp < 3; ++cp)
+                                for (int j = 0; j < 27; ++j) {
+                                    const int64_t p = find_col(rowptr, cols, c * nn + idx[i], (int32_t)(cp * nn + idx[j]));
+                                    vals[p] += Ae[(c * 27 + i) * 81 + cp * 27 + j];
+                                }
+                    free(Ae);
+                }
+    }
+    apply_dirichlet(m, 3, rowptr, cols, vals);
+}
+
+/* y = A x */
+void orc_spmv(int64_t nrows, const int64_t *rowptr, const int32_t *cols, const double *vals,
+              const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        double s = 0.0;
+        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) s += vals[p] * x[cols[p]];
+        y[r] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Selected rows of y = A x, from cell matrices, without assembling A        */
+/* (for spot checks at sizes where the global matrix is too large).          */
+/* ------------------------------------------------------------------------ */
+
+static void cells_of_node(const orc_mesh *m, int64_t id, int clo[3], int chi[3])
+{
+    const int NX = 2 * m->n[0] + 1, NY = 2 * m->n[1] + 1;
+    const int t[3] = {(int)(id % NX), (int)((id / NX) % NY), (int)(id / ((int64_t)NX * NY))};
+    for (int d = 0; d < 3; ++d) {
+        int lo, hi;
+        neighbor_range(t[d], m->n[d], &lo, &hi);
+        clo[d] = lo / 2;
+        chi[d] = (hi - 2) / 2;
+    }
+}
+
+void orc_heat_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *kq,
+                   const double *rcq, const double *x, int64_t nrows, const int64_t *rows, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < nrows; ++s) {
+        const int64_t r = rows[s];
+        if (node_constrained(m, r)) { out[s] = x[r]; continue; }
+        int clo[3], chi[3];
+        cells_of_node(m, r, clo, chi);
+        double acc = 0.0;
+        for (int cz = clo[2]; cz <= chi[2]; ++cz)
+            for (int cy = clo[1]; cy <= chi[1]; ++cy)
+                for (int cx = clo[0]; cx <= chi[0]; ++cx) {
+                    double X[8][3], Ae[27 * 27], phi27[27];
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    if (phi) {
+                        for (int a = 0; a < 27; ++a) phi27[a] = phi[idx[a]];
+                        heat_cell_matrix(X, cf, phi27, NULL, NULL, Ae);
+                    } else {
+                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, Ae);
+                    }
+                    int il = -1;
+                    for (int a = 0; a < 27; ++a) if (idx[a] == r) il = a;
+                    for (int j = 0; j < 27; ++j)
+                        if (!node_constrained(m, idx[j])) acc += Ae[il * 27 + j] * x[idx[j]];
+                }
+        out[s] = acc;
+    }
+}
+
+/* rows are dof indices comp * n_nodes + node; transpose != 0 gives rows of A^T x. */
+void orc_oseen_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *u0,
+                    const double *x, int32_t transpose, int64_t nrows, const int64_t *rows, double *out)
+{
+    const int64_t nn = nnodes(m);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < nrows; ++s) {
+        const int64_t r = rows[s];
+        const int64_t node = r % nn;
+        const int comp = (int)(r / nn);
+        if (node_constrained(m, node)) { out[s] = x[r]; continue; }
+        int clo[3], chi[3];
+        cells_of_node(m, node, clo, chi);
+        double acc = 0.0;
+        double *Ae = (double *)malloc(sizeof(double) * 81 * 81);
+        for (int cz = clo[2]; cz <= chi[2]; ++cz)
+            for (int cy = clo[1]; cy <= chi[1]; ++cy)
+                for (int cx = clo[0]; cx <= chi[0]; ++cx) {
+                    double X[8][3], phi27[27], u27[81];
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    for (int a = 0; a < 27; ++a) {
+                        phi27[a] = phi[idx[a]];
+                        for (int c = 0; c < 3; ++c) u27[c * 27 + a] = u0[c * nn + idx[a]];
+                    }
+                    oseen_cell_matrix(X, cf, phi27, u27, Ae);
+                    int il = -1;
+                    for (int a = 0; a < 27; ++a) if (idx[a] == node) il = a;
+                    const int li = comp * 27 + il;
+                    for (int cp = 0; cp < 3; ++cp)
+                        for (int j = 0; j < 27; ++j) {
+                            if (node_constrained(m, idx[j])) continue;
+                            const int lj = cp * 27 + j;
+                            const double a = transpose ? Ae[lj * 81 + li] : Ae[li * 81 + lj];
+                            acc += a * x[cp * nn + idx[j]];
+                        }
+                }
+        free(Ae);
+        out[s] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature-point fields                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Physical coordinates of all quadrature points, [n_cells*27][3]. */
+void orc_quad_points(const orc_mesh *m, double *xq)
+{
+    const int64_t nc = (int64_t)m->n[0] * m->n[1] * m->n[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t cell = 0; cell < nc; ++cell) {
+        const int cx = (int)(cell % m->n[0]), cy = (int)((cell / m->n[0]) % m->n[1]),
+                  cz = (int)(cell / ((int64_t)m->n[0] * m->n[1]));
+        double X[8][3];
+        cell_vertices(m, cx, cy, cz, X);
+        qp_data Q;
+        for (int q = 0; q < 27; ++q) {
+            cell_qp(X, q, &Q);
+            for (int d = 0; d < 3; ++d) xq[(cell * 27 + q) * 3 + d] = Q.x[d];
+        }
+    }
+}
+
+/* k and rho*cp at all quadrature points from nodal phi (eqs. heaviside, muEff). */
+void orc_heat_qp_coeffs(const orc_mesh *m, const orc_coeffs *cf, const double *phi, double *kq, double *rcq)
+{
+    const int64_t nc = (int64_t)m->n[0] * m->n[1] * m->n[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t cell = 0; cell < nc; ++cell) {
+        const int cx = (int)(cell % m->n[0]), cy = (int)((cell / m->n[0]) % m->n[1]),
+                  cz = (int)(cell / ((int64_t)m->n[0] * m->n[1]));
+        double X[8][3];
+        int64_t idx[27];
+        cell_vertices(m, cx, cy, cz, X);
+        cell_nodes(m, cx, cy, cz, idx);
+        qp_data Q;
+        for (int q = 0; q < 27; ++q) {
+            cell_qp(X, q, &Q);
+            double phiq = 0.0, dH;
+            for (int j = 0; j < 27; ++j) phiq += Q.N[j] * phi[idx[j]];
+            const double H = heaviside(cf->heaviside, cf->eps, phiq, &dH);
+            kq[cell * 27 + q] = blend_arith(H, cf->k_l, cf->k_g);
+            rcq[cell * 27 + q] = blend_arith(H, cf->rc_l, cf->rc_g);
+        }
+    }
+}
+
+/* Gradient of L(T) through one implicit heat step A(k, rc) T = alpha_m M(rc) T_old,
+ * given the adjoint state lam (A^T lam = dL/dT):
+ *   dL/dk_q  = -alpha_k W_q grad lam(x_q) . grad T(x_q)
+ *   dL/drc_q = -alpha_m W_q lam(x_q) (T - T_old)(x_q)
+ * and, when phi != NULL (coefficients formed from phi through H),
+ *   dL/dphi_j = sum_{cells, q} N_j(x_q) H'(phi_q) [(k_l - k_g) dL/dk_q + (rc_l - rc_g) dL/drc_q].
+ * The formulas hold for lam = 0 on Dirichlet nodes (adjoint right-hand side
+ * zeroed there, since T is fixed on them) and T, T_old = 0 on Dirichlet nodes.
+ * dphi is accumulated cell by cell (8-colouring) over all nodes. */
+void orc_heat_grad(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *T,
+                   const double *Told, const double *lam, double *dk, double *drc, double *dphi)
+{
+    const int64_t nn = nnodes(m);
+    if (dphi) memset(dphi, 0, sizeof(double) * nn);
+    for (int color = 0; color < 8; ++color) {
+        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
+#pragma omp parallel for collapse(3) schedule(dynamic, 16)
+        for (int cz = pz; cz < m->n[2]; cz += 2)
+            for (int cy = py; cy < m->n[1]; cy += 2)
+                for (int cx = px; cx < m->n[0]; cx += 2) {
+                    double X[8][3];
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    qp_data Q;
+                    for (int q = 0; q < 27; ++q) {
+                        cell_qp(X, q, &Q);
+                        double l = 0, dT = 0, gl[3] = {0, 0, 0}, gT[3] = {0, 0, 0}, phiq = 0;
+                        for (int j = 0; j < 27; ++j) {
+                            const int64_t g = idx[j];
+                            l += Q.N[j] * lam[g];
+                            dT += Q.N[j] * (T[g] - Told[g]);
+                            for (int d = 0; d < 3; ++d) {
+                                gl[d] += Q.G[j][d] * lam[g];
+                                gT[d] += Q.G[j][d] * T[g];
+                            }
+                            if (phi) phiq += Q.N[j] * phi[g];
+                        }
+                        const double gk = -cf->alpha_k * Q.W * (gl[0] * gT[0] + gl[1] * gT[1] + gl[2] * gT[2]);
+                        const double grc = -cf->alpha_m * Q.W * l * dT;
+                        if (dk) dk[cell * 27 + q] = gk;
+                        if (drc) drc[cell * 27 + q] = grc;
+                        if (phi && dphi) {
+                            double dH;
+                            (void)heaviside(cf->heaviside, cf->eps, phiq, &dH);
+                            const double s = dH * ((cf->k_l - cf->k_g) * gk + (cf->rc_l - cf->rc_g) * grc);
+                            for (int j = 0; j < 27; ++j) dphi[idx[j]] += Q.N[j] * s;
+                        }
+                    }
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multigrid transfer: P[i][j] = N_j^coarse(x_i^fine) (Q2 embedding)         */
+/* ------------------------------------------------------------------------ */
+
+/* Count (pass cols == NULL) or fill the CSR of the prolongation from the
+ * coarse mesh mc (n cells) to the fine mesh with 2n cells on the same box.
+ * Entries whose value is exactly zero are dropped. */
+int64_t orc_prolongation(const orc_mesh *mc, int64_t *rowptr, int32_t *cols, double *vals)
+{
+    const int nf[3] = {2 * mc->n[0], 2 * mc->n[1], 2 * mc->n[2]};
+    const int NXf = 2 * nf[0] + 1, NYf = 2 * nf[1] + 1, NZf = 2 * nf[2] + 1;
+    int64_t p = 0;
+    if (!cols) rowptr[0] = 0;
+    for (int k = 0; k < NZf; ++k)
+        for (int j = 0; j < NYf; ++j)
+            for (int i = 0; i < NXf; ++i) {
+                const int64_t row = i + (int64_t)NXf * (j + (int64_t)NYf * k);
+                /* fine node position in coarse-cell units: t/4 cells */
+                const int t[3] = {i, j, k};
+                int c[3];
+                double xi[3];
+                for (int d = 0; d < 3; ++d) {
+                    c[d] = t[d] / 4;
+                    if (c[d] > mc->n[d] - 1) c[d] = mc->n[d] - 1;
+                    xi[d] = (t[d] - 4.0 * c[d]) / 4.0;
+                }
+                int64_t start = cols ? rowptr[row] : p;
+                int64_t q = start;
+                /* columns in increasing global coarse index: c outer, b, a inner */
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int b = 0; b < 3; ++b)
+                        for (int a = 0; a < 3; ++a) {
+                            const double v = lag1(a, xi[0]) * lag1(b, xi[1]) * lag1(cc, xi[2]);
+                            if (v == 0.0) continue;
+                            if (cols) {
+                                cols[q] = (int32_t)node_id(mc, 2 * c[0] + a, 2 * c[1] + b, 2 * c[2] + cc);
+                                vals[q] = v;
+                            }
+                            ++q;
+                        }
+                if (!cols) {
+                    p = q;
+                    rowptr[row + 1] = p;
+                }
+            }
+    return cols ? rowptr[(int64_t)NXf * NYf * NZf] : p;
+}
+
+/* Load vector b_i = int f N_i, by the same Gauss rule, from values of f at the
+ * quadrature points (cell-major, 27 per cell).  No Dirichlet treatment. */
+void orc_load_vector(const orc_mesh *m, const double *fq, double *b)
+{
+    const int64_t nn = nnodes(m);
+    memset(b, 0, sizeof(double) * nn);
+    for (int color = 0; color < 8; ++color) {
+        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
+#pragma omp parallel for collapse(3) schedule(dynamic, 16)
+        for (int cz = pz; cz < m->n[2]; cz += 2)
+            for (int cy = py; cy < m->n[1]; cy += 2)
+                for (int cx = px; cx < m->n[0]; cx += 2) {
+                    double X[8][3];
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    qp_data Q;
+                    for (int q = 0; q < 27; ++q) {
+                        cell_qp(X, q, &Q);
+                        for (int i = 0; i < 27; ++i) b[idx[i]] += Q.W * fq[cell * 27 + q] * Q.N[i];
+                    }
+                }
+    }
+}

@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module only builds input data: node coordinates of the uniform Q2 grid,
+level-set fields, convective fields, manufactured nodal fields and seeded
+random vectors.  It holds none of the operator arithmetic (no basis functions,
+no quadrature, no Heaviside, no property blending): both the GPU library and
+the CPU oracle receive the arrays produced here and do that work themselves.
+
+Node numbering of a mesh with ``n = (nx, ny, nz)`` cells is the Q2 node grid
+``(2nx+1) x (2ny+1) x (2nz+1)`` with global id ``i + (2nx+1)*(j + (2ny+1)*k)``
+(x fastest).  Vector fields are stored component-major (structure of arrays):
+``[3][n_nodes]``.
+
+Level-set profiles follow the initial condition of the paper's level-set
+framework (Sec. 2.2, eq. initial_phi): phi = tanh(d / (2 eps)) with d a signed
+distance that is positive in the liquid.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Tuple
+
+import numpy as np
+
+# Face bits for homogeneous Dirichlet boundaries: bit f <-> face f.
+FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI, FACE_ZLO, FACE_ZHI = (1 << i for i in range(6))
+ALL_FACES = 0x3F
+
+
+@dataclass(frozen=True)
+class Mesh:
+    """Uniform hexahedral mesh of a box split into ``n`` cells per direction."""
+
+    n: Tuple[int, int, int]
+    lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    dirichlet: int = 0  # bit mask of faces with homogeneous Dirichlet conditions
+
+    @property
+    def nodes_per_dim(self) -> Tuple[int, int, int]:
+        return tuple(2 * c + 1 for c in self.n)
+
+    @property
+    def n_nodes(self) -> int:
+        a, b, c = self.nodes_per_dim
+        return a * b * c
+
+    @property
+    def n_cells(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def h(self) -> Tuple[float, float, float]:
+        return tuple((self.hi[d] - self.lo[d]) / self.n[d] for d in range(3))
+
+
+def node_axes(mesh: Mesh):
+    """1D node coordinates per direction (equispaced, spacing h/2)."""
+    return [np.linspace(mesh.lo[d], mesh.hi[d], 2 * mesh.n[d] + 1) for d in range(3)]
+
+
+def node_coords(mesh: Mesh) -> np.ndarray:
+    """(n_nodes, 3) coordinates in global node order (x fastest)."""
+    ax, ay, az = node_axes(mesh)
+    Z, Y, X = np.meshgrid(az, ay, ax, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def uniform(seed: int, n: int) -> np.ndarray:
+    """x ~ U[-1, 1] from numpy's default generator with the given seed."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+
+
+def phi_sphere(mesh: Mesh, radius: float, eps: float, center=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """tanh profile of a liquid sphere: d = radius - |x - center| (liquid inside)."""
+    x = node_coords(mesh)
+    d = radius - np.linalg.norm(x - np.asarray(center)[None, :], axis=1)
+    return np.tanh(d / (2.0 * eps))
+
+
+def phi_wavy_plane(mesh: Mesh, z0: float, amp: float, eps: float) -> np.ndarray:
+    """tanh profile of a liquid layer below z = z0 + amp cos(2 pi x) cos(2 pi y).
+
+    d is the vertical distance to that surface (liquid below)."""
+    x = node_coords(mesh)
+    zs = z0 + amp * np.cos(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+    return np.tanh((zs - x[:, 2]) / (2.0 * eps))
+
+
+def taylor_green(mesh: Mesh) -> np.ndarray:
+    """Divergence-free Taylor-Green vortex at the nodes, SoA [3][n_nodes].
+
+    u = (sin(pi x) cos(pi y) cos(pi z), -cos(pi x) sin(pi y) cos(pi z), 0);
+    its normal component vanishes on the faces of the unit cube."""
+    x = node_coords(mesh)
+    px, py, pz = np.pi * x[:, 0], np.pi * x[:, 1], np.pi * x[:, 2]
+    u = np.empty((3, x.shape[0]))
+    u[0] = np.sin(px) * np.cos(py) * np.cos(pz)
+    u[1] = -np.cos(px) * np.sin(py) * np.cos(pz)
+    u[2] = 0.0
+    return u
+
+
+def manufactured_T(mesh: Mesh) -> np.ndarray:
+    """Nodal values of T = sin(pi x) sin(pi y) sin(pi z)."""
+    x = node_coords(mesh)
+    return np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]) * np.sin(np.pi * x[:, 2])
+
+
+# ---------------------------------------------------------------------------
+# Material data and workload presets
+# ---------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class HeatParams:
+    """Coefficients of the implicit heat operator rc/dt M + K(k).
+
+    heaviside: 0 -> H = clamp((1 + phi)/2, 0, 1); 1 -> sine form in d(phi)."""
+
+    k_l: float = 30.0
+    k_g: float = 0.3
+    rc_l: float = 5.0e6
+    rc_g: float = 5.0e3
+    dt: float = 1.0e-3
+    heaviside: int = 0
+    eps: float = 0.0  # interface thickness parameter (sine form only)
+
+    @property
+    def alpha_m(self) -> float:
+        return 1.0 / self.dt
+
+    alpha_k: float = 1.0
+
+
+@dataclass(frozen=True)
+class OseenParams:
+    """Coefficients of the linearized momentum operator rho/dt M + rho (u0.grad) + 2 mu eps:eps."""
+
+    rho_l: float = 4000.0
+    rho_g: float = 4.0
+    mu_l: float = 5.0e-3
+    mu_g: float = 5.0e-5
+    dt: float = 1.0e-4
+    heaviside: int = 0
+    eps: float = 0.0
+    alpha_c: float = 1.0
+    alpha_v: float = 1.0
+
+    @property
+    def alpha_m(self) -> float:
+        return 1.0 / self.dt
+
+
+@dataclass
+class HeatWorkload:
+    mesh: Mesh
+    params: HeatParams
+    phi: np.ndarray
+    eps: float
+
+
+def heat_sphere_workload(n: int, dirichlet: int, params: HeatParams | None = None) -> HeatWorkload:
+    """Heat operator on the unit cube with a liquid sphere of radius 0.3 at the
+    center, eps = 2h (h = cell edge)."""
+    mesh = Mesh((n, n, n), dirichlet=dirichlet)
+    eps = 2.0 / n
+    p = params or HeatParams()
+    return HeatWorkload(mesh, p, phi_sphere(mesh, 0.3, eps), eps)
+
+
+@dataclass
+class OseenWorkload:
+    mesh: Mesh
+    params: OseenParams
+    phi: np.ndarray
+    u0: np.ndarray
+    eps: float
+
+
+def oseen_wavy_workload(n: int, dirichlet: int = ALL_FACES, params: OseenParams | None = None) -> OseenWorkload:
+    """Oseen operator: liquid below z = 0.5 + 0.05 cos(2 pi x) cos(2 pi y),
+    eps = 2h, Taylor-Green convective field, no-slip on all faces."""
+    mesh = Mesh((n, n, n), dirichlet=dirichlet)
+    eps = 2.0 / n
+    return OseenWorkload(mesh, params or OseenParams(), phi_wavy_plane(mesh, 0.5, 0.05, eps),
+                         taylor_green(mesh), eps)
