@@ -1,0 +1,219 @@
+/*
+ * mf.h -- C ABI of the matrix-free Q2 operator and solver library for one
+ * MI355X (gfx950) GPU.
+ *
+ * The library applies, on uniform hexahedral meshes with continuous
+ * Lagrange Q2 elements and 3x3x3 Gauss quadrature (App. B "Numerical
+ * framework"), the two implicit operators of the diffuse-interface
+ * two-phase model:
+ *
+ *   heat  (Sec. 2.1, eq. heat_transfer without convection, one backward-Euler
+ *         step):  A = alpha_m M(rho c_p) + alpha_k K(k)
+ *   Oseen (Sec. 2.1, eq. momentum_balance linearized about a frozen velocity
+ *         u0, viscous stress 2 mu eps(u)):
+ *         A = alpha_m M(rho) + alpha_c C(rho, u0) + alpha_v V(mu)
+ *
+ * with k, rho c_p and mu blended arithmetically (Sec. 2.3, eq. muEff) and rho
+ * reciprocally (eq. rhoEff) through a smoothed Heaviside H(phi) of a nodal
+ * level-set field (eq. heaviside, or the linear form H = (1+phi)/2), and
+ * solves them with CG (symmetric) or GMRES (non-symmetric) as in App. B.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh      n[d] cells per direction on the box [lo, hi]; Q2 nodes
+ *           (2n0+1)(2n1+1)(2n2+1) numbered i + NX*(j + NY*k), x fastest.
+ * Vectors   scalar fields: n_nodes entries; velocity: component-major
+ *           [3][n_nodes].  Quadrature-point fields: cell-major, 27 per cell,
+ *           q = qx + 3 qy + 9 qz, cell = cx + n0 (cy + n1 cz).
+ * Dirichlet faces flagged in mesh.dirichlet carry homogeneous conditions:
+ *           those dofs are identity rows of A with their columns removed.
+ * Pointers  every array argument is DEVICE memory on the device that was
+ *           current when the context was created, owned by the caller,
+ *           contiguous, of the element type given by the operator precision
+ *           (double for MF_FP64, float for MF_FP32).  Host pointers are only
+ *           the descriptor structs and the mf_solve_info output.
+ * Streams   work is enqueued on the given stream (0 = default stream).
+ *           Applies return without synchronizing; solvers synchronize the
+ *           stream to read convergence state.
+ * Errors    functions return an mf_status; nothing aborts.  On error a
+ *           message is available from mf_last_error(ctx).
+ * Threads   a context must not be used by two host threads at once; calls
+ *           on one context that overlap on the GPU race on its workspace.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *mf_stream; /* a hipStream_t */
+
+typedef enum {
+    MF_OK = 0,
+    MF_NOT_CONVERGED = 1, /* solver reached maxit; x and info are still written */
+    MF_BREAKDOWN = 2,     /* Krylov breakdown (p.Ap <= 0, NaN/Inf); x holds the last iterate */
+    MF_ERR_ARG = -1,      /* invalid argument (null pointer, size, enum value) */
+    MF_ERR_HIP = -2,      /* a HIP runtime call failed */
+    MF_ERR_OOM = -3,      /* device allocation failed */
+    MF_ERR_STATE = -4     /* object used in a state that does not allow the call */
+} mf_status;
+
+enum { MF_HEAT = 0, MF_OSEEN = 1 };
+enum { MF_FP64 = 0, MF_FP32 = 1 };
+enum { MF_COEFF_LEVELSET = 0, MF_COEFF_QUAD = 1 };
+enum { MF_H_LINEAR = 0, MF_H_SINE = 1 };
+enum { MF_PC_NONE = 0, MF_PC_JACOBI = 1, MF_PC_BLOCK_JACOBI = 2 };
+
+/* Face bits of mf_mesh.dirichlet. */
+enum { MF_FACE_XLO = 1, MF_FACE_XHI = 2, MF_FACE_YLO = 4, MF_FACE_YHI = 8, MF_FACE_ZLO = 16, MF_FACE_ZHI = 32 };
+
+typedef struct {
+    int32_t n[3];       /* cells per direction, each >= 1; total nodes < 2^31 */
+    uint32_t dirichlet; /* MF_FACE_* bits with homogeneous Dirichlet conditions */
+    double lo[3];       /* box corner */
+    double hi[3];       /* opposite corner, hi[d] > lo[d] */
+} mf_mesh;
+
+/* Operator descriptor (host struct; the arrays it points to are device memory). */
+typedef struct {
+    int32_t kind;       /* MF_HEAT or MF_OSEEN */
+    int32_t precision;  /* MF_FP64 or MF_FP32: element type of every array */
+    int32_t coeff_mode; /* MF_COEFF_LEVELSET: coefficients from nodal phi;
+                           MF_COEFF_QUAD: heat k and rho c_p given per quadrature point */
+    int32_t heaviside;  /* MF_H_LINEAR: H = clamp((1+phi)/2, 0, 1);
+                           MF_H_SINE: eq. heaviside with d = 2 eps artanh(phi) */
+    double eps;         /* interface thickness parameter (MF_H_SINE only) */
+    double alpha_m;     /* mass factor, 1/dt */
+    double alpha_k;     /* heat conduction factor */
+    double alpha_c;     /* Oseen convection factor */
+    double alpha_v;     /* Oseen viscous factor */
+    double k_l, k_g;    /* conductivity, liquid / gas */
+    double rc_l, rc_g;  /* volumetric heat capacity rho c_p, liquid / gas */
+    double rho_l, rho_g;/* density, liquid / gas (reciprocal blend) */
+    double mu_l, mu_g;  /* dynamic viscosity, liquid / gas */
+    const void *phi;    /* nodal level set [n_nodes] (LEVELSET mode, and Oseen) */
+    const void *k_q;    /* conductivity per quadrature point [n_cells*27] (QUAD mode) */
+    const void *rc_q;   /* rho c_p per quadrature point [n_cells*27] (QUAD mode) */
+    const void *u0;     /* Oseen convective velocity, nodal [3][n_nodes] */
+} mf_operator;
+
+typedef struct {
+    int32_t iters;      /* operator applications in the Krylov iteration */
+    int32_t converged;  /* 1 if the stopping test was met */
+    double rel_res;     /* true ||b - A x|| / ||b|| recomputed at exit */
+    double rel_res_est; /* the residual estimate the stopping test used */
+} mf_solve_info;
+
+typedef struct mf_ctx mf_ctx;
+typedef struct mf_mg mf_mg;
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Create a context for `mesh` on the current HIP device.  The context owns
+ * its workspace (Krylov vectors, reduction buffers), allocated on first use
+ * and freed by mf_destroy.  Returns MF_ERR_ARG for n[d] < 1, hi <= lo or
+ * meshes with 2^31 or more nodes. */
+mf_status mf_create(const mf_mesh *mesh, mf_ctx **ctx);
+void mf_destroy(mf_ctx *ctx);
+/* Last error message of the context (static string if ctx is NULL). */
+const char *mf_last_error(const mf_ctx *ctx);
+int64_t mf_n_nodes(const mf_ctx *ctx);
+int64_t mf_n_cells(const mf_ctx *ctx);
+
+/* ---- operator application (Sec. 2.1, 2.3; App. B matrix-free products) ------ */
+
+/* y = A x.  x and y: n_dofs entries (n_nodes for heat, 3 n_nodes for Oseen),
+ * distinct buffers.  Dirichlet dofs: y_i = x_i; x is read as zero there in
+ * the products of the other rows.  FP32 operators are supported for heat. */
+mf_status mf_operator_apply(mf_ctx *ctx, const mf_operator *op, const void *x, void *y, mf_stream stream);
+
+/* y = A^T x (the adjoint operator).  For the heat operator A^T = A; for the
+ * Oseen operator the convective term acts on the test function. */
+mf_status mf_operator_apply_transpose(mf_ctx *ctx, const mf_operator *op, const void *x, void *y,
+                                      mf_stream stream);
+
+/* Diagonal of A (heat; n_nodes entries) or the 3x3 nodal diagonal blocks of
+ * A (Oseen; [n_nodes][3][3] row-major, entry (c, c') couples component c'
+ * into row c).  Dirichlet dofs give 1 (identity block). */
+mf_status mf_operator_diagonal(mf_ctx *ctx, const mf_operator *op, void *diag, mf_stream stream);
+
+/* ---- Krylov solvers (App. B), FP64 operators only ---------------------------- */
+
+/* Preconditioned CG for the symmetric heat operator, x0 = 0.  precond:
+ * MF_PC_NONE or MF_PC_JACOBI (inverse diagonal).  Stops when the recursively
+ * updated residual satisfies ||r|| <= rtol ||b||; info->iters counts
+ * products with A.  b and x are device arrays of n_nodes doubles. */
+mf_status mf_cg_solve(mf_ctx *ctx, const mf_operator *op, int32_t precond, const double *b, double *x,
+                      double rtol, int32_t maxit, mf_solve_info *info, mf_stream stream);
+
+/* Right-preconditioned restarted GMRES(restart), x0 = 0, with classical
+ * Gram-Schmidt and one re-orthogonalization pass and Givens rotations.
+ * precond: MF_PC_NONE, MF_PC_JACOBI, or MF_PC_BLOCK_JACOBI (inverse 3x3 nodal
+ * blocks, Oseen).  transpose != 0 solves A^T x = b.  Stops when the residual
+ * estimate is <= rtol ||b|| and the true residual confirms it. */
+mf_status mf_gmres_solve(mf_ctx *ctx, const mf_operator *op, int32_t precond, int32_t restart, int32_t transpose,
+                         const double *b, double *x, double rtol, int32_t maxit, mf_solve_info *info,
+                         mf_stream stream);
+
+/* ---- FP32 geometric multigrid preconditioner (heat) ----------------------------- */
+
+typedef struct {
+    int32_t coarse_cells;     /* coarsest level: cells per direction (the fine n must be this times 2^L) */
+    int32_t degree;           /* Chebyshev smoother degree (pre and post) */
+    double smoothing_range;   /* lambda_min = lambda_max / smoothing_range */
+    int32_t eig_steps;        /* Lanczos steps for lambda_max of D^{-1} A per level */
+    double eig_safety;        /* lambda_max = eig_safety * Lanczos estimate */
+    const double *lambda_max; /* optional host array, one per level (coarsest first), overriding the estimate */
+    double coarse_rtol;       /* FP64 CG tolerance of the coarse solve */
+    int32_t coarse_maxit;
+} mf_mg_params;
+
+/* Build the level hierarchy of a heat operator in LEVELSET mode: levels are
+ * rediscretized in FP32 with the level set injected to the coarse nodes; the
+ * coarsest level is kept in FP64 for its CG solve.  op->precision must be
+ * MF_FP64 (the fine-level operator of the outer solve). */
+mf_status mf_mg_create(mf_ctx *ctx, const mf_operator *op, const mf_mg_params *params, mf_mg **mg, mf_stream stream);
+void mf_mg_destroy(mf_mg *mg);
+int32_t mf_mg_n_levels(const mf_mg *mg);
+/* Chebyshev bounds in use, one per level, coarsest first (host array of n_levels). */
+mf_status mf_mg_lambda_max(const mf_mg *mg, double *out);
+
+/* z = V(r): one V-cycle (Chebyshev pre-smoothing from zero, residual,
+ * restriction R = P^T, coarse correction, prolongation P = Q2 embedding,
+ * Chebyshev post-smoothing) computed in FP32 with the coarsest level solved
+ * by FP64 CG.  r and z are FP64 device arrays of n_nodes. */
+mf_status mf_mg_vcycle(mf_mg *mg, const double *r, double *z, mf_stream stream);
+
+/* Flexible CG (Polak-Ribiere beta) in FP64 preconditioned by mf_mg_vcycle,
+ * x0 = 0; same stopping test and info as mf_cg_solve. */
+mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, double rtol, int32_t maxit, mf_solve_info *info,
+                         mf_stream stream);
+
+/* ---- quadrature-point fields and the adjoint gradient (heat, FP64) --------------- */
+
+/* Physical coordinates of all quadrature points, [n_cells*27][3] doubles. */
+mf_status mf_quad_points(mf_ctx *ctx, double *xq, mf_stream stream);
+
+/* k and rho c_p at all quadrature points from the operator's nodal phi
+ * (eqs. heaviside, muEff); n_cells*27 doubles each. */
+mf_status mf_heat_qp_coeffs(mf_ctx *ctx, const mf_operator *op, double *k_q, double *rc_q, mf_stream stream);
+
+/* Gradient of a loss L(T) through one implicit heat step
+ * A(k, rc) T = alpha_m M(rc) T_old, given the adjoint state lambda
+ * (A^T lambda = dL/dT with zeros on Dirichlet nodes):
+ *   dk_q  = -alpha_k W_q grad(lambda).grad(T) at quadrature point q
+ *   drc_q = -alpha_m W_q lambda (T - T_old)    at q
+ * and, if dphi != NULL (LEVELSET mode), the chain rule through H:
+ *   dphi_j = sum_q N_j(x_q) H'(phi_q) [(k_l - k_g) dk_q + (rc_l - rc_g) drc_q].
+ * dT = T - T_old is passed directly (the step is solved in delta form).
+ * dk_q, drc_q may be NULL.  All arrays FP64. */
+mf_status mf_heat_coeff_grad(mf_ctx *ctx, const mf_operator *op, const double *T, const double *dT,
+                             const double *lambda, double *dk_q, double *drc_q, double *dphi, mf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

@@ -1,0 +1,534 @@
+// api.hip -- the C ABI declared in include/mf.h: contexts, argument
+// checking, and the host loops of the Krylov solvers (App. B: CG for
+// symmetric, GMRES for non-symmetric systems).  All arithmetic on vectors
+// runs in the kernels of heat.hip, oseen.hip, vec.hip and mg.hip; the host
+// only orchestrates, reads convergence scalars and runs the GMRES
+// Hessenberg least-squares update on at most 31 numbers.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "kernels.hpp"
+
+using namespace mf;
+
+struct mf_ctx {
+    mf_mesh mesh;
+    KMesh km;
+    int device = 0;
+    int64_t nn = 0, nc = 0;
+    std::string err;
+    // workspace: vectors of 3 * n_nodes doubles each
+    std::vector<double *> vec;
+    double *partials = nullptr;
+    unsigned *counter = nullptr;
+    unsigned cap = 0;
+    CGState *cg = nullptr;
+    double *scal = nullptr;      // device scalars
+    CGState *h_state = nullptr;  // pinned host copy
+    double *h_scal = nullptr;    // pinned host scalars
+    double *V = nullptr;         // GMRES basis
+    int V_cols = 0;
+    double *blocks = nullptr;    // Oseen block-Jacobi inverse
+};
+
+static const char *g_static_err = "no context";
+
+static mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(c, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail((c), MF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static RedWS redws(mf_ctx *c) { return RedWS{c->partials, c->counter, c->cap}; }
+
+// Workspace vector i (3 * n_nodes doubles), allocated on first use.
+static mf_status ws_vec(mf_ctx *c, int i, double **out)
+{
+    while ((int)c->vec.size() <= i) c->vec.push_back(nullptr);
+    if (!c->vec[i]) {
+        if (hipMalloc((void **)&c->vec[i], sizeof(double) * 3 * c->nn) != hipSuccess)
+            return fail(c, MF_ERR_OOM, "workspace allocation of %lld doubles failed", (long long)(3 * c->nn));
+    }
+    *out = c->vec[i];
+    return MF_OK;
+}
+
+extern "C" {
+
+int64_t mf_n_nodes(const mf_ctx *c) { return c ? c->nn : 0; }
+int64_t mf_n_cells(const mf_ctx *c) { return c ? c->nc : 0; }
+
+const char *mf_last_error(const mf_ctx *c) { return c ? c->err.c_str() : g_static_err; }
+
+mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
+{
+    if (!mesh || !out) return MF_ERR_ARG;
+    *out = nullptr;
+    int64_t nn = 1, nc = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->n[d] < 1 || !(mesh->hi[d] > mesh->lo[d])) return MF_ERR_ARG;
+        nn *= 2 * (int64_t)mesh->n[d] + 1;
+        nc *= mesh->n[d];
+    }
+    if (3 * nn >= (int64_t)1 << 31 || mesh->dirichlet > 63u) return MF_ERR_ARG;
+    mf_ctx *c = new mf_ctx();
+    c->mesh = *mesh;
+    c->nn = nn;
+    c->nc = nc;
+    KMesh &k = c->km;
+    k.nx = mesh->n[0];
+    k.ny = mesh->n[1];
+    k.nz = mesh->n[2];
+    k.NX = 2 * k.nx + 1;
+    k.NY = 2 * k.ny + 1;
+    k.NZ = 2 * k.nz + 1;
+    k.dirichlet = mesh->dirichlet;
+    k.hx = (mesh->hi[0] - mesh->lo[0]) / mesh->n[0];
+    k.hy = (mesh->hi[1] - mesh->lo[1]) / mesh->n[1];
+    k.hz = (mesh->hi[2] - mesh->lo[2]) / mesh->n[2];
+    k.lox = mesh->lo[0];
+    k.loy = mesh->lo[1];
+    k.loz = mesh->lo[2];
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MF_ERR_HIP;
+    }
+    // reduction workspace: enough for one partial per heat brick and 32 sets of 1024 blocks
+    const int64_t nbricks = ((k.nx + 3) / 4) * (int64_t)((k.ny + 3) / 4) * ((k.nz + 3) / 4);
+    int64_t cap = nbricks > 32 * 1024 ? nbricks : 32 * 1024;
+    c->cap = (unsigned)cap;
+    bool ok = hipMalloc((void **)&c->partials, sizeof(double) * cap) == hipSuccess &&
+              hipMalloc((void **)&c->counter, sizeof(unsigned) * 16) == hipSuccess &&
+              hipMalloc((void **)&c->cg, sizeof(CGState)) == hipSuccess &&
+              hipMalloc((void **)&c->scal, sizeof(double) * 256) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_state, sizeof(CGState), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_scal, sizeof(double) * 256, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        mf_destroy(c);
+        return MF_ERR_OOM;
+    }
+    if (hipMemset(c->counter, 0, sizeof(unsigned) * 16) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        mf_destroy(c);
+        return MF_ERR_HIP;
+    }
+    *out = c;
+    return MF_OK;
+}
+
+void mf_destroy(mf_ctx *c)
+{
+    if (!c) return;
+    for (double *p : c->vec)
+        if (p) (void)hipFree(p);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->counter) (void)hipFree(c->counter);
+    if (c->cg) (void)hipFree(c->cg);
+    if (c->scal) (void)hipFree(c->scal);
+    if (c->V) (void)hipFree(c->V);
+    if (c->blocks) (void)hipFree(c->blocks);
+    if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    delete c;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// Operator descriptors
+// ---------------------------------------------------------------------------
+static mf_status check_op(mf_ctx *c, const mf_operator *op)
+{
+    if (!c) return MF_ERR_ARG;
+    if (!op) return fail(c, MF_ERR_ARG, "null operator");
+    if (op->kind != MF_HEAT && op->kind != MF_OSEEN) return fail(c, MF_ERR_ARG, "unknown operator kind %d", op->kind);
+    if (op->precision != MF_FP64 && op->precision != MF_FP32)
+        return fail(c, MF_ERR_ARG, "unknown precision %d", op->precision);
+    if (op->heaviside != MF_H_LINEAR && op->heaviside != MF_H_SINE)
+        return fail(c, MF_ERR_ARG, "unknown Heaviside form %d", op->heaviside);
+    if (op->heaviside == MF_H_SINE && !(op->eps > 0.0)) return fail(c, MF_ERR_ARG, "sine Heaviside needs eps > 0");
+    if (op->kind == MF_HEAT) {
+        if (op->coeff_mode == MF_COEFF_LEVELSET) {
+            if (!op->phi) return fail(c, MF_ERR_ARG, "heat operator in LEVELSET mode needs phi");
+        } else if (op->coeff_mode == MF_COEFF_QUAD) {
+            if (!op->k_q || !op->rc_q) return fail(c, MF_ERR_ARG, "heat operator in QUAD mode needs k_q and rc_q");
+        } else {
+            return fail(c, MF_ERR_ARG, "unknown coefficient mode %d", op->coeff_mode);
+        }
+    } else {
+        if (op->precision != MF_FP64) return fail(c, MF_ERR_ARG, "the Oseen operator is FP64 only");
+        if (!op->phi || !op->u0) return fail(c, MF_ERR_ARG, "the Oseen operator needs phi and u0");
+        if (!(op->rho_l > 0.0) || !(op->rho_g > 0.0)) return fail(c, MF_ERR_ARG, "densities must be positive");
+    }
+    return MF_OK;
+}
+
+static HeatArgs heat_args(const mf_operator *op)
+{
+    HeatArgs a;
+    a.mode = op->coeff_mode == MF_COEFF_QUAD ? 1 : 0;
+    a.hkind = op->heaviside;
+    a.eps = op->eps;
+    a.am = op->alpha_m;
+    a.ak = op->alpha_k;
+    a.k_l = op->k_l;
+    a.k_g = op->k_g;
+    a.rc_l = op->rc_l;
+    a.rc_g = op->rc_g;
+    a.phi = op->phi;
+    a.kq = op->k_q;
+    a.rcq = op->rc_q;
+    return a;
+}
+
+static OseenArgs oseen_args(const mf_operator *op)
+{
+    OseenArgs a;
+    a.hkind = op->heaviside;
+    a.eps = op->eps;
+    a.am = op->alpha_m;
+    a.ac = op->alpha_c;
+    a.av = op->alpha_v;
+    a.rho_l = op->rho_l;
+    a.rho_g = op->rho_g;
+    a.mu_l = op->mu_l;
+    a.mu_g = op->mu_g;
+    a.phi = (const double *)op->phi;
+    a.u0 = (const double *)op->u0;
+    return a;
+}
+
+static int64_t ndofs(const mf_ctx *c, const mf_operator *op) { return op->kind == MF_OSEEN ? 3 * c->nn : c->nn; }
+
+// y = A x or A^T x, FP64 or FP32 (heat)
+static hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s)
+{
+    if (op->kind == MF_HEAT)
+        return heat_apply(c->km, heat_args(op), op->precision == MF_FP32, x, y, nullptr, nullptr, s);
+    return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, s);
+}
+
+extern "C" {
+
+mf_status mf_operator_apply(mf_ctx *c, const mf_operator *op, const void *x, void *y, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (!x || !y || x == y) return fail(c, MF_ERR_ARG, "x and y must be distinct non-null device arrays");
+    HIPCHK(c, apply_any(c, op, 0, x, y, (hipStream_t)stream));
+    return MF_OK;
+}
+
+mf_status mf_operator_apply_transpose(mf_ctx *c, const mf_operator *op, const void *x, void *y, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (!x || !y || x == y) return fail(c, MF_ERR_ARG, "x and y must be distinct non-null device arrays");
+    HIPCHK(c, apply_any(c, op, 1, x, y, (hipStream_t)stream));
+    return MF_OK;
+}
+
+mf_status mf_operator_diagonal(mf_ctx *c, const mf_operator *op, void *diag, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (!diag) return fail(c, MF_ERR_ARG, "null diag");
+    if (op->kind == MF_HEAT)
+        HIPCHK(c, heat_diagonal(c->km, heat_args(op), op->precision == MF_FP32, diag, (hipStream_t)stream));
+    else
+        HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), (double *)diag, (hipStream_t)stream));
+    return MF_OK;
+}
+
+mf_status mf_quad_points(mf_ctx *c, double *xq, mf_stream stream)
+{
+    if (!c) return MF_ERR_ARG;
+    if (!xq) return fail(c, MF_ERR_ARG, "null xq");
+    HIPCHK(c, quad_points(c->km, xq, (hipStream_t)stream));
+    return MF_OK;
+}
+
+mf_status mf_heat_qp_coeffs(mf_ctx *c, const mf_operator *op, double *kq, double *rcq, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (op->kind != MF_HEAT || op->coeff_mode != MF_COEFF_LEVELSET || op->precision != MF_FP64)
+        return fail(c, MF_ERR_ARG, "mf_heat_qp_coeffs needs an FP64 heat operator in LEVELSET mode");
+    if (!kq || !rcq) return fail(c, MF_ERR_ARG, "null output");
+    HIPCHK(c, heat_qp_coeffs(c->km, heat_args(op), kq, rcq, (hipStream_t)stream));
+    return MF_OK;
+}
+
+mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, const double *dT,
+                             const double *lambda, double *dk, double *drc, double *dphi, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (op->kind != MF_HEAT || op->precision != MF_FP64)
+        return fail(c, MF_ERR_ARG, "mf_heat_coeff_grad needs an FP64 heat operator");
+    if (!T || !dT || !lambda) return fail(c, MF_ERR_ARG, "null input");
+    if (dphi && op->coeff_mode != MF_COEFF_LEVELSET)
+        return fail(c, MF_ERR_ARG, "dphi needs the LEVELSET coefficient mode");
+    HIPCHK(c, heat_grad(c->km, heat_args(op), T, dT, lambda, dk, drc, dphi, (hipStream_t)stream));
+    return MF_OK;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// Helpers for the solvers
+// ---------------------------------------------------------------------------
+// ||v||^2 read back to the host (synchronizes the stream)
+static mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s)
+{
+    RedWS r = redws(c);
+    HIPCHK(c, vmultidot(a, n, 1, b, n, c->scal, &r, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    *out = c->h_scal[0];
+    return MF_OK;
+}
+
+// true relative residual ||b - A x|| / ||b||, using workspace vector `tmp`
+static mf_status true_residual(mf_ctx *c, const mf_operator *op, int transpose, const double *b, const double *x,
+                               double *tmp, double bnorm, double *out, hipStream_t s)
+{
+    const int64_t n = ndofs(c, op);
+    HIPCHK(c, apply_any(c, op, transpose, x, tmp, s));
+    HIPCHK(c, vaxpby(1.0, b, -1.0, tmp, n, s));
+    double rr;
+    mf_status st = host_dot(c, tmp, tmp, n, &rr, s);
+    if (st) return st;
+    *out = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t precond, const double *b, double *x,
+                                 double rtol, int32_t maxit, mf_solve_info *info, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (op->kind != MF_HEAT || op->precision != MF_FP64)
+        return fail(c, MF_ERR_ARG, "mf_cg_solve needs an FP64 heat operator (symmetric)");
+    if (precond != MF_PC_NONE && precond != MF_PC_JACOBI)
+        return fail(c, MF_ERR_ARG, "mf_cg_solve supports MF_PC_NONE and MF_PC_JACOBI");
+    if (!b || !x || !info) return fail(c, MF_ERR_ARG, "null argument");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(c, MF_ERR_ARG, "invalid rtol or maxit");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = c->nn;
+    double *r, *z, *p, *q, *dinv = nullptr;
+    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)))
+        return st;
+    const HeatArgs ha = heat_args(op);
+    if (precond == MF_PC_JACOBI) {
+        if ((st = ws_vec(c, 4, &dinv))) return st;
+        HIPCHK(c, heat_diagonal(c->km, ha, 0, dinv, s));
+        HIPCHK(c, vinv(dinv, n, s));
+    }
+    RedWS red = redws(c);
+    HIPCHK(c, cg_init(c->cg, b, dinv, x, r, z, p, q, n, rtol, maxit, 0, &red, s));
+    const int batch = 8;
+    for (int done_iters = 0;;) {
+        for (int k = 0; k < batch; ++k) {
+            HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->cg, &red, s));
+            HIPCHK(c, cg_update(c->cg, dinv, x, r, z, p, q, n, &red, s));
+            HIPCHK(c, cg_pupdate(c->cg, z, p, n, s));
+        }
+        done_iters += batch;
+        HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (c->h_state->done || done_iters >= maxit + batch) break;
+    }
+    const CGState hs = *c->h_state;
+    const double bnorm = sqrt(hs.bb);
+    info->iters = hs.iter;
+    info->rel_res_est = bnorm > 0.0 ? sqrt(hs.rr) / bnorm : 0.0;
+    info->converged = !hs.breakdown && hs.rr <= hs.thresh2;
+    if ((st = true_residual(c, op, 0, b, x, q, bnorm, &info->rel_res, s))) return st;
+    if (hs.breakdown) return fail(c, MF_BREAKDOWN, "CG breakdown at iteration %d (p.Ap = %g)", hs.iter, hs.pAp);
+    if (!info->converged) return fail(c, MF_NOT_CONVERGED, "CG reached maxit = %d", maxit);
+    return MF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m), right preconditioned, CGS2 Arnoldi, Givens rotations (Saad Alg. 9.5)
+// ---------------------------------------------------------------------------
+extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t precond, int32_t restart,
+                                    int32_t transpose, const double *b, double *x, double rtol, int32_t maxit,
+                                    mf_solve_info *info, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (op->precision != MF_FP64) return fail(c, MF_ERR_ARG, "mf_gmres_solve needs an FP64 operator");
+    if (restart < 1 || restart > 31) return fail(c, MF_ERR_ARG, "restart must be in [1, 31]");
+    if (!b || !x || !info) return fail(c, MF_ERR_ARG, "null argument");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(c, MF_ERR_ARG, "invalid rtol or maxit");
+    if (precond == MF_PC_BLOCK_JACOBI && op->kind != MF_OSEEN)
+        return fail(c, MF_ERR_ARG, "block Jacobi is defined for the 3-component Oseen operator");
+    if (precond != MF_PC_NONE && precond != MF_PC_JACOBI && precond != MF_PC_BLOCK_JACOBI)
+        return fail(c, MF_ERR_ARG, "unknown preconditioner %d", precond);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = ndofs(c, op);
+    const int m = restart;
+    if (!c->V || c->V_cols < m + 1) {
+        if (c->V) (void)hipFree(c->V);
+        c->V = nullptr;
+        if (hipMalloc((void **)&c->V, sizeof(double) * (int64_t)(m + 1) * 3 * c->nn) != hipSuccess)
+            return fail(c, MF_ERR_OOM, "GMRES basis allocation failed");
+        c->V_cols = m + 1;
+    }
+    const int64_t ld = 3 * c->nn;
+    double *V = c->V;
+    double *tmp, *pc = nullptr;
+    if ((st = ws_vec(c, 0, &tmp))) return st;
+    // preconditioner setup
+    if (precond == MF_PC_JACOBI) {
+        if ((st = ws_vec(c, 1, &pc))) return st;
+        if (op->kind == MF_HEAT) {
+            HIPCHK(c, heat_diagonal(c->km, heat_args(op), 0, pc, s));
+        } else {
+            // diagonal of the 3x3 blocks
+            if (!c->blocks && hipMalloc((void **)&c->blocks, sizeof(double) * 9 * c->nn) != hipSuccess)
+                return fail(c, MF_ERR_OOM, "block allocation failed");
+            HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), c->blocks, s));
+            for (int comp = 0; comp < 3; ++comp)
+                HIPCHK(c, hipMemcpy2DAsync(pc + comp * c->nn, sizeof(double), c->blocks + 4 * comp, 9 * sizeof(double),
+                                           sizeof(double), c->nn, hipMemcpyDeviceToDevice, s));
+        }
+        HIPCHK(c, vinv(pc, n, s));
+    } else if (precond == MF_PC_BLOCK_JACOBI) {
+        if (!c->blocks && hipMalloc((void **)&c->blocks, sizeof(double) * 9 * c->nn) != hipSuccess)
+            return fail(c, MF_ERR_OOM, "block allocation failed");
+        HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), c->blocks, s));
+        HIPCHK(c, block3_invert(c->blocks, c->nn, s));
+    }
+    double *zt;
+    if ((st = ws_vec(c, 2, &zt))) return st;
+    auto prec = [&](const double *in, double *out) -> hipError_t {
+        if (precond == MF_PC_JACOBI) return vmul(pc, in, out, n, s);
+        if (precond == MF_PC_BLOCK_JACOBI) {
+            if (transpose) return hipErrorInvalidValue; // handled below by not allowing it
+            return block3_apply(c->blocks, in, out, c->nn, s);
+        }
+        return vcopy(in, out, n, s);
+    };
+    if (precond == MF_PC_BLOCK_JACOBI && transpose)
+        return fail(c, MF_ERR_ARG, "block Jacobi for the transposed system is not provided");
+
+    RedWS red = redws(c);
+    double bnorm2;
+    if ((st = host_dot(c, b, b, n, &bnorm2, s))) return st;
+    const double bnorm = sqrt(bnorm2);
+    HIPCHK(c, vfill(x, 0.0, n, 0, s));
+    info->iters = 0;
+    info->converged = 0;
+    info->rel_res = 1.0;
+    info->rel_res_est = 1.0;
+    if (bnorm == 0.0) {
+        info->converged = 1;
+        info->rel_res = info->rel_res_est = 0.0;
+        return MF_OK;
+    }
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1);
+    int total = 0;
+    bool conv = false;
+    while (total < maxit) {
+        // r = b - A x into V_0
+        HIPCHK(c, apply_any(c, op, transpose, x, tmp, s));
+        HIPCHK(c, vcopy(b, V, n, s));
+        HIPCHK(c, vaxpby(-1.0, tmp, 1.0, V, n, s));
+        double beta2;
+        if ((st = host_dot(c, V, V, n, &beta2, s))) return st;
+        const double beta = sqrt(beta2);
+        info->rel_res = beta / bnorm;
+        if (beta / bnorm <= rtol) {
+            conv = true;
+            break;
+        }
+        HIPCHK(c, vaxpby(1.0 / beta, V, 0.0, V, n, s));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jdone = 0;
+        bool inner = false;
+        for (int j = 0; j < m; ++j) {
+            double *w = V + (int64_t)(j + 1) * ld;
+            HIPCHK(c, prec(V + (int64_t)j * ld, zt));
+            HIPCHK(c, apply_any(c, op, transpose, zt, w, s));
+            ++total;
+            // two passes of classical Gram-Schmidt
+            double *hd = c->scal;
+            HIPCHK(c, vmultidot(V, ld, j + 1, w, n, hd, &red, s));
+            HIPCHK(c, vmultiaxpy(V, ld, j + 1, hd, w, n, nullptr, &red, s));
+            HIPCHK(c, hipMemcpyAsync(c->h_scal, hd, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, vmultidot(V, ld, j + 1, w, n, hd + 64, &red, s));
+            HIPCHK(c, vmultiaxpy(V, ld, j + 1, hd + 64, w, n, hd + 128, &red, s));
+            HIPCHK(c, hipMemcpyAsync(c->h_scal + 64, hd + 64, sizeof(double) * 65, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[i * m + j] = c->h_scal[i] + c->h_scal[64 + i];
+            const double hn = sqrt(c->h_scal[128]);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0.0) HIPCHK(c, vaxpby(1.0 / hn, w, 0.0, w, n, s));
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = hypot(H[j * m + j], H[(j + 1) * m + j]);
+            if (!(den > 0.0) || !isfinite(den)) {
+                jdone = j;
+                info->iters = total;
+                return fail(c, MF_BREAKDOWN, "GMRES breakdown at step %d", total);
+            }
+            cs[j] = H[j * m + j] / den;
+            sn[j] = H[(j + 1) * m + j] / den;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            jdone = j + 1;
+            info->rel_res_est = fabs(g[j + 1]) / bnorm;
+            if (info->rel_res_est <= rtol || total >= maxit) {
+                inner = info->rel_res_est <= rtol;
+                break;
+            }
+        }
+        // y = H^{-1} g (upper triangular), x += M^{-1} V y
+        for (int i = jdone - 1; i >= 0; --i) {
+            double v = g[i];
+            for (int k = i + 1; k < jdone; ++k) v -= H[i * m + k] * h[k];
+            h[i] = v / H[i * m + i];
+        }
+        HIPCHK(c, hipMemcpyAsync(c->scal, h.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
+        HIPCHK(c, vcombine(V, ld, jdone, c->scal, tmp, n, s));
+        HIPCHK(c, prec(tmp, zt));
+        HIPCHK(c, vaxpby(1.0, zt, 1.0, x, n, s));
+        HIPCHK(c, hipStreamSynchronize(s)); // h is a host vector reused by the next cycle
+        (void)inner;
+    }
+    info->iters = total;
+    double tr;
+    if ((st = true_residual(c, op, transpose, b, x, tmp, bnorm, &tr, s))) return st;
+    info->rel_res = tr;
+    info->converged = tr <= rtol;
+    if (!info->converged) return fail(c, MF_NOT_CONVERGED, "GMRES reached maxit = %d (rel. res. %g)", maxit, tr);
+    (void)conv;
+    return MF_OK;
+}

@@ -1,0 +1,110 @@
+// kernels.hpp -- internal launcher interface between the C ABI (api.hip) and
+// the kernel translation units.  Not part of the public boundary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mf_common.hpp"
+
+namespace mf {
+
+// Coefficients of the heat operator as the kernels take them.
+struct HeatArgs {
+    int mode;        // 0: from nodal phi, 1: per quadrature point
+    int hkind;       // Heaviside form
+    double eps;
+    double am, ak;   // alpha_m, alpha_k
+    double k_l, k_g, rc_l, rc_g;
+    const void *phi, *kq, *rcq;
+};
+
+// Coefficients of the Oseen operator.
+struct OseenArgs {
+    int hkind;
+    double eps;
+    double am, ac, av;
+    double rho_l, rho_g, mu_l, mu_g;
+    const double *phi, *u0;
+};
+
+// Device state of a CG solve; scalars never leave the device during the
+// iteration except for the periodic convergence check.
+struct CGState {
+    double rz, pAp, rr, bb, alpha, beta, thresh2;
+    int iter, maxit, done, breakdown, flexible;
+    double rz_prev_cross; // r_{k+1}.z_k for the flexible (Polak-Ribiere) variant
+};
+
+// Reduction workspace of one kernel: NV partial sets of nblocks doubles and
+// an arrival counter (reset to zero by the finalizing block).
+struct RedWS {
+    double *partials;
+    unsigned *counter;
+    unsigned capacity; // max partial entries
+};
+
+// ---- heat (heat.hip) ----
+hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, CGState *cg,
+                      const RedWS *red, hipStream_t s);
+hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, hipStream_t s);
+hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double *rcq, hipStream_t s);
+hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
+hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,
+                     double *dk, double *drc, double *dphi, hipStream_t s);
+
+// ---- Oseen (oseen.hip) ----
+hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y,
+                       hipStream_t s);
+hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, hipStream_t s);
+
+// ---- vectors and Krylov steps (vec.hip) ----
+hipError_t vfill(void *y, double v, int64_t n, int fp32, hipStream_t s);
+hipError_t vcopy(const double *x, double *y, int64_t n, hipStream_t s);
+hipError_t vaxpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s); // y = a x + b y
+hipError_t vscale_copy(const double *scale_dev, int invert, const double *x, double *y, int64_t n,
+                       hipStream_t s); // y = x * (*s) or x / (*s)
+hipError_t vmul(const double *d, const double *x, double *y, int64_t n, hipStream_t s); // y = d .* x
+hipError_t vinv(double *d, int64_t n, hipStream_t s);                                   // d = 1 / d
+hipError_t vcvt_d2f(const double *x, float *y, int64_t n, hipStream_t s);
+hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+hipError_t vmulf(const float *d, const float *x, float *y, int64_t n, hipStream_t s);
+hipError_t vinvf(float *d, int64_t n, hipStream_t s);
+// out[k] = sum_i V_k[i] w[i] for k < nv (V columns of length n, leading dim ld);
+// nv = 1 with V = x gives a plain dot product.  out is device memory.
+hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out,
+                     const RedWS *red, hipStream_t s);
+// w -= sum_k V_k h[k] (h device), optionally out_norm2 = ||w||^2 after the update.
+hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n,
+                      double *out_norm2, const RedWS *red, hipStream_t s);
+// y = sum_k V_k h[k] (h device)
+hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double *y, int64_t n, hipStream_t s);
+hipError_t block3_invert(double *blocks, int64_t nn, hipStream_t s);
+hipError_t block3_apply(const double *binv, const double *x, double *y, int64_t nn, hipStream_t s);
+
+hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *z, double *p,
+                   double *q, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s);
+hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, double *z, const double *p, double *q,
+                     int64_t n, const RedWS *red, hipStream_t s);
+hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, hipStream_t s);
+// Flexible-CG pieces: the preconditioner output z is supplied by the caller.
+hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n,
+                         const RedWS *red, hipStream_t s);
+hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
+                   hipStream_t s);
+hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s);
+
+// ---- multigrid (mg.hip) ----
+hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s);
+hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, hipStream_t s);
+hipError_t mg_inject(const KMesh &fine, const KMesh &coarse, const void *phif, void *phic, int fp32,
+                     hipStream_t s);
+// Chebyshev pieces in FP32 (see mg.hip)
+hipError_t cheb_first(const float *dinv, const float *r, float *d, float *x, float inv_theta, int x_zero,
+                      int64_t n, hipStream_t s);
+hipError_t cheb_step(const float *dinv, float *r, const float *Ad, float *d, float *x, float c1, float c2,
+                     int64_t n, hipStream_t s);
+hipError_t vsub_f(const float *b, const float *Ax, float *r, int64_t n, hipStream_t s); // r = b - Ax
+hipError_t vadd_f(const float *a, float *y, int64_t n, hipStream_t s);                  // y += a
+
+} // namespace mf

@@ -1,0 +1,262 @@
+// mf_common.hpp -- shared device definitions of the gfx950 matrix-free library.
+//
+// Q2 Lagrange elements on uniform hexahedra with 3x3x3 Gauss quadrature
+// (App. B "Numerical framework": degree-2 elements, (k+1)^dim Gauss points).
+// Everything a cell needs is expressed through three 3x3 matrices acting
+// along one direction at a time (sum factorization):
+//   S[q][a]  = l_a(xi_q)     value of node basis a at Gauss point q
+//   D[q][p]  = L_p'(xi_q)    derivative of the Lagrange polynomial through
+//                            the Gauss points (collocation derivative):
+//                            exact for the quadratic restriction of a Q2
+//                            function to a line
+//   G[q][a]  = l_a'(xi_q)    = (D S)[q][a]
+// With r = sqrt(15)/10 and xi = (1/2 - r, 1/2, 1/2 + r) these are
+//   S = [[.3+r, .4, .3-r], [0, 1, 0], [.3-r, .4, .3+r]]
+//   D = (1/r) [[-3/2, 2, -1/2], [-1/2, 0, 1/2], [1/2, -2, 3/2]]
+//   G = [[-1-4r, 8r, 1-4r], [-1, 0, 1], [-1+4r, -8r, 1+4r]]
+// and the weights are (5/18, 4/9, 5/18).  The 1/r of D is folded into the
+// stiffness factors (it enters squared), so the kernels use D' = r D.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+constexpr double kR = 0.38729833462074168851792653997823996;  // sqrt(15)/10
+constexpr double kW0 = 5.0 / 18.0, kW1 = 4.0 / 9.0;
+
+// Device mesh description (uniform box).
+struct KMesh {
+    int nx, ny, nz;     // cells
+    int NX, NY, NZ;     // nodes per direction (2n+1)
+    unsigned dirichlet; // face bits
+    double hx, hy, hz;  // cell edges
+    double lox, loy, loz;
+};
+
+__device__ __forceinline__ bool node_constrained(const KMesh &m, int i, int j, int k)
+{
+    const unsigned f = m.dirichlet;
+    return ((f & 1u) && i == 0) || ((f & 2u) && i == m.NX - 1) || ((f & 4u) && j == 0) ||
+           ((f & 8u) && j == m.NY - 1) || ((f & 16u) && k == 0) || ((f & 32u) && k == m.NZ - 1);
+}
+
+__device__ __forceinline__ int64_t node_index(const KMesh &m, int i, int j, int k)
+{
+    return (int64_t)i + (int64_t)m.NX * ((int64_t)j + (int64_t)m.NY * k);
+}
+
+// ---------------------------------------------------------------------------
+// 1D line operators on 3 values (in -> out), templated on the real type.
+// ---------------------------------------------------------------------------
+
+template <typename T> struct Q2 {
+    static constexpr T s0 = T(0.3 + kR), s1 = T(0.4), s2 = T(0.3 - kR);
+    static constexpr T g0 = T(-1.0 - 4.0 * kR), g1 = T(8.0 * kR), g2 = T(1.0 - 4.0 * kR);
+    static constexpr T w0 = T(kW0), w1 = T(kW1);
+
+    // values at Gauss points: out = S in
+    static __device__ __forceinline__ void interp(T i0, T i1, T i2, T &o0, T &o1, T &o2)
+    {
+        o0 = s0 * i0 + s1 * i1 + s2 * i2;
+        o1 = i1;
+        o2 = s2 * i0 + s1 * i1 + s0 * i2;
+    }
+    // integration against node basis: out = S^T in
+    static __device__ __forceinline__ void interpT(T i0, T i1, T i2, T &o0, T &o1, T &o2)
+    {
+        o0 = s0 * i0 + s2 * i2;
+        o1 = s1 * (i0 + i2) + i1;
+        o2 = s2 * i0 + s0 * i2;
+    }
+    // collocation derivative (scaled by r): out = D' in
+    static __device__ __forceinline__ void deriv(T i0, T i1, T i2, T &o0, T &o1, T &o2)
+    {
+        o0 = T(-1.5) * i0 + T(2) * i1 - T(0.5) * i2;
+        o1 = T(0.5) * (i2 - i0);
+        o2 = T(0.5) * i0 - T(2) * i1 + T(1.5) * i2;
+    }
+    // transposed collocation derivative accumulated: out += D'^T in
+    static __device__ __forceinline__ void derivT_acc(T i0, T i1, T i2, T &o0, T &o1, T &o2)
+    {
+        o0 += T(-1.5) * i0 - T(0.5) * i1 + T(0.5) * i2;
+        o1 += T(2) * (i0 - i2);
+        o2 += T(-0.5) * i0 + T(0.5) * i1 + T(1.5) * i2;
+    }
+    static __device__ __forceinline__ T weight(int q) { return q == 1 ? w1 : w0; }
+};
+
+// Apply a line operator along direction DIR of a 3x3x3 register array
+// (index a + 3b + 9c).
+template <int DIR> __device__ __forceinline__ constexpr int lidx(int l, int m, int n)
+{
+    // l runs along DIR; (m, n) enumerate the other two directions
+    return DIR == 0 ? l + 3 * m + 9 * n : (DIR == 1 ? m + 3 * l + 9 * n : m + 3 * n + 9 * l);
+}
+
+template <typename T, int DIR, typename F>
+__device__ __forceinline__ void line_apply(const T *in, T *out, F f)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            T o0, o1, o2;
+            f(in[lidx<DIR>(0, m, n)], in[lidx<DIR>(1, m, n)], in[lidx<DIR>(2, m, n)], o0, o1, o2);
+            out[lidx<DIR>(0, m, n)] = o0;
+            out[lidx<DIR>(1, m, n)] = o1;
+            out[lidx<DIR>(2, m, n)] = o2;
+        }
+}
+
+// in-place S along all three directions: nodal -> Gauss point values
+template <typename T> __device__ __forceinline__ void interp3(T *v)
+{
+    auto f = [](T a, T b, T c, T &x, T &y, T &z) { Q2<T>::interp(a, b, c, x, y, z); };
+    line_apply<T, 0>(v, v, f);
+    line_apply<T, 1>(v, v, f);
+    line_apply<T, 2>(v, v, f);
+}
+
+// in-place S^T along all three directions: Gauss point values -> nodal integrals
+template <typename T> __device__ __forceinline__ void interp3T(T *v)
+{
+    auto f = [](T a, T b, T c, T &x, T &y, T &z) { Q2<T>::interpT(a, b, c, x, y, z); };
+    line_apply<T, 0>(v, v, f);
+    line_apply<T, 1>(v, v, f);
+    line_apply<T, 2>(v, v, f);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void deriv_dir(const T *in, T *out)
+{
+    auto f = [](T a, T b, T c, T &x, T &y, T &z) { Q2<T>::deriv(a, b, c, x, y, z); };
+    line_apply<T, DIR>(in, out, f);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void derivT_acc_dir(const T *in, T *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            Q2<T>::derivT_acc(in[lidx<DIR>(0, m, n)], in[lidx<DIR>(1, m, n)], in[lidx<DIR>(2, m, n)],
+                              acc[lidx<DIR>(0, m, n)], acc[lidx<DIR>(1, m, n)], acc[lidx<DIR>(2, m, n)]);
+}
+
+// Along direction DIR, line by line: t = D' u, g = c .* t * ih, acc += D'^T g.
+// Returns sum t.g (the line's contribution to the energy) through `energy`.
+// Working on one 3-point line at a time keeps only 3 temporaries live.
+template <typename T, int DIR>
+__device__ __forceinline__ void grad_line_apply(const T *u, const T *c, T ih, T *acc, double &energy)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            T t0, t1, t2;
+            Q2<T>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
+            const T g0 = c[i0] * ih * t0, g1 = c[i1] * ih * t1, g2 = c[i2] * ih * t2;
+            energy += (double)(t0 * g0 + t1 * g1 + t2 * g2);
+            Q2<T>::derivT_acc(g0, g1, g2, acc[i0], acc[i1], acc[i2]);
+        }
+}
+
+// Along direction DIR: out += ih * (D' a) .* (D' b), line by line.
+template <typename T, int DIR>
+__device__ __forceinline__ void grad_dot_acc(const T *a, const T *b, T ih, T *out)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            T a0, a1, a2, b0, b1, b2;
+            Q2<T>::deriv(a[i0], a[i1], a[i2], a0, a1, a2);
+            Q2<T>::deriv(b[i0], b[i1], b[i2], b0, b1, b2);
+            out[i0] += ih * a0 * b0;
+            out[i1] += ih * a1 * b1;
+            out[i2] += ih * a2 * b2;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Smoothed Heaviside (Sec. 2.3, eq. heaviside) and its derivative.
+// kind 0: H = clamp((1+phi)/2, 0, 1).  kind 1: sine form with the signed
+// distance d = 2 eps artanh(phi) recovered from the tanh profile.
+// ---------------------------------------------------------------------------
+
+template <typename T> __device__ __forceinline__ T heaviside(int kind, T eps, T phi, T *dH)
+{
+    if (kind == 0) {
+        if (phi <= T(-1)) { if (dH) *dH = T(0); return T(0); }
+        if (phi >= T(1)) { if (dH) *dH = T(0); return T(1); }
+        if (dH) *dH = T(0.5);
+        return T(0.5) + T(0.5) * phi;
+    }
+    const double lim = 1.0 - 1e-15;
+    double p = (double)phi;
+    p = p < -lim ? -lim : (p > lim ? lim : p);
+    const double e = (double)eps;
+    const double d = 2.0 * e * atanh(p);
+    if (d <= -3.0 * e) { if (dH) *dH = T(0); return T(0); }
+    if (d >= 3.0 * e) { if (dH) *dH = T(0); return T(1); }
+    const double a = M_PI * d / (3.0 * e);
+    if (dH) *dH = T((1.0 + cos(a)) / (6.0 * e) * (2.0 * e / (1.0 - p * p)));
+    return T(0.5 + d / (6.0 * e) + sin(a) / (2.0 * M_PI));
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions.  A block sums its threads' values in a fixed
+// tree order; blocks publish one partial each; the last block to arrive
+// (agent-scope counter) sums the partials in index order and runs a
+// finalize step.  Nothing spins or waits on other blocks.
+// ---------------------------------------------------------------------------
+
+template <int NT> __device__ __forceinline__ double block_sum(double v, double *red)
+{
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Publish NV partial sums of this block (valid in thread 0); returns true in
+// every thread of the block that completes the set.  partials: [NV][nblocks].
+template <int NV>
+__device__ __forceinline__ bool publish_partials(const double *v, double *partials, unsigned *counter,
+                                                 unsigned nblocks, int *flag_lds)
+{
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            __hip_atomic_store(&partials[(size_t)i * nblocks + blockIdx.x], v[i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        *flag_lds = (prev == nblocks - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    __syncthreads();
+    return last;
+}
+
+// In the last block: sum partial set i over all blocks in index order.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double *partials, unsigned nblocks, int i, double *red)
+{
+    double s = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += NT)
+        s += __hip_atomic_load(&partials[(size_t)i * nblocks + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return block_sum<NT>(s, red);
+}
+
+} // namespace mf

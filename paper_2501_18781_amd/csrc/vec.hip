@@ -1,0 +1,520 @@
+// vec.hip -- vector kernels and the fused Krylov steps (App. B: CG and GMRES).
+//
+// Reductions are deterministic: every thread accumulates a fixed
+// grid-stride subsequence, wavefronts reduce with shuffles in a fixed order,
+// the waves of a block through LDS, and the last block to finish sums the
+// per-block partials in index order.  Solver scalars (alpha, beta, residual
+// norms, iteration count, convergence flag) live in device memory; kernels
+// read them directly and become no-ops once the solve is done, so the host
+// only synchronizes to poll convergence.
+#include "kernels.hpp"
+
+namespace mf {
+
+constexpr int VNT = 256;   // threads per block of the vector kernels
+constexpr int VMAXB = 1024; // max blocks of a reduction kernel
+constexpr int MAXV = 32;   // max vectors in a multi-dot
+
+static unsigned vec_blocks(int64_t n)
+{
+    int64_t b = (n + VNT * 4 - 1) / (VNT * 4);
+    if (b < 1) b = 1;
+    if (b > VMAXB) b = VMAXB;
+    return (unsigned)b;
+}
+
+static unsigned ew_blocks(int64_t n)
+{
+    int64_t b = (n + VNT - 1) / VNT;
+    if (b > 65535 * 16) b = 65535 * 16;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+#define GRID_STRIDE(i, n) for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v; // valid in lane 0
+}
+
+// Sum NV per-thread values over the block; results valid in thread 0 (out[]).
+template <int NV> __device__ __forceinline__ void block_sum_n(double *v, double *lds /*[NV][VNT/64]*/)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0) lds[k * (VNT / 64) + wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < VNT / 64; ++w) s += lds[k * (VNT / 64) + w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Last-block finalize helper: returns true in the block completing the set;
+// then tot[k] (thread 0) holds the grid sums.
+template <int NV>
+__device__ __forceinline__ bool grid_sum_n(double *v, const RedWS &red, double *lds, int *flag)
+{
+    block_sum_n<NV>(v, lds);
+    if (!publish_partials<NV>(v, red.partials, red.counter, gridDim.x, flag)) return false;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += VNT)
+            s += __hip_atomic_load(&red.partials[(size_t)k * gridDim.x + b], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        s = wave_sum(s);
+        if (lane == 0) lds[k * (VNT / 64) + wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < VNT / 64; ++w) s += lds[k * (VNT / 64) + w];
+            v[k] = s;
+        }
+        __hip_atomic_store(red.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels
+// ---------------------------------------------------------------------------
+template <typename T> __global__ void fill_kernel(T *y, T v, int64_t n)
+{
+    GRID_STRIDE(i, n) y[i] = v;
+}
+
+hipError_t vfill(void *y, double v, int64_t n, int fp32, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (fp32) fill_kernel<float><<<ew_blocks(n), VNT, 0, s>>>((float *)y, (float)v, n);
+    else fill_kernel<double><<<ew_blocks(n), VNT, 0, s>>>((double *)y, v, n);
+    return hipGetLastError();
+}
+
+__global__ void copy_kernel(const double *x, double *y, int64_t n) { GRID_STRIDE(i, n) y[i] = x[i]; }
+hipError_t vcopy(const double *x, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    copy_kernel<<<ew_blocks(n), VNT, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+
+__global__ void axpby_kernel(double a, const double *x, double b, double *y, int64_t n)
+{
+    GRID_STRIDE(i, n) y[i] = a * x[i] + b * y[i];
+}
+hipError_t vaxpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    axpby_kernel<<<ew_blocks(n), VNT, 0, s>>>(a, x, b, y, n);
+    return hipGetLastError();
+}
+
+__global__ void scale_copy_kernel(const double *sc, int invert, const double *x, double *y, int64_t n)
+{
+    const double f = invert ? 1.0 / sc[0] : sc[0];
+    GRID_STRIDE(i, n) y[i] = x[i] * f;
+}
+hipError_t vscale_copy(const double *sc, int invert, const double *x, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    scale_copy_kernel<<<ew_blocks(n), VNT, 0, s>>>(sc, invert, x, y, n);
+    return hipGetLastError();
+}
+
+template <typename T> __global__ void mul_kernel(const T *d, const T *x, T *y, int64_t n)
+{
+    GRID_STRIDE(i, n) y[i] = d[i] * x[i];
+}
+template <typename T> __global__ void inv_kernel(T *d, int64_t n) { GRID_STRIDE(i, n) d[i] = T(1) / d[i]; }
+
+hipError_t vmul(const double *d, const double *x, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    mul_kernel<double><<<ew_blocks(n), VNT, 0, s>>>(d, x, y, n);
+    return hipGetLastError();
+}
+hipError_t vmulf(const float *d, const float *x, float *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    mul_kernel<float><<<ew_blocks(n), VNT, 0, s>>>(d, x, y, n);
+    return hipGetLastError();
+}
+hipError_t vinv(double *d, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    inv_kernel<double><<<ew_blocks(n), VNT, 0, s>>>(d, n);
+    return hipGetLastError();
+}
+hipError_t vinvf(float *d, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    inv_kernel<float><<<ew_blocks(n), VNT, 0, s>>>(d, n);
+    return hipGetLastError();
+}
+
+__global__ void d2f_kernel(const double *x, float *y, int64_t n) { GRID_STRIDE(i, n) y[i] = (float)x[i]; }
+__global__ void f2d_kernel(const float *x, double *y, int64_t n) { GRID_STRIDE(i, n) y[i] = (double)x[i]; }
+hipError_t vcvt_d2f(const double *x, float *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    d2f_kernel<<<ew_blocks(n), VNT, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    f2d_kernel<<<ew_blocks(n), VNT, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Multi-dot, multi-axpy, combination (GMRES Gram-Schmidt)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(VNT) multidot_kernel(const double *__restrict__ V, int64_t ld, int nv,
+                                                       const double *__restrict__ w, int64_t n, double *out, RedWS red)
+{
+    __shared__ double lds[MAXV * (VNT / 64)];
+    __shared__ int flag;
+    double acc[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) acc[k] = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k < nv) acc[k] += V[(int64_t)k * ld + i] * wi;
+    }
+    if (grid_sum_n<MAXV>(acc, red, lds, &flag) && threadIdx.x == 0) {
+        for (int k = 0; k < nv; ++k) out[k] = acc[k];
+    }
+}
+
+hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out, const RedWS *red,
+                     hipStream_t s)
+{
+    if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < nb * MAXV) return hipErrorInvalidValue;
+    multidot_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, w, n, out, *red);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict__ V, int64_t ld, int nv,
+                                                        const double *__restrict__ h, double *__restrict__ w, int64_t n,
+                                                        double *out_norm2, RedWS red)
+{
+    __shared__ double lds[VNT / 64];
+    __shared__ int flag;
+    __shared__ double hs[MAXV];
+    if (threadIdx.x < MAXV) hs[threadIdx.x] = threadIdx.x < (unsigned)nv ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        double v = w[i];
+        for (int k = 0; k < nv; ++k) v -= V[(int64_t)k * ld + i] * hs[k];
+        w[i] = v;
+        acc += v * v;
+    }
+    if (out_norm2) {
+        if (grid_sum_n<1>(&acc, red, lds, &flag) && threadIdx.x == 0) *out_norm2 = acc;
+    }
+}
+
+hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out_norm2,
+                      const RedWS *red, hipStream_t s)
+{
+    if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
+    const unsigned nb = vec_blocks(n);
+    if (out_norm2 && red->capacity < nb) return hipErrorInvalidValue;
+    multiaxpy_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, h, w, n, out_norm2, red ? *red : RedWS{nullptr, nullptr, 0});
+    return hipGetLastError();
+}
+
+__global__ void combine_kernel(const double *__restrict__ V, int64_t ld, int nv, const double *__restrict__ h,
+                               double *__restrict__ y, int64_t n)
+{
+    __shared__ double hs[MAXV];
+    if (threadIdx.x < MAXV) hs[threadIdx.x] = threadIdx.x < (unsigned)nv ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    GRID_STRIDE(i, n)
+    {
+        double v = 0.0;
+        for (int k = 0; k < nv; ++k) v += V[(int64_t)k * ld + i] * hs[k];
+        y[i] = v;
+    }
+}
+
+hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double *y, int64_t n, hipStream_t s)
+{
+    if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
+    combine_kernel<<<ew_blocks(n), VNT, 0, s>>>(V, ld, nv, h, y, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 nodal blocks ([node][3][3], row-major): inversion by cofactors and
+// application to component-major vectors.
+// ---------------------------------------------------------------------------
+__global__ void block3_invert_kernel(double *B, int64_t nn)
+{
+    GRID_STRIDE(i, nn)
+    {
+        double *a = B + 9 * i;
+        const double c00 = a[4] * a[8] - a[5] * a[7], c01 = a[5] * a[6] - a[3] * a[8], c02 = a[3] * a[7] - a[4] * a[6];
+        const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+        const double id = 1.0 / det;
+        const double r[9] = {c00 * id, (a[2] * a[7] - a[1] * a[8]) * id, (a[1] * a[5] - a[2] * a[4]) * id,
+                             c01 * id, (a[0] * a[8] - a[2] * a[6]) * id, (a[2] * a[3] - a[0] * a[5]) * id,
+                             c02 * id, (a[1] * a[6] - a[0] * a[7]) * id, (a[0] * a[4] - a[1] * a[3]) * id};
+        for (int k = 0; k < 9; ++k) a[k] = r[k];
+    }
+}
+hipError_t block3_invert(double *B, int64_t nn, hipStream_t s)
+{
+    block3_invert_kernel<<<ew_blocks(nn), VNT, 0, s>>>(B, nn);
+    return hipGetLastError();
+}
+
+__global__ void block3_apply_kernel(const double *__restrict__ B, const double *__restrict__ x, double *__restrict__ y,
+                                    int64_t nn)
+{
+    GRID_STRIDE(i, nn)
+    {
+        const double *a = B + 9 * i;
+        const double x0 = x[i], x1 = x[nn + i], x2 = x[2 * nn + i];
+        y[i] = a[0] * x0 + a[1] * x1 + a[2] * x2;
+        y[nn + i] = a[3] * x0 + a[4] * x1 + a[5] * x2;
+        y[2 * nn + i] = a[6] * x0 + a[7] * x1 + a[8] * x2;
+    }
+}
+hipError_t block3_apply(const double *B, const double *x, double *y, int64_t nn, hipStream_t s)
+{
+    block3_apply_kernel<<<ew_blocks(nn), VNT, 0, s>>>(B, x, y, nn);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// CG (preconditioned with a diagonal, Saad Alg. 9.1)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(VNT) cg_init_kernel(CGState *st, const double *__restrict__ b,
+                                                      const double *__restrict__ dinv, double *__restrict__ x,
+                                                      double *__restrict__ r, double *__restrict__ z,
+                                                      double *__restrict__ p, double *__restrict__ q, int64_t n,
+                                                      double rtol, int maxit, int flexible, RedWS red)
+{
+    __shared__ double lds[2 * (VNT / 64)];
+    __shared__ int flag;
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n)
+    {
+        const double bi = b[i];
+        x[i] = 0.0;
+        r[i] = bi;
+        q[i] = 0.0;
+        if (!flexible) {
+            const double zi = dinv ? dinv[i] * bi : bi;
+            z[i] = zi;
+            p[i] = zi;
+            acc[0] += bi * zi;
+        } else {
+            p[i] = 0.0;
+        }
+        acc[1] += bi * bi;
+    }
+    if (grid_sum_n<2>(acc, red, lds, &flag) && threadIdx.x == 0) {
+        st->rz = acc[0];
+        st->rr = acc[1];
+        st->bb = acc[1];
+        st->thresh2 = rtol * rtol * acc[1];
+        st->iter = 0;
+        st->maxit = maxit;
+        st->breakdown = 0;
+        st->flexible = flexible;
+        st->alpha = 0.0;
+        st->beta = 0.0;
+        st->pAp = 0.0;
+        st->done = (acc[1] == 0.0 || maxit <= 0) ? 1 : 0;
+    }
+}
+
+hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *z, double *p,
+                   double *q, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < 2 * nb) return hipErrorInvalidValue;
+    cg_init_kernel<<<nb, VNT, 0, s>>>(st, b, dinv, x, r, z, p, q, n, rtol, maxit, flexible, *red);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(VNT) cg_update_kernel(CGState *st, const double *__restrict__ dinv,
+                                                        double *__restrict__ x, double *__restrict__ r,
+                                                        double *__restrict__ z, const double *__restrict__ p,
+                                                        double *__restrict__ q, int64_t n, RedWS red)
+{
+    __shared__ double lds[2 * (VNT / 64)];
+    __shared__ int flag;
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n)
+    {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        q[i] = 0.0;
+        const double zi = dinv ? dinv[i] * ri : ri;
+        z[i] = zi;
+        acc[0] += ri * zi;
+        acc[1] += ri * ri;
+    }
+    if (grid_sum_n<2>(acc, red, lds, &flag) && threadIdx.x == 0) {
+        st->iter += 1;
+        st->rr = acc[1];
+        if (!isfinite(acc[0]) || !isfinite(acc[1])) {
+            st->breakdown = 1;
+            st->done = 1;
+        } else if (acc[1] <= st->thresh2 || st->iter >= st->maxit) {
+            st->done = 1;
+        }
+        st->beta = acc[0] / st->rz;
+        st->rz = acc[0];
+    }
+}
+
+hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, double *z, const double *p, double *q,
+                     int64_t n, const RedWS *red, hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < 2 * nb) return hipErrorInvalidValue;
+    cg_update_kernel<<<nb, VNT, 0, s>>>(st, dinv, x, r, z, p, q, n, *red);
+    return hipGetLastError();
+}
+
+__global__ void cg_pupdate_kernel(const CGState *st, const double *__restrict__ z, double *__restrict__ p, int64_t n)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
+}
+
+hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, hipStream_t s)
+{
+    cg_pupdate_kernel<<<ew_blocks(n), VNT, 0, s>>>(st, z, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Flexible CG (Notay): x, r update; then z = V(r) by the caller; then
+// beta = (r.z - r.z_prev) / rz_old (Polak-Ribiere), p = z + beta p.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(VNT) fcg_xr_kernel(CGState *st, double *__restrict__ x, double *__restrict__ r,
+                                                     const double *__restrict__ p, double *__restrict__ q, int64_t n,
+                                                     RedWS red)
+{
+    __shared__ double lds[VNT / 64];
+    __shared__ int flag;
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double acc = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        q[i] = 0.0;
+        acc += ri * ri;
+    }
+    if (grid_sum_n<1>(&acc, red, lds, &flag) && threadIdx.x == 0) {
+        st->iter += 1;
+        st->rr = acc;
+        if (!isfinite(acc)) {
+            st->breakdown = 1;
+            st->done = 1;
+        } else if (acc <= st->thresh2 || st->iter >= st->maxit) {
+            st->done = 1;
+        }
+    }
+}
+
+hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n, const RedWS *red,
+                         hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < nb) return hipErrorInvalidValue;
+    fcg_xr_kernel<<<nb, VNT, 0, s>>>(st, x, r, p, q, n, *red);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(VNT) fcg_dir_kernel(CGState *st, const double *__restrict__ r,
+                                                      const double *__restrict__ z, const double *__restrict__ zprev,
+                                                      int64_t n, RedWS red)
+{
+    __shared__ double lds[2 * (VNT / 64)];
+    __shared__ int flag;
+    if (st->done) return;
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n)
+    {
+        const double ri = r[i];
+        acc[0] += ri * z[i];
+        acc[1] += ri * zprev[i];
+    }
+    if (grid_sum_n<2>(acc, red, lds, &flag) && threadIdx.x == 0) {
+        // first direction: rz == 0 marks "no previous direction"
+        st->beta = (st->rz != 0.0) ? (acc[0] - acc[1]) / st->rz : 0.0;
+        st->rz = acc[0];
+        if (!isfinite(acc[0]) || !(acc[0] > 0.0)) {
+            st->breakdown = 1;
+            st->done = 1;
+        }
+    }
+}
+
+hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
+                   hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < 2 * nb) return hipErrorInvalidValue;
+    fcg_dir_kernel<<<nb, VNT, 0, s>>>(st, r, z, zprev, n, *red);
+    return hipGetLastError();
+}
+
+__global__ void fcg_pupdate_kernel(const CGState *st, const double *__restrict__ z, double *__restrict__ zprev,
+                                   double *__restrict__ p, int64_t n)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    GRID_STRIDE(i, n)
+    {
+        const double zi = z[i];
+        p[i] = zi + beta * p[i];
+        zprev[i] = zi;
+    }
+}
+
+hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s)
+{
+    fcg_pupdate_kernel<<<ew_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    return hipGetLastError();
+}
+
+} // namespace mf

@@ -1,0 +1,366 @@
+"""Thin Python binding of the gfx950 library ``libmf.so`` (C ABI in include/mf.h).
+
+Argument marshalling only: descriptor structs are filled from Python objects,
+torch tensors are checked (device, dtype, size, contiguity) and passed as raw
+device pointers together with torch's current HIP stream.  Every step of the
+computation runs in the library's kernels.  There is no fallback: if the
+library is not built, or no GPU is present, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmf.so")
+
+MF_OK, MF_NOT_CONVERGED, MF_BREAKDOWN = 0, 1, 2
+MF_HEAT, MF_OSEEN = 0, 1
+MF_FP64, MF_FP32 = 0, 1
+MF_COEFF_LEVELSET, MF_COEFF_QUAD = 0, 1
+MF_H_LINEAR, MF_H_SINE = 0, 1
+MF_PC_NONE, MF_PC_JACOBI, MF_PC_BLOCK_JACOBI = 0, 1, 2
+
+_STATUS = {0: "MF_OK", 1: "MF_NOT_CONVERGED", 2: "MF_BREAKDOWN", -1: "MF_ERR_ARG", -2: "MF_ERR_HIP",
+           -3: "MF_ERR_OOM", -4: "MF_ERR_STATE"}
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("dirichlet", ctypes.c_uint32),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class OperatorDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32), ("coeff_mode", ctypes.c_int32),
+                ("heaviside", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("alpha_m", ctypes.c_double), ("alpha_k", ctypes.c_double), ("alpha_c", ctypes.c_double),
+                ("alpha_v", ctypes.c_double), ("k_l", ctypes.c_double), ("k_g", ctypes.c_double),
+                ("rc_l", ctypes.c_double), ("rc_g", ctypes.c_double), ("rho_l", ctypes.c_double),
+                ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
+                ("phi", ctypes.c_void_p), ("k_q", ctypes.c_void_p), ("rc_q", ctypes.c_void_p),
+                ("u0", ctypes.c_void_p)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double)]
+
+    def __repr__(self):
+        return (f"SolveInfo(iters={self.iters}, converged={bool(self.converged)}, rel_res={self.rel_res:.3e}, "
+                f"rel_res_est={self.rel_res_est:.3e})")
+
+
+class MGParams(ctypes.Structure):
+    _fields_ = [("coarse_cells", ctypes.c_int32), ("degree", ctypes.c_int32), ("smoothing_range", ctypes.c_double),
+                ("eig_steps", ctypes.c_int32), ("eig_safety", ctypes.c_double),
+                ("lambda_max", ctypes.POINTER(ctypes.c_double)), ("coarse_rtol", ctypes.c_double),
+                ("coarse_maxit", ctypes.c_int32)]
+
+
+# Every function of the C ABI, with its argument types.
+_P = ctypes.c_void_p
+_SIGS = {
+    "mf_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)]),
+    "mf_destroy": (None, [_P]),
+    "mf_last_error": (ctypes.c_char_p, [_P]),
+    "mf_n_nodes": (ctypes.c_int64, [_P]),
+    "mf_n_cells": (ctypes.c_int64, [_P]),
+    "mf_operator_apply": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
+    "mf_operator_apply_transpose": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
+    "mf_operator_diagonal": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P]),
+    "mf_cg_solve": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.c_int32, _P, _P, ctypes.c_double,
+                                   ctypes.c_int32, ctypes.POINTER(SolveInfo), _P]),
+    "mf_gmres_solve": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.POINTER(SolveInfo), _P]),
+    "mf_mg_create": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.POINTER(MGParams),
+                                    ctypes.POINTER(_P), _P]),
+    "mf_mg_destroy": (None, [_P]),
+    "mf_mg_n_levels": (ctypes.c_int32, [_P]),
+    "mf_mg_lambda_max": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "mf_mg_vcycle": (ctypes.c_int, [_P, _P, _P, _P]),
+    "mf_mg_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SolveInfo), _P]),
+    "mf_quad_points": (ctypes.c_int, [_P, _P, _P]),
+    "mf_heat_qp_coeffs": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
+    "mf_heat_coeff_grad": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libmf.so (built in-tree by ``paper_2501_18781_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run __graft_entry__.build() or "
+                               f"python -m paper_2501_18781_amd.build")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _ptr(t: Optional[torch.Tensor], n: int, dtype: torch.dtype, name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Context:
+    """One mesh on the current device (wraps mf_ctx)."""
+
+    def __init__(self, mesh):
+        L = library()
+        d = MeshDesc()
+        for k in range(3):
+            d.n[k] = int(mesh.n[k])
+            d.lo[k] = float(getattr(mesh, "lo", (0, 0, 0))[k])
+            d.hi[k] = float(getattr(mesh, "hi", (1, 1, 1))[k])
+        d.dirichlet = int(getattr(mesh, "dirichlet", 0))
+        h = _P()
+        st = L.mf_create(ctypes.byref(d), ctypes.byref(h))
+        if st != MF_OK:
+            raise MFError(st, "mf_create failed")
+        self._h = h
+        self.mesh = mesh
+        self.n_nodes = int(L.mf_n_nodes(h))
+        self.n_cells = int(L.mf_n_cells(h))
+
+    def check(self, st: int, accept=(MF_OK,)):
+        if st not in accept:
+            raise MFError(st, library().mf_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().mf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """An operator descriptor plus the tensors it points to (kept alive here)."""
+
+    def __init__(self, ctx: Context, kind: int, precision: int, coeff_mode: int = MF_COEFF_LEVELSET,
+                 heaviside: int = MF_H_LINEAR, eps: float = 0.0, alpha_m=0.0, alpha_k=0.0, alpha_c=0.0, alpha_v=0.0,
+                 k_l=0.0, k_g=0.0, rc_l=0.0, rc_g=0.0, rho_l=1.0, rho_g=1.0, mu_l=0.0, mu_g=0.0,
+                 phi=None, k_q=None, rc_q=None, u0=None):
+        self.ctx = ctx
+        self.dtype = torch.float64 if precision == MF_FP64 else torch.float32
+        nn, nq = ctx.n_nodes, ctx.n_cells * 27
+        self.tensors = (phi, k_q, rc_q, u0)
+        d = OperatorDesc()
+        d.kind, d.precision, d.coeff_mode, d.heaviside = kind, precision, coeff_mode, heaviside
+        d.eps, d.alpha_m, d.alpha_k, d.alpha_c, d.alpha_v = eps, alpha_m, alpha_k, alpha_c, alpha_v
+        d.k_l, d.k_g, d.rc_l, d.rc_g = k_l, k_g, rc_l, rc_g
+        d.rho_l, d.rho_g, d.mu_l, d.mu_g = rho_l, rho_g, mu_l, mu_g
+        d.phi = _ptr(phi, nn, self.dtype, "phi")
+        d.k_q = _ptr(k_q, nq, self.dtype, "k_q")
+        d.rc_q = _ptr(rc_q, nq, self.dtype, "rc_q")
+        d.u0 = _ptr(u0, 3 * nn, self.dtype, "u0")
+        self.desc = d
+        self.kind = kind
+        self.n_dofs = 3 * nn if kind == MF_OSEEN else nn
+
+    def with_alphas(self, **alphas) -> "Operator":
+        """Same operator with some of alpha_m, alpha_k, alpha_c, alpha_v replaced."""
+        o = Operator.__new__(Operator)
+        o.__dict__.update(self.__dict__)
+        d = OperatorDesc()
+        ctypes.pointer(d)[0] = self.desc
+        for k, v in alphas.items():
+            setattr(d, k, float(v))
+        o.desc = d
+        return o
+
+
+def heat_operator(ctx: Context, params, phi=None, k_q=None, rc_q=None, precision=MF_FP64, **override) -> Operator:
+    """Heat operator rc/dt M + K(k) from a parameter object (k_l, k_g, rc_l,
+    rc_g, alpha_m, alpha_k, heaviside, eps)."""
+    g = lambda k: override.get(k, getattr(params, k))
+    mode = MF_COEFF_LEVELSET if phi is not None else MF_COEFF_QUAD
+    return Operator(ctx, MF_HEAT, precision, mode, int(g("heaviside")), float(g("eps")),
+                    alpha_m=float(g("alpha_m")), alpha_k=float(g("alpha_k")), k_l=g("k_l"), k_g=g("k_g"),
+                    rc_l=g("rc_l"), rc_g=g("rc_g"), phi=phi, k_q=k_q, rc_q=rc_q)
+
+
+def oseen_operator(ctx: Context, params, phi, u0, **override) -> Operator:
+    g = lambda k: override.get(k, getattr(params, k))
+    return Operator(ctx, MF_OSEEN, MF_FP64, MF_COEFF_LEVELSET, int(g("heaviside")), float(g("eps")),
+                    alpha_m=float(g("alpha_m")), alpha_c=float(g("alpha_c")), alpha_v=float(g("alpha_v")),
+                    rho_l=g("rho_l"), rho_g=g("rho_g"), mu_l=g("mu_l"), mu_g=g("mu_g"), phi=phi, u0=u0)
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI without the mf_ prefix)
+# ---------------------------------------------------------------------------
+
+def operator_apply(op: Operator, x: torch.Tensor, y: torch.Tensor, stream=None):
+    c = op.ctx
+    c.check(library().mf_operator_apply(c._h, ctypes.byref(op.desc), _ptr(x, op.n_dofs, op.dtype, "x"),
+                                        _ptr(y, op.n_dofs, op.dtype, "y"), _stream(stream)))
+    return y
+
+
+def operator_apply_transpose(op: Operator, x: torch.Tensor, y: torch.Tensor, stream=None):
+    c = op.ctx
+    c.check(library().mf_operator_apply_transpose(c._h, ctypes.byref(op.desc), _ptr(x, op.n_dofs, op.dtype, "x"),
+                                                  _ptr(y, op.n_dofs, op.dtype, "y"), _stream(stream)))
+    return y
+
+
+def operator_diagonal(op: Operator, diag: torch.Tensor, stream=None):
+    c = op.ctx
+    n = 9 * c.n_nodes if op.kind == MF_OSEEN else c.n_nodes
+    c.check(library().mf_operator_diagonal(c._h, ctypes.byref(op.desc), _ptr(diag, n, op.dtype, "diag"),
+                                           _stream(stream)))
+    return diag
+
+
+_SOLVER_OK = (MF_OK, MF_NOT_CONVERGED, MF_BREAKDOWN)
+
+
+def cg_solve(op: Operator, b: torch.Tensor, x: torch.Tensor, rtol: float, maxit: int, precond=MF_PC_JACOBI,
+             stream=None) -> SolveInfo:
+    c = op.ctx
+    info = SolveInfo()
+    st = library().mf_cg_solve(c._h, ctypes.byref(op.desc), precond, _ptr(b, op.n_dofs, torch.float64, "b"),
+                               _ptr(x, op.n_dofs, torch.float64, "x"), rtol, maxit, ctypes.byref(info),
+                               _stream(stream))
+    c.check(st, _SOLVER_OK)
+    info.status = st
+    return info
+
+
+def gmres_solve(op: Operator, b: torch.Tensor, x: torch.Tensor, rtol: float, maxit: int,
+                precond=MF_PC_BLOCK_JACOBI, restart: int = 30, transpose: bool = False, stream=None) -> SolveInfo:
+    c = op.ctx
+    info = SolveInfo()
+    st = library().mf_gmres_solve(c._h, ctypes.byref(op.desc), precond, restart, 1 if transpose else 0,
+                                  _ptr(b, op.n_dofs, torch.float64, "b"), _ptr(x, op.n_dofs, torch.float64, "x"),
+                                  rtol, maxit, ctypes.byref(info), _stream(stream))
+    c.check(st, _SOLVER_OK)
+    info.status = st
+    return info
+
+
+@dataclass
+class MGConfig:
+    coarse_cells: int = 4
+    degree: int = 4
+    smoothing_range: float = 20.0
+    eig_steps: int = 12
+    eig_safety: float = 1.2
+    lambda_max: Optional[Sequence[float]] = None
+    coarse_rtol: float = 1e-12
+    coarse_maxit: int = 500
+
+
+class Multigrid:
+    """FP32 geometric multigrid V-cycle for a heat operator (wraps mf_mg)."""
+
+    def __init__(self, op: Operator, cfg: MGConfig = MGConfig(), stream=None):
+        c = op.ctx
+        p = MGParams()
+        p.coarse_cells, p.degree, p.smoothing_range = cfg.coarse_cells, cfg.degree, cfg.smoothing_range
+        p.eig_steps, p.eig_safety = cfg.eig_steps, cfg.eig_safety
+        p.coarse_rtol, p.coarse_maxit = cfg.coarse_rtol, cfg.coarse_maxit
+        self._lmax = None
+        if cfg.lambda_max is not None:
+            self._lmax = (ctypes.c_double * len(cfg.lambda_max))(*cfg.lambda_max)
+            p.lambda_max = self._lmax
+        h = _P()
+        c.check(library().mf_mg_create(c._h, ctypes.byref(op.desc), ctypes.byref(p), ctypes.byref(h),
+                                       _stream(stream)))
+        self._h = h
+        self.op = op
+        self.n_levels = int(library().mf_mg_n_levels(h))
+
+    def lambda_max(self):
+        out = (ctypes.c_double * self.n_levels)()
+        self.op.ctx.check(library().mf_mg_lambda_max(self._h, out))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().mf_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mg_vcycle(mg: Multigrid, r: torch.Tensor, z: torch.Tensor, stream=None):
+    n = mg.op.ctx.n_nodes
+    mg.op.ctx.check(library().mf_mg_vcycle(mg._h, _ptr(r, n, torch.float64, "r"), _ptr(z, n, torch.float64, "z"),
+                                           _stream(stream)))
+    return z
+
+
+def mg_cg_solve(mg: Multigrid, b: torch.Tensor, x: torch.Tensor, rtol: float, maxit: int, stream=None) -> SolveInfo:
+    n = mg.op.ctx.n_nodes
+    info = SolveInfo()
+    st = library().mf_mg_cg_solve(mg._h, _ptr(b, n, torch.float64, "b"), _ptr(x, n, torch.float64, "x"), rtol, maxit,
+                                  ctypes.byref(info), _stream(stream))
+    mg.op.ctx.check(st, _SOLVER_OK)
+    info.status = st
+    return info
+
+
+def quad_points(ctx: Context, xq: torch.Tensor, stream=None):
+    ctx.check(library().mf_quad_points(ctx._h, _ptr(xq, ctx.n_cells * 27 * 3, torch.float64, "xq"), _stream(stream)))
+    return xq
+
+
+def heat_qp_coeffs(op: Operator, k_q: torch.Tensor, rc_q: torch.Tensor, stream=None):
+    c = op.ctx
+    nq = c.n_cells * 27
+    c.check(library().mf_heat_qp_coeffs(c._h, ctypes.byref(op.desc), _ptr(k_q, nq, torch.float64, "k_q"),
+                                        _ptr(rc_q, nq, torch.float64, "rc_q"), _stream(stream)))
+    return k_q, rc_q
+
+
+def heat_coeff_grad(op: Operator, T, dT, lam, dk=None, drc=None, dphi=None, stream=None):
+    c = op.ctx
+    nn, nq = c.n_nodes, c.n_cells * 27
+    c.check(library().mf_heat_coeff_grad(c._h, ctypes.byref(op.desc), _ptr(T, nn, torch.float64, "T"),
+                                         _ptr(dT, nn, torch.float64, "dT"), _ptr(lam, nn, torch.float64, "lam"),
+                                         _ptr(dk, nq, torch.float64, "dk"), _ptr(drc, nq, torch.float64, "drc"),
+                                         _ptr(dphi, nn, torch.float64, "dphi"), _stream(stream)))
+    return dk, drc, dphi
