@@ -123,6 +123,17 @@ const char *mf_last_error(const mf_ctx *ctx);
 int64_t mf_n_nodes(const mf_ctx *ctx);
 int64_t mf_n_cells(const mf_ctx *ctx);
 
+/* ---- kernel timing (profiling aid) ------------------------------------------- */
+
+/* While enabled, every operator apply records HIP events on the caller's
+ * stream immediately around its main kernel (not around the clearing of the
+ * output).  mf_timing_read waits for the last recorded event and returns the
+ * summed kernel time in milliseconds and the number of timed launches since
+ * the last reset (reset != 0 starts a new count).  Events are owned by the
+ * context. */
+mf_status mf_timing_enable(mf_ctx *ctx, int32_t on);
+mf_status mf_timing_read(mf_ctx *ctx, double *ms, int64_t *launches, int32_t reset);
+
 /* ---- operator application (Sec. 2.1, 2.3; App. B matrix-free products) ------ */
 
 /* y = A x.  x and y: n_dofs entries (n_nodes for heat, 3 n_nodes for Oseen),

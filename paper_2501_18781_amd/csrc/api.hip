@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mf.h"
+#include "mf.h"
 #include "kernels.hpp"
 
 using namespace mf;
@@ -35,6 +35,11 @@ struct mf_ctx {
     double *V = nullptr;         // GMRES basis
     int V_cols = 0;
     double *blocks = nullptr;    // Oseen block-Jacobi inverse
+    double *face = nullptr;      // shared-face partial sums of the brick kernels
+    // kernel timing
+    bool timing = false;
+    std::vector<KTiming> events;
+    size_t events_used = 0;
 };
 
 static const char *g_static_err = "no context";
@@ -117,6 +122,7 @@ mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
     int64_t cap = nbricks > 32 * 1024 ? nbricks : 32 * 1024;
     c->cap = (unsigned)cap;
     bool ok = hipMalloc((void **)&c->partials, sizeof(double) * cap) == hipSuccess &&
+              hipMalloc((void **)&c->face, sizeof(double) * face_buffer_elems(k)) == hipSuccess &&
               hipMalloc((void **)&c->counter, sizeof(unsigned) * 16) == hipSuccess &&
               hipMalloc((void **)&c->cg, sizeof(CGState)) == hipSuccess &&
               hipMalloc((void **)&c->scal, sizeof(double) * 256) == hipSuccess &&
@@ -145,9 +151,37 @@ void mf_destroy(mf_ctx *c)
     if (c->scal) (void)hipFree(c->scal);
     if (c->V) (void)hipFree(c->V);
     if (c->blocks) (void)hipFree(c->blocks);
+    if (c->face) (void)hipFree(c->face);
     if (c->h_state) (void)hipHostFree(c->h_state);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
+    for (KTiming &t : c->events) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
     delete c;
+}
+
+mf_status mf_timing_enable(mf_ctx *c, int32_t on)
+{
+    if (!c) return MF_ERR_ARG;
+    c->timing = on != 0;
+    return MF_OK;
+}
+
+mf_status mf_timing_read(mf_ctx *c, double *ms, int64_t *launches, int32_t reset)
+{
+    if (!c || !ms || !launches) return MF_ERR_ARG;
+    double tot = 0.0;
+    for (size_t i = 0; i < c->events_used; ++i) {
+        float f = 0.0f;
+        HIPCHK(c, hipEventSynchronize(c->events[i].stop));
+        HIPCHK(c, hipEventElapsedTime(&f, c->events[i].start, c->events[i].stop));
+        tot += f;
+    }
+    *ms = tot;
+    *launches = (int64_t)c->events_used;
+    if (reset) c->events_used = 0;
+    return MF_OK;
 }
 
 } // extern "C"
@@ -218,12 +252,26 @@ static OseenArgs oseen_args(const mf_operator *op)
 
 static int64_t ndofs(const mf_ctx *c, const mf_operator *op) { return op->kind == MF_OSEEN ? 3 * c->nn : c->nn; }
 
-// y = A x or A^T x, FP64 or FP32 (heat)
-static hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s)
+// Next event pair for a timed launch (nullptr when timing is off).
+static const KTiming *next_timing(mf_ctx *c)
 {
+    if (!c->timing) return nullptr;
+    if (c->events_used == c->events.size()) {
+        KTiming t;
+        if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return nullptr;
+        c->events.push_back(t);
+    }
+    return &c->events[c->events_used++];
+}
+
+// y = A x or A^T x, FP64 or FP32 (heat)
+static hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s,
+                            bool timed = false)
+{
+    const KTiming *t = timed ? next_timing(c) : nullptr;
     if (op->kind == MF_HEAT)
-        return heat_apply(c->km, heat_args(op), op->precision == MF_FP32, x, y, nullptr, nullptr, s);
-    return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, s);
+        return heat_apply(c->km, heat_args(op), op->precision == MF_FP32, x, y, c->face, nullptr, nullptr, s, t);
+    return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, s, t);
 }
 
 extern "C" {
@@ -233,7 +281,7 @@ mf_status mf_operator_apply(mf_ctx *c, const mf_operator *op, const void *x, voi
     mf_status st = check_op(c, op);
     if (st) return st;
     if (!x || !y || x == y) return fail(c, MF_ERR_ARG, "x and y must be distinct non-null device arrays");
-    HIPCHK(c, apply_any(c, op, 0, x, y, (hipStream_t)stream));
+    HIPCHK(c, apply_any(c, op, 0, x, y, (hipStream_t)stream, true));
     return MF_OK;
 }
 
@@ -242,7 +290,7 @@ mf_status mf_operator_apply_transpose(mf_ctx *c, const mf_operator *op, const vo
     mf_status st = check_op(c, op);
     if (st) return st;
     if (!x || !y || x == y) return fail(c, MF_ERR_ARG, "x and y must be distinct non-null device arrays");
-    HIPCHK(c, apply_any(c, op, 1, x, y, (hipStream_t)stream));
+    HIPCHK(c, apply_any(c, op, 1, x, y, (hipStream_t)stream, true));
     return MF_OK;
 }
 
@@ -348,7 +396,7 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
     const int batch = 8;
     for (int done_iters = 0;;) {
         for (int k = 0; k < batch; ++k) {
-            HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->cg, &red, s));
+            HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
             HIPCHK(c, cg_update(c->cg, dinv, x, r, z, p, q, n, &red, s));
             HIPCHK(c, cg_pupdate(c->cg, z, p, n, s));
         }

@@ -5,126 +5,50 @@
 //   (A x)_i = sum_cells sum_q W_q ( alpha_m rc_q N_i x_q + alpha_k k_q grad N_i . grad x_q )
 // applied without assembling A (App. B: matrix-free products).
 //
-// Work decomposition: one workgroup per brick of BX x BY x BZ cells, one
-// thread per cell.
-//   1. the brick's nodal values of x (Dirichlet nodes read as zero) and of
-//      phi are staged in LDS with contiguous row loads;
-//   2. each thread gathers its cell's 27 values from LDS and evaluates the
-//      cell operator entirely in registers by sum factorization (3x3
-//      contractions along one direction at a time, collocation derivatives
-//      at the Gauss points);
-//   3. the 27 cell results go to a cell-major LDS array; one thread per
-//      brick node sums the contributions of the cells that share it in a
-//      fixed order;
-//   4. nodes interior to the brick are written with plain stores; nodes on a
-//      face shared with a neighbouring brick are added with hardware FP64
-//      atomics into an output the caller zeroed.
-// Dirichlet nodes are written as y_i = x_i.
-#include "kernels.hpp"
+// Work decomposition (brick.hpp): one 64-thread workgroup (one wavefront)
+// per brick of 4x4x4 cells, one thread per cell.
+//   1. the brick's nodal x (Dirichlet nodes read as zero) and phi are staged
+//      in LDS, every node loaded by the one cell that owns it;
+//   2. each thread evaluates its cell entirely in registers by sum
+//      factorization (3x3 contractions along one direction at a time,
+//      collocation derivatives at the Gauss points, one 3-point line at a
+//      time);
+//   3. the 27 cell results go to LDS; each owned node sums the (at most 8)
+//      cells of the brick that share it in a fixed order;
+//   4. nodes complete within the brick are stored; nodes on a face shared
+//      with a neighbouring brick go to a face buffer, and a second kernel
+//      adds the partials of the bricks sharing each such node in a fixed
+//      order.  Every output entry is written once, without atomics, and the
+//      result is bitwise reproducible.  Dirichlet nodes get y_i = x_i.
+#include <type_traits>
+
+#include "brick.hpp"
 
 namespace mf {
-
-template <int BX, int BY, int BZ> struct BrickGeo {
-    static constexpr int PX = 2 * BX + 1, PY = 2 * BY + 1, PZ = 2 * BZ + 1;
-    static constexpr int NB = PX * PY * PZ;
-    static constexpr int NC = BX * BY * BZ;
-    int c0x, c0y, c0z; // first cell
-    int ncx, ncy, ncz; // valid cells in the brick (clipped at the mesh end)
-
-    __device__ __forceinline__ BrickGeo(const KMesh &m, int brick)
-    {
-        const int nbx = (m.nx + BX - 1) / BX, nby = (m.ny + BY - 1) / BY;
-        const int bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
-        c0x = bx * BX;
-        c0y = by * BY;
-        c0z = bz * BZ;
-        ncx = min(BX, m.nx - c0x);
-        ncy = min(BY, m.ny - c0y);
-        ncz = min(BZ, m.nz - c0z);
-    }
-    static __device__ __forceinline__ int lds_index(int lx, int ly, int lz) { return lx + PX * (ly + PY * lz); }
-
-    // Cooperative load of a nodal field into LDS; zero outside the mesh and,
-    // if mask, on Dirichlet nodes.
-    template <int NT, typename T>
-    __device__ __forceinline__ void load(const KMesh &m, const T *__restrict__ g, T *lds, bool mask) const
-    {
-        for (int i = threadIdx.x; i < NB; i += NT) {
-            const int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
-            const int gx = 2 * c0x + lx, gy = 2 * c0y + ly, gz = 2 * c0z + lz;
-            T v = T(0);
-            if (gx < m.NX && gy < m.NY && gz < m.NZ && !(mask && node_constrained(m, gx, gy, gz)))
-                v = g[node_index(m, gx, gy, gz)];
-            lds[i] = v;
-        }
-    }
-
-    __device__ __forceinline__ void cell_of_thread(int t, int &tx, int &ty, int &tz, bool &valid) const
-    {
-        tx = t % BX;
-        ty = (t / BX) % BY;
-        tz = t / (BX * BY);
-        valid = tx < ncx && ty < ncy && tz < ncz;
-    }
-
-    template <typename T> __device__ __forceinline__ void gather27(const T *lds, int tx, int ty, int tz, T *v) const
-    {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) v[a + 3 * b + 9 * c] = lds[lds_index(2 * tx + a, 2 * ty + b, 2 * tz + c)];
-    }
-
-    // Sum of the cell-major contributions E[cell*27 + local] at brick node
-    // (lx, ly, lz), cells in fixed (z, y, x) order.
-    template <typename T> __device__ __forceinline__ T node_sum(const T *E, int lx, int ly, int lz) const
-    {
-        const int xlo = max(0, (lx - 1) >> 1), xhi = min(ncx - 1, lx >> 1);
-        const int ylo = max(0, (ly - 1) >> 1), yhi = min(ncy - 1, ly >> 1);
-        const int zlo = max(0, (lz - 1) >> 1), zhi = min(ncz - 1, lz >> 1);
-        T s = T(0);
-        for (int cz = zlo; cz <= zhi; ++cz)
-            for (int cy = ylo; cy <= yhi; ++cy)
-                for (int cx = xlo; cx <= xhi; ++cx) {
-                    const int cell = cx + BX * (cy + BY * cz);
-                    const int loc = (lx - 2 * cx) + 3 * (ly - 2 * cy) + 9 * (lz - 2 * cz);
-                    s += E[cell * 27 + loc];
-                }
-        return s;
-    }
-
-    // Whether brick node (lx,ly,lz) at global (gx,gy,gz) also belongs to a
-    // neighbouring brick.
-    __device__ __forceinline__ bool shared(const KMesh &m, int lx, int ly, int lz, int gx, int gy, int gz) const
-    {
-        return (lx == 0 && gx > 0) || (lx == 2 * ncx && gx < m.NX - 1) || (ly == 0 && gy > 0) ||
-               (ly == 2 * ncy && gy < m.NY - 1) || (lz == 0 && gz > 0) || (lz == 2 * ncz && gz < m.NZ - 1);
-    }
-    // The brick that writes y = x on a Dirichlet node (the one whose half-open
-    // node range holds it; the last brick also holds the closing node).
-    __device__ __forceinline__ bool owns(const KMesh &m, int lx, int ly, int lz, int gx, int gy, int gz) const
-    {
-        return (lx < 2 * ncx || gx == m.NX - 1) && (ly < 2 * ncy || gy == m.NY - 1) &&
-               (lz < 2 * ncz || gz == m.NZ - 1);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Per-cell coefficient factors at the 27 Gauss points:
 //   cm_q = alpha_m |J| w_q rc_q,   ck_q = alpha_k |J| w_q k_q / r^2
+// MODE 0: from the level set through H (HK 0 linear, HK 1 sine form);
+// MODE 1: k and rc given per quadrature point.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, const T *phq, const T *kq, const T *rcq, T am_w,
+template <typename T, int MODE, int HK>
+__device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, T *phq, const T *kq, const T *rcq, T am_w,
                                                  T ak_w, T *cm, T *ck)
 {
+    if (MODE == 0 && HK == 1) {
+        // out of line and not unrolled: one transcendental evaluation per point
+        for (int q = 0; q < 27; ++q) {
+            double dH;
+            phq[q] = T(heaviside_sine(a.eps, (double)phq[q], &dH));
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         const T wq = Q2<T>::weight(q % 3) * Q2<T>::weight((q / 3) % 3) * Q2<T>::weight(q / 9);
         T k, rc;
         if (MODE == 0) {
-            const T H = heaviside<T>(a.hkind, T(a.eps), phq[q], nullptr);
+            const T H = HK == 0 ? heaviside_linear<T>(phq[q]) : phq[q];
             k = T(a.k_g) + H * (T(a.k_l) - T(a.k_g));
             rc = T(a.rc_g) + H * (T(a.rc_l) - T(a.rc_g));
         } else {
@@ -136,104 +60,96 @@ __device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, const T *phq
     }
 }
 
-// y_e = A_e x_e on one cell, returned in u (27 nodal values); energy += x_e.A_e x_e.
+// y_e = A_e x_e on one cell, in place on u (27 nodal values in, 27 out).
 template <typename T>
-__device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, T ihx, T ihy, T ihz, double &energy)
+__device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, T ihx, T ihy, T ihz)
 {
     interp3(u);
     T acc[27];
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        acc[q] = cm[q] * u[q];
-        energy += (double)(u[q] * acc[q]);
-    }
-    grad_line_apply<T, 0>(u, ck, ihx, acc, energy);
-    grad_line_apply<T, 1>(u, ck, ihy, acc, energy);
-    grad_line_apply<T, 2>(u, ck, ihz, acc, energy);
+    for (int q = 0; q < 27; ++q) acc[q] = cm[q] * u[q];
+    double unused = 0.0;
+    grad_line_apply<T, 0>(u, ck, ihx, acc, unused);
+    grad_line_apply<T, 1>(u, ck, ihy, acc, unused);
+    grad_line_apply<T, 2>(u, ck, ihz, acc, unused);
     interp3T(acc);
 #pragma unroll
     for (int q = 0; q < 27; ++q) u[q] = acc[q];
 }
 
-constexpr int HB_X = 8, HB_Y = 8, HB_Z = 4;
-constexpr int HB_NT = HB_X * HB_Y * HB_Z;
-
-template <typename T, int MODE, bool CG>
-__global__ void __launch_bounds__(HB_NT) heat_apply_kernel(KMesh m, HeatArgs a, const T *__restrict__ x,
-                                                           T *__restrict__ y, CGState *cg, RedWS red)
+template <typename T, int MODE, int HK, bool CG>
+__global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, const T *__restrict__ x,
+                                                         T *__restrict__ y, T *__restrict__ face, CGState *cg,
+                                                         RedWS red)
 {
-    using G = BrickGeo<HB_X, HB_Y, HB_Z>;
-    // x stays resident for the energy; phi and then the cell contributions share the rest
-    constexpr int LDS_T = G::NB + (G::NB > 27 * G::NC ? G::NB : 27 * G::NC);
+    // phi and then the cell contributions share one region; x stays resident
+    // only when the CG epilogue needs it for x.Ax.
+    constexpr int REG = (2 * BNB > 27 * BNT ? 2 * BNB : 27 * BNT);
+    constexpr int LDS_T = CG ? BNB + (BNB > 27 * BNT ? BNB : 27 * BNT) : REG;
     __shared__ T lds[LDS_T];
-    __shared__ double red_lds[HB_NT];
+    __shared__ double red_lds[BNT];
     __shared__ int flag_lds;
     if (CG) {
         if (cg->done) return; // converged or broken down: the rest of the batch is a no-op
     }
-    const G br(m, blockIdx.x);
+    const Brick br(m, threadIdx.x);
     T *xs = lds;
-    T *ps = lds + G::NB;
-    br.template load<HB_NT>(m, x, xs, true);
-    if (MODE == 0) br.template load<HB_NT>(m, (const T *)a.phi, ps, false);
+    T *ps = lds + BNB;
+    br.load(m, x, xs, true);
+    if (MODE == 0) br.load(m, (const T *)a.phi, ps, false);
     __syncthreads();
 
-    int tx, ty, tz;
-    bool valid;
-    br.cell_of_thread(threadIdx.x, tx, ty, tz, valid);
     const T vol = T(m.hx * m.hy * m.hz);
     const T am_w = T(a.am) * vol;
     const T ak_w = T(a.ak) * vol / T(kR * kR);
     const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T u[27];
-    double energy_unused = 0.0;
     {
         T cm[27], ck[27];
         if (MODE == 0) {
             T ph[27];
-            br.gather27(ps, tx, ty, tz, ph);
+            br.gather27(ps, ph);
             interp3(ph);
-            heat_cell_coeffs<T, 0>(a, ph, nullptr, nullptr, am_w, ak_w, cm, ck);
+            heat_cell_coeffs<T, 0, HK>(a, ph, nullptr, nullptr, am_w, ak_w, cm, ck);
         } else {
-            const int64_t cell = valid ? (int64_t)(br.c0x + tx) + (int64_t)m.nx * ((br.c0y + ty) + (int64_t)m.ny * (br.c0z + tz)) : 0;
-            heat_cell_coeffs<T, 1>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w, ak_w,
-                                   cm, ck);
+            const int64_t cell = br.valid ? br.cell_index(m) : 0;
+            heat_cell_coeffs<T, 1, 0>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w,
+                                      ak_w, cm, ck);
         }
-        br.gather27(xs, tx, ty, tz, u);
-        heat_cell_apply<T>(u, cm, ck, ihx, ihy, ihz, energy_unused);
+        br.gather27(xs, u);
+        heat_cell_apply<T>(u, cm, ck, ihx, ihy, ihz);
     }
-    __syncthreads(); // the phi region is now reused for the cell-major contributions
-    T *E = ps;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) E[threadIdx.x * 27 + i] = valid ? u[i] : T(0);
+    __syncthreads(); // the staging region is now reused for the cell contributions
+    T *E = CG ? ps : lds;
+    br.store_cell(E, u);
     __syncthreads();
 
-    // x.Ax = sum over bricks of x_i times the brick's partial sum at node i
+    // Owned nodes: complete ones go to y, shared ones to the face buffer.
+    // x.Ax = sum over bricks of x_i times the brick's partial sum at node i.
     double energy = 0.0;
-    for (int i = threadIdx.x; i < G::NB; i += HB_NT) {
-        const int lx = i % G::PX, ly = (i / G::PX) % G::PY, lz = i / (G::PX * G::PY);
-        if (lx > 2 * br.ncx || ly > 2 * br.ncy || lz > 2 * br.ncz) continue;
-        const int gx = 2 * br.c0x + lx, gy = 2 * br.c0y + ly, gz = 2 * br.c0z + lz;
-        const int64_t g = node_index(m, gx, gy, gz);
-        if (node_constrained(m, gx, gy, gz)) {
-            if (br.owns(m, lx, ly, lz, gx, gy, gz)) {
+    T *fb = face + (int64_t)br.brick * BFACE;
+    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
+        const T s = br.node_sum(E, ai, bi, ci);
+        if (CG) energy += (double)xs[l] * (double)s;
+        T *dst = sh ? fb + face_slot(lx0 + ai, ly0 + bi, lz0 + ci) : y + g;
+        *dst = s;
+    });
+    // Dirichlet rows y_i = x_i: unshared nodes here, shared ones in the
+    // combine pass; x_i^2 enters x.Ax once, in the brick that combines.
+    if (br.touches_dirichlet(m)) { // uniform over the brick
+        br.for_owned_nodes(m, [&](int, int, int, int, int64_t g, bool constrained, int sh) {
+            if (constrained) {
                 const T xv = x[g];
-                y[g] = xv;
-                if (CG) energy += (double)xv * (double)xv;
+                if (!sh) y[g] = xv;
+                if (CG && !(sh & 2)) energy += (double)xv * (double)xv;
             }
-            continue;
-        }
-        const T s = br.node_sum(E, lx, ly, lz);
-        if (CG) energy += (double)xs[i] * (double)s;
-        if (br.shared(m, lx, ly, lz, gx, gy, gz))
-            atomicAdd(&y[g], s);
-        else
-            y[g] = s;
+        });
     }
     if (CG) {
-        const double tot = block_sum<HB_NT>(energy, red_lds);
+        const double tot = block_sum<BNT>(energy, red_lds);
         if (publish_partials<1>(&tot, red.partials, red.counter, gridDim.x, &flag_lds)) {
-            const double pAp = sum_partials<HB_NT>(red.partials, gridDim.x, 0, red_lds);
+            const double pAp = sum_partials<BNT>(red.partials, gridDim.x, 0, red_lds);
             if (threadIdx.x == 0) {
                 cg->pAp = pAp;
                 if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -249,66 +165,94 @@ __global__ void __launch_bounds__(HB_NT) heat_apply_kernel(KMesh m, HeatArgs a, 
     }
 }
 
-hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, CGState *cg,
-                      const RedWS *red, hipStream_t s)
+// Second pass of an apply: shared nodes = sum of the bricks' face partials.
+template <typename T, bool CG>
+__global__ void __launch_bounds__(BNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
+                                                           const T *__restrict__ x, T *__restrict__ y,
+                                                           const CGState *cg)
 {
-    const int nbx = (m.nx + HB_X - 1) / HB_X, nby = (m.ny + HB_Y - 1) / HB_Y, nbz = (m.nz + HB_Z - 1) / HB_Z;
-    const unsigned nb = (unsigned)(nbx * nby * nbz);
-    const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
+    if (CG) {
+        if (cg->done) return;
+    }
+    const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
+    const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
+    combine_faces<T>(m, face, x, y, k * q + min(k, r) + j);
+}
+
+int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
+
+hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, void *face, CGState *cg,
+                      const RedWS *red, hipStream_t s, const KTiming *t)
+{
+    const unsigned nb = (unsigned)n_bricks(m);
     RedWS r = red ? *red : RedWS{nullptr, nullptr, 0};
+    if (!face) return hipErrorInvalidValue;
     if (cg && (!red || red->capacity < nb)) return hipErrorInvalidValue;
-    if (!cg) {
-        hipError_t e = vfill(y, 0.0, nn, fp32, s);
+    if (fp32 && cg) return hipErrorInvalidValue;
+    if (t && t->start) {
+        hipError_t e = hipEventRecord(t->start, s);
         if (e != hipSuccess) return e;
     }
-    if (fp32) {
-        if (cg) return hipErrorInvalidValue;
-        if (a.mode == 0)
-            heat_apply_kernel<float, 0, false><<<nb, HB_NT, 0, s>>>(m, a, (const float *)x, (float *)y, nullptr, r);
-        else
-            heat_apply_kernel<float, 1, false><<<nb, HB_NT, 0, s>>>(m, a, (const float *)x, (float *)y, nullptr, r);
-    } else if (cg) {
-        if (a.mode == 0)
-            heat_apply_kernel<double, 0, true><<<nb, HB_NT, 0, s>>>(m, a, (const double *)x, (double *)y, cg, r);
-        else
-            heat_apply_kernel<double, 1, true><<<nb, HB_NT, 0, s>>>(m, a, (const double *)x, (double *)y, cg, r);
-    } else {
-        if (a.mode == 0)
-            heat_apply_kernel<double, 0, false><<<nb, HB_NT, 0, s>>>(m, a, (const double *)x, (double *)y, nullptr, r);
-        else
-            heat_apply_kernel<double, 1, false><<<nb, HB_NT, 0, s>>>(m, a, (const double *)x, (double *)y, nullptr, r);
+    // (precision, coefficient mode, Heaviside form, CG epilogue)
+    const int key = (fp32 ? 8 : 0) | (a.mode ? 4 : (a.hkind ? 2 : 0)) | (cg ? 1 : 0);
+    switch (key) {
+#define HEAT_CASE(K, T, MODE, HK, CGF)                                                                        \
+    case K:                                                                                                   \
+        heat_apply_kernel<T, MODE, HK, CGF><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, cg, r);  \
+        break;
+        HEAT_CASE(0, double, 0, 0, false)
+        HEAT_CASE(1, double, 0, 0, true)
+        HEAT_CASE(2, double, 0, 1, false)
+        HEAT_CASE(3, double, 0, 1, true)
+        HEAT_CASE(4, double, 1, 0, false)
+        HEAT_CASE(5, double, 1, 0, true)
+        HEAT_CASE(8, float, 0, 0, false)
+        HEAT_CASE(10, float, 0, 1, false)
+        HEAT_CASE(12, float, 1, 0, false)
+#undef HEAT_CASE
+    default:
+        return hipErrorInvalidValue;
     }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
+    if (e != hipSuccess) return e;
+    if (fp32)
+        face_combine_kernel<float, false><<<nb, BNT, 0, s>>>(m, (const float *)face, (const float *)x, (float *)y,
+                                                              nullptr);
+    else if (cg)
+        face_combine_kernel<double, true><<<nb, BNT, 0, s>>>(m, (const double *)face, (const double *)x, (double *)y,
+                                                             cg);
+    else
+        face_combine_kernel<double, false><<<nb, BNT, 0, s>>>(m, (const double *)face, (const double *)x,
+                                                              (double *)y, nullptr);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal: diag_i = sum_cells sum_q cm_q N_i(q)^2 + ck_q sum_d (D'_d N_i(q))^2 / h_d^2,
+// Diagonal: diag_i = sum_cells sum_q cm_q N_i(q)^2 + ck_q sum_d (d_d N_i(q))^2,
 // evaluated per cell node by a direct loop over the Gauss points (setup only).
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ void __launch_bounds__(HB_NT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag)
+template <typename T, int MODE, int HK>
+__global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag)
 {
-    using G = BrickGeo<HB_X, HB_Y, HB_Z>;
-    constexpr int LDS_T = (G::NB > 27 * G::NC ? G::NB : 27 * G::NC);
+    constexpr int LDS_T = (BNB > 27 * BNT ? BNB : 27 * BNT);
     __shared__ T lds[LDS_T];
-    const G br(m, blockIdx.x);
-    if (MODE == 0) br.template load<HB_NT>(m, (const T *)a.phi, lds, false);
+    const Brick br(m, threadIdx.x);
+    if (MODE == 0) br.load(m, (const T *)a.phi, lds, false);
     __syncthreads();
-    int tx, ty, tz;
-    bool valid;
-    br.cell_of_thread(threadIdx.x, tx, ty, tz, valid);
     const T vol = T(m.hx * m.hy * m.hz);
     const T am_w = T(a.am) * vol, ak_w = T(a.ak) * vol;
     const T ih[3] = {T(1.0 / (m.hx * m.hx)), T(1.0 / (m.hy * m.hy)), T(1.0 / (m.hz * m.hz))};
     T cm[27], ck[27];
     if (MODE == 0) {
         T ph[27];
-        br.gather27(lds, tx, ty, tz, ph);
+        br.gather27(lds, ph);
         interp3(ph);
-        heat_cell_coeffs<T, 0>(a, ph, nullptr, nullptr, am_w, ak_w, cm, ck);
+        heat_cell_coeffs<T, 0, HK>(a, ph, nullptr, nullptr, am_w, ak_w, cm, ck);
     } else {
-        const int64_t cell = valid ? (int64_t)(br.c0x + tx) + (int64_t)m.nx * ((br.c0y + ty) + (int64_t)m.ny * (br.c0z + tz)) : 0;
-        heat_cell_coeffs<T, 1>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w, ak_w, cm, ck);
+        const int64_t cell = br.valid ? br.cell_index(m) : 0;
+        heat_cell_coeffs<T, 1, 0>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w, ak_w,
+                                  cm, ck);
     }
     // 1D tables: S[q][a] and G[q][a] = l_a'(xi_q)
     const T S[3][3] = {{Q2<T>::s0, Q2<T>::s1, Q2<T>::s2}, {T(0), T(1), T(0)}, {Q2<T>::s2, Q2<T>::s1, Q2<T>::s0}};
@@ -327,39 +271,35 @@ __global__ void __launch_bounds__(HB_NT) heat_diag_kernel(KMesh m, HeatArgs a, T
         d[i] = s;
     }
     __syncthreads();
-    T *E = lds;
-    for (int i = 0; i < 27; ++i) E[threadIdx.x * 27 + i] = valid ? d[i] : T(0);
+    br.store_cell(lds, d);
     __syncthreads();
-    for (int i = threadIdx.x; i < G::NB; i += HB_NT) {
-        const int lx = i % G::PX, ly = (i / G::PX) % G::PY, lz = i / (G::PX * G::PY);
-        if (lx > 2 * br.ncx || ly > 2 * br.ncy || lz > 2 * br.ncz) continue;
-        const int gx = 2 * br.c0x + lx, gy = 2 * br.c0y + ly, gz = 2 * br.c0z + lz;
-        const int64_t g = node_index(m, gx, gy, gz);
-        if (node_constrained(m, gx, gy, gz)) {
-            if (br.owns(m, lx, ly, lz, gx, gy, gz)) diag[g] = T(1);
-            continue;
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, bool shared) {
+        if (constrained) {
+            diag[g] = T(1);
+            return;
         }
-        const T s = br.node_sum(E, lx, ly, lz);
-        if (br.shared(m, lx, ly, lz, gx, gy, gz))
+        const T s = br.node_sum(lds, ai, bi, ci);
+        if (shared)
             atomicAdd(&diag[g], s);
         else
             diag[g] = s;
-    }
+    });
 }
 
 hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, hipStream_t s)
 {
-    const int nbx = (m.nx + HB_X - 1) / HB_X, nby = (m.ny + HB_Y - 1) / HB_Y, nbz = (m.nz + HB_Z - 1) / HB_Z;
-    const unsigned nb = (unsigned)(nbx * nby * nbz);
+    const unsigned nb = (unsigned)n_bricks(m);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
     hipError_t e = vfill(diag, 0.0, nn, fp32, s);
     if (e != hipSuccess) return e;
     if (fp32) {
-        if (a.mode == 0) heat_diag_kernel<float, 0><<<nb, HB_NT, 0, s>>>(m, a, (float *)diag);
-        else heat_diag_kernel<float, 1><<<nb, HB_NT, 0, s>>>(m, a, (float *)diag);
+        if (a.mode == 1) heat_diag_kernel<float, 1, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag);
+        else if (a.hkind == 1) heat_diag_kernel<float, 0, 1><<<nb, BNT, 0, s>>>(m, a, (float *)diag);
+        else heat_diag_kernel<float, 0, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag);
     } else {
-        if (a.mode == 0) heat_diag_kernel<double, 0><<<nb, HB_NT, 0, s>>>(m, a, (double *)diag);
-        else heat_diag_kernel<double, 1><<<nb, HB_NT, 0, s>>>(m, a, (double *)diag);
+        if (a.mode == 1) heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag);
+        else if (a.hkind == 1) heat_diag_kernel<double, 0, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag);
+        else heat_diag_kernel<double, 0, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag);
     }
     return hipGetLastError();
 }
@@ -390,17 +330,6 @@ hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s)
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void gather_global27(const KMesh &m, const double *__restrict__ g, int cx, int cy, int cz,
-                                                double *v)
-{
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) v[a + 3 * b + 9 * c] = g[node_index(m, 2 * cx + a, 2 * cy + b, 2 * cz + c)];
-}
-
 __global__ void heat_qp_kernel(KMesh m, HeatArgs a, double *__restrict__ kq, double *__restrict__ rcq)
 {
     const int64_t nc = (int64_t)m.nx * m.ny * m.nz;
@@ -408,7 +337,13 @@ __global__ void heat_qp_kernel(KMesh m, HeatArgs a, double *__restrict__ kq, dou
     if (cell >= nc) return;
     const int cx = (int)(cell % m.nx), cy = (int)((cell / m.nx) % m.ny), cz = (int)(cell / ((int64_t)m.nx * m.ny));
     double ph[27];
-    gather_global27(m, (const double *)a.phi, cx, cy, cz, ph);
+    const double *phi = (const double *)a.phi;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ph[i + 3 * b + 9 * c] = phi[node_index(m, 2 * cx + i, 2 * cy + b, 2 * cz + c)];
     interp3(ph);
     for (int q = 0; q < 27; ++q) {
         const double H = heaviside<double>(a.hkind, a.eps, ph[q], nullptr);
@@ -429,36 +364,29 @@ hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double 
 //   dk_q  = -alpha_k W_q grad(lam) . grad(T)
 //   drc_q = -alpha_m W_q lam dT
 //   dphi_j = sum_q N_j(x_q) H'(phi_q) [(k_l - k_g) dk_q + (rc_l - rc_g) drc_q]
-// Brick of 4x4x4 cells, one thread per cell; dphi gathered like the apply.
 // ---------------------------------------------------------------------------
-constexpr int GB = 4, GB_NT = GB * GB * GB;
-
-__global__ void __launch_bounds__(GB_NT) heat_grad_kernel(KMesh m, HeatArgs a, const double *__restrict__ T,
-                                                          const double *__restrict__ dT, const double *__restrict__ lam,
-                                                          double *__restrict__ dk, double *__restrict__ drc,
-                                                          double *__restrict__ dphi)
+__global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, const double *__restrict__ T,
+                                                        const double *__restrict__ dT, const double *__restrict__ lam,
+                                                        double *__restrict__ dk, double *__restrict__ drc,
+                                                        double *__restrict__ dphi)
 {
-    using G = BrickGeo<GB, GB, GB>;
     constexpr int NF = 4;
-    constexpr int LDS_T = (NF * G::NB > 27 * G::NC ? NF * G::NB : 27 * G::NC);
+    constexpr int LDS_T = (NF * BNB > 27 * BNT ? NF * BNB : 27 * BNT);
     __shared__ double lds[LDS_T];
-    const G br(m, blockIdx.x);
-    double *Ts = lds, *dTs = lds + G::NB, *ls = lds + 2 * G::NB, *ps = lds + 3 * G::NB;
-    br.load<GB_NT>(m, T, Ts, false);
-    br.load<GB_NT>(m, dT, dTs, false);
-    br.load<GB_NT>(m, lam, ls, false);
+    const Brick br(m, threadIdx.x);
+    double *Ts = lds, *dTs = lds + BNB, *ls = lds + 2 * BNB, *ps = lds + 3 * BNB;
+    br.load(m, T, Ts, false);
+    br.load(m, dT, dTs, false);
+    br.load(m, lam, ls, false);
     const bool with_phi = (a.mode == 0) && dphi != nullptr;
-    if (with_phi) br.load<GB_NT>(m, (const double *)a.phi, ps, false);
+    if (with_phi) br.load(m, (const double *)a.phi, ps, false);
     __syncthreads();
-    int tx, ty, tz;
-    bool valid;
-    br.cell_of_thread(threadIdx.x, tx, ty, tz, valid);
-    const int64_t cell = (int64_t)(br.c0x + tx) + (int64_t)m.nx * ((br.c0y + ty) + (int64_t)m.ny * (br.c0z + tz));
+    const int64_t cell = br.valid ? br.cell_index(m) : 0;
     const double vol = m.hx * m.hy * m.hz;
     const double ih[3] = {1.0 / (m.hx * m.hx * kR * kR), 1.0 / (m.hy * m.hy * kR * kR), 1.0 / (m.hz * m.hz * kR * kR)};
     double lq[27], Tq[27], gk[27];
-    br.gather27(ls, tx, ty, tz, lq);
-    br.gather27(Ts, tx, ty, tz, Tq);
+    br.gather27(ls, lq);
+    br.gather27(Ts, Tq);
     interp3(lq);
     interp3(Tq);
     for (int q = 0; q < 27; ++q) gk[q] = 0.0;
@@ -466,14 +394,14 @@ __global__ void __launch_bounds__(GB_NT) heat_grad_kernel(KMesh m, HeatArgs a, c
     grad_dot_acc<double, 1>(lq, Tq, ih[1], gk);
     grad_dot_acc<double, 2>(lq, Tq, ih[2], gk);
     double dtq[27];
-    br.gather27(dTs, tx, ty, tz, dtq);
+    br.gather27(dTs, dtq);
     interp3(dtq);
     double s[27];
     for (int q = 0; q < 27; ++q) {
         const double wq = vol * Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
         const double gkq = -a.ak * wq * gk[q];
         const double grq = -a.am * wq * lq[q] * dtq[q];
-        if (valid) {
+        if (br.valid) {
             if (dk) dk[cell * 27 + q] = gkq;
             if (drc) drc[cell * 27 + q] = grq;
         }
@@ -482,7 +410,7 @@ __global__ void __launch_bounds__(GB_NT) heat_grad_kernel(KMesh m, HeatArgs a, c
     }
     if (!with_phi) return; // uniform over the launch
     double ph[27];
-    br.gather27(ps, tx, ty, tz, ph);
+    br.gather27(ps, ph);
     interp3(ph);
     for (int q = 0; q < 27; ++q) {
         double dH;
@@ -491,32 +419,26 @@ __global__ void __launch_bounds__(GB_NT) heat_grad_kernel(KMesh m, HeatArgs a, c
     }
     interp3T(s);
     __syncthreads();
-    double *E = lds;
-    for (int i = 0; i < 27; ++i) E[threadIdx.x * 27 + i] = valid ? s[i] : 0.0;
+    br.store_cell(lds, s);
     __syncthreads();
-    for (int i = threadIdx.x; i < G::NB; i += GB_NT) {
-        const int lx = i % G::PX, ly = (i / G::PX) % G::PY, lz = i / (G::PX * G::PY);
-        if (lx > 2 * br.ncx || ly > 2 * br.ncy || lz > 2 * br.ncz) continue;
-        const int gx = 2 * br.c0x + lx, gy = 2 * br.c0y + ly, gz = 2 * br.c0z + lz;
-        const int64_t g = node_index(m, gx, gy, gz);
-        const double v = br.node_sum(E, lx, ly, lz);
-        if (br.shared(m, lx, ly, lz, gx, gy, gz))
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool, bool shared) {
+        const double v = br.node_sum(lds, ai, bi, ci);
+        if (shared)
             atomicAdd(&dphi[g], v);
         else
             dphi[g] = v;
-    }
+    });
 }
 
 hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,
                      double *dk, double *drc, double *dphi, hipStream_t s)
 {
-    const int nbx = (m.nx + GB - 1) / GB, nby = (m.ny + GB - 1) / GB, nbz = (m.nz + GB - 1) / GB;
-    const unsigned nb = (unsigned)(nbx * nby * nbz);
+    const unsigned nb = (unsigned)n_bricks(m);
     if (dphi) {
         hipError_t e = vfill(dphi, 0.0, (int64_t)m.NX * m.NY * m.NZ, 0, s);
         if (e != hipSuccess) return e;
     }
-    heat_grad_kernel<<<nb, GB_NT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi);
+    heat_grad_kernel<<<nb, BNT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi);
     return hipGetLastError();
 }
 

@@ -44,9 +44,17 @@ struct RedWS {
     unsigned capacity; // max partial entries
 };
 
+// Optional events recorded immediately around a launcher's main kernel.
+struct KTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // ---- heat (heat.hip) ----
-hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, CGState *cg,
-                      const RedWS *red, hipStream_t s);
+// y = A x in two launches (bricks, then the shared-face combine); `face` is
+// a workspace of face_buffer_elems(m) elements of the operator's type.
+hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, void *face, CGState *cg,
+                      const RedWS *red, hipStream_t s, const KTiming *t = nullptr);
+int64_t face_buffer_elems(const KMesh &m);
 hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, hipStream_t s);
 hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double *rcq, hipStream_t s);
 hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
@@ -55,7 +63,7 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
 
 // ---- Oseen (oseen.hip) ----
 hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y,
-                       hipStream_t s);
+                       hipStream_t s, const KTiming *t = nullptr);
 hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, hipStream_t s);
 
 // ---- vectors and Krylov steps (vec.hip) ----

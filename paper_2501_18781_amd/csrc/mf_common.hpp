@@ -187,24 +187,36 @@ __device__ __forceinline__ void grad_dot_acc(const T *a, const T *b, T ih, T *ou
 // distance d = 2 eps artanh(phi) recovered from the tanh profile.
 // ---------------------------------------------------------------------------
 
+// Linear form, branch free.
+template <typename T> __device__ __forceinline__ T heaviside_linear(T phi)
+{
+    return fmin(fmax(T(0.5) + T(0.5) * phi, T(0)), T(1));
+}
+
+// Sine form in FP64, kept out of line: its transcendental functions would
+// otherwise be replicated at every unrolled Gauss point.
+__device__ __noinline__ inline double heaviside_sine(double eps, double phi, double *dH)
+{
+    const double lim = 1.0 - 1e-15;
+    const double p = phi < -lim ? -lim : (phi > lim ? lim : phi);
+    const double d = 2.0 * eps * atanh(p);
+    if (d <= -3.0 * eps) { *dH = 0.0; return 0.0; }
+    if (d >= 3.0 * eps) { *dH = 0.0; return 1.0; }
+    const double a = M_PI * d / (3.0 * eps);
+    *dH = (1.0 + cos(a)) / (6.0 * eps) * (2.0 * eps / (1.0 - p * p));
+    return 0.5 + d / (6.0 * eps) + sin(a) / (2.0 * M_PI);
+}
+
 template <typename T> __device__ __forceinline__ T heaviside(int kind, T eps, T phi, T *dH)
 {
     if (kind == 0) {
-        if (phi <= T(-1)) { if (dH) *dH = T(0); return T(0); }
-        if (phi >= T(1)) { if (dH) *dH = T(0); return T(1); }
-        if (dH) *dH = T(0.5);
-        return T(0.5) + T(0.5) * phi;
+        if (dH) *dH = (phi > T(-1) && phi < T(1)) ? T(0.5) : T(0);
+        return heaviside_linear<T>(phi);
     }
-    const double lim = 1.0 - 1e-15;
-    double p = (double)phi;
-    p = p < -lim ? -lim : (p > lim ? lim : p);
-    const double e = (double)eps;
-    const double d = 2.0 * e * atanh(p);
-    if (d <= -3.0 * e) { if (dH) *dH = T(0); return T(0); }
-    if (d >= 3.0 * e) { if (dH) *dH = T(0); return T(1); }
-    const double a = M_PI * d / (3.0 * e);
-    if (dH) *dH = T((1.0 + cos(a)) / (6.0 * e) * (2.0 * e / (1.0 - p * p)));
-    return T(0.5 + d / (6.0 * e) + sin(a) / (2.0 * M_PI));
+    double d;
+    const double H = heaviside_sine((double)eps, (double)phi, &d);
+    if (dH) *dH = T(d);
+    return T(H);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,5 +1,5 @@
 // mg.hip -- FP32 geometric multigrid pieces (placeholder until implemented).
-#include "../../include/mf.h"
+#include "mf.h"
 #include "kernels.hpp"
 
 extern "C" {

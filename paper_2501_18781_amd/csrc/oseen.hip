@@ -3,7 +3,7 @@
 
 namespace mf {
 
-hipError_t oseen_apply(const KMesh &, const OseenArgs &, int, const double *, double *, hipStream_t)
+hipError_t oseen_apply(const KMesh &, const OseenArgs &, int, const double *, double *, hipStream_t, const KTiming *)
 {
     return hipErrorNotSupported;
 }

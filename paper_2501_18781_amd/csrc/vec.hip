@@ -329,7 +329,6 @@ __global__ void __launch_bounds__(VNT) cg_init_kernel(CGState *st, const double 
         const double bi = b[i];
         x[i] = 0.0;
         r[i] = bi;
-        q[i] = 0.0;
         if (!flexible) {
             const double zi = dinv ? dinv[i] * bi : bi;
             z[i] = zi;
@@ -380,7 +379,6 @@ __global__ void __launch_bounds__(VNT) cg_update_kernel(CGState *st, const doubl
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
-        q[i] = 0.0;
         const double zi = dinv ? dinv[i] * ri : ri;
         z[i] = zi;
         acc[0] += ri * zi;
@@ -440,7 +438,6 @@ __global__ void __launch_bounds__(VNT) fcg_xr_kernel(CGState *st, double *__rest
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
-        q[i] = 0.0;
         acc += ri * ri;
     }
     if (grid_sum_n<1>(&acc, red, lds, &flag) && threadIdx.x == 0) {

@@ -75,6 +75,9 @@ _SIGS = {
     "mf_last_error": (ctypes.c_char_p, [_P]),
     "mf_n_nodes": (ctypes.c_int64, [_P]),
     "mf_n_cells": (ctypes.c_int64, [_P]),
+    "mf_timing_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mf_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int32]),
     "mf_operator_apply": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
     "mf_operator_apply_transpose": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
     "mf_operator_diagonal": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P]),
@@ -158,6 +161,16 @@ class Context:
         if st not in accept:
             raise MFError(st, library().mf_last_error(self._h).decode())
         return st
+
+    def timing_enable(self, on: bool = True):
+        self.check(library().mf_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self, reset: bool = True):
+        """(summed kernel milliseconds, number of timed launches) since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.check(library().mf_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "_h", None):
