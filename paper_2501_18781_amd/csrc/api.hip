@@ -122,7 +122,7 @@ mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
     int64_t cap = nbricks > 32 * 1024 ? nbricks : 32 * 1024;
     c->cap = (unsigned)cap;
     bool ok = hipMalloc((void **)&c->partials, sizeof(double) * cap) == hipSuccess &&
-              hipMalloc((void **)&c->face, sizeof(double) * face_buffer_elems(k)) == hipSuccess &&
+              hipMalloc((void **)&c->face, sizeof(double) * 3 * face_buffer_elems(k)) == hipSuccess &&
               hipMalloc((void **)&c->counter, sizeof(unsigned) * 16) == hipSuccess &&
               hipMalloc((void **)&c->cg, sizeof(CGState)) == hipSuccess &&
               hipMalloc((void **)&c->scal, sizeof(double) * 256) == hipSuccess &&
@@ -271,7 +271,7 @@ static hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, con
     const KTiming *t = timed ? next_timing(c) : nullptr;
     if (op->kind == MF_HEAT)
         return heat_apply(c->km, heat_args(op), op->precision == MF_FP32, x, y, c->face, nullptr, nullptr, s, t);
-    return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, s, t);
+    return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, c->face, s, t);
 }
 
 extern "C" {

@@ -212,7 +212,7 @@ struct Brick {
 // Shared Dirichlet nodes get y = x here.
 template <typename T>
 __device__ __forceinline__ void combine_faces(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
-                                              T *__restrict__ y, int brick)
+                                              T *__restrict__ y, int brick, int lane)
 {
     const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB;
     const int bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
@@ -220,7 +220,7 @@ __device__ __forceinline__ void combine_faces(const KMesh &m, const T *__restric
     const bool shx = bx > 0, shy = by > 0, shz = bz > 0;
     // candidates: plane z = 0 (81), plane y = 0 without the z = 0 row (72),
     // plane x = 0 without the y = 0 and z = 0 rows (64)
-    for (int i = threadIdx.x; i < BP * BP + BP * (BP - 1) + (BP - 1) * (BP - 1); i += BNT) {
+    for (int i = lane; i < BP * BP + BP * (BP - 1) + (BP - 1) * (BP - 1); i += BNT) {
         int lx, ly, lz;
         if (i < BP * BP) {
             lx = i % BP; ly = i / BP; lz = 0;

@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(BNT) face_combine_kernel(KMesh m, const T *__r
     }
     const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
     const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
-    combine_faces<T>(m, face, x, y, k * q + min(k, r) + j);
+    combine_faces<T>(m, face, x, y, k * q + min(k, r) + j, threadIdx.x);
 }
 
 int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }

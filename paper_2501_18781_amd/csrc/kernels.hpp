@@ -62,7 +62,8 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
                      double *dk, double *drc, double *dphi, hipStream_t s);
 
 // ---- Oseen (oseen.hip) ----
-hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y,
+// y = A x or A^T x; `face` holds 3 face_buffer_elems(m) doubles.
+hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y, void *face,
                        hipStream_t s, const KTiming *t = nullptr);
 hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, hipStream_t s);
 

@@ -1,12 +1,366 @@
-// oseen.hip -- matrix-free Q2 linearized momentum (Oseen) operator.
-#include "kernels.hpp"
+// oseen.hip -- matrix-free Q2 linearized momentum (Oseen) operator on gfx950.
+//
+// Operator (Sec. 2.1, eq. momentum_balance with the viscous stress
+// 2 mu eps(u), linearized about a frozen velocity u0 and one backward-Euler
+// step; rho by the reciprocal blend of eq. rhoEff, mu by eq. muEff):
+//   a(u, v) = int alpha_m rho u.v + alpha_c rho ((u0.grad) u).v
+//           + alpha_v mu (grad u + grad u^T) : grad v
+// (the last term equals 2 mu eps(u):eps(v)).  The transpose moves the
+// convective term onto the test function: alpha_c rho u_c (u0.grad) v_c.
+//
+// Work decomposition: one launch per velocity component c, a 64-thread
+// workgroup per brick of 4x4x4 cells (brick.hpp), one thread per cell.
+// Nodal x (3 components), u0 (3 components) and phi are staged in LDS.
+// Per cell and component:
+//   acc = alpha_m rho W u_c                                  (Gauss values)
+//       + alpha_c rho W sum_d u0_d d_d u_c                   (forward)
+//   acc += sum_d D_d^T [ W mu alpha_v (d_d u_c + d_c u_d)    (viscous)
+//                        + alpha_c rho W u0_d u_c ]          (transpose only)
+//   y_c = S^T acc
+// where d_c u_d is formed by interpolating u_d and differentiating along c,
+// so no gradient fields are exchanged between threads.
+#include <type_traits>
+
+#include "brick.hpp"
 
 namespace mf {
 
-hipError_t oseen_apply(const KMesh &, const OseenArgs &, int, const double *, double *, hipStream_t, const KTiming *)
+constexpr int ONT = 3 * BNT; // threads per Oseen brick
+
+// Heaviside of the interpolated level set at the 27 Gauss points (in place).
+template <int HK> __device__ __forceinline__ void heaviside27(const OseenArgs &a, double *ph)
 {
-    return hipErrorNotSupported;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        if (HK == 0) {
+            ph[q] = heaviside_linear<double>(ph[q]);
+        } else {
+            double d;
+            ph[q] = heaviside_sine(a.eps, ph[q], &d);
+        }
+    }
 }
-hipError_t oseen_block_diagonal(const KMesh &, const OseenArgs &, double *, hipStream_t) { return hipErrorNotSupported; }
+
+__device__ __forceinline__ double gauss_weight(int q)
+{
+    return Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
+}
+
+// d_c applied line by line to the Gauss values v (in place), scaled by s.
+template <int DIR> __device__ __forceinline__ void deriv_inplace(double *v, double s)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            double t0, t1, t2;
+            Q2<double>::deriv(v[i0], v[i1], v[i2], t0, t1, t2);
+            v[i0] = s * t0;
+            v[i1] = s * t1;
+            v[i2] = s * t2;
+        }
+}
+
+// Forward convection along DIR: acc += cw .* w .* (d_DIR u), cw = alpha_c rho W, line by line.
+template <int DIR>
+__device__ __forceinline__ void conv_forward(const double *u, const double *rw, const double *w, double s,
+                                             double *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            double t0, t1, t2;
+            Q2<double>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
+            acc[i0] += s * rw[i0] * w[i0] * t0;
+            acc[i1] += s * rw[i1] * w[i1] * t1;
+            acc[i2] += s * rw[i2] * w[i2] * t2;
+        }
+}
+
+// Transposed convection along DIR: acc += D_DIR^T (s rw .* w .* u), line by line.
+template <int DIR>
+__device__ __forceinline__ void conv_transpose(const double *u, const double *rw, const double *w, double s,
+                                               double *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            Q2<double>::derivT_acc(s * rw[i0] * w[i0] * u[i0], s * rw[i1] * w[i1] * u[i1], s * rw[i2] * w[i2] * u[i2],
+                                   acc[i0], acc[i1], acc[i2]);
+        }
+}
+
+// Viscous part along DIR: g = nu .* (s d_DIR u + e), acc += s D_DIR^T g, line
+// by line (e = d_c u_d already scaled, or null for the d = c term with factor 2).
+template <int DIR, bool TWICE>
+__device__ __forceinline__ void visc_dir(const double *u, const double *nu, const double *e, double s, double *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            double t0, t1, t2;
+            Q2<double>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
+            double g0, g1, g2;
+            if (TWICE) {
+                g0 = 2.0 * s * nu[i0] * t0;
+                g1 = 2.0 * s * nu[i1] * t1;
+                g2 = 2.0 * s * nu[i2] * t2;
+            } else {
+                g0 = nu[i0] * (s * t0 + e[i0]);
+                g1 = nu[i1] * (s * t1 + e[i1]);
+                g2 = nu[i2] * (s * t2 + e[i2]);
+            }
+            Q2<double>::derivT_acc(s * g0, s * g1, s * g2, acc[i0], acc[i1], acc[i2]);
+        }
+}
+
+template <int D> __device__ __forceinline__ void conv_any(bool tr, const double *u, const double *rw, const double *w,
+                                                          double s, double *acc)
+{
+    if (tr) conv_transpose<D>(u, rw, w, s, acc);
+    else conv_forward<D>(u, rw, w, s, acc);
+}
+
+// One component C of the Oseen operator on one cell; result (nodal) in acc.
+template <int C, int HK, bool TR>
+__device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, const KMesh &m, const double *ps,
+                                           const double *us, const double *u0s, double *acc)
+{
+    const double vol = m.hx * m.hy * m.hz;
+    const double sdir[3] = {1.0 / (kR * m.hx), 1.0 / (kR * m.hy), 1.0 / (kR * m.hz)};
+    double rw[27]; // rho W
+    br.gather27(ps, rw);
+    interp3(rw);
+    heaviside27<HK>(a, rw);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) rw[q] = vol * gauss_weight(q) / (rw[q] / a.rho_l + (1.0 - rw[q]) / a.rho_g);
+    double u[27];
+    br.gather27(us + C * BNB, u);
+    interp3(u);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) acc[q] = a.am * rw[q] * u[q];
+    {
+        double w[27];
+        br.gather27(u0s, w);
+        interp3(w);
+        conv_any<0>(TR, u, rw, w, a.ac * sdir[0], acc);
+        br.gather27(u0s + BNB, w);
+        interp3(w);
+        conv_any<1>(TR, u, rw, w, a.ac * sdir[1], acc);
+        br.gather27(u0s + 2 * BNB, w);
+        interp3(w);
+        conv_any<2>(TR, u, rw, w, a.ac * sdir[2], acc);
+    }
+    // viscosity nu = alpha_v W mu (overwrites rho W, no longer needed)
+    double *nu = rw;
+    br.gather27(ps, nu);
+    interp3(nu);
+    heaviside27<HK>(a, nu);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) nu[q] = a.av * vol * gauss_weight(q) * (a.mu_g + nu[q] * (a.mu_l - a.mu_g));
+    double e[27];
+    auto cross = [&](auto D) {
+        constexpr int d = decltype(D)::value;
+        if (d == C) {
+            visc_dir<d, true>(u, nu, nullptr, sdir[d], acc);
+        } else {
+            br.gather27(us + d * BNB, e);
+            interp3(e);
+            deriv_inplace<C>(e, sdir[C]); // d_C u_d
+            visc_dir<d, false>(u, nu, e, sdir[d], acc);
+        }
+    };
+    cross(std::integral_constant<int, 0>{});
+    cross(std::integral_constant<int, 1>{});
+    cross(std::integral_constant<int, 2>{});
+    interp3T(acc);
+}
+
+template <int C, int HK, bool TR>
+__global__ void __launch_bounds__(BNT) oseen_apply_kernel(KMesh m, OseenArgs a, const double *__restrict__ x,
+                                                          double *__restrict__ y, double *__restrict__ face)
+{
+    // staging: phi, x (3 components), u0 (3 components); then the cell
+    // contributions of component C
+    constexpr int STAGE = 7 * BNB;
+    __shared__ double lds[STAGE];
+    const Brick br(m, threadIdx.x);
+    const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
+    double *ps = lds, *us = lds + BNB, *u0s = lds + 4 * BNB;
+    br.load(m, a.phi, ps, false);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        br.load(m, x + c * nn, us + c * BNB, true);
+        br.load(m, a.u0 + c * nn, u0s + c * BNB, false);
+    }
+    __syncthreads();
+    double acc[27];
+    oseen_cell<C, HK, TR>(br, a, m, ps, us, u0s, acc);
+    __syncthreads();
+    double *E = lds;
+    br.store_cell(E, acc);
+    __syncthreads();
+    double *fb = face + ((int64_t)C * n_bricks(m) + br.brick) * BFACE;
+    double *yc = y + C * nn;
+    const double *xc = x + C * nn;
+    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool, int sh) {
+        const double s = br.node_sum(E, ai, bi, ci);
+        double *dst = sh ? fb + face_slot(lx0 + ai, ly0 + bi, lz0 + ci) : yc + g;
+        *dst = s;
+    });
+    if (br.touches_dirichlet(m)) {
+        br.for_owned_nodes(m, [&](int, int, int, int, int64_t g, bool constrained, int sh) {
+            if (constrained && !sh) yc[g] = xc[g];
+        });
+    }
+}
+
+__global__ void __launch_bounds__(ONT) oseen_combine_kernel(KMesh m, const double *__restrict__ face,
+                                                            const double *__restrict__ x, double *__restrict__ y)
+{
+    const int comp = threadIdx.x / BNT;
+    const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
+    const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
+    const int64_t nn = (int64_t)m.NX * m.NY * m.NZ, nb = n_bricks(m);
+    combine_faces<double>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn, k * q + min(k, r) + j,
+                          threadIdx.x % BNT);
+}
+
+hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y, void *face,
+                       hipStream_t s, const KTiming *t)
+{
+    const unsigned nb = (unsigned)n_bricks(m);
+    if (!face) return hipErrorInvalidValue;
+    if (t && t->start) {
+        hipError_t e = hipEventRecord(t->start, s);
+        if (e != hipSuccess) return e;
+    }
+    double *fb = (double *)face;
+    const int key = (a.hkind ? 2 : 0) | (transpose ? 1 : 0);
+    switch (key) {
+#define OSEEN_CASE(K, HK, TR)                                                                                 \
+    case K:                                                                                                   \
+        oseen_apply_kernel<0, HK, TR><<<nb, BNT, 0, s>>>(m, a, x, y, fb);                                     \
+        oseen_apply_kernel<1, HK, TR><<<nb, BNT, 0, s>>>(m, a, x, y, fb);                                     \
+        oseen_apply_kernel<2, HK, TR><<<nb, BNT, 0, s>>>(m, a, x, y, fb);                                     \
+        break;
+        OSEEN_CASE(0, 0, false)
+        OSEEN_CASE(1, 0, true)
+        OSEEN_CASE(2, 1, false)
+        OSEEN_CASE(3, 1, true)
+#undef OSEEN_CASE
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
+    if (e != hipSuccess) return e;
+    oseen_combine_kernel<<<nb, ONT, 0, s>>>(m, fb, x, y);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 nodal diagonal blocks: for each cell node i and component pair (c, c'),
+//   B_i[c][c'] = sum_q W [ (alpha_m rho N_i^2 + alpha_c rho N_i (u0.grad N_i)
+//                           + alpha_v mu |grad N_i|^2) delta_cc'
+//                         + alpha_v mu d_c' N_i d_c N_i ]
+// by direct loops over the Gauss points (setup only), one pass per entry.
+// Shared nodes are added with FP64 atomics into a cleared output.
+// ---------------------------------------------------------------------------
+template <int HK>
+__global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, double *__restrict__ blocks)
+{
+    constexpr int STAGE = 4 * BNB, CONTRIB = 27 * BNT;
+    __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
+    __shared__ double E[27 * BNT];
+    const Brick br(m, threadIdx.x);
+    const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
+    double *ps = lds, *u0s = lds + BNB;
+    br.load(m, a.phi, ps, false);
+    for (int c = 0; c < 3; ++c) br.load(m, a.u0 + c * nn, u0s + c * BNB, false);
+    __syncthreads();
+    const double vol = m.hx * m.hy * m.hz;
+    const double ih[3] = {1.0 / m.hx, 1.0 / m.hy, 1.0 / m.hz};
+    double rw[27], nu[27], w0[27], w1[27], w2[27];
+    br.gather27(ps, rw);
+    interp3(rw);
+    heaviside27<HK>(a, rw);
+    for (int q = 0; q < 27; ++q) {
+        const double H = rw[q];
+        const double W = vol * gauss_weight(q);
+        rw[q] = W / (H / a.rho_l + (1.0 - H) / a.rho_g);
+        nu[q] = a.av * W * (a.mu_g + H * (a.mu_l - a.mu_g));
+    }
+    br.gather27(u0s, w0);
+    interp3(w0);
+    br.gather27(u0s + BNB, w1);
+    interp3(w1);
+    br.gather27(u0s + 2 * BNB, w2);
+    interp3(w2);
+    const double S[3][3] = {{Q2<double>::s0, Q2<double>::s1, Q2<double>::s2}, {0.0, 1.0, 0.0},
+                            {Q2<double>::s2, Q2<double>::s1, Q2<double>::s0}};
+    const double Gd[3][3] = {{Q2<double>::g0, Q2<double>::g1, Q2<double>::g2}, {-1.0, 0.0, 1.0},
+                             {-Q2<double>::g2, -Q2<double>::g1, -Q2<double>::g0}};
+    // entries (0,0) (1,1) (2,2) (0,1) (0,2) (1,2); the block is symmetric but
+    // for the convective term, which only enters the diagonal
+    for (int e = 0; e < 6; ++e) {
+        const int c = e < 3 ? e : (e == 5 ? 1 : 0);
+        const int cp = e < 3 ? e : (e == 3 ? 1 : 2);
+        double d[27];
+        for (int i = 0; i < 27; ++i) {
+            const int ia = i % 3, ib = (i / 3) % 3, ic = i / 9;
+            double sacc = 0.0;
+            for (int q = 0; q < 27; ++q) {
+                const int qa = q % 3, qb = (q / 3) % 3, qc = q / 9;
+                const double nx = S[qa][ia], ny = S[qb][ib], nz = S[qc][ic];
+                const double n = nx * ny * nz;
+                const double g[3] = {Gd[qa][ia] * ny * nz * ih[0], nx * Gd[qb][ib] * nz * ih[1],
+                                     nx * ny * Gd[qc][ic] * ih[2]};
+                double v = nu[q] * g[cp] * g[c];
+                if (c == cp) {
+                    v += a.am * rw[q] * n * n + a.ac * rw[q] * n * (w0[q] * g[0] + w1[q] * g[1] + w2[q] * g[2]) +
+                         nu[q] * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                }
+                sacc += v;
+            }
+            d[i] = sacc;
+        }
+        __syncthreads();
+        br.store_cell(E, d);
+        __syncthreads();
+        br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, bool shared) {
+            double *B = blocks + 9 * g;
+            if (constrained) {
+                B[3 * c + cp] = (c == cp) ? 1.0 : 0.0;
+                B[3 * cp + c] = (c == cp) ? 1.0 : 0.0;
+                return;
+            }
+            const double s = br.node_sum(E, ai, bi, ci);
+            if (shared) {
+                atomicAdd(&B[3 * c + cp], s);
+                if (c != cp) atomicAdd(&B[3 * cp + c], s);
+            } else {
+                B[3 * c + cp] = s;
+                if (c != cp) B[3 * cp + c] = s;
+            }
+        });
+    }
+}
+
+hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, hipStream_t s)
+{
+    const unsigned nb = (unsigned)n_bricks(m);
+    hipError_t e = vfill(blocks, 0.0, 9 * (int64_t)m.NX * m.NY * m.NZ, 0, s);
+    if (e != hipSuccess) return e;
+    if (a.hkind == 0) oseen_block_kernel<0><<<nb, BNT, 0, s>>>(m, a, blocks);
+    else oseen_block_kernel<1><<<nb, BNT, 0, s>>>(m, a, blocks);
+    return hipGetLastError();
+}
 
 } // namespace mf
