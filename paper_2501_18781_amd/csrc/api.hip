@@ -12,39 +12,13 @@
 #include <string>
 #include <vector>
 
-#include "mf.h"
-#include "kernels.hpp"
+#include "ctx.hpp"
 
 using namespace mf;
 
-struct mf_ctx {
-    mf_mesh mesh;
-    KMesh km;
-    int device = 0;
-    int64_t nn = 0, nc = 0;
-    std::string err;
-    // workspace: vectors of 3 * n_nodes doubles each
-    std::vector<double *> vec;
-    double *partials = nullptr;
-    unsigned *counter = nullptr;
-    unsigned cap = 0;
-    CGState *cg = nullptr;
-    double *scal = nullptr;      // device scalars
-    CGState *h_state = nullptr;  // pinned host copy
-    double *h_scal = nullptr;    // pinned host scalars
-    double *V = nullptr;         // GMRES basis
-    int V_cols = 0;
-    double *blocks = nullptr;    // Oseen block-Jacobi inverse
-    double *face = nullptr;      // shared-face partial sums of the brick kernels
-    // kernel timing
-    bool timing = false;
-    std::vector<KTiming> events;
-    size_t events_used = 0;
-};
-
 static const char *g_static_err = "no context";
 
-static mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...)
+mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...)
 {
     if (c) {
         char buf[512];
@@ -57,16 +31,23 @@ static mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIPCHK(c, expr)                                                                          \
-    do {                                                                                         \
-        hipError_t e_ = (expr);                                                                  \
-        if (e_ != hipSuccess) return fail((c), MF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-static RedWS redws(mf_ctx *c) { return RedWS{c->partials, c->counter, c->cap}; }
+RedWS redws(mf_ctx *c) { return RedWS{c->partials, c->counter, c->cap}; }
 
 // Workspace vector i (3 * n_nodes doubles), allocated on first use.
-static mf_status ws_vec(mf_ctx *c, int i, double **out)
+mf_status ensure_face(mf_ctx *c, int comps)
+{
+    const int64_t need = comps * face_buffer_elems(c->km);
+    if (c->face_elems >= need) return MF_OK;
+    if (c->face) (void)hipFree(c->face); // synchronizes with work that may still use it
+    c->face = nullptr;
+    c->face_elems = 0;
+    if (hipMalloc((void **)&c->face, sizeof(double) * need) != hipSuccess)
+        return fail(c, MF_ERR_OOM, "face buffer allocation of %lld doubles failed", (long long)need);
+    c->face_elems = need;
+    return MF_OK;
+}
+
+mf_status ws_vec(mf_ctx *c, int i, double **out)
 {
     while ((int)c->vec.size() <= i) c->vec.push_back(nullptr);
     if (!c->vec[i]) {
@@ -122,7 +103,6 @@ mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
     int64_t cap = nbricks > 32 * 1024 ? nbricks : 32 * 1024;
     c->cap = (unsigned)cap;
     bool ok = hipMalloc((void **)&c->partials, sizeof(double) * cap) == hipSuccess &&
-              hipMalloc((void **)&c->face, sizeof(double) * 3 * face_buffer_elems(k)) == hipSuccess &&
               hipMalloc((void **)&c->counter, sizeof(unsigned) * 16) == hipSuccess &&
               hipMalloc((void **)&c->cg, sizeof(CGState)) == hipSuccess &&
               hipMalloc((void **)&c->scal, sizeof(double) * 256) == hipSuccess &&
@@ -189,7 +169,7 @@ mf_status mf_timing_read(mf_ctx *c, double *ms, int64_t *launches, int32_t reset
 // ---------------------------------------------------------------------------
 // Operator descriptors
 // ---------------------------------------------------------------------------
-static mf_status check_op(mf_ctx *c, const mf_operator *op)
+mf_status check_op(mf_ctx *c, const mf_operator *op)
 {
     if (!c) return MF_ERR_ARG;
     if (!op) return fail(c, MF_ERR_ARG, "null operator");
@@ -215,7 +195,7 @@ static mf_status check_op(mf_ctx *c, const mf_operator *op)
     return MF_OK;
 }
 
-static HeatArgs heat_args(const mf_operator *op)
+HeatArgs heat_args(const mf_operator *op)
 {
     HeatArgs a;
     a.mode = op->coeff_mode == MF_COEFF_QUAD ? 1 : 0;
@@ -233,7 +213,7 @@ static HeatArgs heat_args(const mf_operator *op)
     return a;
 }
 
-static OseenArgs oseen_args(const mf_operator *op)
+OseenArgs oseen_args(const mf_operator *op)
 {
     OseenArgs a;
     a.hkind = op->heaviside;
@@ -250,7 +230,7 @@ static OseenArgs oseen_args(const mf_operator *op)
     return a;
 }
 
-static int64_t ndofs(const mf_ctx *c, const mf_operator *op) { return op->kind == MF_OSEEN ? 3 * c->nn : c->nn; }
+int64_t ndofs(const mf_ctx *c, const mf_operator *op) { return op->kind == MF_OSEEN ? 3 * c->nn : c->nn; }
 
 // Next event pair for a timed launch (nullptr when timing is off).
 static const KTiming *next_timing(mf_ctx *c)
@@ -265,9 +245,10 @@ static const KTiming *next_timing(mf_ctx *c)
 }
 
 // y = A x or A^T x, FP64 or FP32 (heat)
-static hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s,
-                            bool timed = false)
+hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s,
+                     bool timed)
 {
+    if (ensure_face(c, op->kind == MF_OSEEN ? 3 : 1) != MF_OK) return hipErrorOutOfMemory;
     const KTiming *t = timed ? next_timing(c) : nullptr;
     if (op->kind == MF_HEAT)
         return heat_apply(c->km, heat_args(op), op->precision == MF_FP32, x, y, c->face, nullptr, nullptr, s, t);
@@ -345,7 +326,7 @@ mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, 
 // Helpers for the solvers
 // ---------------------------------------------------------------------------
 // ||v||^2 read back to the host (synchronizes the stream)
-static mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s)
+mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s)
 {
     RedWS r = redws(c);
     HIPCHK(c, vmultidot(a, n, 1, b, n, c->scal, &r, s));
@@ -356,7 +337,7 @@ static mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n
 }
 
 // true relative residual ||b - A x|| / ||b||, using workspace vector `tmp`
-static mf_status true_residual(mf_ctx *c, const mf_operator *op, int transpose, const double *b, const double *x,
+mf_status true_residual(mf_ctx *c, const mf_operator *op, int transpose, const double *b, const double *x,
                                double *tmp, double bnorm, double *out, hipStream_t s)
 {
     const int64_t n = ndofs(c, op);
@@ -386,6 +367,7 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
     if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)))
         return st;
     const HeatArgs ha = heat_args(op);
+    if ((st = ensure_face(c, 1))) return st;
     if (precond == MF_PC_JACOBI) {
         if ((st = ws_vec(c, 4, &dinv))) return st;
         HIPCHK(c, heat_diagonal(c->km, ha, 0, dinv, s));

@@ -1,0 +1,63 @@
+// ctx.hpp -- internal definition of the library context and the host
+// helpers shared by api.hip (operators, CG, GMRES) and mg.hip (multigrid).
+// Not part of the public boundary (include/mf.h).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "mf.h"
+#include "kernels.hpp"
+
+struct mf_ctx {
+    mf_mesh mesh;
+    mf::KMesh km;
+    int device = 0;
+    int64_t nn = 0, nc = 0;
+    std::string err;
+    // workspace: vectors of 3 * n_nodes doubles each
+    std::vector<double *> vec;
+    double *partials = nullptr;
+    unsigned *counter = nullptr;
+    unsigned cap = 0;
+    mf::CGState *cg = nullptr;
+    double *scal = nullptr;      // device scalars
+    mf::CGState *h_state = nullptr;  // pinned host copy
+    double *h_scal = nullptr;    // pinned host scalars
+    double *V = nullptr;         // GMRES basis
+    int V_cols = 0;
+    double *blocks = nullptr;    // Oseen block-Jacobi inverse
+    double *face = nullptr;      // shared-face partial sums of the brick kernels
+    int64_t face_elems = 0;      // its capacity in doubles
+    // kernel timing
+    bool timing = false;
+    std::vector<mf::KTiming> events;
+    size_t events_used = 0;
+};
+
+
+#define HIPCHK(c, expr)                                                                             \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail((c), MF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Record an error message on the context and return the status.
+mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...);
+mf::RedWS redws(mf_ctx *c);
+// Face buffer for operators with `comps` components (allocated on demand).
+mf_status ensure_face(mf_ctx *c, int comps);
+// Workspace vector i of the context (3 * n_nodes doubles), allocated on first use.
+mf_status ws_vec(mf_ctx *c, int i, double **out);
+mf_status check_op(mf_ctx *c, const mf_operator *op);
+mf::HeatArgs heat_args(const mf_operator *op);
+mf::OseenArgs oseen_args(const mf_operator *op);
+int64_t ndofs(const mf_ctx *c, const mf_operator *op);
+// y = A x or A^T x for any operator kind / precision; timed: record kernel events.
+hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s,
+                     bool timed = false);
+// a.b read back to the host (synchronizes the stream).
+mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s);
+// ||b - A x|| / bnorm using workspace vector tmp.
+mf_status true_residual(mf_ctx *c, const mf_operator *op, int transpose, const double *b, const double *x,
+                        double *tmp, double bnorm, double *out, hipStream_t s);

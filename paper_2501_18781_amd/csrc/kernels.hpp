@@ -114,6 +114,5 @@ hipError_t cheb_first(const float *dinv, const float *r, float *d, float *x, flo
 hipError_t cheb_step(const float *dinv, float *r, const float *Ad, float *d, float *x, float c1, float c2,
                      int64_t n, hipStream_t s);
 hipError_t vsub_f(const float *b, const float *Ax, float *r, int64_t n, hipStream_t s); // r = b - Ax
-hipError_t vadd_f(const float *a, float *y, int64_t n, hipStream_t s);                  // y += a
 
 } // namespace mf

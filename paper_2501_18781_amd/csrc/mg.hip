@@ -1,19 +1,591 @@
-// mg.hip -- FP32 geometric multigrid pieces (placeholder until implemented).
-#include "mf.h"
-#include "kernels.hpp"
+// mg.hip -- FP32 geometric multigrid preconditioner for the heat operator,
+// and flexible CG in FP64 preconditioned by it.
+//
+// Levels: the fine mesh and its uniform coarsenings (cells halved per
+// direction) down to `coarse_cells` cells.  Every level is rediscretized
+// with the level set injected to the coarse nodes; all levels but the
+// coarsest apply the operator in FP32, the coarsest is solved by FP64 CG
+// (App. B: CG for symmetric systems) with a Jacobi preconditioner.
+//
+// Transfer: P is the embedding of the coarse Q2 space into the fine one
+// (coarse Q2 functions are fine Q2 functions): in 1D a fine node at a coarse
+// node takes its value, the fine nodes at the quarter points of a coarse
+// cell take (3/8, 3/4, -1/8) and (-1/8, 3/4, 3/8) of the cell's three coarse
+// nodes; in 3D the tensor product.  Restriction R = P^T.  Rows of P at
+// Dirichlet fine nodes and columns at Dirichlet coarse nodes are zero.
+//
+// Smoother: Chebyshev iteration of degree k on D^{-1} A over
+// [lambda_max / range, lambda_max] (Saad, Iterative Methods, Alg. 12.1, with
+// the residual updated recursively); lambda_max = safety x the largest
+// eigenvalue of the Lanczos tridiagonal matrix of D^{-1/2} A D^{-1/2} after
+// a fixed number of steps from a deterministic start vector (Knuth's
+// multiplicative hash).  The V-cycle: pre-smoothing from zero, residual,
+// restriction, coarse correction, prolongation, post-smoothing.
+#include <math.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "ctx.hpp"
+
+using namespace mf;
+
+namespace mf {
+
+#define GSTRIDE(i, n) for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+static unsigned grid_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 65535 * 16) b = 65535 * 16;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Prolongation-add: xf += P ec.  One thread per fine node.
+__global__ void prolong_add_kernel(KMesh c, KMesh f, const float *__restrict__ ec, float *__restrict__ xf)
+{
+    const int64_t nf = (int64_t)f.NX * f.NY * f.NZ;
+    GSTRIDE(i, nf)
+    {
+        const int fx = (int)(i % f.NX), fy = (int)((i / f.NX) % f.NY), fz = (int)(i / ((int64_t)f.NX * f.NY));
+        if (node_constrained(f, fx, fy, fz)) continue;
+        int ix[3], iy[3], iz[3];
+        float wx[3], wy[3], wz[3];
+        int nx = 0, ny = 0, nz = 0;
+        auto taps = [](int t, int *idx, float *w) -> int {
+            if ((t & 1) == 0) {
+                idx[0] = t >> 1;
+                w[0] = 1.0f;
+                return 1;
+            }
+            const int cc = t >> 2;
+            const bool first = (t & 3) == 1;
+            idx[0] = 2 * cc;
+            idx[1] = 2 * cc + 1;
+            idx[2] = 2 * cc + 2;
+            w[0] = first ? 0.375f : -0.125f;
+            w[1] = 0.75f;
+            w[2] = first ? -0.125f : 0.375f;
+            return 3;
+        };
+        nx = taps(fx, ix, wx);
+        ny = taps(fy, iy, wy);
+        nz = taps(fz, iz, wz);
+        float s = 0.0f;
+        for (int kz = 0; kz < nz; ++kz)
+            for (int ky = 0; ky < ny; ++ky)
+                for (int kx = 0; kx < nx; ++kx) {
+                    if (node_constrained(c, ix[kx], iy[ky], iz[kz])) continue;
+                    s += wx[kx] * wy[ky] * wz[kz] * ec[node_index(c, ix[kx], iy[ky], iz[kz])];
+                }
+        xf[i] += s;
+    }
+}
+
+// Restriction rc = P^T rf.  One thread per coarse node.
+__global__ void restrict_kernel(KMesh f, KMesh c, const float *__restrict__ rf, float *__restrict__ rc)
+{
+    const int64_t ncn = (int64_t)c.NX * c.NY * c.NZ;
+    GSTRIDE(i, ncn)
+    {
+        const int sx = (int)(i % c.NX), sy = (int)((i / c.NX) % c.NY), sz = (int)(i / ((int64_t)c.NX * c.NY));
+        if (node_constrained(c, sx, sy, sz)) {
+            rc[i] = 0.0f;
+            continue;
+        }
+        auto taps = [](int s, int tmax, int *idx, float *w) -> int {
+            int n = 0;
+            auto add = [&](int t, float wt) {
+                if (t >= 0 && t <= tmax) {
+                    idx[n] = t;
+                    w[n] = wt;
+                    ++n;
+                }
+            };
+            if ((s & 1) == 0) {
+                add(2 * s - 3, -0.125f);
+                add(2 * s - 1, 0.375f);
+                add(2 * s, 1.0f);
+                add(2 * s + 1, 0.375f);
+                add(2 * s + 3, -0.125f);
+            } else {
+                add(2 * s - 1, 0.75f);
+                add(2 * s, 1.0f);
+                add(2 * s + 1, 0.75f);
+            }
+            return n;
+        };
+        int ix[5], iy[5], iz[5];
+        float wx[5], wy[5], wz[5];
+        const int nx = taps(sx, f.NX - 1, ix, wx), ny = taps(sy, f.NY - 1, iy, wy), nz = taps(sz, f.NZ - 1, iz, wz);
+        float s = 0.0f;
+        for (int kz = 0; kz < nz; ++kz)
+            for (int ky = 0; ky < ny; ++ky)
+                for (int kx = 0; kx < nx; ++kx) {
+                    if (node_constrained(f, ix[kx], iy[ky], iz[kz])) continue;
+                    s += wx[kx] * wy[ky] * wz[kz] * rf[node_index(f, ix[kx], iy[ky], iz[kz])];
+                }
+        rc[i] = s;
+    }
+}
+
+template <typename T> __global__ void inject_kernel(KMesh f, KMesh c, const T *__restrict__ pf, T *__restrict__ pc)
+{
+    const int64_t ncn = (int64_t)c.NX * c.NY * c.NZ;
+    GSTRIDE(i, ncn)
+    {
+        const int sx = (int)(i % c.NX), sy = (int)((i / c.NX) % c.NY), sz = (int)(i / ((int64_t)c.NX * c.NY));
+        pc[i] = pf[node_index(f, 2 * sx, 2 * sy, 2 * sz)];
+    }
+}
+
+// Chebyshev: d = D^{-1} r / theta, x = d (from zero) or x += d.
+__global__ void cheb_first_kernel(const float *__restrict__ dinv, const float *__restrict__ r, float *__restrict__ d,
+                                  float *__restrict__ x, float inv_theta, int x_zero, int64_t n)
+{
+    GSTRIDE(i, n)
+    {
+        const float di = dinv[i] * r[i] * inv_theta;
+        d[i] = di;
+        x[i] = x_zero ? di : x[i] + di;
+    }
+}
+
+// Chebyshev step: r -= A d, d = c1 d + c2 D^{-1} r, x += d.
+__global__ void cheb_step_kernel(const float *__restrict__ dinv, float *__restrict__ r, const float *__restrict__ Ad,
+                                 float *__restrict__ d, float *__restrict__ x, float c1, float c2, int64_t n)
+{
+    GSTRIDE(i, n)
+    {
+        const float ri = r[i] - Ad[i];
+        r[i] = ri;
+        const float di = c1 * d[i] + c2 * dinv[i] * ri;
+        d[i] = di;
+        x[i] += di;
+    }
+}
+
+__global__ void sub_f_kernel(const float *__restrict__ b, const float *__restrict__ Ax, float *__restrict__ r, int64_t n)
+{
+    GSTRIDE(i, n) r[i] = b[i] - Ax[i];
+}
+
+__global__ void copy_f_kernel(const float *__restrict__ a, float *__restrict__ y, int64_t n) { GSTRIDE(i, n) y[i] = a[i]; }
+
+__global__ void knuth_kernel(double *__restrict__ v, int64_t n)
+{
+    GSTRIDE(i, n)
+    {
+        const uint32_t h = (uint32_t)i * 2654435761u; // wraps modulo 2^32
+        v[i] = (double)h / 4294967296.0 - 0.5;
+    }
+}
+
+__global__ void sqrt_kernel(const double *__restrict__ d, double *__restrict__ s, int64_t n) { GSTRIDE(i, n) s[i] = sqrt(d[i]); }
+
+hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s)
+{
+    restrict_kernel<<<grid_for((int64_t)coarse.NX * coarse.NY * coarse.NZ), 256, 0, s>>>(fine, coarse, rf, rc);
+    return hipGetLastError();
+}
+
+hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, hipStream_t s)
+{
+    prolong_add_kernel<<<grid_for((int64_t)fine.NX * fine.NY * fine.NZ), 256, 0, s>>>(coarse, fine, ec, xf);
+    return hipGetLastError();
+}
+
+hipError_t mg_inject(const KMesh &fine, const KMesh &coarse, const void *phif, void *phic, int fp32, hipStream_t s)
+{
+    const unsigned g = grid_for((int64_t)coarse.NX * coarse.NY * coarse.NZ);
+    if (fp32) inject_kernel<float><<<g, 256, 0, s>>>(fine, coarse, (const float *)phif, (float *)phic);
+    else inject_kernel<double><<<g, 256, 0, s>>>(fine, coarse, (const double *)phif, (double *)phic);
+    return hipGetLastError();
+}
+
+hipError_t cheb_first(const float *dinv, const float *r, float *d, float *x, float inv_theta, int x_zero, int64_t n,
+                      hipStream_t s)
+{
+    cheb_first_kernel<<<grid_for(n), 256, 0, s>>>(dinv, r, d, x, inv_theta, x_zero, n);
+    return hipGetLastError();
+}
+
+hipError_t cheb_step(const float *dinv, float *r, const float *Ad, float *d, float *x, float c1, float c2, int64_t n,
+                     hipStream_t s)
+{
+    cheb_step_kernel<<<grid_for(n), 256, 0, s>>>(dinv, r, Ad, d, x, c1, c2, n);
+    return hipGetLastError();
+}
+
+hipError_t vsub_f(const float *b, const float *Ax, float *r, int64_t n, hipStream_t s)
+{
+    sub_f_kernel<<<grid_for(n), 256, 0, s>>>(b, Ax, r, n);
+    return hipGetLastError();
+}
+
+hipError_t vcopy_f(const float *a, float *y, int64_t n, hipStream_t s)
+{
+    copy_f_kernel<<<grid_for(n), 256, 0, s>>>(a, y, n);
+    return hipGetLastError();
+}
+
+hipError_t vknuth(double *v, int64_t n, hipStream_t s)
+{
+    knuth_kernel<<<grid_for(n), 256, 0, s>>>(v, n);
+    return hipGetLastError();
+}
+
+hipError_t vsqrt(const double *d, double *out, int64_t n, hipStream_t s)
+{
+    sqrt_kernel<<<grid_for(n), 256, 0, s>>>(d, out, n);
+    return hipGetLastError();
+}
+
+} // namespace mf
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (a, b) by bisection
+// on the Sturm count of the LDL^T pivots.
+static double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b)
+{
+    const int n = (int)a.size();
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < n - 1 ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < n; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= n) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+struct MGLevel {
+    mf_ctx *ctx = nullptr;     // mesh context of the level (workspace, face buffer)
+    mf_mesh mesh;
+    int64_t nn = 0;
+    double *phi64 = nullptr;   // level set, FP64 (owned except on the finest level)
+    bool own_phi64 = false;
+    float *phi32 = nullptr;
+    float *dinv = nullptr;     // FP32 inverse diagonal
+    float *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+    double lmax = 0.0, lmin = 0.0;
+    mf_operator op32, op64;
+};
+
+struct mf_mg {
+    mf_ctx *parent = nullptr;
+    mf_operator fine_op;
+    mf_mg_params prm;
+    std::vector<MGLevel> L; // 0 = coarsest
+    double *b64 = nullptr, *x64 = nullptr; // coarse FP64 right-hand side and solution
+};
+
+static mf_status mg_fail(mf_mg *mg, mf_status st, const char *msg)
+{
+    return fail(mg ? mg->parent : nullptr, st, "%s", msg);
+}
+
+#define MGCHK(mg, expr)                                                                                   \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) return fail((mg)->parent, MF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static void mg_free(mf_mg *mg)
+{
+    if (!mg) return;
+    for (MGLevel &l : mg->L) {
+        if (l.own_phi64 && l.phi64) (void)hipFree(l.phi64);
+        for (void *p : {(void *)l.phi32, (void *)l.dinv, (void *)l.b, (void *)l.x, (void *)l.r, (void *)l.d, (void *)l.t})
+            if (p) (void)hipFree(p);
+        if (l.ctx) mf_destroy(l.ctx);
+    }
+    if (mg->b64) (void)hipFree(mg->b64);
+    if (mg->x64) (void)hipFree(mg->x64);
+    delete mg;
+}
+
+// lambda_max of D^{-1} A on a level: Lanczos on D^{-1/2} A D^{-1/2} in FP64.
+static mf_status lanczos_lmax(mf_mg *mg, MGLevel &l, int steps, double *out, hipStream_t s)
+{
+    mf_ctx *c = l.ctx;
+    const int64_t n = l.nn;
+    double *sv, *q, *qp, *w, *tmp;
+    mf_status st;
+    if ((st = ws_vec(c, 0, &sv)) || (st = ws_vec(c, 1, &q)) || (st = ws_vec(c, 2, &qp)) || (st = ws_vec(c, 3, &w)) ||
+        (st = ws_vec(c, 4, &tmp)))
+        return st;
+    MGCHK(mg, heat_diagonal(c->km, heat_args(&l.op64), 0, tmp, s));
+    MGCHK(mg, vinv(tmp, n, s));
+    MGCHK(mg, vsqrt(tmp, sv, n, s));
+    MGCHK(mg, vknuth(q, n, s));
+    double nq2;
+    if ((st = host_dot(c, q, q, n, &nq2, s))) return st;
+    MGCHK(mg, vaxpby(1.0 / sqrt(nq2), q, 0.0, q, n, s));
+    MGCHK(mg, vfill(qp, 0.0, n, 0, s));
+    std::vector<double> al, be;
+    double beta = 0.0;
+    for (int k = 0; k < steps; ++k) {
+        MGCHK(mg, vmul(sv, q, tmp, n, s));
+        MGCHK(mg, heat_apply(c->km, heat_args(&l.op64), 0, tmp, w, c->face, nullptr, nullptr, s));
+        MGCHK(mg, vmul(sv, w, w, n, s));
+        double a;
+        if ((st = host_dot(c, w, q, n, &a, s))) return st;
+        MGCHK(mg, vaxpby(-a, q, 1.0, w, n, s));
+        MGCHK(mg, vaxpby(-beta, qp, 1.0, w, n, s));
+        al.push_back(a);
+        double b2;
+        if ((st = host_dot(c, w, w, n, &b2, s))) return st;
+        beta = sqrt(b2);
+        if (k == steps - 1 || beta == 0.0) break;
+        be.push_back(beta);
+        MGCHK(mg, vcopy(q, qp, n, s));
+        MGCHK(mg, vaxpby(1.0 / beta, w, 0.0, q, n, s));
+    }
+    be.resize(al.size() > 0 ? al.size() - 1 : 0);
+    *out = tridiag_max_eig(al, be);
+    return MF_OK;
+}
 
 extern "C" {
-mf_status mf_mg_create(mf_ctx *, const mf_operator *, const mf_mg_params *, mf_mg **mg, mf_stream)
+
+mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm, mf_mg **out, mf_stream stream)
 {
-    if (mg) *mg = nullptr;
-    return MF_ERR_STATE;
+    if (!out) return MF_ERR_ARG;
+    *out = nullptr;
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (!prm) return fail(c, MF_ERR_ARG, "null multigrid parameters");
+    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET)
+        return fail(c, MF_ERR_ARG, "multigrid needs an FP64 heat operator in LEVELSET mode");
+    if (prm->coarse_cells < 1 || prm->degree < 1 || !(prm->smoothing_range > 1.0) || prm->eig_steps < 1 ||
+        !(prm->eig_safety >= 1.0) || !(prm->coarse_rtol > 0.0) || prm->coarse_maxit < 1)
+        return fail(c, MF_ERR_ARG, "invalid multigrid parameters");
+    hipStream_t s = (hipStream_t)stream;
+    // level meshes: halve every direction while n[0] > coarse_cells
+    std::vector<mf_mesh> meshes{c->mesh};
+    while (meshes.back().n[0] > prm->coarse_cells) {
+        mf_mesh m = meshes.back();
+        for (int d = 0; d < 3; ++d) {
+            if (m.n[d] % 2) return fail(c, MF_ERR_ARG, "cells per direction must halve evenly down to the coarse level");
+            m.n[d] /= 2;
+        }
+        meshes.push_back(m);
+    }
+    if (meshes.size() < 2) return fail(c, MF_ERR_ARG, "the mesh is already at the coarse size");
+    mf_mg *mg = new mf_mg();
+    mg->parent = c;
+    mg->fine_op = *op;
+    mg->prm = *prm;
+    const int nl = (int)meshes.size();
+    mg->L.resize(nl);
+    for (int i = 0; i < nl; ++i) {
+        MGLevel &l = mg->L[nl - 1 - i]; // index 0 = coarsest
+        l.mesh = meshes[i];
+        if ((st = mf_create(&l.mesh, &l.ctx)) != MF_OK) {
+            mg_free(mg);
+            return fail(c, st, "level context creation failed");
+        }
+        l.nn = l.ctx->nn;
+    }
+    // level sets: finest borrowed (FP64), the others injected
+    MGLevel &top = mg->L[nl - 1];
+    top.phi64 = (double *)op->phi;
+    for (int li = nl - 2; li >= 0; --li) {
+        MGLevel &l = mg->L[li], &f = mg->L[li + 1];
+        bool ok = hipMalloc((void **)&l.phi64, sizeof(double) * l.nn) == hipSuccess;
+        l.own_phi64 = ok;
+        if (!ok) {
+            mg_free(mg);
+            return fail(c, MF_ERR_OOM, "multigrid allocation failed");
+        }
+        MGCHK(mg, mg_inject(f.ctx->km, l.ctx->km, f.phi64, l.phi64, 0, s));
+    }
+    for (int li = 0; li < nl; ++li) {
+        MGLevel &l = mg->L[li];
+        l.op64 = *op;
+        l.op64.phi = l.phi64;
+        l.op32 = l.op64;
+        l.op32.precision = MF_FP32;
+        const size_t fb = sizeof(float) * l.nn;
+        bool ok = hipMalloc((void **)&l.b, fb) == hipSuccess && hipMalloc((void **)&l.x, fb) == hipSuccess;
+        if (ok && li > 0) // the coarsest level only needs its right-hand side and solution
+            ok = hipMalloc((void **)&l.phi32, fb) == hipSuccess && hipMalloc((void **)&l.dinv, fb) == hipSuccess &&
+                 hipMalloc((void **)&l.r, fb) == hipSuccess && hipMalloc((void **)&l.d, fb) == hipSuccess &&
+                 hipMalloc((void **)&l.t, fb) == hipSuccess;
+        if (!ok) {
+            mg_free(mg);
+            return fail(c, MF_ERR_OOM, "multigrid allocation failed");
+        }
+        if (li == 0) continue; // coarsest: FP64 CG only
+        MGCHK(mg, vcvt_d2f(l.phi64, l.phi32, l.nn, s));
+        l.op32.phi = l.phi32;
+        if ((st = ensure_face(l.ctx, 1))) {
+            mg_free(mg);
+            return st;
+        }
+        MGCHK(mg, heat_diagonal(l.ctx->km, heat_args(&l.op32), 1, l.dinv, s));
+        MGCHK(mg, vinvf(l.dinv, l.nn, s));
+        double est = 0.0;
+        if (prm->lambda_max) {
+            l.lmax = prm->lambda_max[li];
+        } else {
+            if ((st = lanczos_lmax(mg, l, prm->eig_steps, &est, s))) {
+                mg_free(mg);
+                return st;
+            }
+            l.lmax = prm->eig_safety * est;
+        }
+        l.lmin = l.lmax / prm->smoothing_range;
+    }
+    MGLevel &co = mg->L[0];
+    if (hipMalloc((void **)&mg->b64, sizeof(double) * co.nn) != hipSuccess ||
+        hipMalloc((void **)&mg->x64, sizeof(double) * co.nn) != hipSuccess) {
+        mg_free(mg);
+        return fail(c, MF_ERR_OOM, "multigrid allocation failed");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        mg_free(mg);
+        return fail(c, MF_ERR_HIP, "multigrid setup failed");
+    }
+    *out = mg;
+    return MF_OK;
 }
-void mf_mg_destroy(mf_mg *) {}
-int32_t mf_mg_n_levels(const mf_mg *) { return 0; }
-mf_status mf_mg_lambda_max(const mf_mg *, double *) { return MF_ERR_STATE; }
-mf_status mf_mg_vcycle(mf_mg *, const double *, double *, mf_stream) { return MF_ERR_STATE; }
-mf_status mf_mg_cg_solve(mf_mg *, const double *, double *, double, int32_t, mf_solve_info *, mf_stream)
+
+void mf_mg_destroy(mf_mg *mg) { mg_free(mg); }
+
+int32_t mf_mg_n_levels(const mf_mg *mg) { return mg ? (int32_t)mg->L.size() : 0; }
+
+mf_status mf_mg_lambda_max(const mf_mg *mg, double *out)
 {
-    return MF_ERR_STATE;
+    if (!mg || !out) return MF_ERR_ARG;
+    for (size_t i = 0; i < mg->L.size(); ++i) out[i] = mg->L[i].lmax;
+    return MF_OK;
 }
+
+} // extern "C"
+
+// Chebyshev smoothing of A_l x = b on level l (FP32); x from zero if x_zero.
+static mf_status cheb_smooth(mf_mg *mg, MGLevel &l, const float *b, float *x, bool x_zero, hipStream_t s)
+{
+    mf_ctx *c = l.ctx;
+    const int64_t n = l.nn;
+    const double theta = 0.5 * (l.lmax + l.lmin), delta = 0.5 * (l.lmax - l.lmin), sigma = theta / delta;
+    if (x_zero) {
+        MGCHK(mg, vcopy_f(b, l.r, n, s));
+    } else {
+        MGCHK(mg, heat_apply(c->km, heat_args(&l.op32), 1, x, l.t, c->face, nullptr, nullptr, s));
+        MGCHK(mg, vsub_f(b, l.t, l.r, n, s));
+    }
+    MGCHK(mg, cheb_first(l.dinv, l.r, l.d, x, (float)(1.0 / theta), x_zero ? 1 : 0, n, s));
+    double rho = 1.0 / sigma;
+    for (int k = 1; k < mg->prm.degree; ++k) {
+        MGCHK(mg, heat_apply(c->km, heat_args(&l.op32), 1, l.d, l.t, c->face, nullptr, nullptr, s));
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        MGCHK(mg, cheb_step(l.dinv, l.r, l.t, l.d, x, (float)(rho_new * rho), (float)(2.0 * rho_new / delta), n, s));
+        rho = rho_new;
+    }
+    return MF_OK;
+}
+
+// x_l = V_l(b_l): recursive V-cycle, level 0 solved by FP64 CG.
+static mf_status vcycle(mf_mg *mg, int li, hipStream_t s)
+{
+    MGLevel &l = mg->L[li];
+    mf_status st;
+    if (li == 0) {
+        MGCHK(mg, vcvt_f2d(l.b, mg->b64, l.nn, s));
+        mf_solve_info info;
+        st = mf_cg_solve(l.ctx, &l.op64, MF_PC_JACOBI, mg->b64, mg->x64, mg->prm.coarse_rtol, mg->prm.coarse_maxit,
+                         &info, (mf_stream)s);
+        if (st < 0) return fail(mg->parent, st, "coarse solve: %s", mf_last_error(l.ctx));
+        MGCHK(mg, vcvt_d2f(mg->x64, l.x, l.nn, s));
+        return MF_OK;
+    }
+    MGLevel &cl = mg->L[li - 1];
+    if ((st = cheb_smooth(mg, l, l.b, l.x, true, s))) return st;
+    MGCHK(mg, heat_apply(l.ctx->km, heat_args(&l.op32), 1, l.x, l.t, l.ctx->face, nullptr, nullptr, s));
+    MGCHK(mg, vsub_f(l.b, l.t, l.r, l.nn, s));
+    MGCHK(mg, mg_restrict(l.ctx->km, cl.ctx->km, l.r, cl.b, s));
+    if ((st = vcycle(mg, li - 1, s))) return st;
+    MGCHK(mg, mg_prolong_add(cl.ctx->km, l.ctx->km, cl.x, l.x, s));
+    return cheb_smooth(mg, l, l.b, l.x, false, s);
+}
+
+extern "C" mf_status mf_mg_vcycle(mf_mg *mg, const double *r, double *z, mf_stream stream)
+{
+    if (!mg) return MF_ERR_ARG;
+    if (!r || !z) return mg_fail(mg, MF_ERR_ARG, "null vector");
+    hipStream_t s = (hipStream_t)stream;
+    MGLevel &top = mg->L.back();
+    MGCHK(mg, vcvt_d2f(r, top.b, top.nn, s));
+    mf_status st = vcycle(mg, (int)mg->L.size() - 1, s);
+    if (st) return st;
+    MGCHK(mg, vcvt_f2d(top.x, z, top.nn, s));
+    return MF_OK;
+}
+
+// Flexible CG (Notay; Polak-Ribiere beta) in FP64 preconditioned by the V-cycle.
+extern "C" mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, double rtol, int32_t maxit,
+                                    mf_solve_info *info, mf_stream stream)
+{
+    if (!mg) return MF_ERR_ARG;
+    mf_ctx *c = mg->parent;
+    if (!b || !x || !info) return fail(c, MF_ERR_ARG, "null argument");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(c, MF_ERR_ARG, "invalid rtol or maxit");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = c->nn;
+    double *r, *z, *p, *q, *zp;
+    mf_status st;
+    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)) ||
+        (st = ws_vec(c, 5, &zp)))
+        return st;
+    RedWS red = redws(c);
+    if ((st = ensure_face(c, 1))) return st;
+    const HeatArgs ha = heat_args(&mg->fine_op);
+    HIPCHK(c, cg_init(c->cg, b, nullptr, x, r, z, p, q, n, rtol, maxit, 1, &red, s));
+    HIPCHK(c, vfill(zp, 0.0, n, 0, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!c->h_state->done) {
+        if ((st = mf_mg_vcycle(mg, r, z, stream))) return st;
+        HIPCHK(c, fcg_dir(c->cg, r, z, zp, n, &red, s));
+        HIPCHK(c, fcg_pupdate(c->cg, z, zp, p, n, s));
+        for (;;) {
+            HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
+            HIPCHK(c, fcg_update_xr(c->cg, x, r, p, q, n, &red, s));
+            HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            if (c->h_state->done) break;
+            if ((st = mf_mg_vcycle(mg, r, z, stream))) return st;
+            HIPCHK(c, fcg_dir(c->cg, r, z, zp, n, &red, s));
+            HIPCHK(c, fcg_pupdate(c->cg, z, zp, p, n, s));
+        }
+    }
+    const CGState hs = *c->h_state;
+    const double bnorm = sqrt(hs.bb);
+    info->iters = hs.iter;
+    info->rel_res_est = bnorm > 0.0 ? sqrt(hs.rr) / bnorm : 0.0;
+    info->converged = !hs.breakdown && hs.rr <= hs.thresh2;
+    if ((st = true_residual(c, &mg->fine_op, 0, b, x, q, bnorm, &info->rel_res, s))) return st;
+    if (hs.breakdown) return fail(c, MF_BREAKDOWN, "flexible CG breakdown at iteration %d", hs.iter);
+    if (!info->converged) return fail(c, MF_NOT_CONVERGED, "flexible CG reached maxit = %d", maxit);
+    return MF_OK;
 }

@@ -1,0 +1,114 @@
+"""FP32 geometric multigrid (V-cycle, Chebyshev smoothing, FP64 coarse CG) and
+the flexible CG it preconditions, against the FP64 oracle.
+
+Bars:
+* lambda_max estimates (FP64 Lanczos on both sides, same start vector and
+  step count): relative difference <= 1e-9.
+* one V-cycle, same Chebyshev bounds on both sides: GPU FP32 vs oracle FP64
+  normwise relative difference <= 2e-6 (about 30 FP32 unit roundoffs of
+  6e-8: rounding enters every apply, transfer and smoother update and the
+  degree-4 Chebyshev recurrences amplify it mildly; measured 6e-8 to 2e-7).
+* flexible CG: the true FP64 residual meets the tolerance, and the solution
+  matches the direct solution within kappa * rtol.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2501_18781_amd import mf
+from paper_2501_18781_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def relerr(a, b):
+    a = a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else a
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n,coarse,dirichlet", [(8, 2, W.ALL_FACES), (16, 4, W.ALL_FACES), (8, 4, 0)])
+def test_vcycle_matches_oracle(gpu, n, coarse, dirichlet):
+    wl = W.heat_sphere_workload(n, dirichlet)
+    print(f"vcycle n={n} coarse={coarse}", flush=True)
+    levels = O.heat_mg_levels(wl.mesh, wl.params, wl.phi, n_coarse=coarse)
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    lmax = [lv.lmax for lv in levels]
+    mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=coarse, lambda_max=lmax, coarse_rtol=1e-14))
+    assert mg.n_levels == len(levels)
+    r = W.uniform(3, wl.mesh.n_nodes)
+    z = torch.empty_like(dev(r))
+    mf.mg_vcycle(mg, dev(r), z)
+    ref = O.vcycle(levels, r)
+    err = relerr(z, ref)
+    print(f"  V-cycle FP32 vs FP64 oracle: {err:.2e}", flush=True)
+    assert err <= 2e-6
+
+
+def test_lanczos_estimates_match_oracle(gpu):
+    wl = W.heat_sphere_workload(16, W.ALL_FACES)
+    levels = O.heat_mg_levels(wl.mesh, wl.params, wl.phi, n_coarse=4)
+    ctx = mf.Context(wl.mesh)
+    mg = mf.Multigrid(mf.heat_operator(ctx, wl.params, phi=dev(wl.phi)), mf.MGConfig(coarse_cells=4))
+    got = mg.lambda_max()
+    for li in range(1, len(levels)):
+        assert abs(got[li] - levels[li].lmax) <= 1e-9 * levels[li].lmax, (li, got[li], levels[li].lmax)
+
+
+def test_flexible_cg_with_multigrid(gpu):
+    wl = W.heat_sphere_workload(16, W.ALL_FACES)
+    A = O.heat_matrix(wl.mesh, wl.params, phi=wl.phi)
+    levels = O.heat_mg_levels(wl.mesh, wl.params, wl.phi, n_coarse=4)
+    xr = W.uniform(5, wl.mesh.n_nodes)
+    b = A @ xr
+    ref = O.flexible_cg(A, b, lambda v: O.vcycle(levels, v), rtol=1e-8)
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=4, lambda_max=[lv.lmax for lv in levels]))
+    x = torch.empty_like(dev(b))
+    info = mf.mg_cg_solve(mg, dev(b), x, 1e-8, 100)
+    print(info, ref.iters, flush=True)
+    assert info.converged and info.rel_res <= 1e-8 and abs(info.iters - ref.iters) <= 1
+    assert relerr(x, xr) <= 1e-6
+    info = mf.mg_cg_solve(mg, dev(b), x, 1e-13, 100)
+    assert info.converged and relerr(x, O.direct_solve(A, b)) <= 1e-11
+
+
+def test_multigrid_stiff_regime_and_manufactured_rhs(gpu):
+    # dt = 100 s at 32^3: k/h^2 exceeds rc/dt in the vapor, the stiffness term
+    # dominates and Jacobi-CG needs many more iterations than at dt = 1e-3
+    p = W.HeatParams(dt=100.0)
+    wl = W.heat_sphere_workload(32, W.ALL_FACES, p)
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    b = torch.empty(wl.mesh.n_nodes, dtype=torch.float64, device="cuda")
+    mf.operator_apply(op, dev(W.manufactured_T(wl.mesh)), b)
+    xc, xm = torch.empty_like(b), torch.empty_like(b)
+    ic = mf.cg_solve(op, b, xc, 1e-8, 5000)
+    mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=4))
+    im = mf.mg_cg_solve(mg, b, xm, 1e-8, 200)
+    print(ic, im, flush=True)
+    assert ic.converged and im.converged and im.iters < ic.iters / 3
+    # both solve the same discrete problem: distance within kappa * rtol
+    assert float(torch.linalg.norm(xm - xc) / torch.linalg.norm(xc)) <= 1e-5
+    xs = W.manufactured_T(wl.mesh)
+    assert float(torch.linalg.norm(xm - dev(xs)) / np.linalg.norm(xs)) <= 1e-5
+
+
+def test_multigrid_argument_errors(gpu):
+    wl = W.heat_sphere_workload(10, W.ALL_FACES)
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    with pytest.raises(mf.MFError):
+        mf.Multigrid(op, mf.MGConfig(coarse_cells=2))  # 10 -> 5 cannot halve again
+    with pytest.raises(mf.MFError):
+        mf.Multigrid(op, mf.MGConfig(coarse_cells=16))  # already coarse
+    assert mf.Multigrid(op, mf.MGConfig(coarse_cells=5)).n_levels == 2
+    kq = torch.ones(ctx.n_cells * 27, dtype=torch.float64, device="cuda")
+    with pytest.raises(mf.MFError):
+        mf.Multigrid(mf.heat_operator(ctx, wl.params, k_q=kq, rc_q=kq), mf.MGConfig(coarse_cells=3))
