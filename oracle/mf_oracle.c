@@ -664,11 +664,13 @@ void orc_heat_qp_coeffs(const orc_mesh *m, const orc_coeffs *cf, const double *p
  *   dL/drc_q = -alpha_m W_q lam(x_q) (T - T_old)(x_q)
  * and, when phi != NULL (coefficients formed from phi through H),
  *   dL/dphi_j = sum_{cells, q} N_j(x_q) H'(phi_q) [(k_l - k_g) dL/dk_q + (rc_l - rc_g) dL/drc_q].
+ * T - T_old is taken from dTin when given (the step solved in delta form),
+ * which avoids the cancellation of forming it from T and T_old.
  * The formulas hold for lam = 0 on Dirichlet nodes (adjoint right-hand side
  * zeroed there, since T is fixed on them) and T, T_old = 0 on Dirichlet nodes.
  * dphi is accumulated cell by cell (8-colouring) over all nodes. */
 void orc_heat_grad(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *T,
-                   const double *Told, const double *lam, double *dk, double *drc, double *dphi)
+                   const double *Told, const double *dTin, const double *lam, double *dk, double *drc, double *dphi)
 {
     const int64_t nn = nnodes(m);
     if (dphi) memset(dphi, 0, sizeof(double) * nn);
@@ -690,7 +692,7 @@ void orc_heat_grad(const orc_mesh *m, const orc_coeffs *cf, const double *phi, c
                         for (int j = 0; j < 27; ++j) {
                             const int64_t g = idx[j];
                             l += Q.N[j] * lam[g];
-                            dT += Q.N[j] * (T[g] - Told[g]);
+                            dT += Q.N[j] * (dTin ? dTin[g] : T[g] - Told[g]);
                             for (int d = 0; d < 3; ++d) {
                                 gl[d] += Q.G[j][d] * lam[g];
                                 gT[d] += Q.G[j][d] * T[g];

@@ -261,16 +261,17 @@ def heat_qp_coeffs(mesh, params, phi, **override):
     return kq, rcq
 
 
-def heat_grad(mesh, params, T, Told, lam, phi=None, **override):
+def heat_grad(mesh, params, T, Told, lam, phi=None, dT=None, **override):
     """dL/dk_q, dL/drc_q and (with phi) dL/dphi_j for one implicit heat step,
-    given the adjoint state lam."""
+    given the adjoint state lam.  dT = T - T_old may be passed directly."""
     m = omesh(mesh)
     c = ocoeffs(params, **override)
     dk = np.zeros(n_cells(mesh) * 27)
     drc = np.zeros_like(dk)
     dphi = np.zeros(n_nodes(mesh)) if phi is not None else None
     lib().orc_heat_grad(ctypes.byref(m), ctypes.byref(c), _p(None if phi is None else _f64(phi)),
-                        _p(_f64(T)), _p(_f64(Told)), _p(_f64(lam)), _p(dk), _p(drc), _p(dphi))
+                        _p(_f64(T)), _p(_f64(Told)), _p(None if dT is None else _f64(dT)), _p(_f64(lam)),
+                        _p(dk), _p(drc), _p(dphi))
     return dk, drc, dphi
 
 
