@@ -23,6 +23,9 @@ mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -44,6 +47,19 @@ FLOPS_PER_CELL = 1998
 BYTES_PER_NODE = 24
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+METRIC = "Q2 operator-apply DoFs/s + HBM GB/s; FP32-MG vs FP64 CG time to 1e-8 resid"
+
+# HBM traffic of the apply kernel, from hardware counters (FETCH_SIZE and
+# WRITE_SIZE, one profiler pass each, scaled by what the same counters read for
+# a copy kernel of known size).  The summary records a hash of the sources the
+# kernel is built from; once they change, the figure no longer describes the
+# kernel and traffic is reported as null.
+APPLY_KERNEL = "heat_apply_kernel<double, 0, 0, false>"
+CALIB_KERNEL = "neg_kernel"
+CALIB_BYTES = 8 << 26  # 2^26 doubles read and 2^26 written by the calibration copy
+KERNEL_SOURCES = ["paper_2501_18781_amd/csrc/heat.hip", "paper_2501_18781_amd/csrc/brick.hpp",
+                  "paper_2501_18781_amd/csrc/mf_common.hpp", "paper_2501_18781_amd/csrc/kernels.hpp"]
+TRAFFIC_SUMMARY = "profiles/heat_apply_64cells_hbm_traffic.txt"
 
 
 def parse():
@@ -57,17 +73,91 @@ def parse():
     p.add_argument("--no-mg", action="store_true")
     p.add_argument("--no-cold", action="store_true")
     p.add_argument("--mg-cells", type=int, default=128)
+    p.add_argument("--no-oseen", action="store_true")
+    p.add_argument("--no-grad", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
+    p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="write the HBM traffic summary from two rocprofv3 --pmc output folders and exit")
+    p.add_argument("--command", default="", help="profiled command line, recorded in the summary")
     return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(folder, counter):
+    """Mean counter value per dispatch of the apply kernel and of the calibration copy."""
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    vals = {APPLY_KERNEL: [], CALIB_KERNEL: []}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            for k in vals:
+                if k in r["Kernel_Name"] and (k != CALIB_KERNEL or int(r["Grid_Size"]) >= (1 << 24)):
+                    vals[k].append(float(r["Counter_Value"]))
+    for k, v in vals.items():
+        if not v:
+            raise SystemExit(f"no {counter} rows for {k} in {folder}")
+    return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+
+def summarize_counters(fetch_dir, write_dir, command):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the apply kernel, scaled
+    so that the calibration copy reads as its true 512 MiB each way."""
+    f, nf = _counter_means(fetch_dir, "FETCH_SIZE")
+    w, nw = _counter_means(write_dir, "WRITE_SIZE")
+    sf = CALIB_BYTES / (f[CALIB_KERNEL] * 1024.0)
+    sw = CALIB_BYTES / (w[CALIB_KERNEL] * 1024.0)
+    fetch_b = f[APPLY_KERNEL] * 1024.0 * sf
+    write_b = w[APPLY_KERNEL] * 1024.0 * sw
+    lines = [
+        "HBM traffic of the FP64 heat apply kernel, 64^3 cells (2,146,689 nodes)",
+        f"command: {command}",
+        f"kernel: {APPLY_KERNEL} ({nf[APPLY_KERNEL]} dispatches counted for FETCH_SIZE, "
+        f"{nw[APPLY_KERNEL]} for WRITE_SIZE)",
+        f"calibration: {CALIB_KERNEL} over 2^26 doubles ({CALIB_BYTES} bytes read, {CALIB_BYTES} written)",
+        f"calibration FETCH_SIZE KiB: {f[CALIB_KERNEL]:.1f} (scale {sf:.4f})",
+        f"calibration WRITE_SIZE KiB: {w[CALIB_KERNEL]:.1f} (scale {sw:.4f})",
+        f"apply FETCH_SIZE KiB per dispatch: {f[APPLY_KERNEL]:.1f}",
+        f"apply WRITE_SIZE KiB per dispatch: {w[APPLY_KERNEL]:.1f}",
+        f"fetch_bytes_per_launch: {fetch_b:.0f}",
+        f"write_bytes_per_launch: {write_b:.0f}",
+        f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
+        f"algorithmic_bytes_per_launch: {BYTES_PER_NODE * 129 ** 3}",
+        f"source_hash: {kernel_source_hash()}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def measured_traffic():
+    """Scaled counter bytes per launch from the committed summary, or None if
+    the summary is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l)
+    if fields.get("source_hash", "").strip() != kernel_source_hash():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, x, b_T, nspmv=300):
-    """The oracle as it is (assembled CSR + OpenMP SpMV, numpy CG) on the same workload."""
+def cpu_baseline(wl, x, b_T, min_spmv_s=10.0, max_spmv=3000):
+    """The oracle as it is (assembled CSR + OpenMP SpMV, numpy CG) on the same
+    workload: assembly, CSR SpMVs until min_spmv_s seconds have passed (at
+    most max_spmv), and one Jacobi-CG solve.  value = SpMV DoFs/s."""
     import numpy as np
 
     import oracle as O
@@ -77,8 +167,10 @@ def cpu_baseline(wl, x, b_T, nspmv=300):
     t_asm = time.perf_counter() - t0
     y = O.spmv(A, x)
     t0 = time.perf_counter()
-    for _ in range(nspmv):
+    nspmv = 0
+    while nspmv < max_spmv and (time.perf_counter() - t0) < min_spmv_s:
         y = O.spmv(A, x)
+        nspmv += 1
     t_spmv = time.perf_counter() - t0
     b = O.spmv(A, b_T)
     t0 = time.perf_counter()
@@ -102,6 +194,9 @@ def cpu_baseline(wl, x, b_T, nspmv=300):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        sys.stdout.write(summarize_counters(*args.summarize_counters, args.command))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (every box has one GPU); "
@@ -121,7 +216,7 @@ def main():
         src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     n = args.cells
@@ -175,7 +270,8 @@ def main():
         roof = {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": frac_alu}
     else:
         roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": frac_hbm}
-    roof["traffic"] = None
+    traffic = measured_traffic() if n == 64 else None
+    roof["traffic"] = traffic
     roof["kernel"] = "heat_apply_kernel<double, levelset>"
     roof["kernel_us"] = k_s * 1e6
     roof["flops_per_launch"] = flops
@@ -188,7 +284,7 @@ def main():
     log(f"[bench] CG {info.iters} iterations, {cg_ms:.2f} ms, true rel. residual {info.rel_res:.2e}")
 
     result = {
-        "metric": "Q2 operator-apply DoFs/s (FP64 heat operator, 64^3 cells)",
+        "metric": METRIC,
         "value": value,
         "unit": "DoFs/s",
         "n_gpus": 1,
@@ -236,11 +332,16 @@ def main():
         log(f"[bench] cold apply kernel {kc * 1e6:.1f} us ({bytes_ / kc / 1e9:.0f} GB/s)")
         del sets
 
-    if not args.no_mg:
+    del ctx, op
+    for flag, key, fn in [(args.no_mg, "mg_vs_cg", lambda: mg_vs_cg(args.mg_cells, dev)),
+                          (args.no_oseen, "oseen", lambda: oseen_bench(dev)),
+                          (args.no_grad, "gradient", lambda: grad_bench(dev))]:
+        if flag:
+            continue
         try:
-            result["mg_vs_cg"] = mg_vs_cg(args.mg_cells, dev)
+            result[key] = fn()
         except Exception as e:  # reported, never silently replaced
-            result["mg_vs_cg"] = {"error": f"{type(e).__name__}: {e}"}
+            result[key] = {"error": f"{type(e).__name__}: {e}"}
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
@@ -292,6 +393,91 @@ def mg_vs_cg(n, dev):
             f"(setup {tsetup * 1e3:.0f} ms) | diff {err:.1e}")
         mg.close()
         del op, ctx
+    return out
+
+
+def oseen_bench(dev, applies=50):
+    """Linearized momentum operator on 48^3 cells (3 x 912,673 velocity DoFs):
+    apply throughput, and GMRES(30) with 3x3 point-block Jacobi to 1e-8 on
+    b = A x_ref (x_ref ~ U[-1,1], seed 1)."""
+    import torch
+
+    from paper_2501_18781_amd import mf
+    from paper_2501_18781_amd import workloads as W
+
+    wl = W.oseen_wavy_workload(48)
+    nd = 3 * wl.mesh.n_nodes
+    log(f"[bench] oseen 48^3: {nd} velocity DoFs")
+    ctx = mf.Context(wl.mesh)
+    op = mf.oseen_operator(ctx, wl.params, dev(wl.phi), dev(wl.u0))
+    xr = dev(W.uniform(1, nd))
+    b = torch.empty_like(xr)
+    s = torch.cuda.current_stream()
+    out = {"cells": 48, "velocity_dofs": nd}
+    for label, fn in [("apply", mf.operator_apply), ("apply_transpose", mf.operator_apply_transpose)]:
+        fn(op, xr, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(applies):
+            fn(op, xr, b)
+        e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / applies
+        out[label] = {"us": us, "dofs_per_s": nd / (us * 1e-6)}
+    mf.operator_apply(op, xr, b)
+    x = torch.empty_like(b)
+    mf.gmres_solve(op, b, x, 1e-8, 3000, precond=mf.MF_PC_BLOCK_JACOBI, restart=30)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = mf.gmres_solve(op, b, x, 1e-8, 3000, precond=mf.MF_PC_BLOCK_JACOBI, restart=30)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    err = float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
+    out["gmres30_block_jacobi"] = {"ms": t * 1e3, "iters": info.iters, "rel_res": info.rel_res,
+                                   "converged": bool(info.converged), "rel_err_vs_x_ref": err}
+    log(f"[bench]   apply {out['apply']['us']:.1f} us, transpose {out['apply_transpose']['us']:.1f} us; "
+        f"GMRES(30) {info.iters} it {t * 1e3:.1f} ms, err {err:.1e}")
+    return out
+
+
+def grad_bench(dev, reps=5):
+    """One differentiable implicit heat step on 32^3 cells: forward (delta-form
+    Jacobi-CG to 1e-14) and backward (adjoint CG + gradient kernel), with
+    respect to the level set and to the quadrature-point coefficients."""
+    import torch
+
+    from paper_2501_18781_amd import mf
+    from paper_2501_18781_amd import workloads as W
+    from paper_2501_18781_amd.autograd import HeatStep, heat_step
+
+    wl = W.heat_sphere_workload(32, W.ALL_FACES)
+    ctx = mf.Context(wl.mesh)
+    step = HeatStep(ctx, wl.params)
+    Told = dev(W.manufactured_T(wl.mesh))
+    tgt = Told * 0.999
+    nq = ctx.n_cells * 27
+    kq = torch.empty(nq, dtype=torch.float64, device="cuda")
+    rcq = torch.empty_like(kq)
+    mf.heat_qp_coeffs(step.operator(phi=dev(wl.phi)), kq, rcq)
+    out = {"cells": 32, "nodes": wl.mesh.n_nodes, "quad_points": nq}
+    for label, make in [("wrt_phi", lambda: {"phi": dev(wl.phi).requires_grad_(True)}),
+                        ("wrt_k_rc", lambda: {"k_q": kq.clone().requires_grad_(True),
+                                              "rc_q": rcq.clone().requires_grad_(True)})]:
+        times = []
+        for _ in range(reps + 1):
+            kw = make()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            T, _ = heat_step(step, Told, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            torch.sum((T - tgt) ** 2).backward()
+            torch.cuda.synchronize()
+            times.append((t1 - t0, time.perf_counter() - t1))
+        fw = sorted(t[0] for t in times[1:])[reps // 2]
+        bw = sorted(t[1] for t in times[1:])[reps // 2]
+        out[label] = {"forward_ms": fw * 1e3, "backward_ms": bw * 1e3}
+        log(f"[bench]   gradient {label}: forward {fw * 1e3:.2f} ms, backward {bw * 1e3:.2f} ms")
     return out
 
 

@@ -31,7 +31,7 @@ mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...)
     return st;
 }
 
-RedWS redws(mf_ctx *c) { return RedWS{c->partials, c->counter, c->cap}; }
+RedWS redws(mf_ctx *c) { return RedWS{c->partials, c->cap}; }
 
 // Workspace vector i (3 * n_nodes doubles), allocated on first use.
 mf_status ensure_face(mf_ctx *c, int comps)
@@ -103,7 +103,6 @@ mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
     int64_t cap = nbricks > 32 * 1024 ? nbricks : 32 * 1024;
     c->cap = (unsigned)cap;
     bool ok = hipMalloc((void **)&c->partials, sizeof(double) * cap) == hipSuccess &&
-              hipMalloc((void **)&c->counter, sizeof(unsigned) * 16) == hipSuccess &&
               hipMalloc((void **)&c->cg, sizeof(CGState)) == hipSuccess &&
               hipMalloc((void **)&c->scal, sizeof(double) * 256) == hipSuccess &&
               hipHostMalloc((void **)&c->h_state, sizeof(CGState), hipHostMallocDefault) == hipSuccess &&
@@ -111,10 +110,6 @@ mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
     if (!ok) {
         mf_destroy(c);
         return MF_ERR_OOM;
-    }
-    if (hipMemset(c->counter, 0, sizeof(unsigned) * 16) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        mf_destroy(c);
-        return MF_ERR_HIP;
     }
     *out = c;
     return MF_OK;
@@ -126,7 +121,6 @@ void mf_destroy(mf_ctx *c)
     for (double *p : c->vec)
         if (p) (void)hipFree(p);
     if (c->partials) (void)hipFree(c->partials);
-    if (c->counter) (void)hipFree(c->counter);
     if (c->cg) (void)hipFree(c->cg);
     if (c->scal) (void)hipFree(c->scal);
     if (c->V) (void)hipFree(c->V);
@@ -280,9 +274,10 @@ mf_status mf_operator_diagonal(mf_ctx *c, const mf_operator *op, void *diag, mf_
     mf_status st = check_op(c, op);
     if (st) return st;
     if (!diag) return fail(c, MF_ERR_ARG, "null diag");
-    if (op->kind == MF_HEAT)
-        HIPCHK(c, heat_diagonal(c->km, heat_args(op), op->precision == MF_FP32, diag, (hipStream_t)stream));
-    else
+    if (op->kind == MF_HEAT) {
+        if ((st = ensure_face(c, 1))) return st;
+        HIPCHK(c, heat_diagonal(c->km, heat_args(op), op->precision == MF_FP32, diag, c->face, (hipStream_t)stream));
+    } else
         HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), (double *)diag, (hipStream_t)stream));
     return MF_OK;
 }
@@ -316,7 +311,8 @@ mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, 
     if (!T || !dT || !lambda) return fail(c, MF_ERR_ARG, "null input");
     if (dphi && op->coeff_mode != MF_COEFF_LEVELSET)
         return fail(c, MF_ERR_ARG, "dphi needs the LEVELSET coefficient mode");
-    HIPCHK(c, heat_grad(c->km, heat_args(op), T, dT, lambda, dk, drc, dphi, (hipStream_t)stream));
+    if (dphi && (st = ensure_face(c, 1))) return st;
+    HIPCHK(c, heat_grad(c->km, heat_args(op), T, dT, lambda, dk, drc, dphi, c->face, (hipStream_t)stream));
     return MF_OK;
 }
 
@@ -370,7 +366,7 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
     if ((st = ensure_face(c, 1))) return st;
     if (precond == MF_PC_JACOBI) {
         if ((st = ws_vec(c, 4, &dinv))) return st;
-        HIPCHK(c, heat_diagonal(c->km, ha, 0, dinv, s));
+        HIPCHK(c, heat_diagonal(c->km, ha, 0, dinv, c->face, s));
         HIPCHK(c, vinv(dinv, n, s));
     }
     RedWS red = redws(c);
@@ -380,7 +376,7 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
         for (int k = 0; k < batch; ++k) {
             HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
             HIPCHK(c, cg_update(c->cg, dinv, x, r, z, p, q, n, &red, s));
-            HIPCHK(c, cg_pupdate(c->cg, z, p, n, s));
+            HIPCHK(c, cg_pupdate(c->cg, z, p, n, &red, s));
         }
         done_iters += batch;
         HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -433,7 +429,8 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
     if (precond == MF_PC_JACOBI) {
         if ((st = ws_vec(c, 1, &pc))) return st;
         if (op->kind == MF_HEAT) {
-            HIPCHK(c, heat_diagonal(c->km, heat_args(op), 0, pc, s));
+            if ((st = ensure_face(c, 1))) return st;
+            HIPCHK(c, heat_diagonal(c->km, heat_args(op), 0, pc, c->face, s));
         } else {
             // diagonal of the 3x3 blocks
             if (!c->blocks && hipMalloc((void **)&c->blocks, sizeof(double) * 9 * c->nn) != hipSuccess)

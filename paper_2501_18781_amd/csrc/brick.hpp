@@ -209,8 +209,10 @@ struct Brick {
 // global index g has g = 8 b in a shared direction); every shared node is
 // finished by exactly one brick.  Partials are summed over the contributing
 // bricks in a fixed order (own brick first, then x, y, z neighbours).
-// Shared Dirichlet nodes get y = x here.
-template <typename T>
+// Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
+// operator), DMODE 2 writes y = 1 (its diagonal), DMODE 0 sums them like
+// every other node (a plain nodal field such as a gradient).
+template <typename T, int DMODE = 1>
 __device__ __forceinline__ void combine_faces(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
                                               T *__restrict__ y, int brick, int lane)
 {
@@ -241,8 +243,8 @@ __device__ __forceinline__ void combine_faces(const KMesh &m, const T *__restric
         if (!(sx || sy || sz)) continue;
         const int gx = 2 * bx * BB + lx, gy = 2 * by * BB + ly, gz = 2 * bz * BB + lz;
         const int64_t g = node_index(m, gx, gy, gz);
-        if (node_constrained(m, gx, gy, gz)) {
-            y[g] = x[g];
+        if (DMODE != 0 && node_constrained(m, gx, gy, gz)) {
+            y[g] = DMODE == 1 ? x[g] : T(1);
             continue;
         }
         T s = T(0);

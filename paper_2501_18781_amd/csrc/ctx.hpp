@@ -18,7 +18,6 @@ struct mf_ctx {
     // workspace: vectors of 3 * n_nodes doubles each
     std::vector<double *> vec;
     double *partials = nullptr;
-    unsigned *counter = nullptr;
     unsigned cap = 0;
     mf::CGState *cg = nullptr;
     double *scal = nullptr;      // device scalars

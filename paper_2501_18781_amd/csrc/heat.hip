@@ -88,7 +88,6 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     constexpr int LDS_T = CG ? BNB + (BNB > 27 * BNT ? BNB : 27 * BNT) : REG;
     __shared__ T lds[LDS_T];
     __shared__ double red_lds[BNT];
-    __shared__ int flag_lds;
     if (CG) {
         if (cg->done) return; // converged or broken down: the rest of the batch is a no-op
     }
@@ -147,26 +146,14 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         });
     }
     if (CG) {
+        // one partial per brick; the alpha kernel sums them in brick order
         const double tot = block_sum<BNT>(energy, red_lds);
-        if (publish_partials<1>(&tot, red.partials, red.counter, gridDim.x, &flag_lds)) {
-            const double pAp = sum_partials<BNT>(red.partials, gridDim.x, 0, red_lds);
-            if (threadIdx.x == 0) {
-                cg->pAp = pAp;
-                if (!(pAp > 0.0) || !isfinite(pAp)) {
-                    cg->breakdown = 1;
-                    cg->done = 1;
-                    cg->alpha = 0.0;
-                } else {
-                    cg->alpha = cg->rz / pAp;
-                }
-                __hip_atomic_store(red.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
+        write_partials<1>(&tot, red.partials, gridDim.x, (unsigned)br.brick);
     }
 }
 
 // Second pass of an apply: shared nodes = sum of the bricks' face partials.
-template <typename T, bool CG>
+template <typename T, bool CG, int DMODE = 1>
 __global__ void __launch_bounds__(BNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
                                                            const T *__restrict__ x, T *__restrict__ y,
                                                            const CGState *cg)
@@ -176,7 +163,7 @@ __global__ void __launch_bounds__(BNT) face_combine_kernel(KMesh m, const T *__r
     }
     const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
     const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
-    combine_faces<T>(m, face, x, y, k * q + min(k, r) + j, threadIdx.x);
+    combine_faces<T, DMODE>(m, face, x, y, k * q + min(k, r) + j, threadIdx.x);
 }
 
 int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
@@ -185,7 +172,7 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
                       const RedWS *red, hipStream_t s, const KTiming *t)
 {
     const unsigned nb = (unsigned)n_bricks(m);
-    RedWS r = red ? *red : RedWS{nullptr, nullptr, 0};
+    RedWS r = red ? *red : RedWS{nullptr, 0};
     if (!face) return hipErrorInvalidValue;
     if (cg && (!red || red->capacity < nb)) return hipErrorInvalidValue;
     if (fp32 && cg) return hipErrorInvalidValue;
@@ -225,15 +212,31 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     else
         face_combine_kernel<double, false><<<nb, BNT, 0, s>>>(m, (const double *)face, (const double *)x,
                                                               (double *)y, nullptr);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess || !cg) return e;
+    return cg_alpha(cg, &r, nb, s);
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal: diag_i = sum_cells sum_q cm_q N_i(q)^2 + ck_q sum_d (d_d N_i(q))^2,
-// evaluated per cell node by a direct loop over the Gauss points (setup only).
+// Diagonal: diag_i = sum_cells sum_q cm_q N_i(q)^2 + ck_q sum_d ih_d (d_d N_i(q))^2.
+// N_i(q) and its derivatives are products of 1D factors, so the sum over q
+// factorizes like the apply: contractions with the elementwise squares of
+// the 1D value and derivative tables S and G along z, y, x.  Node sums and
+// shared faces as in the apply; Dirichlet nodes get 1.
 // ---------------------------------------------------------------------------
+// out = in contracted along direction DIR with M: out[.., a, ..] = sum_q M[q][a] in[.., q, ..]
+template <int DIR, typename T> __device__ __forceinline__ void contract1d(const T *in, T *out, const T (&M)[3][3])
+{
+    constexpr int st = DIR == 0 ? 1 : (DIR == 1 ? 3 : 9);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int a = (i / st) % 3, base = i - a * st;
+        out[i] = M[0][a] * in[base] + M[1][a] * in[base + st] + M[2][a] * in[base + 2 * st];
+    }
+}
+
 template <typename T, int MODE, int HK>
-__global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag)
+__global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag, T *__restrict__ face)
 {
     constexpr int LDS_T = (BNB > 27 * BNT ? BNB : 27 * BNT);
     __shared__ T lds[LDS_T];
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     __syncthreads();
     const T vol = T(m.hx * m.hy * m.hz);
     const T am_w = T(a.am) * vol, ak_w = T(a.ak) * vol;
-    const T ih[3] = {T(1.0 / (m.hx * m.hx)), T(1.0 / (m.hy * m.hy)), T(1.0 / (m.hz * m.hz))};
+    const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T cm[27], ck[27];
     if (MODE == 0) {
         T ph[27];
@@ -254,53 +257,63 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
         heat_cell_coeffs<T, 1, 0>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w, ak_w,
                                   cm, ck);
     }
-    // 1D tables: S[q][a] and G[q][a] = l_a'(xi_q)
-    const T S[3][3] = {{Q2<T>::s0, Q2<T>::s1, Q2<T>::s2}, {T(0), T(1), T(0)}, {Q2<T>::s2, Q2<T>::s1, Q2<T>::s0}};
-    const T Gd[3][3] = {{Q2<T>::g0, Q2<T>::g1, Q2<T>::g2}, {T(-1), T(0), T(1)}, {-Q2<T>::g2, -Q2<T>::g1, -Q2<T>::g0}};
+    // squares of S[q][a] = l_a(xi_q) and G[q][a] = l_a'(xi_q)
+    constexpr T s0 = Q2<T>::s0, s1 = Q2<T>::s1, s2 = Q2<T>::s2;
+    constexpr T g0 = Q2<T>::g0, g1 = Q2<T>::g1, g2 = Q2<T>::g2;
+    const T S2[3][3] = {{s0 * s0, s1 * s1, s2 * s2}, {T(0), T(1), T(0)}, {s2 * s2, s1 * s1, s0 * s0}};
+    const T G2[3][3] = {{g0 * g0, g1 * g1, g2 * g2}, {T(1), T(0), T(1)}, {g2 * g2, g1 * g1, g0 * g0}};
     T d[27];
-    for (int i = 0; i < 27; ++i) {
-        const int ia = i % 3, ib = (i / 3) % 3, ic = i / 9;
-        T s = T(0);
-        for (int q = 0; q < 27; ++q) {
-            const int qa = q % 3, qb = (q / 3) % 3, qc = q / 9;
-            const T nx = S[qa][ia], ny = S[qb][ib], nz = S[qc][ic];
-            const T n = nx * ny * nz;
-            const T gx = Gd[qa][ia] * ny * nz, gy = nx * Gd[qb][ib] * nz, gz = nx * ny * Gd[qc][ic];
-            s += cm[q] * n * n + ck[q] * (gx * gx * ih[0] + gy * gy * ih[1] + gz * gz * ih[2]);
-        }
-        d[i] = s;
+    {
+        T t[27], u[27], w[27];
+        contract1d<2>(cm, t, S2);
+        contract1d<1>(t, w, S2);          // mass, contracted along z and y
+        contract1d<2>(ck, t, S2);
+        contract1d<1>(t, u, G2);          // y-derivative part
+#pragma unroll
+        for (int i = 0; i < 27; ++i) w[i] += ihy * u[i];
+        contract1d<1>(t, u, S2);          // x-derivative part, before x
+        contract1d<0>(u, d, G2);
+        contract1d<2>(ck, t, G2);
+        contract1d<1>(t, u, S2);          // z-derivative part
+#pragma unroll
+        for (int i = 0; i < 27; ++i) w[i] += ihz * u[i];
+        contract1d<0>(w, t, S2);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) d[i] = t[i] + ihx * d[i];
     }
     __syncthreads();
     br.store_cell(lds, d);
     __syncthreads();
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, bool shared) {
-        if (constrained) {
-            diag[g] = T(1);
-            return;
-        }
-        const T s = br.node_sum(lds, ai, bi, ci);
-        if (shared)
-            atomicAdd(&diag[g], s);
-        else
-            diag[g] = s;
+    T *fb = face + (int64_t)br.brick * BFACE;
+    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, int sh) {
+        const T v = br.node_sum(lds, ai, bi, ci);
+        if (sh) fb[face_slot(lx0 + ai, ly0 + bi, lz0 + ci)] = v; // constrained ones: 1 in the combine
+        else diag[g] = constrained ? T(1) : v;
     });
 }
 
-hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, hipStream_t s)
+hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s)
 {
     const unsigned nb = (unsigned)n_bricks(m);
-    const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    hipError_t e = vfill(diag, 0.0, nn, fp32, s);
-    if (e != hipSuccess) return e;
+    if (!face) return hipErrorInvalidValue;
     if (fp32) {
-        if (a.mode == 1) heat_diag_kernel<float, 1, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag);
-        else if (a.hkind == 1) heat_diag_kernel<float, 0, 1><<<nb, BNT, 0, s>>>(m, a, (float *)diag);
-        else heat_diag_kernel<float, 0, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag);
+        if (a.mode == 1) heat_diag_kernel<float, 1, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
+        else if (a.hkind == 1) heat_diag_kernel<float, 0, 1><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
+        else heat_diag_kernel<float, 0, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
     } else {
-        if (a.mode == 1) heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag);
-        else if (a.hkind == 1) heat_diag_kernel<double, 0, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag);
-        else heat_diag_kernel<double, 0, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag);
+        if (a.mode == 1) heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+        else if (a.hkind == 1) heat_diag_kernel<double, 0, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+        else heat_diag_kernel<double, 0, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (fp32)
+        face_combine_kernel<float, false, 2><<<nb, BNT, 0, s>>>(m, (const float *)face, nullptr, (float *)diag,
+                                                                nullptr);
+    else
+        face_combine_kernel<double, false, 2><<<nb, BNT, 0, s>>>(m, (const double *)face, nullptr, (double *)diag,
+                                                                 nullptr);
     return hipGetLastError();
 }
 
@@ -368,7 +381,7 @@ hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double 
 __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, const double *__restrict__ T,
                                                         const double *__restrict__ dT, const double *__restrict__ lam,
                                                         double *__restrict__ dk, double *__restrict__ drc,
-                                                        double *__restrict__ dphi)
+                                                        double *__restrict__ dphi, double *__restrict__ face)
 {
     constexpr int NF = 4;
     constexpr int LDS_T = (NF * BNB > 27 * BNT ? NF * BNB : 27 * BNT);
@@ -421,24 +434,25 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
     __syncthreads();
     br.store_cell(lds, s);
     __syncthreads();
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool, bool shared) {
+    double *fb = face + (int64_t)br.brick * BFACE;
+    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool, int sh) {
         const double v = br.node_sum(lds, ai, bi, ci);
-        if (shared)
-            atomicAdd(&dphi[g], v);
-        else
-            dphi[g] = v;
+        if (sh) fb[face_slot(lx0 + ai, ly0 + bi, lz0 + ci)] = v;
+        else dphi[g] = v;
     });
 }
 
 hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,
-                     double *dk, double *drc, double *dphi, hipStream_t s)
+                     double *dk, double *drc, double *dphi, void *face, hipStream_t s)
 {
     const unsigned nb = (unsigned)n_bricks(m);
-    if (dphi) {
-        hipError_t e = vfill(dphi, 0.0, (int64_t)m.NX * m.NY * m.NZ, 0, s);
-        if (e != hipSuccess) return e;
-    }
-    heat_grad_kernel<<<nb, BNT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi);
+    if (dphi && !face) return hipErrorInvalidValue;
+    heat_grad_kernel<<<nb, BNT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi, (double *)face);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !dphi || a.mode != 0) return e;
+    // the level-set gradient sums over Dirichlet nodes too (DMODE 0)
+    face_combine_kernel<double, false, 0><<<nb, BNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr);
     return hipGetLastError();
 }
 

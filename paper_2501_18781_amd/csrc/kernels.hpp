@@ -29,18 +29,18 @@ struct OseenArgs {
 };
 
 // Device state of a CG solve; scalars never leave the device during the
-// iteration except for the periodic convergence check.
+// iteration except for the periodic convergence check.  rz_old is a copy of
+// rz taken one launch before rz is overwritten, so that no kernel reads a
+// field that another workgroup of the same launch writes.
 struct CGState {
-    double rz, pAp, rr, bb, alpha, beta, thresh2;
-    int iter, maxit, done, breakdown, flexible;
-    double rz_prev_cross; // r_{k+1}.z_k for the flexible (Polak-Ribiere) variant
+    double rz, rz_old, pAp, rr, bb, alpha, beta, thresh2;
+    int iter, maxit, done, breakdown, flexible, pad;
 };
 
-// Reduction workspace of one kernel: NV partial sets of nblocks doubles and
-// an arrival counter (reset to zero by the finalizing block).
+// Partial sums of one reduction: NV sets of nblocks doubles, reduced by a
+// later launch.
 struct RedWS {
     double *partials;
-    unsigned *counter;
     unsigned capacity; // max partial entries
 };
 
@@ -51,15 +51,17 @@ struct KTiming {
 
 // ---- heat (heat.hip) ----
 // y = A x in two launches (bricks, then the shared-face combine); `face` is
-// a workspace of face_buffer_elems(m) elements of the operator's type.
+// a workspace of face_buffer_elems(m) elements of the operator's type.  With
+// cg != nullptr (FP64 only) the apply also forms p.Ap from per-brick
+// partials and a third, single-workgroup launch sets alpha = rz / p.Ap.
 hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, void *face, CGState *cg,
                       const RedWS *red, hipStream_t s, const KTiming *t = nullptr);
 int64_t face_buffer_elems(const KMesh &m);
-hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, hipStream_t s);
 hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double *rcq, hipStream_t s);
 hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
+hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s);
 hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,
-                     double *dk, double *drc, double *dphi, hipStream_t s);
+                     double *dk, double *drc, double *dphi, void *face, hipStream_t s);
 
 // ---- Oseen (oseen.hip) ----
 // y = A x or A^T x; `face` holds 3 face_buffer_elems(m) doubles.
@@ -93,9 +95,11 @@ hipError_t block3_apply(const double *binv, const double *x, double *y, int64_t 
 
 hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *z, double *p,
                    double *q, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s);
+// alpha = rz / p.Ap from the nb per-brick partials of a CG-mode apply.
+hipError_t cg_alpha(CGState *st, const RedWS *red, unsigned nb, hipStream_t s);
 hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, double *z, const double *p, double *q,
                      int64_t n, const RedWS *red, hipStream_t s);
-hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, hipStream_t s);
+hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s);
 // Flexible-CG pieces: the preconditioner output z is supplied by the caller.
 hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n,
                          const RedWS *red, hipStream_t s);

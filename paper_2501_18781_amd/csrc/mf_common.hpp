@@ -220,10 +220,14 @@ template <typename T> __device__ __forceinline__ T heaviside(int kind, T eps, T 
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reductions.  A block sums its threads' values in a fixed
-// tree order; blocks publish one partial each; the last block to arrive
-// (agent-scope counter) sums the partials in index order and runs a
-// finalize step.  Nothing spins or waits on other blocks.
+// Deterministic reductions without atomics.  A block sums its threads' values
+// in a fixed tree order and stores one partial per set with a plain store
+// (layout [NV][nblocks]).  A later launch, whose start makes those stores
+// visible, sums the partials in a fixed order: every reader of a partial set
+// obtains bitwise the same total, and no workgroup waits on another.
+// (A last-block-arrives scheme needs one device-scope acquire-release atomic
+// per workgroup on a single address; with thousands of workgroups these
+// serialize across the XCDs and cost more than the kernel's own work.)
 // ---------------------------------------------------------------------------
 
 template <int NT> __device__ __forceinline__ double block_sum(double v, double *red)
@@ -241,34 +245,34 @@ template <int NT> __device__ __forceinline__ double block_sum(double v, double *
     return r;
 }
 
-// Publish NV partial sums of this block (valid in thread 0); returns true in
-// every thread of the block that completes the set.  partials: [NV][nblocks].
+// Store NV block sums (valid in thread 0) as partial `block` of each set.
 template <int NV>
-__device__ __forceinline__ bool publish_partials(const double *v, double *partials, unsigned *counter,
-                                                 unsigned nblocks, int *flag_lds)
+__device__ __forceinline__ void write_partials(const double *v, double *partials, unsigned nblocks, unsigned block)
 {
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            __hip_atomic_store(&partials[(size_t)i * nblocks + blockIdx.x], v[i], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *flag_lds = (prev == nblocks - 1) ? 1 : 0;
+        for (int i = 0; i < NV; ++i) partials[(size_t)i * nblocks + block] = v[i];
     }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    __syncthreads();
-    return last;
 }
 
-// In the last block: sum partial set i over all blocks in index order.
+// Total of partial set i (nblocks entries written by an earlier launch),
+// returned to every thread of an NT-thread block.  Thread t sums entries
+// t, t + NT, ... with four interleaved accumulators (combined in a fixed
+// order), then the block sums the threads in a fixed tree.
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double *partials, unsigned nblocks, int i, double *red)
 {
-    double s = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += NT)
-        s += __hip_atomic_load(&partials[(size_t)i * nblocks + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return block_sum<NT>(s, red);
+    const double *p = partials + (size_t)i * nblocks;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    unsigned b = threadIdx.x;
+    for (; b + 3 * NT < nblocks; b += 4 * NT) {
+        s0 += p[b];
+        s1 += p[b + NT];
+        s2 += p[b + 2 * NT];
+        s3 += p[b + 3 * NT];
+    }
+    for (; b < nblocks; b += NT) s0 += p[b];
+    return block_sum<NT>((s0 + s1) + (s2 + s3), red);
 }
 
 } // namespace mf

@@ -1,12 +1,14 @@
 // vec.hip -- vector kernels and the fused Krylov steps (App. B: CG and GMRES).
 //
-// Reductions are deterministic: every thread accumulates a fixed
-// grid-stride subsequence, wavefronts reduce with shuffles in a fixed order,
-// the waves of a block through LDS, and the last block to finish sums the
-// per-block partials in index order.  Solver scalars (alpha, beta, residual
-// norms, iteration count, convergence flag) live in device memory; kernels
-// read them directly and become no-ops once the solve is done, so the host
-// only synchronizes to poll convergence.
+// Reductions are deterministic and use no atomics: every thread accumulates
+// a fixed grid-stride subsequence, wavefronts reduce with shuffles in a fixed
+// order, the waves of a block through LDS, and each block stores its partial;
+// the next launch sums the partials in a fixed order (a single-workgroup
+// finalize kernel, or every workgroup of the consuming kernel when the
+// partials are few).  Solver scalars (alpha, beta, residual norms, iteration
+// count, convergence flag) live in device memory; kernels read them directly
+// and become no-ops once the solve is done, so the host only synchronizes to
+// poll convergence.
 #include "kernels.hpp"
 
 namespace mf {
@@ -14,6 +16,9 @@ namespace mf {
 constexpr int VNT = 256;   // threads per block of the vector kernels
 constexpr int VMAXB = 1024; // max blocks of a reduction kernel
 constexpr int MAXV = 32;   // max vectors in a multi-dot
+constexpr int FNT = 1024;  // threads of the single-workgroup finalize kernels
+constexpr unsigned CG_UPDATE_BLOCKS = 512;  // partials the CG direction update reduces in every block
+constexpr unsigned CG_PUPDATE_BLOCKS = 1024;
 
 static unsigned vec_blocks(int64_t n)
 {
@@ -61,34 +66,47 @@ template <int NV> __device__ __forceinline__ void block_sum_n(double *v, double 
     __syncthreads();
 }
 
-// Last-block finalize helper: returns true in the block completing the set;
-// then tot[k] (thread 0) holds the grid sums.
-template <int NV>
-__device__ __forceinline__ bool grid_sum_n(double *v, const RedWS &red, double *lds, int *flag)
+// Block sums of NV values, stored as this block's partials.
+template <int NV> __device__ __forceinline__ void grid_partials(double *v, const RedWS &red, double *lds)
 {
     block_sum_n<NV>(v, lds);
-    if (!publish_partials<NV>(v, red.partials, red.counter, gridDim.x, flag)) return false;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
+    write_partials<NV>(v, red.partials, gridDim.x, blockIdx.x);
+}
+
+// Totals of NV <= blockDim/64 partial sets of nb entries: wavefront k sums
+// set k (lane-strided, then shuffles) and publishes it in out_lds[k].
+template <int NV>
+__device__ __forceinline__ void wave_set_sums(const double *partials, unsigned nb, double *out_lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w < NV) {
+        const double *p = partials + (size_t)w * nb;
         double s = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += VNT)
-            s += __hip_atomic_load(&red.partials[(size_t)k * gridDim.x + b], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        for (unsigned b = lane; b < nb; b += 64) s += p[b];
         s = wave_sum(s);
-        if (lane == 0) lds[k * (VNT / 64) + wid] = s;
+        if (lane == 0) out_lds[w] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < VNT / 64; ++w) s += lds[k * (VNT / 64) + w];
-            v[k] = s;
-        }
-        __hip_atomic_store(red.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// out[k] = total of partial set k, k < nv.
+__global__ void __launch_bounds__(FNT) sum_finalize_kernel(const double *__restrict__ partials, unsigned nb, int nv,
+                                                           double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = w; k < nv; k += FNT / 64) {
+        const double *p = partials + (size_t)k * nb;
+        double s = 0.0;
+        for (unsigned b = lane; b < nb; b += 64) s += p[b];
+        s = wave_sum(s);
+        if (lane == 0) out[k] = s;
     }
-    return true;
+}
+
+static hipError_t sum_finalize(const RedWS &red, unsigned nb, int nv, double *out, hipStream_t s)
+{
+    sum_finalize_kernel<<<1, FNT, 0, s>>>(red.partials, nb, nv, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -191,7 +209,6 @@ __global__ void __launch_bounds__(VNT) multidot_kernel(const double *__restrict_
                                                        const double *__restrict__ w, int64_t n, double *out, RedWS red)
 {
     __shared__ double lds[MAXV * (VNT / 64)];
-    __shared__ int flag;
     double acc[MAXV];
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) acc[k] = 0.0;
@@ -202,9 +219,9 @@ __global__ void __launch_bounds__(VNT) multidot_kernel(const double *__restrict_
         for (int k = 0; k < MAXV; ++k)
             if (k < nv) acc[k] += V[(int64_t)k * ld + i] * wi;
     }
-    if (grid_sum_n<MAXV>(acc, red, lds, &flag) && threadIdx.x == 0) {
-        for (int k = 0; k < nv; ++k) out[k] = acc[k];
-    }
+    block_sum_n<MAXV>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nv; ++k) red.partials[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
 }
 
 hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out, const RedWS *red,
@@ -214,7 +231,8 @@ hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64
     const unsigned nb = vec_blocks(n);
     if (red->capacity < nb * MAXV) return hipErrorInvalidValue;
     multidot_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, w, n, out, *red);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
 }
 
 __global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict__ V, int64_t ld, int nv,
@@ -222,7 +240,6 @@ __global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict
                                                         double *out_norm2, RedWS red)
 {
     __shared__ double lds[VNT / 64];
-    __shared__ int flag;
     __shared__ double hs[MAXV];
     if (threadIdx.x < MAXV) hs[threadIdx.x] = threadIdx.x < (unsigned)nv ? h[threadIdx.x] : 0.0;
     __syncthreads();
@@ -234,9 +251,7 @@ __global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict
         w[i] = v;
         acc += v * v;
     }
-    if (out_norm2) {
-        if (grid_sum_n<1>(&acc, red, lds, &flag) && threadIdx.x == 0) *out_norm2 = acc;
-    }
+    if (out_norm2) grid_partials<1>(&acc, red, lds);
 }
 
 hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out_norm2,
@@ -245,8 +260,10 @@ hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, doub
     if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
     const unsigned nb = vec_blocks(n);
     if (out_norm2 && red->capacity < nb) return hipErrorInvalidValue;
-    multiaxpy_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, h, w, n, out_norm2, red ? *red : RedWS{nullptr, nullptr, 0});
-    return hipGetLastError();
+    multiaxpy_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, h, w, n, out_norm2, red ? *red : RedWS{nullptr, 0});
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !out_norm2) return e;
+    return sum_finalize(*red, nb, 1, out_norm2, s);
 }
 
 __global__ void combine_kernel(const double *__restrict__ V, int64_t ld, int nv, const double *__restrict__ h,
@@ -313,16 +330,20 @@ hipError_t block3_apply(const double *B, const double *x, double *y, int64_t nn,
 }
 
 // ---------------------------------------------------------------------------
-// CG (preconditioned with a diagonal, Saad Alg. 9.1)
+// CG (preconditioned with a diagonal, Saad Alg. 9.1).  One iteration is
+//   apply   q = A p, per-brick partials of p.q     (heat.hip, CG mode)
+//   alpha   alpha = rz / p.q                        (one workgroup)
+//   update  x += alpha p, r -= alpha q, z = D^-1 r, partials of r.z, r.r;
+//           iteration count, rz_old = rz
+//   pupdate every workgroup sums the update's partials in the same order:
+//           beta = r.z / rz_old, convergence test, p = z + beta p
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(VNT) cg_init_kernel(CGState *st, const double *__restrict__ b,
-                                                      const double *__restrict__ dinv, double *__restrict__ x,
-                                                      double *__restrict__ r, double *__restrict__ z,
-                                                      double *__restrict__ p, double *__restrict__ q, int64_t n,
-                                                      double rtol, int maxit, int flexible, RedWS red)
+__global__ void __launch_bounds__(VNT) cg_init_kernel(const double *__restrict__ b, const double *__restrict__ dinv,
+                                                      double *__restrict__ x, double *__restrict__ r,
+                                                      double *__restrict__ z, double *__restrict__ p, int64_t n,
+                                                      int flexible, RedWS red)
 {
     __shared__ double lds[2 * (VNT / 64)];
-    __shared__ int flag;
     double acc[2] = {0.0, 0.0};
     GRID_STRIDE(i, n)
     {
@@ -339,11 +360,20 @@ __global__ void __launch_bounds__(VNT) cg_init_kernel(CGState *st, const double 
         }
         acc[1] += bi * bi;
     }
-    if (grid_sum_n<2>(acc, red, lds, &flag) && threadIdx.x == 0) {
-        st->rz = acc[0];
-        st->rr = acc[1];
-        st->bb = acc[1];
-        st->thresh2 = rtol * rtol * acc[1];
+    grid_partials<2>(acc, red, lds);
+}
+
+__global__ void __launch_bounds__(FNT) cg_init_finalize_kernel(CGState *st, const double *__restrict__ partials,
+                                                               unsigned nb, double rtol, int maxit, int flexible)
+{
+    __shared__ double tot[2];
+    wave_set_sums<2>(partials, nb, tot);
+    if (threadIdx.x == 0) {
+        st->rz = tot[0];
+        st->rz_old = 0.0;
+        st->rr = tot[1];
+        st->bb = tot[1];
+        st->thresh2 = rtol * rtol * tot[1];
         st->iter = 0;
         st->maxit = maxit;
         st->breakdown = 0;
@@ -351,26 +381,58 @@ __global__ void __launch_bounds__(VNT) cg_init_kernel(CGState *st, const double 
         st->alpha = 0.0;
         st->beta = 0.0;
         st->pAp = 0.0;
-        st->done = (acc[1] == 0.0 || maxit <= 0) ? 1 : 0;
+        st->done = (tot[1] == 0.0 || maxit <= 0) ? 1 : 0;
     }
 }
 
 hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *z, double *p,
-                   double *q, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s)
+                   double *, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s)
 {
     const unsigned nb = vec_blocks(n);
     if (red->capacity < 2 * nb) return hipErrorInvalidValue;
-    cg_init_kernel<<<nb, VNT, 0, s>>>(st, b, dinv, x, r, z, p, q, n, rtol, maxit, flexible, *red);
+    cg_init_kernel<<<nb, VNT, 0, s>>>(b, dinv, x, r, z, p, n, flexible, *red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cg_init_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb, rtol, maxit, flexible);
     return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(FNT) cg_alpha_kernel(CGState *st, const double *__restrict__ partials, unsigned nb)
+{
+    __shared__ double lds[FNT];
+    if (st->done) return; // the apply was skipped; its partials are stale
+    const double pAp = sum_partials<FNT>(partials, nb, 0, lds);
+    if (threadIdx.x == 0) {
+        st->pAp = pAp;
+        if (!(pAp > 0.0) || !isfinite(pAp)) {
+            st->breakdown = 1;
+            st->done = 1;
+            st->alpha = 0.0;
+        } else {
+            st->alpha = st->rz / pAp;
+        }
+    }
+}
+
+hipError_t cg_alpha(CGState *st, const RedWS *red, unsigned nb, hipStream_t s)
+{
+    if (red->capacity < nb) return hipErrorInvalidValue;
+    cg_alpha_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
+    return hipGetLastError();
+}
+
+static unsigned cg_update_blocks(int64_t n)
+{
+    const unsigned b = vec_blocks(n);
+    return b < CG_UPDATE_BLOCKS ? b : CG_UPDATE_BLOCKS;
 }
 
 __global__ void __launch_bounds__(VNT) cg_update_kernel(CGState *st, const double *__restrict__ dinv,
                                                         double *__restrict__ x, double *__restrict__ r,
                                                         double *__restrict__ z, const double *__restrict__ p,
-                                                        double *__restrict__ q, int64_t n, RedWS red)
+                                                        const double *__restrict__ q, int64_t n, RedWS red)
 {
     __shared__ double lds[2 * (VNT / 64)];
-    __shared__ int flag;
     if (st->done) return;
     const double alpha = st->alpha;
     double acc[2] = {0.0, 0.0};
@@ -384,39 +446,55 @@ __global__ void __launch_bounds__(VNT) cg_update_kernel(CGState *st, const doubl
         acc[0] += ri * zi;
         acc[1] += ri * ri;
     }
-    if (grid_sum_n<2>(acc, red, lds, &flag) && threadIdx.x == 0) {
+    grid_partials<2>(acc, red, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // no other workgroup of this launch reads these two fields
         st->iter += 1;
-        st->rr = acc[1];
-        if (!isfinite(acc[0]) || !isfinite(acc[1])) {
-            st->breakdown = 1;
-            st->done = 1;
-        } else if (acc[1] <= st->thresh2 || st->iter >= st->maxit) {
-            st->done = 1;
-        }
-        st->beta = acc[0] / st->rz;
-        st->rz = acc[0];
+        st->rz_old = st->rz;
     }
 }
 
 hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, double *z, const double *p, double *q,
                      int64_t n, const RedWS *red, hipStream_t s)
 {
-    const unsigned nb = vec_blocks(n);
+    const unsigned nb = cg_update_blocks(n);
     if (red->capacity < 2 * nb) return hipErrorInvalidValue;
     cg_update_kernel<<<nb, VNT, 0, s>>>(st, dinv, x, r, z, p, q, n, *red);
     return hipGetLastError();
 }
 
-__global__ void cg_pupdate_kernel(const CGState *st, const double *__restrict__ z, double *__restrict__ p, int64_t n)
+__global__ void __launch_bounds__(VNT) cg_pupdate_kernel(CGState *st, const double *__restrict__ partials,
+                                                         unsigned nb, const double *__restrict__ z,
+                                                         double *__restrict__ p, int64_t n)
 {
-    if (st->done) return;
-    const double beta = st->beta;
+    __shared__ double tot[2];
+    __shared__ int skip;
+    // Workgroup 0 of this launch may set done while others start: one read
+    // per workgroup keeps the decision uniform within it.
+    if (threadIdx.x == 0) skip = st->done;
+    __syncthreads();
+    if (skip) return;
+    wave_set_sums<2>(partials, nb, tot);
+    const double rz = tot[0], rr = tot[1];
+    const bool bad = !isfinite(rz) || !isfinite(rr);
+    const bool stop = bad || rr <= st->thresh2 || st->iter >= st->maxit;
+    const double beta = rz / st->rz_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr = rr;
+        st->rz = rz;
+        st->beta = beta;
+        if (bad) st->breakdown = 1;
+        if (stop) st->done = 1;
+    }
+    if (stop) return;
     GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
 }
 
-hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, hipStream_t s)
+hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s)
 {
-    cg_pupdate_kernel<<<ew_blocks(n), VNT, 0, s>>>(st, z, p, n);
+    unsigned nb = ew_blocks(n);
+    if (nb > CG_PUPDATE_BLOCKS) nb = CG_PUPDATE_BLOCKS;
+    cg_pupdate_kernel<<<nb, VNT, 0, s>>>(st, red->partials, cg_update_blocks(n), z, p, n);
     return hipGetLastError();
 }
 
@@ -424,12 +502,11 @@ hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, hipStr
 // Flexible CG (Notay): x, r update; then z = V(r) by the caller; then
 // beta = (r.z - r.z_prev) / rz_old (Polak-Ribiere), p = z + beta p.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(VNT) fcg_xr_kernel(CGState *st, double *__restrict__ x, double *__restrict__ r,
-                                                     const double *__restrict__ p, double *__restrict__ q, int64_t n,
-                                                     RedWS red)
+__global__ void __launch_bounds__(VNT) fcg_xr_kernel(const CGState *st, double *__restrict__ x,
+                                                     double *__restrict__ r, const double *__restrict__ p,
+                                                     const double *__restrict__ q, int64_t n, RedWS red)
 {
     __shared__ double lds[VNT / 64];
-    __shared__ int flag;
     if (st->done) return;
     const double alpha = st->alpha;
     double acc = 0.0;
@@ -440,13 +517,23 @@ __global__ void __launch_bounds__(VNT) fcg_xr_kernel(CGState *st, double *__rest
         r[i] = ri;
         acc += ri * ri;
     }
-    if (grid_sum_n<1>(&acc, red, lds, &flag) && threadIdx.x == 0) {
+    grid_partials<1>(&acc, red, lds);
+}
+
+__global__ void __launch_bounds__(FNT) fcg_xr_finalize_kernel(CGState *st, const double *__restrict__ partials,
+                                                              unsigned nb)
+{
+    __shared__ double tot[1];
+    if (st->done) return;
+    wave_set_sums<1>(partials, nb, tot);
+    if (threadIdx.x == 0) {
+        const double rr = tot[0];
         st->iter += 1;
-        st->rr = acc;
-        if (!isfinite(acc)) {
+        st->rr = rr;
+        if (!isfinite(rr)) {
             st->breakdown = 1;
             st->done = 1;
-        } else if (acc <= st->thresh2 || st->iter >= st->maxit) {
+        } else if (rr <= st->thresh2 || st->iter >= st->maxit) {
             st->done = 1;
         }
     }
@@ -458,15 +545,17 @@ hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, dou
     const unsigned nb = vec_blocks(n);
     if (red->capacity < nb) return hipErrorInvalidValue;
     fcg_xr_kernel<<<nb, VNT, 0, s>>>(st, x, r, p, q, n, *red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    fcg_xr_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(VNT) fcg_dir_kernel(CGState *st, const double *__restrict__ r,
+__global__ void __launch_bounds__(VNT) fcg_dir_kernel(const CGState *st, const double *__restrict__ r,
                                                       const double *__restrict__ z, const double *__restrict__ zprev,
                                                       int64_t n, RedWS red)
 {
     __shared__ double lds[2 * (VNT / 64)];
-    __shared__ int flag;
     if (st->done) return;
     double acc[2] = {0.0, 0.0};
     GRID_STRIDE(i, n)
@@ -475,11 +564,20 @@ __global__ void __launch_bounds__(VNT) fcg_dir_kernel(CGState *st, const double 
         acc[0] += ri * z[i];
         acc[1] += ri * zprev[i];
     }
-    if (grid_sum_n<2>(acc, red, lds, &flag) && threadIdx.x == 0) {
+    grid_partials<2>(acc, red, lds);
+}
+
+__global__ void __launch_bounds__(FNT) fcg_dir_finalize_kernel(CGState *st, const double *__restrict__ partials,
+                                                               unsigned nb)
+{
+    __shared__ double tot[2];
+    if (st->done) return;
+    wave_set_sums<2>(partials, nb, tot);
+    if (threadIdx.x == 0) {
         // first direction: rz == 0 marks "no previous direction"
-        st->beta = (st->rz != 0.0) ? (acc[0] - acc[1]) / st->rz : 0.0;
-        st->rz = acc[0];
-        if (!isfinite(acc[0]) || !(acc[0] > 0.0)) {
+        st->beta = (st->rz != 0.0) ? (tot[0] - tot[1]) / st->rz : 0.0;
+        st->rz = tot[0];
+        if (!isfinite(tot[0]) || !(tot[0] > 0.0)) {
             st->breakdown = 1;
             st->done = 1;
         }
@@ -492,6 +590,9 @@ hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *
     const unsigned nb = vec_blocks(n);
     if (red->capacity < 2 * nb) return hipErrorInvalidValue;
     fcg_dir_kernel<<<nb, VNT, 0, s>>>(st, r, z, zprev, n, *red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    fcg_dir_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
     return hipGetLastError();
 }
 
