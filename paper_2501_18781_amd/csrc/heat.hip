@@ -235,6 +235,33 @@ template <int DIR, typename T> __device__ __forceinline__ void contract1d(const 
     }
 }
 
+// Cell diagonal from cm_q and ck_q (ck_q for the true 1D derivatives G).
+template <typename T>
+__device__ __forceinline__ void heat_cell_diag(const T *cm, const T *ck, T ihx, T ihy, T ihz, T *d)
+{
+    // squares of S[q][a] = l_a(xi_q) and G[q][a] = l_a'(xi_q)
+    constexpr T s0 = Q2<T>::s0, s1 = Q2<T>::s1, s2 = Q2<T>::s2;
+    constexpr T g0 = Q2<T>::g0, g1 = Q2<T>::g1, g2 = Q2<T>::g2;
+    const T S2[3][3] = {{s0 * s0, s1 * s1, s2 * s2}, {T(0), T(1), T(0)}, {s2 * s2, s1 * s1, s0 * s0}};
+    const T G2[3][3] = {{g0 * g0, g1 * g1, g2 * g2}, {T(1), T(0), T(1)}, {g2 * g2, g1 * g1, g0 * g0}};
+    T t[27], u[27], w[27];
+    contract1d<2>(cm, t, S2);
+    contract1d<1>(t, w, S2);          // mass, contracted along z and y
+    contract1d<2>(ck, t, S2);
+    contract1d<1>(t, u, G2);          // y-derivative part
+#pragma unroll
+    for (int i = 0; i < 27; ++i) w[i] += ihy * u[i];
+    contract1d<1>(t, u, S2);          // x-derivative part, before x
+    contract1d<0>(u, d, G2);
+    contract1d<2>(ck, t, G2);
+    contract1d<1>(t, u, S2);          // z-derivative part
+#pragma unroll
+    for (int i = 0; i < 27; ++i) w[i] += ihz * u[i];
+    contract1d<0>(w, t, S2);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) d[i] = t[i] + ihx * d[i];
+}
+
 template <typename T, int MODE, int HK>
 __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag, T *__restrict__ face)
 {
@@ -257,30 +284,8 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
         heat_cell_coeffs<T, 1, 0>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w, ak_w,
                                   cm, ck);
     }
-    // squares of S[q][a] = l_a(xi_q) and G[q][a] = l_a'(xi_q)
-    constexpr T s0 = Q2<T>::s0, s1 = Q2<T>::s1, s2 = Q2<T>::s2;
-    constexpr T g0 = Q2<T>::g0, g1 = Q2<T>::g1, g2 = Q2<T>::g2;
-    const T S2[3][3] = {{s0 * s0, s1 * s1, s2 * s2}, {T(0), T(1), T(0)}, {s2 * s2, s1 * s1, s0 * s0}};
-    const T G2[3][3] = {{g0 * g0, g1 * g1, g2 * g2}, {T(1), T(0), T(1)}, {g2 * g2, g1 * g1, g0 * g0}};
     T d[27];
-    {
-        T t[27], u[27], w[27];
-        contract1d<2>(cm, t, S2);
-        contract1d<1>(t, w, S2);          // mass, contracted along z and y
-        contract1d<2>(ck, t, S2);
-        contract1d<1>(t, u, G2);          // y-derivative part
-#pragma unroll
-        for (int i = 0; i < 27; ++i) w[i] += ihy * u[i];
-        contract1d<1>(t, u, S2);          // x-derivative part, before x
-        contract1d<0>(u, d, G2);
-        contract1d<2>(ck, t, G2);
-        contract1d<1>(t, u, S2);          // z-derivative part
-#pragma unroll
-        for (int i = 0; i < 27; ++i) w[i] += ihz * u[i];
-        contract1d<0>(w, t, S2);
-#pragma unroll
-        for (int i = 0; i < 27; ++i) d[i] = t[i] + ihx * d[i];
-    }
+    heat_cell_diag<T>(cm, ck, ihx, ihy, ihz, d);
     __syncthreads();
     br.store_cell(lds, d);
     __syncthreads();
@@ -314,6 +319,113 @@ hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag
     else
         face_combine_kernel<double, false, 2><<<nb, BNT, 0, s>>>(m, (const double *)face, nullptr, (double *)diag,
                                                                  nullptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Whole Jacobi-preconditioned CG solve (x0 = 0) of an FP64 heat operator on a
+// mesh that is a single brick (at most 4 cells per direction), in one
+// workgroup launch: all vectors live in LDS, the cell coefficients stay in
+// registers across iterations, reductions are one wavefront's shuffles.
+// Serves the coarsest multigrid level, whose right-hand side and solution
+// are FP32.  Stops when ||r|| <= rtol ||b||, at maxit, or on breakdown.
+// ---------------------------------------------------------------------------
+// Sum over the wavefront, identical in every lane.
+__device__ __forceinline__ double wave_total(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return __shfl(v, 0, 64);
+}
+
+template <int HK>
+__global__ void __launch_bounds__(BNT) heat_cg_brick_kernel(KMesh m, HeatArgs a, const float *__restrict__ b32,
+                                                            float *__restrict__ x32, double rtol, int maxit)
+{
+    __shared__ double X[BNB], R[BNB], P[BNB], Q[BNB], S[BNB], Dv[BNB];
+    __shared__ double E[27 * BNT];
+    const Brick br(m, threadIdx.x);
+    br.load(m, (const double *)a.phi, S, false);
+    __syncthreads();
+    const double vol = m.hx * m.hy * m.hz;
+    const double am_w = a.am * vol, ak_w = a.ak * vol / (kR * kR);
+    const double ihx = 1.0 / (m.hx * m.hx), ihy = 1.0 / (m.hy * m.hy), ihz = 1.0 / (m.hz * m.hz);
+    double cm[27], ck[27];
+    {
+        double ph[27];
+        br.gather27(S, ph);
+        interp3(ph);
+        heat_cell_coeffs<double, 0, HK>(a, ph, nullptr, nullptr, am_w, ak_w, cm, ck);
+        double ckd[27], d[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) ckd[q] = ck[q] * (kR * kR);
+        heat_cell_diag<double>(cm, ckd, ihx, ihy, ihz, d);
+        br.store_cell(E, d);
+    }
+    __syncthreads();
+    double rz = 0.0, bb = 0.0;
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int) {
+        const double dv = br.node_sum(E, ai, bi, ci);
+        const double di = constrained ? 1.0 : 1.0 / dv;
+        const double bv = (double)b32[g];
+        Dv[l] = di;
+        X[l] = 0.0;
+        R[l] = bv;
+        const double z = di * bv;
+        P[l] = z;
+        rz += bv * z;
+        bb += bv * bv;
+    });
+    rz = wave_total(rz);
+    bb = wave_total(bb);
+    const double thresh2 = rtol * rtol * bb;
+    for (int it = 0; it < maxit && bb > 0.0; ++it) {
+        br.for_owned_nodes(m, [&](int, int, int, int l, int64_t, bool constrained, int) {
+            S[l] = constrained ? 0.0 : P[l];
+        });
+        __syncthreads(); // S complete; E no longer read
+        double u[27];
+        br.gather27(S, u);
+        heat_cell_apply<double>(u, cm, ck, ihx, ihy, ihz);
+        br.store_cell(E, u);
+        __syncthreads();
+        double pq = 0.0;
+        br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t, bool constrained, int) {
+            const double qv = constrained ? P[l] : br.node_sum(E, ai, bi, ci);
+            Q[l] = qv;
+            pq += P[l] * qv;
+        });
+        pq = wave_total(pq);
+        if (!(pq > 0.0) || !isfinite(pq)) break;
+        const double alpha = rz / pq;
+        double rzn = 0.0, rr = 0.0;
+        br.for_owned_nodes(m, [&](int, int, int, int l, int64_t, bool, int) {
+            X[l] += alpha * P[l];
+            const double r = R[l] - alpha * Q[l];
+            R[l] = r;
+            const double z = Dv[l] * r;
+            Q[l] = z;
+            rzn += r * z;
+            rr += r * r;
+        });
+        rzn = wave_total(rzn);
+        rr = wave_total(rr);
+        if (rr <= thresh2 || !isfinite(rr)) break;
+        const double beta = rzn / rz;
+        rz = rzn;
+        br.for_owned_nodes(m, [&](int, int, int, int l, int64_t, bool, int) { P[l] = Q[l] + beta * P[l]; });
+    }
+    br.for_owned_nodes(m, [&](int, int, int, int l, int64_t g, bool, int) { x32[g] = (float)X[l]; });
+}
+
+bool heat_fits_one_brick(const KMesh &m) { return m.nx <= BB && m.ny <= BB && m.nz <= BB; }
+
+hipError_t heat_cg_one_brick(const KMesh &m, const HeatArgs &a, const float *b32, float *x32, double rtol, int maxit,
+                             hipStream_t s)
+{
+    if (!heat_fits_one_brick(m) || a.mode != 0) return hipErrorInvalidValue;
+    if (a.hkind == 1) heat_cg_brick_kernel<1><<<1, BNT, 0, s>>>(m, a, b32, x32, rtol, maxit);
+    else heat_cg_brick_kernel<0><<<1, BNT, 0, s>>>(m, a, b32, x32, rtol, maxit);
     return hipGetLastError();
 }
 

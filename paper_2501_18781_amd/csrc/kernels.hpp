@@ -58,6 +58,12 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
                       const RedWS *red, hipStream_t s, const KTiming *t = nullptr);
 int64_t face_buffer_elems(const KMesh &m);
 hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double *rcq, hipStream_t s);
+// Whole FP64 Jacobi-CG solve (x0 = 0) in one single-workgroup launch, for a
+// LEVELSET-mode operator on a mesh of at most 4 cells per direction; b and x
+// are FP32 (the coarsest multigrid level).
+bool heat_fits_one_brick(const KMesh &m);
+hipError_t heat_cg_one_brick(const KMesh &m, const HeatArgs &a, const float *b32, float *x32, double rtol, int maxit,
+                             hipStream_t s);
 hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
 hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s);
 hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,

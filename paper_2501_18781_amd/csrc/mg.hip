@@ -41,92 +41,127 @@ static unsigned grid_for(int64_t n)
     return (unsigned)(b < 1 ? 1 : b);
 }
 
-// Prolongation-add: xf += P ec.  One thread per fine node.
-__global__ void prolong_add_kernel(KMesh c, KMesh f, const float *__restrict__ ec, float *__restrict__ xf)
+// 1D transfer taps.  Prolongation, fine node t from coarse nodes s0..s0+2:
+// t even: the coincident coarse node t/2; t = 4c+1 and t = 4c+3: the quarter
+// points of coarse cell c, weights (3/8, 3/4, -1/8) and (-1/8, 3/4, 3/8).
+// Unused taps get weight 0 and a valid index.  A tap on a Dirichlet face of
+// the coarse mesh (direction bits lo/hi) gets weight 0 (column zeroed).
+__device__ __forceinline__ void prolong_taps(int t, int NC, bool dlo, bool dhi, int &s0, float *w)
 {
-    const int64_t nf = (int64_t)f.NX * f.NY * f.NZ;
-    GSTRIDE(i, nf)
-    {
-        const int fx = (int)(i % f.NX), fy = (int)((i / f.NX) % f.NY), fz = (int)(i / ((int64_t)f.NX * f.NY));
-        if (node_constrained(f, fx, fy, fz)) continue;
-        int ix[3], iy[3], iz[3];
-        float wx[3], wy[3], wz[3];
-        int nx = 0, ny = 0, nz = 0;
-        auto taps = [](int t, int *idx, float *w) -> int {
-            if ((t & 1) == 0) {
-                idx[0] = t >> 1;
-                w[0] = 1.0f;
-                return 1;
-            }
-            const int cc = t >> 2;
-            const bool first = (t & 3) == 1;
-            idx[0] = 2 * cc;
-            idx[1] = 2 * cc + 1;
-            idx[2] = 2 * cc + 2;
-            w[0] = first ? 0.375f : -0.125f;
-            w[1] = 0.75f;
-            w[2] = first ? -0.125f : 0.375f;
-            return 3;
-        };
-        nx = taps(fx, ix, wx);
-        ny = taps(fy, iy, wy);
-        nz = taps(fz, iz, wz);
-        float s = 0.0f;
-        for (int kz = 0; kz < nz; ++kz)
-            for (int ky = 0; ky < ny; ++ky)
-                for (int kx = 0; kx < nx; ++kx) {
-                    if (node_constrained(c, ix[kx], iy[ky], iz[kz])) continue;
-                    s += wx[kx] * wy[ky] * wz[kz] * ec[node_index(c, ix[kx], iy[ky], iz[kz])];
-                }
-        xf[i] += s;
+    if ((t & 1) == 0) {
+        const int sc = t >> 1;
+        s0 = sc < NC - 3 ? sc : NC - 3; // NC >= 3: three valid indices
+        const int k = sc - s0;
+        w[0] = k == 0 ? 1.0f : 0.0f;
+        w[1] = k == 1 ? 1.0f : 0.0f;
+        w[2] = k == 2 ? 1.0f : 0.0f;
+    } else {
+        s0 = 2 * (t >> 2);
+        const bool first = (t & 3) == 1;
+        w[0] = first ? 0.375f : -0.125f;
+        w[1] = 0.75f;
+        w[2] = first ? -0.125f : 0.375f;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int sk = s0 + k;
+        if ((dlo && sk == 0) || (dhi && sk == NC - 1)) w[k] = 0.0f;
     }
 }
 
-// Restriction rc = P^T rf.  One thread per coarse node.
-__global__ void restrict_kernel(KMesh f, KMesh c, const float *__restrict__ rf, float *__restrict__ rc)
+// Restriction (transpose), coarse node s from fine nodes: s even:
+// 2s-3, 2s-1, 2s, 2s+1, 2s+3 with (-1/8, 3/8, 1, 3/8, -1/8); s odd: 2s-1,
+// 2s, 2s+1 with (3/4, 1, 3/4), padded to five taps.  Taps outside the fine
+// mesh or on its Dirichlet faces get weight 0 (rows of P zeroed).
+__device__ __forceinline__ void restrict_taps(int s, int NF, bool dlo, bool dhi, int *t, float *w)
 {
-    const int64_t ncn = (int64_t)c.NX * c.NY * c.NZ;
-    GSTRIDE(i, ncn)
-    {
-        const int sx = (int)(i % c.NX), sy = (int)((i / c.NX) % c.NY), sz = (int)(i / ((int64_t)c.NX * c.NY));
-        if (node_constrained(c, sx, sy, sz)) {
-            rc[i] = 0.0f;
-            continue;
+    if ((s & 1) == 0) {
+        const int tt[5] = {2 * s - 3, 2 * s - 1, 2 * s, 2 * s + 1, 2 * s + 3};
+        const float ww[5] = {-0.125f, 0.375f, 1.0f, 0.375f, -0.125f};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            t[k] = tt[k];
+            w[k] = ww[k];
         }
-        auto taps = [](int s, int tmax, int *idx, float *w) -> int {
-            int n = 0;
-            auto add = [&](int t, float wt) {
-                if (t >= 0 && t <= tmax) {
-                    idx[n] = t;
-                    w[n] = wt;
-                    ++n;
-                }
-            };
-            if ((s & 1) == 0) {
-                add(2 * s - 3, -0.125f);
-                add(2 * s - 1, 0.375f);
-                add(2 * s, 1.0f);
-                add(2 * s + 1, 0.375f);
-                add(2 * s + 3, -0.125f);
-            } else {
-                add(2 * s - 1, 0.75f);
-                add(2 * s, 1.0f);
-                add(2 * s + 1, 0.75f);
-            }
-            return n;
-        };
-        int ix[5], iy[5], iz[5];
-        float wx[5], wy[5], wz[5];
-        const int nx = taps(sx, f.NX - 1, ix, wx), ny = taps(sy, f.NY - 1, iy, wy), nz = taps(sz, f.NZ - 1, iz, wz);
-        float s = 0.0f;
-        for (int kz = 0; kz < nz; ++kz)
-            for (int ky = 0; ky < ny; ++ky)
-                for (int kx = 0; kx < nx; ++kx) {
-                    if (node_constrained(f, ix[kx], iy[ky], iz[kz])) continue;
-                    s += wx[kx] * wy[ky] * wz[kz] * rf[node_index(f, ix[kx], iy[ky], iz[kz])];
-                }
-        rc[i] = s;
+    } else {
+        const int tt[5] = {2 * s - 1, 2 * s, 2 * s + 1, 2 * s, 2 * s};
+        const float ww[5] = {0.75f, 1.0f, 0.75f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            t[k] = tt[k];
+            w[k] = ww[k];
+        }
     }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const bool out = t[k] < 0 || t[k] > NF - 1;
+        if (out || (dlo && t[k] == 0) || (dhi && t[k] == NF - 1)) w[k] = 0.0f;
+        if (out) t[k] = 2 * s;
+    }
+}
+
+constexpr int TNT = 64; // threads per transfer workgroup (one row segment along x)
+
+// xf += P ec over the fine nodes; grid (ceil(NXf / TNT), NYf, NZf).
+__global__ void __launch_bounds__(TNT) prolong_add_kernel(KMesh c, KMesh f, const float *__restrict__ ec,
+                                                          float *__restrict__ xf)
+{
+    const int fx = blockIdx.x * TNT + threadIdx.x, fy = blockIdx.y, fz = blockIdx.z;
+    if (fx >= f.NX || node_constrained(f, fx, fy, fz)) return;
+    const unsigned D = c.dirichlet;
+    int sx, sy, sz;
+    float wx[3], wy[3], wz[3];
+    prolong_taps(fx, c.NX, D & 1u, D & 2u, sx, wx);
+    prolong_taps(fy, c.NY, D & 4u, D & 8u, sy, wy);
+    prolong_taps(fz, c.NZ, D & 16u, D & 32u, sz, wz);
+    const int ny = (fy & 1) ? 3 : 1, nz = (fz & 1) ? 3 : 1; // uniform over the workgroup
+    if (!(fy & 1)) {
+        sy = fy >> 1;
+        wy[0] = ((D & 4u) && sy == 0) || ((D & 8u) && sy == c.NY - 1) ? 0.0f : 1.0f;
+    }
+    if (!(fz & 1)) {
+        sz = fz >> 1;
+        wz[0] = ((D & 16u) && sz == 0) || ((D & 32u) && sz == c.NZ - 1) ? 0.0f : 1.0f;
+    }
+    float acc = 0.0f;
+    for (int kz = 0; kz < nz; ++kz)
+        for (int ky = 0; ky < ny; ++ky) {
+            const float *row = ec + node_index(c, sx, sy + ky, sz + kz);
+            const float wyz = wy[ky] * wz[kz];
+            acc += wyz * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
+        }
+    xf[node_index(f, fx, fy, fz)] += acc;
+}
+
+// rc = P^T rf over the coarse nodes; grid (ceil(NXc / TNT), NYc, NZc).
+__global__ void __launch_bounds__(TNT) restrict_kernel(KMesh f, KMesh c, const float *__restrict__ rf,
+                                                       float *__restrict__ rc)
+{
+    const int sx = blockIdx.x * TNT + threadIdx.x, sy = blockIdx.y, sz = blockIdx.z;
+    if (sx >= c.NX) return;
+    const int64_t o = node_index(c, sx, sy, sz);
+    if (node_constrained(c, sx, sy, sz)) {
+        rc[o] = 0.0f;
+        return;
+    }
+    const unsigned D = f.dirichlet;
+    int tx[5], ty[5], tz[5];
+    float wx[5], wy[5], wz[5];
+    restrict_taps(sx, f.NX, D & 1u, D & 2u, tx, wx);
+    restrict_taps(sy, f.NY, D & 4u, D & 8u, ty, wy);
+    restrict_taps(sz, f.NZ, D & 16u, D & 32u, tz, wz);
+    const int ny = (sy & 1) ? 3 : 5, nz = (sz & 1) ? 3 : 5; // uniform over the workgroup
+    float acc = 0.0f;
+    for (int kz = 0; kz < nz; ++kz)
+        for (int ky = 0; ky < ny; ++ky) {
+            const float wyz = wy[ky] * wz[kz];
+            const float *row = rf + node_index(f, 0, ty[ky], tz[kz]);
+            float sxs = 0.0f;
+#pragma unroll
+            for (int kx = 0; kx < 5; ++kx) sxs += wx[kx] * row[tx[kx]];
+            acc += wyz * sxs;
+        }
+    rc[o] = acc;
 }
 
 template <typename T> __global__ void inject_kernel(KMesh f, KMesh c, const T *__restrict__ pf, T *__restrict__ pc)
@@ -185,13 +220,15 @@ __global__ void sqrt_kernel(const double *__restrict__ d, double *__restrict__ s
 
 hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s)
 {
-    restrict_kernel<<<grid_for((int64_t)coarse.NX * coarse.NY * coarse.NZ), 256, 0, s>>>(fine, coarse, rf, rc);
+    const dim3 g((coarse.NX + TNT - 1) / TNT, coarse.NY, coarse.NZ);
+    restrict_kernel<<<g, TNT, 0, s>>>(fine, coarse, rf, rc);
     return hipGetLastError();
 }
 
 hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, hipStream_t s)
 {
-    prolong_add_kernel<<<grid_for((int64_t)fine.NX * fine.NY * fine.NZ), 256, 0, s>>>(coarse, fine, ec, xf);
+    const dim3 g((fine.NX + TNT - 1) / TNT, fine.NY, fine.NZ);
+    prolong_add_kernel<<<g, TNT, 0, s>>>(coarse, fine, ec, xf);
     return hipGetLastError();
 }
 
@@ -511,6 +548,11 @@ static mf_status vcycle(mf_mg *mg, int li, hipStream_t s)
     MGLevel &l = mg->L[li];
     mf_status st;
     if (li == 0) {
+        if (heat_fits_one_brick(l.ctx->km)) {
+            MGCHK(mg, heat_cg_one_brick(l.ctx->km, heat_args(&l.op64), l.b, l.x, mg->prm.coarse_rtol,
+                                        mg->prm.coarse_maxit, s));
+            return MF_OK;
+        }
         MGCHK(mg, vcvt_f2d(l.b, mg->b64, l.nn, s));
         mf_solve_info info;
         st = mf_cg_solve(l.ctx, &l.op64, MF_PC_JACOBI, mg->b64, mg->x64, mg->prm.coarse_rtol, mg->prm.coarse_maxit,
