@@ -293,6 +293,32 @@ def test_spot_rows_agree_with_assembled_matrix():
         assert np.abs(got - ref[rows]).max() < 1e-13 * np.abs(ref).max()
 
 
+def test_csr_spmv_matches_sparse_product():
+    # the oracle's own OpenMP CSR product (timed as the CPU baseline) against scipy's
+    wl = W.heat_sphere_workload(5, W.ALL_FACES)
+    A = O.heat_matrix(wl.mesh, wl.params, phi=wl.phi)
+    x = W.uniform(4, wl.mesh.n_nodes)
+    ref = A @ x
+    assert np.abs(O.spmv(A, x) - ref).max() <= 1e-15 * np.abs(ref).max()
+
+
+def test_block_jacobi_blocks_are_the_nodal_3x3_blocks():
+    # read off the dense matrix by (component, node) index: block(i)[c][c'] = A[c nn + i, c' nn + i]
+    ow = W.oseen_wavy_workload(2)
+    nn = ow.mesh.n_nodes
+    B = O.oseen_matrix(ow.mesh, ow.params, ow.phi, ow.u0)
+    dense = B.toarray()
+    bj = O.block_jacobi(B, nn)
+    for i in (0, 7, nn // 2, nn - 1):
+        blk = np.array([[dense[c * nn + i, cp * nn + i] for cp in range(3)] for c in range(3)])
+        assert np.array_equal(bj.blocks[i], blk)
+    assert np.allclose(np.einsum("nij,njk->nik", bj.inverse, bj.blocks), np.eye(3), atol=1e-12)
+    # applying the preconditioner to B's own block-diagonal part returns the input
+    v = W.uniform(5, 3 * nn)
+    Dv = np.einsum("nij,nj->ni", bj.blocks, v.reshape(3, nn).T).T.reshape(-1)
+    assert np.allclose(bj(Dv), v, atol=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Solvers
 # ---------------------------------------------------------------------------
