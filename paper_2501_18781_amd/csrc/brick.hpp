@@ -13,7 +13,7 @@
 //
 // A node on a face that a neighbouring brick also touches ("shared") is not
 // written to the output: its partial sum goes to the brick's slot in a face
-// buffer (386 slots per brick: the 9x9x9 surface), and a second kernel adds
+// buffer (one slot per brick node), and a second kernel adds
 // the partials of the (2, 4 or 8) bricks that share it, in a fixed order.
 // Every output entry is therefore written exactly once, without atomics and
 // without clearing the output first, and the result is bitwise reproducible.
@@ -33,7 +33,7 @@ constexpr int BB = 4;               // cells per brick edge
 constexpr int BNT = BB * BB * BB;   // threads (cells) per brick
 constexpr int BP = 2 * BB + 1;      // nodes per brick edge
 constexpr int BNB = BP * BP * BP;   // nodes per brick
-constexpr int BFACE = BNB - (BP - 2) * (BP - 2) * (BP - 2); // 386 surface nodes
+constexpr int BFACE = BNB;         // face-buffer slots per brick (indexed like the LDS brick)
 constexpr int NXCD = 8;
 
 __host__ __device__ inline int64_t n_bricks(const KMesh &m)
@@ -41,17 +41,10 @@ __host__ __device__ inline int64_t n_bricks(const KMesh &m)
     return (int64_t)((m.nx + BB - 1) / BB) * ((m.ny + BB - 1) / BB) * ((m.nz + BB - 1) / BB);
 }
 
-// Slot of a surface node (at least one local coordinate 0 or 8) of a brick:
-// the z faces first, then the y faces without the z rows, then the x faces.
-__device__ __forceinline__ int face_slot(int lx, int ly, int lz)
-{
-    if (lz == 0) return lx + BP * ly;
-    if (lz == BP - 1) return BP * BP + lx + BP * ly;
-    if (ly == 0) return 2 * BP * BP + lx + BP * (lz - 1);
-    if (ly == BP - 1) return 2 * BP * BP + BP * (BP - 2) + lx + BP * (lz - 1);
-    if (lx == 0) return 2 * BP * BP + 2 * BP * (BP - 2) + (ly - 1) + (BP - 2) * (lz - 1);
-    return 2 * BP * BP + 2 * BP * (BP - 2) + (BP - 2) * (BP - 2) + (ly - 1) + (BP - 2) * (lz - 1);
-}
+// Face-buffer slot of a brick node: the brick-local lexicographic index, so
+// that a node's slot is the LDS index its thread already holds (only the
+// slots of shared surface nodes are ever written or read).
+__host__ __device__ __forceinline__ constexpr int face_slot(int lx, int ly, int lz) { return lx + BP * (ly + BP * lz); }
 
 struct Brick {
     int brick;         // natural brick index (x fastest)
@@ -204,55 +197,89 @@ struct Brick {
     }
 };
 
-// Add the face partials of the bricks sharing each shared node.  One
-// workgroup per brick handles the shared nodes on its low faces (their
-// global index g has g = 8 b in a shared direction); every shared node is
-// finished by exactly one brick.  Partials are summed over the contributing
-// bricks in a fixed order (own brick first, then x, y, z neighbours).
-// Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
+// ---------------------------------------------------------------------------
+// Shared-node combine.  The nodes that several bricks touch lie on the
+// internal brick planes g = 8k, 0 < g < N - 1, of some direction.  They are
+// enumerated as rows of one workgroup each, every shared node exactly once:
+//   Z rows: g_z on an internal plane, one row per (plane, g_y), along x;
+//   Y rows: g_y on an internal plane, g_z not, one row per (plane, g_z), along x;
+//   X rows: g_x on an internal plane, g_y and g_z not, one row per (plane, g_z),
+//           along y.
+// A node's value is the sum of the face partials of the 2, 4 or 8 bricks
+// containing it, in a fixed order (z outer, then y, then x; lower brick
+// first).  Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
 // operator), DMODE 2 writes y = 1 (its diagonal), DMODE 0 sums them like
 // every other node (a plain nodal field such as a gradient).
-template <typename T, int DMODE = 1>
-__device__ __forceinline__ void combine_faces(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
-                                              T *__restrict__ y, int brick, int lane)
+// ---------------------------------------------------------------------------
+constexpr int CNT = 128; // threads per combine row
+
+__host__ __device__ inline int internal_planes(int N) { return N >= 2 ? (N - 2) / (2 * BB) : 0; }
+
+__device__ __forceinline__ bool on_internal_plane(int g, int N) { return (g & (2 * BB - 1)) == 0 && g > 0 && g < N - 1; }
+
+__host__ __device__ inline int combine_rows(const KMesh &m)
 {
-    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB;
-    const int bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
-    const int ncx = min(BB, m.nx - bx * BB), ncy = min(BB, m.ny - by * BB), ncz = min(BB, m.nz - bz * BB);
-    const bool shx = bx > 0, shy = by > 0, shz = bz > 0;
-    // candidates: plane z = 0 (81), plane y = 0 without the z = 0 row (72),
-    // plane x = 0 without the y = 0 and z = 0 rows (64)
-    for (int i = lane; i < BP * BP + BP * (BP - 1) + (BP - 1) * (BP - 1); i += BNT) {
-        int lx, ly, lz;
-        if (i < BP * BP) {
-            lx = i % BP; ly = i / BP; lz = 0;
-        } else if (i < BP * BP + BP * (BP - 1)) {
-            const int j = i - BP * BP;
-            lx = j % BP; ly = 0; lz = 1 + j / BP;
-        } else {
-            const int j = i - BP * BP - BP * (BP - 1);
-            lx = 0; ly = 1 + j % (BP - 1); lz = 1 + j / (BP - 1);
-        }
-        if (lx > 2 * ncx || ly > 2 * ncy || lz > 2 * ncz) continue;
-        // nodes on the high faces belong to the next brick unless the mesh ends
-        if ((lx == BP - 1 && 2 * ncx == BP - 1 && bx * BB + ncx < m.nx) ||
-            (ly == BP - 1 && 2 * ncy == BP - 1 && by * BB + ncy < m.ny) ||
-            (lz == BP - 1 && 2 * ncz == BP - 1 && bz * BB + ncz < m.nz))
-            continue;
-        const bool sx = lx == 0 && shx, sy = ly == 0 && shy, sz = lz == 0 && shz;
-        if (!(sx || sy || sz)) continue;
-        const int gx = 2 * bx * BB + lx, gy = 2 * by * BB + ly, gz = 2 * bz * BB + lz;
+    return internal_planes(m.NZ) * m.NY + (internal_planes(m.NY) + internal_planes(m.NX)) * m.NZ;
+}
+
+// Bricks containing node coordinate g along a direction with N nodes and nb
+// bricks: (k0, l0) and, if two, (k0 + 1, 0).
+__device__ __forceinline__ int brick_entries(int g, int N, int nb, int &k0, int &l0)
+{
+    if (on_internal_plane(g, N)) {
+        k0 = g / (2 * BB) - 1;
+        l0 = 2 * BB;
+        return 2;
+    }
+    k0 = min(g / (2 * BB), nb - 1);
+    l0 = g - 2 * BB * k0;
+    return 1;
+}
+
+template <typename T, int DMODE>
+__device__ __forceinline__ void combine_row(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
+                                            T *__restrict__ y, int row)
+{
+    const int nzp = internal_planes(m.NZ), nyp = internal_planes(m.NY);
+    int gx0 = 0, gy0 = 0, gz;
+    bool along_y = false;
+    if (row < nzp * m.NY) {
+        const int p = row / m.NY;
+        gy0 = row - p * m.NY;
+        gz = 2 * BB * (p + 1);
+    } else if (row < nzp * m.NY + nyp * m.NZ) {
+        const int r = row - nzp * m.NY, p = r / m.NZ;
+        gz = r - p * m.NZ;
+        gy0 = 2 * BB * (p + 1);
+        if (on_internal_plane(gz, m.NZ)) return; // a Z row has it
+    } else {
+        const int r = row - nzp * m.NY - nyp * m.NZ, p = r / m.NZ;
+        gz = r - p * m.NZ;
+        gx0 = 2 * BB * (p + 1);
+        along_y = true;
+        if (on_internal_plane(gz, m.NZ)) return;
+    }
+    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
+    int kz0, lz0;
+    const int nze = brick_entries(gz, m.NZ, nbz, kz0, lz0);
+    const int len = along_y ? m.NY : m.NX;
+    for (int i = threadIdx.x; i < len; i += CNT) {
+        const int gx = along_y ? gx0 : i, gy = along_y ? i : gy0;
+        if (along_y && on_internal_plane(gy, m.NY)) continue; // a Y row has it
         const int64_t g = node_index(m, gx, gy, gz);
         if (DMODE != 0 && node_constrained(m, gx, gy, gz)) {
             y[g] = DMODE == 1 ? x[g] : T(1);
             continue;
         }
+        int kx0, lx0, ky0, ly0;
+        const int nxe = brick_entries(gx, m.NX, nbx, kx0, lx0);
+        const int nye = brick_entries(gy, m.NY, nby, ky0, ly0);
         T s = T(0);
-        for (int dz = 0; dz <= (sz ? 1 : 0); ++dz)
-            for (int dy = 0; dy <= (sy ? 1 : 0); ++dy)
-                for (int dx = 0; dx <= (sx ? 1 : 0); ++dx) {
-                    const int nb = brick - dx - nbx * (dy + nby * dz);
-                    s += face[(int64_t)nb * BFACE + face_slot(lx + (BP - 1) * dx, ly + (BP - 1) * dy, lz + (BP - 1) * dz)];
+        for (int ez = 0; ez < nze; ++ez)
+            for (int ey = 0; ey < nye; ++ey)
+                for (int ex = 0; ex < nxe; ++ex) {
+                    const int b = (kx0 + ex) + nbx * ((ky0 + ey) + nby * (kz0 + ez));
+                    s += face[(int64_t)b * BFACE + face_slot(ex ? 0 : lx0, ey ? 0 : ly0, ez ? 0 : lz0)];
                 }
         y[g] = s;
     }

@@ -43,20 +43,34 @@ __device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, T *phq, cons
             phq[q] = T(heaviside_sine(a.eps, (double)phq[q], &dH));
         }
     }
+    // The Gauss weight of point q is w[q%3] w[q/3%3] w[q/9], one of four
+    // products w0^3, w0^2 w1, w0 w1^2, w1^3 (class = number of middle-point
+    // indices).  cm_q = A[class] + B[class] H_q, ck_q likewise: one FMA each.
+    T Am[4], Bm[4], Ak[4], Bk[4];
+    if (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            T w = T(1);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) w *= i < j ? Q2<T>::w1 : Q2<T>::w0;
+            Am[j] = am_w * w * T(a.rc_g);
+            Bm[j] = am_w * w * (T(a.rc_l) - T(a.rc_g));
+            Ak[j] = ak_w * w * T(a.k_g);
+            Bk[j] = ak_w * w * (T(a.k_l) - T(a.k_g));
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
-        const T wq = Q2<T>::weight(q % 3) * Q2<T>::weight((q / 3) % 3) * Q2<T>::weight(q / 9);
-        T k, rc;
+        const int j = (q % 3 == 1) + ((q / 3) % 3 == 1) + (q / 9 == 1);
         if (MODE == 0) {
             const T H = HK == 0 ? heaviside_linear<T>(phq[q]) : phq[q];
-            k = T(a.k_g) + H * (T(a.k_l) - T(a.k_g));
-            rc = T(a.rc_g) + H * (T(a.rc_l) - T(a.rc_g));
+            cm[q] = Am[j] + Bm[j] * H;
+            ck[q] = Ak[j] + Bk[j] * H;
         } else {
-            k = kq[q];
-            rc = rcq[q];
+            const T wq = Q2<T>::weight(q % 3) * Q2<T>::weight((q / 3) % 3) * Q2<T>::weight(q / 9);
+            cm[q] = am_w * wq * rcq[q];
+            ck[q] = ak_w * wq * kq[q];
         }
-        cm[q] = am_w * wq * rc;
-        ck[q] = ak_w * wq * k;
     }
 }
 
@@ -68,10 +82,9 @@ __device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, 
     T acc[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) acc[q] = cm[q] * u[q];
-    double unused = 0.0;
-    grad_line_apply<T, 0>(u, ck, ihx, acc, unused);
-    grad_line_apply<T, 1>(u, ck, ihy, acc, unused);
-    grad_line_apply<T, 2>(u, ck, ihz, acc, unused);
+    grad_line_apply<T, 0>(u, ck, ihx, acc);
+    grad_line_apply<T, 1>(u, ck, ihy, acc);
+    grad_line_apply<T, 2>(u, ck, ihz, acc);
     interp3T(acc);
 #pragma unroll
     for (int q = 0; q < 27; ++q) u[q] = acc[q];
@@ -127,11 +140,10 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     // x.Ax = sum over bricks of x_i times the brick's partial sum at node i.
     double energy = 0.0;
     T *fb = face + (int64_t)br.brick * BFACE;
-    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const T s = br.node_sum(E, ai, bi, ci);
         if (CG) energy += (double)xs[l] * (double)s;
-        T *dst = sh ? fb + face_slot(lx0 + ai, ly0 + bi, lz0 + ci) : y + g;
+        T *dst = sh ? fb + l : y + g;
         *dst = s;
     });
     // Dirichlet rows y_i = x_i: unshared nodes here, shared ones in the
@@ -154,16 +166,14 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
 
 // Second pass of an apply: shared nodes = sum of the bricks' face partials.
 template <typename T, bool CG, int DMODE = 1>
-__global__ void __launch_bounds__(BNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
+__global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
                                                            const T *__restrict__ x, T *__restrict__ y,
                                                            const CGState *cg)
 {
     if (CG) {
         if (cg->done) return;
     }
-    const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
-    const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
-    combine_faces<T, DMODE>(m, face, x, y, k * q + min(k, r) + j, threadIdx.x);
+    combine_row<T, DMODE>(m, face, x, y, blockIdx.x);
 }
 
 int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
@@ -203,15 +213,18 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
     if (e != hipSuccess) return e;
-    if (fp32)
-        face_combine_kernel<float, false><<<nb, BNT, 0, s>>>(m, (const float *)face, (const float *)x, (float *)y,
-                                                              nullptr);
+    const unsigned rows = (unsigned)combine_rows(m);
+    if (rows == 0) {
+        // single brick: nothing shared
+    } else if (fp32)
+        face_combine_kernel<float, false><<<rows, CNT, 0, s>>>(m, (const float *)face, (const float *)x, (float *)y,
+                                                               nullptr);
     else if (cg)
-        face_combine_kernel<double, true><<<nb, BNT, 0, s>>>(m, (const double *)face, (const double *)x, (double *)y,
-                                                             cg);
+        face_combine_kernel<double, true><<<rows, CNT, 0, s>>>(m, (const double *)face, (const double *)x,
+                                                               (double *)y, cg);
     else
-        face_combine_kernel<double, false><<<nb, BNT, 0, s>>>(m, (const double *)face, (const double *)x,
-                                                              (double *)y, nullptr);
+        face_combine_kernel<double, false><<<rows, CNT, 0, s>>>(m, (const double *)face, (const double *)x,
+                                                                (double *)y, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess || !cg) return e;
     return cg_alpha(cg, &r, nb, s);
@@ -290,10 +303,9 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     br.store_cell(lds, d);
     __syncthreads();
     T *fb = face + (int64_t)br.brick * BFACE;
-    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, int sh) {
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
         const T v = br.node_sum(lds, ai, bi, ci);
-        if (sh) fb[face_slot(lx0 + ai, ly0 + bi, lz0 + ci)] = v; // constrained ones: 1 in the combine
+        if (sh) fb[l] = v; // constrained ones: 1 in the combine
         else diag[g] = constrained ? T(1) : v;
     });
 }
@@ -313,12 +325,14 @@ hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const unsigned rows = (unsigned)combine_rows(m);
+    if (rows == 0) return hipSuccess;
     if (fp32)
-        face_combine_kernel<float, false, 2><<<nb, BNT, 0, s>>>(m, (const float *)face, nullptr, (float *)diag,
-                                                                nullptr);
+        face_combine_kernel<float, false, 2><<<rows, CNT, 0, s>>>(m, (const float *)face, nullptr, (float *)diag,
+                                                                  nullptr);
     else
-        face_combine_kernel<double, false, 2><<<nb, BNT, 0, s>>>(m, (const double *)face, nullptr, (double *)diag,
-                                                                 nullptr);
+        face_combine_kernel<double, false, 2><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr,
+                                                                   (double *)diag, nullptr);
     return hipGetLastError();
 }
 
@@ -547,10 +561,9 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
     br.store_cell(lds, s);
     __syncthreads();
     double *fb = face + (int64_t)br.brick * BFACE;
-    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool, int sh) {
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double v = br.node_sum(lds, ai, bi, ci);
-        if (sh) fb[face_slot(lx0 + ai, ly0 + bi, lz0 + ci)] = v;
+        if (sh) fb[l] = v;
         else dphi[g] = v;
     });
 }
@@ -564,7 +577,9 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !dphi || a.mode != 0) return e;
     // the level-set gradient sums over Dirichlet nodes too (DMODE 0)
-    face_combine_kernel<double, false, 0><<<nb, BNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr);
+    const unsigned rows = (unsigned)combine_rows(m);
+    if (rows == 0) return hipSuccess;
+    face_combine_kernel<double, false, 0><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr);
     return hipGetLastError();
 }
 

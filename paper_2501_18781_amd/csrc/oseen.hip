@@ -210,10 +210,9 @@ __global__ void __launch_bounds__(BNT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     double *fb = face + ((int64_t)C * n_bricks(m) + br.brick) * BFACE;
     double *yc = y + C * nn;
     const double *xc = x + C * nn;
-    const int lx0 = 2 * br.tx, ly0 = 2 * br.ty, lz0 = 2 * br.tz;
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool, int sh) {
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double s = br.node_sum(E, ai, bi, ci);
-        double *dst = sh ? fb + face_slot(lx0 + ai, ly0 + bi, lz0 + ci) : yc + g;
+        double *dst = sh ? fb + l : yc + g;
         *dst = s;
     });
     if (br.touches_dirichlet(m)) {
@@ -223,15 +222,12 @@ __global__ void __launch_bounds__(BNT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     }
 }
 
-__global__ void __launch_bounds__(ONT) oseen_combine_kernel(KMesh m, const double *__restrict__ face,
+__global__ void __launch_bounds__(CNT) oseen_combine_kernel(KMesh m, const double *__restrict__ face,
                                                             const double *__restrict__ x, double *__restrict__ y)
 {
-    const int comp = threadIdx.x / BNT;
-    const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
-    const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
+    const int comp = blockIdx.y;
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ, nb = n_bricks(m);
-    combine_faces<double>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn, k * q + min(k, r) + j,
-                          threadIdx.x % BNT);
+    combine_row<double, 1>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn, blockIdx.x);
 }
 
 hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y, void *face,
@@ -261,7 +257,8 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
     if (e != hipSuccess) return e;
-    oseen_combine_kernel<<<nb, ONT, 0, s>>>(m, fb, x, y);
+    const unsigned rows = (unsigned)combine_rows(m);
+    if (rows > 0) oseen_combine_kernel<<<dim3(rows, 3), CNT, 0, s>>>(m, fb, x, y);
     return hipGetLastError();
 }
 
