@@ -152,6 +152,48 @@ struct Brick {
         });
     }
 
+    // Stage one or two nodal fields into LDS, unmasked.  Every global load is
+    // issued before the first LDS write, so a wavefront waits for memory
+    // once instead of once per group of owned nodes.
+    template <typename T>
+    __device__ __forceinline__ void load_fields(const KMesh &m, const T *__restrict__ g0, T *l0,
+                                                const T *__restrict__ g1 = nullptr, T *l1 = nullptr) const
+    {
+        T v0[27], v1[27];
+        for_owned_nodes(m, [&](int a, int b, int c, int, int64_t gi, bool, int) {
+            v0[a + 3 * b + 9 * c] = g0[gi];
+            if (g1) v1[a + 3 * b + 9 * c] = g1[gi];
+        });
+        for_owned_nodes(m, [&](int a, int b, int c, int l, int64_t, bool, int) {
+            l0[l] = v0[a + 3 * b + 9 * c];
+            if (g1) l1[l] = v1[a + 3 * b + 9 * c];
+        });
+    }
+
+    // The cell's 27 nodal values with its Dirichlet nodes read as zero (the
+    // constrained columns are removed); bricks away from Dirichlet faces
+    // skip the test (uniform branch).
+    template <typename T> __device__ __forceinline__ void gather27_dirichlet(const KMesh &m, const T *lds, T *v) const
+    {
+        gather27(lds, v);
+        if (!touches_dirichlet(m)) return;
+        const unsigned f6 = m.dirichlet;
+        const int gx0 = 2 * (c0x + tx), gy0 = 2 * (c0y + ty), gz0 = 2 * (c0z + tz);
+        const bool dx0 = (f6 & 1u) && gx0 == 0, dx2 = (f6 & 2u) && gx0 + 2 == m.NX - 1;
+        const bool dy0 = (f6 & 4u) && gy0 == 0, dy2 = (f6 & 8u) && gy0 + 2 == m.NY - 1;
+        const bool dz0 = (f6 & 16u) && gz0 == 0, dz2 = (f6 & 32u) && gz0 + 2 == m.NZ - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const bool k = (a == 0 && dx0) || (a == 2 && dx2) || (b == 0 && dy0) || (b == 2 && dy2) ||
+                                   (c == 0 && dz0) || (c == 2 && dz2);
+                    v[a + 3 * b + 9 * c] = k ? T(0) : v[a + 3 * b + 9 * c];
+                }
+    }
+
     // The cell's 27 nodal values from LDS (zero for threads without a cell).
     template <typename T> __device__ __forceinline__ void gather27(const T *lds, T *v) const
     {

@@ -95,10 +95,9 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
                                                          T *__restrict__ y, T *__restrict__ face, CGState *cg,
                                                          RedWS red)
 {
-    // phi and then the cell contributions share one region; x stays resident
-    // only when the CG epilogue needs it for x.Ax.
-    constexpr int REG = (2 * BNB > 27 * BNT ? 2 * BNB : 27 * BNT);
-    constexpr int LDS_T = CG ? BNB + (BNB > 27 * BNT ? BNB : 27 * BNT) : REG;
+    // x stays resident (Dirichlet rows y = x and the CG epilogue read it);
+    // phi and then the cell contributions share the second region.
+    constexpr int LDS_T = BNB + (BNB > 27 * BNT ? BNB : 27 * BNT);
     __shared__ T lds[LDS_T];
     __shared__ double red_lds[BNT];
     if (CG) {
@@ -107,8 +106,8 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     const Brick br(m, threadIdx.x);
     T *xs = lds;
     T *ps = lds + BNB;
-    br.load(m, x, xs, true);
-    if (MODE == 0) br.load(m, (const T *)a.phi, ps, false);
+    if (MODE == 0) br.load_fields(m, x, xs, (const T *)a.phi, ps);
+    else br.load_fields(m, x, xs);
     __syncthreads();
 
     const T vol = T(m.hx * m.hy * m.hz);
@@ -128,35 +127,31 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
             heat_cell_coeffs<T, 1, 0>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w,
                                       ak_w, cm, ck);
         }
-        br.gather27(xs, u);
+        br.gather27_dirichlet(m, xs, u);
         heat_cell_apply<T>(u, cm, ck, ihx, ihy, ihz);
     }
-    __syncthreads(); // the staging region is now reused for the cell contributions
-    T *E = CG ? ps : lds;
+    __syncthreads(); // the phi region is now reused for the cell contributions
+    T *E = ps;
     br.store_cell(E, u);
     __syncthreads();
 
-    // Owned nodes: complete ones go to y, shared ones to the face buffer.
-    // x.Ax = sum over bricks of x_i times the brick's partial sum at node i.
+    // Owned nodes: all node sums first (LDS), then the stores.  Complete
+    // nodes go to y, shared ones to the face buffer; Dirichlet rows get
+    // y_i = x_i (shared ones in the combine pass).  x.Ax = sum over bricks of
+    // x_i times the brick's partial sum at node i, with x_i^2 for a Dirichlet
+    // node counted once, by the brick that finishes it.
     double energy = 0.0;
     T *fb = face + (int64_t)br.brick * BFACE;
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
-        const T s = br.node_sum(E, ai, bi, ci);
-        if (CG) energy += (double)xs[l] * (double)s;
-        T *dst = sh ? fb + l : y + g;
-        *dst = s;
+    T sums[27];
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t, bool, int) {
+        sums[ai + 3 * bi + 9 * ci] = br.node_sum(E, ai, bi, ci);
     });
-    // Dirichlet rows y_i = x_i: unshared nodes here, shared ones in the
-    // combine pass; x_i^2 enters x.Ax once, in the brick that combines.
-    if (br.touches_dirichlet(m)) { // uniform over the brick
-        br.for_owned_nodes(m, [&](int, int, int, int, int64_t g, bool constrained, int sh) {
-            if (constrained) {
-                const T xv = x[g];
-                if (!sh) y[g] = xv;
-                if (CG && !(sh & 2)) energy += (double)xv * (double)xv;
-            }
-        });
-    }
+    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
+        const T xv = xs[l], s = sums[ai + 3 * bi + 9 * ci];
+        if (CG) energy += constrained ? ((sh & 2) ? 0.0 : (double)xv * (double)xv) : (double)xv * (double)s;
+        T *dst = sh ? fb + l : y + g;
+        *dst = constrained ? xv : s;
+    });
     if (CG) {
         // one partial per brick; the alpha kernel sums them in brick order
         const double tot = block_sum<BNT>(energy, red_lds);
