@@ -20,6 +20,8 @@
 //      adds the partials of the bricks sharing each such node in a fixed
 //      order.  Every output entry is written once, without atomics, and the
 //      result is bitwise reproducible.  Dirichlet nodes get y_i = x_i.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "brick.hpp"
@@ -181,16 +183,20 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     if (!face) return hipErrorInvalidValue;
     if (cg && (!red || red->capacity < nb)) return hipErrorInvalidValue;
     if (fp32 && cg) return hipErrorInvalidValue;
-    if (t && t->start) {
-        hipError_t e = hipEventRecord(t->start, s);
-        if (e != hipSuccess) return e;
-    }
+    // With timing on, the events are attached to the kernel's own dispatch
+    // (they record its start and end, not the neighbouring queue packets).
+    hipEvent_t ev0 = t ? t->start : nullptr, ev1 = t ? t->stop : nullptr;
     // (precision, coefficient mode, Heaviside form, CG epilogue)
     const int key = (fp32 ? 8 : 0) | (a.mode ? 4 : (a.hkind ? 2 : 0)) | (cg ? 1 : 0);
     switch (key) {
 #define HEAT_CASE(K, T, MODE, HK, CGF)                                                                        \
     case K:                                                                                                   \
-        heat_apply_kernel<T, MODE, HK, CGF><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, cg, r);  \
+        if (ev0)                                                                                              \
+            hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF>, dim3(nb), dim3(BNT), 0, s, ev0, ev1, 0, \
+                                  m, a, (const T *)x, (T *)y, (T *)face, cg, r);                              \
+        else                                                                                                  \
+            heat_apply_kernel<T, MODE, HK, CGF><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, cg, \
+                                                                   r);                                        \
         break;
         HEAT_CASE(0, double, 0, 0, false)
         HEAT_CASE(1, double, 0, 0, true)
@@ -206,7 +212,6 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
         return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
     if (e != hipSuccess) return e;
     const unsigned rows = (unsigned)combine_rows(m);
     if (rows == 0) {
