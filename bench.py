@@ -278,6 +278,21 @@ def main():
     roof["bytes_per_launch"] = bytes_
     roof["hbm_frac"] = frac_hbm
     roof["fp64_frac"] = frac_alu
+    # attainable-bandwidth reference: a streaming copy (torch.neg) of 512 MiB
+    src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(s)
+    for _ in range(10):
+        torch.neg(src, out=dst)
+    c1.record(s)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    roof["copy_gbs"] = copy_gbs
+    roof["hbm_frac_vs_copy"] = gbs / copy_gbs
+    roof["whole_apply_us"] = apply_ms / args.steps / args.applies * 1e3
     log(f"[bench] apply kernel {k_s * 1e6:.1f} us: {tflops:.2f} TFLOP/s ({frac_alu:.1%} FP64), "
         f"{gbs:.0f} GB/s ({frac_hbm:.1%} HBM); whole apply {apply_ms / args.steps / args.applies * 1e3:.1f} us")
     info = infos[-1]
@@ -423,7 +438,8 @@ def oseen_bench(dev, applies=50):
         e1.record(s)
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / applies
-        out[label] = {"us": us, "dofs_per_s": nd / (us * 1e-6)}
+        # algorithmic bytes per velocity DoF: x, y, u0 (8 B each) and phi (8 B per 3 DoFs)
+        out[label] = {"us": us, "dofs_per_s": nd / (us * 1e-6), "algorithmic_gbs": nd * (24 + 8 / 3) / (us * 1e-6) / 1e9}
     mf.operator_apply(op, xr, b)
     x = torch.empty_like(b)
     mf.gmres_solve(op, b, x, 1e-8, 3000, precond=mf.MF_PC_BLOCK_JACOBI, restart=30)  # warm
