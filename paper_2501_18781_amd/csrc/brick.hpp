@@ -33,7 +33,7 @@ constexpr int BB = 4;               // cells per brick edge
 constexpr int BNT = BB * BB * BB;   // threads (cells) per brick
 constexpr int BP = 2 * BB + 1;      // nodes per brick edge
 constexpr int BNB = BP * BP * BP;   // nodes per brick
-constexpr int BFACE = BNB;         // face-buffer slots per brick (indexed like the LDS brick)
+constexpr int BFACE = BNB + 2 * BP * BP; // face-buffer slots per brick (see face_slot)
 constexpr int NXCD = 8;
 
 __host__ __device__ inline int64_t n_bricks(const KMesh &m)
@@ -41,10 +41,15 @@ __host__ __device__ inline int64_t n_bricks(const KMesh &m)
     return (int64_t)((m.nx + BB - 1) / BB) * ((m.ny + BB - 1) / BB) * ((m.nz + BB - 1) / BB);
 }
 
-// Face-buffer slot of a brick node: the brick-local lexicographic index, so
-// that a node's slot is the LDS index its thread already holds (only the
-// slots of shared surface nodes are ever written or read).
-__host__ __device__ __forceinline__ constexpr int face_slot(int lx, int ly, int lz) { return lx + BP * (ly + BP * lz); }
+// Face-buffer slot of a brick node (only the slots of shared surface nodes
+// are ever written or read).  Nodes on the brick's two x faces get a region
+// of their own, (side, ly, lz) with ly fastest, so that the combine pass
+// reads them in runs along y; every other node keeps its lexicographic brick
+// index, so that runs along x stay contiguous.
+__host__ __device__ __forceinline__ constexpr int face_slot(int lx, int ly, int lz)
+{
+    return (lx == 0 || lx == 2 * BB) ? BNB + (lx ? BP * BP : 0) + ly + BP * lz : lx + BP * (ly + BP * lz);
+}
 
 struct Brick {
     int brick;         // natural brick index (x fastest)
@@ -82,6 +87,14 @@ struct Brick {
     }
 
     static __device__ __forceinline__ constexpr int lds_index(int lx, int ly, int lz) { return lx + BP * (ly + BP * lz); }
+
+    // face_slot of this thread's cell node (a, b, c), whose LDS index is l.
+    __device__ __forceinline__ int fslot(int a, int b, int c, int l) const
+    {
+        if (a == 1) return l;
+        const bool xface = a == 0 ? tx == 0 : tx == BB - 1;
+        return xface ? BNB + (a ? BP * BP : 0) + (2 * ty + b) + BP * (2 * tz + c) : l;
+    }
 
     __device__ __forceinline__ int64_t cell_index(const KMesh &m) const
     {
@@ -241,28 +254,35 @@ struct Brick {
 
 // ---------------------------------------------------------------------------
 // Shared-node combine.  The nodes that several bricks touch lie on the
-// internal brick planes g = 8k, 0 < g < N - 1, of some direction.  They are
-// enumerated as rows of one workgroup each, every shared node exactly once:
-//   Z rows: g_z on an internal plane, one row per (plane, g_y), along x;
-//   Y rows: g_y on an internal plane, g_z not, one row per (plane, g_z), along x;
-//   X rows: g_x on an internal plane, g_y and g_z not, one row per (plane, g_z),
-//           along y.
+// internal brick planes g = 8k, 0 < g < N - 1, of some direction.  One
+// thread per shared node, enumerated in three sections so that every shared
+// node comes exactly once:
+//   Z: g_z on an internal plane; order (plane, g_y, g_x);
+//   Y: g_y on an internal plane, g_z not; order (plane, g_z, g_x);
+//   X: g_x on an internal plane, g_y and g_z not; order (g_z, plane, g_y).
+// Z and Y threads run along x, X threads along y, which is the direction in
+// which the face slots they read are contiguous; the X order keeps the
+// output entries a row's planes share (8 nodes apart) close in time.
 // A node's value is the sum of the face partials of the 2, 4 or 8 bricks
 // containing it, in a fixed order (z outer, then y, then x; lower brick
 // first).  Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
 // operator), DMODE 2 writes y = 1 (its diagonal), DMODE 0 sums them like
 // every other node (a plain nodal field such as a gradient).
 // ---------------------------------------------------------------------------
-constexpr int CNT = 128; // threads per combine row
+constexpr int CNT = 256; // threads per combine workgroup
 
 __host__ __device__ inline int internal_planes(int N) { return N >= 2 ? (N - 2) / (2 * BB) : 0; }
 
 __device__ __forceinline__ bool on_internal_plane(int g, int N) { return (g & (2 * BB - 1)) == 0 && g > 0 && g < N - 1; }
 
-__host__ __device__ inline int combine_rows(const KMesh &m)
+// Threads of the combine pass (one per enumerated node, skipped ones included).
+__host__ __device__ inline int64_t combine_nodes(const KMesh &m)
 {
-    return internal_planes(m.NZ) * m.NY + (internal_planes(m.NY) + internal_planes(m.NX)) * m.NZ;
+    return (int64_t)internal_planes(m.NZ) * m.NX * m.NY + (int64_t)internal_planes(m.NY) * m.NX * m.NZ +
+           (int64_t)internal_planes(m.NX) * m.NY * m.NZ;
 }
+
+__host__ inline unsigned combine_blocks(const KMesh &m) { return (unsigned)((combine_nodes(m) + CNT - 1) / CNT); }
 
 // Bricks containing node coordinate g along a direction with N nodes and nb
 // bricks: (k0, l0) and, if two, (k0 + 1, 0).
@@ -278,53 +298,75 @@ __device__ __forceinline__ int brick_entries(int g, int N, int nb, int &k0, int 
     return 1;
 }
 
-template <typename T, int DMODE>
-__device__ __forceinline__ void combine_row(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
-                                            T *__restrict__ y, int row)
+// The combine thread's enumerated node; workgroups are numbered so that each
+// XCD receives a contiguous range of them (neighbouring rows share face
+// cache lines).  Returns false for a thread without a node of its own.
+__device__ __forceinline__ bool combine_node(const KMesh &m, int &gx, int &gy, int &gz)
 {
-    const int nzp = internal_planes(m.NZ), nyp = internal_planes(m.NY);
-    int gx0 = 0, gy0 = 0, gz;
-    bool along_y = false;
-    if (row < nzp * m.NY) {
-        const int p = row / m.NY;
-        gy0 = row - p * m.NY;
+    const unsigned G = gridDim.x, q = G / NXCD, r = G % NXCD;
+    const unsigned k = blockIdx.x % NXCD, jb = blockIdx.x / NXCD;
+    const unsigned blk = k * q + min(k, r) + jb;
+    unsigned j = blk * CNT + threadIdx.x;
+    const unsigned NX = m.NX, NY = m.NY, NZ = m.NZ;
+    const unsigned nzp = internal_planes(m.NZ), nyp = internal_planes(m.NY), nxp = internal_planes(m.NX);
+    const unsigned sz = nzp * NX * NY, sy = nyp * NX * NZ, sx = nxp * NY * NZ;
+    if (j < sz) {
+        const unsigned p = j / (NX * NY), rr = j - p * NX * NY, y = rr / NX;
         gz = 2 * BB * (p + 1);
-    } else if (row < nzp * m.NY + nyp * m.NZ) {
-        const int r = row - nzp * m.NY, p = r / m.NZ;
-        gz = r - p * m.NZ;
-        gy0 = 2 * BB * (p + 1);
-        if (on_internal_plane(gz, m.NZ)) return; // a Z row has it
-    } else {
-        const int r = row - nzp * m.NY - nyp * m.NZ, p = r / m.NZ;
-        gz = r - p * m.NZ;
-        gx0 = 2 * BB * (p + 1);
-        along_y = true;
-        if (on_internal_plane(gz, m.NZ)) return;
+        gy = y;
+        gx = rr - y * NX;
+        return true;
+    }
+    j -= sz;
+    if (j < sy) {
+        const unsigned p = j / (NX * NZ), rr = j - p * NX * NZ, z = rr / NX;
+        gy = 2 * BB * (p + 1);
+        gz = z;
+        gx = rr - z * NX;
+        return !on_internal_plane(gz, m.NZ);
+    }
+    j -= sy;
+    if (j < sx) {
+        const unsigned z = j / (nxp * NY), rr = j - z * nxp * NY, p = rr / NY;
+        gx = 2 * BB * (p + 1);
+        gz = z;
+        gy = rr - p * NY;
+        return !on_internal_plane(gy, m.NY) && !on_internal_plane(gz, m.NZ);
+    }
+    return false;
+}
+
+template <typename T, int DMODE>
+__device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
+                                               T *__restrict__ y)
+{
+    int gx, gy, gz;
+    if (!combine_node(m, gx, gy, gz)) return;
+    const int64_t g = node_index(m, gx, gy, gz);
+    if (DMODE != 0 && node_constrained(m, gx, gy, gz)) {
+        y[g] = DMODE == 1 ? x[g] : T(1);
+        return;
     }
     const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
-    int kz0, lz0;
+    int kx0, lx0, ky0, ly0, kz0, lz0;
+    const int nxe = brick_entries(gx, m.NX, nbx, kx0, lx0);
+    const int nye = brick_entries(gy, m.NY, nby, ky0, ly0);
     const int nze = brick_entries(gz, m.NZ, nbz, kz0, lz0);
-    const int len = along_y ? m.NY : m.NX;
-    for (int i = threadIdx.x; i < len; i += CNT) {
-        const int gx = along_y ? gx0 : i, gy = along_y ? i : gy0;
-        if (along_y && on_internal_plane(gy, m.NY)) continue; // a Y row has it
-        const int64_t g = node_index(m, gx, gy, gz);
-        if (DMODE != 0 && node_constrained(m, gx, gy, gz)) {
-            y[g] = DMODE == 1 ? x[g] : T(1);
-            continue;
+    // all (up to 8) loads first, then the sum in the fixed order
+    T v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+        v[e] = T(0);
+        if (ex < nxe && ey < nye && ez < nze) {
+            const int b = (kx0 + ex) + nbx * ((ky0 + ey) + nby * (kz0 + ez));
+            v[e] = face[(int64_t)b * BFACE + face_slot(ex ? 0 : lx0, ey ? 0 : ly0, ez ? 0 : lz0)];
         }
-        int kx0, lx0, ky0, ly0;
-        const int nxe = brick_entries(gx, m.NX, nbx, kx0, lx0);
-        const int nye = brick_entries(gy, m.NY, nby, ky0, ly0);
-        T s = T(0);
-        for (int ez = 0; ez < nze; ++ez)
-            for (int ey = 0; ey < nye; ++ey)
-                for (int ex = 0; ex < nxe; ++ex) {
-                    const int b = (kx0 + ex) + nbx * ((ky0 + ey) + nby * (kz0 + ez));
-                    s += face[(int64_t)b * BFACE + face_slot(ex ? 0 : lx0, ey ? 0 : ly0, ez ? 0 : lz0)];
-                }
-        y[g] = s;
     }
+    T s = v[0];
+#pragma unroll
+    for (int e = 1; e < 8; ++e) s += v[e];
+    y[g] = s;
 }
 
 } // namespace mf

@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
         const T xv = xs[l], s = sums[ai + 3 * bi + 9 * ci];
         if (CG) energy += constrained ? ((sh & 2) ? 0.0 : (double)xv * (double)xv) : (double)xv * (double)s;
-        T *dst = sh ? fb + l : y + g;
+        T *dst = sh ? fb + br.fslot(ai, bi, ci, l) : y + g;
         *dst = constrained ? xv : s;
     });
     if (CG) {
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__r
     if (CG) {
         if (cg->done) return;
     }
-    combine_row<T, DMODE>(m, face, x, y, blockIdx.x);
+    combine_shared<T, DMODE>(m, face, x, y);
 }
 
 int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
@@ -213,7 +213,7 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned rows = (unsigned)combine_rows(m);
+    const unsigned rows = combine_blocks(m);
     if (rows == 0) {
         // single brick: nothing shared
     } else if (fp32)
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     T *fb = face + (int64_t)br.brick * BFACE;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
         const T v = br.node_sum(lds, ai, bi, ci);
-        if (sh) fb[l] = v; // constrained ones: 1 in the combine
+        if (sh) fb[br.fslot(ai, bi, ci, l)] = v; // constrained ones: 1 in the combine
         else diag[g] = constrained ? T(1) : v;
     });
 }
@@ -325,7 +325,7 @@ hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned rows = (unsigned)combine_rows(m);
+    const unsigned rows = combine_blocks(m);
     if (rows == 0) return hipSuccess;
     if (fp32)
         face_combine_kernel<float, false, 2><<<rows, CNT, 0, s>>>(m, (const float *)face, nullptr, (float *)diag,
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
     double *fb = face + (int64_t)br.brick * BFACE;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double v = br.node_sum(lds, ai, bi, ci);
-        if (sh) fb[l] = v;
+        if (sh) fb[br.fslot(ai, bi, ci, l)] = v;
         else dphi[g] = v;
     });
 }
@@ -577,7 +577,7 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !dphi || a.mode != 0) return e;
     // the level-set gradient sums over Dirichlet nodes too (DMODE 0)
-    const unsigned rows = (unsigned)combine_rows(m);
+    const unsigned rows = combine_blocks(m);
     if (rows == 0) return hipSuccess;
     face_combine_kernel<double, false, 0><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr);
     return hipGetLastError();

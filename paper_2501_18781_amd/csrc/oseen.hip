@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(BNT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     const double *xc = x + C * nn;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double s = br.node_sum(E, ai, bi, ci);
-        double *dst = sh ? fb + l : yc + g;
+        double *dst = sh ? fb + br.fslot(ai, bi, ci, l) : yc + g;
         *dst = s;
     });
     if (br.touches_dirichlet(m)) {
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(CNT) oseen_combine_kernel(KMesh m, const doubl
 {
     const int comp = blockIdx.y;
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ, nb = n_bricks(m);
-    combine_row<double, 1>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn, blockIdx.x);
+    combine_shared<double, 1>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn);
 }
 
 hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y, void *face,
@@ -257,7 +257,7 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
     if (e != hipSuccess) return e;
-    const unsigned rows = (unsigned)combine_rows(m);
+    const unsigned rows = combine_blocks(m);
     if (rows > 0) oseen_combine_kernel<<<dim3(rows, 3), CNT, 0, s>>>(m, fb, x, y);
     return hipGetLastError();
 }
