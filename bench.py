@@ -34,7 +34,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one heat apply in the FP64 level-set mode (see DESIGN.md):
+# Algorithmic work of one heat apply in the FP64 level-set mode:
 #   flops per cell, counted from the sum-factorized algorithm:
 #     2 fields x 3 interpolation passes x 9 lines x 10 flops      = 540
 #     coefficients, 27 Gauss points x 10 flops                      = 270
@@ -373,8 +373,10 @@ def mg_vs_cg(n, dev):
     from paper_2501_18781_amd import workloads as W
 
     out = {"cells": n, "rtol": 1e-8}
-    for label, params in [("dt=1e-3", W.HeatParams()), ("dt=1 (stiffness-dominated, supplementary)",
-                                                       W.HeatParams(dt=1.0))]:
+    regimes = [("dt=1e-3", W.HeatParams()),
+               ("dt=1 (mass and conduction comparable, supplementary)", W.HeatParams(dt=1.0)),
+               ("dt=1e3 (conduction-dominated, supplementary)", W.HeatParams(dt=1e3))]
+    for label, params in regimes:
         wl = W.heat_sphere_workload(n, W.ALL_FACES, params)
         log(f"[bench] mg vs cg {n}^3 {label}")
         ctx = mf.Context(wl.mesh)

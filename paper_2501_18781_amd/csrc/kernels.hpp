@@ -119,10 +119,11 @@ hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *e
 hipError_t mg_inject(const KMesh &fine, const KMesh &coarse, const void *phif, void *phic, int fp32,
                      hipStream_t s);
 // Chebyshev pieces in FP32 (see mg.hip)
-hipError_t cheb_first(const float *dinv, const float *r, float *d, float *x, float inv_theta, int x_zero,
-                      int64_t n, hipStream_t s);
-hipError_t cheb_step(const float *dinv, float *r, const float *Ad, float *d, float *x, float c1, float c2,
-                     int64_t n, hipStream_t s);
+// Chebyshev smoother vector steps (FP32); see mg.hip.
+hipError_t cheb_first(const float *dinv, const float *b, const float *t, float *r, float *d, float *x, float inv_theta,
+                      bool more, int64_t n, hipStream_t s);
+hipError_t cheb_step(const float *dinv, const float *rin, const float *Ad, float *r, float *d, float *x, float c1,
+                     float c2, bool xprev_d, bool last, int64_t n, hipStream_t s);
 hipError_t vsub_f(const float *b, const float *Ax, float *r, int64_t n, hipStream_t s); // r = b - Ax
 
 } // namespace mf

@@ -174,29 +174,41 @@ template <typename T> __global__ void inject_kernel(KMesh f, KMesh c, const T *_
     }
 }
 
-// Chebyshev: d = D^{-1} r / theta, x = d (from zero) or x += d.
-__global__ void cheb_first_kernel(const float *__restrict__ dinv, const float *__restrict__ r, float *__restrict__ d,
-                                  float *__restrict__ x, float inv_theta, int x_zero, int64_t n)
+// First Chebyshev step on the residual r = b - t (t null: x starts from zero
+// and r = b): d = D^{-1} r / theta, then x = d or x += d.  With MORE steps to
+// follow, r and d are stored; from zero neither r (the next step reads b)
+// nor x (the next step forms x = d + d') is written.
+template <bool XZERO, bool MORE>
+__global__ void cheb_first_kernel(const float *__restrict__ dinv, const float *__restrict__ b,
+                                  const float *__restrict__ t, float *__restrict__ r, float *__restrict__ d,
+                                  float *__restrict__ x, float inv_theta, int64_t n)
 {
     GSTRIDE(i, n)
     {
-        const float di = dinv[i] * r[i] * inv_theta;
-        d[i] = di;
-        x[i] = x_zero ? di : x[i] + di;
+        const float ri = XZERO ? b[i] : b[i] - t[i];
+        if (MORE && !XZERO) r[i] = ri;
+        const float di = dinv[i] * ri * inv_theta;
+        if (MORE) d[i] = di;
+        if (!XZERO) x[i] += di;
+        else if (!MORE) x[i] = di;
     }
 }
 
-// Chebyshev step: r -= A d, d = c1 d + c2 D^{-1} r, x += d.
-__global__ void cheb_step_kernel(const float *__restrict__ dinv, float *__restrict__ r, const float *__restrict__ Ad,
-                                 float *__restrict__ d, float *__restrict__ x, float c1, float c2, int64_t n)
+// Chebyshev step: r = rin - A d, d = c1 d + c2 D^{-1} r, x += d (x = d_old + d
+// right after a first step from zero).  The last step stores x only.  rin and
+// r may be the same vector.
+template <bool XPREV_D, bool LAST>
+__global__ void cheb_step_kernel(const float *__restrict__ dinv, const float *rin, const float *__restrict__ Ad,
+                                 float *r, float *__restrict__ d, float *__restrict__ x, float c1, float c2, int64_t n)
 {
     GSTRIDE(i, n)
     {
-        const float ri = r[i] - Ad[i];
-        r[i] = ri;
-        const float di = c1 * d[i] + c2 * dinv[i] * ri;
-        d[i] = di;
-        x[i] += di;
+        const float ri = rin[i] - Ad[i];
+        if (!LAST) r[i] = ri;
+        const float dold = d[i];
+        const float di = c1 * dold + c2 * dinv[i] * ri;
+        if (!LAST) d[i] = di;
+        x[i] = (XPREV_D ? dold : x[i]) + di;
     }
 }
 
@@ -204,8 +216,6 @@ __global__ void sub_f_kernel(const float *__restrict__ b, const float *__restric
 {
     GSTRIDE(i, n) r[i] = b[i] - Ax[i];
 }
-
-__global__ void copy_f_kernel(const float *__restrict__ a, float *__restrict__ y, int64_t n) { GSTRIDE(i, n) y[i] = a[i]; }
 
 __global__ void knuth_kernel(double *__restrict__ v, int64_t n)
 {
@@ -240,29 +250,37 @@ hipError_t mg_inject(const KMesh &fine, const KMesh &coarse, const void *phif, v
     return hipGetLastError();
 }
 
-hipError_t cheb_first(const float *dinv, const float *r, float *d, float *x, float inv_theta, int x_zero, int64_t n,
-                      hipStream_t s)
+hipError_t cheb_first(const float *dinv, const float *b, const float *t, float *r, float *d, float *x, float inv_theta,
+                      bool more, int64_t n, hipStream_t s)
 {
-    cheb_first_kernel<<<grid_for(n), 256, 0, s>>>(dinv, r, d, x, inv_theta, x_zero, n);
+    const unsigned g = grid_for(n);
+    if (!t) {
+        if (more) cheb_first_kernel<true, true><<<g, 256, 0, s>>>(dinv, b, t, r, d, x, inv_theta, n);
+        else cheb_first_kernel<true, false><<<g, 256, 0, s>>>(dinv, b, t, r, d, x, inv_theta, n);
+    } else {
+        if (more) cheb_first_kernel<false, true><<<g, 256, 0, s>>>(dinv, b, t, r, d, x, inv_theta, n);
+        else cheb_first_kernel<false, false><<<g, 256, 0, s>>>(dinv, b, t, r, d, x, inv_theta, n);
+    }
     return hipGetLastError();
 }
 
-hipError_t cheb_step(const float *dinv, float *r, const float *Ad, float *d, float *x, float c1, float c2, int64_t n,
-                     hipStream_t s)
+hipError_t cheb_step(const float *dinv, const float *rin, const float *Ad, float *r, float *d, float *x, float c1,
+                     float c2, bool xprev_d, bool last, int64_t n, hipStream_t s)
 {
-    cheb_step_kernel<<<grid_for(n), 256, 0, s>>>(dinv, r, Ad, d, x, c1, c2, n);
+    const unsigned g = grid_for(n);
+    if (xprev_d) {
+        if (last) cheb_step_kernel<true, true><<<g, 256, 0, s>>>(dinv, rin, Ad, r, d, x, c1, c2, n);
+        else cheb_step_kernel<true, false><<<g, 256, 0, s>>>(dinv, rin, Ad, r, d, x, c1, c2, n);
+    } else {
+        if (last) cheb_step_kernel<false, true><<<g, 256, 0, s>>>(dinv, rin, Ad, r, d, x, c1, c2, n);
+        else cheb_step_kernel<false, false><<<g, 256, 0, s>>>(dinv, rin, Ad, r, d, x, c1, c2, n);
+    }
     return hipGetLastError();
 }
 
 hipError_t vsub_f(const float *b, const float *Ax, float *r, int64_t n, hipStream_t s)
 {
     sub_f_kernel<<<grid_for(n), 256, 0, s>>>(b, Ax, r, n);
-    return hipGetLastError();
-}
-
-hipError_t vcopy_f(const float *a, float *y, int64_t n, hipStream_t s)
-{
-    copy_f_kernel<<<grid_for(n), 256, 0, s>>>(a, y, n);
     return hipGetLastError();
 }
 
@@ -520,23 +538,23 @@ mf_status mf_mg_lambda_max(const mf_mg *mg, double *out)
 } // extern "C"
 
 // Chebyshev smoothing of A_l x = b on level l (FP32); x from zero if x_zero.
+// Residual and direction are kept in l.r and l.d; the first step fuses the
+// initial residual, the last one updates x only.
 static mf_status cheb_smooth(mf_mg *mg, MGLevel &l, const float *b, float *x, bool x_zero, hipStream_t s)
 {
     mf_ctx *c = l.ctx;
     const int64_t n = l.nn;
+    const int deg = mg->prm.degree;
     const double theta = 0.5 * (l.lmax + l.lmin), delta = 0.5 * (l.lmax - l.lmin), sigma = theta / delta;
-    if (x_zero) {
-        MGCHK(mg, vcopy_f(b, l.r, n, s));
-    } else {
-        MGCHK(mg, heat_apply(c->km, heat_args(&l.op32), 1, x, l.t, c->face, nullptr, nullptr, s));
-        MGCHK(mg, vsub_f(b, l.t, l.r, n, s));
-    }
-    MGCHK(mg, cheb_first(l.dinv, l.r, l.d, x, (float)(1.0 / theta), x_zero ? 1 : 0, n, s));
+    if (!x_zero) MGCHK(mg, heat_apply(c->km, heat_args(&l.op32), 1, x, l.t, c->face, nullptr, nullptr, s));
+    MGCHK(mg, cheb_first(l.dinv, b, x_zero ? nullptr : l.t, l.r, l.d, x, (float)(1.0 / theta), deg > 1, n, s));
     double rho = 1.0 / sigma;
-    for (int k = 1; k < mg->prm.degree; ++k) {
+    for (int k = 1; k < deg; ++k) {
         MGCHK(mg, heat_apply(c->km, heat_args(&l.op32), 1, l.d, l.t, c->face, nullptr, nullptr, s));
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        MGCHK(mg, cheb_step(l.dinv, l.r, l.t, l.d, x, (float)(rho_new * rho), (float)(2.0 * rho_new / delta), n, s));
+        const bool from_zero = x_zero && k == 1; // x is still d, r is still b
+        MGCHK(mg, cheb_step(l.dinv, from_zero ? b : l.r, l.t, l.r, l.d, x, (float)(rho_new * rho),
+                            (float)(2.0 * rho_new / delta), from_zero, k == deg - 1, n, s));
         rho = rho_new;
     }
     return MF_OK;
