@@ -270,13 +270,16 @@ static inline double blend_recip(double H, double r_l, double r_g) { return 1.0 
 /* Cell matrices                                                             */
 /* ------------------------------------------------------------------------ */
 
-/* Heat cell matrix, from the weak form of eq. heat_transfer (without the
- * convective term) after one backward-Euler step:
- *   A_e[i][j] = sum_q W_q ( alpha_m rc_q N_i N_j + alpha_k k_q grad N_i . grad N_j ).
- * Coefficients: from nodal phi (phi27 != NULL) through H and eq. muEff, or
- * given per quadrature point (kq27, rcq27). */
+/* Heat cell matrix, from the weak form of eq. heat_transfer after one
+ * backward-Euler step:
+ *   A_e[i][j] = sum_q W_q ( alpha_m rc_q N_i N_j + alpha_k k_q grad N_i . grad N_j
+ *                         + alpha_c rc_q N_i (u_q . grad N_j) ),
+ * the last (convective) term only when a nodal velocity u0_27x3 (component
+ * major, 3 x 27) is given, u_q = sum_j N_j(x_q) u_j.  Coefficients: from
+ * nodal phi (phi27 != NULL) through H and eq. muEff, or given per
+ * quadrature point (kq27, rcq27). */
 static void heat_cell_matrix(const double X[8][3], const orc_coeffs *cf, const double *phi27,
-                             const double *kq27, const double *rcq27, double *Ae)
+                             const double *kq27, const double *rcq27, const double *u0_27x3, double *Ae)
 {
     memset(Ae, 0, sizeof(double) * 27 * 27);
     qp_data Q;
@@ -298,15 +301,32 @@ static void heat_cell_matrix(const double X[8][3], const orc_coeffs *cf, const d
             for (int j = 0; j < 27; ++j)
                 Ae[i * 27 + j] += cm * Q.N[i] * Q.N[j] +
                                   ck * (Q.G[i][0] * Q.G[j][0] + Q.G[i][1] * Q.G[j][1] + Q.G[i][2] * Q.G[j][2]);
+        if (u0_27x3) {
+            double uq[3] = {0.0, 0.0, 0.0};
+            for (int j = 0; j < 27; ++j)
+                for (int c = 0; c < 3; ++c) uq[c] += Q.N[j] * u0_27x3[c * 27 + j];
+            const double cc = Q.W * cf->alpha_c * rc;
+            for (int i = 0; i < 27; ++i)
+                for (int j = 0; j < 27; ++j)
+                    Ae[i * 27 + j] += cc * Q.N[i] * (uq[0] * Q.G[j][0] + uq[1] * Q.G[j][1] + uq[2] * Q.G[j][2]);
+        }
     }
 }
 
 void orc_heat_cell_matrix(const double *X24, const orc_coeffs *cf, const double *phi27,
-                          const double *kq27, const double *rcq27, double *Ae)
+                          const double *kq27, const double *rcq27, const double *u0_27x3, double *Ae)
 {
     double X[8][3];
     memcpy(X, X24, sizeof(X));
-    heat_cell_matrix(X, cf, phi27, kq27, rcq27, Ae);
+    heat_cell_matrix(X, cf, phi27, kq27, rcq27, u0_27x3, Ae);
+}
+
+/* The 27 nodal values of a cell of the nodal velocity u0 ([3][n_nodes]), 3 x 27. */
+static void cell_velocity(const orc_mesh *m, const double *u0, const int64_t idx[27], double *u27)
+{
+    const int64_t nn = nnodes(m);
+    for (int a = 0; a < 27; ++a)
+        for (int c = 0; c < 3; ++c) u27[c * 27 + a] = u0[c * nn + idx[a]];
 }
 
 /* Linearized momentum cell matrix from eq. momentum_balance with the viscous
@@ -438,9 +458,10 @@ static void apply_dirichlet(const orc_mesh *m, int ncomp, const int64_t *rowptr,
 }
 
 /* Assembly of the heat operator.  phi (nodal) or kq/rcq (per quadrature point,
- * cell-major, 27 per cell) select how the coefficients are formed. */
+ * cell-major, 27 per cell) select how the coefficients are formed; a non-NULL
+ * nodal velocity u0 ([3][n_nodes]) adds the convective term. */
 void orc_assemble_heat(const orc_mesh *m, const orc_coeffs *cf, const double *phi,
-                       const double *kq, const double *rcq,
+                       const double *kq, const double *rcq, const double *u0,
                        const int64_t *rowptr, const int32_t *cols, double *vals)
 {
     const int64_t nnz = rowptr[nnodes(m)];
@@ -451,16 +472,17 @@ void orc_assemble_heat(const orc_mesh *m, const orc_coeffs *cf, const double *ph
         for (int cz = pz; cz < m->n[2]; cz += 2)
             for (int cy = py; cy < m->n[1]; cy += 2)
                 for (int cx = px; cx < m->n[0]; cx += 2) {
-                    double X[8][3], Ae[27 * 27], phi27[27];
+                    double X[8][3], Ae[27 * 27], phi27[27], u27[81];
                     int64_t idx[27];
                     cell_vertices(m, cx, cy, cz, X);
                     cell_nodes(m, cx, cy, cz, idx);
                     const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    if (u0) cell_velocity(m, u0, idx, u27);
                     if (phi) {
                         for (int a = 0; a < 27; ++a) phi27[a] = phi[idx[a]];
-                        heat_cell_matrix(X, cf, phi27, NULL, NULL, Ae);
+                        heat_cell_matrix(X, cf, phi27, NULL, NULL, u0 ? u27 : NULL, Ae);
                     } else {
-                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, Ae);
+                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, u0 ? u27 : NULL, Ae);
                     }
                     for (int i = 0; i < 27; ++i)
                         for (int j = 0; j < 27; ++j) {
@@ -536,8 +558,11 @@ static void cells_of_node(const orc_mesh *m, int64_t id, int clo[3], int chi[3])
     }
 }
 
+/* Rows of y = A x (transpose != 0: of y = A^T x) of the heat operator, with
+ * the convective term when u0 is given. */
 void orc_heat_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *kq,
-                   const double *rcq, const double *x, int64_t nrows, const int64_t *rows, double *out)
+                   const double *rcq, const double *u0, const double *x, int32_t transpose, int64_t nrows,
+                   const int64_t *rows, double *out)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < nrows; ++s) {
@@ -549,21 +574,24 @@ void orc_heat_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, c
         for (int cz = clo[2]; cz <= chi[2]; ++cz)
             for (int cy = clo[1]; cy <= chi[1]; ++cy)
                 for (int cx = clo[0]; cx <= chi[0]; ++cx) {
-                    double X[8][3], Ae[27 * 27], phi27[27];
+                    double X[8][3], Ae[27 * 27], phi27[27], u27[81];
                     int64_t idx[27];
                     cell_vertices(m, cx, cy, cz, X);
                     cell_nodes(m, cx, cy, cz, idx);
                     const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    if (u0) cell_velocity(m, u0, idx, u27);
                     if (phi) {
                         for (int a = 0; a < 27; ++a) phi27[a] = phi[idx[a]];
-                        heat_cell_matrix(X, cf, phi27, NULL, NULL, Ae);
+                        heat_cell_matrix(X, cf, phi27, NULL, NULL, u0 ? u27 : NULL, Ae);
                     } else {
-                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, Ae);
+                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, u0 ? u27 : NULL, Ae);
                     }
                     int il = -1;
                     for (int a = 0; a < 27; ++a) if (idx[a] == r) il = a;
-                    for (int j = 0; j < 27; ++j)
-                        if (!node_constrained(m, idx[j])) acc += Ae[il * 27 + j] * x[idx[j]];
+                    for (int j = 0; j < 27; ++j) {
+                        const double e = transpose ? Ae[j * 27 + il] : Ae[il * 27 + j];
+                        if (!node_constrained(m, idx[j])) acc += e * x[idx[j]];
+                    }
                 }
         out[s] = acc;
     }

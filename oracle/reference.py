@@ -140,13 +140,15 @@ def constrained_mask(mesh) -> np.ndarray:
     return mask.astype(bool)
 
 
-def heat_cell_matrix(X8x3, params, phi27=None, kq27=None, rcq27=None, **override) -> np.ndarray:
+def heat_cell_matrix(X8x3, params, phi27=None, kq27=None, rcq27=None, u0_3x27=None, **override) -> np.ndarray:
+    """Heat cell matrix; u0_3x27 (nodal velocity of the cell) adds the convective term."""
     X = _f64(X8x3).reshape(8, 3)
     Ae = np.zeros((27, 27))
     c = ocoeffs(params, **override)
     lib().orc_heat_cell_matrix(_p(X), ctypes.byref(c), _p(None if phi27 is None else _f64(phi27)),
                                _p(None if kq27 is None else _f64(kq27)),
-                               _p(None if rcq27 is None else _f64(rcq27)), _p(Ae))
+                               _p(None if rcq27 is None else _f64(rcq27)),
+                               _p(None if u0_3x27 is None else _f64(u0_3x27)), _p(Ae))
     return Ae
 
 
@@ -180,15 +182,17 @@ def _pattern(mesh, ncomp: int):
     return m, rowptr, cols
 
 
-def heat_matrix(mesh, params, phi=None, kq=None, rcq=None, **override) -> sp.csr_matrix:
-    """Global heat matrix (CSR), coefficients from nodal phi or from per-qp arrays."""
+def heat_matrix(mesh, params, phi=None, kq=None, rcq=None, u0=None, **override) -> sp.csr_matrix:
+    """Global heat matrix (CSR), coefficients from nodal phi or from per-qp arrays;
+    a nodal velocity u0 ([3][n_nodes]) adds the convective term."""
     m, rowptr, cols = _pattern(mesh, 1)
     vals = np.zeros(cols.size)
     c = ocoeffs(params, **override)
     phi = None if phi is None else _f64(phi)
     kq = None if kq is None else _f64(kq)
     rcq = None if rcq is None else _f64(rcq)
-    lib().orc_assemble_heat(ctypes.byref(m), ctypes.byref(c), _p(phi), _p(kq), _p(rcq),
+    u0 = None if u0 is None else _f64(u0)
+    lib().orc_assemble_heat(ctypes.byref(m), ctypes.byref(c), _p(phi), _p(kq), _p(rcq), _p(u0),
                             _p(rowptr), _p(cols), _p(vals))
     n = n_nodes(mesh)
     return sp.csr_matrix((vals, cols, rowptr), shape=(n, n))
@@ -215,15 +219,17 @@ def spmv(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
     return y
 
 
-def heat_rows(mesh, params, x, rows, phi=None, kq=None, rcq=None, **override) -> np.ndarray:
-    """Selected entries of y = A x for the heat operator, from cell matrices only."""
+def heat_rows(mesh, params, x, rows, phi=None, kq=None, rcq=None, u0=None, transpose=False,
+              **override) -> np.ndarray:
+    """Selected entries of y = A x (or A^T x) for the heat operator, from cell matrices only."""
     m = omesh(mesh)
     c = ocoeffs(params, **override)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     out = np.zeros(rows.size)
     lib().orc_heat_rows(ctypes.byref(m), ctypes.byref(c), _p(None if phi is None else _f64(phi)),
                         _p(None if kq is None else _f64(kq)), _p(None if rcq is None else _f64(rcq)),
-                        _p(_f64(x)), ctypes.c_int64(rows.size), _p(rows), _p(out))
+                        _p(None if u0 is None else _f64(u0)), _p(_f64(x)), ctypes.c_int32(1 if transpose else 0),
+                        ctypes.c_int64(rows.size), _p(rows), _p(out))
     return out
 
 

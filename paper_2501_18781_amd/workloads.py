@@ -130,6 +130,7 @@ class HeatParams:
         return 1.0 / self.dt
 
     alpha_k: float = 1.0
+    alpha_c: float = 1.0  # factor of the convective term rho c_p u.grad T (used only with a velocity field)
 
 
 @dataclass(frozen=True)
@@ -166,6 +167,23 @@ def heat_sphere_workload(n: int, dirichlet: int, params: HeatParams | None = Non
     eps = 2.0 / n
     p = params or HeatParams()
     return HeatWorkload(mesh, p, phi_sphere(mesh, 0.3, eps), eps)
+
+
+@dataclass
+class HeatConvWorkload:
+    mesh: Mesh
+    params: HeatParams
+    phi: np.ndarray
+    u0: np.ndarray
+    eps: float
+
+
+def heat_conv_workload(n: int, dirichlet: int, params: HeatParams | None = None,
+                       speed: float = 1.0) -> HeatConvWorkload:
+    """Heat operator with convection: the sphere level set of heat_sphere_workload
+    and the Taylor-Green vortex (peak speed `speed`, m/s) as the velocity field."""
+    wl = heat_sphere_workload(n, dirichlet, params)
+    return HeatConvWorkload(wl.mesh, wl.params, wl.phi, speed * taylor_green(wl.mesh), wl.eps)
 
 
 @dataclass

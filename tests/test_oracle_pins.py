@@ -277,6 +277,45 @@ def test_oseen_convective_term_closed_forms():
     assert np.abs(y[:nn]).max() == 0.0 and np.abs(y[2 * nn:]).max() == 0.0
 
 
+def test_heat_convection_closed_forms_both_orientations():
+    # The convective heat form c(f, g) = alpha_c int rc f (u0 . grad g) with the
+    # linear field u0 = (y, 2z, 3x), f = x, g = x^2 + y^2 + z^2 (all exact in
+    # Q2, integrands of degree <= 3 per direction, so the Gauss rule is exact):
+    #   f^T C g = alpha_c rc int x (2xy + 4yz + 6xz) = alpha_c rc (1/3 + 1/2 + 1)  = alpha_c rc 11/6
+    #   g^T C f = alpha_c rc int (x^2 + y^2 + z^2) y                        = alpha_c rc 7/12
+    # catches: N_i and grad N_j swapped (the two values trade places), wrong
+    # sign, velocity components mixed up, u0 not interpolated at the points
+    mesh = W.Mesh((2, 3, 2))
+    x = W.node_coords(mesh)
+    u0 = np.stack([x[:, 1], 2 * x[:, 2], 3 * x[:, 0]])
+    ones = np.ones(mesh.n_cells * 27)
+    rc, ac = 2.5, 1.5
+    A = O.heat_matrix(mesh, None, kq=ones, rcq=rc * ones, u0=u0, alpha_m=0.0, alpha_k=0.0, alpha_c=ac)
+    f = x[:, 0]
+    g = (x ** 2).sum(axis=1)
+    assert abs(f @ (A @ g) - ac * rc * 11 / 6) < 1e-13
+    assert abs(g @ (A @ f) - ac * rc * 7 / 12) < 1e-13
+
+
+def test_heat_convection_annihilates_constants_and_is_skew_with_dirichlet():
+    # Sum_j N_j = 1, so C 1 = 0 for any velocity and coefficient (catches a
+    # value instead of a derivative).  For constant u0 and rc, int v (u0 . grad w)
+    # is skew for v, w vanishing on the boundary: with all faces Dirichlet the
+    # symmetric part of A is exactly the operator without convection.
+    wl = W.heat_conv_workload(3, 0)
+    C = O.heat_matrix(wl.mesh, wl.params, phi=wl.phi, u0=wl.u0, alpha_m=0.0, alpha_k=0.0)
+    assert np.abs(C @ np.ones(wl.mesh.n_nodes)).max() < 1e-12 * abs(C).max()
+    mesh = W.Mesh((3, 2, 3), dirichlet=W.ALL_FACES)
+    nn = mesh.n_nodes
+    phi = np.full(nn, 0.3)
+    a = np.array([0.7, -1.3, 0.4])
+    u0 = np.repeat(a[:, None], nn, axis=1)
+    A = O.heat_matrix(mesh, W.HeatParams(), phi=phi, u0=u0, alpha_c=2.0e3)
+    A0 = O.heat_matrix(mesh, W.HeatParams(), phi=phi)
+    assert abs((A + A.T) / 2 - A0).max() < 1e-12 * abs(A0).max()
+    assert abs(A - A.T).max() > 1e-3 * abs(A0).max()
+
+
 def test_spot_rows_agree_with_assembled_matrix():
     wl = W.heat_sphere_workload(3, W.FACE_YLO | W.FACE_ZHI)
     A = O.heat_matrix(wl.mesh, wl.params, phi=wl.phi)
@@ -284,6 +323,11 @@ def test_spot_rows_agree_with_assembled_matrix():
     rows = np.arange(0, wl.mesh.n_nodes, 5)
     y = A @ x
     assert np.abs(O.heat_rows(wl.mesh, wl.params, x, rows, phi=wl.phi) - y[rows]).max() < 1e-14 * np.abs(y).max()
+    cw = W.heat_conv_workload(3, W.FACE_XHI | W.FACE_YLO)
+    Ac = O.heat_matrix(cw.mesh, cw.params, phi=cw.phi, u0=cw.u0)
+    for tr, ref in [(False, Ac @ x), (True, Ac.T @ x)]:
+        got = O.heat_rows(cw.mesh, cw.params, x, rows, phi=cw.phi, u0=cw.u0, transpose=tr)
+        assert np.abs(got - ref[rows]).max() < 1e-13 * np.abs(ref).max()
     ow = W.oseen_wavy_workload(2)
     B = O.oseen_matrix(ow.mesh, ow.params, ow.phi, ow.u0)
     x = W.uniform(1, B.shape[0])
