@@ -174,6 +174,8 @@ mf_status check_op(mf_ctx *c, const mf_operator *op)
         return fail(c, MF_ERR_ARG, "unknown Heaviside form %d", op->heaviside);
     if (op->heaviside == MF_H_SINE && !(op->eps > 0.0)) return fail(c, MF_ERR_ARG, "sine Heaviside needs eps > 0");
     if (op->kind == MF_HEAT) {
+        if (op->u0 && (op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET))
+            return fail(c, MF_ERR_ARG, "the convective heat operator (u0 given) is FP64 in LEVELSET mode only");
         if (op->coeff_mode == MF_COEFF_LEVELSET) {
             if (!op->phi) return fail(c, MF_ERR_ARG, "heat operator in LEVELSET mode needs phi");
         } else if (op->coeff_mode == MF_COEFF_QUAD) {
@@ -204,6 +206,9 @@ HeatArgs heat_args(const mf_operator *op)
     a.phi = op->phi;
     a.kq = op->k_q;
     a.rcq = op->rc_q;
+    a.conv = op->u0 ? 1 : 0;
+    a.ac = op->alpha_c;
+    a.u0 = (const double *)op->u0;
     return a;
 }
 
@@ -244,8 +249,11 @@ hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void
 {
     if (ensure_face(c, op->kind == MF_OSEEN ? 3 : 1) != MF_OK) return hipErrorOutOfMemory;
     const KTiming *t = timed ? next_timing(c) : nullptr;
-    if (op->kind == MF_HEAT)
-        return heat_apply(c->km, heat_args(op), op->precision == MF_FP32, x, y, c->face, nullptr, nullptr, s, t);
+    if (op->kind == MF_HEAT) {
+        HeatArgs ha = heat_args(op);
+        if (transpose && ha.conv) ha.conv = 2; // without convection A^T = A
+        return heat_apply(c->km, ha, op->precision == MF_FP32, x, y, c->face, nullptr, nullptr, s, t);
+    }
     return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, c->face, s, t);
 }
 
@@ -306,8 +314,8 @@ mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, 
 {
     mf_status st = check_op(c, op);
     if (st) return st;
-    if (op->kind != MF_HEAT || op->precision != MF_FP64)
-        return fail(c, MF_ERR_ARG, "mf_heat_coeff_grad needs an FP64 heat operator");
+    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->u0)
+        return fail(c, MF_ERR_ARG, "mf_heat_coeff_grad needs an FP64 heat operator without convection");
     if (!T || !dT || !lambda) return fail(c, MF_ERR_ARG, "null input");
     if (dphi && op->coeff_mode != MF_COEFF_LEVELSET)
         return fail(c, MF_ERR_ARG, "dphi needs the LEVELSET coefficient mode");
@@ -351,8 +359,8 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
 {
     mf_status st = check_op(c, op);
     if (st) return st;
-    if (op->kind != MF_HEAT || op->precision != MF_FP64)
-        return fail(c, MF_ERR_ARG, "mf_cg_solve needs an FP64 heat operator (symmetric)");
+    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->u0)
+        return fail(c, MF_ERR_ARG, "mf_cg_solve needs a symmetric operator: FP64 heat without convection");
     if (precond != MF_PC_NONE && precond != MF_PC_JACOBI)
         return fail(c, MF_ERR_ARG, "mf_cg_solve supports MF_PC_NONE and MF_PC_JACOBI");
     if (!b || !x || !info) return fail(c, MF_ERR_ARG, "null argument");

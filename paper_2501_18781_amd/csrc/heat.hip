@@ -1,9 +1,13 @@
 // heat.hip -- matrix-free Q2 heat operator on gfx950.
 //
-// Operator (Sec. 2.1, eq. heat_transfer without convection, one backward
-// Euler step; coefficients by eqs. heaviside and muEff of Sec. 2.3):
-//   (A x)_i = sum_cells sum_q W_q ( alpha_m rc_q N_i x_q + alpha_k k_q grad N_i . grad x_q )
-// applied without assembling A (App. B: matrix-free products).
+// Operator (Sec. 2.1, eq. heat_transfer, one backward Euler step;
+// coefficients by eqs. heaviside and muEff of Sec. 2.3):
+//   (A x)_i = sum_cells sum_q W_q ( alpha_m rc_q N_i x_q + alpha_k k_q grad N_i . grad x_q
+//                                 [+ alpha_c rc_q N_i u_q . grad x_q] )
+// applied without assembling A (App. B: matrix-free products).  The
+// bracketed convective term, with a frozen nodal velocity u, is optional
+// (FP64, level-set coefficients); its transpose moves the derivative onto
+// the test function: alpha_c rc_q x_q u_q . grad N_i.
 //
 // Work decomposition (brick.hpp): one 64-thread workgroup (one wavefront)
 // per brick of 4x4x4 cells, one thread per cell.
@@ -92,14 +96,51 @@ __device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, 
     for (int q = 0; q < 27; ++q) u[q] = acc[q];
 }
 
-template <typename T, int MODE, int HK, bool CG>
+// The convective heat operator on one cell (or its transpose, TR), in place
+// on u; rcw_q = |J| w_q rc_q, ck as in heat_cell_coeffs, us the brick's
+// staged velocity components.  Mass and conduction first, so that ck is dead
+// before the velocity is interpolated.
+template <bool TR>
+__device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMesh &m, const double *us, double *u,
+                                                     const double *rcw, const double *ck, double am, double ac)
+{
+    interp3(u);
+    double acc[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) acc[q] = am * rcw[q] * u[q];
+    grad_line_apply<double, 0>(u, ck, 1.0 / (m.hx * m.hx), acc);
+    grad_line_apply<double, 1>(u, ck, 1.0 / (m.hy * m.hy), acc);
+    grad_line_apply<double, 2>(u, ck, 1.0 / (m.hz * m.hz), acc);
+    double w[27];
+    auto dir = [&](auto D) {
+        constexpr int d = decltype(D)::value;
+        const double h = d == 0 ? m.hx : (d == 1 ? m.hy : m.hz);
+        br.gather27(us + d * BNB, w);
+        interp3(w);
+        if (TR) conv_transpose<double, d>(u, rcw, w, ac / (kR * h), acc);
+        else conv_forward<double, d>(u, rcw, w, ac / (kR * h), acc);
+    };
+    dir(std::integral_constant<int, 0>{});
+    dir(std::integral_constant<int, 1>{});
+    dir(std::integral_constant<int, 2>{});
+    interp3T(acc);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) u[q] = acc[q];
+}
+
+// CONV: 0 plain heat operator; 1 with the convective term; 2 its transpose
+// (FP64, level-set coefficients, no CG epilogue).
+template <typename T, int MODE, int HK, bool CG, int CONV = 0>
 __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, const T *__restrict__ x,
                                                          T *__restrict__ y, T *__restrict__ face, CGState *cg,
                                                          RedWS red)
 {
+    static_assert(CONV == 0 || (std::is_same<T, double>::value && MODE == 0 && !CG), "convective form: FP64 only");
     // x stays resident (Dirichlet rows y = x and the CG epilogue read it);
-    // phi and then the cell contributions share the second region.
-    constexpr int LDS_T = BNB + (BNB > 27 * BNT ? BNB : 27 * BNT);
+    // phi (and the velocity) and then the cell contributions share the
+    // second region.
+    constexpr int STAGE = CONV ? 4 * BNB : BNB;
+    constexpr int LDS_T = BNB + (STAGE > 27 * BNT ? STAGE : 27 * BNT);
     __shared__ T lds[LDS_T];
     __shared__ double red_lds[BNT];
     if (CG) {
@@ -110,14 +151,28 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     T *ps = lds + BNB;
     if (MODE == 0) br.load_fields(m, x, xs, (const T *)a.phi, ps);
     else br.load_fields(m, x, xs);
+    if constexpr (CONV != 0) {
+        const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
+        for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, ps + (c + 1) * BNB, false);
+    }
     __syncthreads();
 
     const T vol = T(m.hx * m.hy * m.hz);
-    const T am_w = T(a.am) * vol;
+    const T am_w = CONV ? vol : T(a.am) * vol; // the convective form applies alpha_m itself
     const T ak_w = T(a.ak) * vol / T(kR * kR);
     const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T u[27];
-    {
+    if constexpr (CONV != 0) {
+        double rcw[27], ck[27];
+        {
+            double ph[27];
+            br.gather27(ps, ph);
+            interp3(ph);
+            heat_cell_coeffs<double, 0, HK>(a, ph, nullptr, nullptr, am_w, ak_w, rcw, ck);
+        }
+        br.gather27_dirichlet(m, xs, u);
+        heat_conv_cell_apply<CONV == 2>(br, m, ps + BNB, u, rcw, ck, a.am, a.ac);
+    } else {
         T cm[27], ck[27];
         if (MODE == 0) {
             T ph[27];
@@ -186,27 +241,32 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     // With timing on, the events are attached to the kernel's own dispatch
     // (they record its start and end, not the neighbouring queue packets).
     hipEvent_t ev0 = t ? t->start : nullptr, ev1 = t ? t->stop : nullptr;
-    // (precision, coefficient mode, Heaviside form, CG epilogue)
-    const int key = (fp32 ? 8 : 0) | (a.mode ? 4 : (a.hkind ? 2 : 0)) | (cg ? 1 : 0);
+    if (a.conv && (fp32 || cg || a.mode != 0 || !a.u0)) return hipErrorInvalidValue;
+    // (convective form, precision, coefficient mode, Heaviside form, CG epilogue)
+    const int key = (a.conv << 4) | (fp32 ? 8 : 0) | (a.mode ? 4 : (a.hkind ? 2 : 0)) | (cg ? 1 : 0);
     switch (key) {
-#define HEAT_CASE(K, T, MODE, HK, CGF)                                                                        \
+#define HEAT_CASE(K, T, MODE, HK, CGF, CV)                                                                    \
     case K:                                                                                                   \
         if (ev0)                                                                                              \
-            hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF>, dim3(nb), dim3(BNT), 0, s, ev0, ev1, 0, \
-                                  m, a, (const T *)x, (T *)y, (T *)face, cg, r);                              \
+            hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF, CV>, dim3(nb), dim3(BNT), 0, s, ev0, ev1, \
+                                  0, m, a, (const T *)x, (T *)y, (T *)face, cg, r);                           \
         else                                                                                                  \
-            heat_apply_kernel<T, MODE, HK, CGF><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, cg, \
-                                                                   r);                                        \
+            heat_apply_kernel<T, MODE, HK, CGF, CV><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, \
+                                                                       cg, r);                                \
         break;
-        HEAT_CASE(0, double, 0, 0, false)
-        HEAT_CASE(1, double, 0, 0, true)
-        HEAT_CASE(2, double, 0, 1, false)
-        HEAT_CASE(3, double, 0, 1, true)
-        HEAT_CASE(4, double, 1, 0, false)
-        HEAT_CASE(5, double, 1, 0, true)
-        HEAT_CASE(8, float, 0, 0, false)
-        HEAT_CASE(10, float, 0, 1, false)
-        HEAT_CASE(12, float, 1, 0, false)
+        HEAT_CASE(0, double, 0, 0, false, 0)
+        HEAT_CASE(1, double, 0, 0, true, 0)
+        HEAT_CASE(2, double, 0, 1, false, 0)
+        HEAT_CASE(3, double, 0, 1, true, 0)
+        HEAT_CASE(4, double, 1, 0, false, 0)
+        HEAT_CASE(5, double, 1, 0, true, 0)
+        HEAT_CASE(8, float, 0, 0, false, 0)
+        HEAT_CASE(10, float, 0, 1, false, 0)
+        HEAT_CASE(12, float, 1, 0, false, 0)
+        HEAT_CASE(16, double, 0, 0, false, 1)
+        HEAT_CASE(18, double, 0, 1, false, 1)
+        HEAT_CASE(32, double, 0, 0, false, 2)
+        HEAT_CASE(34, double, 0, 1, false, 2)
 #undef HEAT_CASE
     default:
         return hipErrorInvalidValue;
@@ -275,16 +335,50 @@ __device__ __forceinline__ void heat_cell_diag(const T *cm, const T *ck, T ihx, 
     for (int i = 0; i < 27; ++i) d[i] = t[i] + ihx * d[i];
 }
 
-template <typename T, int MODE, int HK>
+// Convective part of the cell diagonal: sum_q c_q N_i(q) u_q . grad N_i(q)
+// with c_q = alpha_c |J| w_q rc_q (rcw_q times alpha_c).  Along direction d,
+// N_i d_d N_i is (1/h_d) l_a l_a' along d times l^2 along the other two, so
+// each velocity component is contracted with S.G along d and S^2 elsewhere.
+__device__ __forceinline__ void heat_cell_conv_diag(const Brick &br, const KMesh &m, const double *us,
+                                                    const double *rcw, double ac, double *d)
+{
+    constexpr double s0 = Q2<double>::s0, s1 = Q2<double>::s1, s2 = Q2<double>::s2;
+    constexpr double g0 = Q2<double>::g0, g1 = Q2<double>::g1, g2 = Q2<double>::g2;
+    const double S2[3][3] = {{s0 * s0, s1 * s1, s2 * s2}, {0.0, 1.0, 0.0}, {s2 * s2, s1 * s1, s0 * s0}};
+    const double SG[3][3] = {{s0 * g0, s1 * g1, s2 * g2}, {0.0, 0.0, 0.0}, {-s2 * g2, -s1 * g1, -s0 * g0}};
+    const double h[3] = {m.hx, m.hy, m.hz};
+    double w[27], t[27], v[27];
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        br.gather27(us + dir * BNB, w);
+        interp3(w);
+        const double sc = ac / h[dir];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) w[q] *= sc * rcw[q];
+        contract1d<2>(w, t, dir == 2 ? SG : S2);
+        contract1d<1>(t, v, dir == 1 ? SG : S2);
+        contract1d<0>(v, t, dir == 0 ? SG : S2);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) d[i] += t[i];
+    }
+}
+
+template <typename T, int MODE, int HK, bool CONV = false>
 __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag, T *__restrict__ face)
 {
-    constexpr int LDS_T = (BNB > 27 * BNT ? BNB : 27 * BNT);
+    static_assert(!CONV || (std::is_same<T, double>::value && MODE == 0), "convective form: FP64 only");
+    constexpr int STAGE = CONV ? 4 * BNB : BNB;
+    constexpr int LDS_T = (STAGE > 27 * BNT ? STAGE : 27 * BNT);
     __shared__ T lds[LDS_T];
     const Brick br(m, threadIdx.x);
     if (MODE == 0) br.load(m, (const T *)a.phi, lds, false);
+    if constexpr (CONV) {
+        const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
+        for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, lds + (c + 1) * BNB, false);
+    }
     __syncthreads();
     const T vol = T(m.hx * m.hy * m.hz);
-    const T am_w = T(a.am) * vol, ak_w = T(a.ak) * vol;
+    const T am_w = CONV ? vol : T(a.am) * vol, ak_w = T(a.ak) * vol;
     const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T cm[27], ck[27];
     if (MODE == 0) {
@@ -298,7 +392,16 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
                                   cm, ck);
     }
     T d[27];
-    heat_cell_diag<T>(cm, ck, ihx, ihy, ihz, d);
+    if constexpr (CONV) {
+        // cm holds |J| w_q rc_q here
+        T md[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) md[q] = T(a.am) * cm[q];
+        heat_cell_diag<T>(md, ck, ihx, ihy, ihz, d);
+        heat_cell_conv_diag(br, m, (const double *)lds + BNB, (const double *)cm, a.ac, (double *)d);
+    } else {
+        heat_cell_diag<T>(cm, ck, ihx, ihy, ihz, d);
+    }
     __syncthreads();
     br.store_cell(lds, d);
     __syncthreads();
@@ -318,6 +421,10 @@ hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag
         if (a.mode == 1) heat_diag_kernel<float, 1, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
         else if (a.hkind == 1) heat_diag_kernel<float, 0, 1><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
         else heat_diag_kernel<float, 0, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
+    } else if (a.conv) {
+        if (a.mode != 0 || !a.u0) return hipErrorInvalidValue;
+        if (a.hkind == 1) heat_diag_kernel<double, 0, 1, true><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+        else heat_diag_kernel<double, 0, 0, true><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
     } else {
         if (a.mode == 1) heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
         else if (a.hkind == 1) heat_diag_kernel<double, 0, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);

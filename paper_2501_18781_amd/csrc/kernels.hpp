@@ -17,6 +17,9 @@ struct HeatArgs {
     double am, ak;   // alpha_m, alpha_k
     double k_l, k_g, rc_l, rc_g;
     const void *phi, *kq, *rcq;
+    int conv;        // convective term: 0 none, 1 A, 2 A^T (FP64, mode 0)
+    double ac;       // alpha_c
+    const double *u0; // nodal velocity [3][n_nodes] (conv != 0)
 };
 
 // Coefficients of the Oseen operator.

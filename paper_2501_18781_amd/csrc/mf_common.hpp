@@ -172,6 +172,39 @@ __device__ __forceinline__ void grad_line_apply(const T *u, const T *c, T ih, T 
         }
 }
 
+// Convection along DIR, line by line, with t = D'_DIR u the collocation derivative:
+// forward, acc += s rw .* w .* t; transposed, acc += D'_DIR^T (s rw .* w .* u).
+// (rw: coefficient times quadrature weight, w: velocity component DIR at the
+// Gauss points, s = alpha / (r h_DIR).)
+template <typename T, int DIR>
+__device__ __forceinline__ void conv_forward(const T *u, const T *rw, const T *w, T s, T *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            T t0, t1, t2;
+            Q2<T>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
+            acc[i0] += s * rw[i0] * w[i0] * t0;
+            acc[i1] += s * rw[i1] * w[i1] * t1;
+            acc[i2] += s * rw[i2] * w[i2] * t2;
+        }
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void conv_transpose(const T *u, const T *rw, const T *w, T s, T *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            Q2<T>::derivT_acc(s * rw[i0] * w[i0] * u[i0], s * rw[i1] * w[i1] * u[i1], s * rw[i2] * w[i2] * u[i2],
+                              acc[i0], acc[i1], acc[i2]);
+        }
+}
+
 // Along direction DIR: out += ih * (D' a) .* (D' b), line by line.
 template <typename T, int DIR>
 __device__ __forceinline__ void grad_dot_acc(const T *a, const T *b, T ih, T *out)

@@ -62,39 +62,6 @@ template <int DIR> __device__ __forceinline__ void deriv_inplace(double *v, doub
         }
 }
 
-// Forward convection along DIR: acc += cw .* w .* (d_DIR u), cw = alpha_c rho W, line by line.
-template <int DIR>
-__device__ __forceinline__ void conv_forward(const double *u, const double *rw, const double *w, double s,
-                                             double *acc)
-{
-#pragma unroll
-    for (int n = 0; n < 3; ++n)
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
-            double t0, t1, t2;
-            Q2<double>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
-            acc[i0] += s * rw[i0] * w[i0] * t0;
-            acc[i1] += s * rw[i1] * w[i1] * t1;
-            acc[i2] += s * rw[i2] * w[i2] * t2;
-        }
-}
-
-// Transposed convection along DIR: acc += D_DIR^T (s rw .* w .* u), line by line.
-template <int DIR>
-__device__ __forceinline__ void conv_transpose(const double *u, const double *rw, const double *w, double s,
-                                               double *acc)
-{
-#pragma unroll
-    for (int n = 0; n < 3; ++n)
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
-            Q2<double>::derivT_acc(s * rw[i0] * w[i0] * u[i0], s * rw[i1] * w[i1] * u[i1], s * rw[i2] * w[i2] * u[i2],
-                                   acc[i0], acc[i1], acc[i2]);
-        }
-}
-
 // Viscous part along DIR: g = nu .* (s d_DIR u + e), acc += s D_DIR^T g, line
 // by line (e = d_c u_d already scaled, or null for the d = c term with factor 2).
 template <int DIR, bool TWICE>
@@ -124,8 +91,8 @@ __device__ __forceinline__ void visc_dir(const double *u, const double *nu, cons
 template <int D> __device__ __forceinline__ void conv_any(bool tr, const double *u, const double *rw, const double *w,
                                                           double s, double *acc)
 {
-    if (tr) conv_transpose<D>(u, rw, w, s, acc);
-    else conv_forward<D>(u, rw, w, s, acc);
+    if (tr) conv_transpose<double, D>(u, rw, w, s, acc);
+    else conv_forward<double, D>(u, rw, w, s, acc);
 }
 
 // One component C of the Oseen operator on one cell; result (nodal) in acc.

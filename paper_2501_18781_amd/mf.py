@@ -220,14 +220,18 @@ class Operator:
         return o
 
 
-def heat_operator(ctx: Context, params, phi=None, k_q=None, rc_q=None, precision=MF_FP64, **override) -> Operator:
+def heat_operator(ctx: Context, params, phi=None, k_q=None, rc_q=None, precision=MF_FP64, u0=None,
+                  **override) -> Operator:
     """Heat operator rc/dt M + K(k) from a parameter object (k_l, k_g, rc_l,
-    rc_g, alpha_m, alpha_k, heaviside, eps)."""
+    rc_g, alpha_m, alpha_k, heaviside, eps); with a nodal velocity u0
+    ([3][n_nodes], FP64, level-set mode) it gains the convective term
+    alpha_c C(rc, u0) and is no longer symmetric."""
     g = lambda k: override.get(k, getattr(params, k))
     mode = MF_COEFF_LEVELSET if phi is not None else MF_COEFF_QUAD
+    ac = float(override.get("alpha_c", getattr(params, "alpha_c", 0.0))) if u0 is not None else 0.0
     return Operator(ctx, MF_HEAT, precision, mode, int(g("heaviside")), float(g("eps")),
-                    alpha_m=float(g("alpha_m")), alpha_k=float(g("alpha_k")), k_l=g("k_l"), k_g=g("k_g"),
-                    rc_l=g("rc_l"), rc_g=g("rc_g"), phi=phi, k_q=k_q, rc_q=rc_q)
+                    alpha_m=float(g("alpha_m")), alpha_k=float(g("alpha_k")), alpha_c=ac, k_l=g("k_l"),
+                    k_g=g("k_g"), rc_l=g("rc_l"), rc_g=g("rc_g"), phi=phi, k_q=k_q, rc_q=rc_q, u0=u0)
 
 
 def oseen_operator(ctx: Context, params, phi, u0, **override) -> Operator:
