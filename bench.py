@@ -19,6 +19,7 @@ roofline   = the apply kernel alone (events around the kernel inside the
 cpu_baseline = the CPU oracle (assembled CSR, OpenMP) on the same workload.
 mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
              both to 1e-8, on 128^3 cells (257^3 nodes).
+oseen, heat_convection, gradient = the other operators and the adjoint step.
 """
 from __future__ import annotations
 
@@ -45,6 +46,13 @@ sys.path.insert(0, ROOT)
 #   bytes per node: read x, read phi, write y, 8 bytes each        =  24
 FLOPS_PER_CELL = 1998
 BYTES_PER_NODE = 24
+# With the convective term (heat operator given a velocity field), per cell:
+#   3 velocity components x 3 interpolation passes x 9 lines x 10 flops = 810
+#   u.grad T: 3 directions x 9 lines x (12 derivative + 9 products)    = 567
+#   rc W (alpha_m T + alpha_c u.grad T), 27 points x 3 flops           =  81
+# and per node 48 bytes: x, phi, the 3 velocity components and y.
+FLOPS_PER_CELL_CONV = FLOPS_PER_CELL + 810 + 567 + 81
+BYTES_PER_NODE_CONV = 48
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 METRIC = "Q2 operator-apply DoFs/s + HBM GB/s; FP32-MG vs FP64 CG time to 1e-8 resid"
@@ -75,6 +83,7 @@ def parse():
     p.add_argument("--mg-cells", type=int, default=128)
     p.add_argument("--no-oseen", action="store_true")
     p.add_argument("--no-grad", action="store_true")
+    p.add_argument("--no-conv", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -350,6 +359,7 @@ def main():
     del ctx, op
     for flag, key, fn in [(args.no_mg, "mg_vs_cg", lambda: mg_vs_cg(args.mg_cells, dev)),
                           (args.no_oseen, "oseen", lambda: oseen_bench(dev)),
+                          (args.no_conv, "heat_convection", lambda: heat_conv_bench(dev)),
                           (args.no_grad, "gradient", lambda: grad_bench(dev))]:
         if flag:
             continue
@@ -455,6 +465,62 @@ def oseen_bench(dev, applies=50):
                                    "converged": bool(info.converged), "rel_err_vs_x_ref": err}
     log(f"[bench]   apply {out['apply']['us']:.1f} us, transpose {out['apply_transpose']['us']:.1f} us; "
         f"GMRES(30) {info.iters} it {t * 1e3:.1f} ms, err {err:.1e}")
+    return out
+
+
+def heat_conv_bench(dev, applies=50):
+    """Heat operator with the convective term on the 64^3 heat mesh (2,146,689
+    nodes) with the Taylor-Green velocity (peak 1 m/s): apply and transpose
+    throughput (kernel alone and whole apply), and Jacobi-GMRES(30) to 1e-8 on
+    b = A x_ref (x_ref ~ U[-1,1], seed 0)."""
+    import torch
+
+    from paper_2501_18781_amd import mf
+    from paper_2501_18781_amd import workloads as W
+
+    n = 64
+    wl = W.heat_conv_workload(n, W.ALL_FACES)
+    nn = wl.mesh.n_nodes
+    log(f"[bench] heat with convection {n}^3: {nn} nodes")
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi), u0=dev(wl.u0))
+    xr = dev(W.uniform(0, nn))
+    b = torch.empty_like(xr)
+    s = torch.cuda.current_stream()
+    flops, bytes_ = FLOPS_PER_CELL_CONV * n ** 3, BYTES_PER_NODE_CONV * nn
+    out = {"cells": n, "nodes": nn, "flops_per_cell": FLOPS_PER_CELL_CONV, "bytes_per_node": BYTES_PER_NODE_CONV}
+    for label, fn in [("apply", mf.operator_apply), ("apply_transpose", mf.operator_apply_transpose)]:
+        for _ in range(5):
+            fn(op, xr, b)
+        torch.cuda.synchronize()
+        ctx.timing_enable(True)
+        ctx.timing_read(reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(applies):
+            fn(op, xr, b)
+        e1.record(s)
+        torch.cuda.synchronize()
+        kms, kl = ctx.timing_read(reset=True)
+        ctx.timing_enable(False)
+        kt = kms * 1e-3 / kl
+        whole = e0.elapsed_time(e1) * 1e-3 / applies
+        out[label] = {"us": whole * 1e6, "dofs_per_s": nn / whole, "kernel_us": kt * 1e6,
+                      "kernel_algorithmic_gbs": bytes_ / kt / 1e9, "kernel_tflops": flops / kt / 1e12,
+                      "hbm_frac": bytes_ / kt / 1e9 / PEAK_HBM_GBS, "fp64_frac": flops / kt / 1e12 / PEAK_FP64_TFLOPS}
+    mf.operator_apply(op, xr, b)
+    x = torch.empty_like(b)
+    mf.gmres_solve(op, b, x, 1e-8, 3000, precond=mf.MF_PC_JACOBI, restart=30)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = mf.gmres_solve(op, b, x, 1e-8, 3000, precond=mf.MF_PC_JACOBI, restart=30)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    err = float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
+    out["gmres30_jacobi"] = {"ms": t * 1e3, "iters": info.iters, "rel_res": info.rel_res,
+                             "converged": bool(info.converged), "rel_err_vs_x_ref": err}
+    log(f"[bench]   apply {out['apply']['us']:.1f} us (kernel {out['apply']['kernel_us']:.1f}), transpose "
+        f"{out['apply_transpose']['us']:.1f} us; GMRES(30) {info.iters} it {t * 1e3:.1f} ms, err {err:.1e}")
     return out
 
 

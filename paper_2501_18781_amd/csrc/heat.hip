@@ -96,33 +96,122 @@ __device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, 
     for (int q = 0; q < 27; ++q) u[q] = acc[q];
 }
 
-// The convective heat operator on one cell (or its transpose, TR), in place
-// on u; rcw_q = |J| w_q rc_q, ck as in heat_cell_coeffs, us the brick's
-// staged velocity components.  Mass and conduction first, so that ck is dead
-// before the velocity is interpolated.
-template <bool TR>
-__device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMesh &m, const double *us, double *u,
-                                                     const double *rcw, const double *ck, double am, double ac)
-{
-    interp3(u);
-    double acc[27];
+// A coefficient at the 27 Gauss points from H_q: A[class] + B[class] H_q,
+// class = number of middle-point indices of q (the Gauss weight's class).
+struct ClassCoef {
+    const double *H;
+    double A[4], B[4];
+    __device__ __forceinline__ ClassCoef(const double *h, double scale, double c_g, double c_l) : H(h)
+    {
 #pragma unroll
-    for (int q = 0; q < 27; ++q) acc[q] = am * rcw[q] * u[q];
-    grad_line_apply<double, 0>(u, ck, 1.0 / (m.hx * m.hx), acc);
-    grad_line_apply<double, 1>(u, ck, 1.0 / (m.hy * m.hy), acc);
-    grad_line_apply<double, 2>(u, ck, 1.0 / (m.hz * m.hz), acc);
-    double w[27];
-    auto dir = [&](auto D) {
-        constexpr int d = decltype(D)::value;
-        const double h = d == 0 ? m.hx : (d == 1 ? m.hy : m.hz);
-        br.gather27(us + d * BNB, w);
-        interp3(w);
-        if (TR) conv_transpose<double, d>(u, rcw, w, ac / (kR * h), acc);
-        else conv_forward<double, d>(u, rcw, w, ac / (kR * h), acc);
+        for (int j = 0; j < 4; ++j) {
+            double w = 1.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) w *= i < j ? kW1 : kW0;
+            A[j] = scale * w * c_g;
+            B[j] = scale * w * (c_l - c_g);
+        }
+    }
+    __device__ __forceinline__ double operator[](int q) const
+    {
+        const int j = (q % 3 == 1) + ((q / 3) % 3 == 1) + (q / 9 == 1);
+        return A[j] + B[j] * H[q];
+    }
+};
+
+// Ordering point: all 27 values of v are computed before it and no memory
+// access moves across it (keeps the passes of a cell from being merged into
+// one long live range).
+__device__ __forceinline__ void pin27(double *v)
+{
+#pragma unroll
+    for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(v[i])::"memory");
+}
+
+// H(phi) at the Gauss points of this thread's cell, phi from the LDS brick.
+template <int HK>
+__device__ __forceinline__ void cell_heaviside(const Brick &br, const HeatArgs &a, const double *ps, double *H)
+{
+    br.gather27(ps, H);
+    interp3(H);
+    if (HK == 1) {
+        for (int q = 0; q < 27; ++q) { // out of line, not unrolled (as in heat_cell_coeffs)
+            double dH;
+            H[q] = heaviside_sine(a.eps, H[q], &dH);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) H[q] = heaviside_linear<double>(H[q]);
+    }
+}
+
+// The convective heat operator on one cell (or its transpose, TR), in place
+// on u (nodal x in, nodal y out); ps is the brick's staged phi, us its
+// staged velocity components.  The coefficients rc W and k W are evaluated
+// from H(phi) where they are used, and the passes are ordered so that at
+// most three 27-vectors are live besides the one being formed:
+//   A:   cv = u0 . grad u;  H;  acc = rc W (alpha_m u + alpha_c cv);  acc += conduction
+//   A^T: H;  acc = conduction;  z = rc W u;  acc += alpha_m z + alpha_c sum_d D_d^T (u0_d z)
+template <bool TR, int HK>
+__device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMesh &m, const HeatArgs &a,
+                                                     const double *ps, const double *us, double *u)
+{
+    const double vol = m.hx * m.hy * m.hz;
+    const double h[3] = {m.hx, m.hy, m.hz};
+    interp3(u);
+    double acc[27], v[27]; // v: a velocity component, then H
+    auto velocity = [&](int d) {
+        // read and interpolate each component where it is used, and keep the
+        // derivatives of u from being formed ahead of it
+        pin27(acc);
+        pin27(u);
+        br.gather27(us + d * BNB, v);
+        interp3(v);
     };
-    dir(std::integral_constant<int, 0>{});
-    dir(std::integral_constant<int, 1>{});
-    dir(std::integral_constant<int, 2>{});
+    auto conduction = [&](const ClassCoef &ckw) {
+        grad_line_apply<double, 0>(u, ckw, 1.0 / (h[0] * h[0]), acc);
+        grad_line_apply<double, 1>(u, ckw, 1.0 / (h[1] * h[1]), acc);
+        grad_line_apply<double, 2>(u, ckw, 1.0 / (h[2] * h[2]), acc);
+    };
+#pragma unroll
+    for (int q = 0; q < 27; ++q) acc[q] = 0.0;
+    if (!TR) {
+        velocity(0);
+        vel_grad_acc<double, 0>(u, v, 1.0 / (kR * h[0]), acc);
+        velocity(1);
+        vel_grad_acc<double, 1>(u, v, 1.0 / (kR * h[1]), acc);
+        velocity(2);
+        vel_grad_acc<double, 2>(u, v, 1.0 / (kR * h[2]), acc);
+        pin27(acc);
+        cell_heaviside<HK>(br, a, ps, v);
+        const ClassCoef rcw(v, vol, a.rc_g, a.rc_l);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) acc[q] = rcw[q] * (a.am * u[q] + a.ac * acc[q]);
+        const ClassCoef ckw(v, a.ak * vol / (kR * kR), a.k_g, a.k_l);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) v[q] = ckw[q]; // H -> k W, in place
+        pin27(v);
+        pin27(u);
+        pin27(acc);
+        grad_line_apply<double, 0>(u, v, 1.0 / (h[0] * h[0]), acc);
+        grad_line_apply<double, 1>(u, v, 1.0 / (h[1] * h[1]), acc);
+        grad_line_apply<double, 2>(u, v, 1.0 / (h[2] * h[2]), acc);
+    } else {
+        cell_heaviside<HK>(br, a, ps, v);
+        conduction(ClassCoef(v, a.ak * vol / (kR * kR), a.k_g, a.k_l));
+        const ClassCoef rcw(v, vol, a.rc_g, a.rc_l);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            u[q] *= rcw[q];
+            acc[q] += a.am * u[q];
+        }
+        velocity(0);
+        vel_gradT_acc<double, 0>(u, v, a.ac / (kR * h[0]), acc);
+        velocity(1);
+        vel_gradT_acc<double, 1>(u, v, a.ac / (kR * h[1]), acc);
+        velocity(2);
+        vel_gradT_acc<double, 2>(u, v, a.ac / (kR * h[2]), acc);
+    }
     interp3T(acc);
 #pragma unroll
     for (int q = 0; q < 27; ++q) u[q] = acc[q];
@@ -158,20 +247,13 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     __syncthreads();
 
     const T vol = T(m.hx * m.hy * m.hz);
-    const T am_w = CONV ? vol : T(a.am) * vol; // the convective form applies alpha_m itself
+    const T am_w = T(a.am) * vol;
     const T ak_w = T(a.ak) * vol / T(kR * kR);
     const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T u[27];
     if constexpr (CONV != 0) {
-        double rcw[27], ck[27];
-        {
-            double ph[27];
-            br.gather27(ps, ph);
-            interp3(ph);
-            heat_cell_coeffs<double, 0, HK>(a, ph, nullptr, nullptr, am_w, ak_w, rcw, ck);
-        }
         br.gather27_dirichlet(m, xs, u);
-        heat_conv_cell_apply<CONV == 2>(br, m, ps + BNB, u, rcw, ck, a.am, a.ac);
+        heat_conv_cell_apply<CONV == 2, HK>(br, m, a, ps, ps + BNB, u);
     } else {
         T cm[27], ck[27];
         if (MODE == 0) {

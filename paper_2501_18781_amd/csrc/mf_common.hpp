@@ -158,8 +158,8 @@ template <typename T, int DIR> __device__ __forceinline__ void derivT_acc_dir(co
 
 // Along direction DIR, line by line: t = ih D' u, g = c .* t, acc += D'^T g.
 // Working on one 3-point line at a time keeps only 3 temporaries live.
-template <typename T, int DIR>
-__device__ __forceinline__ void grad_line_apply(const T *u, const T *c, T ih, T *acc)
+template <typename T, int DIR, typename C>
+__device__ __forceinline__ void grad_line_apply(const T *u, const C &c, T ih, T *acc)
 {
 #pragma unroll
     for (int n = 0; n < 3; ++n)
@@ -189,6 +189,37 @@ __device__ __forceinline__ void conv_forward(const T *u, const T *rw, const T *w
             acc[i0] += s * rw[i0] * w[i0] * t0;
             acc[i1] += s * rw[i1] * w[i1] * t1;
             acc[i2] += s * rw[i2] * w[i2] * t2;
+        }
+}
+
+// Velocity component DIR times the derivative along DIR, accumulated:
+// cv += s w .* (D'_DIR u), line by line.
+template <typename T, int DIR>
+__device__ __forceinline__ void vel_grad_acc(const T *u, const T *w, T s, T *cv)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            T t0, t1, t2;
+            Q2<T>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
+            cv[i0] += s * w[i0] * t0;
+            cv[i1] += s * w[i1] * t1;
+            cv[i2] += s * w[i2] * t2;
+        }
+}
+
+// Its transpose: acc += D'_DIR^T (s w .* z), line by line.
+template <typename T, int DIR>
+__device__ __forceinline__ void vel_gradT_acc(const T *z, const T *w, T s, T *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            Q2<T>::derivT_acc(s * w[i0] * z[i0], s * w[i1] * z[i1], s * w[i2] * z[i2], acc[i0], acc[i1], acc[i2]);
         }
 }
 
