@@ -56,11 +56,12 @@ struct Brick {
     int bx, by, bz;    // brick coordinates
     int c0x, c0y, c0z; // first cell of the brick
     int ncx, ncy, ncz; // valid cells per direction (clipped at the mesh end)
+    int t;             // this thread's cell slot within the brick (0..63)
     int tx, ty, tz;    // this thread's cell within the brick
     bool valid;
     bool lastx, lasty, lastz;
 
-    __device__ __forceinline__ Brick(const KMesh &m, int t)
+    __device__ __forceinline__ Brick(const KMesh &m, int slot) : t(slot)
     {
         // XCD-contiguous numbering: workgroup b runs on XCD b % 8; XCD k gets
         // bricks [start_k, start_k + count_k).
@@ -222,7 +223,6 @@ struct Brick {
     // Cell results, node-major: E[local * BNT + thread]; zero without a cell.
     template <typename T> __device__ __forceinline__ void store_cell(T *E, const T *v) const
     {
-        const int t = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < 27; ++i) E[i * BNT + t] = valid ? v[i] : T(0);
     }
@@ -233,7 +233,6 @@ struct Brick {
     // missing neighbour (brick edge) reads this cell's slot, weighted by 0.
     template <typename T> __device__ __forceinline__ T node_sum(const T *E, int a, int b, int c) const
     {
-        const int t = threadIdx.x;
         T s = E[(a + 3 * b + 9 * c) * BNT + t];
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)

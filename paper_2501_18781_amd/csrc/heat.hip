@@ -119,15 +119,6 @@ struct ClassCoef {
     }
 };
 
-// Ordering point: all 27 values of v are computed before it and no memory
-// access moves across it (keeps the passes of a cell from being merged into
-// one long live range).
-__device__ __forceinline__ void pin27(double *v)
-{
-#pragma unroll
-    for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(v[i])::"memory");
-}
-
 // H(phi) at the Gauss points of this thread's cell, phi from the LDS brick.
 template <int HK>
 __device__ __forceinline__ void cell_heaviside(const Brick &br, const HeatArgs &a, const double *ps, double *H)

@@ -172,6 +172,16 @@ __device__ __forceinline__ void grad_line_apply(const T *u, const C &c, T ih, T 
         }
 }
 
+// Ordering point: all 27 values of v are computed before it and no memory
+// access moves across it.  Placed at the phase boundaries of a cell's
+// computation, it keeps the compiler from forming later passes early and
+// merging them into one long live range.
+__device__ __forceinline__ void pin27(double *v)
+{
+#pragma unroll
+    for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(v[i])::"memory");
+}
+
 // Convection along DIR, line by line, with t = D'_DIR u the collocation derivative:
 // forward, acc += s rw .* w .* t; transposed, acc += D'_DIR^T (s rw .* w .* u).
 // (rw: coefficient times quadrature weight, w: velocity component DIR at the

@@ -8,10 +8,10 @@
 // (the last term equals 2 mu eps(u):eps(v)).  The transpose moves the
 // convective term onto the test function: alpha_c rho u_c (u0.grad) v_c.
 //
-// Work decomposition: one launch per velocity component c, a 64-thread
-// workgroup per brick of 4x4x4 cells (brick.hpp), one thread per cell.
-// Nodal x (3 components), u0 (3 components) and phi are staged in LDS.
-// Per cell and component:
+// Work decomposition: one workgroup of three wavefronts per brick of 4x4x4
+// cells (brick.hpp); wavefront c takes velocity component c, one thread per
+// cell.  Nodal x (3 components), u0 (3 components) and phi are staged in LDS
+// once for the three.  Per cell and component:
 //   acc = alpha_m rho W u_c                                  (Gauss values)
 //       + alpha_c rho W sum_d u0_d d_d u_c                   (forward)
 //   acc += sum_d D_d^T [ W mu alpha_v (d_d u_c + d_c u_d)    (viscous)
@@ -115,17 +115,22 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
     for (int q = 0; q < 27; ++q) acc[q] = a.am * rw[q] * u[q];
     {
         double w[27];
-        br.gather27(u0s, w);
-        interp3(w);
+        auto velocity = [&](int d) {
+            pin27(acc);
+            pin27(u);
+            br.gather27(u0s + d * BNB, w);
+            interp3(w);
+        };
+        velocity(0);
         conv_any<0>(TR, u, rw, w, a.ac * sdir[0], acc);
-        br.gather27(u0s + BNB, w);
-        interp3(w);
+        velocity(1);
         conv_any<1>(TR, u, rw, w, a.ac * sdir[1], acc);
-        br.gather27(u0s + 2 * BNB, w);
-        interp3(w);
+        velocity(2);
         conv_any<2>(TR, u, rw, w, a.ac * sdir[2], acc);
     }
     // viscosity nu = alpha_v W mu (overwrites rho W, no longer needed)
+    pin27(acc);
+    pin27(u);
     double *nu = rw;
     br.gather27(ps, nu);
     interp3(nu);
@@ -138,6 +143,9 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
         if (d == C) {
             visc_dir<d, true>(u, nu, nullptr, sdir[d], acc);
         } else {
+            pin27(acc);
+            pin27(u);
+            pin27(nu);
             br.gather27(us + d * BNB, e);
             interp3(e);
             deriv_inplace<C>(e, sdir[C]); // d_C u_d
@@ -150,33 +158,35 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
     interp3T(acc);
 }
 
-template <int C, int HK, bool TR>
-__global__ void __launch_bounds__(BNT) oseen_apply_kernel(KMesh m, OseenArgs a, const double *__restrict__ x,
+// One workgroup of three wavefronts per brick: wave c computes velocity
+// component c of every cell, from one shared staging of phi, x and u0.
+template <int HK, bool TR>
+__global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, const double *__restrict__ x,
                                                           double *__restrict__ y, double *__restrict__ face)
 {
     // staging: phi, x (3 components), u0 (3 components); then the cell
-    // contributions of component C
-    constexpr int STAGE = 7 * BNB;
-    __shared__ double lds[STAGE];
-    const Brick br(m, threadIdx.x);
+    // contributions of the 3 components
+    constexpr int STAGE = 7 * BNB, CONTRIB = 3 * 27 * BNT;
+    __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
+    const int comp = threadIdx.x / BNT; // uniform over a wavefront
+    const Brick br(m, threadIdx.x % BNT);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
     double *ps = lds, *us = lds + BNB, *u0s = lds + 4 * BNB;
-    br.load(m, a.phi, ps, false);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        br.load(m, x + c * nn, us + c * BNB, true);
-        br.load(m, a.u0 + c * nn, u0s + c * BNB, false);
-    }
+    if (comp == 0) br.load(m, a.phi, ps, false);
+    br.load(m, x + comp * nn, us + comp * BNB, true);
+    br.load(m, a.u0 + comp * nn, u0s + comp * BNB, false);
     __syncthreads();
     double acc[27];
-    oseen_cell<C, HK, TR>(br, a, m, ps, us, u0s, acc);
-    __syncthreads();
-    double *E = lds;
+    if (comp == 0) oseen_cell<0, HK, TR>(br, a, m, ps, us, u0s, acc);
+    else if (comp == 1) oseen_cell<1, HK, TR>(br, a, m, ps, us, u0s, acc);
+    else oseen_cell<2, HK, TR>(br, a, m, ps, us, u0s, acc);
+    __syncthreads(); // staging no longer read
+    double *E = lds + comp * 27 * BNT;
     br.store_cell(E, acc);
     __syncthreads();
-    double *fb = face + ((int64_t)C * n_bricks(m) + br.brick) * BFACE;
-    double *yc = y + C * nn;
-    const double *xc = x + C * nn;
+    double *fb = face + ((int64_t)comp * n_bricks(m) + br.brick) * BFACE;
+    double *yc = y + comp * nn;
+    const double *xc = x + comp * nn;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double s = br.node_sum(E, ai, bi, ci);
         double *dst = sh ? fb + br.fslot(ai, bi, ci, l) : yc + g;
@@ -209,17 +219,10 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
     double *fb = (double *)face;
     const int key = (a.hkind ? 2 : 0) | (transpose ? 1 : 0);
     switch (key) {
-#define OSEEN_CASE(K, HK, TR)                                                                                 \
-    case K:                                                                                                   \
-        oseen_apply_kernel<0, HK, TR><<<nb, BNT, 0, s>>>(m, a, x, y, fb);                                     \
-        oseen_apply_kernel<1, HK, TR><<<nb, BNT, 0, s>>>(m, a, x, y, fb);                                     \
-        oseen_apply_kernel<2, HK, TR><<<nb, BNT, 0, s>>>(m, a, x, y, fb);                                     \
-        break;
-        OSEEN_CASE(0, 0, false)
-        OSEEN_CASE(1, 0, true)
-        OSEEN_CASE(2, 1, false)
-        OSEEN_CASE(3, 1, true)
-#undef OSEEN_CASE
+    case 0: oseen_apply_kernel<0, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 1: oseen_apply_kernel<0, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 2: oseen_apply_kernel<1, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 3: oseen_apply_kernel<1, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
