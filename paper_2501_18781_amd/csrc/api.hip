@@ -508,12 +508,12 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
             HIPCHK(c, prec(V + (int64_t)j * ld, zt));
             HIPCHK(c, apply_any(c, op, transpose, zt, w, s));
             ++total;
-            // two passes of classical Gram-Schmidt
+            // two passes of classical Gram-Schmidt: the first update and the
+            // second projection share one read of V (three passes, not four)
             double *hd = c->scal;
             HIPCHK(c, vmultidot(V, ld, j + 1, w, n, hd, &red, s));
-            HIPCHK(c, vmultiaxpy(V, ld, j + 1, hd, w, n, nullptr, &red, s));
+            HIPCHK(c, vmultiaxpy_dot(V, ld, j + 1, hd, w, n, hd + 64, &red, s));
             HIPCHK(c, hipMemcpyAsync(c->h_scal, hd, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-            HIPCHK(c, vmultidot(V, ld, j + 1, w, n, hd + 64, &red, s));
             HIPCHK(c, vmultiaxpy(V, ld, j + 1, hd + 64, w, n, hd + 128, &red, s));
             HIPCHK(c, hipMemcpyAsync(c->h_scal + 64, hd + 64, sizeof(double) * 65, hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));

@@ -97,6 +97,9 @@ hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64
 // w -= sum_k V_k h[k] (h device), optionally out_norm2 = ||w||^2 after the update.
 hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n,
                       double *out_norm2, const RedWS *red, hipStream_t s);
+// w -= V h, then out = V^T w (nv <= 32), in one pass over V.
+hipError_t vmultiaxpy_dot(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out,
+                          const RedWS *red, hipStream_t s);
 // y = sum_k V_k h[k] (h device)
 hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double *y, int64_t n, hipStream_t s);
 hipError_t block3_invert(double *blocks, int64_t nn, hipStream_t s);

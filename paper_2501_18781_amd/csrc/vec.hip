@@ -203,25 +203,41 @@ hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Multi-dot, multi-axpy, combination (GMRES Gram-Schmidt)
+// Multi-dot, multi-axpy, combination (GMRES Gram-Schmidt).  The number of
+// vectors NV is a template parameter (1..32, chosen by a switch), so that
+// every loop over the vectors is unrolled without conditions and all NV
+// loads of an element are in flight together.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(VNT) multidot_kernel(const double *__restrict__ V, int64_t ld, int nv,
-                                                       const double *__restrict__ w, int64_t n, double *out, RedWS red)
+#define MF_NV_CASES(X)                                                                                      \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+        X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+// Block partials of NV sums: set k of the partials holds block b at k * gridDim.x + b.
+template <int NV> __device__ __forceinline__ void store_block_partials(double *acc, double *lds, const RedWS &red)
 {
-    __shared__ double lds[MAXV * (VNT / 64)];
-    double acc[MAXV];
+    block_sum_n<NV>(acc, lds);
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < MAXV; ++k) acc[k] = 0.0;
+        for (int k = 0; k < NV; ++k) red.partials[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
+    }
+}
+
+// out_k = V_k . w
+template <int NV>
+__global__ void __launch_bounds__(VNT) multidot_kernel(const double *__restrict__ V, int64_t ld,
+                                                       const double *__restrict__ w, int64_t n, RedWS red)
+{
+    __shared__ double lds[NV * (VNT / 64)];
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
     GRID_STRIDE(i, n)
     {
         const double wi = w[i];
 #pragma unroll
-        for (int k = 0; k < MAXV; ++k)
-            if (k < nv) acc[k] += V[(int64_t)k * ld + i] * wi;
+        for (int k = 0; k < NV; ++k) acc[k] += V[(int64_t)k * ld + i] * wi;
     }
-    block_sum_n<MAXV>(acc, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < nv; ++k) red.partials[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
+    store_block_partials<NV>(acc, lds, red);
 }
 
 hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out, const RedWS *red,
@@ -230,28 +246,39 @@ hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64
     if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
     const unsigned nb = vec_blocks(n);
     if (red->capacity < nb * MAXV) return hipErrorInvalidValue;
-    multidot_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, w, n, out, *red);
+    switch (nv) {
+#define MF_CASE(N)                                                                                            \
+    case N: multidot_kernel<N><<<nb, VNT, 0, s>>>(V, ld, w, n, *red); break;
+        MF_NV_CASES(MF_CASE)
+#undef MF_CASE
+    }
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
 }
 
-__global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict__ V, int64_t ld, int nv,
-                                                        const double *__restrict__ h, double *__restrict__ w, int64_t n,
-                                                        double *out_norm2, RedWS red)
+// w -= V h; optionally ||w||^2 of the result
+template <int NV>
+__global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict__ V, int64_t ld,
+                                                        const double *__restrict__ h, double *__restrict__ w,
+                                                        int64_t n, bool norm, RedWS red)
 {
     __shared__ double lds[VNT / 64];
-    __shared__ double hs[MAXV];
-    if (threadIdx.x < MAXV) hs[threadIdx.x] = threadIdx.x < (unsigned)nv ? h[threadIdx.x] : 0.0;
+    __shared__ double hs[NV];
+    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
     __syncthreads();
     double acc = 0.0;
     GRID_STRIDE(i, n)
     {
+        double vk[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vk[k] = V[(int64_t)k * ld + i];
         double v = w[i];
-        for (int k = 0; k < nv; ++k) v -= V[(int64_t)k * ld + i] * hs[k];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v -= vk[k] * hs[k];
         w[i] = v;
         acc += v * v;
     }
-    if (out_norm2) grid_partials<1>(&acc, red, lds);
+    if (norm) grid_partials<1>(&acc, red, lds);
 }
 
 hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out_norm2,
@@ -260,22 +287,81 @@ hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, doub
     if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
     const unsigned nb = vec_blocks(n);
     if (out_norm2 && red->capacity < nb) return hipErrorInvalidValue;
-    multiaxpy_kernel<<<nb, VNT, 0, s>>>(V, ld, nv, h, w, n, out_norm2, red ? *red : RedWS{nullptr, 0});
+    const RedWS r = red ? *red : RedWS{nullptr, 0};
+    const bool norm = out_norm2 != nullptr;
+    switch (nv) {
+#define MF_CASE(N)                                                                                            \
+    case N: multiaxpy_kernel<N><<<nb, VNT, 0, s>>>(V, ld, h, w, n, norm, r); break;
+        MF_NV_CASES(MF_CASE)
+#undef MF_CASE
+    }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !out_norm2) return e;
+    if (e != hipSuccess || !norm) return e;
     return sum_finalize(*red, nb, 1, out_norm2, s);
 }
 
-__global__ void combine_kernel(const double *__restrict__ V, int64_t ld, int nv, const double *__restrict__ h,
+// w -= V h and, in the same pass, g = V^T w (the new w): the first update
+// and the second projection of classical Gram-Schmidt applied twice share
+// one read of V.
+template <int NV>
+__global__ void __launch_bounds__(VNT) multiaxpy_dot_kernel(const double *__restrict__ V, int64_t ld,
+                                                            const double *__restrict__ h, double *__restrict__ w,
+                                                            int64_t n, RedWS red)
+{
+    __shared__ double lds[NV * (VNT / 64)];
+    __shared__ double hs[NV];
+    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        double vk[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vk[k] = V[(int64_t)k * ld + i];
+        double v = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v -= vk[k] * hs[k];
+        w[i] = v;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += vk[k] * v;
+    }
+    store_block_partials<NV>(acc, lds, red);
+}
+
+hipError_t vmultiaxpy_dot(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out,
+                          const RedWS *red, hipStream_t s)
+{
+    if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < nb * MAXV) return hipErrorInvalidValue;
+    switch (nv) {
+#define MF_CASE(N)                                                                                            \
+    case N: multiaxpy_dot_kernel<N><<<nb, VNT, 0, s>>>(V, ld, h, w, n, *red); break;
+        MF_NV_CASES(MF_CASE)
+#undef MF_CASE
+    }
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
+}
+
+// y = V h
+template <int NV>
+__global__ void combine_kernel(const double *__restrict__ V, int64_t ld, const double *__restrict__ h,
                                double *__restrict__ y, int64_t n)
 {
-    __shared__ double hs[MAXV];
-    if (threadIdx.x < MAXV) hs[threadIdx.x] = threadIdx.x < (unsigned)nv ? h[threadIdx.x] : 0.0;
+    __shared__ double hs[NV];
+    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
     __syncthreads();
     GRID_STRIDE(i, n)
     {
+        double vk[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vk[k] = V[(int64_t)k * ld + i];
         double v = 0.0;
-        for (int k = 0; k < nv; ++k) v += V[(int64_t)k * ld + i] * hs[k];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v += vk[k] * hs[k];
         y[i] = v;
     }
 }
@@ -283,9 +369,17 @@ __global__ void combine_kernel(const double *__restrict__ V, int64_t ld, int nv,
 hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double *y, int64_t n, hipStream_t s)
 {
     if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
-    combine_kernel<<<ew_blocks(n), VNT, 0, s>>>(V, ld, nv, h, y, n);
+    const unsigned g = ew_blocks(n);
+    switch (nv) {
+#define MF_CASE(N)                                                                                            \
+    case N: combine_kernel<N><<<g, VNT, 0, s>>>(V, ld, h, y, n); break;
+        MF_NV_CASES(MF_CASE)
+#undef MF_CASE
+    }
     return hipGetLastError();
 }
+
+#undef MF_NV_CASES
 
 // ---------------------------------------------------------------------------
 // 3x3 nodal blocks ([node][3][3], row-major): inversion by cofactors and
