@@ -815,3 +815,95 @@ void orc_load_vector(const orc_mesh *m, const double *fq, double *b)
                 }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Interface heat sources (Sec. 2.4, Sec. 4)                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t terms;        /* bit 0: evaporative cooling, bit 1: laser heat flux */
+    int32_t pad_;
+    double evap_coeff;    /* evaporation coefficient of the Tanasawa model, 0 < . <= 1 */
+    double molar_mass;    /* M, kg/mol; specific gas constant R/M */
+    double vapor_density; /* vapor density in the Tanasawa coefficient */
+    double T_boil;        /* boiling temperature T_v */
+    double h_v;           /* latent heat of evaporation */
+    double power, absorptivity, radius; /* laser P_L, chi_L, r_L */
+    double focus[3];      /* a point of the beam axis */
+    double dir[3];        /* unit beam direction e_L */
+} orc_sources;
+
+/* Right-hand side of the heat equation from the interface fluxes,
+ *   b_i = sum_cells sum_q W_q N_i(x_q) [ s_evap(x_q) + q_laser(x_q) ],
+ * with, at each quadrature point (phi, grad phi and T interpolated from the
+ * nodes):
+ *   delta     = |grad H(phi)| = H'(phi) |grad phi|                 (eq. delta)
+ *   delta_rcp = delta rc(phi) c_rcp, c_rcp = 3 / (rc_g^2 + rc_l rc_g + rc_l^2)
+ *                                                                (eq. deltaRhoCp)
+ *   mdot      = alpha_v (T - T_v),                              (eq. mDotTanasawa)
+ *   alpha_v   = 2 gamma / (2 - gamma) h_v / sqrt(2 pi R/M) rho_v / T_v^{3/2}
+ *   s_evap    = -mdot h_v delta_rcp                          (eq. vapor_heat_loss)
+ *   n         = -grad phi / |grad phi| (from the liquid, phi > 0, into the gas)
+ *   q_laser   = 2 chi P / (pi r^2) <-n . e_L> exp(-2 d_L^2 / r^2) delta_rcp
+ *                                                                (eq. laser_gauss)
+ * d_L the distance of x_q from the beam axis.  Dirichlet nodes get 0.  The
+ * temperature enters at the quadrature point itself (local temperature). */
+void orc_heat_sources(const orc_mesh *m, const orc_coeffs *cf, const orc_sources *src, const double *phi,
+                      const double *T, double *b)
+{
+    const int64_t nn = nnodes(m);
+    memset(b, 0, sizeof(double) * nn);
+    const double Rgas = 8.314;
+    const double gam = src->evap_coeff;
+    const double alpha_v = 2.0 * gam / (2.0 - gam) * src->h_v / sqrt(2.0 * M_PI * Rgas / src->molar_mass) *
+                           src->vapor_density / pow(src->T_boil, 1.5);
+    const double c_rcp = 3.0 / (cf->rc_g * cf->rc_g + cf->rc_l * cf->rc_g + cf->rc_l * cf->rc_l);
+    const double peak = 2.0 * src->absorptivity * src->power / (M_PI * src->radius * src->radius);
+    for (int color = 0; color < 8; ++color) {
+        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
+#pragma omp parallel for collapse(3) schedule(dynamic, 16)
+        for (int cz = pz; cz < m->n[2]; cz += 2)
+            for (int cy = py; cy < m->n[1]; cy += 2)
+                for (int cx = px; cx < m->n[0]; cx += 2) {
+                    double X[8][3];
+                    int64_t idx[27];
+                    cell_vertices(m, cx, cy, cz, X);
+                    cell_nodes(m, cx, cy, cz, idx);
+                    qp_data Q;
+                    for (int q = 0; q < 27; ++q) {
+                        cell_qp(X, q, &Q);
+                        double ph = 0.0, Tq = 0.0, g[3] = {0.0, 0.0, 0.0};
+                        for (int j = 0; j < 27; ++j) {
+                            ph += Q.N[j] * phi[idx[j]];
+                            Tq += Q.N[j] * T[idx[j]];
+                            for (int d = 0; d < 3; ++d) g[d] += Q.G[j][d] * phi[idx[j]];
+                        }
+                        double dH;
+                        const double H = heaviside(cf->heaviside, cf->eps, ph, &dH);
+                        const double gnorm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                        const double delta = dH * gnorm;
+                        const double delta_rcp = delta * blend_arith(H, cf->rc_l, cf->rc_g) * c_rcp;
+                        double s = 0.0;
+                        if (src->terms & 1) s += -alpha_v * (Tq - src->T_boil) * src->h_v * delta_rcp;
+                        if ((src->terms & 2) && gnorm > 0.0) {
+                            double n_dot_e = 0.0, r[3], t = 0.0;
+                            for (int d = 0; d < 3; ++d) {
+                                n_dot_e += -g[d] / gnorm * src->dir[d];
+                                r[d] = Q.x[d] - src->focus[d];
+                                t += r[d] * src->dir[d];
+                            }
+                            double dl2 = 0.0;
+                            for (int d = 0; d < 3; ++d) {
+                                const double p = r[d] - t * src->dir[d];
+                                dl2 += p * p;
+                            }
+                            const double mac = -n_dot_e > 0.0 ? -n_dot_e : 0.0;
+                            s += peak * mac * exp(-2.0 * dl2 / (src->radius * src->radius)) * delta_rcp;
+                        }
+                        for (int i = 0; i < 27; ++i) b[idx[i]] += Q.W * Q.N[i] * s;
+                    }
+                }
+    }
+    for (int64_t i = 0; i < nn; ++i)
+        if (node_constrained(m, i)) b[i] = 0.0;
+}

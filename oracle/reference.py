@@ -60,7 +60,7 @@ def lib():
                      "orc_heat_cell_matrix", "orc_oseen_cell_matrix", "orc_csr_cols",
                      "orc_assemble_heat", "orc_assemble_oseen", "orc_spmv", "orc_heat_rows",
                      "orc_oseen_rows", "orc_quad_points", "orc_heat_qp_coeffs", "orc_heat_grad",
-                     "orc_load_vector"]:
+                     "orc_load_vector", "orc_heat_sources"]:
             getattr(L, name).restype = None
         L.orc_basis1d.argtypes = [D, P, P]
         L.orc_heaviside.argtypes = [ctypes.c_int32, D, P, P, P, I64]
@@ -627,3 +627,36 @@ def flexible_cg(A, b, precond, rtol=1e-8, maxit=1000, matvec=None) -> SolveResul
         p = z + beta * p
     true = np.linalg.norm(b - mv(x)) / bn
     return SolveResult(x, it, true, conv, hist)
+
+
+# ---------------------------------------------------------------------------
+# Interface heat sources
+# ---------------------------------------------------------------------------
+
+class OSources(ctypes.Structure):
+    _fields_ = [("terms", ctypes.c_int32), ("pad_", ctypes.c_int32), ("evap_coeff", ctypes.c_double),
+                ("molar_mass", ctypes.c_double), ("vapor_density", ctypes.c_double), ("T_boil", ctypes.c_double),
+                ("h_v", ctypes.c_double), ("power", ctypes.c_double), ("absorptivity", ctypes.c_double),
+                ("radius", ctypes.c_double), ("focus", ctypes.c_double * 3), ("dir", ctypes.c_double * 3)]
+
+
+def osources(sp) -> OSources:
+    o = OSources()
+    o.terms = int(sp.terms)
+    for name in ["evap_coeff", "molar_mass", "vapor_density", "T_boil", "h_v", "power", "absorptivity", "radius"]:
+        setattr(o, name, float(getattr(sp, name)))
+    for d in range(3):
+        o.focus[d] = float(sp.focus[d])
+        o.dir[d] = float(sp.dir[d])
+    return o
+
+
+def heat_sources(mesh, params, sources, phi, T, **override) -> np.ndarray:
+    """Heat right-hand side of the interface fluxes (evaporative cooling and the
+    laser heat flux) from nodal phi and T; zero on Dirichlet nodes."""
+    m = omesh(mesh)
+    c = ocoeffs(params, **override)
+    s = osources(sources)
+    b = np.zeros(n_nodes(mesh))
+    lib().orc_heat_sources(ctypes.byref(m), ctypes.byref(c), ctypes.byref(s), _p(_f64(phi)), _p(_f64(T)), _p(b))
+    return b

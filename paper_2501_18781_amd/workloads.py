@@ -169,6 +169,50 @@ def heat_sphere_workload(n: int, dirichlet: int, params: HeatParams | None = Non
     return HeatWorkload(mesh, p, phi_sphere(mesh, 0.3, eps), eps)
 
 
+@dataclass(frozen=True)
+class SourceParams:
+    """Interface heat sources: evaporative cooling (Tanasawa mass flux) and a
+    Gaussian laser heat flux.  Material and laser values of the Ti-6Al-4V
+    melt-pool setup (molar mass, boiling point, latent heat, vapor density;
+    laser power and absorptivity); lengths are in units of the unit cube.
+
+    terms: bit 0 evaporative cooling, bit 1 laser heat flux."""
+
+    terms: int = 3
+    evap_coeff: float = 1.0
+    molar_mass: float = 4.78e-2
+    vapor_density: float = 4.087
+    T_boil: float = 3133.0
+    h_v: float = 8.84e6
+    power: float = 78.0
+    absorptivity: float = 0.35
+    radius: float = 0.1
+    focus: tuple = (0.5, 0.5, 1.0)
+    dir: tuple = (0.0, 0.0, -1.0)
+
+
+@dataclass
+class HeatSourceWorkload:
+    mesh: Mesh
+    params: HeatParams
+    sources: SourceParams
+    phi: np.ndarray
+    T: np.ndarray
+    eps: float
+
+
+def heat_source_workload(n: int, dirichlet: int, params: HeatParams | None = None,
+                         sources: SourceParams | None = None) -> HeatSourceWorkload:
+    """Interface heat sources on the sphere level set of heat_sphere_workload,
+    with a temperature field around the boiling point that peaks under the
+    beam: T = T_v + 600 K exp(-((x-1/2)^2 + (y-1/2)^2) / 0.05) (z - 0.3)."""
+    wl = heat_sphere_workload(n, dirichlet, params)
+    sp = sources or SourceParams()
+    x = node_coords(wl.mesh)
+    T = sp.T_boil + 600.0 * np.exp(-((x[:, 0] - 0.5) ** 2 + (x[:, 1] - 0.5) ** 2) / 0.05) * (x[:, 2] - 0.3)
+    return HeatSourceWorkload(wl.mesh, wl.params, sp, wl.phi, T, wl.eps)
+
+
 @dataclass
 class HeatConvWorkload:
     mesh: Mesh

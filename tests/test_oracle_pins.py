@@ -281,7 +281,7 @@ def test_heat_convection_closed_forms_both_orientations():
     # The convective heat form c(f, g) = alpha_c int rc f (u0 . grad g) with the
     # linear field u0 = (y, 2z, 3x), f = x, g = x^2 + y^2 + z^2 (all exact in
     # Q2, integrands of degree <= 3 per direction, so the Gauss rule is exact):
-    #   f^T C g = alpha_c rc int x (2xy + 4yz + 6xz) = alpha_c rc (1/3 + 1/2 + 1)  = alpha_c rc 11/6
+    #   f^T C g = alpha_c rc int x (2xy + 4yz + 6xz) = alpha_c rc (1/3 + 1/2 + 1) = alpha_c rc 11/6
     #   g^T C f = alpha_c rc int (x^2 + y^2 + z^2) y                        = alpha_c rc 7/12
     # catches: N_i and grad N_j swapped (the two values trade places), wrong
     # sign, velocity components mixed up, u0 not interpolated at the points
@@ -314,6 +314,94 @@ def test_heat_convection_annihilates_constants_and_is_skew_with_dirichlet():
     A0 = O.heat_matrix(mesh, W.HeatParams(), phi=phi)
     assert abs((A + A.T) / 2 - A0).max() < 1e-12 * abs(A0).max()
     assert abs(A - A.T).max() > 1e-3 * abs(A0).max()
+
+
+# ---------------------------------------------------------------------------
+# Interface heat sources (evaporative cooling, laser heat flux)
+# ---------------------------------------------------------------------------
+
+# gamma = 1, R/M = 1/(2 pi), rho_v = 1/2, T_v = 1, h_v = 1 make the Tanasawa
+# coefficient 2/(2-1) * 1/sqrt(1) * (1/2)/1 = 1, so mdot = T - 1.
+UNIT_EVAP = dict(evap_coeff=1.0, molar_mass=2 * np.pi * 8.314, vapor_density=0.5, T_boil=1.0, h_v=1.0)
+
+
+def _linear_phi_case(n=(2, 3, 2), a=0.8, z0=0.5):
+    # phi = a (z0 - z) stays inside (-1, 1): H = (1 + phi)/2, H' = 1/2, |grad phi| = a,
+    # so delta = a/2 and rc = A + B z with A = rc_g + (rc_l - rc_g)(1 + a z0)/2,
+    # B = -(rc_l - rc_g) a / 2; with rc_l = 3, rc_g = 1: c_rcp = 3/13.
+    mesh = W.Mesh(n)
+    x = W.node_coords(mesh)
+    phi = a * (z0 - x[:, 2])
+    p = W.HeatParams(rc_l=3.0, rc_g=1.0, heaviside=0)
+    A, B = 1.0 + 2.0 * (1 + a * z0) / 2, -2.0 * a / 2
+    return mesh, x, phi, p, a / 2, A, B, 3.0 / 13.0
+
+
+def test_evaporative_cooling_closed_forms():
+    # s = -mdot h_v delta rc c_rcp with mdot = tau: linear in z, so the Gauss
+    # rule integrates the moments exactly:
+    #   sum b = int s,  sum b z = int z s,  sum b x = int x s = (1/2) int s
+    # catches: a wrong Tanasawa coefficient, delta without |grad phi|, the
+    # blend of rc, z and x mixed up
+    mesh, x, phi, p, delta, A, B, c = _linear_phi_case()
+    tau = 2.0
+    sp = W.SourceParams(terms=1, **UNIT_EVAP)
+    b = O.heat_sources(mesh, p, sp, phi, np.full(mesh.n_nodes, 1.0 + tau))
+    k = -tau * delta * c
+    assert abs(b.sum() - k * (A + B / 2)) < 1e-13
+    assert abs(b @ x[:, 2] - k * (A / 2 + B / 3)) < 1e-13
+    assert abs(b @ x[:, 0] - k * (A + B / 2) / 2) < 1e-13
+    # linear in T - T_v, zero at the boiling point
+    b2 = O.heat_sources(mesh, p, sp, phi, np.full(mesh.n_nodes, 1.0 + 2 * tau))
+    assert np.abs(b2 - 2 * b).max() < 1e-13 * np.abs(b).max()
+    # (at T = T_v the interpolated T - T_v is a rounding residue)
+    assert np.abs(O.heat_sources(mesh, p, sp, phi, np.ones(mesh.n_nodes))).max() < 1e-14 * np.abs(b).max()
+
+
+def test_laser_flux_side_and_power():
+    # flat liquid surface (phi > 0 below z0), normal n = -grad phi/|grad phi| = +e_z:
+    # a beam pointing down (e_L = -e_z) is absorbed, one pointing up is not;
+    # the absorbed power of a beam well inside the box is chi P (int delta_rcp dz)
+    #   = chi P delta c (A + B/2) per unit area, with the Gaussian integrating to
+    #   pi r^2 / 2 (tails beyond the box ~ exp(-50)); the centroid of b is the focus.
+    mesh, x, phi, p, delta, A, B, c = _linear_phi_case(n=(2, 2, 2))
+    up = W.SourceParams(terms=2, dir=(0.0, 0.0, 1.0))
+    assert np.abs(O.heat_sources(mesh, p, up, phi, np.zeros(mesh.n_nodes))).max() == 0.0
+    errs = []
+    for n in (8, 16, 32):
+        mesh, x, phi, p, delta, A, B, c = _linear_phi_case(n=(n, n, 2))
+        sp = W.SourceParams(terms=2, radius=0.1, power=78.0, absorptivity=0.35, focus=(0.45, 0.55, 1.0))
+        b = O.heat_sources(mesh, p, sp, phi, np.zeros(mesh.n_nodes))
+        ref = 0.35 * 78.0 * delta * c * (A + B / 2)
+        errs.append(abs(b.sum() - ref) / ref)
+        cx, cy = (b @ x[:, 0]) / b.sum(), (b @ x[:, 1]) / b.sum()
+    # Gauss rule on the Gaussian: fast convergence in h (3e-3, 9e-8, 5e-16 measured)
+    assert errs[2] < 1e-10 and errs[1] < errs[0] / 100 and errs[2] < errs[1] / 100, errs
+    assert abs(cx - 0.45) < 1e-10 and abs(cy - 0.55) < 1e-10
+
+
+def test_sine_delta_integrates_to_one_across_a_flat_interface():
+    # tanh profile, sine Heaviside: int delta f(H) dz = int_0^1 f(H) dH (co-area),
+    # here f = -mdot h_v rc c_rcp with mdot = 2: sum b -> -2 c (rc_l + rc_g)/2 as h -> 0
+    eps, errs = 0.04, []
+    for n in (16, 32, 64):
+        mesh = W.Mesh((1, 1, n))
+        x = W.node_coords(mesh)
+        phi = np.tanh((0.5 - x[:, 2]) / (2 * eps))
+        p = W.HeatParams(rc_l=3.0, rc_g=1.0, heaviside=1, eps=eps)
+        sp = W.SourceParams(terms=1, **UNIT_EVAP)
+        b = O.heat_sources(mesh, p, sp, phi, np.full(mesh.n_nodes, 3.0))
+        ref = -2.0 * (3.0 / 13.0) * (3.0 + 1.0) / 2
+        errs.append(abs(b.sum() - ref) / abs(ref))
+    # 3.7e-4, 6.1e-5, 1.2e-5 measured
+    assert errs[2] < 5e-5 and errs[2] < errs[1] < errs[0], errs
+
+
+def test_heat_sources_vanish_on_dirichlet_nodes():
+    wl = W.heat_source_workload(3, W.FACE_ZHI | W.FACE_XLO)
+    b = O.heat_sources(wl.mesh, wl.params, wl.sources, wl.phi, wl.T)
+    cm = O.constrained_mask(wl.mesh)
+    assert np.all(b[cm] == 0.0) and np.abs(b[~cm]).max() > 0.0
 
 
 def test_spot_rows_agree_with_assembled_matrix():
