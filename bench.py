@@ -19,7 +19,8 @@ roofline   = the apply kernel alone (events around the kernel inside the
 cpu_baseline = the CPU oracle (assembled CSR, OpenMP) on the same workload.
 mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
              both to 1e-8, on 128^3 cells (257^3 nodes).
-oseen, heat_convection, gradient = the other operators and the adjoint step.
+oseen, heat_convection, heat_sources, gradient = the other operators, the
+             interface-flux right-hand side and the adjoint step.
 """
 from __future__ import annotations
 
@@ -84,6 +85,7 @@ def parse():
     p.add_argument("--no-oseen", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-conv", action="store_true")
+    p.add_argument("--no-sources", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -360,6 +362,7 @@ def main():
     for flag, key, fn in [(args.no_mg, "mg_vs_cg", lambda: mg_vs_cg(args.mg_cells, dev)),
                           (args.no_oseen, "oseen", lambda: oseen_bench(dev)),
                           (args.no_conv, "heat_convection", lambda: heat_conv_bench(dev)),
+                          (args.no_sources, "heat_sources", lambda: heat_sources_bench(dev)),
                           (args.no_grad, "gradient", lambda: grad_bench(dev))]:
         if flag:
             continue
@@ -521,6 +524,40 @@ def heat_conv_bench(dev, applies=50):
                              "converged": bool(info.converged), "rel_err_vs_x_ref": err}
     log(f"[bench]   apply {out['apply']['us']:.1f} us (kernel {out['apply']['kernel_us']:.1f}), transpose "
         f"{out['apply_transpose']['us']:.1f} us; GMRES(30) {info.iters} it {t * 1e3:.1f} ms, err {err:.1e}")
+    return out
+
+
+def heat_sources_bench(dev, reps=50):
+    """Right-hand side of the interface heat fluxes (evaporative cooling and the
+    laser heat flux) on the 64^3 heat mesh: sphere level set, temperature
+    around the boiling point, beam along -z.  Whole assembly (kernel + shared
+    node combine), HIP events; 24 algorithmic bytes per node (phi, T, b)."""
+    import torch
+
+    from paper_2501_18781_amd import mf
+    from paper_2501_18781_amd import workloads as W
+
+    n = 64
+    wl = W.heat_source_workload(n, W.ALL_FACES)
+    nn = wl.mesh.n_nodes
+    log(f"[bench] interface heat sources {n}^3: {nn} nodes")
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    T = dev(wl.T)
+    b = torch.empty_like(T)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        mf.heat_source_rhs(op, wl.sources, T, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        mf.heat_source_rhs(op, wl.sources, T, b)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    out = {"cells": n, "nodes": nn, "us": t * 1e6, "dofs_per_s": nn / t, "algorithmic_gbs": 24 * nn / t / 1e9,
+           "terms": "evaporative cooling (Tanasawa, local T) + Gaussian laser flux"}
+    log(f"[bench]   assembly {t * 1e6:.1f} us ({24 * nn / t / 1e9:.0f} GB/s algorithmic)")
     return out
 
 

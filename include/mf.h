@@ -212,6 +212,40 @@ mf_status mf_quad_points(mf_ctx *ctx, double *xq, mf_stream stream);
  * (eqs. heaviside, muEff); n_cells*27 doubles each. */
 mf_status mf_heat_qp_coeffs(mf_ctx *ctx, const mf_operator *op, double *k_q, double *rc_q, mf_stream stream);
 
+/* ---- interface heat sources (heat right-hand side) ----------------------------- */
+
+enum { MF_SRC_EVAPORATION = 1, MF_SRC_LASER = 2 };
+
+typedef struct {
+    int32_t terms;                   /* MF_SRC_* bits */
+    double evaporation_coefficient;  /* gamma of the Tanasawa model, 0 < gamma <= 1 */
+    double molar_mass;               /* M, kg/mol (specific gas constant 8.314/M) */
+    double vapor_density;            /* vapor density in the Tanasawa coefficient, kg/m^3 */
+    double boiling_temperature;      /* T_v, K */
+    double latent_heat;              /* h_v, J/kg */
+    double laser_power;              /* P_L, W */
+    double absorptivity;             /* chi_L */
+    double laser_radius;             /* r_L, > 0 */
+    double focus[3];                 /* a point of the beam axis */
+    double direction[3];             /* e_L, unit length (within 1e-9) */
+} mf_heat_sources;
+
+/* Right-hand side of the heat equation from the interface fluxes (Sec. 2.4,
+ * Sec. 4), integrated against the Q2 basis by the Gauss rule:
+ *   b_i = sum_cells sum_q W_q N_i(x_q) s(x_q),  s = s_evap + q_laser,
+ *   s_evap  = -mdot(T) h_v delta_rcp,  mdot = alpha_v (T - T_v)   (eq. vapor_heat_loss,
+ *             alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R/M) rho_v / T_v^{3/2})  eq. mDotTanasawa)
+ *   q_laser = 2 chi P/(pi r^2) <-n . e_L> exp(-2 d_L^2/r^2) delta_rcp  (eq. laser_gauss)
+ *   delta_rcp = |grad H(phi)| rc(phi) 3/(rc_g^2 + rc_l rc_g + rc_l^2)  (eqs. delta, deltaRhoCp)
+ * with phi, grad phi and T interpolated at each quadrature point (the local
+ * temperature), n = -grad phi/|grad phi| the interface normal pointing from
+ * the liquid (phi > 0) into the gas, and d_L the distance from the beam axis.
+ * op: FP64 heat operator in LEVELSET mode (phi, Heaviside form, rc_l, rc_g).
+ * T: nodal temperature (n_nodes doubles; may be NULL without evaporation).
+ * b: n_nodes doubles, overwritten; 0 on Dirichlet nodes. */
+mf_status mf_heat_source_rhs(mf_ctx *ctx, const mf_operator *op, const mf_heat_sources *src, const double *T,
+                             double *b, mf_stream stream);
+
 /* Gradient of a loss L(T) through one implicit heat step
  * A(k, rc) T = alpha_m M(rc) T_old, given the adjoint state lambda
  * (A^T lambda = dL/dT with zeros on Dirichlet nodes):

@@ -309,6 +309,50 @@ mf_status mf_heat_qp_coeffs(mf_ctx *c, const mf_operator *op, double *kq, double
     return MF_OK;
 }
 
+mf_status mf_heat_source_rhs(mf_ctx *c, const mf_operator *op, const mf_heat_sources *src, const double *T,
+                             double *b, mf_stream stream)
+{
+    mf_status st = check_op(c, op);
+    if (st) return st;
+    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET)
+        return fail(c, MF_ERR_ARG, "mf_heat_source_rhs needs an FP64 heat operator in LEVELSET mode");
+    if (!src || !b) return fail(c, MF_ERR_ARG, "null argument");
+    if (src->terms & ~(MF_SRC_EVAPORATION | MF_SRC_LASER)) return fail(c, MF_ERR_ARG, "unknown source terms");
+    SourceArgs sa{};
+    sa.terms = src->terms;
+    if (src->terms & MF_SRC_EVAPORATION) {
+        const double gam = src->evaporation_coefficient;
+        if (!T) return fail(c, MF_ERR_ARG, "evaporative cooling needs the temperature");
+        if (!(gam > 0.0 && gam <= 1.0) || !(src->molar_mass > 0.0) || !(src->boiling_temperature > 0.0))
+            return fail(c, MF_ERR_ARG, "invalid evaporation parameters");
+        // Tanasawa: alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R_s) rho_v / T_v^{3/2}, R_s = R/M
+        const double Rs = 8.314 / src->molar_mass;
+        sa.alpha_v = 2.0 * gam / (2.0 - gam) * src->latent_heat / sqrt(2.0 * M_PI * Rs) * src->vapor_density /
+                     (src->boiling_temperature * sqrt(src->boiling_temperature));
+        sa.T_boil = src->boiling_temperature;
+        sa.h_v = src->latent_heat;
+    }
+    if (src->terms & MF_SRC_LASER) {
+        const double *e = src->direction;
+        const double len = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        if (!(src->laser_radius > 0.0)) return fail(c, MF_ERR_ARG, "laser radius must be positive");
+        if (!(fabs(len - 1.0) <= 1e-9)) return fail(c, MF_ERR_ARG, "laser direction must be a unit vector");
+        sa.peak = 2.0 * src->absorptivity * src->laser_power / (M_PI * src->laser_radius * src->laser_radius);
+        sa.inv_r2 = 1.0 / (src->laser_radius * src->laser_radius);
+        for (int d = 0; d < 3; ++d) {
+            sa.focus[d] = src->focus[d];
+            sa.dir[d] = e[d];
+        }
+    }
+    sa.c_rcp = 3.0 / (op->rc_g * op->rc_g + op->rc_l * op->rc_g + op->rc_l * op->rc_l);
+    if ((st = ensure_face(c, 1))) return st;
+    // the sources use the level set and rho c_p of the operator only (no convection)
+    HeatArgs ha = heat_args(op);
+    ha.conv = 0;
+    HIPCHK(c, heat_sources(c->km, ha, sa, T ? T : (const double *)op->phi, b, c->face, (hipStream_t)stream));
+    return MF_OK;
+}
+
 mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, const double *dT,
                              const double *lambda, double *dk, double *drc, double *dphi, mf_stream stream)
 {

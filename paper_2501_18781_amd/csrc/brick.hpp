@@ -265,8 +265,9 @@ struct Brick {
 // A node's value is the sum of the face partials of the 2, 4 or 8 bricks
 // containing it, in a fixed order (z outer, then y, then x; lower brick
 // first).  Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
-// operator), DMODE 2 writes y = 1 (its diagonal), DMODE 0 sums them like
-// every other node (a plain nodal field such as a gradient).
+// operator), DMODE 2 writes y = 1 (its diagonal), DMODE 3 writes 0 (a
+// right-hand side), DMODE 0 sums them like every other node (a plain nodal
+// field such as a gradient).
 // ---------------------------------------------------------------------------
 constexpr int CNT = 256; // threads per combine workgroup
 
@@ -343,7 +344,7 @@ __device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restri
     if (!combine_node(m, gx, gy, gz)) return;
     const int64_t g = node_index(m, gx, gy, gz);
     if (DMODE != 0 && node_constrained(m, gx, gy, gz)) {
-        y[g] = DMODE == 1 ? x[g] : T(1);
+        y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
         return;
     }
     const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;

@@ -22,6 +22,15 @@ struct HeatArgs {
     const double *u0; // nodal velocity [3][n_nodes] (conv != 0)
 };
 
+// Interface heat sources as the kernel takes them (scalars formed on the host).
+struct SourceArgs {
+    int terms;                 // bit 0 evaporative cooling, bit 1 laser heat flux
+    double alpha_v, T_boil, h_v; // Tanasawa coefficient, boiling temperature, latent heat
+    double peak, inv_r2;       // 2 chi P / (pi r^2), 1 / r^2
+    double focus[3], dir[3];   // beam axis point and unit direction
+    double c_rcp;              // 3 / (rc_g^2 + rc_l rc_g + rc_l^2)
+};
+
 // Coefficients of the Oseen operator.
 struct OseenArgs {
     int hkind;
@@ -71,6 +80,12 @@ hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
 hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s);
 hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,
                      double *dk, double *drc, double *dphi, void *face, hipStream_t s);
+
+// ---- interface heat sources (sources.hip) ----
+// b = right-hand side of the interface fluxes from nodal phi (in a) and T;
+// level-set mode, FP64; 0 on Dirichlet nodes.
+hipError_t heat_sources(const KMesh &m, const HeatArgs &a, const SourceArgs &sa, const double *T, double *b,
+                        void *face, hipStream_t s);
 
 // ---- Oseen (oseen.hip) ----
 // y = A x or A^T x; `face` holds 3 face_buffer_elems(m) doubles.

@@ -67,6 +67,17 @@ class MGParams(ctypes.Structure):
                 ("coarse_maxit", ctypes.c_int32)]
 
 
+MF_SRC_EVAPORATION, MF_SRC_LASER = 1, 2
+
+
+class SourcesDesc(ctypes.Structure):
+    _fields_ = [("terms", ctypes.c_int32), ("evaporation_coefficient", ctypes.c_double),
+                ("molar_mass", ctypes.c_double), ("vapor_density", ctypes.c_double),
+                ("boiling_temperature", ctypes.c_double), ("latent_heat", ctypes.c_double),
+                ("laser_power", ctypes.c_double), ("absorptivity", ctypes.c_double),
+                ("laser_radius", ctypes.c_double), ("focus", ctypes.c_double * 3), ("direction", ctypes.c_double * 3)]
+
+
 # Every function of the C ABI, with its argument types.
 _P = ctypes.c_void_p
 _SIGS = {
@@ -96,6 +107,8 @@ _SIGS = {
     "mf_quad_points": (ctypes.c_int, [_P, _P, _P]),
     "mf_heat_qp_coeffs": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
     "mf_heat_coeff_grad": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, _P, _P, _P, _P]),
+    "mf_heat_source_rhs": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.POINTER(SourcesDesc), _P, _P,
+                                          _P]),
 }
 
 _lib = None
@@ -381,3 +394,25 @@ def heat_coeff_grad(op: Operator, T, dT, lam, dk=None, drc=None, dphi=None, stre
                                          _ptr(dk, nq, torch.float64, "dk"), _ptr(drc, nq, torch.float64, "drc"),
                                          _ptr(dphi, nn, torch.float64, "dphi"), _stream(stream)))
     return dk, drc, dphi
+
+
+def heat_source_rhs(op: Operator, sources, T: Optional[torch.Tensor], b: torch.Tensor, stream=None):
+    """b = right-hand side of the interface heat fluxes (evaporative cooling,
+    laser heat flux) for the level set of the heat operator op and the nodal
+    temperature T.  sources: object with terms, evap_coeff, molar_mass,
+    vapor_density, T_boil, h_v, power, absorptivity, radius, focus, dir."""
+    c = op.ctx
+    d = SourcesDesc()
+    d.terms = int(sources.terms)
+    d.evaporation_coefficient, d.molar_mass = float(sources.evap_coeff), float(sources.molar_mass)
+    d.vapor_density, d.boiling_temperature = float(sources.vapor_density), float(sources.T_boil)
+    d.latent_heat, d.laser_power = float(sources.h_v), float(sources.power)
+    d.absorptivity, d.laser_radius = float(sources.absorptivity), float(sources.radius)
+    for k in range(3):
+        d.focus[k] = float(sources.focus[k])
+        d.direction[k] = float(sources.dir[k])
+    nn = c.n_nodes
+    c.check(library().mf_heat_source_rhs(c._h, ctypes.byref(op.desc), ctypes.byref(d),
+                                         _ptr(T, nn, torch.float64, "T"), _ptr(b, nn, torch.float64, "b"),
+                                         _stream(stream)))
+    return b
