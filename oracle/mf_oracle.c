@@ -49,6 +49,11 @@ typedef struct {
     double alpha_c;    /* convection factor (momentum) */
     double alpha_v;    /* viscous factor (momentum) */
     double k_l, k_g, rc_l, rc_g, rho_l, rho_g, mu_l, mu_g;
+    /* three-phase coefficients (used when a nodal temperature Tc is given) */
+    double k_s, rc_s, rho_s, mu_s; /* solid properties */
+    double T_sol, T_liq;           /* solidus and liquidus temperatures */
+    double darcy_C, darcy_b;       /* Darcy damping of the solid (momentum) */
+    double penalty;                /* Tanasawa penalty beta (heat), 0: off */
 } orc_coeffs;
 
 /* ------------------------------------------------------------------------ */
@@ -266,6 +271,40 @@ static inline double blend_arith(double H, double a_l, double a_g) { return H * 
 /* eq. rhoEff: reciprocal interpolation of the density */
 static inline double blend_recip(double H, double r_l, double r_g) { return 1.0 / (H / r_l + (1.0 - H) / r_g); }
 
+/* Solid fraction from the temperature (eq. solid_fraction): 1 below the
+ * solidus, 0 above the liquidus, linear in between. */
+static double solid_fraction(double T, double Ts, double Tl)
+{
+    if (T < Ts) return 1.0;
+    if (T > Tl) return 0.0;
+    return (Tl - T) / (Tl - Ts);
+}
+
+/* Smooth solid indicator (eq. heaviside_sl), zero slope at both ends. */
+static inline double heaviside_sl(double fs) { return 3.0 * fs * fs - 2.0 * fs * fs * fs; }
+
+/* Three-phase arithmetic blend (eqs. phase_fractions, solid_liquid_gas_property):
+ * a = H_phi (H_s a_s + (1 - H_s) a_l) + (1 - H_phi) a_g. */
+static inline double blend3(double Hp, double Hs, double a_s, double a_l, double a_g)
+{
+    return Hp * (Hs * a_s + (1.0 - Hs) * a_l) + (1.0 - Hp) * a_g;
+}
+
+/* Three-phase density (eq. solid_liquid_gas_density): reciprocal between the
+ * dense mixture H_s rho_s + (1 - H_s) rho_l and the gas. */
+static inline double density3(double Hp, double Hs, const orc_coeffs *cf)
+{
+    return blend_recip(Hp, Hs * cf->rho_s + (1.0 - Hs) * cf->rho_l, cf->rho_g);
+}
+
+/* Coefficient of the Darcy damping (eq. darcy_damping_force): the force is
+ * K u with K = -C fs^2 / ((1 - fs)^3 + b); on the left-hand side of the
+ * momentum balance it is the reaction term +C fs^2 / ((1 - fs)^3 + b) u. */
+static inline double darcy(double fs, const orc_coeffs *cf)
+{
+    return cf->darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + cf->darcy_b);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Cell matrices                                                             */
 /* ------------------------------------------------------------------------ */
@@ -279,24 +318,43 @@ static inline double blend_recip(double H, double r_l, double r_g) { return 1.0 
  * nodal phi (phi27 != NULL) through H and eq. muEff, or given per
  * quadrature point (kq27, rcq27). */
 static void heat_cell_matrix(const double X[8][3], const orc_coeffs *cf, const double *phi27,
-                             const double *kq27, const double *rcq27, const double *u0_27x3, double *Ae)
+                             const double *kq27, const double *rcq27, const double *u0_27x3, const double *Tc27,
+                             double *Ae)
 {
     memset(Ae, 0, sizeof(double) * 27 * 27);
     qp_data Q;
     for (int q = 0; q < 27; ++q) {
         cell_qp(X, q, &Q);
-        double k, rc;
+        double k, rc, react = 0.0;
         if (phi27) {
-            double phiq = 0.0, dH;
-            for (int j = 0; j < 27; ++j) phiq += Q.N[j] * phi27[j];
+            double phiq = 0.0, dH, g[3] = {0.0, 0.0, 0.0};
+            for (int j = 0; j < 27; ++j) {
+                phiq += Q.N[j] * phi27[j];
+                for (int d = 0; d < 3; ++d) g[d] += Q.G[j][d] * phi27[j];
+            }
             const double H = heaviside(cf->heaviside, cf->eps, phiq, &dH);
-            k = blend_arith(H, cf->k_l, cf->k_g);
-            rc = blend_arith(H, cf->rc_l, cf->rc_g);
+            if (Tc27) { /* three phases at the frozen temperature */
+                double Tq = 0.0;
+                for (int j = 0; j < 27; ++j) Tq += Q.N[j] * Tc27[j];
+                const double Hs = heaviside_sl(solid_fraction(Tq, cf->T_sol, cf->T_liq));
+                k = blend3(H, Hs, cf->k_s, cf->k_l, cf->k_g);
+                rc = blend3(H, Hs, cf->rc_s, cf->rc_l, cf->rc_g);
+            } else {
+                k = blend_arith(H, cf->k_l, cf->k_g);
+                rc = blend_arith(H, cf->rc_l, cf->rc_g);
+            }
+            if (cf->penalty != 0.0) {
+                /* Tanasawa penalty beta delta_rcp T (App. C, eq. penalty_virtual_work), with
+                 * delta_rcp of eq. deltaRhoCp: the liquid-gas blend of rc */
+                const double c_rcp = 3.0 / (cf->rc_g * cf->rc_g + cf->rc_l * cf->rc_g + cf->rc_l * cf->rc_l);
+                react = cf->penalty * dH * sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) *
+                        blend_arith(H, cf->rc_l, cf->rc_g) * c_rcp;
+            }
         } else {
             k = kq27[q];
             rc = rcq27[q];
         }
-        const double cm = Q.W * cf->alpha_m * rc, ck = Q.W * cf->alpha_k * k;
+        const double cm = Q.W * (cf->alpha_m * rc + react), ck = Q.W * cf->alpha_k * k;
         for (int i = 0; i < 27; ++i)
             for (int j = 0; j < 27; ++j)
                 Ae[i * 27 + j] += cm * Q.N[i] * Q.N[j] +
@@ -314,11 +372,12 @@ static void heat_cell_matrix(const double X[8][3], const orc_coeffs *cf, const d
 }
 
 void orc_heat_cell_matrix(const double *X24, const orc_coeffs *cf, const double *phi27,
-                          const double *kq27, const double *rcq27, const double *u0_27x3, double *Ae)
+                          const double *kq27, const double *rcq27, const double *u0_27x3, const double *Tc27,
+                          double *Ae)
 {
     double X[8][3];
     memcpy(X, X24, sizeof(X));
-    heat_cell_matrix(X, cf, phi27, kq27, rcq27, u0_27x3, Ae);
+    heat_cell_matrix(X, cf, phi27, kq27, rcq27, u0_27x3, Tc27, Ae);
 }
 
 /* The 27 nodal values of a cell of the nodal velocity u0 ([3][n_nodes]), 3 x 27. */
@@ -337,7 +396,7 @@ static void cell_velocity(const orc_mesh *m, const double *u0, const int64_t idx
  *                                 + alpha_v mu (grad N_i . grad N_j d_cc' + d_c' N_i d_c N_j) ]
  * rho by the reciprocal blend of eq. rhoEff, mu by eq. muEff. */
 static void oseen_cell_matrix(const double X[8][3], const orc_coeffs *cf, const double *phi27,
-                              const double *u0_27x3, double *Ae)
+                              const double *u0_27x3, const double *Tc27, double *Ae)
 {
     memset(Ae, 0, sizeof(double) * 81 * 81);
     qp_data Q;
@@ -349,14 +408,23 @@ static void oseen_cell_matrix(const double X[8][3], const orc_coeffs *cf, const 
             for (int c = 0; c < 3; ++c) u0q[c] += Q.N[j] * u0_27x3[c * 27 + j];
         }
         const double H = heaviside(cf->heaviside, cf->eps, phiq, &dH);
-        const double rho = blend_recip(H, cf->rho_l, cf->rho_g);
-        const double mu = blend_arith(H, cf->mu_l, cf->mu_g);
+        double rho = blend_recip(H, cf->rho_l, cf->rho_g);
+        double mu = blend_arith(H, cf->mu_l, cf->mu_g), react = 0.0;
+        if (Tc27) { /* three phases at the frozen temperature, Darcy damping of the solid */
+            double Tq = 0.0;
+            for (int j = 0; j < 27; ++j) Tq += Q.N[j] * Tc27[j];
+            const double fs = solid_fraction(Tq, cf->T_sol, cf->T_liq), Hs = heaviside_sl(fs);
+            rho = density3(H, Hs, cf);
+            mu = blend3(H, Hs, cf->mu_s, cf->mu_l, cf->mu_g);
+            react = darcy(fs, cf);
+        }
         for (int i = 0; i < 27; ++i)
             for (int j = 0; j < 27; ++j) {
                 const double mass = Q.N[i] * Q.N[j];
                 const double conv = Q.N[i] * (u0q[0] * Q.G[j][0] + u0q[1] * Q.G[j][1] + u0q[2] * Q.G[j][2]);
                 const double lap = Q.G[i][0] * Q.G[j][0] + Q.G[i][1] * Q.G[j][1] + Q.G[i][2] * Q.G[j][2];
-                const double diag = Q.W * (cf->alpha_m * rho * mass + cf->alpha_c * rho * conv + cf->alpha_v * mu * lap);
+                const double diag = Q.W * ((cf->alpha_m * rho + react) * mass + cf->alpha_c * rho * conv +
+                                           cf->alpha_v * mu * lap);
                 for (int c = 0; c < 3; ++c)
                     for (int cp = 0; cp < 3; ++cp) {
                         double v = Q.W * cf->alpha_v * mu * Q.G[i][cp] * Q.G[j][c];
@@ -368,11 +436,11 @@ static void oseen_cell_matrix(const double X[8][3], const orc_coeffs *cf, const 
 }
 
 void orc_oseen_cell_matrix(const double *X24, const orc_coeffs *cf, const double *phi27,
-                           const double *u0_27x3, double *Ae)
+                           const double *u0_27x3, const double *Tc27, double *Ae)
 {
     double X[8][3];
     memcpy(X, X24, sizeof(X));
-    oseen_cell_matrix(X, cf, phi27, u0_27x3, Ae);
+    oseen_cell_matrix(X, cf, phi27, u0_27x3, Tc27, Ae);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -461,7 +529,7 @@ static void apply_dirichlet(const orc_mesh *m, int ncomp, const int64_t *rowptr,
  * cell-major, 27 per cell) select how the coefficients are formed; a non-NULL
  * nodal velocity u0 ([3][n_nodes]) adds the convective term. */
 void orc_assemble_heat(const orc_mesh *m, const orc_coeffs *cf, const double *phi,
-                       const double *kq, const double *rcq, const double *u0,
+                       const double *kq, const double *rcq, const double *u0, const double *Tc,
                        const int64_t *rowptr, const int32_t *cols, double *vals)
 {
     const int64_t nnz = rowptr[nnodes(m)];
@@ -477,12 +545,15 @@ void orc_assemble_heat(const orc_mesh *m, const orc_coeffs *cf, const double *ph
                     cell_vertices(m, cx, cy, cz, X);
                     cell_nodes(m, cx, cy, cz, idx);
                     const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    double Tc27[27];
                     if (u0) cell_velocity(m, u0, idx, u27);
+                    if (Tc)
+                        for (int a = 0; a < 27; ++a) Tc27[a] = Tc[idx[a]];
                     if (phi) {
                         for (int a = 0; a < 27; ++a) phi27[a] = phi[idx[a]];
-                        heat_cell_matrix(X, cf, phi27, NULL, NULL, u0 ? u27 : NULL, Ae);
+                        heat_cell_matrix(X, cf, phi27, NULL, NULL, u0 ? u27 : NULL, Tc ? Tc27 : NULL, Ae);
                     } else {
-                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, u0 ? u27 : NULL, Ae);
+                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, u0 ? u27 : NULL, NULL, Ae);
                     }
                     for (int i = 0; i < 27; ++i)
                         for (int j = 0; j < 27; ++j) {
@@ -495,7 +566,7 @@ void orc_assemble_heat(const orc_mesh *m, const orc_coeffs *cf, const double *ph
 }
 
 void orc_assemble_oseen(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *u0,
-                        const int64_t *rowptr, const int32_t *cols, double *vals)
+                        const double *Tc, const int64_t *rowptr, const int32_t *cols, double *vals)
 {
     const int64_t nn = nnodes(m);
     const int64_t nnz = rowptr[3 * nn];
@@ -506,16 +577,17 @@ void orc_assemble_oseen(const orc_mesh *m, const orc_coeffs *cf, const double *p
         for (int cz = pz; cz < m->n[2]; cz += 2)
             for (int cy = py; cy < m->n[1]; cy += 2)
                 for (int cx = px; cx < m->n[0]; cx += 2) {
-                    double X[8][3], phi27[27], u27[81];
+                    double X[8][3], phi27[27], u27[81], Tc27[27];
                     double *Ae = (double *)malloc(sizeof(double) * 81 * 81);
                     int64_t idx[27];
                     cell_vertices(m, cx, cy, cz, X);
                     cell_nodes(m, cx, cy, cz, idx);
                     for (int a = 0; a < 27; ++a) {
                         phi27[a] = phi[idx[a]];
+                        if (Tc) Tc27[a] = Tc[idx[a]];
                         for (int c = 0; c < 3; ++c) u27[c * 27 + a] = u0[c * nn + idx[a]];
                     }
-                    oseen_cell_matrix(X, cf, phi27, u27, Ae);
+                    oseen_cell_matrix(X, cf, phi27, u27, Tc ? Tc27 : NULL, Ae);
                     for (int c = 0; c < 3; ++c)
                         for (int i = 0; i < 27; ++i)
                             for (int cp = 0; cp < 3; ++cp)
@@ -561,8 +633,8 @@ static void cells_of_node(const orc_mesh *m, int64_t id, int clo[3], int chi[3])
 /* Rows of y = A x (transpose != 0: of y = A^T x) of the heat operator, with
  * the convective term when u0 is given. */
 void orc_heat_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *kq,
-                   const double *rcq, const double *u0, const double *x, int32_t transpose, int64_t nrows,
-                   const int64_t *rows, double *out)
+                   const double *rcq, const double *u0, const double *Tc, const double *x, int32_t transpose,
+                   int64_t nrows, const int64_t *rows, double *out)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < nrows; ++s) {
@@ -579,12 +651,15 @@ void orc_heat_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, c
                     cell_vertices(m, cx, cy, cz, X);
                     cell_nodes(m, cx, cy, cz, idx);
                     const int64_t cell = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                    double Tc27[27];
                     if (u0) cell_velocity(m, u0, idx, u27);
+                    if (Tc)
+                        for (int a = 0; a < 27; ++a) Tc27[a] = Tc[idx[a]];
                     if (phi) {
                         for (int a = 0; a < 27; ++a) phi27[a] = phi[idx[a]];
-                        heat_cell_matrix(X, cf, phi27, NULL, NULL, u0 ? u27 : NULL, Ae);
+                        heat_cell_matrix(X, cf, phi27, NULL, NULL, u0 ? u27 : NULL, Tc ? Tc27 : NULL, Ae);
                     } else {
-                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, u0 ? u27 : NULL, Ae);
+                        heat_cell_matrix(X, cf, NULL, kq + 27 * cell, rcq + 27 * cell, u0 ? u27 : NULL, NULL, Ae);
                     }
                     int il = -1;
                     for (int a = 0; a < 27; ++a) if (idx[a] == r) il = a;
@@ -599,7 +674,8 @@ void orc_heat_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, c
 
 /* rows are dof indices comp * n_nodes + node; transpose != 0 gives rows of A^T x. */
 void orc_oseen_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, const double *u0,
-                    const double *x, int32_t transpose, int64_t nrows, const int64_t *rows, double *out)
+                    const double *Tc, const double *x, int32_t transpose, int64_t nrows, const int64_t *rows,
+                    double *out)
 {
     const int64_t nn = nnodes(m);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -615,15 +691,16 @@ void orc_oseen_rows(const orc_mesh *m, const orc_coeffs *cf, const double *phi, 
         for (int cz = clo[2]; cz <= chi[2]; ++cz)
             for (int cy = clo[1]; cy <= chi[1]; ++cy)
                 for (int cx = clo[0]; cx <= chi[0]; ++cx) {
-                    double X[8][3], phi27[27], u27[81];
+                    double X[8][3], phi27[27], u27[81], Tc27[27];
                     int64_t idx[27];
                     cell_vertices(m, cx, cy, cz, X);
                     cell_nodes(m, cx, cy, cz, idx);
                     for (int a = 0; a < 27; ++a) {
                         phi27[a] = phi[idx[a]];
+                        if (Tc) Tc27[a] = Tc[idx[a]];
                         for (int c = 0; c < 3; ++c) u27[c * 27 + a] = u0[c * nn + idx[a]];
                     }
-                    oseen_cell_matrix(X, cf, phi27, u27, Ae);
+                    oseen_cell_matrix(X, cf, phi27, u27, Tc ? Tc27 : NULL, Ae);
                     int il = -1;
                     for (int a = 0; a < 27; ++a) if (idx[a] == node) il = a;
                     const int li = comp * 27 + il;
@@ -821,7 +898,8 @@ void orc_load_vector(const orc_mesh *m, const double *fq, double *b)
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    int32_t terms;        /* bit 0: evaporative cooling, bit 1: laser heat flux */
+    int32_t terms;        /* bit 0: evaporative cooling, bit 1: laser heat flux,
+                             bit 2: right-hand side of the Tanasawa penalty, beta T_v delta_rcp */
     int32_t pad_;
     double evap_coeff;    /* evaporation coefficient of the Tanasawa model, 0 < . <= 1 */
     double molar_mass;    /* M, kg/mol; specific gas constant R/M */
@@ -885,6 +963,7 @@ void orc_heat_sources(const orc_mesh *m, const orc_coeffs *cf, const orc_sources
                         const double delta_rcp = delta * blend_arith(H, cf->rc_l, cf->rc_g) * c_rcp;
                         double s = 0.0;
                         if (src->terms & 1) s += -alpha_v * (Tq - src->T_boil) * src->h_v * delta_rcp;
+                        if (src->terms & 4) s += cf->penalty * src->T_boil * delta_rcp;
                         if ((src->terms & 2) && gnorm > 0.0) {
                             double n_dot_e = 0.0, r[3], t = 0.0;
                             for (int d = 0; d < 3; ++d) {

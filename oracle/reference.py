@@ -39,7 +39,10 @@ class OCoeffs(ctypes.Structure):
                 ("k_l", ctypes.c_double), ("k_g", ctypes.c_double),
                 ("rc_l", ctypes.c_double), ("rc_g", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
-                ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double)]
+                ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
+                ("k_s", ctypes.c_double), ("rc_s", ctypes.c_double), ("rho_s", ctypes.c_double),
+                ("mu_s", ctypes.c_double), ("T_sol", ctypes.c_double), ("T_liq", ctypes.c_double),
+                ("darcy_C", ctypes.c_double), ("darcy_b", ctypes.c_double), ("penalty", ctypes.c_double)]
 
 
 _lib = None
@@ -140,23 +143,27 @@ def constrained_mask(mesh) -> np.ndarray:
     return mask.astype(bool)
 
 
-def heat_cell_matrix(X8x3, params, phi27=None, kq27=None, rcq27=None, u0_3x27=None, **override) -> np.ndarray:
-    """Heat cell matrix; u0_3x27 (nodal velocity of the cell) adds the convective term."""
+def heat_cell_matrix(X8x3, params, phi27=None, kq27=None, rcq27=None, u0_3x27=None, Tc27=None,
+                     **override) -> np.ndarray:
+    """Heat cell matrix; u0_3x27 (nodal velocity of the cell) adds the convective
+    term, Tc27 (nodal temperature of the cell) selects the three-phase coefficients."""
     X = _f64(X8x3).reshape(8, 3)
     Ae = np.zeros((27, 27))
     c = ocoeffs(params, **override)
     lib().orc_heat_cell_matrix(_p(X), ctypes.byref(c), _p(None if phi27 is None else _f64(phi27)),
                                _p(None if kq27 is None else _f64(kq27)),
                                _p(None if rcq27 is None else _f64(rcq27)),
-                               _p(None if u0_3x27 is None else _f64(u0_3x27)), _p(Ae))
+                               _p(None if u0_3x27 is None else _f64(u0_3x27)),
+                               _p(None if Tc27 is None else _f64(Tc27)), _p(Ae))
     return Ae
 
 
-def oseen_cell_matrix(X8x3, params, phi27, u0_3x27, **override) -> np.ndarray:
+def oseen_cell_matrix(X8x3, params, phi27, u0_3x27, Tc27=None, **override) -> np.ndarray:
     X = _f64(X8x3).reshape(8, 3)
     Ae = np.zeros((81, 81))
     c = ocoeffs(params, **override)
-    lib().orc_oseen_cell_matrix(_p(X), ctypes.byref(c), _p(_f64(phi27)), _p(_f64(u0_3x27)), _p(Ae))
+    lib().orc_oseen_cell_matrix(_p(X), ctypes.byref(c), _p(_f64(phi27)), _p(_f64(u0_3x27)),
+                                _p(None if Tc27 is None else _f64(Tc27)), _p(Ae))
     return Ae
 
 
@@ -182,9 +189,10 @@ def _pattern(mesh, ncomp: int):
     return m, rowptr, cols
 
 
-def heat_matrix(mesh, params, phi=None, kq=None, rcq=None, u0=None, **override) -> sp.csr_matrix:
+def heat_matrix(mesh, params, phi=None, kq=None, rcq=None, u0=None, Tc=None, **override) -> sp.csr_matrix:
     """Global heat matrix (CSR), coefficients from nodal phi or from per-qp arrays;
-    a nodal velocity u0 ([3][n_nodes]) adds the convective term."""
+    a nodal velocity u0 ([3][n_nodes]) adds the convective term, a nodal
+    temperature Tc selects the three-phase coefficients."""
     m, rowptr, cols = _pattern(mesh, 1)
     vals = np.zeros(cols.size)
     c = ocoeffs(params, **override)
@@ -192,18 +200,19 @@ def heat_matrix(mesh, params, phi=None, kq=None, rcq=None, u0=None, **override) 
     kq = None if kq is None else _f64(kq)
     rcq = None if rcq is None else _f64(rcq)
     u0 = None if u0 is None else _f64(u0)
-    lib().orc_assemble_heat(ctypes.byref(m), ctypes.byref(c), _p(phi), _p(kq), _p(rcq), _p(u0),
+    Tc = None if Tc is None else _f64(Tc)
+    lib().orc_assemble_heat(ctypes.byref(m), ctypes.byref(c), _p(phi), _p(kq), _p(rcq), _p(u0), _p(Tc),
                             _p(rowptr), _p(cols), _p(vals))
     n = n_nodes(mesh)
     return sp.csr_matrix((vals, cols, rowptr), shape=(n, n))
 
 
-def oseen_matrix(mesh, params, phi, u0, **override) -> sp.csr_matrix:
+def oseen_matrix(mesh, params, phi, u0, Tc=None, **override) -> sp.csr_matrix:
     m, rowptr, cols = _pattern(mesh, 3)
     vals = np.zeros(cols.size)
     c = ocoeffs(params, **override)
     lib().orc_assemble_oseen(ctypes.byref(m), ctypes.byref(c), _p(_f64(phi)), _p(_f64(u0)),
-                             _p(rowptr), _p(cols), _p(vals))
+                             _p(None if Tc is None else _f64(Tc)), _p(rowptr), _p(cols), _p(vals))
     n = 3 * n_nodes(mesh)
     return sp.csr_matrix((vals, cols, rowptr), shape=(n, n))
 
@@ -219,7 +228,7 @@ def spmv(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
     return y
 
 
-def heat_rows(mesh, params, x, rows, phi=None, kq=None, rcq=None, u0=None, transpose=False,
+def heat_rows(mesh, params, x, rows, phi=None, kq=None, rcq=None, u0=None, transpose=False, Tc=None,
               **override) -> np.ndarray:
     """Selected entries of y = A x (or A^T x) for the heat operator, from cell matrices only."""
     m = omesh(mesh)
@@ -228,17 +237,19 @@ def heat_rows(mesh, params, x, rows, phi=None, kq=None, rcq=None, u0=None, trans
     out = np.zeros(rows.size)
     lib().orc_heat_rows(ctypes.byref(m), ctypes.byref(c), _p(None if phi is None else _f64(phi)),
                         _p(None if kq is None else _f64(kq)), _p(None if rcq is None else _f64(rcq)),
-                        _p(None if u0 is None else _f64(u0)), _p(_f64(x)), ctypes.c_int32(1 if transpose else 0),
+                        _p(None if u0 is None else _f64(u0)), _p(None if Tc is None else _f64(Tc)), _p(_f64(x)),
+                        ctypes.c_int32(1 if transpose else 0),
                         ctypes.c_int64(rows.size), _p(rows), _p(out))
     return out
 
 
-def oseen_rows(mesh, params, phi, u0, x, rows, transpose=False, **override) -> np.ndarray:
+def oseen_rows(mesh, params, phi, u0, x, rows, transpose=False, Tc=None, **override) -> np.ndarray:
     m = omesh(mesh)
     c = ocoeffs(params, **override)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     out = np.zeros(rows.size)
-    lib().orc_oseen_rows(ctypes.byref(m), ctypes.byref(c), _p(_f64(phi)), _p(_f64(u0)), _p(_f64(x)),
+    lib().orc_oseen_rows(ctypes.byref(m), ctypes.byref(c), _p(_f64(phi)), _p(_f64(u0)),
+                         _p(None if Tc is None else _f64(Tc)), _p(_f64(x)),
                          ctypes.c_int32(1 if transpose else 0), ctypes.c_int64(rows.size), _p(rows), _p(out))
     return out
 

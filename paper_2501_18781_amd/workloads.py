@@ -131,6 +131,13 @@ class HeatParams:
 
     alpha_k: float = 1.0
     alpha_c: float = 1.0  # factor of the convective term rho c_p u.grad T (used only with a velocity field)
+    # three phases (used only with a nodal temperature for the coefficients):
+    # solid conductivity and rho c_p, Ti-6Al-4V solidus and liquidus
+    k_s: float = 20.0
+    rc_s: float = 4.0e6
+    T_sol: float = 1933.0
+    T_liq: float = 2200.0
+    penalty: float = 0.0  # Tanasawa penalty beta = alpha_v h_v (0: off)
 
 
 @dataclass(frozen=True)
@@ -146,10 +153,24 @@ class OseenParams:
     eps: float = 0.0
     alpha_c: float = 1.0
     alpha_v: float = 1.0
+    # three phases (used only with a nodal temperature for the coefficients):
+    # solid density and viscosity, melting range, Darcy damping C fs^2/((1-fs)^3+b)
+    rho_s: float = 4200.0
+    mu_s: float = 5.0e-3
+    T_sol: float = 1933.0
+    T_liq: float = 2200.0
+    darcy_C: float = 1.0e8
+    darcy_b: float = 1.0
 
     @property
     def alpha_m(self) -> float:
         return 1.0 / self.dt
+
+
+def melt_temperature(mesh: Mesh) -> np.ndarray:
+    """A frozen temperature field across the melting range of HeatParams:
+    T = 1800 K + 600 K z (solid below z ~ 0.22, liquid above z ~ 0.67)."""
+    return 1800.0 + 600.0 * node_coords(mesh)[:, 2]
 
 
 @dataclass

@@ -404,6 +404,71 @@ def test_heat_sources_vanish_on_dirichlet_nodes():
     assert np.all(b[cm] == 0.0) and np.abs(b[~cm]).max() > 0.0
 
 
+# ---------------------------------------------------------------------------
+# Three phases (solid fraction from T), Darcy damping, Tanasawa penalty
+# ---------------------------------------------------------------------------
+
+def test_three_phase_coefficients_at_known_states():
+    # With phi = 1 (dense) the heat matrix at a frozen temperature T equals the
+    # matrix with the hand-computed constant coefficients (given per point):
+    #   below the solidus: solid values; above the liquidus: liquid values;
+    #   f_s = 1/2: H_s = 3/4 - 2/8 = 1/2; f_s = 1/4: H_s = 3/16 - 2/64 = 5/32;
+    # with phi = -1 (gas) the gas values whatever T.
+    # catches: f_s or H_s wrong (slope, ends), solid and liquid swapped
+    mesh = W.Mesh((2, 2, 3))
+    nn, nq = mesh.n_nodes, mesh.n_cells * 27
+    p = W.HeatParams()
+    ts, tl = p.T_sol, p.T_liq
+    for T, phi0, Hs in [(ts - 50, 1.0, 1.0), (tl + 50, 1.0, 0.0), ((ts + tl) / 2, 1.0, 0.5),
+                        (tl - (tl - ts) / 4, 1.0, 5 / 32), (ts - 50, -1.0, None)]:
+        A = O.heat_matrix(mesh, p, phi=np.full(nn, phi0), Tc=np.full(nn, T))
+        if Hs is None:
+            k, rc = p.k_g, p.rc_g
+        else:
+            k, rc = Hs * p.k_s + (1 - Hs) * p.k_l, Hs * p.rc_s + (1 - Hs) * p.rc_l
+        B = O.heat_matrix(mesh, p, kq=np.full(nq, k), rcq=np.full(nq, rc))
+        assert abs(A - B).max() < 1e-13 * abs(B).max(), (T, phi0)
+
+
+def test_darcy_damping_is_a_mass_term_of_the_solid():
+    # Oseen with alpha_m = alpha_c = alpha_v = 0, phi = 1, at a frozen T: the
+    # Darcy term is C fs^2 / ((1-fs)^3 + b) times the mass matrix per component:
+    # fs = 1 -> C/b; fs = 1/2 -> C (1/4) / (1/8 + b); fs = 0 -> 0
+    mesh = W.Mesh((2, 1, 2))
+    nn = mesh.n_nodes
+    q = W.OseenParams(darcy_C=3.0e5, darcy_b=0.5)
+    M = O.heat_matrix(mesh, None, kq=np.ones(mesh.n_cells * 27), rcq=np.ones(mesh.n_cells * 27),
+                      alpha_m=1.0, alpha_k=0.0).toarray()
+    zero = np.zeros((3, nn))
+    for T, K in [(q.T_sol - 10, 3.0e5 / 0.5), ((q.T_sol + q.T_liq) / 2, 3.0e5 * 0.25 / (0.125 + 0.5)),
+                 (q.T_liq + 10, 0.0)]:
+        D = O.oseen_matrix(mesh, q, np.ones(nn), zero, Tc=np.full(nn, T), alpha_m=0.0, alpha_c=0.0,
+                           alpha_v=0.0).toarray()
+        for c in range(3):
+            blk = D[c * nn:(c + 1) * nn, c * nn:(c + 1) * nn]
+            assert np.abs(blk - K * M).max() <= 1e-12 * max(K, 1.0) * np.abs(M).max()
+        assert np.abs(D[:nn, nn:]).max() == 0.0
+
+
+def test_penalty_term_moments_and_equivalence_with_evaporative_cooling():
+    # Linear level set (delta = a/2, rc(z) = A + B z, see _linear_phi_case):
+    # the penalty matrix R = beta delta_rcp N_i N_j has exact moments
+    #   1^T R 1 = beta (a/2) c (A + B/2),  1^T R z = beta (a/2) c (A/2 + B/3);
+    # and for any T, b_penalty(T_v) - R T equals the explicit evaporative
+    # cooling with alpha_v h_v = beta (the penalty form of App. C).
+    mesh, x, phi, p, delta, A, B, c = _linear_phi_case(n=(2, 2, 3))
+    beta = 1.0  # = alpha_v h_v of UNIT_EVAP
+    R = O.heat_matrix(mesh, p, phi=phi, alpha_m=0.0, alpha_k=0.0, penalty=beta)
+    one = np.ones(mesh.n_nodes)
+    assert abs(one @ (R @ one) - beta * delta * c * (A + B / 2)) < 1e-13
+    assert abs(one @ (R @ x[:, 2]) - beta * delta * c * (A / 2 + B / 3)) < 1e-13
+    T = 1.0 + W.uniform(5, mesh.n_nodes)
+    b_pen = O.heat_sources(mesh, p, W.SourceParams(terms=4, **UNIT_EVAP), phi, T, penalty=beta)
+    b_evap = O.heat_sources(mesh, p, W.SourceParams(terms=1, **UNIT_EVAP), phi, T)
+    assert abs(b_pen.sum() - beta * 1.0 * delta * c * (A + B / 2)) < 1e-13
+    assert np.abs(b_pen - R @ T - b_evap).max() < 1e-13 * np.abs(b_evap).max()
+
+
 def test_spot_rows_agree_with_assembled_matrix():
     wl = W.heat_sphere_workload(3, W.FACE_YLO | W.FACE_ZHI)
     A = O.heat_matrix(wl.mesh, wl.params, phi=wl.phi)
