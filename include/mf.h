@@ -97,7 +97,22 @@ typedef struct {
     const void *phi;    /* nodal level set [n_nodes] (LEVELSET mode, and Oseen) */
     const void *k_q;    /* conductivity per quadrature point [n_cells*27] (QUAD mode) */
     const void *rc_q;   /* rho c_p per quadrature point [n_cells*27] (QUAD mode) */
-    const void *u0;     /* Oseen convective velocity, nodal [3][n_nodes] */
+    const void *u0;     /* Oseen convective velocity, nodal [3][n_nodes]; for heat, optional:
+                           the convective term alpha_c C(rc, u0) (FP64, LEVELSET mode) */
+    /* Three phases (Sec. 3.2-3.3, FP64, LEVELSET mode): if T_coef is given the
+     * coefficients are evaluated at that frozen nodal temperature with the
+     * solid fraction f_s(T) (eq. solid_fraction, solidus T_sol < liquidus
+     * T_liq), H_s = 3 f_s^2 - 2 f_s^3 (eq. heaviside_sl) and the blends
+     * a = H (H_s a_s + (1 - H_s) a_l) + (1 - H) a_g (k, rc_p, mu), rho
+     * reciprocal between H_s rho_s + (1 - H_s) rho_l and rho_g; the Oseen
+     * operator then gains the Darcy damping of the solid
+     * + darcy_C f_s^2 / ((1 - f_s)^3 + darcy_b) u (eq. darcy_damping_force). */
+    double k_s, rc_s, rho_s, mu_s; /* solid properties */
+    double T_sol, T_liq;
+    double darcy_C, darcy_b;
+    double penalty;     /* heat, LEVELSET mode: Tanasawa penalty beta delta_rcp T on the left-hand
+                           side (App. C, eq. penalty_virtual_work; 0: off) */
+    const void *T_coef; /* nodal temperature of the coefficients [n_nodes], or NULL */
 } mf_operator;
 
 typedef struct {
@@ -214,7 +229,7 @@ mf_status mf_heat_qp_coeffs(mf_ctx *ctx, const mf_operator *op, double *k_q, dou
 
 /* ---- interface heat sources (heat right-hand side) ----------------------------- */
 
-enum { MF_SRC_EVAPORATION = 1, MF_SRC_LASER = 2 };
+enum { MF_SRC_EVAPORATION = 1, MF_SRC_LASER = 2, MF_SRC_PENALTY = 4 };
 
 typedef struct {
     int32_t terms;                   /* MF_SRC_* bits */
@@ -240,6 +255,9 @@ typedef struct {
  * with phi, grad phi and T interpolated at each quadrature point (the local
  * temperature), n = -grad phi/|grad phi| the interface normal pointing from
  * the liquid (phi > 0) into the gas, and d_L the distance from the beam axis.
+ * MF_SRC_PENALTY adds the right-hand side of the Tanasawa penalty, beta T_v
+ * delta_rcp with beta = op->penalty and T_v = boiling_temperature (the
+ * penalty form of the evaporative cooling, App. C).
  * op: FP64 heat operator in LEVELSET mode (phi, Heaviside form, rc_l, rc_g).
  * T: nodal temperature (n_nodes doubles; may be NULL without evaporation).
  * b: n_nodes doubles, overwritten; 0 on Dirichlet nodes. */

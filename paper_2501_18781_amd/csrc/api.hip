@@ -173,6 +173,16 @@ mf_status check_op(mf_ctx *c, const mf_operator *op)
     if (op->heaviside != MF_H_LINEAR && op->heaviside != MF_H_SINE)
         return fail(c, MF_ERR_ARG, "unknown Heaviside form %d", op->heaviside);
     if (op->heaviside == MF_H_SINE && !(op->eps > 0.0)) return fail(c, MF_ERR_ARG, "sine Heaviside needs eps > 0");
+    if (op->T_coef || op->penalty != 0.0) {
+        if (op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET)
+            return fail(c, MF_ERR_ARG, "three-phase coefficients and the penalty need FP64 and LEVELSET mode");
+        if (op->T_coef && !(op->T_liq > op->T_sol)) return fail(c, MF_ERR_ARG, "need T_sol < T_liq");
+        if (op->kind == MF_HEAT && op->u0)
+            return fail(c, MF_ERR_ARG, "convection with three-phase coefficients or the penalty is not provided");
+        if (op->kind == MF_OSEEN && op->penalty != 0.0) return fail(c, MF_ERR_ARG, "the penalty is a heat term");
+    }
+    if (op->kind == MF_OSEEN && op->T_coef && op->darcy_C != 0.0 && !(op->darcy_b > 0.0))
+        return fail(c, MF_ERR_ARG, "Darcy damping needs darcy_b > 0");
     if (op->kind == MF_HEAT) {
         if (op->u0 && (op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET))
             return fail(c, MF_ERR_ARG, "the convective heat operator (u0 given) is FP64 in LEVELSET mode only");
@@ -209,6 +219,13 @@ HeatArgs heat_args(const mf_operator *op)
     a.conv = op->u0 ? 1 : 0;
     a.ac = op->alpha_c;
     a.u0 = (const double *)op->u0;
+    a.k_s = op->k_s;
+    a.rc_s = op->rc_s;
+    a.T_sol = op->T_sol;
+    a.T_liq = op->T_liq;
+    a.penalty = op->penalty;
+    a.tc = (const double *)op->T_coef;
+    if (a.mode == 0 && (a.tc || a.penalty != 0.0)) a.mode = 2;
     return a;
 }
 
@@ -226,6 +243,13 @@ OseenArgs oseen_args(const mf_operator *op)
     a.mu_g = op->mu_g;
     a.phi = (const double *)op->phi;
     a.u0 = (const double *)op->u0;
+    a.rho_s = op->rho_s;
+    a.mu_s = op->mu_s;
+    a.T_sol = op->T_sol;
+    a.T_liq = op->T_liq;
+    a.darcy_C = op->darcy_C;
+    a.darcy_b = op->darcy_b;
+    a.tc = (const double *)op->T_coef;
     return a;
 }
 
@@ -302,8 +326,8 @@ mf_status mf_heat_qp_coeffs(mf_ctx *c, const mf_operator *op, double *kq, double
 {
     mf_status st = check_op(c, op);
     if (st) return st;
-    if (op->kind != MF_HEAT || op->coeff_mode != MF_COEFF_LEVELSET || op->precision != MF_FP64)
-        return fail(c, MF_ERR_ARG, "mf_heat_qp_coeffs needs an FP64 heat operator in LEVELSET mode");
+    if (op->kind != MF_HEAT || op->coeff_mode != MF_COEFF_LEVELSET || op->precision != MF_FP64 || op->T_coef)
+        return fail(c, MF_ERR_ARG, "mf_heat_qp_coeffs needs an FP64 two-phase heat operator in LEVELSET mode");
     if (!kq || !rcq) return fail(c, MF_ERR_ARG, "null output");
     HIPCHK(c, heat_qp_coeffs(c->km, heat_args(op), kq, rcq, (hipStream_t)stream));
     return MF_OK;
@@ -317,9 +341,15 @@ mf_status mf_heat_source_rhs(mf_ctx *c, const mf_operator *op, const mf_heat_sou
     if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET)
         return fail(c, MF_ERR_ARG, "mf_heat_source_rhs needs an FP64 heat operator in LEVELSET mode");
     if (!src || !b) return fail(c, MF_ERR_ARG, "null argument");
-    if (src->terms & ~(MF_SRC_EVAPORATION | MF_SRC_LASER)) return fail(c, MF_ERR_ARG, "unknown source terms");
+    if (src->terms & ~(MF_SRC_EVAPORATION | MF_SRC_LASER | MF_SRC_PENALTY))
+        return fail(c, MF_ERR_ARG, "unknown source terms");
     SourceArgs sa{};
     sa.terms = src->terms;
+    if (src->terms & MF_SRC_PENALTY) {
+        if (!(src->boiling_temperature > 0.0)) return fail(c, MF_ERR_ARG, "invalid boiling temperature");
+        sa.penalty = op->penalty;
+        sa.T_boil = src->boiling_temperature;
+    }
     if (src->terms & MF_SRC_EVAPORATION) {
         const double gam = src->evaporation_coefficient;
         if (!T) return fail(c, MF_ERR_ARG, "evaporative cooling needs the temperature");
@@ -358,8 +388,8 @@ mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, 
 {
     mf_status st = check_op(c, op);
     if (st) return st;
-    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->u0)
-        return fail(c, MF_ERR_ARG, "mf_heat_coeff_grad needs an FP64 heat operator without convection");
+    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->u0 || op->T_coef || op->penalty != 0.0)
+        return fail(c, MF_ERR_ARG, "mf_heat_coeff_grad needs an FP64 two-phase heat operator without convection");
     if (!T || !dT || !lambda) return fail(c, MF_ERR_ARG, "null input");
     if (dphi && op->coeff_mode != MF_COEFF_LEVELSET)
         return fail(c, MF_ERR_ARG, "dphi needs the LEVELSET coefficient mode");

@@ -80,6 +80,65 @@ __device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, T *phq, cons
     }
 }
 
+// Mode 2 coefficients (FP64): three phases at the frozen nodal temperature
+// (staged at ts, if a.tc) and/or the Tanasawa penalty.  At each Gauss point
+//   H = H(phi), H_s = 3 f_s^2 - 2 f_s^3 with f_s = clamp((T_liq - T)/(T_liq - T_sol), 0, 1),
+//   k, rc = H (H_s a_s + (1 - H_s) a_l) + (1 - H) a_g         (H_s = 0 without a.tc)
+//   cm_q = |J| w_q (alpha_m rc + beta H' |grad phi| rc_lg c_rcp),  ck_q = alpha_k |J| w_q k / r^2
+// with rc_lg the liquid-gas blend of eq. deltaRhoCp.
+template <int HK>
+__device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &m, const HeatArgs &a,
+                                                  const double *ps, const double *ts, double *cm, double *ck)
+{
+    double ph[27], gn[27], Tq[27];
+    br.gather27(ps, ph);
+    interp3(ph);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) gn[q] = 0.0;
+    if (a.penalty != 0.0) { // |grad phi|^2 at the Gauss points
+        const double h[3] = {m.hx, m.hy, m.hz};
+        auto dir = [&](auto D) {
+            constexpr int d = decltype(D)::value;
+#pragma unroll
+            for (int n = 0; n < 3; ++n)
+#pragma unroll
+                for (int mm = 0; mm < 3; ++mm) {
+                    const int i0 = lidx<d>(0, mm, n), i1 = lidx<d>(1, mm, n), i2 = lidx<d>(2, mm, n);
+                    double t0, t1, t2;
+                    Q2<double>::deriv_scaled(ph[i0], ph[i1], ph[i2], 1.0 / (kR * h[d]), t0, t1, t2);
+                    gn[i0] += t0 * t0;
+                    gn[i1] += t1 * t1;
+                    gn[i2] += t2 * t2;
+                }
+        };
+        dir(std::integral_constant<int, 0>{});
+        dir(std::integral_constant<int, 1>{});
+        dir(std::integral_constant<int, 2>{});
+    }
+    if (a.tc) {
+        br.gather27(ts, Tq);
+        interp3(Tq);
+    }
+    const double vol = m.hx * m.hy * m.hz;
+    const double c_rcp = 3.0 / (a.rc_g * a.rc_g + a.rc_l * a.rc_g + a.rc_l * a.rc_l);
+    const double inv_range = 1.0 / (a.T_liq - a.T_sol);
+    for (int q = 0; q < 27; ++q) { // not unrolled: the sine form calls out of line
+        double dH;
+        const double H = heaviside<double>(HK, a.eps, ph[q], &dH);
+        double Hs = 0.0;
+        if (a.tc) {
+            const double fs = fmin(fmax((a.T_liq - Tq[q]) * inv_range, 0.0), 1.0);
+            Hs = fs * fs * (3.0 - 2.0 * fs);
+        }
+        const double k = H * (Hs * a.k_s + (1.0 - Hs) * a.k_l) + (1.0 - H) * a.k_g;
+        const double rc = H * (Hs * a.rc_s + (1.0 - Hs) * a.rc_l) + (1.0 - H) * a.rc_g;
+        const double react = a.penalty * dH * sqrt(gn[q]) * (a.rc_g + H * (a.rc_l - a.rc_g)) * c_rcp;
+        const double w = vol * Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
+        cm[q] = w * (a.am * rc + react);
+        ck[q] = w * a.ak * k / (kR * kR);
+    }
+}
+
 // y_e = A_e x_e on one cell, in place on u (27 nodal values in, 27 out).
 template <typename T>
 __device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, T ihx, T ihy, T ihz)
@@ -216,6 +275,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
                                                          RedWS red)
 {
     static_assert(CONV == 0 || (std::is_same<T, double>::value && MODE == 0 && !CG), "convective form: FP64 only");
+    static_assert(MODE != 2 || std::is_same<T, double>::value, "three-phase coefficients: FP64 only");
     // x stays resident (Dirichlet rows y = x and the CG epilogue read it);
     // phi (and the velocity) and then the cell contributions share the
     // second region.
@@ -229,8 +289,9 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     const Brick br(m, threadIdx.x);
     T *xs = lds;
     T *ps = lds + BNB;
-    if (MODE == 0) br.load_fields(m, x, xs, (const T *)a.phi, ps);
+    if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
     else br.load_fields(m, x, xs);
+    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + BNB, false);
     if constexpr (CONV != 0) {
         const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
         for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, ps + (c + 1) * BNB, false);
@@ -247,7 +308,9 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         heat_conv_cell_apply<CONV == 2, HK>(br, m, a, ps, ps + BNB, u);
     } else {
         T cm[27], ck[27];
-        if (MODE == 0) {
+        if constexpr (MODE == 2) {
+            heat_cell_coeffs3<HK>(br, m, a, (const double *)ps, (const double *)ps + BNB, cm, ck);
+        } else if (MODE == 0) {
             T ph[27];
             br.gather27(ps, ph);
             interp3(ph);
@@ -315,8 +378,10 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     // (they record its start and end, not the neighbouring queue packets).
     hipEvent_t ev0 = t ? t->start : nullptr, ev1 = t ? t->stop : nullptr;
     if (a.conv && (fp32 || cg || a.mode != 0 || !a.u0)) return hipErrorInvalidValue;
+    if (a.mode == 2 && fp32) return hipErrorInvalidValue;
     // (convective form, precision, coefficient mode, Heaviside form, CG epilogue)
-    const int key = (a.conv << 4) | (fp32 ? 8 : 0) | (a.mode ? 4 : (a.hkind ? 2 : 0)) | (cg ? 1 : 0);
+    const int hk = a.mode == 1 ? 0 : (a.hkind ? 1 : 0);
+    const int key = (a.conv << 5) | (fp32 ? 16 : 0) | (a.mode << 2) | (hk << 1) | (cg ? 1 : 0);
     switch (key) {
 #define HEAT_CASE(K, T, MODE, HK, CGF, CV)                                                                    \
     case K:                                                                                                   \
@@ -333,13 +398,17 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
         HEAT_CASE(3, double, 0, 1, true, 0)
         HEAT_CASE(4, double, 1, 0, false, 0)
         HEAT_CASE(5, double, 1, 0, true, 0)
-        HEAT_CASE(8, float, 0, 0, false, 0)
-        HEAT_CASE(10, float, 0, 1, false, 0)
-        HEAT_CASE(12, float, 1, 0, false, 0)
-        HEAT_CASE(16, double, 0, 0, false, 1)
-        HEAT_CASE(18, double, 0, 1, false, 1)
-        HEAT_CASE(32, double, 0, 0, false, 2)
-        HEAT_CASE(34, double, 0, 1, false, 2)
+        HEAT_CASE(8, double, 2, 0, false, 0)
+        HEAT_CASE(9, double, 2, 0, true, 0)
+        HEAT_CASE(10, double, 2, 1, false, 0)
+        HEAT_CASE(11, double, 2, 1, true, 0)
+        HEAT_CASE(16, float, 0, 0, false, 0)
+        HEAT_CASE(18, float, 0, 1, false, 0)
+        HEAT_CASE(20, float, 1, 0, false, 0)
+        HEAT_CASE(32, double, 0, 0, false, 1)
+        HEAT_CASE(34, double, 0, 1, false, 1)
+        HEAT_CASE(64, double, 0, 0, false, 2)
+        HEAT_CASE(66, double, 0, 1, false, 2)
 #undef HEAT_CASE
     default:
         return hipErrorInvalidValue;
@@ -444,7 +513,8 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     constexpr int LDS_T = (STAGE > 27 * BNT ? STAGE : 27 * BNT);
     __shared__ T lds[LDS_T];
     const Brick br(m, threadIdx.x);
-    if (MODE == 0) br.load(m, (const T *)a.phi, lds, false);
+    if (MODE != 1) br.load(m, (const T *)a.phi, lds, false);
+    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, lds + BNB, false);
     if constexpr (CONV) {
         const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
         for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, lds + (c + 1) * BNB, false);
@@ -454,7 +524,12 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     const T am_w = CONV ? vol : T(a.am) * vol, ak_w = T(a.ak) * vol;
     const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T cm[27], ck[27];
-    if (MODE == 0) {
+    if constexpr (MODE == 2) {
+        heat_cell_coeffs3<HK>(br, m, a, (const double *)lds, (const double *)lds + BNB, cm, ck);
+        // heat_cell_diag takes the stiffness factor for the true derivatives (no 1/r^2)
+#pragma unroll
+        for (int q = 0; q < 27; ++q) ck[q] *= kR * kR;
+    } else if (MODE == 0) {
         T ph[27];
         br.gather27(lds, ph);
         interp3(ph);
@@ -499,7 +574,11 @@ hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag
         if (a.hkind == 1) heat_diag_kernel<double, 0, 1, true><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
         else heat_diag_kernel<double, 0, 0, true><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
     } else {
-        if (a.mode == 1) heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+        if (a.mode == 2) {
+            if (a.hkind == 1) heat_diag_kernel<double, 2, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+            else heat_diag_kernel<double, 2, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+        } else if (a.mode == 1)
+            heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
         else if (a.hkind == 1) heat_diag_kernel<double, 0, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
         else heat_diag_kernel<double, 0, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
     }

@@ -20,12 +20,17 @@ struct HeatArgs {
     int conv;        // convective term: 0 none, 1 A, 2 A^T (FP64, mode 0)
     double ac;       // alpha_c
     const double *u0; // nodal velocity [3][n_nodes] (conv != 0)
+    // mode 2: three phases at the frozen nodal temperature tc, and/or the
+    // Tanasawa penalty (FP64)
+    double k_s, rc_s, T_sol, T_liq, penalty;
+    const double *tc;
 };
 
 // Interface heat sources as the kernel takes them (scalars formed on the host).
 struct SourceArgs {
-    int terms;                 // bit 0 evaporative cooling, bit 1 laser heat flux
+    int terms;                 // bit 0 evaporative cooling, bit 1 laser heat flux, bit 2 penalty right-hand side
     double alpha_v, T_boil, h_v; // Tanasawa coefficient, boiling temperature, latent heat
+    double penalty;            // Tanasawa penalty beta (bit 2: beta T_v delta_rcp)
     double peak, inv_r2;       // 2 chi P / (pi r^2), 1 / r^2
     double focus[3], dir[3];   // beam axis point and unit direction
     double c_rcp;              // 3 / (rc_g^2 + rc_l rc_g + rc_l^2)
@@ -38,6 +43,9 @@ struct OseenArgs {
     double am, ac, av;
     double rho_l, rho_g, mu_l, mu_g;
     const double *phi, *u0;
+    // three phases at the frozen nodal temperature tc (null: two phases)
+    double rho_s, mu_s, T_sol, T_liq, darcy_C, darcy_b;
+    const double *tc;
 };
 
 // Device state of a CG solve; scalars never leave the device during the

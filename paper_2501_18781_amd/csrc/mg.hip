@@ -428,8 +428,9 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
     mf_status st = check_op(c, op);
     if (st) return st;
     if (!prm) return fail(c, MF_ERR_ARG, "null multigrid parameters");
-    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET || op->u0)
-        return fail(c, MF_ERR_ARG, "multigrid needs an FP64 heat operator in LEVELSET mode without convection");
+    if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET || op->u0 ||
+        op->T_coef || op->penalty != 0.0)
+        return fail(c, MF_ERR_ARG, "multigrid needs an FP64 two-phase heat operator in LEVELSET mode without convection");
     if (prm->coarse_cells < 1 || prm->degree < 1 || !(prm->smoothing_range > 1.0) || prm->eig_steps < 1 ||
         !(prm->eig_safety >= 1.0) || !(prm->coarse_rtol > 0.0) || prm->coarse_maxit < 1)
         return fail(c, MF_ERR_ARG, "invalid multigrid parameters");

@@ -95,10 +95,19 @@ template <int D> __device__ __forceinline__ void conv_any(bool tr, const double 
     else conv_forward<double, D>(u, rw, w, s, acc);
 }
 
+// Solid fraction (eq. solid_fraction) and smooth indicator H_s (eq. heaviside_sl).
+__device__ __forceinline__ double solid_fraction(const OseenArgs &a, double T)
+{
+    return fmin(fmax((a.T_liq - T) / (a.T_liq - a.T_sol), 0.0), 1.0);
+}
+__device__ __forceinline__ double solid_indicator(double fs) { return fs * fs * (3.0 - 2.0 * fs); }
+
 // One component C of the Oseen operator on one cell; result (nodal) in acc.
-template <int C, int HK, bool TR>
+// TP: three phases at the frozen temperature staged at tcs, with the Darcy
+// damping of the solid added to the mass term.
+template <int C, int HK, bool TR, bool TP>
 __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, const KMesh &m, const double *ps,
-                                           const double *us, const double *u0s, double *acc)
+                                           const double *us, const double *u0s, const double *tcs, double *acc)
 {
     const double vol = m.hx * m.hy * m.hz;
     const double sdir[3] = {1.0 / (kR * m.hx), 1.0 / (kR * m.hy), 1.0 / (kR * m.hz)};
@@ -106,13 +115,30 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
     br.gather27(ps, rw);
     interp3(rw);
     heaviside27<HK>(a, rw);
-#pragma unroll
-    for (int q = 0; q < 27; ++q) rw[q] = vol * gauss_weight(q) / (rw[q] / a.rho_l + (1.0 - rw[q]) / a.rho_g);
     double u[27];
+    if constexpr (!TP) {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) rw[q] = vol * gauss_weight(q) / (rw[q] / a.rho_l + (1.0 - rw[q]) / a.rho_g);
+    }
     br.gather27(us + C * BNB, u);
     interp3(u);
+    if constexpr (TP) {
+        double t[27];
+        br.gather27(tcs, t);
+        interp3(t);
 #pragma unroll
-    for (int q = 0; q < 27; ++q) acc[q] = a.am * rw[q] * u[q];
+        for (int q = 0; q < 27; ++q) {
+            const double fs = solid_fraction(a, t[q]), Hs = solid_indicator(fs);
+            const double rho_sl = Hs * a.rho_s + (1.0 - Hs) * a.rho_l;
+            const double W = vol * gauss_weight(q);
+            rw[q] = W / (rw[q] / rho_sl + (1.0 - rw[q]) / a.rho_g);
+            const double darcy = a.darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + a.darcy_b);
+            acc[q] = (a.am * rw[q] + darcy * W) * u[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) acc[q] = a.am * rw[q] * u[q];
+    }
     {
         double w[27];
         auto velocity = [&](int d) {
@@ -135,8 +161,20 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
     br.gather27(ps, nu);
     interp3(nu);
     heaviside27<HK>(a, nu);
+    if constexpr (TP) {
+        double t[27];
+        br.gather27(tcs, t);
+        interp3(t);
 #pragma unroll
-    for (int q = 0; q < 27; ++q) nu[q] = a.av * vol * gauss_weight(q) * (a.mu_g + nu[q] * (a.mu_l - a.mu_g));
+        for (int q = 0; q < 27; ++q) {
+            const double Hs = solid_indicator(solid_fraction(a, t[q]));
+            const double mu = nu[q] * (Hs * a.mu_s + (1.0 - Hs) * a.mu_l) + (1.0 - nu[q]) * a.mu_g;
+            nu[q] = a.av * vol * gauss_weight(q) * mu;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) nu[q] = a.av * vol * gauss_weight(q) * (a.mu_g + nu[q] * (a.mu_l - a.mu_g));
+    }
     double e[27];
     auto cross = [&](auto D) {
         constexpr int d = decltype(D)::value;
@@ -160,26 +198,28 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
 
 // One workgroup of three wavefronts per brick: wave c computes velocity
 // component c of every cell, from one shared staging of phi, x and u0.
-template <int HK, bool TR>
+template <int HK, bool TR, bool TP>
 __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, const double *__restrict__ x,
                                                           double *__restrict__ y, double *__restrict__ face)
 {
-    // staging: phi, x (3 components), u0 (3 components); then the cell
-    // contributions of the 3 components
-    constexpr int STAGE = 7 * BNB, CONTRIB = 3 * 27 * BNT;
+    // staging: phi, x (3 components), u0 (3 components) and, with three
+    // phases, the frozen temperature; then the cell contributions of the 3
+    // components
+    constexpr int STAGE = (TP ? 8 : 7) * BNB, CONTRIB = 3 * 27 * BNT;
     __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
     const int comp = threadIdx.x / BNT; // uniform over a wavefront
     const Brick br(m, threadIdx.x % BNT);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    double *ps = lds, *us = lds + BNB, *u0s = lds + 4 * BNB;
+    double *ps = lds, *us = lds + BNB, *u0s = lds + 4 * BNB, *tcs = lds + 7 * BNB;
     if (comp == 0) br.load(m, a.phi, ps, false);
+    if (TP && comp == 1) br.load(m, a.tc, tcs, false);
     br.load(m, x + comp * nn, us + comp * BNB, true);
     br.load(m, a.u0 + comp * nn, u0s + comp * BNB, false);
     __syncthreads();
     double acc[27];
-    if (comp == 0) oseen_cell<0, HK, TR>(br, a, m, ps, us, u0s, acc);
-    else if (comp == 1) oseen_cell<1, HK, TR>(br, a, m, ps, us, u0s, acc);
-    else oseen_cell<2, HK, TR>(br, a, m, ps, us, u0s, acc);
+    if (comp == 0) oseen_cell<0, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
+    else if (comp == 1) oseen_cell<1, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
+    else oseen_cell<2, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
     __syncthreads(); // staging no longer read
     double *E = lds + comp * 27 * BNT;
     br.store_cell(E, acc);
@@ -217,12 +257,16 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
         if (e != hipSuccess) return e;
     }
     double *fb = (double *)face;
-    const int key = (a.hkind ? 2 : 0) | (transpose ? 1 : 0);
+    const int key = (a.tc ? 4 : 0) | (a.hkind ? 2 : 0) | (transpose ? 1 : 0);
     switch (key) {
-    case 0: oseen_apply_kernel<0, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
-    case 1: oseen_apply_kernel<0, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
-    case 2: oseen_apply_kernel<1, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
-    case 3: oseen_apply_kernel<1, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 0: oseen_apply_kernel<0, false, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 1: oseen_apply_kernel<0, true, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 2: oseen_apply_kernel<1, false, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 3: oseen_apply_kernel<1, true, false><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 4: oseen_apply_kernel<0, false, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 5: oseen_apply_kernel<0, true, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 6: oseen_apply_kernel<1, false, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
+    case 7: oseen_apply_kernel<1, true, true><<<nb, ONT, 0, s>>>(m, a, x, y, fb); break;
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
@@ -240,29 +284,43 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
 // by direct loops over the Gauss points (setup only), one pass per entry.
 // Shared nodes are added with FP64 atomics into a cleared output.
 // ---------------------------------------------------------------------------
-template <int HK>
+template <int HK, bool TP>
 __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, double *__restrict__ blocks)
 {
-    constexpr int STAGE = 4 * BNB, CONTRIB = 27 * BNT;
+    constexpr int STAGE = (TP ? 5 : 4) * BNB, CONTRIB = 27 * BNT;
     __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
     __shared__ double E[27 * BNT];
     const Brick br(m, threadIdx.x);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    double *ps = lds, *u0s = lds + BNB;
+    double *ps = lds, *u0s = lds + BNB, *tcs = lds + 4 * BNB;
     br.load(m, a.phi, ps, false);
     for (int c = 0; c < 3; ++c) br.load(m, a.u0 + c * nn, u0s + c * BNB, false);
+    if (TP) br.load(m, a.tc, tcs, false);
     __syncthreads();
     const double vol = m.hx * m.hy * m.hz;
     const double ih[3] = {1.0 / m.hx, 1.0 / m.hy, 1.0 / m.hz};
-    double rw[27], nu[27], w0[27], w1[27], w2[27];
+    double rw[27], nu[27], w0[27], w1[27], w2[27], dw[27]; // rho W, alpha_v mu W, velocity, Darcy W
     br.gather27(ps, rw);
     interp3(rw);
     heaviside27<HK>(a, rw);
+    if (TP) {
+        br.gather27(tcs, dw);
+        interp3(dw);
+    }
     for (int q = 0; q < 27; ++q) {
         const double H = rw[q];
         const double W = vol * gauss_weight(q);
-        rw[q] = W / (H / a.rho_l + (1.0 - H) / a.rho_g);
-        nu[q] = a.av * W * (a.mu_g + H * (a.mu_l - a.mu_g));
+        if (TP) {
+            const double fs = solid_fraction(a, dw[q]), Hs = solid_indicator(fs);
+            const double rho_sl = Hs * a.rho_s + (1.0 - Hs) * a.rho_l;
+            rw[q] = W / (H / rho_sl + (1.0 - H) / a.rho_g);
+            nu[q] = a.av * W * (H * (Hs * a.mu_s + (1.0 - Hs) * a.mu_l) + (1.0 - H) * a.mu_g);
+            dw[q] = W * a.darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + a.darcy_b);
+        } else {
+            rw[q] = W / (H / a.rho_l + (1.0 - H) / a.rho_g);
+            nu[q] = a.av * W * (a.mu_g + H * (a.mu_l - a.mu_g));
+            dw[q] = 0.0;
+        }
     }
     br.gather27(u0s, w0);
     interp3(w0);
@@ -291,7 +349,7 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
                                      nx * ny * Gd[qc][ic] * ih[2]};
                 double v = nu[q] * g[cp] * g[c];
                 if (c == cp) {
-                    v += a.am * rw[q] * n * n + a.ac * rw[q] * n * (w0[q] * g[0] + w1[q] * g[1] + w2[q] * g[2]) +
+                    v += (a.am * rw[q] + dw[q]) * n * n + a.ac * rw[q] * n * (w0[q] * g[0] + w1[q] * g[1] + w2[q] * g[2]) +
                          nu[q] * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
                 }
                 sacc += v;
@@ -325,8 +383,13 @@ hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *bloc
     const unsigned nb = (unsigned)n_bricks(m);
     hipError_t e = vfill(blocks, 0.0, 9 * (int64_t)m.NX * m.NY * m.NZ, 0, s);
     if (e != hipSuccess) return e;
-    if (a.hkind == 0) oseen_block_kernel<0><<<nb, BNT, 0, s>>>(m, a, blocks);
-    else oseen_block_kernel<1><<<nb, BNT, 0, s>>>(m, a, blocks);
+    if (a.tc) {
+        if (a.hkind == 0) oseen_block_kernel<0, true><<<nb, BNT, 0, s>>>(m, a, blocks);
+        else oseen_block_kernel<1, true><<<nb, BNT, 0, s>>>(m, a, blocks);
+    } else {
+        if (a.hkind == 0) oseen_block_kernel<0, false><<<nb, BNT, 0, s>>>(m, a, blocks);
+        else oseen_block_kernel<1, false><<<nb, BNT, 0, s>>>(m, a, blocks);
+    }
     return hipGetLastError();
 }
 

@@ -4,8 +4,10 @@
 // with the Tanasawa mass flux, eq. mDotTanasawa; Sec. 4: the Gaussian laser
 // heat flux, eq. laser_gauss):
 //   b_i = sum_cells sum_q W_q N_i(x_q) s(x_q),
-//   s   = [ -alpha_v (T - T_v) h_v |grad phi|
+//   s   = [ -alpha_v (T - T_v) h_v |grad phi| + beta T_v |grad phi|
 //           + peak <grad phi . e_L> exp(-2 d_L^2 / r^2) ] H'(phi) rc(phi) c_rcp
+// (the second term, the right-hand side of the Tanasawa penalty of App. C,
+// only on request)
 // (the laser factor <-n . e_L> |grad H| with n = -grad phi/|grad phi| is
 // H' <grad phi . e_L>, so no division by |grad phi| is needed).
 //
@@ -56,8 +58,9 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
     grad_dir(std::integral_constant<int, 0>{});
     grad_dir(std::integral_constant<int, 1>{});
     grad_dir(std::integral_constant<int, 2>{});
-    // evaporative part, -alpha_v (T - T_v) h_v |grad phi|, in place of |grad phi|^2
-    const bool evap = sa.terms & 1, laser = sa.terms & 2;
+    // evaporative part, -alpha_v (T - T_v) h_v |grad phi|, and the penalty
+    // right-hand side, beta T_v |grad phi|, in place of |grad phi|^2
+    const bool evap = sa.terms & 1, laser = sa.terms & 2, pen = sa.terms & 4;
     pin27(ph);
     pin27(ge);
     pin27(gn);
@@ -66,7 +69,9 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
         br.gather27(ts, Tq);
         interp3(Tq);
 #pragma unroll
-        for (int q = 0; q < 27; ++q) gn[q] = evap ? -sa.alpha_v * (Tq[q] - sa.T_boil) * sa.h_v * sqrt(gn[q]) : 0.0;
+        for (int q = 0; q < 27; ++q)
+            gn[q] = ((evap ? -sa.alpha_v * (Tq[q] - sa.T_boil) * sa.h_v : 0.0) + (pen ? sa.penalty * sa.T_boil : 0.0)) *
+                    sqrt(gn[q]);
     }
     pin27(gn);
 
@@ -124,7 +129,7 @@ hipError_t heat_sources(const KMesh &m, const HeatArgs &a, const SourceArgs &sa,
                         void *face, hipStream_t s)
 {
     const unsigned nb = (unsigned)n_bricks(m);
-    if (!face || !T || !b || a.mode != 0) return hipErrorInvalidValue;
+    if (!face || !T || !b || a.mode == 1) return hipErrorInvalidValue;
     if (a.hkind == 1) heat_source_kernel<1><<<nb, BNT, 0, s>>>(m, a, sa, T, b, (double *)face);
     else heat_source_kernel<0><<<nb, BNT, 0, s>>>(m, a, sa, T, b, (double *)face);
     hipError_t e = hipGetLastError();

@@ -48,7 +48,10 @@ class OperatorDesc(ctypes.Structure):
                 ("rc_l", ctypes.c_double), ("rc_g", ctypes.c_double), ("rho_l", ctypes.c_double),
                 ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
                 ("phi", ctypes.c_void_p), ("k_q", ctypes.c_void_p), ("rc_q", ctypes.c_void_p),
-                ("u0", ctypes.c_void_p)]
+                ("u0", ctypes.c_void_p), ("k_s", ctypes.c_double), ("rc_s", ctypes.c_double),
+                ("rho_s", ctypes.c_double), ("mu_s", ctypes.c_double), ("T_sol", ctypes.c_double),
+                ("T_liq", ctypes.c_double), ("darcy_C", ctypes.c_double), ("darcy_b", ctypes.c_double),
+                ("penalty", ctypes.c_double), ("T_coef", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -67,7 +70,7 @@ class MGParams(ctypes.Structure):
                 ("coarse_maxit", ctypes.c_int32)]
 
 
-MF_SRC_EVAPORATION, MF_SRC_LASER = 1, 2
+MF_SRC_EVAPORATION, MF_SRC_LASER, MF_SRC_PENALTY = 1, 2, 4
 
 
 class SourcesDesc(ctypes.Structure):
@@ -203,11 +206,12 @@ class Operator:
     def __init__(self, ctx: Context, kind: int, precision: int, coeff_mode: int = MF_COEFF_LEVELSET,
                  heaviside: int = MF_H_LINEAR, eps: float = 0.0, alpha_m=0.0, alpha_k=0.0, alpha_c=0.0, alpha_v=0.0,
                  k_l=0.0, k_g=0.0, rc_l=0.0, rc_g=0.0, rho_l=1.0, rho_g=1.0, mu_l=0.0, mu_g=0.0,
-                 phi=None, k_q=None, rc_q=None, u0=None):
+                 phi=None, k_q=None, rc_q=None, u0=None, T_coef=None, k_s=0.0, rc_s=0.0, rho_s=1.0, mu_s=0.0,
+                 T_sol=0.0, T_liq=1.0, darcy_C=0.0, darcy_b=1.0, penalty=0.0):
         self.ctx = ctx
         self.dtype = torch.float64 if precision == MF_FP64 else torch.float32
         nn, nq = ctx.n_nodes, ctx.n_cells * 27
-        self.tensors = (phi, k_q, rc_q, u0)
+        self.tensors = (phi, k_q, rc_q, u0, T_coef)
         d = OperatorDesc()
         d.kind, d.precision, d.coeff_mode, d.heaviside = kind, precision, coeff_mode, heaviside
         d.eps, d.alpha_m, d.alpha_k, d.alpha_c, d.alpha_v = eps, alpha_m, alpha_k, alpha_c, alpha_v
@@ -217,6 +221,9 @@ class Operator:
         d.k_q = _ptr(k_q, nq, self.dtype, "k_q")
         d.rc_q = _ptr(rc_q, nq, self.dtype, "rc_q")
         d.u0 = _ptr(u0, 3 * nn, self.dtype, "u0")
+        d.k_s, d.rc_s, d.rho_s, d.mu_s = k_s, rc_s, rho_s, mu_s
+        d.T_sol, d.T_liq, d.darcy_C, d.darcy_b, d.penalty = T_sol, T_liq, darcy_C, darcy_b, penalty
+        d.T_coef = _ptr(T_coef, nn, self.dtype, "T_coef")
         self.desc = d
         self.kind = kind
         self.n_dofs = 3 * nn if kind == MF_OSEEN else nn
@@ -233,25 +240,36 @@ class Operator:
         return o
 
 
-def heat_operator(ctx: Context, params, phi=None, k_q=None, rc_q=None, precision=MF_FP64, u0=None,
+def heat_operator(ctx: Context, params, phi=None, k_q=None, rc_q=None, precision=MF_FP64, u0=None, T_coef=None,
                   **override) -> Operator:
     """Heat operator rc/dt M + K(k) from a parameter object (k_l, k_g, rc_l,
     rc_g, alpha_m, alpha_k, heaviside, eps); with a nodal velocity u0
     ([3][n_nodes], FP64, level-set mode) it gains the convective term
-    alpha_c C(rc, u0) and is no longer symmetric."""
+    alpha_c C(rc, u0) and is no longer symmetric; with a nodal temperature
+    T_coef the coefficients are the three-phase ones at that temperature
+    (k_s, rc_s, T_sol, T_liq); a nonzero `penalty` adds the Tanasawa penalty."""
     g = lambda k: override.get(k, getattr(params, k))
+    opt = lambda k, d: float(override.get(k, getattr(params, k, d)))
     mode = MF_COEFF_LEVELSET if phi is not None else MF_COEFF_QUAD
-    ac = float(override.get("alpha_c", getattr(params, "alpha_c", 0.0))) if u0 is not None else 0.0
+    ac = opt("alpha_c", 0.0) if u0 is not None else 0.0
     return Operator(ctx, MF_HEAT, precision, mode, int(g("heaviside")), float(g("eps")),
                     alpha_m=float(g("alpha_m")), alpha_k=float(g("alpha_k")), alpha_c=ac, k_l=g("k_l"),
-                    k_g=g("k_g"), rc_l=g("rc_l"), rc_g=g("rc_g"), phi=phi, k_q=k_q, rc_q=rc_q, u0=u0)
+                    k_g=g("k_g"), rc_l=g("rc_l"), rc_g=g("rc_g"), phi=phi, k_q=k_q, rc_q=rc_q, u0=u0,
+                    T_coef=T_coef, k_s=opt("k_s", 0.0), rc_s=opt("rc_s", 0.0), T_sol=opt("T_sol", 0.0),
+                    T_liq=opt("T_liq", 1.0), penalty=opt("penalty", 0.0))
 
 
-def oseen_operator(ctx: Context, params, phi, u0, **override) -> Operator:
+def oseen_operator(ctx: Context, params, phi, u0, T_coef=None, **override) -> Operator:
+    """Linearized momentum operator; with a nodal temperature T_coef the
+    coefficients are the three-phase ones at that temperature (rho_s, mu_s,
+    T_sol, T_liq) and the Darcy damping of the solid (darcy_C, darcy_b) is added."""
     g = lambda k: override.get(k, getattr(params, k))
+    opt = lambda k, d: float(override.get(k, getattr(params, k, d)))
     return Operator(ctx, MF_OSEEN, MF_FP64, MF_COEFF_LEVELSET, int(g("heaviside")), float(g("eps")),
                     alpha_m=float(g("alpha_m")), alpha_c=float(g("alpha_c")), alpha_v=float(g("alpha_v")),
-                    rho_l=g("rho_l"), rho_g=g("rho_g"), mu_l=g("mu_l"), mu_g=g("mu_g"), phi=phi, u0=u0)
+                    rho_l=g("rho_l"), rho_g=g("rho_g"), mu_l=g("mu_l"), mu_g=g("mu_g"), phi=phi, u0=u0,
+                    T_coef=T_coef, rho_s=opt("rho_s", 1.0), mu_s=opt("mu_s", 0.0), T_sol=opt("T_sol", 0.0),
+                    T_liq=opt("T_liq", 1.0), darcy_C=opt("darcy_C", 0.0), darcy_b=opt("darcy_b", 1.0))
 
 
 # ---------------------------------------------------------------------------

@@ -37,11 +37,29 @@ def test_binding_matches_header():
     assert sorted(mf._SIGS) == declared_functions()
 
 
-def test_struct_layouts_match_header():
-    # offsets the C compiler gives the descriptor structs (natural alignment)
+def test_struct_layouts_match_header(tmp_path):
+    # every ctypes mirror has the size and field offsets the C compiler gives
+    # the header's struct of the same name
+    import shutil
+    import subprocess
     from paper_2501_18781_amd import mf
-    assert ctypes.sizeof(mf.MeshDesc) == 64
-    assert mf.OperatorDesc.phi.offset == 16 + 13 * 8
-    assert ctypes.sizeof(mf.OperatorDesc) == 16 + 13 * 8 + 4 * 8
-    assert ctypes.sizeof(mf.SolveInfo) == 24
-    assert mf.MGParams.lambda_max.offset == 32 and ctypes.sizeof(mf.MGParams) == 56
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("mf_mesh", mf.MeshDesc), ("mf_operator", mf.OperatorDesc), ("mf_solve_info", mf.SolveInfo),
+             ("mf_mg_params", mf.MGParams), ("mf_heat_sources", mf.SourcesDesc)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mf.h"', "int main(void) {"]
+    expect = []
+    for cname, py in pairs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(py))
+        for fname, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+            expect.append(getattr(py, fname).offset)
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect

@@ -1,0 +1,285 @@
+"""GPU three-phase coefficients (Sec. 3.2-3.3), the Darcy damping of the
+solid (eq. darcy_damping_force) and the Tanasawa penalty (App. C) vs the
+FP64 oracle, through the C ABI.
+
+The coefficients are evaluated at a frozen nodal temperature that crosses the
+melting range (solid, mushy and liquid layers) and a level set that cuts it
+(gas above the interface).  Bar (FP64): normwise relative error <= 1e-12 for
+applies, transposes, diagonals, nodal blocks and the penalty right-hand side;
+solves against the sparse direct solution within kappa * rtol.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2501_18781_amd import mf
+from paper_2501_18781_amd import picard
+from paper_2501_18781_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+BETA = 2.0e9  # penalty strength: its term is of the order of the mass term near the interface
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def relerr(a, b):
+    a = a.detach().cpu().double().numpy() if isinstance(a, torch.Tensor) else a
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def heat_case(n, dirichlet, hkind=0, penalty=0.0):
+    mesh = W.Mesh(n, dirichlet=dirichlet)
+    eps = 2.0 / max(n)
+    p = W.HeatParams(heaviside=hkind, eps=eps if hkind else 0.0, penalty=penalty)
+    phi = W.phi_sphere(mesh, 0.35, eps, center=(0.5, 0.5, 0.3))
+    return mesh, p, phi, W.melt_temperature(mesh)
+
+
+def oseen_case(n, dirichlet, hkind=0):
+    mesh = W.Mesh(n, dirichlet=dirichlet)
+    eps = 2.0 / max(n)
+    p = W.OseenParams(heaviside=hkind, eps=eps if hkind else 0.0)
+    phi = W.phi_wavy_plane(mesh, 0.7, 0.05, eps)
+    return mesh, p, phi, W.taylor_green(mesh), W.melt_temperature(mesh)
+
+
+MESHES = [((1, 1, 1), 0), ((3, 3, 3), W.ALL_FACES), ((5, 3, 7), W.FACE_XLO | W.FACE_ZHI),
+          ((9, 9, 9), W.ALL_FACES), ((8, 8, 8), 0), ((17, 10, 5), W.FACE_YHI | W.FACE_XHI)]
+
+
+def test_melt_field_spans_the_three_phases():
+    mesh, p, phi, Tc = heat_case((9, 9, 9), 0)
+    assert Tc.min() < p.T_sol < p.T_liq < Tc.max()
+    assert phi.min() < 0.0 < phi.max()
+
+
+@pytest.mark.parametrize("n,dirichlet", MESHES)
+@pytest.mark.parametrize("penalty", [0.0, BETA])
+def test_heat_three_phase_apply_matches_oracle(gpu, n, dirichlet, penalty):
+    mesh, p, phi, Tc = heat_case(n, dirichlet, penalty=penalty)
+    print(f"three-phase heat n={n} dirichlet={dirichlet} penalty={penalty}", flush=True)
+    x = W.uniform(0, mesh.n_nodes)
+    A = O.heat_matrix(mesh, p, phi=phi, Tc=Tc)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc))
+    y = torch.empty(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    mf.operator_apply(op, dev(x), y)
+    assert relerr(y, A @ x) <= TOL64
+    mf.operator_apply_transpose(op, dev(x), y)
+    assert relerr(y, A @ x) <= TOL64
+    # conduction alone: the three-phase k shows, the mass term does not hide it
+    K = O.heat_matrix(mesh, p, phi=phi, Tc=Tc, alpha_m=0.0, penalty=0.0)
+    mf.operator_apply(op.with_alphas(alpha_m=0.0, penalty=0.0), dev(x), y)
+    assert relerr(y, K @ x) <= TOL64
+
+
+@pytest.mark.parametrize("hkind", [0, 1])
+def test_heat_penalty_alone_and_without_temperature(gpu, hkind):
+    # the penalty term on its own (alpha_m = alpha_k = 0), with and without the
+    # three-phase coefficients: it depends on phi only
+    mesh, p, phi, Tc = heat_case((7, 6, 8), W.ALL_FACES, hkind=hkind, penalty=BETA)
+    x = W.uniform(1, mesh.n_nodes)
+    ctx = mf.Context(mesh)
+    y = torch.empty(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    R = O.heat_matrix(mesh, p, phi=phi, alpha_m=0.0, alpha_k=0.0)
+    assert R.nnz > 0 and abs(R @ x).max() > 0.0
+    for tc in (None, dev(Tc)):
+        op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=tc).with_alphas(alpha_m=0.0, alpha_k=0.0)
+        mf.operator_apply(op, dev(x), y)
+        assert relerr(y, R @ x) <= TOL64
+    # the whole operator with the sine Heaviside
+    A = O.heat_matrix(mesh, p, phi=phi, Tc=Tc)
+    mf.operator_apply(mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc)), dev(x), y)
+    assert relerr(y, A @ x) <= TOL64
+
+
+@pytest.mark.parametrize("n,dirichlet", MESHES[1:4])
+@pytest.mark.parametrize("hkind", [0, 1])
+def test_heat_three_phase_diagonal(gpu, n, dirichlet, hkind):
+    mesh, p, phi, Tc = heat_case(n, dirichlet, hkind=hkind, penalty=BETA)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc))
+    d = torch.empty(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    for o, kw in [(op, {}), (op.with_alphas(alpha_m=0.0), {"alpha_m": 0.0})]:
+        mf.operator_diagonal(o, d)
+        assert relerr(d, O.heat_matrix(mesh, p, phi=phi, Tc=Tc, **kw).diagonal()) <= TOL64, kw
+
+
+def test_heat_three_phase_full_size_sampled_rows(gpu):
+    # 64^3 cells (2.15M nodes), the heat benchmark mesh
+    mesh, p, phi, Tc = heat_case((64, 64, 64), W.ALL_FACES, penalty=BETA)
+    nn = mesh.n_nodes
+    x = W.uniform(0, nn)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc))
+    y = torch.empty(nn, dtype=torch.float64, device="cuda")
+    mf.operator_apply(op, dev(x), y)
+    rows = np.unique(np.concatenate([np.random.default_rng(9).integers(0, nn, 300), [0, nn - 1, nn // 2]]))
+    ref = O.heat_rows(mesh, p, x, rows, phi=phi, Tc=Tc)
+    assert np.abs(y.cpu().numpy()[rows] - ref).max() <= TOL64 * np.abs(ref).max()
+
+
+def test_heat_three_phase_cg_matches_direct_solve(gpu):
+    mesh, p, phi, Tc = heat_case((6, 6, 6), W.ALL_FACES, penalty=BETA)
+    A = O.heat_matrix(mesh, p, phi=phi, Tc=Tc)
+    xr = W.uniform(5, mesh.n_nodes)
+    b = A @ xr
+    ref = O.jacobi_cg(A, b, rtol=1e-8)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc))
+    x = torch.empty_like(dev(b))
+    info = mf.cg_solve(op, dev(b), x, 1e-8, 1000)
+    print(info, ref.iters, flush=True)
+    assert info.converged and abs(info.iters - ref.iters) <= 2
+    info = mf.cg_solve(op, dev(b), x, 1e-13, 2000)
+    assert info.converged and relerr(x, O.direct_solve(A, b)) <= 1e-10
+
+
+@pytest.mark.parametrize("n,dirichlet", [((2, 2, 2), W.ALL_FACES), ((3, 4, 5), 0), ((5, 5, 5), W.ALL_FACES),
+                                         ((9, 4, 6), W.FACE_XLO | W.FACE_YHI)])
+def test_oseen_three_phase_apply_and_transpose(gpu, n, dirichlet):
+    mesh, p, phi, u0, Tc = oseen_case(n, dirichlet)
+    print(f"three-phase oseen n={n} dirichlet={dirichlet}", flush=True)
+    x = W.uniform(1, 3 * mesh.n_nodes)
+    ctx = mf.Context(mesh)
+    y = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device="cuda")
+    op = mf.oseen_operator(ctx, p, dev(phi), dev(u0), T_coef=dev(Tc))
+    for o, kw in [(op, {}), (op.with_alphas(alpha_c=0.0, alpha_v=0.0), {"alpha_c": 0.0, "alpha_v": 0.0})]:
+        A = O.oseen_matrix(mesh, p, phi, u0, Tc=Tc, **kw)
+        mf.operator_apply(o, dev(x), y)
+        assert relerr(y, A @ x) <= TOL64, kw
+        mf.operator_apply_transpose(o, dev(x), y)
+        assert relerr(y, A.T @ x) <= TOL64, kw
+
+
+def test_oseen_darcy_term_alone(gpu):
+    # alpha_m = alpha_c = alpha_v = 0 leaves the Darcy reaction of the solid only
+    mesh, p, phi, u0, Tc = oseen_case((5, 4, 6), W.ALL_FACES, hkind=1)
+    x = W.uniform(2, 3 * mesh.n_nodes)
+    kw = dict(alpha_m=0.0, alpha_c=0.0, alpha_v=0.0)
+    D = O.oseen_matrix(mesh, p, phi, u0, Tc=Tc, **kw)
+    assert abs(D @ x).max() > 0.0
+    ctx = mf.Context(mesh)
+    y = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device="cuda")
+    mf.operator_apply(mf.oseen_operator(ctx, p, dev(phi), dev(u0), T_coef=dev(Tc)).with_alphas(**kw), dev(x), y)
+    assert relerr(y, D @ x) <= TOL64
+
+
+@pytest.mark.parametrize("n,dirichlet", [((3, 3, 3), W.ALL_FACES), ((5, 4, 6), W.FACE_ZLO)])
+def test_oseen_three_phase_block_diagonal_and_gmres(gpu, n, dirichlet):
+    mesh, p, phi, u0, Tc = oseen_case(n, dirichlet)
+    A = O.oseen_matrix(mesh, p, phi, u0, Tc=Tc)
+    ctx = mf.Context(mesh)
+    op = mf.oseen_operator(ctx, p, dev(phi), dev(u0), T_coef=dev(Tc))
+    B = torch.empty(9 * mesh.n_nodes, dtype=torch.float64, device="cuda")
+    mf.operator_diagonal(op, B)
+    assert relerr(B.cpu().numpy().reshape(-1, 3, 3), O.block_jacobi(A, mesh.n_nodes).blocks) <= TOL64
+    b = A @ W.uniform(4, 3 * mesh.n_nodes)
+    x = torch.empty_like(dev(b))
+    info = mf.gmres_solve(op, dev(b), x, 1e-13, 2000, precond=mf.MF_PC_BLOCK_JACOBI, restart=30)
+    assert info.converged and relerr(x, O.direct_solve(A, b)) <= 1e-10
+
+
+def test_oseen_three_phase_full_size_sampled_rows(gpu):
+    # 48^3 cells, the Oseen benchmark mesh
+    mesh, p, phi, u0, Tc = oseen_case((48, 48, 48), W.ALL_FACES)
+    nn = mesh.n_nodes
+    x = W.uniform(1, 3 * nn)
+    ctx = mf.Context(mesh)
+    op = mf.oseen_operator(ctx, p, dev(phi), dev(u0), T_coef=dev(Tc))
+    y = torch.empty(3 * nn, dtype=torch.float64, device="cuda")
+    rows = np.unique(np.random.default_rng(11).integers(0, 3 * nn, 300))
+    for tr in (False, True):
+        (mf.operator_apply_transpose if tr else mf.operator_apply)(op, dev(x), y)
+        ref = O.oseen_rows(mesh, p, phi, u0, x, rows, transpose=tr, Tc=Tc)
+        assert np.abs(y.cpu().numpy()[rows] - ref).max() <= TOL64 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,dirichlet", [((3, 3, 3), W.ALL_FACES), ((9, 9, 9), 0), ((17, 10, 5), W.FACE_XHI)])
+def test_penalty_right_hand_side(gpu, n, dirichlet):
+    mesh, p, phi, Tc = heat_case(n, dirichlet, penalty=BETA)
+    sp = dataclasses.replace(W.SourceParams(), terms=mf.MF_SRC_PENALTY)
+    ref = O.heat_sources(mesh, p, sp, phi, Tc)
+    assert np.abs(ref).max() > 0.0
+    ctx = mf.Context(mesh)
+    b = torch.full((mesh.n_nodes,), 3.0, dtype=torch.float64, device="cuda")
+    mf.heat_source_rhs(mf.heat_operator(ctx, p, phi=dev(phi)), sp, None, b)
+    assert relerr(b, ref) <= TOL64
+    # with the other two terms, at the three-phase operator
+    sp3 = dataclasses.replace(sp, terms=7, radius=0.25)
+    mf.heat_source_rhs(mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc)), sp3, dev(Tc), b)
+    assert relerr(b, O.heat_sources(mesh, p, sp3, phi, Tc)) <= TOL64
+
+
+def oracle_picard(mesh, p, phi, T_old, sp, tol, maxit):
+    """Picard iteration of one implicit three-phase step with the oracle's
+    assembled matrices and direct solves."""
+    T = T_old.copy()
+    for k in range(maxit):
+        A = O.heat_matrix(mesh, p, phi=phi, Tc=T)
+        KR = O.heat_matrix(mesh, p, phi=phi, Tc=T, alpha_m=0.0)
+        b = O.heat_sources(mesh, p, sp, phi, T) if sp is not None else np.zeros_like(T)
+        Tn = T_old + O.direct_solve(A, b - KR @ T_old)
+        upd = np.linalg.norm(Tn - T) / np.linalg.norm(Tn)
+        T = Tn
+        if upd <= tol:
+            return T, k + 1
+    return T, maxit
+
+
+def test_picard_step_matches_oracle(gpu):
+    # insulated faces; a step of 100 s lets conduction and the penalty (which
+    # pulls the interface towards T_v) move T by ~50 K across the mushy layer,
+    # so the coefficients change between iterates (about seven Picard steps)
+    mesh, p, phi, T_old = heat_case((8, 8, 8), 0, penalty=BETA)
+    p = dataclasses.replace(p, dt=1e2)
+    sp = dataclasses.replace(W.SourceParams(), terms=7, radius=0.25)
+    ref, its = oracle_picard(mesh, p, phi, T_old, sp, 1e-11, 40)
+    assert 4 <= its < 40
+    ctx = mf.Context(mesh)
+    res = picard.heat_step(ctx, p, dev(phi), dev(T_old), sources=sp, tol=1e-11, maxit=40)
+    print(res.iterations, its, res.updates, res.cg_iterations, flush=True)
+    assert res.converged and abs(res.iterations - its) <= 1
+    assert relerr(res.T - dev(T_old), ref - T_old) <= 1e-9
+
+
+def test_three_phase_argument_errors(gpu):
+    mesh, p, phi, Tc = heat_case((4, 4, 4), W.ALL_FACES)
+    ctx = mf.Context(mesh)
+    n = mesh.n_nodes
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    with pytest.raises(mf.MFError, match="T_sol"):
+        mf.operator_apply(mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc), T_liq=p.T_sol), b, x)
+    with pytest.raises(mf.MFError, match="FP64"):
+        op32 = mf.heat_operator(ctx, p, phi=dev(phi, torch.float32), T_coef=dev(Tc, torch.float32),
+                                precision=mf.MF_FP32)
+        mf.operator_apply(op32, b.float(), x.float())
+    ones = torch.ones(mesh.n_cells * 27, dtype=torch.float64, device="cuda")
+    with pytest.raises(mf.MFError, match="LEVELSET"):
+        mf.operator_apply(mf.heat_operator(ctx, p, k_q=ones, rc_q=ones, T_coef=dev(Tc)), b, x)
+    op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc))
+    with pytest.raises(mf.MFError, match="two-phase"):
+        mf.Multigrid(op)
+    with pytest.raises(mf.MFError, match="two-phase"):
+        mf.heat_coeff_grad(op, b, b, b, dphi=torch.empty_like(b))
+    u0 = dev(W.taylor_green(mesh))
+    with pytest.raises(mf.MFError, match="convection"):
+        mf.operator_apply(mf.heat_operator(ctx, p, phi=dev(phi), u0=u0, T_coef=dev(Tc)), b, x)
+    q = W.OseenParams()
+    with pytest.raises(mf.MFError, match="darcy_b"):
+        op = mf.oseen_operator(ctx, q, dev(phi), u0, T_coef=dev(Tc), darcy_b=0.0)
+        mf.operator_apply(op, torch.ones(3 * n, dtype=torch.float64, device="cuda"),
+                          torch.empty(3 * n, dtype=torch.float64, device="cuda"))
+    with pytest.raises(mf.MFError, match="penalty"):
+        op = mf.oseen_operator(ctx, q, dev(phi), u0)
+        op = op.with_alphas(penalty=1.0)
+        mf.operator_apply(op, torch.ones(3 * n, dtype=torch.float64, device="cuda"),
+                          torch.empty(3 * n, dtype=torch.float64, device="cuda"))
