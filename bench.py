@@ -19,8 +19,10 @@ roofline   = the apply kernel alone (events around the kernel inside the
 cpu_baseline = the CPU oracle (assembled CSR, OpenMP) on the same workload.
 mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
              both to 1e-8, on 128^3 cells (257^3 nodes).
-oseen, heat_convection, heat_sources, gradient = the other operators, the
-             interface-flux right-hand side and the adjoint step.
+oseen, heat_convection, heat_sources, three_phase, gradient = the other
+             operators, the interface-flux right-hand side, the three-phase
+             coefficients with the Tanasawa penalty and Darcy damping (and one
+             Picard step), and the adjoint step.
 """
 from __future__ import annotations
 
@@ -86,6 +88,7 @@ def parse():
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-conv", action="store_true")
     p.add_argument("--no-sources", action="store_true")
+    p.add_argument("--no-three-phase", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -363,6 +366,7 @@ def main():
                           (args.no_oseen, "oseen", lambda: oseen_bench(dev)),
                           (args.no_conv, "heat_convection", lambda: heat_conv_bench(dev)),
                           (args.no_sources, "heat_sources", lambda: heat_sources_bench(dev)),
+                          (args.no_three_phase, "three_phase", lambda: three_phase_bench(dev)),
                           (args.no_grad, "gradient", lambda: grad_bench(dev))]:
         if flag:
             continue
@@ -558,6 +562,105 @@ def heat_sources_bench(dev, reps=50):
     out = {"cells": n, "nodes": nn, "us": t * 1e6, "dofs_per_s": nn / t, "algorithmic_gbs": 24 * nn / t / 1e9,
            "terms": "evaporative cooling (Tanasawa, local T) + Gaussian laser flux"}
     log(f"[bench]   assembly {t * 1e6:.1f} us ({24 * nn / t / 1e9:.0f} GB/s algorithmic)")
+    return out
+
+
+def _time_applies(ctx, fn, op, x, y, applies):
+    """Whole-apply and apply-kernel time (seconds per apply) of `applies`
+    back-to-back calls, after a warm-up."""
+    import torch
+    for _ in range(5):
+        fn(op, x, y)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    ctx.timing_read(reset=True)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(applies):
+        fn(op, x, y)
+    e1.record(s)
+    torch.cuda.synchronize()
+    kms, kl = ctx.timing_read(reset=True)
+    ctx.timing_enable(False)
+    return e0.elapsed_time(e1) * 1e-3 / applies, kms * 1e-3 / kl
+
+
+def three_phase_bench(dev, applies=50, beta=2.0e9):
+    """Three-phase coefficients at a frozen temperature crossing the melting
+    range (T = 1800 K + 600 K z):
+      heat, 64^3 cells with the sphere level set and the Tanasawa penalty
+      (beta = 2e9): apply (32 algorithmic bytes per node: x, phi, T, y),
+      Jacobi-CG to 1e-8 on b = A x_ref next to the two-phase operator's, and one
+      Picard step (dt = 1e-3, evaporation + laser + penalty right-hand side,
+      update 1e-10);
+      Oseen, 48^3 cells with the wavy-plane level set and Darcy damping:
+      apply and transpose (3 x 8 + 8/3 + 8/3 bytes per velocity DoF)."""
+    import dataclasses
+
+    import torch
+
+    from paper_2501_18781_amd import mf, picard
+    from paper_2501_18781_amd import workloads as W
+
+    n = 64
+    wl = W.heat_sphere_workload(n, W.ALL_FACES)
+    nn = wl.mesh.n_nodes
+    log(f"[bench] three-phase heat {n}^3: {nn} nodes")
+    ctx = mf.Context(wl.mesh)
+    p = dataclasses.replace(wl.params, penalty=beta)
+    Tc = dev(W.melt_temperature(wl.mesh))
+    op = mf.heat_operator(ctx, p, phi=dev(wl.phi), T_coef=Tc)
+    op2 = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    xr = dev(W.uniform(0, nn))
+    b = torch.empty_like(xr)
+    out = {"heat": {"cells": n, "nodes": nn, "bytes_per_node": 32, "penalty": beta}}
+    for label, fn in [("apply", mf.operator_apply)]:
+        whole, kt = _time_applies(ctx, fn, op, xr, b, applies)
+        out["heat"][label] = {"us": whole * 1e6, "dofs_per_s": nn / whole, "kernel_us": kt * 1e6,
+                              "kernel_algorithmic_gbs": 32 * nn / kt / 1e9,
+                              "hbm_frac": 32 * nn / kt / 1e9 / PEAK_HBM_GBS}
+    x = torch.empty_like(xr)
+    for label, o in [("cg_jacobi", op), ("cg_jacobi_two_phase", op2)]:
+        mf.operator_apply(o, xr, b)
+        mf.cg_solve(o, b, x, 1e-8, 5000)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = mf.cg_solve(o, b, x, 1e-8, 5000)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["heat"][label] = {"ms": t * 1e3, "iters": info.iters, "rel_res": info.rel_res,
+                              "converged": bool(info.converged)}
+    sp = dataclasses.replace(W.heat_source_workload(n, W.ALL_FACES).sources, terms=7)
+    T_old = dev(W.melt_temperature(wl.mesh))
+    picard.heat_step(ctx, p, dev(wl.phi), T_old, sources=sp, tol=1e-10, maxit=10)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = picard.heat_step(ctx, p, dev(wl.phi), T_old, sources=sp, tol=1e-10, maxit=10)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["heat"]["picard_step"] = {"ms": t * 1e3, "iterations": res.iterations, "converged": res.converged,
+                                  "cg_iterations": res.cg_iterations}
+    h = out["heat"]
+    log(f"[bench]   apply {h['apply']['us']:.1f} us (kernel {h['apply']['kernel_us']:.1f}); CG "
+        f"{h['cg_jacobi']['iters']} it {h['cg_jacobi']['ms']:.1f} ms (two-phase {h['cg_jacobi_two_phase']['iters']} it "
+        f"{h['cg_jacobi_two_phase']['ms']:.1f} ms); Picard {res.iterations} it {t * 1e3:.1f} ms")
+
+    wo = W.oseen_wavy_workload(48)
+    nd = 3 * wo.mesh.n_nodes
+    log(f"[bench] three-phase oseen 48^3: {nd} velocity DoFs")
+    octx = mf.Context(wo.mesh)
+    oop = mf.oseen_operator(octx, wo.params, dev(wo.phi), dev(wo.u0), T_coef=dev(W.melt_temperature(wo.mesh)))
+    xo = dev(W.uniform(1, nd))
+    bo = torch.empty_like(xo)
+    bpd = 24 + 16 / 3
+    out["oseen"] = {"cells": 48, "velocity_dofs": nd, "bytes_per_dof": bpd}
+    for label, fn in [("apply", mf.operator_apply), ("apply_transpose", mf.operator_apply_transpose)]:
+        whole, kt = _time_applies(octx, fn, oop, xo, bo, applies)
+        out["oseen"][label] = {"us": whole * 1e6, "dofs_per_s": nd / whole, "kernel_us": kt * 1e6,
+                               "kernel_algorithmic_gbs": bpd * nd / kt / 1e9}
+    log(f"[bench]   oseen apply {out['oseen']['apply']['us']:.1f} us, transpose "
+        f"{out['oseen']['apply_transpose']['us']:.1f} us")
     return out
 
 
