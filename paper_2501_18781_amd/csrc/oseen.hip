@@ -116,13 +116,9 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
     interp3(rw);
     heaviside27<HK>(a, rw);
     double u[27];
-    if constexpr (!TP) {
-#pragma unroll
-        for (int q = 0; q < 27; ++q) rw[q] = vol * gauss_weight(q) / (rw[q] / a.rho_l + (1.0 - rw[q]) / a.rho_g);
-    }
-    br.gather27(us + C * BNB, u);
-    interp3(u);
     if constexpr (TP) {
+        // the temperature is needed for rho W and the Darcy weight only, so
+        // both are formed (the latter in acc) before u is gathered
         double t[27];
         br.gather27(tcs, t);
         interp3(t);
@@ -132,9 +128,19 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
             const double rho_sl = Hs * a.rho_s + (1.0 - Hs) * a.rho_l;
             const double W = vol * gauss_weight(q);
             rw[q] = W / (rw[q] / rho_sl + (1.0 - rw[q]) / a.rho_g);
-            const double darcy = a.darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + a.darcy_b);
-            acc[q] = (a.am * rw[q] + darcy * W) * u[q];
+            acc[q] = W * a.darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + a.darcy_b);
         }
+        pin27(rw);
+        pin27(acc);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) rw[q] = vol * gauss_weight(q) / (rw[q] / a.rho_l + (1.0 - rw[q]) / a.rho_g);
+    }
+    br.gather27(us + C * BNB, u);
+    interp3(u);
+    if constexpr (TP) {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) acc[q] = (a.am * rw[q] + acc[q]) * u[q];
     } else {
 #pragma unroll
         for (int q = 0; q < 27; ++q) acc[q] = a.am * rw[q] * u[q];
@@ -155,23 +161,37 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
         conv_any<2>(TR, u, rw, w, a.ac * sdir[2], acc);
     }
     // viscosity nu = alpha_v W mu (overwrites rho W, no longer needed)
-    pin27(acc);
-    pin27(u);
     double *nu = rw;
-    br.gather27(ps, nu);
-    interp3(nu);
-    heaviside27<HK>(a, nu);
-    if constexpr (TP) {
+    if constexpr (TP || HK == 1) {
+        // u is gathered again afterwards: live next to the temperature (or
+        // the sine Heaviside) it would exceed the register budget
+        pin27(acc);
         double t[27];
-        br.gather27(tcs, t);
-        interp3(t);
+        if constexpr (TP) {
+            br.gather27(tcs, t);
+            interp3(t);
 #pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            const double Hs = solid_indicator(solid_fraction(a, t[q]));
-            const double mu = nu[q] * (Hs * a.mu_s + (1.0 - Hs) * a.mu_l) + (1.0 - nu[q]) * a.mu_g;
-            nu[q] = a.av * vol * gauss_weight(q) * mu;
+            for (int q = 0; q < 27; ++q) {
+                const double Hs = solid_indicator(solid_fraction(a, t[q]));
+                t[q] = Hs * a.mu_s + (1.0 - Hs) * a.mu_l;
+            }
         }
+        br.gather27(ps, nu);
+        interp3(nu);
+        heaviside27<HK>(a, nu);
+#pragma unroll
+        for (int q = 0; q < 27; ++q)
+            nu[q] = a.av * vol * gauss_weight(q) * (nu[q] * (TP ? t[q] : a.mu_l) + (1.0 - nu[q]) * a.mu_g);
+        pin27(acc);
+        pin27(nu);
+        br.gather27(us + C * BNB, u);
+        interp3(u);
     } else {
+        pin27(acc);
+        pin27(u);
+        br.gather27(ps, nu);
+        interp3(nu);
+        heaviside27<HK>(a, nu);
 #pragma unroll
         for (int q = 0; q < 27; ++q) nu[q] = a.av * vol * gauss_weight(q) * (a.mu_g + nu[q] * (a.mu_l - a.mu_g));
     }
