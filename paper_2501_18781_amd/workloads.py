@@ -156,7 +156,7 @@ class OseenParams:
     # three phases (used only with a nodal temperature for the coefficients):
     # solid density and viscosity, melting range, Darcy damping C fs^2/((1-fs)^3+b)
     rho_s: float = 4200.0
-    mu_s: float = 5.0e-3
+    mu_s: float = 2.0e-2
     T_sol: float = 1933.0
     T_liq: float = 2200.0
     darcy_C: float = 1.0e8

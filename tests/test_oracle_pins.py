@@ -450,6 +450,30 @@ def test_darcy_damping_is_a_mass_term_of_the_solid():
         assert np.abs(D[:nn, nn:]).max() == 0.0
 
 
+def test_oseen_three_phase_density_and_viscosity_reduce_to_two_phase():
+    # At a uniform frozen temperature (H_s constant) and without Darcy damping
+    # the three-phase Oseen matrix is the two-phase one with the liquid
+    # values replaced by the solid-liquid blends rho_sl = H_s rho_s + (1 - H_s)
+    # rho_l, mu_sl likewise (the two-phase path is pinned on its own); the
+    # level set crosses the interface, so the reciprocal density blend and the
+    # arithmetic viscosity blend are both exercised.
+    # catches: rho blended arithmetically with gas, solid and liquid swapped,
+    # H_s applied to the gas side
+    mesh = W.Mesh((2, 3, 2), dirichlet=W.FACE_ZLO)
+    nn = mesh.n_nodes
+    q = W.OseenParams(darcy_C=0.0, mu_s=2.0e-2)  # solid values distinct from the liquid ones
+    assert q.rho_s != q.rho_l and q.mu_s != q.mu_l
+    phi = W.phi_wavy_plane(mesh, 0.5, 0.05, 0.25)
+    u0 = W.taylor_green(mesh)
+    for fs in (0.0, 0.3, 1.0):
+        T = q.T_liq - fs * (q.T_liq - q.T_sol)
+        Hs = 3 * fs ** 2 - 2 * fs ** 3
+        A3 = O.oseen_matrix(mesh, q, phi, u0, Tc=np.full(nn, T))
+        A2 = O.oseen_matrix(mesh, q, phi, u0, rho_l=Hs * q.rho_s + (1 - Hs) * q.rho_l,
+                            mu_l=Hs * q.mu_s + (1 - Hs) * q.mu_l)
+        assert abs(A3 - A2).max() <= 1e-13 * abs(A2).max(), fs
+
+
 def test_penalty_term_moments_and_equivalence_with_evaporative_cooling():
     # Linear level set (delta = a/2, rc(z) = A + B z, see _linear_phi_case):
     # the penalty matrix R = beta delta_rcp N_i N_j has exact moments
