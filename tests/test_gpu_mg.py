@@ -100,6 +100,42 @@ def test_multigrid_stiff_regime_and_manufactured_rhs(gpu):
     assert float(torch.linalg.norm(xm - dev(xs)) / np.linalg.norm(xs)) <= 1e-5
 
 
+@pytest.mark.parametrize("dt", [1e-3, 1e3])
+def test_multigrid_full_size_128(gpu, dt):
+    # The mixed-precision configuration at its full size (128^3 cells,
+    # 16,974,593 nodes) and in the launch configuration the benchmark times:
+    # properties that hold at any size.  The FCG solution's true residual is
+    # within rtol, also at rows the oracle evaluates from its own cell
+    # matrices; the FP32 V-cycle is symmetric (to FP32 rounding) and positive.
+    p = W.HeatParams(dt=dt)
+    wl = W.heat_sphere_workload(128, W.ALL_FACES, p)
+    nn = wl.mesh.n_nodes
+    print(f"multigrid 128^3 dt={dt}", flush=True)
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    b = torch.empty(nn, dtype=torch.float64, device="cuda")
+    mf.operator_apply(op, dev(W.manufactured_T(wl.mesh)), b)
+    mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=4))
+    try:
+        x = torch.empty_like(b)
+        info = mf.mg_cg_solve(mg, b, x, 1e-8, 200)
+        print(info, mg.n_levels, flush=True)
+        assert info.converged and info.rel_res <= 1e-8 and mg.n_levels == 6
+        rows = np.unique(np.concatenate([np.random.default_rng(4).integers(0, nn, 200), [0, nn // 2, nn - 1]]))
+        bh, xh = b.cpu().numpy(), x.cpu().numpy()
+        r_rows = bh[rows] - O.heat_rows(wl.mesh, wl.params, xh, rows, phi=wl.phi)
+        assert np.abs(r_rows).max() <= 1e-8 * np.linalg.norm(bh)
+        r1, r2 = dev(W.uniform(6, nn)), dev(W.uniform(7, nn))
+        z1, z2 = torch.empty_like(r1), torch.empty_like(r1)
+        mf.mg_vcycle(mg, r1, z1)
+        mf.mg_vcycle(mg, r2, z2)
+        a12, a21 = float(r2 @ z1), float(r1 @ z2)
+        assert abs(a12 - a21) <= 1e-5 * float(torch.linalg.norm(r2) * torch.linalg.norm(z1))
+        assert float(r1 @ z1) > 0.0 and float(r2 @ z2) > 0.0
+    finally:
+        mg.close()
+
+
 def test_multigrid_argument_errors(gpu):
     wl = W.heat_sphere_workload(10, W.ALL_FACES)
     ctx = mf.Context(wl.mesh)
