@@ -72,10 +72,22 @@ def uniform(seed: int, n: int) -> np.ndarray:
 
 
 def phi_sphere(mesh: Mesh, radius: float, eps: float, center=(0.5, 0.5, 0.5)) -> np.ndarray:
-    """tanh profile of a liquid sphere: d = radius - |x - center| (liquid inside)."""
-    x = node_coords(mesh)
-    d = radius - np.linalg.norm(x - np.asarray(center)[None, :], axis=1)
-    return np.tanh(d / (2.0 * eps))
+    """tanh profile of a liquid sphere: d = radius - |x - center| (liquid inside).
+
+    Evaluated one z plane of nodes at a time (the same elementwise arithmetic
+    as on the whole coordinate array), so that the largest meshes need no
+    (n_nodes, 3) temporaries."""
+    ax, ay, az = node_axes(mesh)
+    Y, X = np.meshgrid(ay, ax, indexing="ij")
+    pts = np.empty((X.size, 3))
+    pts[:, 0], pts[:, 1] = X.ravel(), Y.ravel()
+    c = np.asarray(center)[None, :]
+    out = np.empty(mesh.n_nodes)
+    for k, z in enumerate(az):
+        pts[:, 2] = z
+        d = radius - np.linalg.norm(pts - c, axis=1)
+        out[k * X.size:(k + 1) * X.size] = np.tanh(d / (2.0 * eps))
+    return out
 
 
 def phi_wavy_plane(mesh: Mesh, z0: float, amp: float, eps: float) -> np.ndarray:

@@ -200,3 +200,25 @@ def test_cg_edge_cases(gpu):
     assert info.status == mf.MF_BREAKDOWN
     with pytest.raises(mf.MFError):
         mf.cg_solve(op, dev(b), x, 1e-10, 100, precond=mf.MF_PC_BLOCK_JACOBI)
+
+
+def test_heat_apply_largest_mesh(gpu):
+    # the largest cube the boundary accepts: 446^3 cells, 893^3 = 712,121,957
+    # nodes (3 n_nodes < 2^31), 5.7 GB per nodal vector; sampled rows against
+    # the oracle's cell matrices, including the first and last node
+    mesh = W.Mesh((446, 446, 446), dirichlet=W.ALL_FACES)
+    nn = mesh.n_nodes
+    assert 3 * nn < 2 ** 31
+    print(f"largest mesh: {nn} nodes", flush=True)
+    p = W.HeatParams()
+    phi = W.phi_sphere(mesh, 0.3, 2.0 / 446)
+    x = W.uniform(0, nn)
+    print("inputs ready", flush=True)
+    ctx = mf.Context(mesh)
+    xd = dev(x)
+    y = torch.empty(nn, dtype=torch.float64, device="cuda")
+    mf.operator_apply(mf.heat_operator(ctx, p, phi=dev(phi)), xd, y)
+    rows = np.unique(np.concatenate([np.random.default_rng(12).integers(0, nn, 300), [0, 1, nn // 2, nn - 1]]))
+    got = y[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    ref = O.heat_rows(mesh, p, x, rows, phi=phi)
+    assert np.abs(got - ref).max() <= TOL64 * np.abs(ref).max()
