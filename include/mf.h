@@ -248,10 +248,13 @@ typedef struct {
 /* Right-hand side of the heat equation from the interface fluxes (Sec. 2.4,
  * Sec. 4), integrated against the Q2 basis by the Gauss rule:
  *   b_i = sum_cells sum_q W_q N_i(x_q) s(x_q),  s = s_evap + q_laser,
- *   s_evap  = -mdot(T) h_v delta_rcp,  mdot = alpha_v (T - T_v)   (eq. vapor_heat_loss,
- *             alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R/M) rho_v / T_v^{3/2})  eq. mDotTanasawa)
+ *   s_evap  = -mdot(T) h_v delta_rcp                                     (eq. vapor_heat_loss)
+ *   mdot    = alpha_v (T - T_v),
+ *   alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R/M) rho_v / T_v^{3/2}  (eq. mDotTanasawa)
  *   q_laser = 2 chi P/(pi r^2) <-n . e_L> exp(-2 d_L^2/r^2) delta_rcp  (eq. laser_gauss)
  *   delta_rcp = |grad H(phi)| rc(phi) 3/(rc_g^2 + rc_l rc_g + rc_l^2)  (eqs. delta, deltaRhoCp)
+ * where rc(phi) is the liquid-gas blend of rc_l and rc_g, also when the
+ * operator carries a frozen temperature for three-phase coefficients.
  * with phi, grad phi and T interpolated at each quadrature point (the local
  * temperature), n = -grad phi/|grad phi| the interface normal pointing from
  * the liquid (phi > 0) into the gas, and d_L the distance from the beam axis.
