@@ -58,25 +58,11 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
     grad_dir(std::integral_constant<int, 0>{});
     grad_dir(std::integral_constant<int, 1>{});
     grad_dir(std::integral_constant<int, 2>{});
-    // evaporative part, -alpha_v (T - T_v) h_v |grad phi|, and the penalty
-    // right-hand side, beta T_v |grad phi|, in place of |grad phi|^2
+    // Pointwise, phi's last use: the laser term times delta_rcp in place of
+    // grad phi . e_L, and delta_rcp = |grad phi| H' rc c_rcp in place of
+    // |grad phi|^2, so that phi is dead before the temperature is gathered
+    // (three 27-vectors live at a time).
     const bool evap = sa.terms & 1, laser = sa.terms & 2, pen = sa.terms & 4;
-    pin27(ph);
-    pin27(ge);
-    pin27(gn);
-    {
-        double Tq[27];
-        br.gather27(ts, Tq);
-        interp3(Tq);
-#pragma unroll
-        for (int q = 0; q < 27; ++q)
-            gn[q] = ((evap ? -sa.alpha_v * (Tq[q] - sa.T_boil) * sa.h_v : 0.0) + (pen ? sa.penalty * sa.T_boil : 0.0)) *
-                    sqrt(gn[q]);
-    }
-    pin27(gn);
-
-    // the pointwise source, weighted, in place of phi
-    const double vol = m.hx * m.hy * m.hz;
     const double xc[3] = {m.lox + m.hx * (br.c0x + br.tx), m.loy + m.hy * (br.c0y + br.ty),
                           m.loz + m.hz * (br.c0z + br.tz)};
     const double xi[3] = {0.5 - kR, 0.5, 0.5 + kR};
@@ -86,7 +72,7 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
         double dH;
         const double H = heaviside<double>(HK, a.eps, ph[q], &dH);
         const double drc = dH * (a.rc_g + H * (a.rc_l - a.rc_g)) * sa.c_rcp; // delta_rcp / |grad phi|
-        double s = gn[q];
+        double lq = 0.0;
         if (laser && ge[q] > 0.0) {
             double r[3], t = 0.0;
 #pragma unroll
@@ -100,10 +86,27 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
                 const double p = r[d] - t * sa.dir[d];
                 d2 += p * p;
             }
-            s += sa.peak * ge[q] * exp(-2.0 * d2 * sa.inv_r2);
+            lq = sa.peak * ge[q] * exp(-2.0 * d2 * sa.inv_r2) * drc;
         }
-        const double w = Q2<double>::weight(qi[0]) * Q2<double>::weight(qi[1]) * Q2<double>::weight(qi[2]);
-        ph[q] = vol * w * s * drc;
+        ge[q] = lq;
+        gn[q] = sqrt(gn[q]) * drc; // delta_rcp
+        // one point at a time: interleaving the 27 exponentials would take
+        // more registers than the three live vectors
+        asm volatile("" : "+v"(ge[q]), "+v"(gn[q]));
+    }
+    pin27(ge);
+    pin27(gn);
+    // evaporative part, -alpha_v (T - T_v) h_v delta_rcp, and the penalty
+    // right-hand side, beta T_v delta_rcp; the weighted source in place of T
+    const double vol = m.hx * m.hy * m.hz;
+    double *sq = ph;
+    br.gather27(ts, sq);
+    interp3(sq);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        const double f = (evap ? -sa.alpha_v * (sq[q] - sa.T_boil) * sa.h_v : 0.0) + (pen ? sa.penalty * sa.T_boil : 0.0);
+        const double w = Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
+        sq[q] = vol * w * (f * gn[q] + ge[q]);
     }
     interp3T(ph);
 
