@@ -122,7 +122,8 @@ __device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &
     const double vol = m.hx * m.hy * m.hz;
     const double c_rcp = 3.0 / (a.rc_g * a.rc_g + a.rc_l * a.rc_g + a.rc_l * a.rc_l);
     const double inv_range = 1.0 / (a.T_liq - a.T_sol);
-    for (int q = 0; q < 27; ++q) { // not unrolled: the sine form calls out of line
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
         double dH;
         const double H = heaviside<double>(HK, a.eps, ph[q], &dH);
         double Hs = 0.0;
@@ -136,6 +137,7 @@ __device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &
         const double w = vol * Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
         cm[q] = w * (a.am * rc + react);
         ck[q] = w * a.ak * k / (kR * kR);
+        asm volatile("" : "+v"(cm[q]), "+v"(ck[q])); // one point at a time
     }
 }
 
