@@ -220,11 +220,13 @@ struct Brick {
                 for (int a = 0; a < 3; ++a) v[a + 3 * b + 9 * c] = lds[l0 + a + BP * b + BP * BP * c];
     }
 
-    // Cell results, node-major: E[local * BNT + thread]; zero without a cell.
+    // Cell results, node-major: E[local * BNT + thread].  A thread without a
+    // cell stores whatever it computed: node_sum reads only the lower
+    // neighbours of a valid cell within the brick, and those are valid too.
     template <typename T> __device__ __forceinline__ void store_cell(T *E, const T *v) const
     {
 #pragma unroll
-        for (int i = 0; i < 27; ++i) E[i * BNT + t] = valid ? v[i] : T(0);
+        for (int i = 0; i < 27; ++i) E[i * BNT + t] = v[i];
     }
 
     // Sum over the brick's cells containing local node (a, b, c) of this
