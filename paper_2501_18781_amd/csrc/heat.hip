@@ -765,6 +765,7 @@ hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double 
 //   drc_q = -alpha_m W_q lam dT
 //   dphi_j = sum_q N_j(x_q) H'(phi_q) [(k_l - k_g) dk_q + (rc_l - rc_g) drc_q]
 // ---------------------------------------------------------------------------
+template <int HK>
 __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, const double *__restrict__ T,
                                                         const double *__restrict__ dT, const double *__restrict__ lam,
                                                         double *__restrict__ dk, double *__restrict__ drc,
@@ -793,29 +794,44 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
     grad_dot_acc<double, 0>(lq, Tq, ih[0], gk);
     grad_dot_acc<double, 1>(lq, Tq, ih[1], gk);
     grad_dot_acc<double, 2>(lq, Tq, ih[2], gk);
-    double dtq[27];
-    br.gather27(dTs, dtq);
-    interp3(dtq);
-    double s[27];
+    pin27(gk);
+    pin27(lq);
+    double s[27]; // T - T_old at the Gauss points, then drc_q, then the phi-gradient weights
+    br.gather27(dTs, s);
+    interp3(s);
+#pragma unroll
     for (int q = 0; q < 27; ++q) {
         const double wq = vol * Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
         const double gkq = -a.ak * wq * gk[q];
-        const double grq = -a.am * wq * lq[q] * dtq[q];
+        const double grq = -a.am * wq * lq[q] * s[q];
         if (br.valid) {
             if (dk) dk[cell * 27 + q] = gkq;
             if (drc) drc[cell * 27 + q] = grq;
         }
         gk[q] = gkq;
         s[q] = grq;
+        asm volatile("" : "+v"(gk[q]), "+v"(s[q])::"memory"); // one point at a time
     }
     if (!with_phi) return; // uniform over the launch
+    pin27(gk);
+    pin27(s);
     double ph[27];
     br.gather27(ps, ph);
     interp3(ph);
-    for (int q = 0; q < 27; ++q) {
-        double dH;
-        (void)heaviside<double>(a.hkind, a.eps, ph[q], &dH);
-        s[q] = dH * ((a.k_l - a.k_g) * gk[q] + (a.rc_l - a.rc_g) * s[q]);
+    if constexpr (HK == 0) {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            double dH;
+            (void)heaviside<double>(0, a.eps, ph[q], &dH);
+            s[q] = dH * ((a.k_l - a.k_g) * gk[q] + (a.rc_l - a.rc_g) * s[q]);
+            asm volatile("" : "+v"(s[q])); // one point at a time
+        }
+    } else {
+        for (int q = 0; q < 27; ++q) { // out of line and not unrolled: one transcendental evaluation per point
+            double dH;
+            (void)heaviside<double>(1, a.eps, ph[q], &dH);
+            s[q] = dH * ((a.k_l - a.k_g) * gk[q] + (a.rc_l - a.rc_g) * s[q]);
+        }
     }
     interp3T(s);
     __syncthreads();
@@ -834,7 +850,10 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
 {
     const unsigned nb = (unsigned)n_bricks(m);
     if (dphi && !face) return hipErrorInvalidValue;
-    heat_grad_kernel<<<nb, BNT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi, (double *)face);
+    if (a.mode == 0 && a.hkind)
+        heat_grad_kernel<1><<<nb, BNT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi, (double *)face);
+    else
+        heat_grad_kernel<0><<<nb, BNT, 0, s>>>(m, a, T, dT, lam, dk, drc, dphi, (double *)face);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !dphi || a.mode != 0) return e;
     // the level-set gradient sums over Dirichlet nodes too (DMODE 0)
