@@ -309,8 +309,10 @@ mf_status mf_operator_diagonal(mf_ctx *c, const mf_operator *op, void *diag, mf_
     if (op->kind == MF_HEAT) {
         if ((st = ensure_face(c, 1))) return st;
         HIPCHK(c, heat_diagonal(c->km, heat_args(op), op->precision == MF_FP32, diag, c->face, (hipStream_t)stream));
-    } else
-        HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), (double *)diag, (hipStream_t)stream));
+    } else {
+        if ((st = ensure_face(c, 6))) return st;
+        HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), (double *)diag, c->face, (hipStream_t)stream));
+    }
     return MF_OK;
 }
 
@@ -517,7 +519,8 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
             // diagonal of the 3x3 blocks
             if (!c->blocks && hipMalloc((void **)&c->blocks, sizeof(double) * 9 * c->nn) != hipSuccess)
                 return fail(c, MF_ERR_OOM, "block allocation failed");
-            HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), c->blocks, s));
+            if ((st = ensure_face(c, 6))) return st;
+            HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), c->blocks, c->face, s));
             for (int comp = 0; comp < 3; ++comp)
                 HIPCHK(c, hipMemcpy2DAsync(pc + comp * c->nn, sizeof(double), c->blocks + 4 * comp, 9 * sizeof(double),
                                            sizeof(double), c->nn, hipMemcpyDeviceToDevice, s));
@@ -526,7 +529,8 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
     } else if (precond == MF_PC_BLOCK_JACOBI) {
         if (!c->blocks && hipMalloc((void **)&c->blocks, sizeof(double) * 9 * c->nn) != hipSuccess)
             return fail(c, MF_ERR_OOM, "block allocation failed");
-        HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), c->blocks, s));
+        if ((st = ensure_face(c, 6))) return st;
+        HIPCHK(c, oseen_block_diagonal(c->km, oseen_args(op), c->blocks, c->face, s));
         HIPCHK(c, block3_invert(c->blocks, c->nn, s));
     }
     double *zt;

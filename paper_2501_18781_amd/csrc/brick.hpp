@@ -338,15 +338,18 @@ __device__ __forceinline__ bool combine_node(const KMesh &m, int &gx, int &gy, i
     return false;
 }
 
-template <typename T, int DMODE>
-__device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
-                                               T *__restrict__ y)
+// The combine thread's shared node g, its partials summed in the fixed
+// order: f(g, constrained, sum).  With SKIP_CONSTRAINED a Dirichlet node's
+// partials are not read and f gets a zero sum.
+template <typename T, bool SKIP_CONSTRAINED, typename F>
+__device__ __forceinline__ void combine_visit(const KMesh &m, const T *__restrict__ face, F f)
 {
     int gx, gy, gz;
     if (!combine_node(m, gx, gy, gz)) return;
     const int64_t g = node_index(m, gx, gy, gz);
-    if (DMODE != 0 && node_constrained(m, gx, gy, gz)) {
-        y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
+    const bool constrained = node_constrained(m, gx, gy, gz);
+    if (SKIP_CONSTRAINED && constrained) {
+        f(g, true, T(0));
         return;
     }
     const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
@@ -368,7 +371,17 @@ __device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restri
     T s = v[0];
 #pragma unroll
     for (int e = 1; e < 8; ++e) s += v[e];
-    y[g] = s;
+    f(g, constrained, s);
+}
+
+template <typename T, int DMODE>
+__device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
+                                               T *__restrict__ y)
+{
+    combine_visit<T, DMODE != 0>(m, face, [&](int64_t g, bool constrained, T s) {
+        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
+        else y[g] = s;
+    });
 }
 
 } // namespace mf

@@ -99,7 +99,8 @@ hipError_t heat_sources(const KMesh &m, const HeatArgs &a, const SourceArgs &sa,
 // y = A x or A^T x; `face` holds 3 face_buffer_elems(m) doubles.
 hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y, void *face,
                        hipStream_t s, const KTiming *t = nullptr);
-hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, hipStream_t s);
+// The 3x3 nodal blocks of A ([n_nodes][3][3]); `face` holds 6 face_buffer_elems(m) doubles.
+hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, void *face, hipStream_t s);
 
 // ---- vectors and Krylov steps (vec.hip) ----
 hipError_t vfill(void *y, double v, int64_t n, int fp32, hipStream_t s);

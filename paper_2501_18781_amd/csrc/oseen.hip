@@ -301,11 +301,14 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
 //   B_i[c][c'] = sum_q W [ (alpha_m rho N_i^2 + alpha_c rho N_i (u0.grad N_i)
 //                           + alpha_v mu |grad N_i|^2) delta_cc'
 //                         + alpha_v mu d_c' N_i d_c N_i ]
-// by direct loops over the Gauss points (setup only), one pass per entry.
-// Shared nodes are added with FP64 atomics into a cleared output.
+// (+ the Darcy weight in the mass term with three phases) by direct loops
+// over the Gauss points (setup only), one pass per entry.  Shared nodes go
+// through the face buffer, one sheet per entry, and the combine pass, like
+// the applies: every entry is written once and the result is reproducible.
 // ---------------------------------------------------------------------------
 template <int HK, bool TP>
-__global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, double *__restrict__ blocks)
+__global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, double *__restrict__ blocks,
+                                                          double *__restrict__ face)
 {
     constexpr int STAGE = (TP ? 5 : 4) * BNB, CONTRIB = 27 * BNT;
     __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
@@ -379,37 +382,57 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
         __syncthreads();
         br.store_cell(E, d);
         __syncthreads();
-        br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, bool shared) {
+        // entry e of a shared node goes to face sheet e; the combine sums it
+        double *fb = face + ((int64_t)e * n_bricks(m) + br.brick) * BFACE;
+        br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
             double *B = blocks + 9 * g;
-            if (constrained) {
+            if (sh) {
+                fb[br.fslot(ai, bi, ci, l)] = br.node_sum(E, ai, bi, ci); // Dirichlet ones: identity in the combine
+            } else if (constrained) {
                 B[3 * c + cp] = (c == cp) ? 1.0 : 0.0;
                 B[3 * cp + c] = (c == cp) ? 1.0 : 0.0;
-                return;
-            }
-            const double s = br.node_sum(E, ai, bi, ci);
-            if (shared) {
-                atomicAdd(&B[3 * c + cp], s);
-                if (c != cp) atomicAdd(&B[3 * cp + c], s);
             } else {
+                const double s = br.node_sum(E, ai, bi, ci);
                 B[3 * c + cp] = s;
-                if (c != cp) B[3 * cp + c] = s;
+                B[3 * cp + c] = s;
             }
         });
     }
 }
 
-hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, hipStream_t s)
+// Shared nodes of the 3x3 blocks: entry e = blockIdx.y of the face sheets,
+// summed in the fixed order, written to both symmetric positions; Dirichlet
+// nodes get the identity.
+__global__ void __launch_bounds__(CNT) oseen_block_combine_kernel(KMesh m, const double *__restrict__ face,
+                                                                  double *__restrict__ blocks)
+{
+    const int e = blockIdx.y;
+    const int c = e < 3 ? e : (e == 5 ? 1 : 0), cp = e < 3 ? e : (e == 3 ? 1 : 2);
+    combine_visit<double, true>(m, face + (int64_t)e * n_bricks(m) * BFACE, [&](int64_t g, bool constrained, double v) {
+        double *B = blocks + 9 * g;
+        const double s = constrained ? (c == cp ? 1.0 : 0.0) : v;
+        B[3 * c + cp] = s;
+        B[3 * cp + c] = s;
+    });
+}
+
+hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, void *face, hipStream_t s)
 {
     const unsigned nb = (unsigned)n_bricks(m);
-    hipError_t e = vfill(blocks, 0.0, 9 * (int64_t)m.NX * m.NY * m.NZ, 0, s);
-    if (e != hipSuccess) return e;
+    if (!face) return hipErrorInvalidValue;
+    double *fc = (double *)face;
     if (a.tc) {
-        if (a.hkind == 0) oseen_block_kernel<0, true><<<nb, BNT, 0, s>>>(m, a, blocks);
-        else oseen_block_kernel<1, true><<<nb, BNT, 0, s>>>(m, a, blocks);
+        if (a.hkind == 0) oseen_block_kernel<0, true><<<nb, BNT, 0, s>>>(m, a, blocks, fc);
+        else oseen_block_kernel<1, true><<<nb, BNT, 0, s>>>(m, a, blocks, fc);
     } else {
-        if (a.hkind == 0) oseen_block_kernel<0, false><<<nb, BNT, 0, s>>>(m, a, blocks);
-        else oseen_block_kernel<1, false><<<nb, BNT, 0, s>>>(m, a, blocks);
+        if (a.hkind == 0) oseen_block_kernel<0, false><<<nb, BNT, 0, s>>>(m, a, blocks, fc);
+        else oseen_block_kernel<1, false><<<nb, BNT, 0, s>>>(m, a, blocks, fc);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned rows = combine_blocks(m);
+    if (rows == 0) return hipSuccess; // single brick: nothing shared
+    oseen_block_combine_kernel<<<dim3(rows, 6), CNT, 0, s>>>(m, fc, blocks);
     return hipGetLastError();
 }
 

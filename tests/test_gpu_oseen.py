@@ -98,8 +98,13 @@ def test_oseen_block_diagonal(gpu, n, dirichlet):
     ref = O.block_jacobi(A, mesh.n_nodes).blocks  # (nn, 3, 3)
     ctx = mf.Context(mesh)
     B = torch.empty(9 * mesh.n_nodes, dtype=torch.float64, device="cuda")
-    mf.operator_diagonal(mf.oseen_operator(ctx, p, dev(phi), dev(u0)), B)
+    op = mf.oseen_operator(ctx, p, dev(phi), dev(u0))
+    mf.operator_diagonal(op, B)
     assert relerr(B.cpu().numpy().reshape(-1, 3, 3), ref) <= TOL64
+    # shared nodes are combined in a fixed order: a second evaluation is bitwise equal
+    B2 = torch.full_like(B, 7.0)
+    mf.operator_diagonal(op, B2)
+    assert torch.equal(B, B2)
 
 
 def test_oseen_full_size_sampled_rows(gpu):
