@@ -441,16 +441,6 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
 // the 1D value and derivative tables S and G along z, y, x.  Node sums and
 // shared faces as in the apply; Dirichlet nodes get 1.
 // ---------------------------------------------------------------------------
-// out = in contracted along direction DIR with M: out[.., a, ..] = sum_q M[q][a] in[.., q, ..]
-template <int DIR, typename T> __device__ __forceinline__ void contract1d(const T *in, T *out, const T (&M)[3][3])
-{
-    constexpr int st = DIR == 0 ? 1 : (DIR == 1 ? 3 : 9);
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int a = (i / st) % 3, base = i - a * st;
-        out[i] = M[0][a] * in[base] + M[1][a] * in[base + st] + M[2][a] * in[base + 2 * st];
-    }
-}
 
 // Cell diagonal from cm_q and ck_q (ck_q for the true 1D derivatives G).
 template <typename T>

@@ -172,6 +172,19 @@ __device__ __forceinline__ void grad_line_apply(const T *u, const C &c, T ih, T 
         }
 }
 
+// out = in contracted along direction DIR with M: out[.., a, ..] = sum_q M[q][a] in[.., q, ..]
+// (M a 3x3 table over Gauss points q and nodes a; the diagonals and nodal
+// blocks contract Gauss-point weights with squares and products of S and G).
+template <int DIR, typename T> __device__ __forceinline__ void contract1d(const T *in, T *out, const T (&M)[3][3])
+{
+    constexpr int st = DIR == 0 ? 1 : (DIR == 1 ? 3 : 9);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int a = (i / st) % 3, base = i - a * st;
+        out[i] = M[0][a] * in[base] + M[1][a] * in[base + st] + M[2][a] * in[base + 2 * st];
+    }
+}
+
 // Ordering point: all 27 values of v are computed before it and no memory
 // access moves across it.  Placed at the phase boundaries of a cell's
 // computation, it keeps the compiler from forming later passes early and

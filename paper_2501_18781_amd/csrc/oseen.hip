@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
     __syncthreads();
     const double vol = m.hx * m.hy * m.hz;
     const double ih[3] = {1.0 / m.hx, 1.0 / m.hy, 1.0 / m.hz};
-    double rw[27], nu[27], w0[27], w1[27], w2[27], dw[27]; // rho W, alpha_v mu W, velocity, Darcy W
+    double rw[27], nu[27], w0[27], dw[27]; // rho W, alpha_v mu W, scratch (velocity), Darcy W
     br.gather27(ps, rw);
     interp3(rw);
     heaviside27<HK>(a, rw);
@@ -345,39 +345,57 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
             dw[q] = 0.0;
         }
     }
-    br.gather27(u0s, w0);
-    interp3(w0);
-    br.gather27(u0s + BNB, w1);
-    interp3(w1);
-    br.gather27(u0s + 2 * BNB, w2);
-    interp3(w2);
-    const double S[3][3] = {{Q2<double>::s0, Q2<double>::s1, Q2<double>::s2}, {0.0, 1.0, 0.0},
-                            {Q2<double>::s2, Q2<double>::s1, Q2<double>::s0}};
-    const double Gd[3][3] = {{Q2<double>::g0, Q2<double>::g1, Q2<double>::g2}, {-1.0, 0.0, 1.0},
-                             {-Q2<double>::g2, -Q2<double>::g1, -Q2<double>::g0}};
+    // Every term is a product of 1D factors along x, y, z, so its sum over the
+    // Gauss points is a contraction of a Gauss-point weight with 1D tables
+    // (as the heat diagonal): N_i^2 -> S^2 along all three directions;
+    // N_i d_d N_i -> S.G / h_d along d; (d_d N_i)^2 -> G^2 / h_d^2 along d;
+    // d_c N_i d_c' N_i -> S.G / h along c and along c'.
+    constexpr double s0 = Q2<double>::s0, s1 = Q2<double>::s1, s2 = Q2<double>::s2;
+    constexpr double g0 = Q2<double>::g0, g1 = Q2<double>::g1, g2 = Q2<double>::g2;
+    const double S2[3][3] = {{s0 * s0, s1 * s1, s2 * s2}, {0.0, 1.0, 0.0}, {s2 * s2, s1 * s1, s0 * s0}};
+    const double G2[3][3] = {{g0 * g0, g1 * g1, g2 * g2}, {1.0, 0.0, 1.0}, {g2 * g2, g1 * g1, g0 * g0}};
+    const double SG[3][3] = {{s0 * g0, s1 * g1, s2 * g2}, {0.0, 0.0, 0.0}, {-s2 * g2, -s1 * g1, -s0 * g0}};
+    auto contract3 = [&](const double *f, const double(&Tx)[3][3], const double(&Ty)[3][3],
+                         const double(&Tz)[3][3], double *out) {
+        double t[27], u[27];
+        contract1d<2>(f, t, Tz);
+        contract1d<1>(t, u, Ty);
+        contract1d<0>(u, out, Tx);
+    };
+    // base = mass (with Darcy) + convection + the viscous |grad N_i|^2 part,
+    // common to the three diagonal entries
+    double base[27], t[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) w0[q] = a.am * rw[q] + dw[q];
+    contract3(w0, S2, S2, S2, base);
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        br.gather27(u0s + dir * BNB, w0);
+        interp3(w0);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) w0[q] *= a.ac * rw[q] * ih[dir];
+        contract3(w0, dir == 0 ? SG : S2, dir == 1 ? SG : S2, dir == 2 ? SG : S2, t);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) base[i] += t[i];
+        contract3(nu, dir == 0 ? G2 : S2, dir == 1 ? G2 : S2, dir == 2 ? G2 : S2, t);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) base[i] += ih[dir] * ih[dir] * t[i];
+    }
     // entries (0,0) (1,1) (2,2) (0,1) (0,2) (1,2); the block is symmetric but
     // for the convective term, which only enters the diagonal
     for (int e = 0; e < 6; ++e) {
         const int c = e < 3 ? e : (e == 5 ? 1 : 0);
         const int cp = e < 3 ? e : (e == 3 ? 1 : 2);
         double d[27];
-        for (int i = 0; i < 27; ++i) {
-            const int ia = i % 3, ib = (i / 3) % 3, ic = i / 9;
-            double sacc = 0.0;
-            for (int q = 0; q < 27; ++q) {
-                const int qa = q % 3, qb = (q / 3) % 3, qc = q / 9;
-                const double nx = S[qa][ia], ny = S[qb][ib], nz = S[qc][ic];
-                const double n = nx * ny * nz;
-                const double g[3] = {Gd[qa][ia] * ny * nz * ih[0], nx * Gd[qb][ib] * nz * ih[1],
-                                     nx * ny * Gd[qc][ic] * ih[2]};
-                double v = nu[q] * g[cp] * g[c];
-                if (c == cp) {
-                    v += (a.am * rw[q] + dw[q]) * n * n + a.ac * rw[q] * n * (w0[q] * g[0] + w1[q] * g[1] + w2[q] * g[2]) +
-                         nu[q] * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-                }
-                sacc += v;
-            }
-            d[i] = sacc;
+        if (e < 3) { // base + nu (d_c N_i)^2
+            contract3(nu, c == 0 ? G2 : S2, c == 1 ? G2 : S2, c == 2 ? G2 : S2, d);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) d[i] = base[i] + ih[c] * ih[c] * d[i];
+        } else { // nu d_c N_i d_c' N_i
+            const bool x = c == 0 || cp == 0, y = c == 1 || cp == 1, z = c == 2 || cp == 2;
+            contract3(nu, x ? SG : S2, y ? SG : S2, z ? SG : S2, d);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) d[i] *= ih[c] * ih[cp];
         }
         __syncthreads();
         br.store_cell(E, d);
