@@ -204,12 +204,16 @@ __device__ __forceinline__ void cell_heaviside(const Brick &br, const HeatArgs &
 // most three 27-vectors are live besides the one being formed:
 //   A:   cv = u0 . grad u;  H;  acc = rc W (alpha_m u + alpha_c cv);  acc += conduction
 //   A^T: H;  acc = conduction;  z = rc W u;  acc += alpha_m z + alpha_c sum_d D_d^T (u0_d z)
+// The velocity components are staged in LDS one at a time, in the region
+// vs, just before the pass that uses them (all threads of the brick call
+// this function: the staging barriers are uniform).
 template <bool TR, int HK>
 __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMesh &m, const HeatArgs &a,
-                                                     const double *ps, const double *us, double *u)
+                                                     const double *ps, double *vs, double *u)
 {
     const double vol = m.hx * m.hy * m.hz;
     const double h[3] = {m.hx, m.hy, m.hz};
+    const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
     interp3(u);
     double acc[27], v[27]; // v: a velocity component, then H
     auto velocity = [&](int d) {
@@ -217,7 +221,10 @@ __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMes
         // derivatives of u from being formed ahead of it
         pin27(acc);
         pin27(u);
-        br.gather27(us + d * BNB, v);
+        __syncthreads(); // every thread is done with the previous component
+        br.load(m, a.u0 + d * nn, vs, false);
+        __syncthreads();
+        br.gather27(vs, v);
         interp3(v);
     };
     auto conduction = [&](const ClassCoef &ckw) {
@@ -281,7 +288,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     // x stays resident (Dirichlet rows y = x and the CG epilogue read it);
     // phi (and the velocity) and then the cell contributions share the
     // second region.
-    constexpr int STAGE = CONV ? 4 * BNB : BNB;
+    constexpr int STAGE = CONV ? 2 * BNB : BNB; // phi (and one velocity component at a time)
     constexpr int LDS_T = BNB + (STAGE > 27 * BNT ? STAGE : 27 * BNT);
     __shared__ T lds[LDS_T];
     __shared__ double red_lds[BNT];
@@ -294,10 +301,6 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
     else br.load_fields(m, x, xs);
     if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + BNB, false);
-    if constexpr (CONV != 0) {
-        const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-        for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, ps + (c + 1) * BNB, false);
-    }
     __syncthreads();
 
     const T vol = T(m.hx * m.hy * m.hz);
