@@ -14,8 +14,9 @@ T_I the nodal interpolant of sin(pi x) sin(pi y) sin(pi z).
 
 value      = applied DoFs per second over the timed applies (100 per step),
              whole-apply time (output clearing + kernel) from HIP events.
-roofline   = the apply kernel alone (events around the kernel inside the
-             library), algorithmic flops and bytes per launch.
+roofline   = the apply kernel alone (start/stop events attached to the
+             kernel's own dispatch inside the library, on every 20th apply
+             of the timed steps), algorithmic flops and bytes per launch.
 cpu_baseline = the CPU oracle (assembled CSR, OpenMP) on the same workload.
 mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
              both to 1e-8, on 128^3 cells (257^3 nodes).
@@ -247,10 +248,23 @@ def main():
     xs = torch.empty_like(y)
     s = torch.cuda.current_stream()
 
-    def step(ev):
+    # Every SAMPLE-th apply of a timed step carries start/stop events attached
+    # to the kernel's own dispatch (the roofline's kernel time); events on
+    # every launch would add about 5 us to each whole apply.
+    # The sample sits mid-way through each group of SAMPLE applies, away from
+    # the step's CG solve.
+    SAMPLE = 20
+    phase = min(SAMPLE // 2, args.applies - 1)
+
+    def step(ev, timed=False):
         ev[0].record(s)
-        for _ in range(args.applies):
+        for i in range(args.applies):
+            sample = timed and i % SAMPLE == phase
+            if sample:
+                ctx.timing_enable(True)
             mf.operator_apply(op, x, y)
+            if sample:
+                ctx.timing_enable(False)
         ev[1].record(s)
         info = mf.cg_solve(op, b, xs, 1e-10, 1000)
         ev[2].record(s)
@@ -261,15 +275,13 @@ def main():
         step(ev[i])
     torch.cuda.synchronize()
     log("[bench] warmup done")
-    ctx.timing_enable(True)
     ctx.timing_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = [step(ev[i]) for i in range(args.steps)]
+    infos = [step(ev[i], timed=True) for i in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernel_ms, launches = ctx.timing_read(reset=True)
-    ctx.timing_enable(False)
     apply_ms = sum(e[0].elapsed_time(e[1]) for e in ev[:args.steps])
     cg_ms = sum(e[1].elapsed_time(e[2]) for e in ev[:args.steps]) / args.steps
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -493,25 +505,10 @@ def heat_conv_bench(dev, applies=50):
     op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi), u0=dev(wl.u0))
     xr = dev(W.uniform(0, nn))
     b = torch.empty_like(xr)
-    s = torch.cuda.current_stream()
     flops, bytes_ = FLOPS_PER_CELL_CONV * n ** 3, BYTES_PER_NODE_CONV * nn
     out = {"cells": n, "nodes": nn, "flops_per_cell": FLOPS_PER_CELL_CONV, "bytes_per_node": BYTES_PER_NODE_CONV}
     for label, fn in [("apply", mf.operator_apply), ("apply_transpose", mf.operator_apply_transpose)]:
-        for _ in range(5):
-            fn(op, xr, b)
-        torch.cuda.synchronize()
-        ctx.timing_enable(True)
-        ctx.timing_read(reset=True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(applies):
-            fn(op, xr, b)
-        e1.record(s)
-        torch.cuda.synchronize()
-        kms, kl = ctx.timing_read(reset=True)
-        ctx.timing_enable(False)
-        kt = kms * 1e-3 / kl
-        whole = e0.elapsed_time(e1) * 1e-3 / applies
+        whole, kt = _time_applies(ctx, fn, op, xr, b, applies)
         out[label] = {"us": whole * 1e6, "dofs_per_s": nn / whole, "kernel_us": kt * 1e6,
                       "kernel_algorithmic_gbs": bytes_ / kt / 1e9, "kernel_tflops": flops / kt / 1e12,
                       "hbm_frac": bytes_ / kt / 1e9 / PEAK_HBM_GBS, "fp64_frac": flops / kt / 1e12 / PEAK_FP64_TFLOPS}
@@ -567,19 +564,24 @@ def heat_sources_bench(dev, reps=50):
 
 def _time_applies(ctx, fn, op, x, y, applies):
     """Whole-apply and apply-kernel time (seconds per apply) of `applies`
-    back-to-back calls, after a warm-up."""
+    back-to-back calls each, after a warm-up: the whole applies without
+    kernel events (they would add about 5 us to each), then the kernel alone
+    with start/stop events attached to its dispatch."""
     import torch
     for _ in range(5):
         fn(op, x, y)
     torch.cuda.synchronize()
-    ctx.timing_enable(True)
-    ctx.timing_read(reset=True)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(applies):
         fn(op, x, y)
     e1.record(s)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    ctx.timing_read(reset=True)
+    for _ in range(applies):
+        fn(op, x, y)
     torch.cuda.synchronize()
     kms, kl = ctx.timing_read(reset=True)
     ctx.timing_enable(False)
