@@ -284,7 +284,11 @@ __host__ __device__ inline int64_t combine_nodes(const KMesh &m)
            (int64_t)internal_planes(m.NX) * m.NY * m.NZ;
 }
 
-__host__ inline unsigned combine_blocks(const KMesh &m) { return (unsigned)((combine_nodes(m) + CNT - 1) / CNT); }
+// Workgroups of a combine pass with npt nodes per thread.
+__host__ inline unsigned combine_blocks(const KMesh &m, int npt = 1)
+{
+    return (unsigned)((combine_nodes(m) + (int64_t)CNT * npt - 1) / ((int64_t)CNT * npt));
+}
 
 // Bricks containing node coordinate g along a direction with N nodes and nb
 // bricks: (k0, l0) and, if two, (k0 + 1, 0).
@@ -300,15 +304,11 @@ __device__ __forceinline__ int brick_entries(int g, int N, int nb, int &k0, int 
     return 1;
 }
 
-// The combine thread's enumerated node; workgroups are numbered so that each
-// XCD receives a contiguous range of them (neighbouring rows share face
-// cache lines).  Returns false for a thread without a node of its own.
-__device__ __forceinline__ bool combine_node(const KMesh &m, int &gx, int &gy, int &gz)
+// Enumerated node j (see above); false for an index without a node of its
+// own.  Workgroups are numbered so that each XCD receives a contiguous range
+// of indices (neighbouring rows share face cache lines; combine_visit).
+__device__ __forceinline__ bool combine_node_at(const KMesh &m, unsigned j, int &gx, int &gy, int &gz)
 {
-    const unsigned G = gridDim.x, q = G / NXCD, r = G % NXCD;
-    const unsigned k = blockIdx.x % NXCD, jb = blockIdx.x / NXCD;
-    const unsigned blk = k * q + min(k, r) + jb;
-    unsigned j = blk * CNT + threadIdx.x;
     const unsigned NX = m.NX, NY = m.NY, NZ = m.NZ;
     const unsigned nzp = internal_planes(m.NZ), nyp = internal_planes(m.NY), nxp = internal_planes(m.NX);
     const unsigned sz = nzp * NX * NY, sy = nyp * NX * NZ, sx = nxp * NY * NZ;
@@ -338,47 +338,59 @@ __device__ __forceinline__ bool combine_node(const KMesh &m, int &gx, int &gy, i
     return false;
 }
 
-// The combine thread's shared node g, its partials summed in the fixed
-// order: f(g, constrained, sum).  With SKIP_CONSTRAINED a Dirichlet node's
-// partials are not read and f gets a zero sum.
-template <typename T, bool SKIP_CONSTRAINED, typename F>
+// The combine thread's shared nodes (NPT of them, one from each of NPT
+// sweeps of gridDim.x * CNT enumerated nodes), each with its partials summed
+// in the fixed order: f(g, constrained, sum).  All loads of the thread's
+// nodes are issued before the first sum.  With SKIP_CONSTRAINED a Dirichlet
+// node's partials are not read and f gets a zero sum.
+template <typename T, bool SKIP_CONSTRAINED, int NPT = 1, typename F>
 __device__ __forceinline__ void combine_visit(const KMesh &m, const T *__restrict__ face, F f)
 {
-    int gx, gy, gz;
-    if (!combine_node(m, gx, gy, gz)) return;
-    const int64_t g = node_index(m, gx, gy, gz);
-    const bool constrained = node_constrained(m, gx, gy, gz);
-    if (SKIP_CONSTRAINED && constrained) {
-        f(g, true, T(0));
-        return;
-    }
+    const unsigned G = gridDim.x, q = G / NXCD, r = G % NXCD;
+    const unsigned xk = blockIdx.x % NXCD, jb = blockIdx.x / NXCD;
+    const unsigned j0 = (xk * q + min(xk, r) + jb) * CNT + threadIdx.x;
     const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
-    int kx0, lx0, ky0, ly0, kz0, lz0;
-    const int nxe = brick_entries(gx, m.NX, nbx, kx0, lx0);
-    const int nye = brick_entries(gy, m.NY, nby, ky0, ly0);
-    const int nze = brick_entries(gz, m.NZ, nbz, kz0, lz0);
-    // all (up to 8) loads first, then the sum in the fixed order
-    T v[8];
+    bool has[NPT], con[NPT];
+    int64_t g[NPT];
+    T v[NPT][8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-        v[e] = T(0);
-        if (ex < nxe && ey < nye && ez < nze) {
-            const int b = (kx0 + ex) + nbx * ((ky0 + ey) + nby * (kz0 + ez));
-            v[e] = face[(int64_t)b * BFACE + face_slot(ex ? 0 : lx0, ey ? 0 : ly0, ez ? 0 : lz0)];
+    for (int k = 0; k < NPT; ++k) {
+        int gx, gy, gz;
+        has[k] = combine_node_at(m, j0 + (unsigned)k * G * CNT, gx, gy, gz);
+        con[k] = has[k] && node_constrained(m, gx, gy, gz);
+        g[k] = has[k] ? node_index(m, gx, gy, gz) : 0;
+        const bool read = has[k] && !(SKIP_CONSTRAINED && con[k]);
+        int kx0 = 0, lx0 = 0, ky0 = 0, ly0 = 0, kz0 = 0, lz0 = 0, nxe = 0, nye = 0, nze = 0;
+        if (read) {
+            nxe = brick_entries(gx, m.NX, nbx, kx0, lx0);
+            nye = brick_entries(gy, m.NY, nby, ky0, ly0);
+            nze = brick_entries(gz, m.NZ, nbz, kz0, lz0);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+            v[k][e] = T(0);
+            if (ex < nxe && ey < nye && ez < nze) {
+                const int b = (kx0 + ex) + nbx * ((ky0 + ey) + nby * (kz0 + ez));
+                v[k][e] = face[(int64_t)b * BFACE + face_slot(ex ? 0 : lx0, ey ? 0 : ly0, ez ? 0 : lz0)];
+            }
         }
     }
-    T s = v[0];
 #pragma unroll
-    for (int e = 1; e < 8; ++e) s += v[e];
-    f(g, constrained, s);
+    for (int k = 0; k < NPT; ++k) {
+        if (!has[k]) continue;
+        T s = v[k][0];
+#pragma unroll
+        for (int e = 1; e < 8; ++e) s += v[k][e];
+        f(g[k], con[k], (SKIP_CONSTRAINED && con[k]) ? T(0) : s);
+    }
 }
 
-template <typename T, int DMODE>
+template <typename T, int DMODE, int NPT = 1>
 __device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
                                                T *__restrict__ y)
 {
-    combine_visit<T, DMODE != 0>(m, face, [&](int64_t g, bool constrained, T s) {
+    combine_visit<T, DMODE != 0, NPT>(m, face, [&](int64_t g, bool constrained, T s) {
         if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
         else y[g] = s;
     });

@@ -357,8 +357,9 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     }
 }
 
-// Second pass of an apply: shared nodes = sum of the bricks' face partials.
-template <typename T, bool CG, int DMODE = 1>
+// Second pass of an apply: shared nodes = sum of the bricks' face partials,
+// NPT nodes per thread (their loads in flight together).
+template <typename T, bool CG, int DMODE = 1, int NPT = 1>
 __global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
                                                            const T *__restrict__ x, T *__restrict__ y,
                                                            const CGState *cg)
@@ -366,8 +367,10 @@ __global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__r
     if (CG) {
         if (cg->done) return;
     }
-    combine_shared<T, DMODE>(m, face, x, y);
+    combine_shared<T, DMODE, NPT>(m, face, x, y);
 }
+
+constexpr int APPLY_NPT = 2; // nodes per thread in the combine pass of the applies
 
 int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
 
@@ -420,18 +423,18 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned rows = combine_blocks(m);
+    const unsigned rows = combine_blocks(m, APPLY_NPT);
     if (rows == 0) {
         // single brick: nothing shared
     } else if (fp32)
-        face_combine_kernel<float, false><<<rows, CNT, 0, s>>>(m, (const float *)face, (const float *)x, (float *)y,
-                                                               nullptr);
+        face_combine_kernel<float, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(m, (const float *)face, (const float *)x,
+                                                                            (float *)y, nullptr);
     else if (cg)
-        face_combine_kernel<double, true><<<rows, CNT, 0, s>>>(m, (const double *)face, (const double *)x,
-                                                               (double *)y, cg);
+        face_combine_kernel<double, true, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(m, (const double *)face,
+                                                                            (const double *)x, (double *)y, cg);
     else
-        face_combine_kernel<double, false><<<rows, CNT, 0, s>>>(m, (const double *)face, (const double *)x,
-                                                                (double *)y, nullptr);
+        face_combine_kernel<double, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(m, (const double *)face,
+                                                                             (const double *)x, (double *)y, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess || !cg) return e;
     return cg_alpha(cg, &r, nb, s);
