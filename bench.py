@@ -283,6 +283,7 @@ def main():
     t1 = time.perf_counter()
     kernel_ms, launches = ctx.timing_read(reset=True)
     apply_ms = sum(e[0].elapsed_time(e[1]) for e in ev[:args.steps])
+    per_step_us = [e[0].elapsed_time(e[1]) * 1e3 / args.applies for e in ev[:args.steps]]
     cg_ms = sum(e[1].elapsed_time(e[2]) for e in ev[:args.steps]) / args.steps
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = args.steps * args.applies * nn / (apply_ms * 1e-3)
@@ -342,6 +343,8 @@ def main():
                    "cells": n, "nodes": nn, "applies_per_step": args.applies},
         "roofline": roof,
         "cg": {"iters": info.iters, "ms": cg_ms, "rel_res": info.rel_res, "converged": bool(info.converged)},
+        # the spread of the timed steps (value above is their total)
+        "apply_steps": {"whole_apply_us": per_step_us, "median_us": sorted(per_step_us)[len(per_step_us) // 2]},
     }
 
     if not args.no_cold:
