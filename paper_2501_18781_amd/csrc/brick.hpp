@@ -156,64 +156,62 @@ struct Brick {
         if (lastx && lasty && lastz) node(I2{}, I2{}, I2{});
     }
 
-    // Stage a nodal field into LDS; Dirichlet nodes read as zero if mask.
-    template <typename T>
-    __device__ __forceinline__ void load(const KMesh &m, const T *__restrict__ g, T *lds, bool mask) const
-    {
-        for_owned_nodes(m, [&](int, int, int, int l, int64_t gi, bool constrained, bool) {
-            const T v = g[gi];
-            lds[l] = (mask && constrained) ? T(0) : v;
-        });
-    }
 
-    // Stage one or two nodal fields into LDS, unmasked.  Every global load is
-    // issued before the first LDS write, so a wavefront waits for memory
-    // once instead of once per group of owned nodes.
+    // Nodal fields are read through buffer resources based at the brick's
+    // first node (uniform over the workgroup): the owned node (2tx + a,
+    // 2ty + b, 2tz + c) lies at byte offset vo + a sizeof(T) (per thread,
+    // immediate) plus b sy + c sz (uniform), so the loads need no per-node
+    // 64-bit address arithmetic.  The brick's nodes span less than 2^32 bytes
+    // from its first node; the records limit is the rest of the array.
+    // Buffer resource of a nodal array based at the brick's first node, and
+    // the per-thread offset vo and uniform strides sy, sz (all in bytes).
     template <typename T>
-    __device__ __forceinline__ void load_fields(const KMesh &m, const T *__restrict__ g0, T *l0,
-                                                const T *__restrict__ g1 = nullptr, T *l1 = nullptr) const
-    {
-        T v0[27], v1[27];
-        for_owned_nodes(m, [&](int a, int b, int c, int, int64_t gi, bool, int) {
-            v0[a + 3 * b + 9 * c] = g0[gi];
-            if (g1) v1[a + 3 * b + 9 * c] = g1[gi];
-        });
-        for_owned_nodes(m, [&](int a, int b, int c, int l, int64_t, bool, int) {
-            l0[l] = v0[a + 3 * b + 9 * c];
-            if (g1) l1[l] = v1[a + 3 * b + 9 * c];
-        });
-    }
-
-    // load_fields through buffer resources based at the brick's first node
-    // (uniform over the workgroup): the owned node (2tx + a, 2ty + b, 2tz + c)
-    // lies at byte offset vo + a sizeof(T) (per thread, immediate) plus
-    // b sy + c sz (uniform), so the loads need no per-node 64-bit address
-    // arithmetic.  The brick's nodes span less than 2^32 bytes from its first
-    // node; the records limit is the rest of the array.
-    template <typename T>
-    __device__ __forceinline__ void load_fields_buf(const KMesh &m, const T *__restrict__ g0, T *l0,
-                                                    const T *__restrict__ g1 = nullptr, T *l1 = nullptr) const
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t nodal_rsrc(const KMesh &m, const T *g) const
     {
         static_assert(sizeof(T) == 8 || sizeof(T) == 4, "FP64 or FP32 nodal arrays");
         const int64_t o = node_index(m, 2 * c0x, 2 * c0y, 2 * c0z);
         const int64_t rem = ((int64_t)m.NX * m.NY * m.NZ - o) * (int64_t)sizeof(T);
         const int nrec = (int)(unsigned)(rem > 0xFFFFFFFFll ? 0xFFFFFFFFll : rem);
         constexpr int kFormat = 0x00020000; // buffer descriptor word 3 for the gfx9 family
-        const auto r0 = __builtin_amdgcn_make_buffer_rsrc((void *)(g0 + o), 0, nrec, kFormat);
-        const auto r1 = __builtin_amdgcn_make_buffer_rsrc((void *)((g1 ? g1 : g0) + o), 0, nrec, kFormat);
-        const unsigned vo = (unsigned)sizeof(T) * (unsigned)(2 * tx + m.NX * (2 * ty + m.NY * 2 * tz));
-        const unsigned sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
-        auto ld = [&](const auto &r, unsigned vofs, unsigned sofs) -> T {
-            if constexpr (sizeof(T) == 8)
-                return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vofs, sofs, 0));
-            else
-                return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vofs, sofs, 0));
-        };
+        return __builtin_amdgcn_make_buffer_rsrc((void *)(g + o), 0, nrec, kFormat);
+    }
+    template <typename T> __device__ __forceinline__ unsigned nodal_vo(const KMesh &m) const
+    {
+        return (unsigned)sizeof(T) * (unsigned)(2 * tx + m.NX * (2 * ty + m.NY * 2 * tz));
+    }
+    template <typename T>
+    static __device__ __forceinline__ T nodal_load(__amdgpu_buffer_rsrc_t r, unsigned vofs, unsigned sofs)
+    {
+        if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vofs, sofs, 0));
+        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vofs, sofs, 0));
+    }
+
+    // Stage a nodal field into LDS; Dirichlet nodes read as zero if mask.
+    template <typename T>
+    __device__ __forceinline__ void load(const KMesh &m, const T *__restrict__ g, T *lds, bool mask) const
+    {
+        const __amdgpu_buffer_rsrc_t r = nodal_rsrc(m, g);
+        const unsigned vo = nodal_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
+        for_owned_nodes(m, [&](int a, int b, int c, int l, int64_t, bool constrained, bool) {
+            const T v = nodal_load<T>(r, vo + (unsigned)(a * sizeof(T)), b * sy + c * sz);
+            lds[l] = (mask && constrained) ? T(0) : v;
+        });
+    }
+
+    // Stage one or two nodal fields into LDS, unmasked.  Every load is issued
+    // before the first LDS write, so a wavefront waits for memory once
+    // instead of once per group of owned nodes.
+    template <typename T>
+    __device__ __forceinline__ void load_fields(const KMesh &m, const T *__restrict__ g0, T *l0,
+                                                const T *__restrict__ g1 = nullptr, T *l1 = nullptr) const
+    {
+        const __amdgpu_buffer_rsrc_t r0 = nodal_rsrc(m, g0), r1 = nodal_rsrc(m, g1 ? g1 : g0);
+        const unsigned vo = nodal_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
         T v0[27], v1[27];
         for_owned_nodes(m, [&](int a, int b, int c, int, int64_t, bool, int) {
             const unsigned vofs = vo + (unsigned)(a * sizeof(T)), sofs = b * sy + c * sz;
-            v0[a + 3 * b + 9 * c] = ld(r0, vofs, sofs);
-            if (g1) v1[a + 3 * b + 9 * c] = ld(r1, vofs, sofs);
+            v0[a + 3 * b + 9 * c] = nodal_load<T>(r0, vofs, sofs);
+            if (g1) v1[a + 3 * b + 9 * c] = nodal_load<T>(r1, vofs, sofs);
         });
         for_owned_nodes(m, [&](int a, int b, int c, int l, int64_t, bool, int) {
             l0[l] = v0[a + 3 * b + 9 * c];

@@ -298,8 +298,8 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     const Brick br(m, threadIdx.x);
     T *xs = lds;
     T *ps = lds + BNB;
-    if (MODE != 1) br.load_fields_buf(m, x, xs, (const T *)a.phi, ps);
-    else br.load_fields_buf(m, x, xs);
+    if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
+    else br.load_fields(m, x, xs);
     if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + BNB, false);
     __syncthreads();
 
