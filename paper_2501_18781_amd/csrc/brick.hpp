@@ -3,13 +3,14 @@
 // A 64-thread workgroup (one wavefront) owns a brick of 4x4x4 cells, one
 // thread per cell; the brick's 9x9x9 Q2 nodes are staged in LDS.
 //
-// Node ownership is static: a cell owns its local nodes (a, b, c) with
-// a, b, c in {0, 1}, and the last valid cell of the brick in a direction
-// also owns the local nodes with index 2 in that direction.  Every brick
-// node is therefore loaded and finished by exactly one thread, with fully
-// unrolled code, no index division and no per-node branches.  A node's sum
-// runs over the cells of the brick that contain it (at most 8) in a fixed
-// order.
+// Staging is per cell: each thread reads the 27 nodes of its cell and
+// writes them to LDS (nodes shared by cells of the brick are written with
+// the same value by each).  Finishing is by ownership: a cell owns its
+// local nodes (a, b, c) with a, b, c in {0, 1}, and the last valid cell of
+// the brick in a direction also owns the local nodes with index 2 in that
+// direction, so every brick node is finished by exactly one thread, with
+// fully unrolled code and no index division.  A node's sum runs over the
+// cells of the brick that contain it (at most 8) in a fixed order.
 //
 // A node on a face that a neighbouring brick also touches ("shared") is not
 // written to the output: its partial sum goes to the brick's slot in a face
@@ -186,37 +187,89 @@ struct Brick {
         else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vofs, sofs, 0));
     }
 
+    // Staging reads all 27 nodes of the thread's cell (of the brick's first
+    // cell for a thread without one) and writes them to LDS.  A node that
+    // several cells of the brick share is written by each of them with the
+    // same value, so the staging needs no ownership test and no branches;
+    // every read lies inside the mesh.
+    template <typename T> __device__ __forceinline__ unsigned stage_vo(const KMesh &m) const
+    {
+        return valid ? nodal_vo<T>(m) : 0u;
+    }
+    __device__ __forceinline__ int stage_l0() const { return valid ? lds_index(2 * tx, 2 * ty, 2 * tz) : 0; }
+
     // Stage a nodal field into LDS; Dirichlet nodes read as zero if mask.
     template <typename T>
     __device__ __forceinline__ void load(const KMesh &m, const T *__restrict__ g, T *lds, bool mask) const
     {
         const __amdgpu_buffer_rsrc_t r = nodal_rsrc(m, g);
-        const unsigned vo = nodal_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
-        for_owned_nodes(m, [&](int a, int b, int c, int l, int64_t, bool constrained, bool) {
-            const T v = nodal_load<T>(r, vo + (unsigned)(a * sizeof(T)), b * sy + c * sz);
-            lds[l] = (mask && constrained) ? T(0) : v;
-        });
+        const unsigned vo = stage_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
+        const int l0 = stage_l0();
+        const unsigned f6 = mask ? m.dirichlet : 0u;
+        const int gx0 = 2 * (c0x + (valid ? tx : 0)), gy0 = 2 * (c0y + (valid ? ty : 0)),
+                  gz0 = 2 * (c0z + (valid ? tz : 0));
+        const bool dx0 = (f6 & 1u) && gx0 == 0, dx2 = (f6 & 2u) && gx0 + 2 == m.NX - 1;
+        const bool dy0 = (f6 & 4u) && gy0 == 0, dy2 = (f6 & 8u) && gy0 + 2 == m.NY - 1;
+        const bool dz0 = (f6 & 16u) && gz0 == 0, dz2 = (f6 & 32u) && gz0 + 2 == m.NZ - 1;
+        T v[27];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    v[a + 3 * b + 9 * c] = nodal_load<T>(r, vo + (unsigned)(a * sizeof(T)), b * sy + c * sz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const bool k = (a == 0 && dx0) || (a == 2 && dx2) || (b == 0 && dy0) || (b == 2 && dy2) ||
+                                   (c == 0 && dz0) || (c == 2 && dz2);
+                    lds[l0 + a + BP * b + BP * BP * c] = k ? T(0) : v[a + 3 * b + 9 * c];
+                }
     }
 
-    // Stage one or two nodal fields into LDS, unmasked.  Every load is issued
-    // before the first LDS write, so a wavefront waits for memory once
-    // instead of once per group of owned nodes.
-    template <typename T>
-    __device__ __forceinline__ void load_fields(const KMesh &m, const T *__restrict__ g0, T *l0,
-                                                const T *__restrict__ g1 = nullptr, T *l1 = nullptr) const
+    // Stage NF (1 or 2) nodal fields into LDS, unmasked, every read issued
+    // before the first LDS write.
+    template <int NF, typename T>
+    __device__ __forceinline__ void stage_fields(const KMesh &m, const T *__restrict__ g0, T *l0s,
+                                                 const T *__restrict__ g1, T *l1s) const
     {
-        const __amdgpu_buffer_rsrc_t r0 = nodal_rsrc(m, g0), r1 = nodal_rsrc(m, g1 ? g1 : g0);
-        const unsigned vo = nodal_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
+        const __amdgpu_buffer_rsrc_t r0 = nodal_rsrc(m, g0), r1 = nodal_rsrc(m, NF == 2 ? g1 : g0);
+        const unsigned vo = stage_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
+        const int l0 = stage_l0();
         T v0[27], v1[27];
-        for_owned_nodes(m, [&](int a, int b, int c, int, int64_t, bool, int) {
-            const unsigned vofs = vo + (unsigned)(a * sizeof(T)), sofs = b * sy + c * sz;
-            v0[a + 3 * b + 9 * c] = nodal_load<T>(r0, vofs, sofs);
-            if (g1) v1[a + 3 * b + 9 * c] = nodal_load<T>(r1, vofs, sofs);
-        });
-        for_owned_nodes(m, [&](int a, int b, int c, int l, int64_t, bool, int) {
-            l0[l] = v0[a + 3 * b + 9 * c];
-            if (g1) l1[l] = v1[a + 3 * b + 9 * c];
-        });
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const unsigned vofs = vo + (unsigned)(a * sizeof(T)), sofs = b * sy + c * sz;
+                    v0[a + 3 * b + 9 * c] = nodal_load<T>(r0, vofs, sofs);
+                    if constexpr (NF == 2) v1[a + 3 * b + 9 * c] = nodal_load<T>(r1, vofs, sofs);
+                }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int l = l0 + a + BP * b + BP * BP * c;
+                    l0s[l] = v0[a + 3 * b + 9 * c];
+                    if constexpr (NF == 2) l1s[l] = v1[a + 3 * b + 9 * c];
+                }
+    }
+    template <typename T> __device__ __forceinline__ void load_fields(const KMesh &m, const T *g0, T *l0s) const
+    {
+        stage_fields<1, T>(m, g0, l0s, nullptr, nullptr);
+    }
+    template <typename T>
+    __device__ __forceinline__ void load_fields(const KMesh &m, const T *g0, T *l0s, const T *g1, T *l1s) const
+    {
+        stage_fields<2, T>(m, g0, l0s, g1, l1s);
     }
 
     // The cell's 27 nodal values with its Dirichlet nodes read as zero (the
@@ -262,6 +315,54 @@ struct Brick {
     {
 #pragma unroll
         for (int i = 0; i < 27; ++i) E[i * BNT + t] = v[i];
+    }
+
+    // Lane shift within the 16-lane rows of the wavefront (DPP row_shr:S):
+    // lane i takes lane i - S of its row, the first S lanes of a row take 0.
+    template <int S, typename T> static __device__ __forceinline__ T row_shr(T v)
+    {
+        static_assert(S >= 1 && S <= 15, "row shift");
+        constexpr int ctrl = 0x110 + S;
+        if constexpr (sizeof(T) == 8) {
+            const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+            const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, ctrl, 0xF, 0xF, true);
+            const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), ctrl, 0xF, 0xF, true);
+            return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+        } else {
+            return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, true));
+        }
+    }
+
+    // Node sums in registers.  On entry u holds this cell's 27 contributions;
+    // on exit u[a + 3b + 9c] is the sum over the brick's cells containing
+    // that node for every node the cell owns (the entries of index 2 of a
+    // cell that is not the last in that direction are partial).  Cells are
+    // lanes t = tx + 4 ty + 16 tz, so the low neighbour in x is lane t - 1
+    // and in y lane t - 4, both in the same 16-lane row (a DPP row shift;
+    // the first cell of an x line is masked, the first of a y line is at a
+    // row's start and takes zero), and in z lane t - 16, exchanged through
+    // LDS (xch, 9 BNT values).  The sums run x, then y, then z: a fixed order.
+    // All lanes of the wavefront must call it.
+    template <typename T> __device__ __forceinline__ void assemble27(T *u, T *xch) const
+    {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { // x: (b, c) = (i % 3, i / 3)
+            const T nb = row_shr<1>(u[2 + 3 * i]);
+            u[3 * i] += tx > 0 ? nb : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) u[a + 9 * c] += row_shr<4>(u[a + 6 + 9 * c]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) xch[i * BNT + t] = u[18 + i];
+        __syncthreads();
+        const int src = tz > 0 ? t - BB * BB : t;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T nb = xch[i * BNT + src];
+            u[i] += tz > 0 ? nb : T(0);
+        }
     }
 
     // Sum over the brick's cells containing local node (a, b, c) of this

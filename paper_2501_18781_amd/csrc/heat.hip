@@ -286,10 +286,11 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     static_assert(CONV == 0 || (std::is_same<T, double>::value && MODE == 0 && !CG), "convective form: FP64 only");
     static_assert(MODE != 2 || std::is_same<T, double>::value, "three-phase coefficients: FP64 only");
     // x stays resident (Dirichlet rows y = x and the CG epilogue read it);
-    // phi (and the velocity) and then the cell contributions share the
-    // second region.
-    constexpr int STAGE = CONV ? 2 * BNB : BNB; // phi (and one velocity component at a time)
-    constexpr int LDS_T = BNB + (STAGE > 27 * BNT ? STAGE : 27 * BNT);
+    // the second region takes phi (with one velocity component at a time, or
+    // the frozen temperature), then the z exchange of the node sums (for the
+    // transposed convective form, the cell results).
+    constexpr int STAGE = CONV == 2 ? 27 * BNT : ((CONV || MODE == 2) ? 2 * BNB : BNB);
+    constexpr int LDS_T = BNB + STAGE;
     __shared__ T lds[LDS_T];
     __shared__ double red_lds[BNT];
     if (CG) {
@@ -328,24 +329,29 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         br.gather27_dirichlet(m, xs, u);
         heat_cell_apply<T>(u, cm, ck, ihx, ihy, ihz);
     }
-    __syncthreads(); // the phi region is now reused for the cell contributions
-    T *E = ps;
-    br.store_cell(E, u);
-    __syncthreads();
+    __syncthreads(); // the phi region is now reused for the node sums
+    if constexpr (CONV == 2) {
+        // through LDS: the transposed convective form has no registers to
+        // spare for the register exchange
+        T *E = ps;
+        br.store_cell(E, u);
+        __syncthreads();
+        br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t, bool, int) {
+            u[ai + 3 * bi + 9 * ci] = br.node_sum(E, ai, bi, ci);
+        });
+    } else {
+        br.assemble27(u, ps);
+    }
 
-    // Owned nodes: all node sums first (LDS), then the stores.  Complete
-    // nodes go to y, shared ones to the face buffer; Dirichlet rows get
-    // y_i = x_i (shared ones in the combine pass).  x.Ax = sum over bricks of
-    // x_i times the brick's partial sum at node i, with x_i^2 for a Dirichlet
-    // node counted once, by the brick that finishes it.
+    // Owned nodes: complete nodes go to y, shared ones to the face buffer;
+    // Dirichlet rows get y_i = x_i (shared ones in the combine pass).
+    // x.Ax = sum over bricks of x_i times the brick's partial sum at node i,
+    // with x_i^2 for a Dirichlet node counted once, by the brick that
+    // finishes it.
     double energy = 0.0;
     T *fb = face + (int64_t)br.brick * BFACE;
-    T sums[27];
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t, bool, int) {
-        sums[ai + 3 * bi + 9 * ci] = br.node_sum(E, ai, bi, ci);
-    });
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
-        const T xv = xs[l], s = sums[ai + 3 * bi + 9 * ci];
+        const T xv = xs[l], s = u[ai + 3 * bi + 9 * ci];
         if (CG) energy += constrained ? ((sh & 2) ? 0.0 : (double)xv * (double)xv) : (double)xv * (double)s;
         T *dst = sh ? fb + br.fslot(ai, bi, ci, l) : y + g;
         *dst = constrained ? xv : s;

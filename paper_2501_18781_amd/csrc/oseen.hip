@@ -223,9 +223,9 @@ __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, 
                                                           double *__restrict__ y, double *__restrict__ face)
 {
     // staging: phi, x (3 components), u0 (3 components) and, with three
-    // phases, the frozen temperature; then the cell contributions of the 3
+    // phases, the frozen temperature; then the node-sum exchange of the 3
     // components
-    constexpr int STAGE = (TP ? 8 : 7) * BNB, CONTRIB = 3 * 27 * BNT;
+    constexpr int STAGE = (TP ? 8 : 7) * BNB, CONTRIB = 3 * 9 * BNT;
     __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
     const int comp = threadIdx.x / BNT; // uniform over a wavefront
     const Brick br(m, threadIdx.x % BNT);
@@ -241,14 +241,12 @@ __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     else if (comp == 1) oseen_cell<1, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
     else oseen_cell<2, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
     __syncthreads(); // staging no longer read
-    double *E = lds + comp * 27 * BNT;
-    br.store_cell(E, acc);
-    __syncthreads();
+    br.assemble27(acc, lds + comp * 9 * BNT);
     double *fb = face + ((int64_t)comp * n_bricks(m) + br.brick) * BFACE;
     double *yc = y + comp * nn;
     const double *xc = x + comp * nn;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
-        const double s = br.node_sum(E, ai, bi, ci);
+        const double s = acc[ai + 3 * bi + 9 * ci];
         double *dst = sh ? fb + br.fslot(ai, bi, ci, l) : yc + g;
         *dst = s;
     });

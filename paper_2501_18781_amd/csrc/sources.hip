@@ -24,7 +24,7 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
                                                           const double *__restrict__ T, double *__restrict__ b,
                                                           double *__restrict__ face)
 {
-    constexpr int LDS_T = 2 * BNB > 27 * BNT ? 2 * BNB : 27 * BNT; // phi and T; then the cell results
+    constexpr int LDS_T = 2 * BNB > 9 * BNT ? 2 * BNB : 9 * BNT; // phi and T; then the node-sum exchange
     __shared__ double lds[LDS_T];
     const Brick br(m, threadIdx.x);
     double *ps = lds, *ts = lds + BNB;
@@ -111,12 +111,10 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
     interp3T(ph);
 
     __syncthreads(); // staging no longer read
-    double *E = lds;
-    br.store_cell(E, ph);
-    __syncthreads();
+    br.assemble27(ph, lds);
     double *fb = face + (int64_t)br.brick * BFACE;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
-        const double v = br.node_sum(E, ai, bi, ci);
+        const double v = ph[ai + 3 * bi + 9 * ci];
         if (sh) fb[br.fslot(ai, bi, ci, l)] = v; // constrained ones: 0 in the combine
         else b[g] = constrained ? 0.0 : v;
     });
