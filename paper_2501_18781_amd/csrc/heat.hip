@@ -157,6 +157,23 @@ __device__ __forceinline__ void heat_cell_apply(T *u, const T *cm, const T *ck, 
     for (int q = 0; q < 27; ++q) u[q] = acc[q];
 }
 
+// The same on a mesh with equal cell edges: ck4 = ck / (4 h^2) (1/h^2 and
+// the 1/4 of D'' = 2 D' folded into the stiffness weights), so the
+// derivative passes need no scaling.
+template <typename T> __device__ __forceinline__ void heat_cell_apply_iso(T *u, const T *cm, const T *ck4)
+{
+    interp3(u);
+    T acc[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) acc[q] = cm[q] * u[q];
+    grad2_line_apply<T, 0>(u, ck4, acc);
+    grad2_line_apply<T, 1>(u, ck4, acc);
+    grad2_line_apply<T, 2>(u, ck4, acc);
+    interp3T(acc);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) u[q] = acc[q];
+}
+
 // A coefficient at the 27 Gauss points from H_q: A[class] + B[class] H_q,
 // class = number of middle-point indices of q (the Gauss weight's class).
 struct ClassCoef {
@@ -278,7 +295,7 @@ __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMes
 
 // CONV: 0 plain heat operator; 1 with the convective term; 2 its transpose
 // (FP64, level-set coefficients, no CG epilogue).
-template <typename T, int MODE, int HK, bool CG, int CONV = 0>
+template <typename T, int MODE, int HK, bool CG, int CONV = 0, bool ISO = false>
 __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, const T *__restrict__ x,
                                                          T *__restrict__ y, T *__restrict__ face, CGState *cg,
                                                          RedWS red)
@@ -313,6 +330,11 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         br.gather27_dirichlet(m, xs, u);
         heat_conv_cell_apply<CONV == 2, HK>(br, m, a, ps, ps + BNB, u);
     } else {
+        // With equal cell edges (ISO) 1/h^2 and the 1/4 of D'' = 2 D' go into
+        // the stiffness weights, and the derivative passes take the integer
+        // form (5 operations per line instead of 7).
+        static_assert(!ISO || MODE != 2, "equal-edge form: level-set and quadrature-point modes");
+        const T akw = ISO ? ak_w * ihx * T(0.25) : ak_w;
         T cm[27], ck[27];
         if constexpr (MODE == 2) {
             heat_cell_coeffs3<HK>(br, m, a, (const double *)ps, (const double *)ps + BNB, cm, ck);
@@ -320,14 +342,15 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
             T ph[27];
             br.gather27(ps, ph);
             interp3(ph);
-            heat_cell_coeffs<T, 0, HK>(a, ph, nullptr, nullptr, am_w, ak_w, cm, ck);
+            heat_cell_coeffs<T, 0, HK>(a, ph, nullptr, nullptr, am_w, akw, cm, ck);
         } else {
             const int64_t cell = br.valid ? br.cell_index(m) : 0;
             heat_cell_coeffs<T, 1, 0>(a, nullptr, (const T *)a.kq + 27 * cell, (const T *)a.rcq + 27 * cell, am_w,
-                                      ak_w, cm, ck);
+                                      akw, cm, ck);
         }
         br.gather27_dirichlet(m, xs, u);
-        heat_cell_apply<T>(u, cm, ck, ihx, ihy, ihz);
+        if constexpr (ISO) heat_cell_apply_iso<T>(u, cm, ck);
+        else heat_cell_apply<T>(u, cm, ck, ihx, ihy, ihz);
     }
     __syncthreads(); // the phi region is now reused for the node sums
     if constexpr (CONV == 2) {
@@ -395,34 +418,45 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     if (a.mode == 2 && fp32) return hipErrorInvalidValue;
     // (convective form, precision, coefficient mode, Heaviside form, CG epilogue)
     const int hk = a.mode == 1 ? 0 : (a.hkind ? 1 : 0);
-    const int key = (a.conv << 5) | (fp32 ? 16 : 0) | (a.mode << 2) | (hk << 1) | (cg ? 1 : 0);
+    // equal cell edges (a cube's cells): the scale-free derivative form
+    const bool iso = a.conv == 0 && a.mode != 2 && m.hx == m.hy && m.hy == m.hz;
+    const int key = (iso ? 128 : 0) | (a.conv << 5) | (fp32 ? 16 : 0) | (a.mode << 2) | (hk << 1) | (cg ? 1 : 0);
     switch (key) {
-#define HEAT_CASE(K, T, MODE, HK, CGF, CV)                                                                    \
+#define HEAT_CASE(K, T, MODE, HK, CGF, CV, ISO)                                                               \
     case K:                                                                                                   \
         if (ev0)                                                                                              \
-            hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF, CV>, dim3(nb), dim3(BNT), 0, s, ev0, ev1, \
-                                  0, m, a, (const T *)x, (T *)y, (T *)face, cg, r);                           \
+            hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF, CV, ISO>, dim3(nb), dim3(BNT), 0, s, ev0, \
+                                  ev1, 0, m, a, (const T *)x, (T *)y, (T *)face, cg, r);                      \
         else                                                                                                  \
-            heat_apply_kernel<T, MODE, HK, CGF, CV><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, \
-                                                                       cg, r);                                \
+            heat_apply_kernel<T, MODE, HK, CGF, CV, ISO><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y,        \
+                                                                            (T *)face, cg, r);                \
         break;
-        HEAT_CASE(0, double, 0, 0, false, 0)
-        HEAT_CASE(1, double, 0, 0, true, 0)
-        HEAT_CASE(2, double, 0, 1, false, 0)
-        HEAT_CASE(3, double, 0, 1, true, 0)
-        HEAT_CASE(4, double, 1, 0, false, 0)
-        HEAT_CASE(5, double, 1, 0, true, 0)
-        HEAT_CASE(8, double, 2, 0, false, 0)
-        HEAT_CASE(9, double, 2, 0, true, 0)
-        HEAT_CASE(10, double, 2, 1, false, 0)
-        HEAT_CASE(11, double, 2, 1, true, 0)
-        HEAT_CASE(16, float, 0, 0, false, 0)
-        HEAT_CASE(18, float, 0, 1, false, 0)
-        HEAT_CASE(20, float, 1, 0, false, 0)
-        HEAT_CASE(32, double, 0, 0, false, 1)
-        HEAT_CASE(34, double, 0, 1, false, 1)
-        HEAT_CASE(64, double, 0, 0, false, 2)
-        HEAT_CASE(66, double, 0, 1, false, 2)
+        HEAT_CASE(0, double, 0, 0, false, 0, false)
+        HEAT_CASE(1, double, 0, 0, true, 0, false)
+        HEAT_CASE(2, double, 0, 1, false, 0, false)
+        HEAT_CASE(3, double, 0, 1, true, 0, false)
+        HEAT_CASE(4, double, 1, 0, false, 0, false)
+        HEAT_CASE(5, double, 1, 0, true, 0, false)
+        HEAT_CASE(8, double, 2, 0, false, 0, false)
+        HEAT_CASE(9, double, 2, 0, true, 0, false)
+        HEAT_CASE(10, double, 2, 1, false, 0, false)
+        HEAT_CASE(11, double, 2, 1, true, 0, false)
+        HEAT_CASE(16, float, 0, 0, false, 0, false)
+        HEAT_CASE(18, float, 0, 1, false, 0, false)
+        HEAT_CASE(20, float, 1, 0, false, 0, false)
+        HEAT_CASE(32, double, 0, 0, false, 1, false)
+        HEAT_CASE(34, double, 0, 1, false, 1, false)
+        HEAT_CASE(64, double, 0, 0, false, 2, false)
+        HEAT_CASE(66, double, 0, 1, false, 2, false)
+        HEAT_CASE(128, double, 0, 0, false, 0, true)
+        HEAT_CASE(129, double, 0, 0, true, 0, true)
+        HEAT_CASE(130, double, 0, 1, false, 0, true)
+        HEAT_CASE(131, double, 0, 1, true, 0, true)
+        HEAT_CASE(132, double, 1, 0, false, 0, true)
+        HEAT_CASE(133, double, 1, 0, true, 0, true)
+        HEAT_CASE(144, float, 0, 0, false, 0, true)
+        HEAT_CASE(146, float, 0, 1, false, 0, true)
+        HEAT_CASE(148, float, 1, 0, false, 0, true)
 #undef HEAT_CASE
     default:
         return hipErrorInvalidValue;

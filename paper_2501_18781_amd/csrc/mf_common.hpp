@@ -96,6 +96,24 @@ template <typename T> struct Q2 {
         o1 += T(2) * (i0 - i2);
         o2 += T(-0.5) * i0 + T(0.5) * i1 + T(1.5) * i2;
     }
+    // D'' = 2 D' = [[-3, 4, -1], [-1, 0, 1], [1, -4, 3]] (integer entries):
+    // with d = i2 - i0 and w = 2 i1 - (i0 + i2), out = (d + 2w, d, d - 2w),
+    // 5 operations.
+    static __device__ __forceinline__ void deriv2(T i0, T i1, T i2, T &o0, T &o1, T &o2)
+    {
+        const T d = i2 - i0;
+        const T w = T(2) * i1 - (i0 + i2);
+        o0 = T(2) * w + d;
+        o1 = d;
+        o2 = T(-2) * w + d;
+    }
+    // out += D''^T in
+    static __device__ __forceinline__ void deriv2T_acc(T i0, T i1, T i2, T &o0, T &o1, T &o2)
+    {
+        o0 += T(-3) * i0 - i1 + i2;
+        o1 += T(4) * (i0 - i2);
+        o2 += T(3) * i2 + (i1 - i0);
+    }
     static __device__ __forceinline__ T weight(int q) { return q == 1 ? w1 : w0; }
 };
 
@@ -169,6 +187,20 @@ __device__ __forceinline__ void grad_line_apply(const T *u, const C &c, T ih, T 
             T t0, t1, t2;
             Q2<T>::deriv_scaled(u[i0], u[i1], u[i2], ih, t0, t1, t2);
             Q2<T>::derivT_acc(c[i0] * t0, c[i1] * t1, c[i2] * t2, acc[i0], acc[i1], acc[i2]);
+        }
+}
+
+// The same with D'' and no scale (the scale is in c): acc += D''^T (c .* D'' u).
+template <typename T, int DIR, typename C> __device__ __forceinline__ void grad2_line_apply(const T *u, const C &c, T *acc)
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int i0 = lidx<DIR>(0, m, n), i1 = lidx<DIR>(1, m, n), i2 = lidx<DIR>(2, m, n);
+            T t0, t1, t2;
+            Q2<T>::deriv2(u[i0], u[i1], u[i2], t0, t1, t2);
+            Q2<T>::deriv2T_acc(c[i0] * t0, c[i1] * t1, c[i2] * t2, acc[i0], acc[i1], acc[i2]);
         }
 }
 
