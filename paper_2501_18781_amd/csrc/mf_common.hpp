@@ -70,12 +70,16 @@ template <typename T> struct Q2 {
         o1 = s1 * (i0 + i2) + i1;
         o2 = s2 * i0 + s0 * i2;
     }
-    // collocation derivative (scaled by r): out = D' in
+    // collocation derivative (scaled by r): out = D' in, in even/odd form:
+    // with h = (i2 - i0) / 2 and w = 2 i1 - (i0 + i2), out = (h + w, h, h - w)
+    // (6 operations instead of 8).
     static __device__ __forceinline__ void deriv(T i0, T i1, T i2, T &o0, T &o1, T &o2)
     {
-        o0 = T(-1.5) * i0 + T(2) * i1 - T(0.5) * i2;
-        o1 = T(0.5) * (i2 - i0);
-        o2 = T(0.5) * i0 - T(2) * i1 + T(1.5) * i2;
+        const T h = T(0.5) * (i2 - i0);
+        const T w = T(2) * i1 - (i0 + i2);
+        o0 = h + w;
+        o1 = h;
+        o2 = h - w;
     }
     // out = s D' in for a uniform scale s, in even/odd form:
     // with e = i0 + i2, h = s (i2 - i0) / 2, w = s (2 i1 - e):
