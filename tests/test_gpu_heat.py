@@ -38,7 +38,7 @@ def heat_case(n, dirichlet, seed=0, phi_kind="sphere", hkind=0):
     return mesh, p, phi
 
 
-# meshes smaller than, equal to and straddling the 8x8x4 brick, with ragged tails
+# meshes smaller than, equal to and straddling the 4x4x4-cell brick, with ragged tails
 MESHES = [((1, 1, 1), 0), ((3, 3, 3), W.ALL_FACES), ((5, 3, 7), W.FACE_XLO | W.FACE_ZHI),
           ((9, 9, 9), W.ALL_FACES), ((8, 8, 8), 0), ((17, 10, 5), W.FACE_YHI | W.FACE_XHI)]
 
@@ -78,8 +78,12 @@ def test_heat_apply_heaviside_forms(gpu, hkind, phi_kind):
     assert relerr(y, A @ x) <= TOL64
 
 
-def test_heat_apply_quadrature_point_coefficients(gpu):
-    mesh = W.Mesh((7, 4, 5), dirichlet=W.FACE_ZLO | W.FACE_YHI)
+# (7, 4, 5) cells on the unit cube have unequal edges, (6, 6, 6) equal ones:
+# the two forms of the derivative passes
+@pytest.mark.parametrize("n", [(7, 4, 5), (6, 6, 6)])
+def test_heat_apply_quadrature_point_coefficients(gpu, n):
+    mesh = W.Mesh(n, dirichlet=W.FACE_ZLO | W.FACE_YHI)
+    print(f"heat apply, coefficients per quadrature point, n={n}", flush=True)
     rng = np.random.default_rng(5)
     kq = rng.uniform(0.3, 30.0, mesh.n_cells * 27)
     rcq = rng.uniform(5e3, 5e6, mesh.n_cells * 27)
