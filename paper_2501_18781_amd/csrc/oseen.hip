@@ -328,6 +328,9 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
         br.gather27(tcs, dw);
         interp3(dw);
     }
+    // unrolled (a loop over q would index the arrays at run time and put them
+    // in scratch memory), one point at a time
+#pragma unroll
     for (int q = 0; q < 27; ++q) {
         const double H = rw[q];
         const double W = vol * gauss_weight(q);
@@ -342,6 +345,7 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
             nu[q] = a.av * W * (a.mu_g + H * (a.mu_l - a.mu_g));
             dw[q] = 0.0;
         }
+        asm volatile("" : "+v"(rw[q]), "+v"(nu[q]), "+v"(dw[q]));
     }
     // Every term is a product of 1D factors along x, y, z, so its sum over the
     // Gauss points is a contraction of a Gauss-point weight with 1D tables
