@@ -766,7 +766,10 @@ hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void heat_qp_kernel(KMesh m, HeatArgs a, double *__restrict__ kq, double *__restrict__ rcq)
+constexpr int QPT = 256; // threads per workgroup of the quadrature-point coefficient pass
+
+__global__ void __launch_bounds__(QPT) heat_qp_kernel(KMesh m, HeatArgs a, double *__restrict__ kq,
+                                                     double *__restrict__ rcq)
 {
     const int64_t nc = (int64_t)m.nx * m.ny * m.nz;
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -781,6 +784,9 @@ __global__ void heat_qp_kernel(KMesh m, HeatArgs a, double *__restrict__ kq, dou
 #pragma unroll
             for (int i = 0; i < 3; ++i) ph[i + 3 * b + 9 * c] = phi[node_index(m, 2 * cx + i, 2 * cy + b, 2 * cz + c)];
     interp3(ph);
+    // unrolled: a loop over q would index ph at run time and put it in
+    // scratch memory
+#pragma unroll
     for (int q = 0; q < 27; ++q) {
         const double H = heaviside<double>(a.hkind, a.eps, ph[q], nullptr);
         kq[cell * 27 + q] = a.k_g + H * (a.k_l - a.k_g);
@@ -791,7 +797,7 @@ __global__ void heat_qp_kernel(KMesh m, HeatArgs a, double *__restrict__ kq, dou
 hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double *rcq, hipStream_t s)
 {
     const int64_t nc = (int64_t)m.nx * m.ny * m.nz;
-    heat_qp_kernel<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(m, a, kq, rcq);
+    heat_qp_kernel<<<(unsigned)((nc + QPT - 1) / QPT), QPT, 0, s>>>(m, a, kq, rcq);
     return hipGetLastError();
 }
 
