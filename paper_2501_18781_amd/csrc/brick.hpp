@@ -159,13 +159,12 @@ struct Brick {
 
 
     // Nodal fields are read through buffer resources based at the brick's
-    // first node (uniform over the workgroup): the owned node (2tx + a,
-    // 2ty + b, 2tz + c) lies at byte offset vo + a sizeof(T) (per thread,
-    // immediate) plus b sy + c sz (uniform), so the loads need no per-node
-    // 64-bit address arithmetic.  The brick's nodes span less than 2^32 bytes
-    // from its first node; the records limit is the rest of the array.
-    // Buffer resource of a nodal array based at the brick's first node, and
-    // the per-thread offset vo and uniform strides sy, sz (all in bytes).
+    // first node (uniform over the workgroup): node (2tx + a, 2ty + b,
+    // 2tz + c) of the thread's cell lies at byte offset vo + a sizeof(T)
+    // (per thread, immediate) plus b sy + c sz (uniform), so the loads need
+    // no per-node 64-bit address arithmetic.  The brick's nodes span less
+    // than 2^32 bytes from its first node; the records limit is the rest of
+    // the array.  nodal_rsrc is the resource, nodal_vo the per-thread offset.
     template <typename T>
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t nodal_rsrc(const KMesh &m, const T *g) const
     {
