@@ -88,7 +88,8 @@ __device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, T *phq, cons
 // with rc_lg the liquid-gas blend of eq. deltaRhoCp.
 template <int HK>
 __device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &m, const HeatArgs &a,
-                                                  const double *ps, const double *ts, double *cm, double *ck)
+                                                  const double *ps, const double *ts, double *cm, double *ck,
+                                                  double ck_scale = 1.0)
 {
     double ph[27], gn[27], Tq[27];
     br.gather27(ps, ph);
@@ -122,6 +123,7 @@ __device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &
     const double vol = m.hx * m.hy * m.hz;
     const double c_rcp = 3.0 / (a.rc_g * a.rc_g + a.rc_l * a.rc_g + a.rc_l * a.rc_l);
     const double inv_range = 1.0 / (a.T_liq - a.T_sol);
+    const double ak_r2 = a.ak * ck_scale / (kR * kR); // ck_scale: 1, or 1/(4 h^2) for the equal-edge form
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         double dH;
@@ -136,7 +138,7 @@ __device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &
         const double react = a.penalty * dH * sqrt(gn[q]) * (a.rc_g + H * (a.rc_l - a.rc_g)) * c_rcp;
         const double w = vol * Q2<double>::weight(q % 3) * Q2<double>::weight((q / 3) % 3) * Q2<double>::weight(q / 9);
         cm[q] = w * (a.am * rc + react);
-        ck[q] = w * a.ak * k / (kR * kR);
+        ck[q] = w * ak_r2 * k;
         asm volatile("" : "+v"(cm[q]), "+v"(ck[q])); // one point at a time
     }
 }
@@ -333,11 +335,11 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         // With equal cell edges (ISO) 1/h^2 and the 1/4 of D'' = 2 D' go into
         // the stiffness weights, and the derivative passes take the integer
         // form (5 operations per line instead of 7).
-        static_assert(!ISO || MODE != 2, "equal-edge form: level-set and quadrature-point modes");
         const T akw = ISO ? ak_w * ihx * T(0.25) : ak_w;
         T cm[27], ck[27];
         if constexpr (MODE == 2) {
-            heat_cell_coeffs3<HK>(br, m, a, (const double *)ps, (const double *)ps + BNB, cm, ck);
+            heat_cell_coeffs3<HK>(br, m, a, (const double *)ps, (const double *)ps + BNB, cm, ck,
+                                  ISO ? double(ihx) * 0.25 : 1.0);
         } else if (MODE == 0) {
             T ph[27];
             br.gather27(ps, ph);
@@ -419,7 +421,7 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     // (convective form, precision, coefficient mode, Heaviside form, CG epilogue)
     const int hk = a.mode == 1 ? 0 : (a.hkind ? 1 : 0);
     // equal cell edges (a cube's cells): the scale-free derivative form
-    const bool iso = a.conv == 0 && a.mode != 2 && m.hx == m.hy && m.hy == m.hz;
+    const bool iso = a.conv == 0 && m.hx == m.hy && m.hy == m.hz;
     const int key = (iso ? 128 : 0) | (a.conv << 5) | (fp32 ? 16 : 0) | (a.mode << 2) | (hk << 1) | (cg ? 1 : 0);
     switch (key) {
 #define HEAT_CASE(K, T, MODE, HK, CGF, CV, ISO)                                                               \
@@ -454,6 +456,10 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
         HEAT_CASE(131, double, 0, 1, true, 0, true)
         HEAT_CASE(132, double, 1, 0, false, 0, true)
         HEAT_CASE(133, double, 1, 0, true, 0, true)
+        HEAT_CASE(136, double, 2, 0, false, 0, true)
+        HEAT_CASE(137, double, 2, 0, true, 0, true)
+        HEAT_CASE(138, double, 2, 1, false, 0, true)
+        HEAT_CASE(139, double, 2, 1, true, 0, true)
         HEAT_CASE(144, float, 0, 0, false, 0, true)
         HEAT_CASE(146, float, 0, 1, false, 0, true)
         HEAT_CASE(148, float, 1, 0, false, 0, true)
