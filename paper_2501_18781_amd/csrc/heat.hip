@@ -226,7 +226,7 @@ __device__ __forceinline__ void cell_heaviside(const Brick &br, const HeatArgs &
 // The velocity components are staged in LDS one at a time, in the region
 // vs, just before the pass that uses them (all threads of the brick call
 // this function: the staging barriers are uniform).
-template <bool TR, int HK>
+template <bool TR, int HK, bool ISO = false>
 __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMesh &m, const HeatArgs &a,
                                                      const double *ps, double *vs, double *u)
 {
@@ -246,10 +246,19 @@ __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMes
         br.gather27(vs, v);
         interp3(v);
     };
+    // with equal cell edges (ISO) 1/(4 h^2) is in the stiffness weights and
+    // the passes take the integer derivative form
+    const double kscale = ISO ? a.ak * vol / (kR * kR) * 0.25 / (h[0] * h[0]) : a.ak * vol / (kR * kR);
     auto conduction = [&](const ClassCoef &ckw) {
-        grad_line_apply<double, 0>(u, ckw, 1.0 / (h[0] * h[0]), acc);
-        grad_line_apply<double, 1>(u, ckw, 1.0 / (h[1] * h[1]), acc);
-        grad_line_apply<double, 2>(u, ckw, 1.0 / (h[2] * h[2]), acc);
+        if constexpr (ISO) {
+            grad2_line_apply<double, 0>(u, ckw, acc);
+            grad2_line_apply<double, 1>(u, ckw, acc);
+            grad2_line_apply<double, 2>(u, ckw, acc);
+        } else {
+            grad_line_apply<double, 0>(u, ckw, 1.0 / (h[0] * h[0]), acc);
+            grad_line_apply<double, 1>(u, ckw, 1.0 / (h[1] * h[1]), acc);
+            grad_line_apply<double, 2>(u, ckw, 1.0 / (h[2] * h[2]), acc);
+        }
     };
 #pragma unroll
     for (int q = 0; q < 27; ++q) acc[q] = 0.0;
@@ -265,18 +274,24 @@ __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMes
         const ClassCoef rcw(v, vol, a.rc_g, a.rc_l);
 #pragma unroll
         for (int q = 0; q < 27; ++q) acc[q] = rcw[q] * (a.am * u[q] + a.ac * acc[q]);
-        const ClassCoef ckw(v, a.ak * vol / (kR * kR), a.k_g, a.k_l);
+        const ClassCoef ckw(v, kscale, a.k_g, a.k_l);
 #pragma unroll
         for (int q = 0; q < 27; ++q) v[q] = ckw[q]; // H -> k W, in place
         pin27(v);
         pin27(u);
         pin27(acc);
-        grad_line_apply<double, 0>(u, v, 1.0 / (h[0] * h[0]), acc);
-        grad_line_apply<double, 1>(u, v, 1.0 / (h[1] * h[1]), acc);
-        grad_line_apply<double, 2>(u, v, 1.0 / (h[2] * h[2]), acc);
+        if constexpr (ISO) {
+            grad2_line_apply<double, 0>(u, v, acc);
+            grad2_line_apply<double, 1>(u, v, acc);
+            grad2_line_apply<double, 2>(u, v, acc);
+        } else {
+            grad_line_apply<double, 0>(u, v, 1.0 / (h[0] * h[0]), acc);
+            grad_line_apply<double, 1>(u, v, 1.0 / (h[1] * h[1]), acc);
+            grad_line_apply<double, 2>(u, v, 1.0 / (h[2] * h[2]), acc);
+        }
     } else {
         cell_heaviside<HK>(br, a, ps, v);
-        conduction(ClassCoef(v, a.ak * vol / (kR * kR), a.k_g, a.k_l));
+        conduction(ClassCoef(v, kscale, a.k_g, a.k_l));
         const ClassCoef rcw(v, vol, a.rc_g, a.rc_l);
 #pragma unroll
         for (int q = 0; q < 27; ++q) {
@@ -330,7 +345,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     T u[27];
     if constexpr (CONV != 0) {
         br.gather27_dirichlet(m, xs, u);
-        heat_conv_cell_apply<CONV == 2, HK>(br, m, a, ps, ps + BNB, u);
+        heat_conv_cell_apply<CONV == 2, HK, ISO>(br, m, a, ps, ps + BNB, u);
     } else {
         // With equal cell edges (ISO) 1/h^2 and the 1/4 of D'' = 2 D' go into
         // the stiffness weights, and the derivative passes take the integer
@@ -421,7 +436,7 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     // (convective form, precision, coefficient mode, Heaviside form, CG epilogue)
     const int hk = a.mode == 1 ? 0 : (a.hkind ? 1 : 0);
     // equal cell edges (a cube's cells): the scale-free derivative form
-    const bool iso = a.conv == 0 && m.hx == m.hy && m.hy == m.hz;
+    const bool iso = m.hx == m.hy && m.hy == m.hz;
     const int key = (iso ? 128 : 0) | (a.conv << 5) | (fp32 ? 16 : 0) | (a.mode << 2) | (hk << 1) | (cg ? 1 : 0);
     switch (key) {
 #define HEAT_CASE(K, T, MODE, HK, CGF, CV, ISO)                                                               \
@@ -460,6 +475,10 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
         HEAT_CASE(137, double, 2, 0, true, 0, true)
         HEAT_CASE(138, double, 2, 1, false, 0, true)
         HEAT_CASE(139, double, 2, 1, true, 0, true)
+        HEAT_CASE(160, double, 0, 0, false, 1, true)
+        HEAT_CASE(162, double, 0, 1, false, 1, true)
+        HEAT_CASE(192, double, 0, 0, false, 2, true)
+        HEAT_CASE(194, double, 0, 1, false, 2, true)
         HEAT_CASE(144, float, 0, 0, false, 0, true)
         HEAT_CASE(146, float, 0, 1, false, 0, true)
         HEAT_CASE(148, float, 1, 0, false, 0, true)
