@@ -99,7 +99,7 @@ typedef struct {
     const void *rc_q;   /* rho c_p per quadrature point [n_cells*27] (QUAD mode) */
     const void *u0;     /* Oseen convective velocity, nodal [3][n_nodes]; for heat, optional:
                            the convective term alpha_c C(rc, u0) (FP64, LEVELSET mode) */
-    /* Three phases (Sec. 3.2-3.3, FP64, LEVELSET mode): if T_coef is given the
+    /* Three phases (Sec. 4.1-4.3, FP64, LEVELSET mode): if T_coef is given the
      * coefficients are evaluated at that frozen nodal temperature with the
      * solid fraction f_s(T) (eq. solid_fraction, solidus T_sol < liquidus
      * T_liq), H_s = 3 f_s^2 - 2 f_s^3 (eq. heaviside_sl) and the blends
@@ -278,6 +278,67 @@ mf_status mf_heat_source_rhs(mf_ctx *ctx, const mf_operator *op, const mf_heat_s
  * dk_q, drc_q may be NULL.  All arrays FP64. */
 mf_status mf_heat_coeff_grad(mf_ctx *ctx, const mf_operator *op, const double *T, const double *dT,
                              const double *lambda, double *dk_q, double *drc_q, double *dphi, mf_stream stream);
+
+/* ---- whole implicit heat steps (Sec. 2.1 eq. heat_transfer, backward Euler; App. B) ---- */
+
+/* Boundary values.  In the step functions below a Dirichlet face holds the
+ * values of T_old: T = T_old on Dirichlet nodes, and the free rows see those
+ * values (the operator's columns at Dirichlet nodes are present when it acts
+ * on T_old), i.e. on the free rows
+ *     alpha_m M(rc) (T - T_old) + alpha_k K(k) T (+ R T) = b.
+ * With T_old = 0 on Dirichlet nodes this is the homogeneous problem. */
+
+/* One backward-Euler step of the two-phase heat equation in delta form:
+ * dT = T - T_old solves A dT = -alpha_k K T_old on the free rows (dT = 0 on
+ * Dirichlet nodes) by Jacobi-CG (x0 = 0, stopping test and info as
+ * mf_cg_solve), then T = T_old + dT.  Forming T - T_old from T would cancel
+ * about eight digits at small time steps, so dT is returned as well.
+ * op: FP64 heat operator, LEVELSET or QUAD coefficients, no convection, no
+ * T_coef, no penalty.  T_old, T, dT: distinct device arrays of n_nodes
+ * doubles; T and dT are written.  Returns the CG status (MF_NOT_CONVERGED
+ * and MF_BREAKDOWN still write T and dT). */
+mf_status mf_heat_step(mf_ctx *ctx, const mf_operator *op, const double *T_old, double *T, double *dT, double rtol,
+                       int32_t maxit, mf_solve_info *info, mf_stream stream);
+
+/* Adjoint of mf_heat_step for a loss L(T, dT) with gradients gT = dL/dT and
+ * gdT = dL/d(dT) (either may be NULL: zero).  Solves A lam = gT + gdT on
+ * the free rows (A is symmetric; lam = 0 on Dirichlet nodes) by Jacobi-CG,
+ * then writes, for every output that is not NULL:
+ *   dk_q, drc_q, dphi   the gradients of mf_heat_coeff_grad at (T, dT, lam)
+ *                       (dphi needs LEVELSET mode);
+ *   gT_old = dL/dT_old = gT - alpha_k K lam, the operator's columns at
+ *                       Dirichlet nodes present (on free rows this equals
+ *                       alpha_m M lam - gdT; on Dirichlet rows gT - alpha_k (K lam)).
+ * T and dT are those returned by mf_heat_step.  All arrays FP64 device
+ * memory (quadrature-point arrays n_cells*27, nodal ones n_nodes). */
+mf_status mf_heat_step_adjoint(mf_ctx *ctx, const mf_operator *op, const double *T, const double *dT, const double *gT,
+                               const double *gdT, double rtol, int32_t maxit, double *dk_q, double *drc_q,
+                               double *dphi, double *gT_old, mf_solve_info *info, mf_stream stream);
+
+typedef struct {
+    int32_t iterations;    /* Picard iterations done */
+    int32_t converged;     /* 1 if the update test was met */
+    int32_t cg_iterations; /* CG iterations summed over the Picard iterations */
+    int32_t pad;
+    double update;         /* ||T^{k+1} - T^k|| / ||T^{k+1}|| of the last iteration */
+} mf_picard_info;
+
+/* One implicit heat step with temperature-dependent three-phase coefficients
+ * (Sec. 4.1-4.3), the Tanasawa penalty of op (App. C) and the interface
+ * sources of src (Sec. 2.4, Sec. 4; NULL: none), by Picard iteration:
+ * T^0 = T_old; with the coefficients and b frozen at T^k, solve
+ *     A(T^k) dT = b(T^k) - (K(T^k) + R(T^k)) T_old   (free rows; dT = 0 on Dirichlet nodes)
+ * by Jacobi-CG to cg_rtol, set T^{k+1} = T_old + dT, and stop when
+ * ||T^{k+1} - T^k|| <= tol ||T^{k+1}||.  A = alpha_m M + K + R is symmetric.
+ * op: FP64 heat operator in LEVELSET mode with the three-phase data (k_s,
+ * rc_s, T_sol < T_liq), no convection and T_coef = NULL (the iterate is
+ * used).  T: n_nodes doubles, written (the last iterate on any status).
+ * updates, cg_iters: optional host arrays of maxit entries, per iteration.
+ * Returns MF_NOT_CONVERGED after maxit iterations, MF_BREAKDOWN on a CG
+ * breakdown or a non-finite iterate. */
+mf_status mf_heat_picard_step(mf_ctx *ctx, const mf_operator *op, const mf_heat_sources *src, const double *T_old,
+                              double *T, double tol, int32_t maxit, double cg_rtol, int32_t cg_maxit,
+                              mf_picard_info *info, double *updates, int32_t *cg_iters, mf_stream stream);
 
 #ifdef __cplusplus
 }

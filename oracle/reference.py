@@ -671,3 +671,83 @@ def heat_sources(mesh, params, sources, phi, T, **override) -> np.ndarray:
     b = np.zeros(n_nodes(mesh))
     lib().orc_heat_sources(ctypes.byref(m), ctypes.byref(c), ctypes.byref(s), _p(_f64(phi)), _p(_f64(T)), _p(b))
     return b
+
+
+# ---------------------------------------------------------------------------
+# Whole implicit heat steps with the Dirichlet nodes held at T_old
+# ---------------------------------------------------------------------------
+
+def without_dirichlet(mesh) -> MeshDesc:
+    """The same mesh with no Dirichlet faces: every column of the operator present."""
+    return MeshDesc(tuple(int(c) for c in mesh.n), tuple(getattr(mesh, "lo", (0.0, 0.0, 0.0))),
+                    tuple(getattr(mesh, "hi", (1.0, 1.0, 1.0))), 0)
+
+
+def heat_step(mesh, params, T_old, phi=None, kq=None, rcq=None, delta=True):
+    """One backward-Euler step of the heat equation (Sec. 2.1, eq. heat_transfer)
+    with the Dirichlet nodes held at T_old; on the free rows
+
+        alpha_m M (T - T_old) + alpha_k K T = 0,    T = T_old on Dirichlet nodes,
+
+    with M and K assembled on the mesh without Dirichlet faces (every column
+    present) and the free block solved by sparse LU.
+
+    delta=False solves for T itself:  A_ff T_f = (alpha_m M T_old)_f - A_fD T_old_D.
+    delta=True solves for dT = T - T_old:  A_ff dT_f = -(alpha_k K T_old)_f, which
+    avoids the cancellation of forming T - T_old at small time steps.
+    Returns (T, dT)."""
+    T_old = _f64(T_old)
+    m0 = without_dirichlet(mesh)
+    free = ~constrained_mask(mesh)
+    A = heat_matrix(m0, params, phi=phi, kq=kq, rcq=rcq).tocsr()
+    Aff = A[free][:, free]
+    if delta:
+        K = heat_matrix(m0, params, phi=phi, kq=kq, rcq=rcq, alpha_m=0.0)
+        dT = np.zeros_like(T_old)
+        dT[free] = direct_solve(Aff, -(K @ T_old)[free])
+        return T_old + dT, dT
+    M = heat_matrix(m0, params, phi=phi, kq=kq, rcq=rcq, alpha_k=0.0)
+    T = T_old.copy()
+    rhs = (M @ T_old)[free] - A[free][:, ~free] @ T_old[~free]
+    T[free] = direct_solve(Aff, rhs)
+    return T, T - T_old
+
+
+@dataclass
+class PicardResult:
+    T: np.ndarray
+    iterations: int
+    converged: bool
+    updates: List[float]
+
+
+def picard_step(mesh, params, phi, T_old, sources=None, tol=1e-11, maxit=40) -> PicardResult:
+    """One implicit heat step with temperature-dependent three-phase coefficients
+    (Sec. 4.1-4.3), the Tanasawa penalty R of params.penalty (App. C) and the
+    interface sources b (Sec. 2.4, Sec. 4; None: none):
+
+        alpha_m M(T) (T - T_old) + K(T) T + R T = b(T)  on the free rows,
+        T = T_old on Dirichlet nodes,
+
+    by Picard iteration: with the coefficients and b frozen at T^k, solve the
+    linear step for dT = T^{k+1} - T_old on the free rows,
+        (alpha_m M + K + R)(T^k)_ff dT_f = (b(T^k) - (K + R)(T^k) T_old)_f,
+    with every column present (assembled on the mesh without Dirichlet faces),
+    by sparse LU, until ||T^{k+1} - T^k|| <= tol ||T^{k+1}||."""
+    T_old = _f64(T_old)
+    m0 = without_dirichlet(mesh)
+    free = ~constrained_mask(mesh)
+    T = T_old.copy()
+    updates = []
+    for k in range(maxit):
+        A = heat_matrix(m0, params, phi=phi, Tc=T).tocsr()
+        KR = heat_matrix(m0, params, phi=phi, Tc=T, alpha_m=0.0)
+        b = heat_sources(mesh, params, sources, phi, T) if sources is not None else np.zeros_like(T)
+        Tn = T_old.copy()
+        Tn[free] += direct_solve(A[free][:, free], (b - KR @ T_old)[free])
+        upd = float(np.linalg.norm(Tn - T) / np.linalg.norm(Tn))
+        updates.append(upd)
+        T = Tn
+        if upd <= tol:
+            return PicardResult(T, k + 1, True, updates)
+    return PicardResult(T, maxit, False, updates)

@@ -281,6 +281,55 @@ hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void
     return oseen_apply(c->km, oseen_args(op), transpose, (const double *)x, (double *)y, c->face, s, t);
 }
 
+// Kernel arguments of the interface heat sources (scalars formed on the host).
+mf_status source_args(mf_ctx *c, const mf_operator *op, const mf_heat_sources *src, const double *T,
+                      SourceArgs *out)
+{
+    if (src->terms & ~(MF_SRC_EVAPORATION | MF_SRC_LASER | MF_SRC_PENALTY))
+        return fail(c, MF_ERR_ARG, "unknown source terms");
+    SourceArgs sa{};
+    sa.terms = src->terms;
+    if (src->terms & MF_SRC_PENALTY) {
+        if (!(src->boiling_temperature > 0.0)) return fail(c, MF_ERR_ARG, "invalid boiling temperature");
+        sa.penalty = op->penalty;
+        sa.T_boil = src->boiling_temperature;
+    }
+    if (src->terms & MF_SRC_EVAPORATION) {
+        const double gam = src->evaporation_coefficient;
+        if (!T) return fail(c, MF_ERR_ARG, "evaporative cooling needs the temperature");
+        if (!(gam > 0.0 && gam <= 1.0) || !(src->molar_mass > 0.0) || !(src->boiling_temperature > 0.0))
+            return fail(c, MF_ERR_ARG, "invalid evaporation parameters");
+        sa.alpha_v = tanasawa_coefficient(src);
+        sa.T_boil = src->boiling_temperature;
+        sa.h_v = src->latent_heat;
+    }
+    if (src->terms & MF_SRC_LASER) {
+        const double *e = src->direction;
+        const double len = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        if (!(src->laser_radius > 0.0)) return fail(c, MF_ERR_ARG, "laser radius must be positive");
+        if (!(fabs(len - 1.0) <= 1e-9)) return fail(c, MF_ERR_ARG, "laser direction must be a unit vector");
+        sa.peak = 2.0 * src->absorptivity * src->laser_power / (M_PI * src->laser_radius * src->laser_radius);
+        sa.inv_r2 = 1.0 / (src->laser_radius * src->laser_radius);
+        for (int d = 0; d < 3; ++d) {
+            sa.focus[d] = src->focus[d];
+            sa.dir[d] = e[d];
+        }
+    }
+    sa.c_rcp = 3.0 / (op->rc_g * op->rc_g + op->rc_l * op->rc_g + op->rc_l * op->rc_l);
+    *out = sa;
+    return MF_OK;
+}
+
+// Tanasawa: alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R_s) rho_v / T_v^{3/2}, R_s = R/M
+// (eq. mDotTanasawa, mdot = alpha_v (T - T_v)).
+double tanasawa_coefficient(const mf_heat_sources *src)
+{
+    const double gam = src->evaporation_coefficient;
+    const double Rs = 8.314 / src->molar_mass;
+    return 2.0 * gam / (2.0 - gam) * src->latent_heat / sqrt(2.0 * M_PI * Rs) * src->vapor_density /
+           (src->boiling_temperature * sqrt(src->boiling_temperature));
+}
+
 extern "C" {
 
 mf_status mf_operator_apply(mf_ctx *c, const mf_operator *op, const void *x, void *y, mf_stream stream)
@@ -343,40 +392,8 @@ mf_status mf_heat_source_rhs(mf_ctx *c, const mf_operator *op, const mf_heat_sou
     if (op->kind != MF_HEAT || op->precision != MF_FP64 || op->coeff_mode != MF_COEFF_LEVELSET)
         return fail(c, MF_ERR_ARG, "mf_heat_source_rhs needs an FP64 heat operator in LEVELSET mode");
     if (!src || !b) return fail(c, MF_ERR_ARG, "null argument");
-    if (src->terms & ~(MF_SRC_EVAPORATION | MF_SRC_LASER | MF_SRC_PENALTY))
-        return fail(c, MF_ERR_ARG, "unknown source terms");
     SourceArgs sa{};
-    sa.terms = src->terms;
-    if (src->terms & MF_SRC_PENALTY) {
-        if (!(src->boiling_temperature > 0.0)) return fail(c, MF_ERR_ARG, "invalid boiling temperature");
-        sa.penalty = op->penalty;
-        sa.T_boil = src->boiling_temperature;
-    }
-    if (src->terms & MF_SRC_EVAPORATION) {
-        const double gam = src->evaporation_coefficient;
-        if (!T) return fail(c, MF_ERR_ARG, "evaporative cooling needs the temperature");
-        if (!(gam > 0.0 && gam <= 1.0) || !(src->molar_mass > 0.0) || !(src->boiling_temperature > 0.0))
-            return fail(c, MF_ERR_ARG, "invalid evaporation parameters");
-        // Tanasawa: alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R_s) rho_v / T_v^{3/2}, R_s = R/M
-        const double Rs = 8.314 / src->molar_mass;
-        sa.alpha_v = 2.0 * gam / (2.0 - gam) * src->latent_heat / sqrt(2.0 * M_PI * Rs) * src->vapor_density /
-                     (src->boiling_temperature * sqrt(src->boiling_temperature));
-        sa.T_boil = src->boiling_temperature;
-        sa.h_v = src->latent_heat;
-    }
-    if (src->terms & MF_SRC_LASER) {
-        const double *e = src->direction;
-        const double len = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-        if (!(src->laser_radius > 0.0)) return fail(c, MF_ERR_ARG, "laser radius must be positive");
-        if (!(fabs(len - 1.0) <= 1e-9)) return fail(c, MF_ERR_ARG, "laser direction must be a unit vector");
-        sa.peak = 2.0 * src->absorptivity * src->laser_power / (M_PI * src->laser_radius * src->laser_radius);
-        sa.inv_r2 = 1.0 / (src->laser_radius * src->laser_radius);
-        for (int d = 0; d < 3; ++d) {
-            sa.focus[d] = src->focus[d];
-            sa.dir[d] = e[d];
-        }
-    }
-    sa.c_rcp = 3.0 / (op->rc_g * op->rc_g + op->rc_l * op->rc_g + op->rc_l * op->rc_l);
+    if ((st = source_args(c, op, src, T, &sa))) return st;
     if ((st = ensure_face(c, 1))) return st;
     // the sources use the level set and rho c_p of the operator only (no convection)
     HeatArgs ha = heat_args(op);
@@ -441,7 +458,15 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
         return fail(c, MF_ERR_ARG, "mf_cg_solve supports MF_PC_NONE and MF_PC_JACOBI");
     if (!b || !x || !info) return fail(c, MF_ERR_ARG, "null argument");
     if (!(rtol >= 0.0) || maxit < 0) return fail(c, MF_ERR_ARG, "invalid rtol or maxit");
-    hipStream_t s = (hipStream_t)stream;
+    return cg_solve(c, op, precond, b, x, rtol, maxit, info, (hipStream_t)stream);
+}
+
+// The CG iteration of mf_cg_solve on a checked symmetric heat operator;
+// uses workspace vectors 0-4.
+mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *b, double *x, double rtol, int maxit,
+                   mf_solve_info *info, hipStream_t s)
+{
+    mf_status st;
     const int64_t n = c->nn;
     double *r, *z, *p, *q, *dinv = nullptr;
     if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)))

@@ -60,3 +60,12 @@ mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, doubl
 // ||b - A x|| / bnorm using workspace vector tmp.
 mf_status true_residual(mf_ctx *c, const mf_operator *op, int transpose, const double *b, const double *x,
                         double *tmp, double bnorm, double *out, hipStream_t s);
+// Jacobi-preconditioned (or plain) CG on a checked FP64 heat operator without
+// convection, x0 = 0; workspace vectors 0-4.  Status and info as mf_cg_solve.
+mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *b, double *x, double rtol, int maxit,
+                   mf_solve_info *info, hipStream_t s);
+// Kernel arguments of the interface heat sources of mf_heat_source_rhs.
+mf_status source_args(mf_ctx *c, const mf_operator *op, const mf_heat_sources *src, const double *T,
+                      mf::SourceArgs *out);
+// Tanasawa coefficient alpha_v of mdot = alpha_v (T - T_v) from the evaporation parameters.
+double tanasawa_coefficient(const mf_heat_sources *src);

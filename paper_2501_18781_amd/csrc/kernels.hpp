@@ -106,6 +106,15 @@ hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *bloc
 hipError_t vfill(void *y, double v, int64_t n, int fp32, hipStream_t s);
 hipError_t vcopy(const double *x, double *y, int64_t n, hipStream_t s);
 hipError_t vaxpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s); // y = a x + b y
+hipError_t vaxpbyz(double a, const double *x, double b, const double *y, double *z, int64_t n,
+                   hipStream_t s); // z = a x + b y
+// z = a x + b y on free dofs, 0 on Dirichlet dofs (comps components of the
+// mesh's nodes); a null x or y reads as zero.
+hipError_t vmask_axpby(const KMesh &m, int comps, double a, const double *x, double b, const double *y, double *z,
+                       hipStream_t s);
+// T = T_old + dT; out[0] = ||T_new - T_prev||^2, out[1] = ||T_new||^2 (device)
+hipError_t picard_update(const double *T_old, const double *dT, double *T, int64_t n, double *out, const RedWS *red,
+                         hipStream_t s);
 hipError_t vscale_copy(const double *scale_dev, int invert, const double *x, double *y, int64_t n,
                        hipStream_t s); // y = x * (*s) or x / (*s)
 hipError_t vmul(const double *d, const double *x, double *y, int64_t n, hipStream_t s); // y = d .* x

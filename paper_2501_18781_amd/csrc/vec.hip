@@ -202,6 +202,71 @@ hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// z = a x + b y out of place (z may alias x or y).
+__global__ void axpbyz_kernel(double a, const double *x, double b, const double *y, double *z, int64_t n)
+{
+    GRID_STRIDE(i, n) z[i] = a * x[i] + b * y[i];
+}
+hipError_t vaxpbyz(double a, const double *x, double b, const double *y, double *z, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    axpbyz_kernel<<<ew_blocks(n), VNT, 0, s>>>(a, x, b, y, z, n);
+    return hipGetLastError();
+}
+
+// z = a x + b y on the free dofs and 0 on the Dirichlet dofs of the mesh; a
+// null x or y reads as zero.  The grid runs over the comps * NY * NZ node
+// rows (y, z and the component from the workgroup index), x across threads,
+// so the Dirichlet test needs no division.
+__global__ void mask_axpby_kernel(KMesh m, double a, const double *__restrict__ x, double b,
+                                  const double *__restrict__ y, double *__restrict__ z)
+{
+    const int row = blockIdx.y, k = blockIdx.z % m.NZ;
+    const int64_t base = (int64_t)m.NX * m.NY * m.NZ * (blockIdx.z / m.NZ) + (int64_t)m.NX * (row + (int64_t)m.NY * k);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m.NX; i += gridDim.x * blockDim.x) {
+        const int64_t g = base + i;
+        double v = 0.0;
+        if (!node_constrained(m, i, row, k)) v = (x ? a * x[g] : 0.0) + (y ? b * y[g] : 0.0);
+        z[g] = v;
+    }
+}
+hipError_t vmask_axpby(const KMesh &m, int comps, double a, const double *x, double b, const double *y, double *z,
+                       hipStream_t s)
+{
+    const unsigned bx = (unsigned)((m.NX + VNT - 1) / VNT);
+    mask_axpby_kernel<<<dim3(bx, m.NY, m.NZ * comps), VNT, 0, s>>>(m, a, x, b, y, z);
+    return hipGetLastError();
+}
+
+// Picard update: T = T_old + dT, with the partials of ||T_new - T||^2 and
+// ||T_new||^2 (T holds the previous iterate on entry); out[0], out[1] are
+// their totals (device).
+__global__ void __launch_bounds__(VNT) picard_update_kernel(const double *__restrict__ T_old,
+                                                            const double *__restrict__ dT, double *__restrict__ T,
+                                                            int64_t n, RedWS red)
+{
+    __shared__ double lds[2 * (VNT / 64)];
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n)
+    {
+        const double tn = T_old[i] + dT[i];
+        const double d = tn - T[i];
+        T[i] = tn;
+        acc[0] += d * d;
+        acc[1] += tn * tn;
+    }
+    grid_partials<2>(acc, red, lds);
+}
+hipError_t picard_update(const double *T_old, const double *dT, double *T, int64_t n, double *out, const RedWS *red,
+                         hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < 2 * nb) return hipErrorInvalidValue;
+    picard_update_kernel<<<nb, VNT, 0, s>>>(T_old, dT, T, n, *red);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : sum_finalize(*red, nb, 2, out, s);
+}
+
 // ---------------------------------------------------------------------------
 // Multi-dot, multi-axpy, combination (GMRES Gram-Schmidt).  The number of
 // vectors NV is a template parameter (1..32, chosen by a switch), so that

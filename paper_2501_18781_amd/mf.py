@@ -81,6 +81,11 @@ class SourcesDesc(ctypes.Structure):
                 ("laser_radius", ctypes.c_double), ("focus", ctypes.c_double * 3), ("direction", ctypes.c_double * 3)]
 
 
+class PicardInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("cg_iterations", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("update", ctypes.c_double)]
+
+
 # Every function of the C ABI, with its argument types.
 _P = ctypes.c_void_p
 _SIGS = {
@@ -112,6 +117,14 @@ _SIGS = {
     "mf_heat_coeff_grad": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, _P, _P, _P, _P]),
     "mf_heat_source_rhs": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.POINTER(SourcesDesc), _P, _P,
                                           _P]),
+    "mf_heat_step": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.POINTER(SolveInfo), _P]),
+    "mf_heat_step_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, _P, ctypes.c_double,
+                                            ctypes.c_int32, _P, _P, _P, _P, ctypes.POINTER(SolveInfo), _P]),
+    "mf_heat_picard_step": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.POINTER(SourcesDesc), _P, _P,
+                                           ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                           ctypes.POINTER(PicardInfo), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int32), _P]),
 }
 
 _lib = None
@@ -414,12 +427,7 @@ def heat_coeff_grad(op: Operator, T, dT, lam, dk=None, drc=None, dphi=None, stre
     return dk, drc, dphi
 
 
-def heat_source_rhs(op: Operator, sources, T: Optional[torch.Tensor], b: torch.Tensor, stream=None):
-    """b = right-hand side of the interface heat fluxes (evaporative cooling,
-    laser heat flux) for the level set of the heat operator op and the nodal
-    temperature T.  sources: object with terms, evap_coeff, molar_mass,
-    vapor_density, T_boil, h_v, power, absorptivity, radius, focus, dir."""
-    c = op.ctx
+def _sources_desc(sources) -> SourcesDesc:
     d = SourcesDesc()
     d.terms = int(sources.terms)
     d.evaporation_coefficient, d.molar_mass = float(sources.evap_coeff), float(sources.molar_mass)
@@ -429,8 +437,71 @@ def heat_source_rhs(op: Operator, sources, T: Optional[torch.Tensor], b: torch.T
     for k in range(3):
         d.focus[k] = float(sources.focus[k])
         d.direction[k] = float(sources.dir[k])
+    return d
+
+
+def heat_source_rhs(op: Operator, sources, T: Optional[torch.Tensor], b: torch.Tensor, stream=None):
+    """b = right-hand side of the interface heat fluxes (evaporative cooling,
+    laser heat flux) for the level set of the heat operator op and the nodal
+    temperature T.  sources: object with terms, evap_coeff, molar_mass,
+    vapor_density, T_boil, h_v, power, absorptivity, radius, focus, dir."""
+    c = op.ctx
+    d = _sources_desc(sources)
     nn = c.n_nodes
     c.check(library().mf_heat_source_rhs(c._h, ctypes.byref(op.desc), ctypes.byref(d),
                                          _ptr(T, nn, torch.float64, "T"), _ptr(b, nn, torch.float64, "b"),
                                          _stream(stream)))
     return b
+
+
+def heat_step(op: Operator, T_old: torch.Tensor, T: torch.Tensor, dT: torch.Tensor, rtol: float, maxit: int,
+              stream=None) -> SolveInfo:
+    """One backward-Euler heat step in delta form (mf_heat_step): writes T and dT = T - T_old."""
+    c = op.ctx
+    nn = c.n_nodes
+    info = SolveInfo()
+    st = library().mf_heat_step(c._h, ctypes.byref(op.desc), _ptr(T_old, nn, torch.float64, "T_old"),
+                                _ptr(T, nn, torch.float64, "T"), _ptr(dT, nn, torch.float64, "dT"), rtol, maxit,
+                                ctypes.byref(info), _stream(stream))
+    c.check(st, _SOLVER_OK)
+    info.status = st
+    return info
+
+
+def heat_step_adjoint(op: Operator, T, dT, gT, gdT, rtol: float, maxit: int, dk=None, drc=None, dphi=None,
+                      gT_old=None, stream=None) -> SolveInfo:
+    """Adjoint of heat_step (mf_heat_step_adjoint): gradients of a loss with
+    dL/dT = gT and dL/d(dT) = gdT (None: zero) with respect to k_q, rc_q, phi
+    and T_old, written into the tensors given."""
+    c = op.ctx
+    nn, nq = c.n_nodes, c.n_cells * 27
+    f64 = torch.float64
+    info = SolveInfo()
+    st = library().mf_heat_step_adjoint(c._h, ctypes.byref(op.desc), _ptr(T, nn, f64, "T"), _ptr(dT, nn, f64, "dT"),
+                                        _ptr(gT, nn, f64, "gT"), _ptr(gdT, nn, f64, "gdT"), rtol, maxit,
+                                        _ptr(dk, nq, f64, "dk"), _ptr(drc, nq, f64, "drc"),
+                                        _ptr(dphi, nn, f64, "dphi"), _ptr(gT_old, nn, f64, "gT_old"),
+                                        ctypes.byref(info), _stream(stream))
+    c.check(st, _SOLVER_OK)
+    info.status = st
+    return info
+
+
+def heat_picard_step(op: Operator, sources, T_old: torch.Tensor, T: torch.Tensor, tol: float, maxit: int,
+                     cg_rtol: float, cg_maxit: int, stream=None):
+    """Picard iteration of one implicit three-phase heat step
+    (mf_heat_picard_step); returns (PicardInfo, per-iteration updates,
+    per-iteration CG iteration counts).  sources: as heat_source_rhs, or None."""
+    c = op.ctx
+    nn = c.n_nodes
+    info = PicardInfo()
+    upd = (ctypes.c_double * maxit)()
+    its = (ctypes.c_int32 * maxit)()
+    src = ctypes.byref(_sources_desc(sources)) if sources is not None else None
+    st = library().mf_heat_picard_step(c._h, ctypes.byref(op.desc), src, _ptr(T_old, nn, torch.float64, "T_old"),
+                                       _ptr(T, nn, torch.float64, "T"), tol, maxit, cg_rtol, cg_maxit,
+                                       ctypes.byref(info), upd, its, _stream(stream))
+    c.check(st, _SOLVER_OK)
+    info.status = st
+    k = info.iterations
+    return info, list(upd[:k]), list(its[:k])

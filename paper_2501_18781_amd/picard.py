@@ -1,22 +1,19 @@
 """One implicit heat step with temperature-dependent (three-phase)
-coefficients, solved by Picard iteration over the C ABI.
+coefficients, solved by Picard iteration in the library
+(``mf_heat_picard_step``).
 
 The step is backward Euler for eq. heat_transfer with the coefficients of
-Sec. 3.2-3.3 (solid fraction from T, three-phase blends of k and rho c_p) and
+Sec. 4.1-4.3 (solid fraction from T, three-phase blends of k and rho c_p) and
 optionally the Tanasawa penalty of App. C and interface sources (Sec. 2.4,
 Sec. 4):
 
-    alpha_m M(rc(T)) (T - T_old) + K(k(T)) T + R T = b(T),
+    alpha_m M(rc(T)) (T - T_old) + K(k(T)) T + R T = b(T)   on the free rows,
 
-with R the penalty term beta delta_rcp T and b the source right-hand side.
-Picard: freeze the coefficients at T^k, solve the linear system for T^{k+1}
-in delta form,
-
-    A(T^k) dT = b(T^k) - (K(T^k) + R) T_old,   T^{k+1} = T_old + dT,
-
-with A = alpha_m M + K + R (symmetric: Jacobi-CG), until
-||T^{k+1} - T^k|| <= tol ||T^{k+1}||.  Every product, source assembly and
-solve runs in the library; this module only orders the calls.
+with R the penalty term beta delta_rcp T, b the source right-hand side and
+the Dirichlet nodes held at T_old.  Picard: freeze the coefficients at T^k,
+solve A(T^k) dT = b(T^k) - (K(T^k) + R) T_old by Jacobi-CG, set
+T^{k+1} = T_old + dT, until ||T^{k+1} - T^k|| <= tol ||T^{k+1}||.  This
+module only allocates the output and marshals the call.
 """
 from __future__ import annotations
 
@@ -41,27 +38,8 @@ def heat_step(ctx: mf.Context, params, phi: torch.Tensor, T_old: torch.Tensor, s
     """Picard iteration for one implicit three-phase heat step (module docstring).
     params: heat parameters (k_*, rc_*, T_sol, T_liq, penalty, dt, heaviside,
     eps); sources: SourceParams-like object or None (no right-hand side)."""
-    T = T_old.clone()
-    b = torch.zeros_like(T_old)
-    kr = torch.empty_like(T_old)
-    rhs = torch.empty_like(T_old)
-    dT = torch.empty_like(T_old)
-    res = PicardResult(T=T, iterations=0, converged=False)
-    for k in range(maxit):
-        op = mf.heat_operator(ctx, params, phi=phi, T_coef=T)
-        if sources is not None:
-            mf.heat_source_rhs(op, sources, T, b)
-        mf.operator_apply(op.with_alphas(alpha_m=0.0), T_old, kr)
-        torch.sub(b, kr, out=rhs)
-        info = mf.cg_solve(op, rhs, dT, cg_rtol, cg_maxit)
-        res.cg_iterations.append(info.iters)
-        Tn = T_old + dT
-        upd = float(torch.linalg.norm(Tn - T) / torch.linalg.norm(Tn))
-        res.updates.append(upd)
-        T = Tn
-        res.iterations = k + 1
-        if upd <= tol:
-            res.converged = True
-            break
-    res.T = T
-    return res
+    op = mf.heat_operator(ctx, params, phi=phi)
+    T = torch.empty_like(T_old)
+    info, updates, cg_its = mf.heat_picard_step(op, sources, T_old.contiguous(), T, tol, maxit, cg_rtol, cg_maxit)
+    return PicardResult(T=T, iterations=info.iterations, converged=bool(info.converged), updates=updates,
+                        cg_iterations=cg_its)

@@ -26,8 +26,13 @@ def dev(a, dtype=torch.float64):
 
 
 def relerr(a, b):
+    """The larger of the normwise error ||a - b|| / ||b|| and the element-wise
+    error max |a - b| / max |b|: a bar on it holds for both."""
     a = a.detach().cpu().double().numpy() if isinstance(a, torch.Tensor) else a
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    b = np.asarray(b, dtype=np.float64)
+    d = np.asarray(a, dtype=np.float64) - b
+    return float(max(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300),
+                     np.abs(d).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300)))
 
 
 MESHES = [((1, 1, 1), 0), ((3, 3, 3), W.ALL_FACES), ((5, 3, 7), W.FACE_XLO | W.FACE_ZHI),

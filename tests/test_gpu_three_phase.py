@@ -1,4 +1,5 @@
-"""GPU three-phase coefficients (Sec. 3.2-3.3), the Darcy damping of the
+"""GPU three-phase coefficients (Sec. 4.1-4.3, eqs. solid_fraction,
+heaviside_sl, solid_liquid_gas_property), the Darcy damping of the
 solid (eq. darcy_damping_force) and the Tanasawa penalty (App. C) vs the
 FP64 oracle, through the C ABI.
 
@@ -30,6 +31,18 @@ def dev(a, dtype=torch.float64):
 
 
 def relerr(a, b):
+    """The larger of the normwise error ||a - b|| / ||b|| and the element-wise
+    error max |a - b| / max |b|: a bar on it holds for both."""
+    a = a.detach().cpu().double().numpy() if isinstance(a, torch.Tensor) else a
+    b = np.asarray(b, dtype=np.float64)
+    d = np.asarray(a, dtype=np.float64) - b
+    return float(max(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300),
+                     np.abs(d).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300)))
+
+
+def normerr(a, b):
+    """Normwise ||a - b|| / ||b||: the measure of the kappa * rtol bound on the
+    solution of a solve stopped at a finite relative residual rtol."""
     a = a.detach().cpu().double().numpy() if isinstance(a, torch.Tensor) else a
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
@@ -112,18 +125,19 @@ def test_heat_three_phase_diagonal(gpu, n, dirichlet, hkind):
         assert relerr(d, O.heat_matrix(mesh, p, phi=phi, Tc=Tc, **kw).diagonal()) <= TOL64, kw
 
 
-def test_heat_three_phase_full_size_sampled_rows(gpu):
-    # 64^3 cells (2.15M nodes), the heat benchmark mesh
+def test_heat_three_phase_full_size(gpu):
+    # 64^3 cells (2.15M nodes), the heat benchmark mesh: every entry against
+    # the oracle's assembled matrix
     mesh, p, phi, Tc = heat_case((64, 64, 64), W.ALL_FACES, penalty=BETA)
     nn = mesh.n_nodes
+    print("three-phase heat apply 64^3: assembling the oracle matrix", flush=True)
+    A = O.heat_matrix(mesh, p, phi=phi, Tc=Tc)
     x = W.uniform(0, nn)
     ctx = mf.Context(mesh)
     op = mf.heat_operator(ctx, p, phi=dev(phi), T_coef=dev(Tc))
     y = torch.empty(nn, dtype=torch.float64, device="cuda")
     mf.operator_apply(op, dev(x), y)
-    rows = np.unique(np.concatenate([np.random.default_rng(9).integers(0, nn, 300), [0, nn - 1, nn // 2]]))
-    ref = O.heat_rows(mesh, p, x, rows, phi=phi, Tc=Tc)
-    assert np.abs(y.cpu().numpy()[rows] - ref).max() <= TOL64 * np.abs(ref).max()
+    assert relerr(y, O.spmv(A, x)) <= TOL64
 
 
 def test_heat_three_phase_cg_matches_direct_solve(gpu):
@@ -184,22 +198,25 @@ def test_oseen_three_phase_block_diagonal_and_gmres(gpu, n, dirichlet):
     b = A @ W.uniform(4, 3 * mesh.n_nodes)
     x = torch.empty_like(dev(b))
     info = mf.gmres_solve(op, dev(b), x, 1e-13, 2000, precond=mf.MF_PC_BLOCK_JACOBI, restart=30)
-    assert info.converged and relerr(x, O.direct_solve(A, b)) <= 1e-10
+    # the Darcy damping of the solid (C = 1e8) raises the condition number
+    assert info.converged and normerr(x, O.direct_solve(A, b)) <= 1e-10
 
 
-def test_oseen_three_phase_full_size_sampled_rows(gpu):
-    # 48^3 cells, the Oseen benchmark mesh
+def test_oseen_three_phase_full_size(gpu):
+    # 48^3 cells, the Oseen benchmark mesh: every entry of A x and A^T x
+    # against the oracle's assembled matrix
     mesh, p, phi, u0, Tc = oseen_case((48, 48, 48), W.ALL_FACES)
     nn = mesh.n_nodes
+    print("three-phase Oseen apply 48^3: assembling the oracle matrix", flush=True)
+    A = O.oseen_matrix(mesh, p, phi, u0, Tc=Tc)
     x = W.uniform(1, 3 * nn)
     ctx = mf.Context(mesh)
     op = mf.oseen_operator(ctx, p, dev(phi), dev(u0), T_coef=dev(Tc))
     y = torch.empty(3 * nn, dtype=torch.float64, device="cuda")
-    rows = np.unique(np.random.default_rng(11).integers(0, 3 * nn, 300))
-    for tr in (False, True):
-        (mf.operator_apply_transpose if tr else mf.operator_apply)(op, dev(x), y)
-        ref = O.oseen_rows(mesh, p, phi, u0, x, rows, transpose=tr, Tc=Tc)
-        assert np.abs(y.cpu().numpy()[rows] - ref).max() <= TOL64 * np.abs(ref).max()
+    mf.operator_apply(op, dev(x), y)
+    assert relerr(y, O.spmv(A, x)) <= TOL64
+    mf.operator_apply_transpose(op, dev(x), y)
+    assert relerr(y, A.T @ x) <= TOL64
 
 
 @pytest.mark.parametrize("n,dirichlet", [((3, 3, 3), W.ALL_FACES), ((9, 9, 9), 0), ((17, 10, 5), W.FACE_XHI)])
@@ -218,36 +235,28 @@ def test_penalty_right_hand_side(gpu, n, dirichlet):
     assert relerr(b, O.heat_sources(mesh, p, sp3, phi, Tc)) <= TOL64
 
 
-def oracle_picard(mesh, p, phi, T_old, sp, tol, maxit):
-    """Picard iteration of one implicit three-phase step with the oracle's
-    assembled matrices and direct solves."""
-    T = T_old.copy()
-    for k in range(maxit):
-        A = O.heat_matrix(mesh, p, phi=phi, Tc=T)
-        KR = O.heat_matrix(mesh, p, phi=phi, Tc=T, alpha_m=0.0)
-        b = O.heat_sources(mesh, p, sp, phi, T) if sp is not None else np.zeros_like(T)
-        Tn = T_old + O.direct_solve(A, b - KR @ T_old)
-        upd = np.linalg.norm(Tn - T) / np.linalg.norm(Tn)
-        T = Tn
-        if upd <= tol:
-            return T, k + 1
-    return T, maxit
-
-
-def test_picard_step_matches_oracle(gpu):
-    # insulated faces; a step of 100 s lets conduction and the penalty (which
-    # pulls the interface towards T_v) move T by ~50 K across the mushy layer,
-    # so the coefficients change between iterates (about seven Picard steps)
-    mesh, p, phi, T_old = heat_case((8, 8, 8), 0, penalty=BETA)
+@pytest.mark.parametrize("dirichlet", [0, W.ALL_FACES])
+def test_picard_step_matches_oracle(gpu, dirichlet):
+    # a step of 100 s lets conduction and the penalty (which pulls the
+    # interface towards T_v) move T by ~50 K across the mushy layer, so the
+    # coefficients change between iterates (about seven Picard steps); with
+    # Dirichlet faces the walls hold T_old (1800-2400 K), which the free rows
+    # next to them must see
+    mesh, p, phi, T_old = heat_case((8, 8, 8), dirichlet, penalty=BETA)
     p = dataclasses.replace(p, dt=1e2)
     sp = dataclasses.replace(W.SourceParams(), terms=7, radius=0.25)
-    ref, its = oracle_picard(mesh, p, phi, T_old, sp, 1e-11, 40)
-    assert 4 <= its < 40
+    print(f"Picard step, dirichlet={dirichlet}", flush=True)
+    ref = O.picard_step(mesh, p, phi, T_old, sp, tol=1e-11, maxit=40)
+    assert ref.converged and 4 <= ref.iterations < 40
     ctx = mf.Context(mesh)
     res = picard.heat_step(ctx, p, dev(phi), dev(T_old), sources=sp, tol=1e-11, maxit=40)
-    print(res.iterations, its, res.updates, res.cg_iterations, flush=True)
-    assert res.converged and abs(res.iterations - its) <= 1
-    assert relerr(res.T - dev(T_old), ref - T_old) <= 1e-9
+    print(res.iterations, ref.iterations, res.updates, res.cg_iterations, flush=True)
+    assert res.converged and abs(res.iterations - ref.iterations) <= 1
+    got = res.T.cpu().numpy()
+    d, dref = got - T_old, ref.T - T_old
+    assert np.abs(d - dref).max() <= 1e-9 * np.abs(dref).max()
+    cm = O.constrained_mask(mesh)
+    assert np.array_equal(got[cm], T_old[cm])
 
 
 def test_three_phase_argument_errors(gpu):

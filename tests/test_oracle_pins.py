@@ -729,3 +729,77 @@ def test_gradient_wrt_phi_matches_central_differences():
         s = 1e-6
         fd = (loss(wl.phi + s * v)[0] - loss(wl.phi - s * v)[0]) / (2 * s)
         assert abs(fd - dphi @ v) < 1e-6 * abs(fd)
+
+
+# ---------------------------------------------------------------------------
+# Whole steps with the Dirichlet nodes held at T_old
+# ---------------------------------------------------------------------------
+
+def test_heat_step_keeps_constants_steady_and_holds_boundary_values():
+    # A constant temperature is a steady state of the step (K annihilates
+    # constants), also where the Dirichlet nodes hold it.  Catches a missing
+    # lifting of the boundary values: free rows that see 0 at the walls cool
+    # the field next to them.
+    wl = W.heat_sphere_workload(3, W.ALL_FACES)
+    mesh, p = wl.mesh, wl.params
+    kq, rcq = O.heat_qp_coeffs(mesh, p, wl.phi)
+    n = mesh.n_nodes
+    for delta in (True, False):
+        T, _ = O.heat_step(mesh, p, np.full(n, 1234.5), kq=kq, rcq=rcq, delta=delta)
+        assert np.abs(T - 1234.5).max() <= 1e-12 * 1234.5
+    # A general field, nonzero on the walls: the delta and the plain form
+    # agree, the Dirichlet nodes keep T_old, and the free rows satisfy
+    # alpha_m M (T - T_old) + K T = 0 with every column present (a residual
+    # of the assembled equation, not of either solve).
+    cm = O.constrained_mask(mesh)
+    Told = 2000.0 + 300.0 * W.manufactured_T(mesh) + 10.0 * W.uniform(5, n)
+    T1, dT1 = O.heat_step(mesh, p, Told, kq=kq, rcq=rcq, delta=True)
+    T2, _ = O.heat_step(mesh, p, Told, kq=kq, rcq=rcq, delta=False)
+    assert np.linalg.norm(T1 - T2) <= 1e-14 * np.linalg.norm(T1)
+    assert np.array_equal(T1[cm], Told[cm]) and not dT1[cm].any()
+    m0 = O.without_dirichlet(mesh)
+    M = O.heat_matrix(m0, p, kq=kq, rcq=rcq, alpha_k=0.0)
+    K = O.heat_matrix(m0, p, kq=kq, rcq=rcq, alpha_m=0.0)
+    res = (M @ dT1 + K @ T1)[~cm]
+    assert np.abs(res).max() <= 1e-12 * np.abs(K @ T1).max()
+    # with T_old = 0 on the walls it is the homogeneous step
+    Told[cm] = 0.0
+    _, T3 = _one_step(mesh, p, kq, rcq, Told)
+    T4, _ = O.heat_step(mesh, p, Told, kq=kq, rcq=rcq, delta=False)
+    assert np.linalg.norm(T3 - T4) <= 1e-14 * np.linalg.norm(T3)
+
+
+def _three_phase_case(n=(4, 4, 4), dirichlet=W.ALL_FACES, penalty=2.0e9, dt=1e2):
+    import dataclasses
+    mesh = W.Mesh(n, dirichlet=dirichlet)
+    eps = 2.0 / max(n)
+    p = dataclasses.replace(W.HeatParams(eps=eps, penalty=penalty), dt=dt)
+    phi = W.phi_sphere(mesh, 0.35, eps, center=(0.5, 0.5, 0.3))
+    return mesh, p, phi, W.melt_temperature(mesh)
+
+
+def test_picard_step_solves_the_nonlinear_step():
+    # The converged iterate satisfies the nonlinear step itself,
+    #   alpha_m M(T) (T - T_old) + (K + R)(T) T = b(T) on the free rows,
+    # with the matrices evaluated at the final T (not at the iterate the last
+    # solve used) and the Dirichlet nodes holding T_old.  Catches a lifting
+    # that drops the boundary values, a right-hand side frozen at T_old, and
+    # a penalty or source term missing from one side.
+    import dataclasses
+    mesh, p, phi, Told = _three_phase_case()
+    sp = dataclasses.replace(W.SourceParams(), terms=7, radius=0.25)
+    r = O.picard_step(mesh, p, phi, Told, sp, tol=1e-12, maxit=60)
+    assert r.converged and r.iterations >= 3
+    cm = O.constrained_mask(mesh)
+    assert np.array_equal(r.T[cm], Told[cm])
+    m0 = O.without_dirichlet(mesh)
+    M = O.heat_matrix(m0, p, phi=phi, Tc=r.T, alpha_k=0.0, penalty=0.0)
+    KR = O.heat_matrix(m0, p, phi=phi, Tc=r.T, alpha_m=0.0)
+    b = O.heat_sources(mesh, p, sp, phi, r.T)
+    res = (M @ (r.T - Told) + KR @ r.T - b)[~cm]
+    assert np.abs(res).max() <= 1e-8 * np.abs(KR @ r.T).max()
+    # T_old at the boiling temperature everywhere, penalty as the only term:
+    # R T_v = b_penalty, so T_v is a steady state (first update exactly 0)
+    Tv = np.full(mesh.n_nodes, sp.T_boil)
+    r = O.picard_step(mesh, p, phi, Tv, dataclasses.replace(sp, terms=4), tol=1e-12, maxit=5)
+    assert r.iterations == 1 and np.abs(r.T - sp.T_boil).max() <= 1e-9 * sp.T_boil
