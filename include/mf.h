@@ -133,7 +133,8 @@ typedef struct mf_mg mf_mg;
  * meshes with 2^31 or more nodes. */
 mf_status mf_create(const mf_mesh *mesh, mf_ctx **ctx);
 void mf_destroy(mf_ctx *ctx);
-/* Last error message of the context (static string if ctx is NULL). */
+/* Last error message of the context; with ctx NULL, of the last failed call
+ * without a context on this host thread. */
 const char *mf_last_error(const mf_ctx *ctx);
 int64_t mf_n_nodes(const mf_ctx *ctx);
 int64_t mf_n_cells(const mf_ctx *ctx);
@@ -155,6 +156,22 @@ mf_status mf_timing_read(mf_ctx *ctx, double *ms, int64_t *launches, int32_t res
  * distinct buffers.  Dirichlet dofs: y_i = x_i; x is read as zero there in
  * the products of the other rows.  FP32 operators are supported for heat. */
 mf_status mf_operator_apply(mf_ctx *ctx, const mf_operator *op, const void *x, void *y, mf_stream stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x as
+ * mf_operator_apply, without a context and without any allocation.  The
+ * brick kernels' shared-face scratch lives in a fixed device array of 64 MiB
+ * per GPU (held until the process ends), enough for
+ *   n_bricks * 891 * comps * sizeof(element) bytes,
+ * n_bricks = ceil(n0/4) ceil(n1/4) ceil(n2/4), comps 1 (heat) or 3 (Oseen):
+ * e.g. heat FP64 up to 64^3 cells and beyond (64^3 needs 29.2 MB), Oseen
+ * FP64 at 48^3 (37 MB).  A larger mesh returns MF_ERR_ARG with a message.
+ * Calls on one GPU share that array and keep no state between calls;
+ * calls that overlap on one GPU (other streams or host threads) race on it.
+ * mesh: as mf_create; op, x, y: as mf_operator_apply (FP32 heat included).
+ * Errors are reported by mf_last_error(NULL) of the calling host thread. */
+mf_status mf_operator_apply_noalloc(const mf_mesh *mesh, const mf_operator *op, const void *x, void *y,
+                                    mf_stream stream);
 
 /* y = A^T x (the adjoint operator).  For the heat operator A^T = A; for the
  * Oseen operator the convective term acts on the test function. */

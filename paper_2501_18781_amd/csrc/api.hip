@@ -16,19 +16,52 @@
 
 using namespace mf;
 
-static const char *g_static_err = "no context";
+// Message of the last failed call that had no context, per host thread (a
+// fixed buffer: recording it allocates nothing).
+static thread_local char g_noctx_err[512] = "no context";
 
 mf_status fail(mf_ctx *c, mf_status st, const char *fmt, ...)
 {
-    if (c) {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
-        c->err = buf;
-    }
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c ? buf : g_noctx_err, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
     return st;
+}
+
+// Validate a mesh descriptor and fill the kernels' mesh description.
+mf_status mesh_to_kmesh(mf_ctx *c, const mf_mesh *mesh, KMesh *out, int64_t *n_nodes, int64_t *n_cells)
+{
+    if (!mesh) return fail(c, MF_ERR_ARG, "null mesh");
+    int64_t nn = 1, nc = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->n[d] < 1 || !(mesh->hi[d] > mesh->lo[d]))
+            return fail(c, MF_ERR_ARG, "mesh needs n[d] >= 1 and hi[d] > lo[d]");
+        nn *= 2 * (int64_t)mesh->n[d] + 1;
+        nc *= mesh->n[d];
+    }
+    if (3 * nn >= (int64_t)1 << 31) return fail(c, MF_ERR_ARG, "mesh too large: 3 n_nodes must stay below 2^31");
+    if (mesh->dirichlet > 63u) return fail(c, MF_ERR_ARG, "unknown Dirichlet face bits");
+    KMesh k;
+    k.nx = mesh->n[0];
+    k.ny = mesh->n[1];
+    k.nz = mesh->n[2];
+    k.NX = 2 * k.nx + 1;
+    k.NY = 2 * k.ny + 1;
+    k.NZ = 2 * k.nz + 1;
+    k.dirichlet = mesh->dirichlet;
+    k.hx = (mesh->hi[0] - mesh->lo[0]) / mesh->n[0];
+    k.hy = (mesh->hi[1] - mesh->lo[1]) / mesh->n[1];
+    k.hz = (mesh->hi[2] - mesh->lo[2]) / mesh->n[2];
+    k.lox = mesh->lo[0];
+    k.loy = mesh->lo[1];
+    k.loz = mesh->lo[2];
+    *out = k;
+    if (n_nodes) *n_nodes = nn;
+    if (n_cells) *n_cells = nc;
+    return MF_OK;
 }
 
 RedWS redws(mf_ctx *c) { return RedWS{c->partials, c->cap}; }
@@ -63,37 +96,21 @@ extern "C" {
 int64_t mf_n_nodes(const mf_ctx *c) { return c ? c->nn : 0; }
 int64_t mf_n_cells(const mf_ctx *c) { return c ? c->nc : 0; }
 
-const char *mf_last_error(const mf_ctx *c) { return c ? c->err.c_str() : g_static_err; }
+const char *mf_last_error(const mf_ctx *c) { return c ? c->err.c_str() : g_noctx_err; }
 
 mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
 {
     if (!mesh || !out) return MF_ERR_ARG;
     *out = nullptr;
-    int64_t nn = 1, nc = 1;
-    for (int d = 0; d < 3; ++d) {
-        if (mesh->n[d] < 1 || !(mesh->hi[d] > mesh->lo[d])) return MF_ERR_ARG;
-        nn *= 2 * (int64_t)mesh->n[d] + 1;
-        nc *= mesh->n[d];
-    }
-    if (3 * nn >= (int64_t)1 << 31 || mesh->dirichlet > 63u) return MF_ERR_ARG;
+    KMesh km;
+    int64_t nn, nc;
+    if (mesh_to_kmesh(nullptr, mesh, &km, &nn, &nc)) return MF_ERR_ARG;
     mf_ctx *c = new mf_ctx();
     c->mesh = *mesh;
     c->nn = nn;
     c->nc = nc;
-    KMesh &k = c->km;
-    k.nx = mesh->n[0];
-    k.ny = mesh->n[1];
-    k.nz = mesh->n[2];
-    k.NX = 2 * k.nx + 1;
-    k.NY = 2 * k.ny + 1;
-    k.NZ = 2 * k.nz + 1;
-    k.dirichlet = mesh->dirichlet;
-    k.hx = (mesh->hi[0] - mesh->lo[0]) / mesh->n[0];
-    k.hy = (mesh->hi[1] - mesh->lo[1]) / mesh->n[1];
-    k.hz = (mesh->hi[2] - mesh->lo[2]) / mesh->n[2];
-    k.lox = mesh->lo[0];
-    k.loy = mesh->lo[1];
-    k.loz = mesh->lo[2];
+    c->km = km;
+    const KMesh &k = c->km;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return MF_ERR_HIP;
@@ -166,6 +183,11 @@ mf_status mf_timing_read(mf_ctx *c, double *ms, int64_t *launches, int32_t reset
 mf_status check_op(mf_ctx *c, const mf_operator *op)
 {
     if (!c) return MF_ERR_ARG;
+    return check_op_desc(c, op);
+}
+
+mf_status check_op_desc(mf_ctx *c, const mf_operator *op)
+{
     if (!op) return fail(c, MF_ERR_ARG, "null operator");
     if (op->kind != MF_HEAT && op->kind != MF_OSEEN) return fail(c, MF_ERR_ARG, "unknown operator kind %d", op->kind);
     if (op->precision != MF_FP64 && op->precision != MF_FP32)

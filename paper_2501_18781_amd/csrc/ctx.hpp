@@ -49,6 +49,11 @@ mf_status ensure_face(mf_ctx *c, int comps);
 // Workspace vector i of the context (3 * n_nodes doubles), allocated on first use.
 mf_status ws_vec(mf_ctx *c, int i, double **out);
 mf_status check_op(mf_ctx *c, const mf_operator *op);
+// The descriptor checks of check_op; c may be null (messages then go to the
+// calling thread's context-free error buffer, read by mf_last_error(NULL)).
+mf_status check_op_desc(mf_ctx *c, const mf_operator *op);
+// Validate a mesh descriptor and fill the kernels' mesh description (c may be null).
+mf_status mesh_to_kmesh(mf_ctx *c, const mf_mesh *mesh, mf::KMesh *out, int64_t *n_nodes, int64_t *n_cells);
 mf::HeatArgs heat_args(const mf_operator *op);
 mf::OseenArgs oseen_args(const mf_operator *op);
 int64_t ndofs(const mf_ctx *c, const mf_operator *op);

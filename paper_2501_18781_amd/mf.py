@@ -99,6 +99,7 @@ _SIGS = {
                                       ctypes.c_int32]),
     "mf_operator_apply": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
     "mf_operator_apply_transpose": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P]),
+    "mf_operator_apply_noalloc": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(OperatorDesc), _P, _P, _P]),
     "mf_operator_diagonal": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P]),
     "mf_cg_solve": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.c_int32, _P, _P, ctypes.c_double,
                                    ctypes.c_int32, ctypes.POINTER(SolveInfo), _P]),
@@ -171,12 +172,7 @@ class Context:
 
     def __init__(self, mesh):
         L = library()
-        d = MeshDesc()
-        for k in range(3):
-            d.n[k] = int(mesh.n[k])
-            d.lo[k] = float(getattr(mesh, "lo", (0, 0, 0))[k])
-            d.hi[k] = float(getattr(mesh, "hi", (1, 1, 1))[k])
-        d.dirichlet = int(getattr(mesh, "dirichlet", 0))
+        d = mesh_desc(mesh)
         h = _P()
         st = L.mf_create(ctypes.byref(d), ctypes.byref(h))
         if st != MF_OK:
@@ -293,6 +289,28 @@ def operator_apply(op: Operator, x: torch.Tensor, y: torch.Tensor, stream=None):
     c = op.ctx
     c.check(library().mf_operator_apply(c._h, ctypes.byref(op.desc), _ptr(x, op.n_dofs, op.dtype, "x"),
                                         _ptr(y, op.n_dofs, op.dtype, "y"), _stream(stream)))
+    return y
+
+
+def mesh_desc(mesh) -> MeshDesc:
+    d = MeshDesc()
+    for k in range(3):
+        d.n[k] = int(mesh.n[k])
+        d.lo[k] = float(getattr(mesh, "lo", (0, 0, 0))[k])
+        d.hi[k] = float(getattr(mesh, "hi", (1, 1, 1))[k])
+    d.dirichlet = int(getattr(mesh, "dirichlet", 0))
+    return d
+
+
+def operator_apply_noalloc(op: Operator, x: torch.Tensor, y: torch.Tensor, stream=None):
+    """y = A x through mf_operator_apply_noalloc (no context, no allocation);
+    the mesh is the one of the operator's context."""
+    d = mesh_desc(op.ctx.mesh)
+    st = library().mf_operator_apply_noalloc(ctypes.byref(d), ctypes.byref(op.desc),
+                                             _ptr(x, op.n_dofs, op.dtype, "x"), _ptr(y, op.n_dofs, op.dtype, "y"),
+                                             _stream(stream))
+    if st != MF_OK:
+        raise MFError(st, library().mf_last_error(None).decode())
     return y
 
 
