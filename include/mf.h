@@ -284,6 +284,40 @@ typedef struct {
 mf_status mf_heat_source_rhs(mf_ctx *ctx, const mf_operator *op, const mf_heat_sources *src, const double *T,
                              double *b, mf_stream stream);
 
+/* ---- level-set transport velocity (Sec. 2.5, App. A) ------------------------- */
+
+enum { MF_TRANSPORT_LOCAL = 1, MF_TRANSPORT_LIQUID_EXTENSION = 2 };
+
+typedef struct {
+    int32_t variant;                /* MF_TRANSPORT_LOCAL or MF_TRANSPORT_LIQUID_EXTENSION */
+    int32_t heaviside;              /* H of rho(phi) (local variant); the extension needs MF_H_SINE */
+    double eps;                     /* interface thickness parameter, > 0 */
+    double rho_l, rho_g;            /* densities, liquid / gas */
+    double evaporation_coefficient; /* Tanasawa model (eq. mDotTanasawa), as in mf_heat_sources */
+    double molar_mass;
+    double vapor_density;
+    double boiling_temperature;
+    double latent_heat;
+} mf_transport_params;
+
+/* Level-set transport velocity at every node of the nodal level set:
+ *   MF_TRANSPORT_LOCAL (eq. transport_vel_local_continuous):
+ *       u_G = u + mdot(T) / rho(phi) n,        rho by eq. rhoEff;
+ *   MF_TRANSPORT_LIQUID_EXTENSION (eq. transport_vel_extension_liquid):
+ *       u_G = u(x_l) + mdot(T(x_G)) / rho_l n,
+ * with mdot = alpha_v (T - T_v) (eq. mDotTanasawa), the recovered signed
+ * distance d = 2 eps artanh(phi) (phi clamped to +-(1 - 1e-15)), the unit
+ * normal n = grad d / |grad d| pointing into the liquid (phi > 0; n = 0 where
+ * |grad d| <= 1e-8, e.g. at a sphere's centre), grad d the gradient of the Q2 interpolant of the
+ * nodal d averaged over the cells that contain the node, the projections
+ * x_G = x - d n onto phi = 0 and x_l = x + (3 eps - d) n onto d = 3 eps (where
+ * the sine Heaviside reaches 1), and u(x_l), T(x_G) the values of the Q2
+ * interpolants at those points, each moved to the nearest point of the box.
+ * phi, T: n_nodes doubles; u, u_gamma: [3][n_nodes] doubles (u_gamma != u).
+ * Uses one workspace vector of the context. */
+mf_status mf_transport_velocity(mf_ctx *ctx, const mf_transport_params *params, const double *phi, const double *u,
+                                const double *T, double *u_gamma, mf_stream stream);
+
 /* Gradient of a loss L(T) through one implicit heat step
  * A(k, rc) T = alpha_m M(rc) T_old, given the adjoint state lambda
  * (A^T lambda = dL/dT with zeros on Dirichlet nodes):

@@ -986,3 +986,138 @@ void orc_heat_sources(const orc_mesh *m, const orc_coeffs *cf, const orc_sources
     for (int64_t i = 0; i < nn; ++i)
         if (node_constrained(m, i)) b[i] = 0.0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Level-set transport velocity (Sec. 2.5, App. A)                           */
+/* ------------------------------------------------------------------------ */
+
+/* Signed distance recovered from the tanh profile of eq. initial_phi,
+ * phi = tanh(d / (2 eps)):  d = 2 eps artanh(phi), phi clamped to
+ * +-(1 - 1e-15) (the same reading as the sine Heaviside). */
+static double distance_from_phi(double eps, double phi)
+{
+    const double lim = 1.0 - 1e-15;
+    const double p = phi < -lim ? -lim : (phi > lim ? lim : phi);
+    return eps * log((1.0 + p) / (1.0 - p));
+}
+
+/* Gradient of the Q2 interpolant of the nodal field f at every node,
+ * averaged over the cells that contain the node: for each cell, the physical
+ * basis gradients (general trilinear map) are evaluated at the reference
+ * position (a/2, b/2, c/2) of each of its 27 nodes.  g: component-major [3][n]. */
+void orc_nodal_gradient(const orc_mesh *m, const double *f, double *g)
+{
+    const int64_t nn = nnodes(m);
+    int *cnt = (int *)calloc((size_t)nn, sizeof(int));
+    memset(g, 0, sizeof(double) * 3 * nn);
+    for (int cz = 0; cz < m->n[2]; ++cz)
+        for (int cy = 0; cy < m->n[1]; ++cy)
+            for (int cx = 0; cx < m->n[0]; ++cx) {
+                double X[8][3];
+                int64_t idx[27];
+                cell_vertices(m, cx, cy, cz, X);
+                cell_nodes(m, cx, cy, cz, idx);
+                for (int i = 0; i < 27; ++i) {
+                    const double xi[3] = {NODE1D[i % 3], NODE1D[(i / 3) % 3], NODE1D[i / 9]};
+                    qp_data P;
+                    eval_point(X, xi, &P, 1.0);
+                    for (int d = 0; d < 3; ++d) {
+                        double s = 0.0;
+                        for (int j = 0; j < 27; ++j) s += P.G[j][d] * f[idx[j]];
+                        g[d * nn + idx[i]] += s;
+                    }
+                    cnt[idx[i]] += 1;
+                }
+            }
+    for (int64_t i = 0; i < nn; ++i)
+        for (int d = 0; d < 3; ++d) g[d * nn + i] /= cnt[i];
+    free(cnt);
+}
+
+/* Value at the physical point x of the Q2 interpolant of the nodal field f:
+ * x is first moved to the nearest point of the box, then located in its
+ * cell (the uniform mesh's affine map inverted), and the 27 basis functions
+ * are evaluated there explicitly. */
+static double point_value(const orc_mesh *m, const double *f, const double x[3])
+{
+    int c[3];
+    double xi[3];
+    for (int d = 0; d < 3; ++d) {
+        const double h = (m->hi[d] - m->lo[d]) / m->n[d];
+        double p = x[d] < m->lo[d] ? m->lo[d] : (x[d] > m->hi[d] ? m->hi[d] : x[d]);
+        int k = (int)floor((p - m->lo[d]) / h);
+        if (k < 0) k = 0;
+        if (k > m->n[d] - 1) k = m->n[d] - 1;
+        c[d] = k;
+        xi[d] = (p - (m->lo[d] + h * k)) / h;
+    }
+    int64_t idx[27];
+    cell_nodes(m, c[0], c[1], c[2], idx);
+    double v = 0.0;
+    for (int i = 0; i < 27; ++i)
+        v += f[idx[i]] * lag1(i % 3, xi[0]) * lag1((i / 3) % 3, xi[1]) * lag1(i / 9, xi[2]);
+    return v;
+}
+
+void orc_point_values(const orc_mesh *m, const double *f, int64_t np, const double *x, double *out)
+{
+    for (int64_t p = 0; p < np; ++p) out[p] = point_value(m, f, x + 3 * p);
+}
+
+/* Level-set transport velocity at every node (u, u_gamma component-major):
+ *   n      = grad d / |grad d| (0 where |grad d| <= 1e-8: no normal), with
+ *            d_j = d(phi_j) the recovered signed distance: the unit normal
+ *            pointing into the liquid (phi > 0);
+ *   mdot   = alpha_v (T - T_v)                                 (eq. mDotTanasawa)
+ *   variant 1 (eq. transport_vel_local_continuous):
+ *            u_gamma = u_j + mdot(T_j) / rho(phi_j) n_j, rho by eq. rhoEff;
+ *   variant 2 (eq. transport_vel_extension_liquid):
+ *            x_G = x_j - d_j n_j          (projection along n to phi = 0),
+ *            x_l = x_j + (3 eps - d_j) n_j (to the contour d = 3 eps, H = 1),
+ *            u_gamma = u(x_l) + mdot(T(x_G)) / rho_l n_j,
+ *            u(x_l), T(x_G) values of the Q2 interpolants.
+ * Optional outputs (component-major [3][n]): nrm, xg, xl (variant 2). */
+void orc_transport_velocity(const orc_mesh *m, const orc_coeffs *cf, const orc_sources *src, int32_t variant,
+                            const double *phi, const double *u, const double *T, double *ug, double *nrm,
+                            double *xg, double *xl)
+{
+    const int64_t nn = nnodes(m);
+    const double gam = src->evap_coeff;
+    const double alpha_v = 2.0 * gam / (2.0 - gam) * src->h_v / sqrt(2.0 * M_PI * 8.314 / src->molar_mass) *
+                           src->vapor_density / pow(src->T_boil, 1.5);
+    double *d = (double *)calloc((size_t)nn, sizeof(double));
+    double *g = (double *)calloc((size_t)(3 * nn), sizeof(double));
+    for (int64_t i = 0; i < nn; ++i) d[i] = distance_from_phi(cf->eps, phi[i]);
+    orc_nodal_gradient(m, d, g);
+    const int NX = 2 * m->n[0] + 1, NY = 2 * m->n[1] + 1;
+    for (int64_t i = 0; i < nn; ++i) {
+        const int ijk[3] = {(int)(i % NX), (int)((i / NX) % NY), (int)(i / ((int64_t)NX * NY))};
+        double x[3], n[3];
+        for (int k = 0; k < 3; ++k) x[k] = m->lo[k] + ijk[k] * 0.5 * (m->hi[k] - m->lo[k]) / m->n[k];
+        const double gn = sqrt(g[i] * g[i] + g[nn + i] * g[nn + i] + g[2 * nn + i] * g[2 * nn + i]);
+        /* |grad d| is 1 for a signed distance; where it is (numerically) zero,
+         * at a point of symmetry or where phi saturates, there is no normal */
+        for (int k = 0; k < 3; ++k) n[k] = gn > 1e-8 ? g[k * nn + i] / gn : 0.0;
+        if (nrm)
+            for (int k = 0; k < 3; ++k) nrm[k * nn + i] = n[k];
+        if (variant == 1) {
+            double dH;
+            const double H = heaviside(cf->heaviside, cf->eps, phi[i], &dH);
+            const double mdot = alpha_v * (T[i] - src->T_boil);
+            const double rho = blend_recip(H, cf->rho_l, cf->rho_g);
+            for (int k = 0; k < 3; ++k) ug[k * nn + i] = u[k * nn + i] + mdot / rho * n[k];
+        } else {
+            double pg[3], pl[3];
+            for (int k = 0; k < 3; ++k) {
+                pg[k] = x[k] - d[i] * n[k];
+                pl[k] = x[k] + (3.0 * cf->eps - d[i]) * n[k];
+                if (xg) xg[k * nn + i] = pg[k];
+                if (xl) xl[k * nn + i] = pl[k];
+            }
+            const double mdot = alpha_v * (point_value(m, T, pg) - src->T_boil);
+            for (int k = 0; k < 3; ++k) ug[k * nn + i] = point_value(m, u + k * nn, pl) + mdot / cf->rho_l * n[k];
+        }
+    }
+    free(d);
+    free(g);
+}

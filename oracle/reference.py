@@ -63,7 +63,8 @@ def lib():
                      "orc_heat_cell_matrix", "orc_oseen_cell_matrix", "orc_csr_cols",
                      "orc_assemble_heat", "orc_assemble_oseen", "orc_spmv", "orc_heat_rows",
                      "orc_oseen_rows", "orc_quad_points", "orc_heat_qp_coeffs", "orc_heat_grad",
-                     "orc_load_vector", "orc_heat_sources"]:
+                     "orc_load_vector", "orc_heat_sources", "orc_nodal_gradient", "orc_point_values",
+                     "orc_transport_velocity"]:
             getattr(L, name).restype = None
         L.orc_basis1d.argtypes = [D, P, P]
         L.orc_heaviside.argtypes = [ctypes.c_int32, D, P, P, P, I64]
@@ -751,3 +752,52 @@ def picard_step(mesh, params, phi, T_old, sources=None, tol=1e-11, maxit=40) -> 
         if upd <= tol:
             return PicardResult(T, k + 1, True, updates)
     return PicardResult(T, maxit, False, updates)
+
+
+# ---------------------------------------------------------------------------
+# Level-set transport velocity (Sec. 2.5, App. A)
+# ---------------------------------------------------------------------------
+
+def nodal_gradient(mesh, f) -> np.ndarray:
+    """Gradient of the Q2 interpolant of nodal f at every node, averaged over
+    the cells containing the node; shape (3, n_nodes)."""
+    m = omesh(mesh)
+    g = np.zeros(3 * n_nodes(mesh))
+    lib().orc_nodal_gradient(ctypes.byref(m), _p(_f64(f)), _p(g))
+    return g.reshape(3, -1)
+
+
+def point_values(mesh, f, x) -> np.ndarray:
+    """Values of the Q2 interpolant of nodal f at points x (shape (np, 3)),
+    each moved to the nearest point of the box first."""
+    m = omesh(mesh)
+    x = _f64(np.asarray(x).reshape(-1, 3))
+    out = np.zeros(x.shape[0])
+    lib().orc_point_values(ctypes.byref(m), _p(_f64(f)), ctypes.c_int64(x.shape[0]), _p(x), _p(out))
+    return out
+
+
+@dataclass
+class TransportVelocity:
+    u_gamma: np.ndarray         # (3, n_nodes)
+    normal: np.ndarray          # (3, n_nodes), into the liquid
+    x_gamma: Optional[np.ndarray] = None   # (3, n_nodes), variant 2
+    x_liquid: Optional[np.ndarray] = None  # (3, n_nodes), variant 2
+
+
+def transport_velocity(mesh, params, sources, variant, phi, u, T, **override) -> TransportVelocity:
+    """Level-set transport velocity at every node: variant 1 (eq.
+    transport_vel_local_continuous) or 2 (eq. transport_vel_extension_liquid),
+    the Tanasawa mass flux of ``sources`` (eq. mDotTanasawa); params carries
+    heaviside, eps, rho_l, rho_g.  u: nodal velocity [3][n_nodes]."""
+    m = omesh(mesh)
+    c = ocoeffs(params, **override)
+    s = osources(sources)
+    nn = n_nodes(mesh)
+    ug, nrm = np.zeros(3 * nn), np.zeros(3 * nn)
+    xg = np.zeros(3 * nn) if variant == 2 else None
+    xl = np.zeros(3 * nn) if variant == 2 else None
+    lib().orc_transport_velocity(ctypes.byref(m), ctypes.byref(c), ctypes.byref(s), ctypes.c_int32(variant),
+                                 _p(_f64(phi)), _p(_f64(u)), _p(_f64(T)), _p(ug), _p(nrm), _p(xg), _p(xl))
+    sh = lambda a: None if a is None else a.reshape(3, nn)
+    return TransportVelocity(sh(ug), sh(nrm), sh(xg), sh(xl))

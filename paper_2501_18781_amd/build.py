@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmf.so")
-SOURCES = ["api.hip", "heat.hip", "oseen.hip", "vec.hip", "mg.hip", "sources.hip", "steps.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "heat.hip", "oseen.hip", "vec.hip", "mg.hip", "sources.hip", "steps.hip", "noalloc.hip", "transport.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

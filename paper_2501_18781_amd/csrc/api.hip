@@ -321,7 +321,8 @@ mf_status source_args(mf_ctx *c, const mf_operator *op, const mf_heat_sources *s
         if (!T) return fail(c, MF_ERR_ARG, "evaporative cooling needs the temperature");
         if (!(gam > 0.0 && gam <= 1.0) || !(src->molar_mass > 0.0) || !(src->boiling_temperature > 0.0))
             return fail(c, MF_ERR_ARG, "invalid evaporation parameters");
-        sa.alpha_v = tanasawa_coefficient(src);
+        sa.alpha_v = tanasawa_coefficient(gam, src->molar_mass, src->vapor_density, src->boiling_temperature,
+                                          src->latent_heat);
         sa.T_boil = src->boiling_temperature;
         sa.h_v = src->latent_heat;
     }
@@ -344,12 +345,10 @@ mf_status source_args(mf_ctx *c, const mf_operator *op, const mf_heat_sources *s
 
 // Tanasawa: alpha_v = 2 gamma/(2 - gamma) h_v / sqrt(2 pi R_s) rho_v / T_v^{3/2}, R_s = R/M
 // (eq. mDotTanasawa, mdot = alpha_v (T - T_v)).
-double tanasawa_coefficient(const mf_heat_sources *src)
+double tanasawa_coefficient(double gamma, double molar_mass, double vapor_density, double T_v, double h_v)
 {
-    const double gam = src->evaporation_coefficient;
-    const double Rs = 8.314 / src->molar_mass;
-    return 2.0 * gam / (2.0 - gam) * src->latent_heat / sqrt(2.0 * M_PI * Rs) * src->vapor_density /
-           (src->boiling_temperature * sqrt(src->boiling_temperature));
+    const double Rs = 8.314 / molar_mass;
+    return 2.0 * gamma / (2.0 - gamma) * h_v / sqrt(2.0 * M_PI * Rs) * vapor_density / (T_v * sqrt(T_v));
 }
 
 extern "C" {
@@ -421,6 +420,38 @@ mf_status mf_heat_source_rhs(mf_ctx *c, const mf_operator *op, const mf_heat_sou
     HeatArgs ha = heat_args(op);
     ha.conv = 0;
     HIPCHK(c, heat_sources(c->km, ha, sa, T ? T : (const double *)op->phi, b, c->face, (hipStream_t)stream));
+    return MF_OK;
+}
+
+mf_status mf_transport_velocity(mf_ctx *c, const mf_transport_params *p, const double *phi, const double *u,
+                                const double *T, double *u_gamma, mf_stream stream)
+{
+    if (!c) return MF_ERR_ARG;
+    if (!p || !phi || !u || !T || !u_gamma) return fail(c, MF_ERR_ARG, "null argument");
+    if (u_gamma == u) return fail(c, MF_ERR_ARG, "u_gamma must not alias u");
+    if (p->variant != MF_TRANSPORT_LOCAL && p->variant != MF_TRANSPORT_LIQUID_EXTENSION)
+        return fail(c, MF_ERR_ARG, "unknown transport-velocity variant %d", p->variant);
+    if (p->heaviside != MF_H_LINEAR && p->heaviside != MF_H_SINE)
+        return fail(c, MF_ERR_ARG, "unknown Heaviside form %d", p->heaviside);
+    if (p->variant == MF_TRANSPORT_LIQUID_EXTENSION && p->heaviside != MF_H_SINE)
+        return fail(c, MF_ERR_ARG, "the liquid-extension variant needs the sine Heaviside (H = 1 at d = 3 eps)");
+    if (!(p->eps > 0.0)) return fail(c, MF_ERR_ARG, "eps must be positive");
+    if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0)) return fail(c, MF_ERR_ARG, "densities must be positive");
+    const double gam = p->evaporation_coefficient;
+    if (!(gam > 0.0 && gam <= 1.0) || !(p->molar_mass > 0.0) || !(p->boiling_temperature > 0.0))
+        return fail(c, MF_ERR_ARG, "invalid evaporation parameters");
+    TransportArgs a;
+    a.variant = p->variant;
+    a.hkind = p->heaviside;
+    a.eps = p->eps;
+    a.rho_l = p->rho_l;
+    a.rho_g = p->rho_g;
+    a.alpha_v = tanasawa_coefficient(gam, p->molar_mass, p->vapor_density, p->boiling_temperature, p->latent_heat);
+    a.T_boil = p->boiling_temperature;
+    double *dwork;
+    mf_status st = ws_vec(c, 6, &dwork);
+    if (st) return st;
+    HIPCHK(c, transport_velocity(c->km, a, phi, u, T, u_gamma, dwork, (hipStream_t)stream));
     return MF_OK;
 }
 

@@ -72,5 +72,7 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
 // Kernel arguments of the interface heat sources of mf_heat_source_rhs.
 mf_status source_args(mf_ctx *c, const mf_operator *op, const mf_heat_sources *src, const double *T,
                       mf::SourceArgs *out);
-// Tanasawa coefficient alpha_v of mdot = alpha_v (T - T_v) from the evaporation parameters.
-double tanasawa_coefficient(const mf_heat_sources *src);
+// Tanasawa coefficient alpha_v of mdot = alpha_v (T - T_v) (eq. mDotTanasawa)
+// from the evaporation coefficient, molar mass, vapor density, boiling
+// temperature and latent heat.
+double tanasawa_coefficient(double gamma, double molar_mass, double vapor_density, double T_v, double h_v);

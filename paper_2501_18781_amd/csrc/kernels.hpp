@@ -36,6 +36,16 @@ struct SourceArgs {
     double c_rcp;              // 3 / (rc_g^2 + rc_l rc_g + rc_l^2)
 };
 
+// Level-set transport velocity (transport.hip).
+struct TransportArgs {
+    int variant;     // 1: local (eq. transport_vel_local_continuous), 2: liquid extension
+    int hkind;       // Heaviside form of rho(phi) in variant 1
+    double eps;      // interface thickness parameter: d = 2 eps artanh(phi), H = 1 at d = 3 eps
+    double rho_l, rho_g;
+    double alpha_v;  // Tanasawa coefficient: mdot = alpha_v (T - T_v)
+    double T_boil;
+};
+
 // Coefficients of the Oseen operator.
 struct OseenArgs {
     int hkind;
@@ -94,6 +104,12 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
 // level-set mode, FP64; 0 on Dirichlet nodes.
 hipError_t heat_sources(const KMesh &m, const HeatArgs &a, const SourceArgs &sa, const double *T, double *b,
                         void *face, hipStream_t s);
+
+// ---- level-set transport velocity (transport.hip) ----
+// ug ([3][n_nodes]) from phi, u ([3][n_nodes]) and T; dwork: n_nodes doubles
+// of workspace (the recovered signed distance).
+hipError_t transport_velocity(const KMesh &m, const TransportArgs &a, const double *phi, const double *u,
+                              const double *T, double *ug, double *dwork, hipStream_t s);
 
 // ---- Oseen (oseen.hip) ----
 // y = A x or A^T x; `face` holds 3 face_buffer_elems(m) doubles.

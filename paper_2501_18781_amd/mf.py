@@ -86,6 +86,17 @@ class PicardInfo(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("update", ctypes.c_double)]
 
 
+MF_TRANSPORT_LOCAL, MF_TRANSPORT_LIQUID_EXTENSION = 1, 2
+
+
+class TransportDesc(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("heaviside", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
+                ("evaporation_coefficient", ctypes.c_double), ("molar_mass", ctypes.c_double),
+                ("vapor_density", ctypes.c_double), ("boiling_temperature", ctypes.c_double),
+                ("latent_heat", ctypes.c_double)]
+
+
 # Every function of the C ABI, with its argument types.
 _P = ctypes.c_void_p
 _SIGS = {
@@ -118,6 +129,7 @@ _SIGS = {
     "mf_heat_coeff_grad": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, _P, _P, _P, _P]),
     "mf_heat_source_rhs": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), ctypes.POINTER(SourcesDesc), _P, _P,
                                           _P]),
+    "mf_transport_velocity": (ctypes.c_int, [_P, ctypes.POINTER(TransportDesc), _P, _P, _P, _P, _P]),
     "mf_heat_step": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, ctypes.c_double, ctypes.c_int32,
                                     ctypes.POINTER(SolveInfo), _P]),
     "mf_heat_step_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(OperatorDesc), _P, _P, _P, _P, ctypes.c_double,
@@ -523,3 +535,21 @@ def heat_picard_step(op: Operator, sources, T_old: torch.Tensor, T: torch.Tensor
     info.status = st
     k = info.iterations
     return info, list(upd[:k]), list(its[:k])
+
+
+def transport_velocity(ctx: Context, variant: int, params, sources, phi, u, T, u_gamma, stream=None):
+    """Level-set transport velocity (mf_transport_velocity): params carries
+    heaviside, eps, rho_l, rho_g; sources the Tanasawa data (evap_coeff,
+    molar_mass, vapor_density, T_boil, h_v)."""
+    d = TransportDesc()
+    d.variant, d.heaviside, d.eps = int(variant), int(params.heaviside), float(params.eps)
+    d.rho_l, d.rho_g = float(params.rho_l), float(params.rho_g)
+    d.evaporation_coefficient, d.molar_mass = float(sources.evap_coeff), float(sources.molar_mass)
+    d.vapor_density, d.boiling_temperature = float(sources.vapor_density), float(sources.T_boil)
+    d.latent_heat = float(sources.h_v)
+    nn = ctx.n_nodes
+    f64 = torch.float64
+    ctx.check(library().mf_transport_velocity(ctx._h, ctypes.byref(d), _ptr(phi, nn, f64, "phi"),
+                                              _ptr(u, 3 * nn, f64, "u"), _ptr(T, nn, f64, "T"),
+                                              _ptr(u_gamma, 3 * nn, f64, "u_gamma"), _stream(stream)))
+    return u_gamma

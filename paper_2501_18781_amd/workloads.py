@@ -279,3 +279,29 @@ def oseen_wavy_workload(n: int, dirichlet: int = ALL_FACES, params: OseenParams 
     eps = 2.0 / n
     return OseenWorkload(mesh, params or OseenParams(), phi_wavy_plane(mesh, 0.5, 0.05, eps),
                          taylor_green(mesh), eps)
+
+
+@dataclass
+class TransportWorkload:
+    mesh: Mesh
+    params: OseenParams
+    sources: SourceParams
+    phi: np.ndarray
+    u: np.ndarray
+    T: np.ndarray
+    eps: float
+
+
+def transport_workload(n: int, params: OseenParams | None = None,
+                       sources: SourceParams | None = None) -> TransportWorkload:
+    """Level-set transport velocity: the liquid sphere of radius 0.3 at the
+    center (eps = 2h) with the sine Heaviside, the densities of OseenParams,
+    the Taylor-Green velocity and a temperature around the boiling point of
+    SourceParams, T = T_v + 300 K (z - 1/2) + 100 K cos(2 pi x) cos(2 pi y)."""
+    mesh = Mesh((n, n, n))
+    eps = 2.0 / n
+    p = params or OseenParams(heaviside=1, eps=eps)
+    sp = sources or SourceParams()
+    x = node_coords(mesh)
+    T = sp.T_boil + 300.0 * (x[:, 2] - 0.5) + 100.0 * np.cos(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+    return TransportWorkload(mesh, p, sp, phi_sphere(mesh, 0.3, eps), taylor_green(mesh), T, eps)

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     pairs = [("mf_mesh", mf.MeshDesc), ("mf_operator", mf.OperatorDesc), ("mf_solve_info", mf.SolveInfo),
-             ("mf_mg_params", mf.MGParams), ("mf_heat_sources", mf.SourcesDesc), ("mf_picard_info", mf.PicardInfo)]
+             ("mf_mg_params", mf.MGParams), ("mf_heat_sources", mf.SourcesDesc), ("mf_picard_info", mf.PicardInfo), ("mf_transport_params", mf.TransportDesc)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mf.h"', "int main(void) {"]
     expect = []
     for cname, py in pairs:

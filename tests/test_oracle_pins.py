@@ -803,3 +803,134 @@ def test_picard_step_solves_the_nonlinear_step():
     Tv = np.full(mesh.n_nodes, sp.T_boil)
     r = O.picard_step(mesh, p, phi, Tv, dataclasses.replace(sp, terms=4), tol=1e-12, maxit=5)
     assert r.iterations == 1 and np.abs(r.T - sp.T_boil).max() <= 1e-9 * sp.T_boil
+
+
+# ---------------------------------------------------------------------------
+# Level-set transport velocity (Sec. 2.5, App. A)
+# ---------------------------------------------------------------------------
+
+def test_nodal_gradient_is_exact_for_q2_polynomials():
+    # a field of degree <= 2 per direction is its own Q2 interpolant, so the
+    # gradient at every node (every cell's one, and their average) is exact;
+    # an off-diagonal product catches swapped directions and a wrong node order
+    mesh = W.Mesh((3, 2, 4), lo=(-0.5, 0.0, 1.0), hi=(1.0, 0.5, 2.0))
+    x, y, z = W.node_coords(mesh).T
+    f = x * x * y - 3.0 * x * z + y * y * z * z + 2.0 * z
+    g = O.nodal_gradient(mesh, f)
+    ref = np.stack([2 * x * y - 3 * z, x * x + 2 * y * z * z, -3 * x + 2 * y * y * z + 2.0])
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_point_values_reproduce_q2_polynomials_and_clamp_to_the_box():
+    mesh = W.Mesh((3, 2, 4), lo=(-0.5, 0.0, 1.0), hi=(1.0, 0.5, 2.0))
+    x, y, z = W.node_coords(mesh).T
+    fun = lambda x, y, z: x * x * y * z - 2.0 * y * z * z + x + 0.5
+    pts = np.random.default_rng(3).uniform((-0.5, 0.0, 1.0), (1.0, 0.5, 2.0), (200, 3))
+    pts = np.vstack([pts, [[-0.5, 0.0, 1.0], [1.0, 0.5, 2.0], [0.0, 0.25, 1.5]]])  # corners, cell faces
+    v = O.point_values(mesh, fun(x, y, z), pts)
+    assert np.abs(v - fun(*pts.T)).max() <= 1e-12
+    # outside the box: the nearest point of the box
+    out = np.array([[-1.0, 0.2, 1.5], [0.3, 0.9, 2.5], [2.0, -1.0, 0.0]])
+    inside = np.clip(out, (-0.5, 0.0, 1.0), (1.0, 0.5, 2.0))
+    assert np.abs(O.point_values(mesh, fun(x, y, z), out) - fun(*inside.T)).max() <= 1e-12
+
+
+def _plane_case(a=(0.3, -0.2, -1.0), z0=0.55, eps=0.1, n=(4, 4, 6)):
+    """Liquid below the oblique plane a.x = -z0 ... i.e. d = (z0 + a.x)/|a|
+    (signed distance, liquid where d > 0), phi = tanh(d / 2 eps)."""
+    mesh = W.Mesh(n)
+    X = W.node_coords(mesh)
+    a = np.asarray(a, float)
+    d = (z0 + X @ a) / np.linalg.norm(a)
+    p = W.OseenParams(heaviside=1, eps=eps)
+    return mesh, X, d, np.tanh(d / (2 * eps)), p, a / np.linalg.norm(a)
+
+
+def test_transport_projections_on_a_plane():
+    # For a planar interface the recovered distance d(phi) is linear, its
+    # nodal gradient exact, so n = grad d / |grad d| is the unit normal into
+    # the liquid and the projections are closed forms: x_G = x - d n on the
+    # plane, x_l = x + (3 eps - d) n on the parallel plane 3 eps into the
+    # liquid.  Catches a flipped normal, a wrong projection distance and the
+    # linear Heaviside's H = 1 contour.
+    mesh, X, d, phi, p, nvec = _plane_case()
+    sp = W.SourceParams()
+    u = np.zeros((3, mesh.n_nodes))
+    T = np.full(mesh.n_nodes, sp.T_boil)
+    r = O.transport_velocity(mesh, p, sp, 2, phi, u, T)
+    assert np.abs(r.normal - nvec[:, None]).max() <= 1e-12
+    assert np.abs(r.x_gamma - (X - d[:, None] * nvec).T).max() <= 1e-12
+    assert np.abs(r.x_liquid - (X + (3 * p.eps - d)[:, None] * nvec).T).max() <= 1e-12
+    # on the plane and 3 eps into the liquid: d(x_G) = 0, d(x_l) = 3 eps
+    dist = lambda P: (0.55 + P.T @ np.array([0.3, -0.2, -1.0])) / np.linalg.norm([0.3, -0.2, -1.0])
+    assert np.abs(dist(r.x_gamma)).max() <= 1e-12
+    assert np.abs(dist(r.x_liquid) - 3 * p.eps).max() <= 1e-12
+
+
+def test_transport_projection_on_a_sphere_converges():
+    # For a sphere the projected point x_G lands on the sphere up to the
+    # second-order error of the nodal gradient of the interpolated distance;
+    # on the band |d| < 3 eps with eps fixed: the error falls by about 4 when h halves
+    errs = []
+    for n in (8, 16, 32):
+        mesh = W.Mesh((n, n, n))
+        eps = 0.05
+        phi = W.phi_sphere(mesh, 0.3, eps)
+        X = W.node_coords(mesh)
+        sp = W.SourceParams()
+        r = O.transport_velocity(mesh, W.OseenParams(heaviside=1, eps=eps), sp, 2, phi,
+                                 np.zeros((3, mesh.n_nodes)), np.full(mesh.n_nodes, sp.T_boil))
+        band = np.abs(0.3 - np.linalg.norm(X - 0.5, axis=1)) < 3 * eps
+        rad = np.linalg.norm(r.x_gamma.T[band] - 0.5, axis=1)
+        errs.append(np.abs(rad - 0.3).max())
+    assert errs[2] < 1e-3 and errs[1] / errs[2] > 3.0 and errs[0] / errs[1] > 3.0, errs
+
+
+def test_transport_velocity_closed_forms_on_a_plane():
+    mesh, X, d, phi, p, nvec = _plane_case()
+    sp = W.SourceParams()
+    gam = sp.evap_coeff
+    alpha_v = 2 * gam / (2 - gam) * sp.h_v / np.sqrt(2 * np.pi * 8.314 / sp.molar_mass) * sp.vapor_density \
+        / sp.T_boil ** 1.5
+    # a velocity linear in x is reproduced exactly at x_l (variant 2); with
+    # T = T_v there is no mass flux and variant 1 returns u itself
+    A = np.array([[0.1, -0.3, 0.2], [0.05, 0.4, -0.1], [-0.2, 0.1, 0.3]])
+    b = np.array([0.5, -1.0, 0.25])
+    u = (X @ A.T + b).T
+    Tv = np.full(mesh.n_nodes, sp.T_boil)
+    r2 = O.transport_velocity(mesh, p, sp, 2, phi, u, Tv)
+    xl = np.clip(r2.x_liquid.T, 0.0, 1.0)
+    assert np.abs(r2.u_gamma - (xl @ A.T + b).T).max() <= 1e-12
+    r1 = O.transport_velocity(mesh, p, sp, 1, phi, u, Tv)
+    assert np.abs(r1.u_gamma - u).max() <= 1e-14
+    # a temperature linear along the normal and quadratic along the plane:
+    # variant 2's mass flux is its value at x_G, the same for every node of a
+    # normal line (constant across the band), here alpha_v (T(x_G) - T_v)
+    c1 = np.array([0.4, 0.7, 0.0])
+    a = np.array([0.3, -0.2, -1.0])
+    dist = lambda P: (0.55 + P @ a) / np.linalg.norm(a)
+    Tfun = lambda P: sp.T_boil + 50.0 * (P @ c1) ** 2 + 80.0 * dist(P)
+    r2 = O.transport_velocity(mesh, p, sp, 2, phi, np.zeros_like(u), Tfun(X))
+    xg = np.clip(r2.x_gamma.T, 0.0, 1.0)  # projections that leave the box are moved back onto it
+    inside = np.all(xg == r2.x_gamma.T, axis=1)
+    assert inside.sum() > mesh.n_nodes // 2
+    ref = alpha_v * (Tfun(xg) - sp.T_boil) / p.rho_l * nvec[:, None]
+    assert np.abs(r2.u_gamma - ref).max() <= 1e-12 * np.abs(ref).max()
+    # where x_G is inside the box, T(x_G) has no normal part: constant along normal lines
+    assert np.abs(Tfun(xg[inside]) - sp.T_boil - 50.0 * (xg[inside] @ c1) ** 2).max() <= 1e-9
+    T = Tfun(X)
+    # variant 1 at H = 1 (deep in the liquid), H = 0 (gas) and H = 1/2 (on
+    # the interface): mdot(T_j) / rho with the reciprocal blend's closed values
+    r1 = O.transport_velocity(mesh, p, sp, 1, phi, np.zeros_like(u), T)
+    mdot = alpha_v * (T - sp.T_boil)
+    for sel, rho in [(d >= 3 * p.eps, p.rho_l), (d <= -3 * p.eps, p.rho_g)]:
+        assert sel.any()
+        ref = (mdot[sel] / rho) * nvec[:, None]
+        assert np.abs(r1.u_gamma[:, sel] - ref).max() <= 1e-12 * np.abs(ref).max()
+    mesh2, X2, d2, phi2, p2, nvec2 = _plane_case(a=(0.0, 0.0, -1.0), z0=0.5)
+    on = np.abs(X2[:, 2] - 0.5) < 1e-12
+    T2 = sp.T_boil + 100.0 * X2[:, 0]
+    r1 = O.transport_velocity(mesh2, p2, sp, 1, phi2, np.zeros((3, mesh2.n_nodes)), T2)
+    rho_half = 1.0 / (0.5 / p2.rho_l + 0.5 / p2.rho_g)
+    ref = alpha_v * 100.0 * X2[on, 0] / rho_half
+    assert np.abs(r1.u_gamma[2, on] + ref).max() <= 1e-12 * np.abs(ref).max()
