@@ -20,10 +20,11 @@ roofline   = the apply kernel alone (start/stop events attached to the
 cpu_baseline = the CPU oracle (assembled CSR, OpenMP) on the same workload.
 mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
              both to 1e-8, on 128^3 cells (257^3 nodes).
-oseen, heat_convection, heat_sources, three_phase, gradient = the other
-             operators, the interface-flux right-hand side, the three-phase
-             coefficients with the Tanasawa penalty and Darcy damping (and one
-             Picard step), and the adjoint step.
+oseen, heat_convection, heat_sources, three_phase, gradient,
+transport_velocity = the other operators, the interface-flux right-hand
+             side, the three-phase coefficients with the Tanasawa penalty and
+             Darcy damping (and one Picard step), the adjoint step, and the
+             level-set transport velocity.
 """
 from __future__ import annotations
 
@@ -90,6 +91,7 @@ def parse():
     p.add_argument("--no-conv", action="store_true")
     p.add_argument("--no-sources", action="store_true")
     p.add_argument("--no-three-phase", action="store_true")
+    p.add_argument("--no-transport", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -169,13 +171,41 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, x, b_T, min_spmv_s=10.0, max_spmv=3000):
-    """The oracle as it is (assembled CSR + OpenMP SpMV, numpy CG) on the same
-    workload: assembly, CSR SpMVs until min_spmv_s seconds have passed (at
-    most max_spmv), and one Jacobi-CG solve.  value = SpMV DoFs/s."""
+def host_cpu():
+    """Model name and logical CPU count of the host, from /proc/cpuinfo and lscpu."""
+    import subprocess
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        lscpu = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        fields = {l.split(":", 1)[0].strip(): l.split(":", 1)[1].strip() for l in lscpu.splitlines() if ":" in l}
+        lscpu = {k: fields[k] for k in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket",
+                                         "Socket(s)", "L3") if k in fields}
+    except Exception:
+        lscpu = {}
+    return {"model": model, "nproc": os.cpu_count(), "lscpu": lscpu}
+
+
+def cpu_baseline(wl, x, b_T, min_spmv_s=5.0, max_spmv=3000):
+    """The oracle as it is (assembled CSR + OpenMP SpMV, numpy Krylov loops):
+      heat 64^3: assembly, CSR SpMVs until min_spmv_s seconds have passed (at
+        most max_spmv), one Jacobi-CG solve to 1e-10 (b = A T_I);
+      Oseen 48^3: assembly, GMRES(30) with 3x3 point-block Jacobi to 1e-8 on
+        b = A x_ref (x_ref ~ U[-1,1], seed 1);
+      gradient 32^3: assembled-matrix adjoint gradient of the one-step
+        misfit with respect to k_q, rc_q and phi (delta-form and adjoint
+        Jacobi-CG to 1e-14).
+    value = heat SpMV DoFs/s."""
     import numpy as np
 
     import oracle as O
+    from paper_2501_18781_amd import workloads as W
 
     t0 = time.perf_counter()
     A = O.heat_matrix(wl.mesh, wl.params, phi=wl.phi)
@@ -193,18 +223,54 @@ def cpu_baseline(wl, x, b_T, min_spmv_s=10.0, max_spmv=3000):
     t_cg = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     del A, y
-    return {
+    out = {
         "value": nspmv * wl.mesh.n_nodes / t_spmv,
         "unit": "DoFs/s",
         "cores": cores,
         "kind": "oracle",
         "sample": (f"{wl.mesh.n[0]}^3 heat operator: CSR assembly by full Gauss quadrature ({t_asm:.1f} s), "
                    f"{nspmv} CSR SpMVs ({t_spmv:.2f} s), Jacobi-CG to 1e-10 ({r.iters} it, {t_cg:.2f} s); "
-                   f"value = SpMV DoFs/s"),
+                   f"value = SpMV DoFs/s; also Oseen 48^3 GMRES(30) and the 32^3 adjoint gradient"),
         "assembly_s": t_asm,
         "cg_s": t_cg,
         "cg_iters": r.iters,
+        "host": host_cpu(),
     }
+    log(f"[bench] CPU heat: {out['value']:.3g} DoFs/s, CG {r.iters} it {t_cg:.2f} s")
+    # Oseen 48^3, GMRES(30) with point-block Jacobi to 1e-8
+    ow = W.oseen_wavy_workload(48)
+    t0 = time.perf_counter()
+    B = O.oseen_matrix(ow.mesh, ow.params, ow.phi, ow.u0)
+    t_oasm = time.perf_counter() - t0
+    xr = W.uniform(1, 3 * ow.mesh.n_nodes)
+    bo = O.spmv(B, xr)
+    t0 = time.perf_counter()
+    pc = O.block_jacobi(B, ow.mesh.n_nodes)
+    ro = O.gmres(B, bo, pc, 30, 1e-8)
+    t_gm = time.perf_counter() - t0
+    out["oseen_gmres30_block_jacobi"] = {"cells": 48, "assembly_s": t_oasm, "solve_s": t_gm, "iters": ro.iters,
+                                         "rel_res": ro.rel_res, "converged": bool(ro.converged),
+                                         "rel_err_vs_x_ref": float(np.linalg.norm(ro.x - xr) / np.linalg.norm(xr))}
+    log(f"[bench] CPU Oseen 48^3: assembly {t_oasm:.1f} s, GMRES(30) {ro.iters} it {t_gm:.1f} s")
+    del B, pc
+    # assembled-adjoint gradient on 32^3 cells
+    gw = W.heat_sphere_workload(32, W.ALL_FACES)
+    t0 = time.perf_counter()
+    m, p = gw.mesh, gw.params
+    kq, rcq = O.heat_qp_coeffs(m, p, gw.phi)
+    Told = W.manufactured_T(m)
+    free = ~O.constrained_mask(m)
+    Told[~free] = 0.0
+    Ag = O.heat_matrix(m, p, kq=kq, rcq=rcq)
+    K = O.heat_matrix(m, p, kq=kq, rcq=rcq, alpha_m=0.0)
+    dT = O.jacobi_cg(Ag, -(K @ Told) * free, 1e-14).x
+    lam = O.jacobi_cg(Ag, 2.0 * (dT - 0.999 * dT) * free, 1e-14).x
+    O.heat_grad(m, p, Told + dT, Told, lam, phi=gw.phi, dT=dT)
+    t_gr = time.perf_counter() - t0
+    out["gradient_32"] = {"cells": 32, "s": t_gr,
+                          "what": "assembly, delta-form CG, adjoint CG, gradients w.r.t. k_q, rc_q, phi"}
+    log(f"[bench] CPU adjoint gradient 32^3: {t_gr:.2f} s")
+    return out
 
 
 def main():
@@ -382,7 +448,8 @@ def main():
                           (args.no_conv, "heat_convection", lambda: heat_conv_bench(dev)),
                           (args.no_sources, "heat_sources", lambda: heat_sources_bench(dev)),
                           (args.no_three_phase, "three_phase", lambda: three_phase_bench(dev)),
-                          (args.no_grad, "gradient", lambda: grad_bench(dev))]:
+                          (args.no_grad, "gradient", lambda: grad_bench(dev)),
+                          (args.no_transport, "transport_velocity", lambda: transport_bench(dev))]:
         if flag:
             continue
         try:
@@ -707,6 +774,45 @@ def grad_bench(dev, reps=5):
         bw = sorted(t[1] for t in times[1:])[reps // 2]
         out[label] = {"forward_ms": fw * 1e3, "backward_ms": bw * 1e3}
         log(f"[bench]   gradient {label}: forward {fw * 1e3:.2f} ms, backward {bw * 1e3:.2f} ms")
+    return out
+
+
+# Algorithmic bytes per node of the transport velocity: read phi, T and the
+# three velocity components, write the three components of u_Gamma.
+BYTES_PER_NODE_TRANSPORT = 8 * 8
+
+
+def transport_bench(dev, reps=50):
+    """Level-set transport velocity on the 64^3 mesh (2,146,689 nodes): the
+    liquid sphere with the sine Heaviside, Taylor-Green velocity, temperature
+    around the boiling point.  Whole call (distance pass + velocity pass),
+    HIP events, both variants; 64 algorithmic bytes per node."""
+    import torch
+
+    from paper_2501_18781_amd import mf
+    from paper_2501_18781_amd import workloads as W
+
+    wl = W.transport_workload(64)
+    nn = wl.mesh.n_nodes
+    log(f"[bench] transport velocity 64^3: {nn} nodes")
+    ctx = mf.Context(wl.mesh)
+    phi, u, T = dev(wl.phi), dev(wl.u), dev(wl.T)
+    ug = torch.empty_like(u)
+    s = torch.cuda.current_stream()
+    out = {"cells": 64, "nodes": nn, "bytes_per_node": BYTES_PER_NODE_TRANSPORT}
+    for variant, label in [(mf.MF_TRANSPORT_LOCAL, "local"), (mf.MF_TRANSPORT_LIQUID_EXTENSION, "liquid_extension")]:
+        for _ in range(3):
+            mf.transport_velocity(ctx, variant, wl.params, wl.sources, phi, u, T, ug)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            mf.transport_velocity(ctx, variant, wl.params, wl.sources, phi, u, T, ug)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        gbs = BYTES_PER_NODE_TRANSPORT * nn / t / 1e9
+        out[label] = {"us": t * 1e6, "nodes_per_s": nn / t, "algorithmic_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        log(f"[bench]   {label}: {t * 1e6:.1f} us ({gbs:.0f} GB/s algorithmic)")
     return out
 
 
