@@ -97,6 +97,9 @@ def parse():
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="write the HBM traffic summary from two rocprofv3 --pmc output folders and exit")
     p.add_argument("--command", default="", help="profiled command line, recorded in the summary")
+    p.add_argument("--profile-leg", default="",
+                   help="run only this supplementary leg (oseen, heat_convection, heat_sources, three_phase, "
+                        "gradient, transport_velocity, mg_vs_cg) and print its JSON, for profiler runs")
     return p.parse_args()
 
 
@@ -292,6 +295,10 @@ def main():
 
     torch.cuda.set_device(0)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    legs = {"mg_vs_cg": lambda: mg_vs_cg(args.mg_cells, dev), "oseen": lambda: oseen_bench(dev),
+            "heat_convection": lambda: heat_conv_bench(dev), "heat_sources": lambda: heat_sources_bench(dev),
+            "three_phase": lambda: three_phase_bench(dev), "gradient": lambda: grad_bench(dev),
+            "transport_velocity": lambda: transport_bench(dev)}
     if args.copy_calibration:
         # 2^26 doubles: FETCH_SIZE and WRITE_SIZE of this copy should read 512 MiB each
         src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
@@ -300,6 +307,9 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.profile_leg:
+        print(json.dumps({args.profile_leg: legs[args.profile_leg]()}), flush=True)
+        return
     n = args.cells
     wl = W.heat_sphere_workload(n, W.ALL_FACES)
     nn, nc = wl.mesh.n_nodes, wl.mesh.n_cells
@@ -443,17 +453,13 @@ def main():
         del sets
 
     del ctx, op
-    for flag, key, fn in [(args.no_mg, "mg_vs_cg", lambda: mg_vs_cg(args.mg_cells, dev)),
-                          (args.no_oseen, "oseen", lambda: oseen_bench(dev)),
-                          (args.no_conv, "heat_convection", lambda: heat_conv_bench(dev)),
-                          (args.no_sources, "heat_sources", lambda: heat_sources_bench(dev)),
-                          (args.no_three_phase, "three_phase", lambda: three_phase_bench(dev)),
-                          (args.no_grad, "gradient", lambda: grad_bench(dev)),
-                          (args.no_transport, "transport_velocity", lambda: transport_bench(dev))]:
+    for flag, key in [(args.no_mg, "mg_vs_cg"), (args.no_oseen, "oseen"), (args.no_conv, "heat_convection"),
+                      (args.no_sources, "heat_sources"), (args.no_three_phase, "three_phase"),
+                      (args.no_grad, "gradient"), (args.no_transport, "transport_velocity")]:
         if flag:
             continue
         try:
-            result[key] = fn()
+            result[key] = legs[key]()
         except Exception as e:  # reported, never silently replaced
             result[key] = {"error": f"{type(e).__name__}: {e}"}
 

@@ -88,13 +88,6 @@ __device__ __forceinline__ void visc_dir(const double *u, const double *nu, cons
         }
 }
 
-template <int D> __device__ __forceinline__ void conv_any(bool tr, const double *u, const double *rw, const double *w,
-                                                          double s, double *acc)
-{
-    if (tr) conv_transpose<double, D>(u, rw, w, s, acc);
-    else conv_forward<double, D>(u, rw, w, s, acc);
-}
-
 // Solid fraction (eq. solid_fraction) and smooth indicator H_s (eq. heaviside_sl).
 __device__ __forceinline__ double solid_fraction(const OseenArgs &a, double T)
 {
@@ -102,110 +95,145 @@ __device__ __forceinline__ double solid_fraction(const OseenArgs &a, double T)
 }
 __device__ __forceinline__ double solid_indicator(double fs) { return fs * fs * (3.0 - 2.0 * fs); }
 
-// One component C of the Oseen operator on one cell; result (nodal) in acc.
-// TP: three phases at the frozen temperature staged at tcs, with the Darcy
-// damping of the solid added to the mass term.
-template <int C, int HK, bool TR, bool TP>
-__device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, const KMesh &m, const double *ps,
-                                           const double *us, const double *u0s, const double *tcs, double *acc)
+// Gauss-point fields shared by the brick's three wavefronts are kept in LDS
+// as [q][cell] (27 x 64 doubles each): a lane reads its own cell's column,
+// consecutive lanes in consecutive banks.
+constexpr int GQ = 27 * BNT; // doubles of one shared Gauss-point field
+
+// Phase 1 of component C on one cell (every wavefront of the brick runs it
+// for its own C, on the staged nodal fields):
+//   u   = S x_C at the Gauss points (returned in u);
+//   w0  = S u0_C at the Gauss points (returned in w0, shared after a barrier);
+//   the coefficients rho W and alpha_v mu W at the nine Gauss points
+//   9C .. 9C + 8 (the three wavefronts split the 27 points), written to the
+//   shared fields rwl and nul;
+//   acc = Darcy weight * u with three phases (TP), untouched otherwise.
+template <int C, int HK, bool TP>
+__device__ __forceinline__ void oseen_phase1(const Brick &br, const OseenArgs &a, const KMesh &m, const double *stage,
+                                             double *rwl, double *nul, double *u, double *w0, double *acc)
 {
+    const double *ps = stage, *us = stage + BNB, *u0s = stage + 4 * BNB, *tcs = stage + 7 * BNB;
     const double vol = m.hx * m.hy * m.hz;
-    const double sdir[3] = {1.0 / (kR * m.hx), 1.0 / (kR * m.hy), 1.0 / (kR * m.hz)};
-    double rw[27]; // rho W
-    br.gather27(ps, rw);
-    interp3(rw);
-    heaviside27<HK>(a, rw);
-    double u[27];
+    const int t = br.t;
+    double h[27];
+    br.gather27(ps, h);
+    interp3(h);
     if constexpr (TP) {
-        // the temperature is needed for rho W and the Darcy weight only, so
-        // both are formed (the latter in acc) before u is gathered
-        double t[27];
-        br.gather27(tcs, t);
-        interp3(t);
+        double tq[27];
+        br.gather27(tcs, tq);
+        interp3(tq);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int q = 9 * C + j;
+            double d;
+            const double H = HK == 0 ? heaviside_linear<double>(h[q]) : heaviside_sine(a.eps, h[q], &d);
+            const double Hs = solid_indicator(solid_fraction(a, tq[q]));
+            const double W = vol * gauss_weight(q);
+            rwl[q * BNT + t] = W / (H / (Hs * a.rho_s + (1.0 - Hs) * a.rho_l) + (1.0 - H) / a.rho_g);
+            nul[q * BNT + t] = a.av * W * (H * (Hs * a.mu_s + (1.0 - Hs) * a.mu_l) + (1.0 - H) * a.mu_g);
+        }
+        // Darcy weight W C fs^2 / ((1 - fs)^3 + b), held in acc until u is known
 #pragma unroll
         for (int q = 0; q < 27; ++q) {
-            const double fs = solid_fraction(a, t[q]), Hs = solid_indicator(fs);
-            const double rho_sl = Hs * a.rho_s + (1.0 - Hs) * a.rho_l;
-            const double W = vol * gauss_weight(q);
-            rw[q] = W / (rw[q] / rho_sl + (1.0 - rw[q]) / a.rho_g);
-            acc[q] = W * a.darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + a.darcy_b);
+            const double fs = solid_fraction(a, tq[q]);
+            acc[q] = vol * gauss_weight(q) * a.darcy_C * fs * fs / ((1.0 - fs) * (1.0 - fs) * (1.0 - fs) + a.darcy_b);
         }
-        pin27(rw);
         pin27(acc);
     } else {
 #pragma unroll
-        for (int q = 0; q < 27; ++q) rw[q] = vol * gauss_weight(q) / (rw[q] / a.rho_l + (1.0 - rw[q]) / a.rho_g);
+        for (int j = 0; j < 9; ++j) {
+            const int q = 9 * C + j;
+            double d;
+            const double H = HK == 0 ? heaviside_linear<double>(h[q]) : heaviside_sine(a.eps, h[q], &d);
+            const double W = vol * gauss_weight(q);
+            rwl[q * BNT + t] = W / (H / a.rho_l + (1.0 - H) / a.rho_g);
+            nul[q * BNT + t] = a.av * W * (a.mu_g + H * (a.mu_l - a.mu_g));
+        }
     }
+    if constexpr (TP) pin27(acc);
     br.gather27(us + C * BNB, u);
     interp3(u);
     if constexpr (TP) {
 #pragma unroll
-        for (int q = 0; q < 27; ++q) acc[q] = (a.am * rw[q] + acc[q]) * u[q];
-    } else {
-#pragma unroll
-        for (int q = 0; q < 27; ++q) acc[q] = a.am * rw[q] * u[q];
-    }
-    {
-        double w[27];
-        auto velocity = [&](int d) {
-            pin27(acc);
-            pin27(u);
-            br.gather27(u0s + d * BNB, w);
-            interp3(w);
-        };
-        velocity(0);
-        conv_any<0>(TR, u, rw, w, a.ac * sdir[0], acc);
-        velocity(1);
-        conv_any<1>(TR, u, rw, w, a.ac * sdir[1], acc);
-        velocity(2);
-        conv_any<2>(TR, u, rw, w, a.ac * sdir[2], acc);
-    }
-    // viscosity nu = alpha_v W mu (overwrites rho W, no longer needed)
-    double *nu = rw;
-    if constexpr (TP || HK == 1) {
-        // u is gathered again afterwards: live next to the temperature (or
-        // the sine Heaviside) it would exceed the register budget
+        for (int q = 0; q < 27; ++q) acc[q] *= u[q];
         pin27(acc);
-        double t[27];
-        if constexpr (TP) {
-            br.gather27(tcs, t);
-            interp3(t);
+    }
+    pin27(u);
+    br.gather27(u0s + C * BNB, w0);
+    interp3(w0);
+}
+
+// Phase 2 of component C: mass and convection with rho W from rwl and the
+// Gauss-point u0 of all three components from the shared fields w0l[d]:
+//   acc (+)= alpha_m rho W u                                   (mass)
+//   forward:   acc += alpha_c rho W sum_d u0_d d_d u
+//   transpose: acc += sum_d D_d^T (alpha_c rho W u0_d u)
+template <int C, bool TR, bool TP>
+__device__ __forceinline__ void oseen_phase2(const Brick &br, const OseenArgs &a, const KMesh &m, const double *rwl,
+                                             const double *w0l, const double *u, double *acc)
+{
+    const int t = br.t;
+    const double sdir[3] = {1.0 / (kR * m.hx), 1.0 / (kR * m.hy), 1.0 / (kR * m.hz)};
+    double rw[27];
 #pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                const double Hs = solid_indicator(solid_fraction(a, t[q]));
-                t[q] = Hs * a.mu_s + (1.0 - Hs) * a.mu_l;
+    for (int q = 0; q < 27; ++q) rw[q] = rwl[q * BNT + t];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) acc[q] = (TP ? acc[q] : 0.0) + a.am * rw[q] * u[q];
+    auto dir = [&](auto D) {
+        constexpr int d = decltype(D)::value;
+        // one direction at a time: its 27 reads are not hoisted above the
+        // previous direction's arithmetic
+        pin27(acc);
+        pin27(rw);
+        pin27((double *)u);
+        const double *w = w0l + d * GQ + t;
+        const double s = a.ac * sdir[d];
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm) {
+                const int i0 = lidx<d>(0, mm, n), i1 = lidx<d>(1, mm, n), i2 = lidx<d>(2, mm, n);
+                if constexpr (TR) {
+                    Q2<double>::derivT_acc(s * rw[i0] * w[i0 * BNT] * u[i0], s * rw[i1] * w[i1 * BNT] * u[i1],
+                                           s * rw[i2] * w[i2 * BNT] * u[i2], acc[i0], acc[i1], acc[i2]);
+                } else {
+                    double t0, t1, t2;
+                    Q2<double>::deriv(u[i0], u[i1], u[i2], t0, t1, t2);
+                    acc[i0] += s * rw[i0] * w[i0 * BNT] * t0;
+                    acc[i1] += s * rw[i1] * w[i1 * BNT] * t1;
+                    acc[i2] += s * rw[i2] * w[i2 * BNT] * t2;
+                }
             }
-        }
-        br.gather27(ps, nu);
-        interp3(nu);
-        heaviside27<HK>(a, nu);
+    };
+    dir(std::integral_constant<int, 0>{});
+    dir(std::integral_constant<int, 1>{});
+    dir(std::integral_constant<int, 2>{});
+}
+
+// Phase 3 of component C: viscosity with nu = alpha_v mu W from nul and the
+// Gauss-point values of the other two components from the shared fields ul[d]:
+//   acc += D_C^T (2 nu d_C u_C) + sum_{d != C} D_d^T (nu (d_d u_C + d_C u_d)),
+// then y_C = S^T acc (in acc).
+template <int C>
+__device__ __forceinline__ void oseen_phase3(const Brick &br, const KMesh &m, const double *nul, const double *ul,
+                                             const double *u, double *acc)
+{
+    const int t = br.t;
+    const double sdir[3] = {1.0 / (kR * m.hx), 1.0 / (kR * m.hy), 1.0 / (kR * m.hz)};
+    double nu[27];
 #pragma unroll
-        for (int q = 0; q < 27; ++q)
-            nu[q] = a.av * vol * gauss_weight(q) * (nu[q] * (TP ? t[q] : a.mu_l) + (1.0 - nu[q]) * a.mu_g);
-        pin27(acc);
-        pin27(nu);
-        br.gather27(us + C * BNB, u);
-        interp3(u);
-    } else {
-        pin27(acc);
-        pin27(u);
-        br.gather27(ps, nu);
-        interp3(nu);
-        heaviside27<HK>(a, nu);
-#pragma unroll
-        for (int q = 0; q < 27; ++q) nu[q] = a.av * vol * gauss_weight(q) * (a.mu_g + nu[q] * (a.mu_l - a.mu_g));
-    }
+    for (int q = 0; q < 27; ++q) nu[q] = nul[q * BNT + t];
     double e[27];
     auto cross = [&](auto D) {
         constexpr int d = decltype(D)::value;
-        if (d == C) {
+        pin27(acc);
+        pin27(nu);
+        pin27((double *)u);
+        if constexpr (d == C) {
             visc_dir<d, true>(u, nu, nullptr, sdir[d], acc);
         } else {
-            pin27(acc);
-            pin27(u);
-            pin27(nu);
-            br.gather27(us + d * BNB, e);
-            interp3(e);
+#pragma unroll
+            for (int q = 0; q < 27; ++q) e[q] = ul[d * GQ + q * BNT + t];
             deriv_inplace<C>(e, sdir[C]); // d_C u_d
             visc_dir<d, false>(u, nu, e, sdir[d], acc);
         }
@@ -216,31 +244,53 @@ __device__ __forceinline__ void oseen_cell(const Brick &br, const OseenArgs &a, 
     interp3T(acc);
 }
 
-// One workgroup of three wavefronts per brick: wave c computes velocity
-// component c of every cell, from one shared staging of phi, x and u0.
+// One workgroup of three wavefronts per brick; wavefront c computes velocity
+// component c of every cell.  The nodal fields (phi, x and u0, three
+// components each, and with three phases the frozen temperature) are staged
+// once; each wavefront interpolates its own components of x and u0 and the
+// coefficients at a third of the Gauss points, and the brick's Gauss-point
+// fields are exchanged through LDS:
+//   region A: staging, then u0 at the Gauss points (3 fields), then x at the
+//             Gauss points (3 fields); region C: rho W and nu.
 template <int HK, bool TR, bool TP>
 __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, const double *__restrict__ x,
                                                           double *__restrict__ y, double *__restrict__ face)
 {
-    // staging: phi, x (3 components), u0 (3 components) and, with three
-    // phases, the frozen temperature; then the node-sum exchange of the 3
-    // components
-    constexpr int STAGE = (TP ? 8 : 7) * BNB, CONTRIB = 3 * 9 * BNT;
-    __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
+    constexpr int STAGE = (TP ? 8 : 7) * BNB, GAUSS3 = 3 * GQ;
+    constexpr int AREG = STAGE > GAUSS3 ? STAGE : GAUSS3;
+    __shared__ double lds[AREG + 2 * GQ];
+    double *A = lds, *rwl = lds + AREG, *nul = rwl + GQ;
     const int comp = threadIdx.x / BNT; // uniform over a wavefront
     const Brick br(m, threadIdx.x % BNT);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    double *ps = lds, *us = lds + BNB, *u0s = lds + 4 * BNB, *tcs = lds + 7 * BNB;
+    double *ps = A, *us = A + BNB, *u0s = A + 4 * BNB, *tcs = A + 7 * BNB;
     if (comp == 0) br.load(m, a.phi, ps, false);
     if (TP && comp == 1) br.load(m, a.tc, tcs, false);
     br.load(m, x + comp * nn, us + comp * BNB, true);
     br.load(m, a.u0 + comp * nn, u0s + comp * BNB, false);
     __syncthreads();
-    double acc[27];
-    if (comp == 0) oseen_cell<0, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
-    else if (comp == 1) oseen_cell<1, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
-    else oseen_cell<2, HK, TR, TP>(br, a, m, ps, us, u0s, tcs, acc);
-    __syncthreads(); // staging no longer read
+    double u[27], acc[27];
+    {
+        double w0[27];
+        if (comp == 0) oseen_phase1<0, HK, TP>(br, a, m, A, rwl, nul, u, w0, acc);
+        else if (comp == 1) oseen_phase1<1, HK, TP>(br, a, m, A, rwl, nul, u, w0, acc);
+        else oseen_phase1<2, HK, TP>(br, a, m, A, rwl, nul, u, w0, acc);
+        __syncthreads(); // staging no longer read: region A takes u0 at the Gauss points
+#pragma unroll
+        for (int q = 0; q < 27; ++q) A[comp * GQ + q * BNT + br.t] = w0[q];
+    }
+    __syncthreads();
+    if (comp == 0) oseen_phase2<0, TR, TP>(br, a, m, rwl, A, u, acc);
+    else if (comp == 1) oseen_phase2<1, TR, TP>(br, a, m, rwl, A, u, acc);
+    else oseen_phase2<2, TR, TP>(br, a, m, rwl, A, u, acc);
+    __syncthreads(); // u0 no longer read: region A takes x at the Gauss points
+#pragma unroll
+    for (int q = 0; q < 27; ++q) A[comp * GQ + q * BNT + br.t] = u[q];
+    __syncthreads();
+    if (comp == 0) oseen_phase3<0>(br, m, nul, A, u, acc);
+    else if (comp == 1) oseen_phase3<1>(br, m, nul, A, u, acc);
+    else oseen_phase3<2>(br, m, nul, A, u, acc);
+    __syncthreads(); // region A no longer read: it takes the node-sum exchange
     br.assemble27(acc, lds + comp * 9 * BNT);
     double *fb = face + ((int64_t)comp * n_bricks(m) + br.brick) * BFACE;
     double *yc = y + comp * nn;
