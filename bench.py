@@ -97,6 +97,15 @@ def parse():
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="write the HBM traffic summary from two rocprofv3 --pmc output folders and exit")
     p.add_argument("--command", default="", help="profiled command line, recorded in the summary")
+    p.add_argument("--kernel", default=APPLY_KERNEL,
+                   help="kernel name (substring) the counter summaries describe")
+    p.add_argument("--algorithmic-bytes", type=float, default=0.0,
+                   help="algorithmic bytes per launch of --kernel, for the traffic summary")
+    p.add_argument("--title", default="", help="first line of a counter summary")
+    p.add_argument("--summarize-sq", nargs="+", metavar="DIR",
+                   help="write the SQ counter summary of --kernel from rocprofv3 --pmc output folders and exit")
+    p.add_argument("--summarize-trace", metavar="DIR",
+                   help="write the kernel statistics of a rocprofv3 --kernel-trace --stats folder and exit")
     p.add_argument("--profile-leg", default="",
                    help="run only this supplementary leg (oseen, heat_convection, heat_sources, three_phase, "
                         "gradient, transport_velocity, mg_vs_cg) and print its JSON, for profiler runs")
@@ -111,12 +120,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def _counter_means(folder, counter):
-    """Mean counter value per dispatch of the apply kernel and of the calibration copy."""
+def _counter_means(folder, counter, kernel=APPLY_KERNEL):
+    """Mean counter value per dispatch of the kernel and of the calibration copy."""
     files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no counter_collection.csv under {folder}")
-    vals = {APPLY_KERNEL: [], CALIB_KERNEL: []}
+    vals = {kernel: [], CALIB_KERNEL: []}
     for f in files:
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] != counter:
@@ -130,31 +139,92 @@ def _counter_means(folder, counter):
     return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
 
 
-def summarize_counters(fetch_dir, write_dir, command):
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the apply kernel, scaled
-    so that the calibration copy reads as its true 512 MiB each way."""
-    f, nf = _counter_means(fetch_dir, "FETCH_SIZE")
-    w, nw = _counter_means(write_dir, "WRITE_SIZE")
+def summarize_counters(fetch_dir, write_dir, command, kernel=APPLY_KERNEL, alg_bytes=0.0, title=""):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernel, scaled so
+    that the calibration copy reads as its true 512 MiB each way."""
+    f, nf = _counter_means(fetch_dir, "FETCH_SIZE", kernel)
+    w, nw = _counter_means(write_dir, "WRITE_SIZE", kernel)
     sf = CALIB_BYTES / (f[CALIB_KERNEL] * 1024.0)
     sw = CALIB_BYTES / (w[CALIB_KERNEL] * 1024.0)
-    fetch_b = f[APPLY_KERNEL] * 1024.0 * sf
-    write_b = w[APPLY_KERNEL] * 1024.0 * sw
+    fetch_b = f[kernel] * 1024.0 * sf
+    write_b = w[kernel] * 1024.0 * sw
+    heat = kernel == APPLY_KERNEL
+    alg = alg_bytes or (BYTES_PER_NODE * 129 ** 3 if heat else 0.0)
     lines = [
-        "HBM traffic of the FP64 heat apply kernel, 64^3 cells (2,146,689 nodes)",
+        title or "HBM traffic of the FP64 heat apply kernel, 64^3 cells (2,146,689 nodes)",
         f"command: {command}",
-        f"kernel: {APPLY_KERNEL} ({nf[APPLY_KERNEL]} dispatches counted for FETCH_SIZE, "
-        f"{nw[APPLY_KERNEL]} for WRITE_SIZE)",
+        f"kernel: {kernel} ({nf[kernel]} dispatches counted for FETCH_SIZE, {nw[kernel]} for WRITE_SIZE)",
         f"calibration: {CALIB_KERNEL} over 2^26 doubles ({CALIB_BYTES} bytes read, {CALIB_BYTES} written)",
         f"calibration FETCH_SIZE KiB: {f[CALIB_KERNEL]:.1f} (scale {sf:.4f})",
         f"calibration WRITE_SIZE KiB: {w[CALIB_KERNEL]:.1f} (scale {sw:.4f})",
-        f"apply FETCH_SIZE KiB per dispatch: {f[APPLY_KERNEL]:.1f}",
-        f"apply WRITE_SIZE KiB per dispatch: {w[APPLY_KERNEL]:.1f}",
+        f"kernel FETCH_SIZE KiB per dispatch: {f[kernel]:.1f}",
+        f"kernel WRITE_SIZE KiB per dispatch: {w[kernel]:.1f}",
         f"fetch_bytes_per_launch: {fetch_b:.0f}",
         f"write_bytes_per_launch: {write_b:.0f}",
         f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
-        f"algorithmic_bytes_per_launch: {BYTES_PER_NODE * 129 ** 3}",
-        f"source_hash: {kernel_source_hash()}",
+        f"algorithmic_bytes_per_launch: {alg:.0f}",
     ]
+    if alg:
+        lines.append(f"traffic / algorithmic: {(fetch_b + write_b) / alg:.3f}")
+    if heat:
+        lines.append(f"source_hash: {kernel_source_hash()}")
+    return "\n".join(lines) + "\n"
+
+
+SQ_ORDER = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_ACTIVE_INST_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY",
+            "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+            "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_MISC"]
+
+
+def summarize_sq(dirs, kernel, command, title=""):
+    """Mean per-dispatch SQ counters of the kernel from rocprofv3 --pmc folders,
+    with the shares of each wavefront's cycles they imply."""
+    vals, ndisp = {}, 0
+    for d in dirs:
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            acc = {}
+            for r in csv.DictReader(open(fn)):
+                if kernel in r["Kernel_Name"]:
+                    acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            for k, v in acc.items():
+                vals[k] = sum(v) / len(v)
+                ndisp = max(ndisp, len(v))
+    lines = [title or f"SQ counters of {kernel}", f"command: {command}", f"kernel: {kernel} ({ndisp} dispatches averaged)",
+             "", "per launch (summed over the device)            value"]
+    for k in SQ_ORDER:
+        if k in vals:
+            lines.append(f"  {k:<40s} {vals[k]:>14.0f}")
+    wc, nw = vals.get("SQ_WAVE_CYCLES"), vals.get("SQ_WAVES")
+    if wc and nw:
+        lines += ["", "derived, per wavefront (share of its wave cycles):"]
+        for k, label in [("SQ_ACTIVE_INST_ANY", "issuing an instruction"), ("SQ_WAIT_INST_ANY", "waiting for the next issue"),
+                         ("SQ_WAIT_ANY", "waiting on memory counters"), ("SQ_ACTIVE_INST_VALU", "VALU issue"),
+                         ("SQ_ACTIVE_INST_LDS", "LDS issue")]:
+            if k in vals:
+                lines.append(f"  {label:<34s} {vals[k] / wc:7.1%}")
+        for k, label in [("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_SALU", "SALU"), ("SQ_INSTS_LDS", "LDS"),
+                         ("SQ_INSTS_VMEM_RD", "vector memory read"), ("SQ_INSTS_VMEM_WR", "vector memory write")]:
+            if k in vals:
+                lines.append(f"  {label + ' instructions per wavefront':<48s} {vals[k] / nw:8.0f}")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_trace(folder, command, title=""):
+    """Per-kernel statistics (calls, average, min, max, share) of a rocprofv3
+    --kernel-trace --stats folder, the kernels sorted by total time."""
+    files = glob.glob(os.path.join(folder, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {folder}")
+    rows = list(csv.DictReader(open(files[0])))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [title or "Kernel statistics", f"command: {command}", "",
+             " calls    avg us    min us    max us  % time  kernel"]
+    for r in rows[:40]:
+        name = r["Name"]
+        name = name[5:] if name.startswith("void ") else name
+        name = name.split("(")[0] if "<" not in name.split("(")[0] else name[:name.index(">(") + 1] if ">(" in name else name
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.1f} {float(r['MinNs']) / 1e3:9.1f} "
+                     f"{float(r['MaxNs']) / 1e3:9.1f} {float(r['Percentage']):6.1f}%  {name}")
     return "\n".join(lines) + "\n"
 
 
@@ -279,7 +349,14 @@ def cpu_baseline(wl, x, b_T, min_spmv_s=5.0, max_spmv=3000):
 def main():
     args = parse()
     if args.summarize_counters:
-        sys.stdout.write(summarize_counters(*args.summarize_counters, args.command))
+        sys.stdout.write(summarize_counters(*args.summarize_counters, args.command, args.kernel,
+                                            args.algorithmic_bytes, args.title))
+        return
+    if args.summarize_sq:
+        sys.stdout.write(summarize_sq(args.summarize_sq, args.kernel, args.command, args.title))
+        return
+    if args.summarize_trace:
+        sys.stdout.write(summarize_trace(args.summarize_trace, args.command, args.title))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
