@@ -19,7 +19,8 @@ roofline   = the apply kernel alone (start/stop events attached to the
              of the timed steps), algorithmic flops and bytes per launch.
 cpu_baseline = the CPU oracle (assembled CSR, OpenMP) on the same workload.
 mg_vs_cg   = FP32-multigrid-preconditioned FP64 flexible CG vs FP64 Jacobi-CG,
-             both to 1e-8, on 128^3 cells (257^3 nodes).
+             both to 1e-8, on 128^3 cells (257^3 nodes): the hierarchy of the
+             level rule and the configured six-level one.
 oseen, heat_convection, heat_sources, three_phase, gradient,
 transport_velocity = the other operators, the interface-flux right-hand
              side, the three-phase coefficients with the Tanasawa penalty and
@@ -547,7 +548,13 @@ def main():
 
 
 def mg_vs_cg(n, dev):
-    """Time to 1e-8 relative residual on n^3 cells: FP32-MG flexible CG vs FP64 Jacobi-CG."""
+    """Time to 1e-8 relative residual on n^3 cells: FP32-multigrid flexible CG
+    vs FP64 Jacobi-CG.  Two hierarchies:
+      fcg_fp32_mg             the level rule (coarsening stops where the mass
+                              term dominates the diagonal, that level smoothed
+                              by Chebyshev(2); Chebyshev(1) on the levels with
+                              a coarse correction, 4^3 coarse level by FP64 CG);
+      fcg_fp32_mg_configured  six levels to 4^3, Chebyshev(4), FP64 CG coarse."""
     import numpy as np
     import torch
 
@@ -558,6 +565,8 @@ def mg_vs_cg(n, dev):
     regimes = [("dt=1e-3", W.HeatParams()),
                ("dt=1 (mass and conduction comparable, supplementary)", W.HeatParams(dt=1.0)),
                ("dt=1e3 (conduction-dominated, supplementary)", W.HeatParams(dt=1e3))]
+    hierarchies = [("fcg_fp32_mg", mf.MGConfig(coarse_cells=4, degree=1, auto_levels=True, smooth_degree=2)),
+                   ("fcg_fp32_mg_configured", mf.MGConfig(coarse_cells=4, degree=4))]
     for label, params in regimes:
         wl = W.heat_sphere_workload(n, W.ALL_FACES, params)
         log(f"[bench] mg vs cg {n}^3 {label}")
@@ -573,24 +582,29 @@ def mg_vs_cg(n, dev):
         ic = mf.cg_solve(op, b, xc, 1e-8, 5000)
         torch.cuda.synchronize()
         tc = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=4))
-        torch.cuda.synchronize()
-        tsetup = time.perf_counter() - t0
-        mf.mg_cg_solve(mg, b, xm, 1e-8, 200)  # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        im = mf.mg_cg_solve(mg, b, xm, 1e-8, 200)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        err = float(torch.linalg.norm(xm - xc) / torch.linalg.norm(xc))
-        out[label] = {"cg_fp64_jacobi": {"ms": tc * 1e3, "iters": ic.iters, "rel_res": ic.rel_res},
-                      "fcg_fp32_mg": {"ms": tm * 1e3, "iters": im.iters, "rel_res": im.rel_res,
-                                      "setup_ms": tsetup * 1e3, "levels": mg.n_levels},
-                      "speedup": tc / tm, "rel_diff_vs_cg": err}
-        log(f"[bench]   CG {ic.iters} it {tc * 1e3:.1f} ms | MG-FCG {im.iters} it {tm * 1e3:.1f} ms "
-            f"(setup {tsetup * 1e3:.0f} ms) | diff {err:.1e}")
-        mg.close()
+        entry = {"cg_fp64_jacobi": {"ms": tc * 1e3, "iters": ic.iters, "rel_res": ic.rel_res}}
+        msg = f"[bench]   CG {ic.iters} it {tc * 1e3:.1f} ms"
+        for key, cfg in hierarchies:
+            t0 = time.perf_counter()
+            mg = mf.Multigrid(op, cfg)
+            torch.cuda.synchronize()
+            tsetup = time.perf_counter() - t0
+            mf.mg_cg_solve(mg, b, xm, 1e-8, 300)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            im = mf.mg_cg_solve(mg, b, xm, 1e-8, 300)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t0
+            err = float(torch.linalg.norm(xm - xc) / torch.linalg.norm(xc))
+            entry[key] = {"ms": tm * 1e3, "iters": im.iters, "rel_res": im.rel_res, "setup_ms": tsetup * 1e3,
+                          "levels": [{"cells": c, "degree": d} for c, d, _, _ in mg.levels()],
+                          "speedup": tc / tm, "rel_diff_vs_cg": err}
+            msg += f" | {key} {im.iters} it {tm * 1e3:.1f} ms ({mg.n_levels} levels, {tc / tm:.2f}x)"
+            mg.close()
+        entry["speedup"] = entry["fcg_fp32_mg"]["speedup"]
+        entry["rel_diff_vs_cg"] = entry["fcg_fp32_mg"]["rel_diff_vs_cg"]
+        out[label] = entry
+        log(msg)
         del op, ctx
     return out
 

@@ -212,6 +212,16 @@ typedef struct {
     const double *lambda_max; /* optional host array, one per level (coarsest first), overriding the estimate */
     double coarse_rtol;       /* FP64 CG tolerance of the coarse solve */
     int32_t coarse_maxit;
+    int32_t auto_levels;      /* 0: levels down to coarse_cells.  1: level rule -- the first level, from the
+                                 finest down, on which the mass term dominates the diagonal,
+                                   beta = 17.5 (hx^-2 + hy^-2 + hz^-2) max(alpha_k k / (alpha_m rc)) <= beta_stop
+                                 (max over the liquid and gas values), becomes the coarsest and is treated by
+                                 Chebyshev smoothing (degree smooth_degree, bounds [lambda_min / eig_safety,
+                                 eig_safety lambda_max] from the Lanczos Ritz values) instead of a coarse
+                                 solve; without such a level the hierarchy goes down to coarse_cells */
+    int32_t smooth_degree;    /* Chebyshev degree on a smoothed coarsest level (auto_levels) */
+    double beta_stop;         /* threshold of the rule (auto_levels), e.g. 1 */
+    const double *lambda_min; /* optional host array, one per level (coarsest first), overriding the lower bound */
 } mf_mg_params;
 
 /* Build the level hierarchy of a heat operator in LEVELSET mode: levels are
@@ -223,6 +233,10 @@ void mf_mg_destroy(mf_mg *mg);
 int32_t mf_mg_n_levels(const mf_mg *mg);
 /* Chebyshev bounds in use, one per level, coarsest first (host array of n_levels). */
 mf_status mf_mg_lambda_max(const mf_mg *mg, double *out);
+/* Per level, coarsest first (host arrays of n_levels entries, each may be
+ * NULL): cells per direction, Chebyshev degree (0 for a coarsest level solved
+ * by CG), and the smoother's bounds. */
+mf_status mf_mg_levels(const mf_mg *mg, int32_t *cells, int32_t *degree, double *lambda_min, double *lambda_max);
 
 /* z = V(r): one V-cycle (Chebyshev pre-smoothing from zero, residual,
  * restriction R = P^T, coarse correction, prolongation P = Q2 embedding,

@@ -162,11 +162,16 @@ hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, doub
                      int64_t n, const RedWS *red, hipStream_t s);
 hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s);
 // Flexible-CG pieces: the preconditioner output z is supplied by the caller.
+// (r32 != null: also store r rounded to FP32, the FP32 preconditioner's input)
 hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n,
-                         const RedWS *red, hipStream_t s);
+                         const RedWS *red, hipStream_t s, float *r32 = nullptr);
 hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
                    hipStream_t s);
 hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s);
+// the same with the preconditioned residuals z and z_prev in FP32
+hipError_t fcg_dir_f32(CGState *st, const double *r, const float *z, const float *zprev, int64_t n, const RedWS *red,
+                       hipStream_t s);
+hipError_t fcg_pupdate_f32(CGState *st, const float *z, float *zprev, double *p, int64_t n, hipStream_t s);
 
 // ---- multigrid (mg.hip) ----
 hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s);

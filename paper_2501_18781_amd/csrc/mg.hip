@@ -7,6 +7,21 @@
 // coarsest apply the operator in FP32, the coarsest is solved by FP64 CG
 // (App. B: CG for symmetric systems) with a Jacobi preconditioner.
 //
+// Level rule (auto_levels): coarsening stops at the first level, from the
+// finest down, on which the mass term dominates the diagonal of A at every
+// node:
+//   beta_l = 17.5 (1/hx^2 + 1/hy^2 + 1/hz^2) max_phase alpha_k k / (alpha_m rc) <= beta_stop,
+// 17.5 being the largest ratio of the 1D Q2 stiffness to mass diagonal
+// entries (a vertex node: (14/3) / (8/30), against 10 at a midpoint), and the
+// arithmetic blends of k and rc never exceeding the larger phase ratio.  Then
+// D^{-1} A is within the factor (1 + beta) of the Jacobi-scaled mass matrix
+// from below, its spectrum is in the smoother's reach and a coarse-grid
+// correction would only add work: the level becomes the coarsest and is
+// treated by Chebyshev smoothing (degree smooth_degree) over the Lanczos
+// estimate [lambda_min / safety, safety lambda_max] of its spectrum, which
+// converges fast for such a well-conditioned operator.  In the
+// mass-dominated regime (small time steps) this is already the finest level.
+//
 // Transfer: P is the embedding of the coarse Q2 space into the fine one
 // (coarse Q2 functions are fine Q2 functions): in 1D a fine node at a coarse
 // node takes its value, the fine nodes at the quarter points of a coarse
@@ -302,9 +317,9 @@ hipError_t vsqrt(const double *d, double *out, int64_t n, hipStream_t s)
 // Host side
 // ---------------------------------------------------------------------------
 
-// Largest eigenvalue of the symmetric tridiagonal matrix (a, b) by bisection
-// on the Sturm count of the LDL^T pivots.
-static double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b)
+// Largest (or smallest) eigenvalue of the symmetric tridiagonal matrix
+// (a, b) by bisection on the Sturm count of the LDL^T pivots.
+static double tridiag_extreme_eig(const std::vector<double> &a, const std::vector<double> &b, bool largest)
 {
     const int n = (int)a.size();
     double lo = a[0], hi = a[0];
@@ -323,9 +338,10 @@ static double tridiag_max_eig(const std::vector<double> &a, const std::vector<do
         }
         return cnt;
     };
+    const int target = largest ? n : 1; // eigenvalues below x: all of them, or at least one
     for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
         const double mid = 0.5 * (lo + hi);
-        if (count_below(mid) >= n) hi = mid;
+        if (count_below(mid) >= target) hi = mid;
         else lo = mid;
     }
     return 0.5 * (lo + hi);
@@ -341,6 +357,8 @@ struct MGLevel {
     float *dinv = nullptr;     // FP32 inverse diagonal
     float *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
     double lmax = 0.0, lmin = 0.0;
+    double est_max = 0.0, est_min = 0.0; // Lanczos Ritz extremes of D^{-1} A (0: not estimated)
+    int degree = 0;                      // Chebyshev degree (0: the level is solved by CG)
     mf_operator op32, op64;
 };
 
@@ -349,7 +367,9 @@ struct mf_mg {
     mf_operator fine_op;
     mf_mg_params prm;
     std::vector<MGLevel> L; // 0 = coarsest
+    bool smooth_coarsest = false;          // the coarsest level is smoothed, not solved (level rule)
     double *b64 = nullptr, *x64 = nullptr; // coarse FP64 right-hand side and solution
+    float *zprev32 = nullptr;              // flexible CG: previous preconditioned residual
 };
 
 static mf_status mg_fail(mf_mg *mg, mf_status st, const char *msg)
@@ -363,22 +383,29 @@ static mf_status mg_fail(mf_mg *mg, mf_status st, const char *msg)
         if (e_ != hipSuccess) return fail((mg)->parent, MF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+static void level_free(MGLevel &l)
+{
+    if (l.own_phi64 && l.phi64) (void)hipFree(l.phi64);
+    for (void *p : {(void *)l.phi32, (void *)l.dinv, (void *)l.b, (void *)l.x, (void *)l.r, (void *)l.d, (void *)l.t})
+        if (p) (void)hipFree(p);
+    if (l.ctx) mf_destroy(l.ctx);
+    l = MGLevel();
+}
+
 static void mg_free(mf_mg *mg)
 {
     if (!mg) return;
-    for (MGLevel &l : mg->L) {
-        if (l.own_phi64 && l.phi64) (void)hipFree(l.phi64);
-        for (void *p : {(void *)l.phi32, (void *)l.dinv, (void *)l.b, (void *)l.x, (void *)l.r, (void *)l.d, (void *)l.t})
-            if (p) (void)hipFree(p);
-        if (l.ctx) mf_destroy(l.ctx);
-    }
+    for (MGLevel &l : mg->L) level_free(l);
     if (mg->b64) (void)hipFree(mg->b64);
     if (mg->x64) (void)hipFree(mg->x64);
+    if (mg->zprev32) (void)hipFree(mg->zprev32);
     delete mg;
 }
 
-// lambda_max of D^{-1} A on a level: Lanczos on D^{-1/2} A D^{-1/2} in FP64.
-static mf_status lanczos_lmax(mf_mg *mg, MGLevel &l, int steps, double *out, hipStream_t s)
+// Extreme Ritz values of D^{-1} A on a level: Lanczos on D^{-1/2} A D^{-1/2}
+// in FP64 (the largest converges from below to lambda_max, the smallest from
+// above to lambda_min).
+static mf_status lanczos_bounds(mf_mg *mg, MGLevel &l, int steps, double *out_max, double *out_min, hipStream_t s)
 {
     mf_ctx *c = l.ctx;
     const int64_t n = l.nn;
@@ -415,7 +442,8 @@ static mf_status lanczos_lmax(mf_mg *mg, MGLevel &l, int steps, double *out, hip
         MGCHK(mg, vaxpby(1.0 / beta, w, 0.0, q, n, s));
     }
     be.resize(al.size() > 0 ? al.size() - 1 : 0);
-    *out = tridiag_max_eig(al, be);
+    *out_max = tridiag_extreme_eig(al, be, true);
+    *out_min = tridiag_extreme_eig(al, be, false);
     return MF_OK;
 }
 
@@ -434,6 +462,8 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
     if (prm->coarse_cells < 1 || prm->degree < 1 || !(prm->smoothing_range > 1.0) || prm->eig_steps < 1 ||
         !(prm->eig_safety >= 1.0) || !(prm->coarse_rtol > 0.0) || prm->coarse_maxit < 1)
         return fail(c, MF_ERR_ARG, "invalid multigrid parameters");
+    if (prm->auto_levels && (prm->smooth_degree < 1 || !(prm->beta_stop > 0.0)))
+        return fail(c, MF_ERR_ARG, "the level rule needs smooth_degree >= 1 and beta_stop > 0");
     hipStream_t s = (hipStream_t)stream;
     // level meshes: halve every direction while n[0] > coarse_cells
     std::vector<mf_mesh> meshes{c->mesh};
@@ -445,7 +475,7 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
         }
         meshes.push_back(m);
     }
-    if (meshes.size() < 2) return fail(c, MF_ERR_ARG, "the mesh is already at the coarse size");
+
     mf_mg *mg = new mf_mg();
     mg->parent = c;
     mg->fine_op = *op;
@@ -480,9 +510,36 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
         l.op64.phi = l.phi64;
         l.op32 = l.op64;
         l.op32.precision = MF_FP32;
+    }
+    // Level rule: from the finest level down, the first level with a
+    // well-conditioned Jacobi-scaled operator becomes the (smoothed) coarsest.
+    int first = 0;
+    if (prm->auto_levels) {
+        const double diff = fmax(op->alpha_k * op->k_l / (op->alpha_m * op->rc_l),
+                                 op->alpha_k * op->k_g / (op->alpha_m * op->rc_g));
+        for (int li = nl - 1; li >= 0; --li) {
+            const KMesh &k = mg->L[li].ctx->km;
+            const double beta = 17.5 * (1.0 / (k.hx * k.hx) + 1.0 / (k.hy * k.hy) + 1.0 / (k.hz * k.hz)) * diff;
+            if (beta <= prm->beta_stop) {
+                first = li;
+                mg->smooth_coarsest = true;
+                break;
+            }
+        }
+        for (int li = 0; li < first; ++li) level_free(mg->L[li]);
+        mg->L.erase(mg->L.begin(), mg->L.begin() + first);
+    }
+    if (mg->L.size() < 2 && !mg->smooth_coarsest) {
+        mg_free(mg);
+        return fail(c, MF_ERR_ARG, "the mesh is already at the coarse size");
+    }
+    const int nk = (int)mg->L.size();
+    for (int li = 0; li < nk; ++li) {
+        MGLevel &l = mg->L[li];
+        const bool smoothed = li > 0 || mg->smooth_coarsest;
         const size_t fb = sizeof(float) * l.nn;
         bool ok = hipMalloc((void **)&l.b, fb) == hipSuccess && hipMalloc((void **)&l.x, fb) == hipSuccess;
-        if (ok && li > 0) // the coarsest level only needs its right-hand side and solution
+        if (ok && smoothed) // a solved coarsest level only needs its right-hand side and solution
             ok = hipMalloc((void **)&l.phi32, fb) == hipSuccess && hipMalloc((void **)&l.dinv, fb) == hipSuccess &&
                  hipMalloc((void **)&l.r, fb) == hipSuccess && hipMalloc((void **)&l.d, fb) == hipSuccess &&
                  hipMalloc((void **)&l.t, fb) == hipSuccess;
@@ -490,7 +547,7 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
             mg_free(mg);
             return fail(c, MF_ERR_OOM, "multigrid allocation failed");
         }
-        if (li == 0) continue; // coarsest: FP64 CG only
+        if (!smoothed) continue; // coarsest: FP64 CG only
         MGCHK(mg, vcvt_d2f(l.phi64, l.phi32, l.nn, s));
         l.op32.phi = l.phi32;
         if ((st = ensure_face(l.ctx, 1))) {
@@ -499,17 +556,20 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
         }
         MGCHK(mg, heat_diagonal(l.ctx->km, heat_args(&l.op32), 1, l.dinv, l.ctx->face, s));
         MGCHK(mg, vinvf(l.dinv, l.nn, s));
-        double est = 0.0;
-        if (prm->lambda_max) {
-            l.lmax = prm->lambda_max[li];
-        } else {
-            if ((st = lanczos_lmax(mg, l, prm->eig_steps, &est, s))) {
-                mg_free(mg);
-                return st;
-            }
-            l.lmax = prm->eig_safety * est;
+        const bool coarsest_smoothed = li == 0 && mg->smooth_coarsest;
+        const bool need_est = !prm->lambda_max || (coarsest_smoothed && !prm->lambda_min);
+        if (need_est && (st = lanczos_bounds(mg, l, prm->eig_steps, &l.est_max, &l.est_min, s))) {
+            mg_free(mg);
+            return st;
         }
-        l.lmin = l.lmax / prm->smoothing_range;
+        l.degree = coarsest_smoothed ? prm->smooth_degree : prm->degree;
+        l.lmax = prm->lambda_max ? prm->lambda_max[li] : prm->eig_safety * l.est_max;
+        if (prm->lambda_min) l.lmin = prm->lambda_min[li];
+        else l.lmin = coarsest_smoothed ? l.est_min / prm->eig_safety : l.lmax / prm->smoothing_range;
+    }
+    if (hipMalloc((void **)&mg->zprev32, sizeof(float) * c->nn) != hipSuccess) {
+        mg_free(mg);
+        return fail(c, MF_ERR_OOM, "multigrid allocation failed");
     }
     MGLevel &co = mg->L[0];
     if (hipMalloc((void **)&mg->b64, sizeof(double) * co.nn) != hipSuccess ||
@@ -536,6 +596,19 @@ mf_status mf_mg_lambda_max(const mf_mg *mg, double *out)
     return MF_OK;
 }
 
+mf_status mf_mg_levels(const mf_mg *mg, int32_t *cells, int32_t *degree, double *lambda_min, double *lambda_max)
+{
+    if (!mg) return MF_ERR_ARG;
+    for (size_t i = 0; i < mg->L.size(); ++i) {
+        const MGLevel &l = mg->L[i];
+        if (cells) cells[i] = l.mesh.n[0];
+        if (degree) degree[i] = l.degree;
+        if (lambda_min) lambda_min[i] = l.lmin;
+        if (lambda_max) lambda_max[i] = l.lmax;
+    }
+    return MF_OK;
+}
+
 } // extern "C"
 
 // Chebyshev smoothing of A_l x = b on level l (FP32); x from zero if x_zero.
@@ -545,7 +618,7 @@ static mf_status cheb_smooth(mf_mg *mg, MGLevel &l, const float *b, float *x, bo
 {
     mf_ctx *c = l.ctx;
     const int64_t n = l.nn;
-    const int deg = mg->prm.degree;
+    const int deg = l.degree;
     const double theta = 0.5 * (l.lmax + l.lmin), delta = 0.5 * (l.lmax - l.lmin), sigma = theta / delta;
     if (!x_zero) MGCHK(mg, heat_apply(c->km, heat_args(&l.op32), 1, x, l.t, c->face, nullptr, nullptr, s));
     MGCHK(mg, cheb_first(l.dinv, b, x_zero ? nullptr : l.t, l.r, l.d, x, (float)(1.0 / theta), deg > 1, n, s));
@@ -566,6 +639,7 @@ static mf_status vcycle(mf_mg *mg, int li, hipStream_t s)
 {
     MGLevel &l = mg->L[li];
     mf_status st;
+    if (li == 0 && mg->smooth_coarsest) return cheb_smooth(mg, l, l.b, l.x, true, s);
     if (li == 0) {
         if (heat_fits_one_brick(l.ctx->km)) {
             MGCHK(mg, heat_cg_one_brick(l.ctx->km, heat_args(&l.op64), l.b, l.x, mg->prm.coarse_rtol,
@@ -603,7 +677,10 @@ extern "C" mf_status mf_mg_vcycle(mf_mg *mg, const double *r, double *z, mf_stre
     return MF_OK;
 }
 
-// Flexible CG (Notay; Polak-Ribiere beta) in FP64 preconditioned by the V-cycle.
+// Flexible CG (Notay; Polak-Ribiere beta) in FP64 preconditioned by the
+// V-cycle.  The V-cycle's FP32 input (the residual, rounded by the update
+// kernel that forms it) and output (z, used as stored: its conversion to
+// FP64 is exact) stay in FP32 on the finest level.
 extern "C" mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, double rtol, int32_t maxit,
                                     mf_solve_info *info, mf_stream stream)
 {
@@ -613,31 +690,33 @@ extern "C" mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, doubl
     if (!(rtol >= 0.0) || maxit < 0) return fail(c, MF_ERR_ARG, "invalid rtol or maxit");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = c->nn;
-    double *r, *z, *p, *q, *zp;
+    double *r, *z, *p, *q;
     mf_status st;
-    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)) ||
-        (st = ws_vec(c, 5, &zp)))
+    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)))
         return st;
     RedWS red = redws(c);
     if ((st = ensure_face(c, 1))) return st;
     const HeatArgs ha = heat_args(&mg->fine_op);
+    MGLevel &top = mg->L.back();
+    const int ltop = (int)mg->L.size() - 1;
     HIPCHK(c, cg_init(c->cg, b, nullptr, x, r, z, p, q, n, rtol, maxit, 1, &red, s));
-    HIPCHK(c, vfill(zp, 0.0, n, 0, s));
+    HIPCHK(c, vfill(mg->zprev32, 0.0, n, 1, s));
+    HIPCHK(c, vcvt_d2f(b, top.b, n, s)); // r = b
     HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (!c->h_state->done) {
-        if ((st = mf_mg_vcycle(mg, r, z, stream))) return st;
-        HIPCHK(c, fcg_dir(c->cg, r, z, zp, n, &red, s));
-        HIPCHK(c, fcg_pupdate(c->cg, z, zp, p, n, s));
+        if ((st = vcycle(mg, ltop, s))) return st;
+        HIPCHK(c, fcg_dir_f32(c->cg, r, top.x, mg->zprev32, n, &red, s));
+        HIPCHK(c, fcg_pupdate_f32(c->cg, top.x, mg->zprev32, p, n, s));
         for (;;) {
             HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
-            HIPCHK(c, fcg_update_xr(c->cg, x, r, p, q, n, &red, s));
+            HIPCHK(c, fcg_update_xr(c->cg, x, r, p, q, n, &red, s, top.b));
             HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             if (c->h_state->done) break;
-            if ((st = mf_mg_vcycle(mg, r, z, stream))) return st;
-            HIPCHK(c, fcg_dir(c->cg, r, z, zp, n, &red, s));
-            HIPCHK(c, fcg_pupdate(c->cg, z, zp, p, n, s));
+            if ((st = vcycle(mg, ltop, s))) return st;
+            HIPCHK(c, fcg_dir_f32(c->cg, r, top.x, mg->zprev32, n, &red, s));
+            HIPCHK(c, fcg_pupdate_f32(c->cg, top.x, mg->zprev32, p, n, s));
         }
     }
     const CGState hs = *c->h_state;

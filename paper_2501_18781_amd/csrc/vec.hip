@@ -663,7 +663,8 @@ hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, const 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(VNT) fcg_xr_kernel(const CGState *st, double *__restrict__ x,
                                                      double *__restrict__ r, const double *__restrict__ p,
-                                                     const double *__restrict__ q, int64_t n, RedWS red)
+                                                     const double *__restrict__ q, int64_t n, RedWS red,
+                                                     float *__restrict__ r32)
 {
     __shared__ double lds[VNT / 64];
     if (st->done) return;
@@ -674,6 +675,7 @@ __global__ void __launch_bounds__(VNT) fcg_xr_kernel(const CGState *st, double *
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
+        if (r32) r32[i] = (float)ri; // the FP32 preconditioner's input
         acc += ri * ri;
     }
     grid_partials<1>(&acc, red, lds);
@@ -699,19 +701,20 @@ __global__ void __launch_bounds__(FNT) fcg_xr_finalize_kernel(CGState *st, const
 }
 
 hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n, const RedWS *red,
-                         hipStream_t s)
+                         hipStream_t s, float *r32)
 {
     const unsigned nb = vec_blocks(n);
     if (red->capacity < nb) return hipErrorInvalidValue;
-    fcg_xr_kernel<<<nb, VNT, 0, s>>>(st, x, r, p, q, n, *red);
+    fcg_xr_kernel<<<nb, VNT, 0, s>>>(st, x, r, p, q, n, *red, r32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     fcg_xr_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
     return hipGetLastError();
 }
 
+template <typename Z>
 __global__ void __launch_bounds__(VNT) fcg_dir_kernel(const CGState *st, const double *__restrict__ r,
-                                                      const double *__restrict__ z, const double *__restrict__ zprev,
+                                                      const Z *__restrict__ z, const Z *__restrict__ zprev,
                                                       int64_t n, RedWS red)
 {
     __shared__ double lds[2 * (VNT / 64)];
@@ -720,8 +723,8 @@ __global__ void __launch_bounds__(VNT) fcg_dir_kernel(const CGState *st, const d
     GRID_STRIDE(i, n)
     {
         const double ri = r[i];
-        acc[0] += ri * z[i];
-        acc[1] += ri * zprev[i];
+        acc[0] += ri * (double)z[i];
+        acc[1] += ri * (double)zprev[i];
     }
     grid_partials<2>(acc, red, lds);
 }
@@ -743,34 +746,51 @@ __global__ void __launch_bounds__(FNT) fcg_dir_finalize_kernel(CGState *st, cons
     }
 }
 
-hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
-                   hipStream_t s)
+template <typename Z>
+static hipError_t fcg_dir_t(CGState *st, const double *r, const Z *z, const Z *zprev, int64_t n, const RedWS *red,
+                            hipStream_t s)
 {
     const unsigned nb = vec_blocks(n);
     if (red->capacity < 2 * nb) return hipErrorInvalidValue;
-    fcg_dir_kernel<<<nb, VNT, 0, s>>>(st, r, z, zprev, n, *red);
+    fcg_dir_kernel<Z><<<nb, VNT, 0, s>>>(st, r, z, zprev, n, *red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     fcg_dir_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
     return hipGetLastError();
 }
+hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
+                   hipStream_t s)
+{
+    return fcg_dir_t<double>(st, r, z, zprev, n, red, s);
+}
+hipError_t fcg_dir_f32(CGState *st, const double *r, const float *z, const float *zprev, int64_t n, const RedWS *red,
+                       hipStream_t s)
+{
+    return fcg_dir_t<float>(st, r, z, zprev, n, red, s);
+}
 
-__global__ void fcg_pupdate_kernel(const CGState *st, const double *__restrict__ z, double *__restrict__ zprev,
+template <typename Z>
+__global__ void fcg_pupdate_kernel(const CGState *st, const Z *__restrict__ z, Z *__restrict__ zprev,
                                    double *__restrict__ p, int64_t n)
 {
     if (st->done) return;
     const double beta = st->beta;
     GRID_STRIDE(i, n)
     {
-        const double zi = z[i];
-        p[i] = zi + beta * p[i];
+        const Z zi = z[i];
+        p[i] = (double)zi + beta * p[i];
         zprev[i] = zi;
     }
 }
 
 hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s)
 {
-    fcg_pupdate_kernel<<<ew_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    fcg_pupdate_kernel<double><<<ew_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    return hipGetLastError();
+}
+hipError_t fcg_pupdate_f32(CGState *st, const float *z, float *zprev, double *p, int64_t n, hipStream_t s)
+{
+    fcg_pupdate_kernel<float><<<ew_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
     return hipGetLastError();
 }
 

@@ -67,7 +67,8 @@ class MGParams(ctypes.Structure):
     _fields_ = [("coarse_cells", ctypes.c_int32), ("degree", ctypes.c_int32), ("smoothing_range", ctypes.c_double),
                 ("eig_steps", ctypes.c_int32), ("eig_safety", ctypes.c_double),
                 ("lambda_max", ctypes.POINTER(ctypes.c_double)), ("coarse_rtol", ctypes.c_double),
-                ("coarse_maxit", ctypes.c_int32)]
+                ("coarse_maxit", ctypes.c_int32), ("auto_levels", ctypes.c_int32), ("smooth_degree", ctypes.c_int32),
+                ("beta_stop", ctypes.c_double), ("lambda_min", ctypes.POINTER(ctypes.c_double))]
 
 
 MF_SRC_EVAPORATION, MF_SRC_LASER, MF_SRC_PENALTY = 1, 2, 4
@@ -122,6 +123,8 @@ _SIGS = {
     "mf_mg_destroy": (None, [_P]),
     "mf_mg_n_levels": (ctypes.c_int32, [_P]),
     "mf_mg_lambda_max": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "mf_mg_levels": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "mf_mg_vcycle": (ctypes.c_int, [_P, _P, _P, _P]),
     "mf_mg_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SolveInfo), _P]),
     "mf_quad_points": (ctypes.c_int, [_P, _P, _P]),
@@ -378,6 +381,10 @@ class MGConfig:
     lambda_max: Optional[Sequence[float]] = None
     coarse_rtol: float = 1e-12
     coarse_maxit: int = 500
+    auto_levels: bool = False
+    smooth_degree: int = 2
+    beta_stop: float = 1.0  # stiffness / mass ratio of the diagonal below which a level is smoothed only
+    lambda_min: Optional[Sequence[float]] = None
 
 
 class Multigrid:
@@ -389,10 +396,14 @@ class Multigrid:
         p.coarse_cells, p.degree, p.smoothing_range = cfg.coarse_cells, cfg.degree, cfg.smoothing_range
         p.eig_steps, p.eig_safety = cfg.eig_steps, cfg.eig_safety
         p.coarse_rtol, p.coarse_maxit = cfg.coarse_rtol, cfg.coarse_maxit
-        self._lmax = None
+        p.auto_levels, p.smooth_degree, p.beta_stop = int(cfg.auto_levels), cfg.smooth_degree, cfg.beta_stop
+        self._lmax = self._lmin = None
         if cfg.lambda_max is not None:
             self._lmax = (ctypes.c_double * len(cfg.lambda_max))(*cfg.lambda_max)
             p.lambda_max = self._lmax
+        if cfg.lambda_min is not None:
+            self._lmin = (ctypes.c_double * len(cfg.lambda_min))(*cfg.lambda_min)
+            p.lambda_min = self._lmin
         h = _P()
         c.check(library().mf_mg_create(c._h, ctypes.byref(op.desc), ctypes.byref(p), ctypes.byref(h),
                                        _stream(stream)))
@@ -404,6 +415,15 @@ class Multigrid:
         out = (ctypes.c_double * self.n_levels)()
         self.op.ctx.check(library().mf_mg_lambda_max(self._h, out))
         return list(out)
+
+    def levels(self):
+        """Per level, coarsest first: (cells per direction, Chebyshev degree (0:
+        solved by CG), lambda_min, lambda_max)."""
+        k = self.n_levels
+        c, d = (ctypes.c_int32 * k)(), (ctypes.c_int32 * k)()
+        lo, hi = (ctypes.c_double * k)(), (ctypes.c_double * k)()
+        self.op.ctx.check(library().mf_mg_levels(self._h, c, d, lo, hi))
+        return [(c[i], d[i], lo[i], hi[i]) for i in range(k)]
 
     def close(self):
         if getattr(self, "_h", None):

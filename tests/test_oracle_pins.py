@@ -934,3 +934,18 @@ def test_transport_velocity_closed_forms_on_a_plane():
     rho_half = 1.0 / (0.5 / p2.rho_l + 0.5 / p2.rho_g)
     ref = alpha_v * 100.0 * X2[on, 0] / rho_half
     assert np.abs(r1.u_gamma[2, on] + ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_largest_stiffness_to_mass_diagonal_ratio():
+    # the multigrid level rule bounds the stiffness part of the diagonal by
+    # 17.5 (1/hx^2 + 1/hy^2 + 1/hz^2) times the mass part (unit coefficients):
+    # a vertex node, (14/3) / (8/30) per direction; catches a wrong constant
+    # (10, the midpoint ratio, or 30, the cell-centre node's)
+    mesh = W.Mesh((3, 2, 4), lo=(0.0, 0.0, 0.0), hi=(1.0, 0.5, 2.0))
+    unit = P(heaviside=0, k_l=1.0, k_g=1.0, rc_l=1.0, rc_g=1.0)
+    phi = np.zeros(mesh.n_nodes)
+    M = O.heat_matrix(mesh, unit, phi=phi, alpha_m=1.0, alpha_k=0.0).diagonal()
+    K = O.heat_matrix(mesh, unit, phi=phi, alpha_m=0.0, alpha_k=1.0).diagonal()
+    h = [(mesh.hi[d] - mesh.lo[d]) / mesh.n[d] for d in range(3)]
+    bound = 17.5 * sum(1.0 / x ** 2 for x in h)
+    assert abs((K / M).max() - bound) <= 1e-12 * bound
