@@ -515,15 +515,14 @@ extern "C" mf_status mf_cg_solve(mf_ctx *c, const mf_operator *op, int32_t preco
 }
 
 // The CG iteration of mf_cg_solve on a checked symmetric heat operator;
-// uses workspace vectors 0-4.
+// uses workspace vectors 0, 2, 3 and 4.
 mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *b, double *x, double rtol, int maxit,
                    mf_solve_info *info, hipStream_t s)
 {
     mf_status st;
     const int64_t n = c->nn;
-    double *r, *z, *p, *q, *dinv = nullptr;
-    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)))
-        return st;
+    double *r, *p, *q, *dinv = nullptr;
+    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q))) return st;
     const HeatArgs ha = heat_args(op);
     if ((st = ensure_face(c, 1))) return st;
     if (precond == MF_PC_JACOBI) {
@@ -532,18 +531,36 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
         HIPCHK(c, vinv(dinv, n, s));
     }
     RedWS red = redws(c);
-    HIPCHK(c, cg_init(c->cg, b, dinv, x, r, z, p, q, n, rtol, maxit, 0, &red, s));
-    const int batch = 8;
+    HIPCHK(c, cg_init(c->cg, b, dinv, x, r, p, n, rtol, maxit, 0, &red, s));
+    // Iterations are launched in batches between host polls of the state;
+    // once done, the rest of a batch is a chain of no-op launches.  After
+    // the first batch the next one is sized from the residual's decay so
+    // far (geometric extrapolation to the threshold): that only sets how
+    // often the host polls, never what is computed.
+    int batch = 8;
+    double rr_prev = -1.0;
+    int iters_prev = 0;
     for (int done_iters = 0;;) {
         for (int k = 0; k < batch; ++k) {
             HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
-            HIPCHK(c, cg_update(c->cg, dinv, x, r, z, p, q, n, &red, s));
-            HIPCHK(c, cg_pupdate(c->cg, z, p, n, &red, s));
+            HIPCHK(c, cg_resid(c->cg, dinv, r, q, n, &red, s));
+            HIPCHK(c, cg_step(c->cg, dinv, x, r, p, n, &red, s));
         }
         done_iters += batch;
         HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        if (c->h_state->done || done_iters >= maxit + batch) break;
+        const CGState &h = *c->h_state;
+        if (h.done || done_iters >= maxit + batch) break;
+        const double rr0 = rr_prev > 0.0 ? rr_prev : h.bb;
+        const int dk = h.iter - iters_prev;
+        batch = 8;
+        if (dk > 0 && h.rr > 0.0 && rr0 > h.rr && h.thresh2 > 0.0) {
+            const double rate = log(h.rr / rr0) / dk; // per iteration, < 0
+            const double need = ceil(log(h.thresh2 / h.rr) / rate);
+            batch = need < 1.0 ? 1 : (need > 16.0 ? 16 : (int)need);
+        }
+        rr_prev = h.rr;
+        iters_prev = h.iter;
     }
     const CGState hs = *c->h_state;
     const double bnorm = sqrt(hs.bb);

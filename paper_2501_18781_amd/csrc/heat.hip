@@ -404,16 +404,35 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
 }
 
 // Second pass of an apply: shared nodes = sum of the bricks' face partials,
-// NPT nodes per thread (their loads in flight together).
+// NPT nodes per thread (their loads in flight together).  In CG mode the
+// first workgroup then also sums the bricks' partials of p.Ap (complete
+// once the brick kernel has finished) and sets alpha = rz / p.Ap, which
+// saves a launch per iteration.  A breakdown sets done here; a workgroup
+// of this launch that then skips its nodes leaves q incomplete, which no
+// later step of the solve reads.
 template <typename T, bool CG, int DMODE = 1, int NPT = 1>
 __global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
-                                                           const T *__restrict__ x, T *__restrict__ y,
-                                                           const CGState *cg)
+                                                           const T *__restrict__ x, T *__restrict__ y, CGState *cg,
+                                                           const double *__restrict__ partials, unsigned nbricks)
 {
     if (CG) {
         if (cg->done) return;
     }
     combine_shared<T, DMODE, NPT>(m, face, x, y);
+    if (CG && blockIdx.x == 0) {
+        __shared__ double red[CNT];
+        const double pAp = sum_partials<CNT>(partials, nbricks, 0, red);
+        if (threadIdx.x == 0) {
+            cg->pAp = pAp;
+            if (!(pAp > 0.0) || !isfinite(pAp)) {
+                cg->breakdown = 1;
+                cg->done = 1;
+                cg->alpha = 0.0;
+            } else {
+                cg->alpha = cg->rz / pAp;
+            }
+        }
+    }
 }
 
 constexpr int APPLY_NPT = 2; // nodes per thread in the combine pass of the applies
@@ -490,19 +509,18 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     if (e != hipSuccess) return e;
     const unsigned rows = combine_blocks(m, APPLY_NPT);
     if (rows == 0) {
-        // single brick: nothing shared
+        // single brick: nothing shared; alpha from the brick's partial
+        return cg ? cg_alpha(cg, &r, nb, s) : hipSuccess;
     } else if (fp32)
-        face_combine_kernel<float, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(m, (const float *)face, (const float *)x,
-                                                                            (float *)y, nullptr);
+        face_combine_kernel<float, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(
+            m, (const float *)face, (const float *)x, (float *)y, nullptr, nullptr, 0);
     else if (cg)
-        face_combine_kernel<double, true, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(m, (const double *)face,
-                                                                            (const double *)x, (double *)y, cg);
+        face_combine_kernel<double, true, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(
+            m, (const double *)face, (const double *)x, (double *)y, cg, r.partials, nb);
     else
-        face_combine_kernel<double, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(m, (const double *)face,
-                                                                             (const double *)x, (double *)y, nullptr);
-    e = hipGetLastError();
-    if (e != hipSuccess || !cg) return e;
-    return cg_alpha(cg, &r, nb, s);
+        face_combine_kernel<double, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(
+            m, (const double *)face, (const double *)x, (double *)y, nullptr, nullptr, 0);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -651,10 +669,10 @@ hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag
     if (rows == 0) return hipSuccess;
     if (fp32)
         face_combine_kernel<float, false, 2><<<rows, CNT, 0, s>>>(m, (const float *)face, nullptr, (float *)diag,
-                                                                  nullptr);
+                                                                  nullptr, nullptr, 0);
     else
         face_combine_kernel<double, false, 2><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr,
-                                                                   (double *)diag, nullptr);
+                                                                   (double *)diag, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 
@@ -926,7 +944,8 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
     // the level-set gradient sums over Dirichlet nodes too (DMODE 0)
     const unsigned rows = combine_blocks(m);
     if (rows == 0) return hipSuccess;
-    face_combine_kernel<double, false, 0><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr);
+    face_combine_kernel<double, false, 0><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr,
+                                                               nullptr, 0);
     return hipGetLastError();
 }
 

@@ -64,7 +64,8 @@ struct OseenArgs {
 // field that another workgroup of the same launch writes.
 struct CGState {
     double rz, rz_old, pAp, rr, bb, alpha, beta, thresh2;
-    int iter, maxit, done, breakdown, flexible, pad;
+    int iter, maxit, done, breakdown, flexible;
+    int run; // set by the CG residual kernel: whether it ran this iteration
 };
 
 // Partial sums of one reduction: NV sets of nblocks doubles, reduced by a
@@ -154,13 +155,17 @@ hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double
 hipError_t block3_invert(double *blocks, int64_t nn, hipStream_t s);
 hipError_t block3_apply(const double *binv, const double *x, double *y, int64_t nn, hipStream_t s);
 
-hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *z, double *p,
-                   double *q, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s);
+// x = 0, r = b, p = D^-1 b (flexible: p = 0), rz and |b|^2 into st.
+hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *p, int64_t n,
+                   double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s);
 // alpha = rz / p.Ap from the nb per-brick partials of a CG-mode apply.
 hipError_t cg_alpha(CGState *st, const RedWS *red, unsigned nb, hipStream_t s);
-hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, double *z, const double *p, double *q,
-                     int64_t n, const RedWS *red, hipStream_t s);
-hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s);
+// r -= alpha q with the partials of r.D^-1 r and r.r (dinv null: no preconditioner)
+hipError_t cg_resid(CGState *st, const double *dinv, double *r, const double *q, int64_t n, const RedWS *red,
+                    hipStream_t s);
+// beta and the convergence test from cg_resid's partials; x += alpha p, p = D^-1 r + beta p
+hipError_t cg_step(CGState *st, const double *dinv, double *x, const double *r, double *p, int64_t n,
+                   const RedWS *red, hipStream_t s);
 // Flexible-CG pieces: the preconditioner output z is supplied by the caller.
 // (r32 != null: also store r rounded to FP32, the FP32 preconditioner's input)
 hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n,

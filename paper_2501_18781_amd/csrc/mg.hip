@@ -699,7 +699,7 @@ extern "C" mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, doubl
     const HeatArgs ha = heat_args(&mg->fine_op);
     MGLevel &top = mg->L.back();
     const int ltop = (int)mg->L.size() - 1;
-    HIPCHK(c, cg_init(c->cg, b, nullptr, x, r, z, p, q, n, rtol, maxit, 1, &red, s));
+    HIPCHK(c, cg_init(c->cg, b, nullptr, x, r, p, n, rtol, maxit, 1, &red, s));
     HIPCHK(c, vfill(mg->zprev32, 0.0, n, 1, s));
     HIPCHK(c, vcvt_d2f(b, top.b, n, s)); // r = b
     HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));

@@ -9,6 +9,8 @@
 // count, convergence flag) live in device memory; kernels read them directly
 // and become no-ops once the solve is done, so the host only synchronizes to
 // poll convergence.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace mf {
@@ -17,8 +19,8 @@ constexpr int VNT = 256;   // threads per block of the vector kernels
 constexpr int VMAXB = 1024; // max blocks of a reduction kernel
 constexpr int MAXV = 32;   // max vectors in a multi-dot
 constexpr int FNT = 1024;  // threads of the single-workgroup finalize kernels
-constexpr unsigned CG_UPDATE_BLOCKS = 512;  // partials the CG direction update reduces in every block
-constexpr unsigned CG_PUPDATE_BLOCKS = 1024;
+constexpr unsigned CG_RESID_BLOCKS = 1024; // partials the CG step kernel reduces in every workgroup
+constexpr int64_t CG_STEP_BLOCKS = 2048;
 
 static unsigned vec_blocks(int64_t n)
 {
@@ -492,15 +494,27 @@ hipError_t block3_apply(const double *B, const double *x, double *y, int64_t nn,
 // CG (preconditioned with a diagonal, Saad Alg. 9.1).  One iteration is
 //   apply   q = A p, per-brick partials of p.q     (heat.hip, CG mode)
 //   alpha   alpha = rz / p.q                        (one workgroup)
-//   update  x += alpha p, r -= alpha q, z = D^-1 r, partials of r.z, r.r;
-//           iteration count, rz_old = rz
-//   pupdate every workgroup sums the update's partials in the same order:
-//           beta = r.z / rz_old, convergence test, p = z + beta p
+//   resid   r -= alpha q; partials of r.(D^-1 r) and r.r; iteration count,
+//           rz_old = rz                              (reads r, q, D^-1; writes r)
+//   step    every workgroup sums the residual partials in the same order:
+//           beta = rz / rz_old and the convergence test; then
+//           x += alpha p and (unless converged) p = D^-1 r + beta p
+//                                                    (reads x, p, r, D^-1;
+//                                                     writes x, p)
+// Ten vector passes per iteration; z = D^-1 r is formed where it is used
+// and never stored (the same products, rounded the same way, as storing it).
+// Each thread keeps CG_UNROLL elements of its grid-stride sequence in flight.
+//
+// The done flag: a kernel that reads it at entry must not write it (another
+// workgroup of the same launch could start after the write).  The step
+// kernel writes it, so it tests `run` instead, which the residual kernel
+// (an earlier launch, that only reads done) sets to whether it ran.
 // ---------------------------------------------------------------------------
+constexpr int CG_UNROLL = 4;
+
 __global__ void __launch_bounds__(VNT) cg_init_kernel(const double *__restrict__ b, const double *__restrict__ dinv,
                                                       double *__restrict__ x, double *__restrict__ r,
-                                                      double *__restrict__ z, double *__restrict__ p, int64_t n,
-                                                      int flexible, RedWS red)
+                                                      double *__restrict__ p, int64_t n, int flexible, RedWS red)
 {
     __shared__ double lds[2 * (VNT / 64)];
     double acc[2] = {0.0, 0.0};
@@ -511,7 +525,6 @@ __global__ void __launch_bounds__(VNT) cg_init_kernel(const double *__restrict__
         r[i] = bi;
         if (!flexible) {
             const double zi = dinv ? dinv[i] * bi : bi;
-            z[i] = zi;
             p[i] = zi;
             acc[0] += bi * zi;
         } else {
@@ -537,6 +550,7 @@ __global__ void __launch_bounds__(FNT) cg_init_finalize_kernel(CGState *st, cons
         st->maxit = maxit;
         st->breakdown = 0;
         st->flexible = flexible;
+        st->run = 0;
         st->alpha = 0.0;
         st->beta = 0.0;
         st->pAp = 0.0;
@@ -544,12 +558,12 @@ __global__ void __launch_bounds__(FNT) cg_init_finalize_kernel(CGState *st, cons
     }
 }
 
-hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *z, double *p,
-                   double *, int64_t n, double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s)
+hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *p, int64_t n,
+                   double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s)
 {
     const unsigned nb = vec_blocks(n);
     if (red->capacity < 2 * nb) return hipErrorInvalidValue;
-    cg_init_kernel<<<nb, VNT, 0, s>>>(b, dinv, x, r, z, p, n, flexible, *red);
+    cg_init_kernel<<<nb, VNT, 0, s>>>(b, dinv, x, r, p, n, flexible, *red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cg_init_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb, rtol, maxit, flexible);
@@ -580,31 +594,57 @@ hipError_t cg_alpha(CGState *st, const RedWS *red, unsigned nb, hipStream_t s)
     return hipGetLastError();
 }
 
-static unsigned cg_update_blocks(int64_t n)
+static unsigned cg_resid_blocks(int64_t n)
 {
-    const unsigned b = vec_blocks(n);
-    return b < CG_UPDATE_BLOCKS ? b : CG_UPDATE_BLOCKS;
+    int64_t b = (n + (int64_t)VNT * CG_UNROLL - 1) / ((int64_t)VNT * CG_UNROLL);
+    if (b < 1) b = 1;
+    return (unsigned)(b < CG_RESID_BLOCKS ? b : CG_RESID_BLOCKS);
 }
 
-__global__ void __launch_bounds__(VNT) cg_update_kernel(CGState *st, const double *__restrict__ dinv,
-                                                        double *__restrict__ x, double *__restrict__ r,
-                                                        double *__restrict__ z, const double *__restrict__ p,
-                                                        const double *__restrict__ q, int64_t n, RedWS red)
+// Grid-stride visit of [0, n) with CG_UNROLL elements per step: load(k, i)
+// for all k first, then use(k, i) in order k = 0, 1, ...
+template <typename L, typename U> __device__ __forceinline__ void grid_stride_unrolled(int64_t n, L load, U use)
+{
+    const int64_t S = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (CG_UNROLL - 1) * S < n; i += CG_UNROLL * S) {
+#pragma unroll
+        for (int k = 0; k < CG_UNROLL; ++k) load(k, i + k * S);
+#pragma unroll
+        for (int k = 0; k < CG_UNROLL; ++k) use(k, i + k * S);
+    }
+    for (; i < n; i += S) {
+        load(0, i);
+        use(0, i);
+    }
+}
+
+template <bool PC>
+__global__ void __launch_bounds__(VNT) cg_resid_kernel(CGState *st, const double *__restrict__ dinv,
+                                                       double *__restrict__ r, const double *__restrict__ q,
+                                                       int64_t n, RedWS red)
 {
     __shared__ double lds[2 * (VNT / 64)];
-    if (st->done) return;
+    const int skip = st->done;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->run = !skip; // read by the step kernel only
+    if (skip) return;
     const double alpha = st->alpha;
     double acc[2] = {0.0, 0.0};
-    GRID_STRIDE(i, n)
-    {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        const double zi = dinv ? dinv[i] * ri : ri;
-        z[i] = zi;
-        acc[0] += ri * zi;
-        acc[1] += ri * ri;
-    }
+    double rv[CG_UNROLL], qv[CG_UNROLL], dv[CG_UNROLL];
+    grid_stride_unrolled(
+        n,
+        [&](int k, int64_t i) {
+            rv[k] = r[i];
+            qv[k] = q[i];
+            if (PC) dv[k] = dinv[i];
+        },
+        [&](int k, int64_t i) {
+            const double ri = rv[k] - alpha * qv[k];
+            r[i] = ri;
+            const double zi = PC ? dv[k] * ri : ri;
+            acc[0] += ri * zi;
+            acc[1] += ri * ri;
+        });
     grid_partials<2>(acc, red, lds);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // no other workgroup of this launch reads these two fields
@@ -613,31 +653,28 @@ __global__ void __launch_bounds__(VNT) cg_update_kernel(CGState *st, const doubl
     }
 }
 
-hipError_t cg_update(CGState *st, const double *dinv, double *x, double *r, double *z, const double *p, double *q,
-                     int64_t n, const RedWS *red, hipStream_t s)
+hipError_t cg_resid(CGState *st, const double *dinv, double *r, const double *q, int64_t n, const RedWS *red,
+                    hipStream_t s)
 {
-    const unsigned nb = cg_update_blocks(n);
+    const unsigned nb = cg_resid_blocks(n);
     if (red->capacity < 2 * nb) return hipErrorInvalidValue;
-    cg_update_kernel<<<nb, VNT, 0, s>>>(st, dinv, x, r, z, p, q, n, *red);
+    if (dinv) cg_resid_kernel<true><<<nb, VNT, 0, s>>>(st, dinv, r, q, n, *red);
+    else cg_resid_kernel<false><<<nb, VNT, 0, s>>>(st, dinv, r, q, n, *red);
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(VNT) cg_pupdate_kernel(CGState *st, const double *__restrict__ partials,
-                                                         unsigned nb, const double *__restrict__ z,
-                                                         double *__restrict__ p, int64_t n)
+template <bool PC>
+__global__ void __launch_bounds__(VNT) cg_step_kernel(CGState *st, const double *__restrict__ partials, unsigned nb,
+                                                      const double *__restrict__ dinv, double *__restrict__ x,
+                                                      const double *__restrict__ r, double *__restrict__ p, int64_t n)
 {
     __shared__ double tot[2];
-    __shared__ int skip;
-    // Workgroup 0 of this launch may set done while others start: one read
-    // per workgroup keeps the decision uniform within it.
-    if (threadIdx.x == 0) skip = st->done;
-    __syncthreads();
-    if (skip) return;
+    if (!st->run) return; // this iteration's residual update was skipped (written by an earlier launch)
     wave_set_sums<2>(partials, nb, tot);
     const double rz = tot[0], rr = tot[1];
     const bool bad = !isfinite(rz) || !isfinite(rr);
     const bool stop = bad || rr <= st->thresh2 || st->iter >= st->maxit;
-    const double beta = rz / st->rz_old;
+    const double beta = rz / st->rz_old, alpha = st->alpha;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->rr = rr;
         st->rz = rz;
@@ -645,15 +682,37 @@ __global__ void __launch_bounds__(VNT) cg_pupdate_kernel(CGState *st, const doub
         if (bad) st->breakdown = 1;
         if (stop) st->done = 1;
     }
-    if (stop) return;
-    GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
+    double xv[CG_UNROLL], pv[CG_UNROLL], rv[CG_UNROLL], dv[CG_UNROLL];
+    if (stop) {
+        // the last iteration: x only
+        grid_stride_unrolled(
+            n, [&](int k, int64_t i) { xv[k] = x[i]; pv[k] = p[i]; },
+            [&](int k, int64_t i) { x[i] = xv[k] + alpha * pv[k]; });
+        return;
+    }
+    grid_stride_unrolled(
+        n,
+        [&](int k, int64_t i) {
+            xv[k] = x[i];
+            pv[k] = p[i];
+            rv[k] = r[i];
+            if (PC) dv[k] = dinv[i];
+        },
+        [&](int k, int64_t i) {
+            x[i] = xv[k] + alpha * pv[k];
+            const double zi = PC ? dv[k] * rv[k] : rv[k];
+            p[i] = zi + beta * pv[k];
+        });
 }
 
-hipError_t cg_pupdate(CGState *st, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s)
+hipError_t cg_step(CGState *st, const double *dinv, double *x, const double *r, double *p, int64_t n,
+                   const RedWS *red, hipStream_t s)
 {
-    unsigned nb = ew_blocks(n);
-    if (nb > CG_PUPDATE_BLOCKS) nb = CG_PUPDATE_BLOCKS;
-    cg_pupdate_kernel<<<nb, VNT, 0, s>>>(st, red->partials, cg_update_blocks(n), z, p, n);
+    unsigned nb = (unsigned)std::min<int64_t>(((n + (int64_t)VNT * CG_UNROLL - 1) / ((int64_t)VNT * CG_UNROLL)),
+                                              CG_STEP_BLOCKS);
+    if (nb < 1) nb = 1;
+    if (dinv) cg_step_kernel<true><<<nb, VNT, 0, s>>>(st, red->partials, cg_resid_blocks(n), dinv, x, r, p, n);
+    else cg_step_kernel<false><<<nb, VNT, 0, s>>>(st, red->partials, cg_resid_blocks(n), dinv, x, r, p, n);
     return hipGetLastError();
 }
 
@@ -670,14 +729,22 @@ __global__ void __launch_bounds__(VNT) fcg_xr_kernel(const CGState *st, double *
     if (st->done) return;
     const double alpha = st->alpha;
     double acc = 0.0;
-    GRID_STRIDE(i, n)
-    {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        if (r32) r32[i] = (float)ri; // the FP32 preconditioner's input
-        acc += ri * ri;
-    }
+    double xv[CG_UNROLL], pv[CG_UNROLL], rv[CG_UNROLL], qv[CG_UNROLL];
+    grid_stride_unrolled(
+        n,
+        [&](int k, int64_t i) {
+            xv[k] = x[i];
+            pv[k] = p[i];
+            rv[k] = r[i];
+            qv[k] = q[i];
+        },
+        [&](int k, int64_t i) {
+            x[i] = xv[k] + alpha * pv[k];
+            const double ri = rv[k] - alpha * qv[k];
+            r[i] = ri;
+            if (r32) r32[i] = (float)ri; // the FP32 preconditioner's input
+            acc += ri * ri;
+        });
     grid_partials<1>(&acc, red, lds);
 }
 
@@ -720,12 +787,19 @@ __global__ void __launch_bounds__(VNT) fcg_dir_kernel(const CGState *st, const d
     __shared__ double lds[2 * (VNT / 64)];
     if (st->done) return;
     double acc[2] = {0.0, 0.0};
-    GRID_STRIDE(i, n)
-    {
-        const double ri = r[i];
-        acc[0] += ri * (double)z[i];
-        acc[1] += ri * (double)zprev[i];
-    }
+    double rv[CG_UNROLL];
+    Z zv[CG_UNROLL], wv[CG_UNROLL];
+    grid_stride_unrolled(
+        n,
+        [&](int k, int64_t i) {
+            rv[k] = r[i];
+            zv[k] = z[i];
+            wv[k] = zprev[i];
+        },
+        [&](int k, int64_t) {
+            acc[0] += rv[k] * (double)zv[k];
+            acc[1] += rv[k] * (double)wv[k];
+        });
     grid_partials<2>(acc, red, lds);
 }
 
@@ -770,27 +844,39 @@ hipError_t fcg_dir_f32(CGState *st, const double *r, const float *z, const float
 }
 
 template <typename Z>
-__global__ void fcg_pupdate_kernel(const CGState *st, const Z *__restrict__ z, Z *__restrict__ zprev,
-                                   double *__restrict__ p, int64_t n)
+__global__ void __launch_bounds__(VNT) fcg_pupdate_kernel(const CGState *st, const Z *__restrict__ z,
+                                                          Z *__restrict__ zprev, double *__restrict__ p, int64_t n)
 {
     if (st->done) return;
     const double beta = st->beta;
-    GRID_STRIDE(i, n)
-    {
-        const Z zi = z[i];
-        p[i] = (double)zi + beta * p[i];
-        zprev[i] = zi;
-    }
+    Z zv[CG_UNROLL];
+    double pv[CG_UNROLL];
+    grid_stride_unrolled(
+        n,
+        [&](int k, int64_t i) {
+            zv[k] = z[i];
+            pv[k] = p[i];
+        },
+        [&](int k, int64_t i) {
+            p[i] = (double)zv[k] + beta * pv[k];
+            zprev[i] = zv[k];
+        });
+}
+
+static unsigned stream_blocks(int64_t n)
+{
+    const int64_t b = (n + (int64_t)VNT * CG_UNROLL - 1) / ((int64_t)VNT * CG_UNROLL);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, CG_STEP_BLOCKS));
 }
 
 hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s)
 {
-    fcg_pupdate_kernel<double><<<ew_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    fcg_pupdate_kernel<double><<<stream_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
     return hipGetLastError();
 }
 hipError_t fcg_pupdate_f32(CGState *st, const float *z, float *zprev, double *p, int64_t n, hipStream_t s)
 {
-    fcg_pupdate_kernel<float><<<ew_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    fcg_pupdate_kernel<float><<<stream_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
     return hipGetLastError();
 }
 
