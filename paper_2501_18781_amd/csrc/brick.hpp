@@ -37,6 +37,17 @@ constexpr int BNB = BP * BP * BP;   // nodes per brick
 constexpr int BFACE = BNB + 2 * BP * BP; // face-buffer slots per brick (see face_slot)
 constexpr int NXCD = 8;
 
+// LDS layout of a staged brick field: node (lx, ly, lz) at lx + R ly + R BP lz.
+// For 8-byte entries the rows are padded to R = 10: a wavefront's gather of
+// node (2tx + a, 2ty + b, 2tz + c) then spreads its stride-2 accesses over
+// more LDS banks than with R = 9 (FP64 apply kernel 30.0 -> 27.7 us at 64^3,
+// Oseen 72.6 -> 68.4 us at 48^3); 4-byte entries keep R = 9 (padding
+// measured no faster there).
+template <typename T> __host__ __device__ constexpr int lds_row() { return sizeof(T) == 8 ? BP + 1 : BP; }
+template <typename T> __host__ __device__ constexpr int lds_plane() { return lds_row<T>() * BP; }
+// LDS entries of one staged field
+template <typename T> __host__ __device__ constexpr int lds_field() { return lds_plane<T>() * BP; }
+
 __host__ __device__ inline int64_t n_bricks(const KMesh &m)
 {
     return (int64_t)((m.nx + BB - 1) / BB) * ((m.ny + BB - 1) / BB) * ((m.nz + BB - 1) / BB);
@@ -88,14 +99,18 @@ struct Brick {
         lastz = valid && tz == ncz - 1;
     }
 
-    static __device__ __forceinline__ constexpr int lds_index(int lx, int ly, int lz) { return lx + BP * (ly + BP * lz); }
-
-    // face_slot of this thread's cell node (a, b, c), whose LDS index is l.
-    __device__ __forceinline__ int fslot(int a, int b, int c, int l) const
+    template <typename T> static __device__ __forceinline__ constexpr int lds_index(int lx, int ly, int lz)
     {
-        if (a == 1) return l;
+        return lx + lds_row<T>() * ly + lds_plane<T>() * lz;
+    }
+
+    // face_slot of this thread's cell node (a, b, c).
+    __device__ __forceinline__ int fslot(int a, int b, int c) const
+    {
+        const int lex = (2 * tx + a) + BP * ((2 * ty + b) + BP * (2 * tz + c));
+        if (a == 1) return lex;
         const bool xface = a == 0 ? tx == 0 : tx == BB - 1;
-        return xface ? BNB + (a ? BP * BP : 0) + (2 * ty + b) + BP * (2 * tz + c) : l;
+        return xface ? BNB + (a ? BP * BP : 0) + (2 * ty + b) + BP * (2 * tz + c) : lex;
     }
 
     __device__ __forceinline__ int64_t cell_index(const KMesh &m) const
@@ -112,19 +127,21 @@ struct Brick {
     }
 
     // Visit the nodes this thread owns: f(a, b, c, lds_index, global_index,
-    // constrained, shared), with a, b, c compile-time constants.  `shared` is
+    // constrained, shared), with a, b, c compile-time constants and
+    // lds_index in the layout of a staged field of T.  `shared` is
     // an int: bit 0 set if a neighbouring brick also touches the node, bit 1
     // if that happens through one of this brick's high faces (the node is
     // then finished by another brick's combine pass).  The eight
     // low nodes of every valid cell come first; the high faces, owned by the
     // last cells, follow in seven groups that each test one uniform flag.
-    template <typename F> __device__ __forceinline__ void for_owned_nodes(const KMesh &m, F f) const
+    template <typename T = double, typename F> __device__ __forceinline__ void for_owned_nodes(const KMesh &m, F f) const
     {
+        constexpr int R = lds_row<T>(), P = lds_plane<T>();
         if (!valid) return;
         const int gx0 = 2 * (c0x + tx), gy0 = 2 * (c0y + ty), gz0 = 2 * (c0z + tz);
         const int64_t g0 = node_index(m, gx0, gy0, gz0);
         const int64_t sy = m.NX, sz = (int64_t)m.NX * m.NY;
-        const int l0 = lds_index(2 * tx, 2 * ty, 2 * tz);
+        const int l0 = lds_index<T>(2 * tx, 2 * ty, 2 * tz);
         // Per direction, for local index 0 and 2 (index 1 is never on a
         // boundary or a brick face): Dirichlet flag and shared-face flag.
         const unsigned f6 = m.dirichlet;
@@ -140,7 +157,7 @@ struct Brick {
                                      (c == 0 && dz0) || (c == 2 && dz2);
             const bool shared_hi = (a == 2 && sx2) || (b == 2 && sy2) || (c == 2 && sz2);
             const bool shared = shared_hi || (a == 0 && sx0) || (b == 0 && sy0) || (c == 0 && sz0);
-            f(a, b, c, l0 + a + BP * b + BP * BP * c, g0 + a + sy * b + sz * c, constrained,
+            f(a, b, c, l0 + a + R * b + P * c, g0 + a + sy * b + sz * c, constrained,
               (shared ? 1 : 0) | (shared_hi ? 2 : 0));
         };
         using I0 = std::integral_constant<int, 0>;
@@ -195,7 +212,10 @@ struct Brick {
     {
         return valid ? nodal_vo<T>(m) : 0u;
     }
-    __device__ __forceinline__ int stage_l0() const { return valid ? lds_index(2 * tx, 2 * ty, 2 * tz) : 0; }
+    template <typename T> __device__ __forceinline__ int stage_l0() const
+    {
+        return valid ? lds_index<T>(2 * tx, 2 * ty, 2 * tz) : 0;
+    }
 
     // Stage a nodal field into LDS; Dirichlet nodes read as zero if mask.
     template <typename T>
@@ -203,7 +223,8 @@ struct Brick {
     {
         const __amdgpu_buffer_rsrc_t r = nodal_rsrc(m, g);
         const unsigned vo = stage_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
-        const int l0 = stage_l0();
+        const int l0 = stage_l0<T>();
+        constexpr int R = lds_row<T>(), P = lds_plane<T>();
         const unsigned f6 = mask ? m.dirichlet : 0u;
         const int gx0 = 2 * (c0x + (valid ? tx : 0)), gy0 = 2 * (c0y + (valid ? ty : 0)),
                   gz0 = 2 * (c0z + (valid ? tz : 0));
@@ -226,7 +247,7 @@ struct Brick {
                 for (int a = 0; a < 3; ++a) {
                     const bool k = (a == 0 && dx0) || (a == 2 && dx2) || (b == 0 && dy0) || (b == 2 && dy2) ||
                                    (c == 0 && dz0) || (c == 2 && dz2);
-                    lds[l0 + a + BP * b + BP * BP * c] = k ? T(0) : v[a + 3 * b + 9 * c];
+                    lds[l0 + a + R * b + P * c] = k ? T(0) : v[a + 3 * b + 9 * c];
                 }
     }
 
@@ -238,7 +259,8 @@ struct Brick {
     {
         const __amdgpu_buffer_rsrc_t r0 = nodal_rsrc(m, g0), r1 = nodal_rsrc(m, NF == 2 ? g1 : g0);
         const unsigned vo = stage_vo<T>(m), sy = (unsigned)sizeof(T) * (unsigned)m.NX, sz = sy * (unsigned)m.NY;
-        const int l0 = stage_l0();
+        const int l0 = stage_l0<T>();
+        constexpr int R = lds_row<T>(), P = lds_plane<T>();
         T v0[27], v1[27];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -256,7 +278,7 @@ struct Brick {
             for (int b = 0; b < 3; ++b)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const int l = l0 + a + BP * b + BP * BP * c;
+                    const int l = l0 + a + R * b + P * c;
                     l0s[l] = v0[a + 3 * b + 9 * c];
                     if constexpr (NF == 2) l1s[l] = v1[a + 3 * b + 9 * c];
                 }
@@ -298,13 +320,14 @@ struct Brick {
     // The cell's 27 nodal values from LDS (zero for threads without a cell).
     template <typename T> __device__ __forceinline__ void gather27(const T *lds, T *v) const
     {
-        const int l0 = valid ? lds_index(2 * tx, 2 * ty, 2 * tz) : 0;
+        const int l0 = valid ? lds_index<T>(2 * tx, 2 * ty, 2 * tz) : 0;
+        constexpr int R = lds_row<T>(), P = lds_plane<T>();
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int b = 0; b < 3; ++b)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) v[a + 3 * b + 9 * c] = lds[l0 + a + BP * b + BP * BP * c];
+                for (int a = 0; a < 3; ++a) v[a + 3 * b + 9 * c] = lds[l0 + a + R * b + P * c];
     }
 
     // Cell results, node-major: E[local * BNT + thread].  A thread without a

@@ -323,8 +323,9 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     // the second region takes phi (with one velocity component at a time, or
     // the frozen temperature), then the z exchange of the node sums (for the
     // transposed convective form, the cell results).
-    constexpr int STAGE = CONV == 2 ? 27 * BNT : ((CONV || MODE == 2) ? 2 * BNB : BNB);
-    constexpr int LDS_T = BNB + STAGE;
+    constexpr int NB = lds_field<T>(); // one staged field
+    constexpr int STAGE = CONV == 2 ? 27 * BNT : ((CONV || MODE == 2) ? 2 * NB : NB);
+    constexpr int LDS_T = NB + STAGE;
     __shared__ T lds[LDS_T];
     __shared__ double red_lds[BNT];
     if (CG) {
@@ -332,10 +333,10 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     }
     const Brick br(m, threadIdx.x);
     T *xs = lds;
-    T *ps = lds + BNB;
+    T *ps = lds + NB;
     if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
     else br.load_fields(m, x, xs);
-    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + BNB, false);
+    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + NB, false);
     __syncthreads();
 
     const T vol = T(m.hx * m.hy * m.hz);
@@ -345,7 +346,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     T u[27];
     if constexpr (CONV != 0) {
         br.gather27_dirichlet(m, xs, u);
-        heat_conv_cell_apply<CONV == 2, HK, ISO>(br, m, a, ps, ps + BNB, u);
+        heat_conv_cell_apply<CONV == 2, HK, ISO>(br, m, a, ps, ps + NB, u);
     } else {
         // With equal cell edges (ISO) 1/h^2 and the 1/4 of D'' = 2 D' go into
         // the stiffness weights, and the derivative passes take the integer
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         const T akw = ISO ? ak_w * ihx * T(0.25) : ak_w;
         T cm[27], ck[27];
         if constexpr (MODE == 2) {
-            heat_cell_coeffs3<HK>(br, m, a, (const double *)ps, (const double *)ps + BNB, cm, ck,
+            heat_cell_coeffs3<HK>(br, m, a, (const double *)ps, (const double *)ps + NB, cm, ck,
                                   ISO ? double(ihx) * 0.25 : 1.0);
         } else if (MODE == 0) {
             T ph[27];
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
         T *E = ps;
         br.store_cell(E, u);
         __syncthreads();
-        br.for_owned_nodes(m, [&](int ai, int bi, int ci, int, int64_t, bool, int) {
+        br.template for_owned_nodes<T>(m, [&](int ai, int bi, int ci, int, int64_t, bool, int) {
             u[ai + 3 * bi + 9 * ci] = br.node_sum(E, ai, bi, ci);
         });
     } else {
@@ -390,10 +391,10 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     // finishes it.
     double energy = 0.0;
     T *fb = face + (int64_t)br.brick * BFACE;
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
+    br.template for_owned_nodes<T>(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
         const T xv = xs[l], s = u[ai + 3 * bi + 9 * ci];
         if (CG) energy += constrained ? ((sh & 2) ? 0.0 : (double)xv * (double)xv) : (double)xv * (double)s;
-        T *dst = sh ? fb + br.fslot(ai, bi, ci, l) : y + g;
+        T *dst = sh ? fb + br.fslot(ai, bi, ci) : y + g;
         *dst = constrained ? xv : s;
     });
     if (CG) {
@@ -573,7 +574,7 @@ __device__ __forceinline__ void heat_cell_conv_diag(const Brick &br, const KMesh
     double w[27], t[27], v[27];
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
-        br.gather27(us + dir * BNB, w);
+        br.gather27(us + dir * lds_field<double>(), w);
         interp3(w);
         const double sc = ac / h[dir];
 #pragma unroll
@@ -590,15 +591,16 @@ template <typename T, int MODE, int HK, bool CONV = false>
 __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag, T *__restrict__ face)
 {
     static_assert(!CONV || (std::is_same<T, double>::value && MODE == 0), "convective form: FP64 only");
-    constexpr int STAGE = CONV ? 4 * BNB : BNB;
+    constexpr int NB = lds_field<T>(); // one staged field
+    constexpr int STAGE = CONV ? 4 * NB : NB;
     constexpr int LDS_T = (STAGE > 27 * BNT ? STAGE : 27 * BNT);
     __shared__ T lds[LDS_T];
     const Brick br(m, threadIdx.x);
     if (MODE != 1) br.load(m, (const T *)a.phi, lds, false);
-    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, lds + BNB, false);
+    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, lds + NB, false);
     if constexpr (CONV) {
         const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-        for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, lds + (c + 1) * BNB, false);
+        for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, lds + (c + 1) * NB, false);
     }
     __syncthreads();
     const T vol = T(m.hx * m.hy * m.hz);
@@ -606,7 +608,7 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     const T ihx = T(1.0 / (m.hx * m.hx)), ihy = T(1.0 / (m.hy * m.hy)), ihz = T(1.0 / (m.hz * m.hz));
     T cm[27], ck[27];
     if constexpr (MODE == 2) {
-        heat_cell_coeffs3<HK>(br, m, a, (const double *)lds, (const double *)lds + BNB, cm, ck);
+        heat_cell_coeffs3<HK>(br, m, a, (const double *)lds, (const double *)lds + NB, cm, ck);
         // heat_cell_diag takes the stiffness factor for the true derivatives (no 1/r^2)
 #pragma unroll
         for (int q = 0; q < 27; ++q) ck[q] *= kR * kR;
@@ -627,7 +629,7 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
 #pragma unroll
         for (int q = 0; q < 27; ++q) md[q] = T(a.am) * cm[q];
         heat_cell_diag<T>(md, ck, ihx, ihy, ihz, d);
-        heat_cell_conv_diag(br, m, (const double *)lds + BNB, (const double *)cm, a.ac, (double *)d);
+        heat_cell_conv_diag(br, m, (const double *)lds + NB, (const double *)cm, a.ac, (double *)d);
     } else {
         heat_cell_diag<T>(cm, ck, ihx, ihy, ihz, d);
     }
@@ -635,9 +637,9 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     br.store_cell(lds, d);
     __syncthreads();
     T *fb = face + (int64_t)br.brick * BFACE;
-    br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
+    br.template for_owned_nodes<T>(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, int sh) {
         const T v = br.node_sum(lds, ai, bi, ci);
-        if (sh) fb[br.fslot(ai, bi, ci, l)] = v; // constrained ones: 1 in the combine
+        if (sh) fb[br.fslot(ai, bi, ci)] = v; // constrained ones: 1 in the combine
         else diag[g] = constrained ? T(1) : v;
     });
 }
@@ -696,7 +698,8 @@ template <int HK>
 __global__ void __launch_bounds__(BNT) heat_cg_brick_kernel(KMesh m, HeatArgs a, const float *__restrict__ b32,
                                                             float *__restrict__ x32, double rtol, int maxit)
 {
-    __shared__ double X[BNB], R[BNB], P[BNB], Q[BNB], S[BNB], Dv[BNB];
+    constexpr int NB = lds_field<double>();
+    __shared__ double X[NB], R[NB], P[NB], Q[NB], S[NB], Dv[NB];
     __shared__ double E[27 * BNT];
     const Brick br(m, threadIdx.x);
     br.load(m, (const double *)a.phi, S, false);
@@ -857,10 +860,11 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
                                                         double *__restrict__ dphi, double *__restrict__ face)
 {
     constexpr int NF = 4;
-    constexpr int LDS_T = (NF * BNB > 27 * BNT ? NF * BNB : 27 * BNT);
+    constexpr int NB = lds_field<double>();
+    constexpr int LDS_T = (NF * NB > 27 * BNT ? NF * NB : 27 * BNT);
     __shared__ double lds[LDS_T];
     const Brick br(m, threadIdx.x);
-    double *Ts = lds, *dTs = lds + BNB, *ls = lds + 2 * BNB, *ps = lds + 3 * BNB;
+    double *Ts = lds, *dTs = lds + NB, *ls = lds + 2 * NB, *ps = lds + 3 * NB;
     br.load(m, T, Ts, false);
     br.load(m, dT, dTs, false);
     br.load(m, lam, ls, false);
@@ -925,7 +929,7 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
     double *fb = face + (int64_t)br.brick * BFACE;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double v = br.node_sum(lds, ai, bi, ci);
-        if (sh) fb[br.fslot(ai, bi, ci, l)] = v;
+        if (sh) fb[br.fslot(ai, bi, ci)] = v;
         else dphi[g] = v;
     });
 }

@@ -26,6 +26,7 @@
 namespace mf {
 
 constexpr int ONT = 3 * BNT; // threads per Oseen brick
+constexpr int NB = lds_field<double>(); // LDS entries of one staged nodal field
 
 // Heaviside of the interpolated level set at the 27 Gauss points (in place).
 template <int HK> __device__ __forceinline__ void heaviside27(const OseenArgs &a, double *ph)
@@ -112,7 +113,7 @@ template <int C, int HK, bool TP>
 __device__ __forceinline__ void oseen_phase1(const Brick &br, const OseenArgs &a, const KMesh &m, const double *stage,
                                              double *rwl, double *nul, double *u, double *w0, double *acc)
 {
-    const double *ps = stage, *us = stage + BNB, *u0s = stage + 4 * BNB, *tcs = stage + 7 * BNB;
+    const double *ps = stage, *us = stage + NB, *u0s = stage + 4 * NB, *tcs = stage + 7 * NB;
     const double vol = m.hx * m.hy * m.hz;
     const int t = br.t;
     double h[27];
@@ -151,7 +152,7 @@ __device__ __forceinline__ void oseen_phase1(const Brick &br, const OseenArgs &a
         }
     }
     if constexpr (TP) pin27(acc);
-    br.gather27(us + C * BNB, u);
+    br.gather27(us + C * NB, u);
     interp3(u);
     if constexpr (TP) {
 #pragma unroll
@@ -159,7 +160,7 @@ __device__ __forceinline__ void oseen_phase1(const Brick &br, const OseenArgs &a
         pin27(acc);
     }
     pin27(u);
-    br.gather27(u0s + C * BNB, w0);
+    br.gather27(u0s + C * NB, w0);
     interp3(w0);
 }
 
@@ -256,18 +257,18 @@ template <int HK, bool TR, bool TP>
 __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, const double *__restrict__ x,
                                                           double *__restrict__ y, double *__restrict__ face)
 {
-    constexpr int STAGE = (TP ? 8 : 7) * BNB, GAUSS3 = 3 * GQ;
+    constexpr int STAGE = (TP ? 8 : 7) * NB, GAUSS3 = 3 * GQ;
     constexpr int AREG = STAGE > GAUSS3 ? STAGE : GAUSS3;
     __shared__ double lds[AREG + 2 * GQ];
     double *A = lds, *rwl = lds + AREG, *nul = rwl + GQ;
     const int comp = threadIdx.x / BNT; // uniform over a wavefront
     const Brick br(m, threadIdx.x % BNT);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    double *ps = A, *us = A + BNB, *u0s = A + 4 * BNB, *tcs = A + 7 * BNB;
+    double *ps = A, *us = A + NB, *u0s = A + 4 * NB, *tcs = A + 7 * NB;
     if (comp == 0) br.load(m, a.phi, ps, false);
     if (TP && comp == 1) br.load(m, a.tc, tcs, false);
-    br.load(m, x + comp * nn, us + comp * BNB, true);
-    br.load(m, a.u0 + comp * nn, u0s + comp * BNB, false);
+    br.load(m, x + comp * nn, us + comp * NB, true);
+    br.load(m, a.u0 + comp * nn, u0s + comp * NB, false);
     __syncthreads();
     double u[27], acc[27];
     {
@@ -297,7 +298,7 @@ __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     const double *xc = x + comp * nn;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool, int sh) {
         const double s = acc[ai + 3 * bi + 9 * ci];
-        double *dst = sh ? fb + br.fslot(ai, bi, ci, l) : yc + g;
+        double *dst = sh ? fb + br.fslot(ai, bi, ci) : yc + g;
         *dst = s;
     });
     if (br.touches_dirichlet(m)) {
@@ -358,14 +359,14 @@ template <int HK, bool TP>
 __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, double *__restrict__ blocks,
                                                           double *__restrict__ face)
 {
-    constexpr int STAGE = (TP ? 5 : 4) * BNB, CONTRIB = 27 * BNT;
+    constexpr int STAGE = (TP ? 5 : 4) * NB, CONTRIB = 27 * BNT;
     __shared__ double lds[STAGE > CONTRIB ? STAGE : CONTRIB];
     __shared__ double E[27 * BNT];
     const Brick br(m, threadIdx.x);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    double *ps = lds, *u0s = lds + BNB, *tcs = lds + 4 * BNB;
+    double *ps = lds, *u0s = lds + NB, *tcs = lds + 4 * NB;
     br.load(m, a.phi, ps, false);
-    for (int c = 0; c < 3; ++c) br.load(m, a.u0 + c * nn, u0s + c * BNB, false);
+    for (int c = 0; c < 3; ++c) br.load(m, a.u0 + c * nn, u0s + c * NB, false);
     if (TP) br.load(m, a.tc, tcs, false);
     __syncthreads();
     const double vol = m.hx * m.hy * m.hz;
@@ -422,7 +423,7 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
     contract3(w0, S2, S2, S2, base);
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
-        br.gather27(u0s + dir * BNB, w0);
+        br.gather27(u0s + dir * NB, w0);
         interp3(w0);
 #pragma unroll
         for (int q = 0; q < 27; ++q) w0[q] *= a.ac * rw[q] * ih[dir];
@@ -457,7 +458,7 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
         br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
             double *B = blocks + 9 * g;
             if (sh) {
-                fb[br.fslot(ai, bi, ci, l)] = br.node_sum(E, ai, bi, ci); // Dirichlet ones: identity in the combine
+                fb[br.fslot(ai, bi, ci)] = br.node_sum(E, ai, bi, ci); // Dirichlet ones: identity in the combine
             } else if (constrained) {
                 B[3 * c + cp] = (c == cp) ? 1.0 : 0.0;
                 B[3 * cp + c] = (c == cp) ? 1.0 : 0.0;

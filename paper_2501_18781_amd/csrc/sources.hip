@@ -19,15 +19,17 @@
 
 namespace mf {
 
+constexpr int NB = lds_field<double>(); // LDS entries of one staged nodal field
+
 template <int HK>
 __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, SourceArgs sa,
                                                           const double *__restrict__ T, double *__restrict__ b,
                                                           double *__restrict__ face)
 {
-    constexpr int LDS_T = 2 * BNB > 9 * BNT ? 2 * BNB : 9 * BNT; // phi and T; then the node-sum exchange
+    constexpr int LDS_T = 2 * NB > 9 * BNT ? 2 * NB : 9 * BNT; // phi and T; then the node-sum exchange
     __shared__ double lds[LDS_T];
     const Brick br(m, threadIdx.x);
-    double *ps = lds, *ts = lds + BNB;
+    double *ps = lds, *ts = lds + NB;
     br.load_fields(m, (const double *)a.phi, ps, T, ts);
     __syncthreads();
 
@@ -115,7 +117,7 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
     double *fb = face + (int64_t)br.brick * BFACE;
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
         const double v = ph[ai + 3 * bi + 9 * ci];
-        if (sh) fb[br.fslot(ai, bi, ci, l)] = v; // constrained ones: 0 in the combine
+        if (sh) fb[br.fslot(ai, bi, ci)] = v; // constrained ones: 0 in the combine
         else b[g] = constrained ? 0.0 : v;
     });
 }
