@@ -3,9 +3,10 @@
 // A 64-thread workgroup (one wavefront) owns a brick of 4x4x4 cells, one
 // thread per cell; the brick's 9x9x9 Q2 nodes are staged in LDS.
 //
-// Staging is per cell: each thread reads the 27 nodes of its cell and
-// writes them to LDS (nodes shared by cells of the brick are written with
-// the same value by each).  Finishing is by ownership: a cell owns its
+// Staging is per cell (each thread reads the 27 nodes of its cell and
+// writes them to LDS; nodes shared by cells of the brick are written with
+// the same value by each) or per node (each lane stages every 64th node of
+// the brick; used by the FP64 heat apply).  Finishing is by ownership: a cell owns its
 // local nodes (a, b, c) with a, b, c in {0, 1}, and the last valid cell of
 // the brick in a direction also owns the local nodes with index 2 in that
 // direction, so every brick node is finished by exactly one thread, with
@@ -283,6 +284,44 @@ struct Brick {
                     if constexpr (NF == 2) l1s[l] = v1[a + 3 * b + 9 * c];
                 }
     }
+    // Node-parallel staging of NF (1 or 2) unmasked fields: lane t reads brick
+    // nodes t, t + 64, ... (at most 12 per lane), each node once, clipped to
+    // the brick's valid node range, all reads before the first LDS write.
+    // Node n = lx + 9 ly + 81 lz splits by a multiply-shift division by 9
+    // (exact for n < 768).  For FP64 fields this beats the per-cell staging
+    // (apply kernel 27.7 -> 26.4 us at 64^3); FP32 fields keep the per-cell
+    // form, whose paired reads do better there.
+    template <int NF, typename T>
+    __device__ __forceinline__ void stage_nodes(const KMesh &m, const T *__restrict__ g0, T *l0s,
+                                                const T *__restrict__ g1, T *l1s) const
+    {
+        constexpr int R = lds_row<T>(), P = lds_plane<T>();
+        constexpr int K = (BNB + BNT - 1) / BNT;
+        const __amdgpu_buffer_rsrc_t r0 = nodal_rsrc(m, g0), r1 = nodal_rsrc(m, NF == 2 ? g1 : g0);
+        const unsigned nxn = 2 * ncx + 1, nyn = 2 * ncy + 1, nzn = 2 * ncz + 1;
+        const unsigned NX = m.NX, NXY = (unsigned)m.NX * m.NY;
+        T v0[K], v1[K];
+        int lo[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const unsigned n = (unsigned)t + (unsigned)BNT * k;
+            const unsigned q1 = (n * 7282u) >> 16, lx = n - 9u * q1;
+            const unsigned q2 = (q1 * 7282u) >> 16, ly = q1 - 9u * q2, lz = q2;
+            const bool ok = n < (unsigned)BNB && lx < nxn && ly < nyn && lz < nzn;
+            const unsigned vofs = ok ? (unsigned)sizeof(T) * (lx + NX * ly + NXY * lz) : 0u;
+            lo[k] = ok ? (int)(lx + R * ly + P * lz) : -1;
+            v0[k] = nodal_load<T>(r0, vofs, 0);
+            if constexpr (NF == 2) v1[k] = nodal_load<T>(r1, vofs, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (lo[k] >= 0) {
+                l0s[lo[k]] = v0[k];
+                if constexpr (NF == 2) l1s[lo[k]] = v1[k];
+            }
+        }
+    }
+
     template <typename T> __device__ __forceinline__ void load_fields(const KMesh &m, const T *g0, T *l0s) const
     {
         stage_fields<1, T>(m, g0, l0s, nullptr, nullptr);

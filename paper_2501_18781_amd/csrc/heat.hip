@@ -11,8 +11,9 @@
 //
 // Work decomposition (brick.hpp): one 64-thread workgroup (one wavefront)
 // per brick of 4x4x4 cells, one thread per cell.
-//   1. the brick's nodal x (Dirichlet nodes read as zero) and phi are staged
-//      in LDS, every node loaded by the one cell that owns it;
+//   1. the brick's nodal x and phi are staged in LDS (FP64: each node read
+//      once, node-parallel over the wavefront; FP32: each cell reads its 27
+//      nodes); Dirichlet columns read as zero when x is gathered;
 //   2. each thread evaluates its cell entirely in registers by sum
 //      factorization (3x3 contractions along one direction at a time,
 //      collocation derivatives at the Gauss points, one 3-point line at a
@@ -334,8 +335,13 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     const Brick br(m, threadIdx.x);
     T *xs = lds;
     T *ps = lds + NB;
-    if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
-    else br.load_fields(m, x, xs);
+    if constexpr (sizeof(T) == 8) {
+        if (MODE != 1) br.template stage_nodes<2, T>(m, x, xs, (const T *)a.phi, ps);
+        else br.template stage_nodes<1, T>(m, x, xs, nullptr, nullptr);
+    } else {
+        if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
+        else br.load_fields(m, x, xs);
+    }
     if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + NB, false);
     __syncthreads();
 
