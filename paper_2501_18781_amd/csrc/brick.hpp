@@ -322,6 +322,46 @@ struct Brick {
         }
     }
 
+    // Node-parallel staging over a workgroup of NT threads (tid = the thread's
+    // index in it): NF FP64 fields, field f read from src[f] into the LDS
+    // region dst[f]; a field with bit f of maskbits set reads its Dirichlet
+    // nodes as zero.  Each brick node is read once per field; all reads are
+    // issued before the first LDS write.
+    template <int NT, int NF>
+    __device__ __forceinline__ void stage_nodes_wg(const KMesh &m, int tid, const double *const (&src)[NF],
+                                                   double *const (&dst)[NF], unsigned maskbits) const
+    {
+        constexpr int R = lds_row<double>(), P = lds_plane<double>();
+        constexpr int K = (BNB + NT - 1) / NT;
+        __amdgpu_buffer_rsrc_t rs[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) rs[f] = nodal_rsrc(m, src[f]);
+        const unsigned nxn = 2 * ncx + 1, nyn = 2 * ncy + 1, nzn = 2 * ncz + 1;
+        const unsigned NX = m.NX, NXY = (unsigned)m.NX * m.NY;
+        double v[K][NF];
+        int lo[K];
+        bool con[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const unsigned n = (unsigned)tid + (unsigned)NT * k;
+            const unsigned q1 = (n * 7282u) >> 16, lx = n - 9u * q1;
+            const unsigned q2 = (q1 * 7282u) >> 16, ly = q1 - 9u * q2, lz = q2;
+            const bool ok = n < (unsigned)BNB && lx < nxn && ly < nyn && lz < nzn;
+            const unsigned vofs = ok ? 8u * (lx + NX * ly + NXY * lz) : 0u;
+            lo[k] = ok ? (int)(lx + R * ly + P * lz) : -1;
+            con[k] = ok && node_constrained(m, 2 * c0x + (int)lx, 2 * c0y + (int)ly, 2 * c0z + (int)lz);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[k][f] = nodal_load<double>(rs[f], vofs, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (lo[k] >= 0) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) dst[f][lo[k]] = ((maskbits >> f) & 1u) && con[k] ? 0.0 : v[k][f];
+            }
+        }
+    }
+
     template <typename T> __device__ __forceinline__ void load_fields(const KMesh &m, const T *g0, T *l0s) const
     {
         stage_fields<1, T>(m, g0, l0s, nullptr, nullptr);

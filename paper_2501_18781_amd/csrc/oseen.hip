@@ -265,10 +265,15 @@ __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     const Brick br(m, threadIdx.x % BNT);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
     double *ps = A, *us = A + NB, *u0s = A + 4 * NB, *tcs = A + 7 * NB;
-    if (comp == 0) br.load(m, a.phi, ps, false);
-    if (TP && comp == 1) br.load(m, a.tc, tcs, false);
-    br.load(m, x + comp * nn, us + comp * NB, true);
-    br.load(m, a.u0 + comp * nn, u0s + comp * NB, false);
+    if constexpr (TP) {
+        const double *src[8] = {a.phi, x, x + nn, x + 2 * nn, a.u0, a.u0 + nn, a.u0 + 2 * nn, a.tc};
+        double *const dst[8] = {ps, us, us + NB, us + 2 * NB, u0s, u0s + NB, u0s + 2 * NB, tcs};
+        br.stage_nodes_wg<ONT, 8>(m, threadIdx.x, src, dst, 0xEu);
+    } else {
+        const double *src[7] = {a.phi, x, x + nn, x + 2 * nn, a.u0, a.u0 + nn, a.u0 + 2 * nn};
+        double *const dst[7] = {ps, us, us + NB, us + 2 * NB, u0s, u0s + NB, u0s + 2 * NB};
+        br.stage_nodes_wg<ONT, 7>(m, threadIdx.x, src, dst, 0xEu);
+    }
     __syncthreads();
     double u[27], acc[27];
     {
