@@ -304,7 +304,8 @@ struct Brick {
         int lo[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const unsigned n = (unsigned)t + (unsigned)BNT * k;
+            unsigned n = (unsigned)t + (unsigned)BNT * k;
+            asm volatile("" : "+v"(n)); // decoded per call: not kept live across stagings
             const unsigned q1 = (n * 7282u) >> 16, lx = n - 9u * q1;
             const unsigned q2 = (q1 * 7282u) >> 16, ly = q1 - 9u * q2, lz = q2;
             const bool ok = n < (unsigned)BNB && lx < nxn && ly < nyn && lz < nzn;
@@ -343,7 +344,8 @@ struct Brick {
         bool con[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const unsigned n = (unsigned)tid + (unsigned)NT * k;
+            unsigned n = (unsigned)tid + (unsigned)NT * k;
+            asm volatile("" : "+v"(n)); // decoded per call: not kept live across stagings
             const unsigned q1 = (n * 7282u) >> 16, lx = n - 9u * q1;
             const unsigned q2 = (q1 * 7282u) >> 16, ly = q1 - 9u * q2, lz = q2;
             const bool ok = n < (unsigned)BNB && lx < nxn && ly < nyn && lz < nzn;

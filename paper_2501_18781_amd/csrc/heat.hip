@@ -242,7 +242,7 @@ __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMes
         pin27(acc);
         pin27(u);
         __syncthreads(); // every thread is done with the previous component
-        br.load(m, a.u0 + d * nn, vs, false);
+        br.stage_nodes<1, double>(m, a.u0 + d * nn, vs, nullptr, nullptr);
         __syncthreads();
         br.gather27(vs, v);
         interp3(v);
@@ -335,14 +335,21 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     const Brick br(m, threadIdx.x);
     T *xs = lds;
     T *ps = lds + NB;
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (MODE == 2) {
+        if (a.tc) {
+            const double *src[3] = {(const double *)x, (const double *)a.phi, (const double *)a.tc};
+            double *const dst[3] = {(double *)xs, (double *)ps, (double *)ps + NB};
+            br.stage_nodes_wg<BNT, 3>(m, threadIdx.x, src, dst, 0u);
+        } else {
+            br.template stage_nodes<2, T>(m, x, xs, (const T *)a.phi, ps);
+        }
+    } else if constexpr (sizeof(T) == 8) {
         if (MODE != 1) br.template stage_nodes<2, T>(m, x, xs, (const T *)a.phi, ps);
         else br.template stage_nodes<1, T>(m, x, xs, nullptr, nullptr);
     } else {
         if (MODE != 1) br.load_fields(m, x, xs, (const T *)a.phi, ps);
         else br.load_fields(m, x, xs);
     }
-    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, ps + NB, false);
     __syncthreads();
 
     const T vol = T(m.hx * m.hy * m.hz);
@@ -602,11 +609,18 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     constexpr int LDS_T = (STAGE > 27 * BNT ? STAGE : 27 * BNT);
     __shared__ T lds[LDS_T];
     const Brick br(m, threadIdx.x);
-    if (MODE != 1) br.load(m, (const T *)a.phi, lds, false);
-    if (MODE == 2 && a.tc) br.load(m, (const T *)a.tc, lds + NB, false);
     if constexpr (CONV) {
         const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-        for (int c = 0; c < 3; ++c) br.load(m, (const T *)a.u0 + c * nn, lds + (c + 1) * NB, false);
+        const double *u0 = (const double *)a.u0;
+        const double *src[4] = {(const double *)a.phi, u0, u0 + nn, u0 + 2 * nn};
+        double *const dst[4] = {(double *)lds, (double *)lds + NB, (double *)lds + 2 * NB, (double *)lds + 3 * NB};
+        br.stage_nodes_wg<BNT, 4>(m, threadIdx.x, src, dst, 0u);
+    } else if constexpr (MODE == 2) {
+        if (a.tc) br.template stage_nodes<2, T>(m, (const T *)a.phi, lds, (const T *)a.tc, lds + NB);
+        else br.template stage_nodes<1, T>(m, (const T *)a.phi, lds, nullptr, nullptr);
+    } else if constexpr (MODE != 1) {
+        if constexpr (sizeof(T) == 8) br.template stage_nodes<1, T>(m, (const T *)a.phi, lds, nullptr, nullptr);
+        else br.load(m, (const T *)a.phi, lds, false);
     }
     __syncthreads();
     const T vol = T(m.hx * m.hy * m.hz);
@@ -708,7 +722,7 @@ __global__ void __launch_bounds__(BNT) heat_cg_brick_kernel(KMesh m, HeatArgs a,
     __shared__ double X[NB], R[NB], P[NB], Q[NB], S[NB], Dv[NB];
     __shared__ double E[27 * BNT];
     const Brick br(m, threadIdx.x);
-    br.load(m, (const double *)a.phi, S, false);
+    br.stage_nodes<1, double>(m, (const double *)a.phi, S, nullptr, nullptr);
     __syncthreads();
     const double vol = m.hx * m.hy * m.hz;
     const double am_w = a.am * vol, ak_w = a.ak * vol / (kR * kR);
@@ -871,11 +885,16 @@ __global__ void __launch_bounds__(BNT) heat_grad_kernel(KMesh m, HeatArgs a, con
     __shared__ double lds[LDS_T];
     const Brick br(m, threadIdx.x);
     double *Ts = lds, *dTs = lds + NB, *ls = lds + 2 * NB, *ps = lds + 3 * NB;
-    br.load(m, T, Ts, false);
-    br.load(m, dT, dTs, false);
-    br.load(m, lam, ls, false);
     const bool with_phi = (a.mode == 0) && dphi != nullptr;
-    if (with_phi) br.load(m, (const double *)a.phi, ps, false);
+    if (with_phi) {
+        const double *src[4] = {T, dT, lam, (const double *)a.phi};
+        double *const dst[4] = {Ts, dTs, ls, ps};
+        br.stage_nodes_wg<BNT, 4>(m, threadIdx.x, src, dst, 0u);
+    } else {
+        const double *src[3] = {T, dT, lam};
+        double *const dst[3] = {Ts, dTs, ls};
+        br.stage_nodes_wg<BNT, 3>(m, threadIdx.x, src, dst, 0u);
+    }
     __syncthreads();
     const int64_t cell = br.valid ? br.cell_index(m) : 0;
     const double vol = m.hx * m.hy * m.hz;

@@ -370,9 +370,15 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
     const Brick br(m, threadIdx.x);
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
     double *ps = lds, *u0s = lds + NB, *tcs = lds + 4 * NB;
-    br.load(m, a.phi, ps, false);
-    for (int c = 0; c < 3; ++c) br.load(m, a.u0 + c * nn, u0s + c * NB, false);
-    if (TP) br.load(m, a.tc, tcs, false);
+    if constexpr (TP) {
+        const double *src[5] = {a.phi, a.u0, a.u0 + nn, a.u0 + 2 * nn, a.tc};
+        double *const dst[5] = {ps, u0s, u0s + NB, u0s + 2 * NB, tcs};
+        br.stage_nodes_wg<BNT, 5>(m, threadIdx.x, src, dst, 0u);
+    } else {
+        const double *src[4] = {a.phi, a.u0, a.u0 + nn, a.u0 + 2 * nn};
+        double *const dst[4] = {ps, u0s, u0s + NB, u0s + 2 * NB};
+        br.stage_nodes_wg<BNT, 4>(m, threadIdx.x, src, dst, 0u);
+    }
     __syncthreads();
     const double vol = m.hx * m.hy * m.hz;
     const double ih[3] = {1.0 / m.hx, 1.0 / m.hy, 1.0 / m.hz};

@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
     __shared__ double lds[LDS_T];
     const Brick br(m, threadIdx.x);
     double *ps = lds, *ts = lds + NB;
-    br.load_fields(m, (const double *)a.phi, ps, T, ts);
+    br.stage_nodes<2, double>(m, (const double *)a.phi, ps, T, ts);
     __syncthreads();
 
     const double h[3] = {m.hx, m.hy, m.hz};
