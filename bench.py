@@ -625,17 +625,9 @@ def oseen_bench(dev, applies=50):
     op = mf.oseen_operator(ctx, wl.params, dev(wl.phi), dev(wl.u0))
     xr = dev(W.uniform(1, nd))
     b = torch.empty_like(xr)
-    s = torch.cuda.current_stream()
     out = {"cells": 48, "velocity_dofs": nd}
     for label, fn in [("apply", mf.operator_apply), ("apply_transpose", mf.operator_apply_transpose)]:
-        fn(op, xr, b)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(applies):
-            fn(op, xr, b)
-        e1.record(s)
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / applies
+        us = _time_calls(lambda: fn(op, xr, b), applies) * 1e6
         # algorithmic bytes per velocity DoF: x, y, u0 (8 B each) and phi (8 B per 3 DoFs)
         out[label] = {"us": us, "dofs_per_s": nd / (us * 1e-6), "algorithmic_gbs": nd * (24 + 8 / 3) / (us * 1e-6) / 1e9}
     mf.operator_apply(op, xr, b)
@@ -713,20 +705,42 @@ def heat_sources_bench(dev, reps=50):
     op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
     T = dev(wl.T)
     b = torch.empty_like(T)
-    s = torch.cuda.current_stream()
-    for _ in range(3):
-        mf.heat_source_rhs(op, wl.sources, T, b)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        mf.heat_source_rhs(op, wl.sources, T, b)
-    e1.record(s)
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) * 1e-3 / reps
+    t = _time_calls(lambda: mf.heat_source_rhs(op, wl.sources, T, b), reps)
     out = {"cells": n, "nodes": nn, "us": t * 1e6, "dofs_per_s": nn / t, "algorithmic_gbs": 24 * nn / t / 1e9,
            "terms": "evaporative cooling (Tanasawa, local T) + Gaussian laser flux"}
     log(f"[bench]   assembly {t * 1e6:.1f} us ({24 * nn / t / 1e9:.0f} GB/s algorithmic)")
     return out
+
+
+def _warm(call, ms=30.0):
+    """Run call() back to back for at least `ms` milliseconds of wall time, so
+    that the timed calls that follow see the GPU at its steady clocks."""
+    import torch
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(5):
+            call()
+        torch.cuda.synchronize()
+        if (time.perf_counter() - t0) * 1e3 >= ms:
+            return
+
+
+def _time_calls(call, n, batches=5):
+    """Median over `batches` batches of n back-to-back calls (HIP events on
+    the current stream) of the time per call in seconds, after a warm-up."""
+    import torch
+    _warm(call)
+    s = torch.cuda.current_stream()
+    per = []
+    for _ in range(batches):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(n):
+            call()
+        e1.record(s)
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1) * 1e-3 / n)
+    return sorted(per)[len(per) // 2]
 
 
 def _time_applies(ctx, fn, op, x, y, applies):
@@ -735,16 +749,7 @@ def _time_applies(ctx, fn, op, x, y, applies):
     kernel events (they would add about 5 us to each), then the kernel alone
     with start/stop events attached to its dispatch."""
     import torch
-    for _ in range(5):
-        fn(op, x, y)
-    torch.cuda.synchronize()
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(applies):
-        fn(op, x, y)
-    e1.record(s)
-    torch.cuda.synchronize()
+    whole = _time_calls(lambda: fn(op, x, y), applies)
     ctx.timing_enable(True)
     ctx.timing_read(reset=True)
     for _ in range(applies):
@@ -752,7 +757,7 @@ def _time_applies(ctx, fn, op, x, y, applies):
     torch.cuda.synchronize()
     kms, kl = ctx.timing_read(reset=True)
     ctx.timing_enable(False)
-    return e0.elapsed_time(e1) * 1e-3 / applies, kms * 1e-3 / kl
+    return whole, kms * 1e-3 / kl
 
 
 def three_phase_bench(dev, applies=50, beta=2.0e9):
@@ -895,18 +900,9 @@ def transport_bench(dev, reps=50):
     ctx = mf.Context(wl.mesh)
     phi, u, T = dev(wl.phi), dev(wl.u), dev(wl.T)
     ug = torch.empty_like(u)
-    s = torch.cuda.current_stream()
     out = {"cells": 64, "nodes": nn, "bytes_per_node": BYTES_PER_NODE_TRANSPORT}
     for variant, label in [(mf.MF_TRANSPORT_LOCAL, "local"), (mf.MF_TRANSPORT_LIQUID_EXTENSION, "liquid_extension")]:
-        for _ in range(3):
-            mf.transport_velocity(ctx, variant, wl.params, wl.sources, phi, u, T, ug)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            mf.transport_velocity(ctx, variant, wl.params, wl.sources, phi, u, T, ug)
-        e1.record(s)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3 / reps
+        t = _time_calls(lambda: mf.transport_velocity(ctx, variant, wl.params, wl.sources, phi, u, T, ug), reps)
         gbs = BYTES_PER_NODE_TRANSPORT * nn / t / 1e9
         out[label] = {"us": t * 1e6, "nodes_per_s": nn / t, "algorithmic_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
         log(f"[bench]   {label}: {t * 1e6:.1f} us ({gbs:.0f} GB/s algorithmic)")

@@ -71,7 +71,7 @@ struct PointLoc {
     double wx[3], wy[3], wz[3];
 };
 
-__device__ __forceinline__ PointLoc locate(const KMesh &m, const double p[3])
+__device__ __forceinline__ PointLoc locate(const KMesh &m, const double p[3], const double ih[3])
 {
     const double lo[3] = {m.lox, m.loy, m.loz}, h[3] = {m.hx, m.hy, m.hz};
     const int n[3] = {m.nx, m.ny, m.nz};
@@ -81,10 +81,10 @@ __device__ __forceinline__ PointLoc locate(const KMesh &m, const double p[3])
     for (int k = 0; k < 3; ++k) {
         const double hi = lo[k] + h[k] * n[k];
         const double q = fmin(fmax(p[k], lo[k]), hi);
-        int ck = (int)floor((q - lo[k]) / h[k]);
+        int ck = (int)floor((q - lo[k]) * ih[k]);
         ck = min(max(ck, 0), n[k] - 1);
         c[k] = ck;
-        xi[k] = (q - (lo[k] + h[k] * ck)) / h[k];
+        xi[k] = (q - (lo[k] + h[k] * ck)) * ih[k];
     }
     PointLoc L;
     L.base = node_index(m, 2 * c[0], 2 * c[1], 2 * c[2]);
@@ -112,6 +112,19 @@ __device__ __forceinline__ double point_value(const KMesh &m, const PointLoc &L,
     return vz;
 }
 
+// H of the sine form from the signed distance d (heaviside_sine recovers
+// the same d from phi first; the distance kernel has stored it).
+__device__ __forceinline__ double heaviside_sine_of_d(double eps, double d)
+{
+    if (d <= -3.0 * eps) return 0.0;
+    if (d >= 3.0 * eps) return 1.0;
+    const double a = M_PI * d / (3.0 * eps);
+    return 0.5 + d / (6.0 * eps) + sin(a) / (2.0 * M_PI);
+}
+
+// One thread per node: blockIdx.y is the z plane, the plane's nodes run
+// along blockIdx.x * TNT + threadIdx.x (row = j, split without an integer
+// division: a single-precision estimate, corrected by one step).
 template <int VARIANT, int HK>
 __global__ void __launch_bounds__(TNT) transport_velocity_kernel(KMesh m, TransportArgs a,
                                                                  const double *__restrict__ phi,
@@ -121,41 +134,45 @@ __global__ void __launch_bounds__(TNT) transport_velocity_kernel(KMesh m, Transp
                                                                  double *__restrict__ ug)
 {
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ;
-    const unsigned NX = m.NX, NY = m.NY;
-    for (int64_t g = (int64_t)blockIdx.x * TNT + threadIdx.x; g < nn; g += (int64_t)gridDim.x * TNT) {
-        const unsigned gi = (unsigned)g, row = gi / NX;
-        const int i = gi - row * NX, j = row % NY, k = row / NY;
-        const double gx = axis_derivative(d, g, i, m.NX, 1, 1.0 / m.hx);
-        const double gy = axis_derivative(d, g, j, m.NY, m.NX, 1.0 / m.hy);
-        const double gz = axis_derivative(d, g, k, m.NZ, (int64_t)m.NX * m.NY, 1.0 / m.hz);
-        const double gn = sqrt(gx * gx + gy * gy + gz * gz);
-        // |grad d| is 1 for a signed distance; at a point of symmetry (a
-        // sphere's centre) or where phi saturates it vanishes: no normal there
-        const double inv = gn > 1e-8 ? 1.0 / gn : 0.0;
-        const double n[3] = {gx * inv, gy * inv, gz * inv};
-        double base[3], mdot, rho;
-        if constexpr (VARIANT == 1) {
-            const double H = heaviside<double>(HK, a.eps, phi[g], nullptr);
-            rho = 1.0 / (H / a.rho_l + (1.0 - H) / a.rho_g);
-            mdot = a.alpha_v * (T[g] - a.T_boil);
+    const unsigned NX = m.NX, NP = NX * (unsigned)m.NY;
+    const unsigned pidx = blockIdx.x * TNT + threadIdx.x, k = blockIdx.y;
+    if (pidx >= NP) return;
+    unsigned j = (unsigned)((float)pidx * (1.0f / (float)NX));
+    if (j * NX > pidx) --j;
+    else if ((j + 1) * NX <= pidx) ++j;
+    const int i = (int)(pidx - j * NX);
+    const int64_t g = (int64_t)k * NP + pidx;
+    const double ih[3] = {1.0 / m.hx, 1.0 / m.hy, 1.0 / m.hz};
+    const double gx = axis_derivative(d, g, i, m.NX, 1, ih[0]);
+    const double gy = axis_derivative(d, g, (int)j, m.NY, m.NX, ih[1]);
+    const double gz = axis_derivative(d, g, (int)k, m.NZ, (int64_t)NP, ih[2]);
+    const double gn = sqrt(gx * gx + gy * gy + gz * gz);
+    // |grad d| is 1 for a signed distance; at a point of symmetry (a
+    // sphere's centre) or where phi saturates it vanishes: no normal there
+    const double inv = gn > 1e-8 ? 1.0 / gn : 0.0;
+    const double n[3] = {gx * inv, gy * inv, gz * inv};
+    double base[3], mdot, irho;
+    if constexpr (VARIANT == 1) {
+        const double H = HK == 1 ? heaviside_sine_of_d(a.eps, d[g]) : heaviside_linear<double>(phi[g]);
+        irho = H / a.rho_l + (1.0 - H) / a.rho_g; // 1 / rho_eff
+        mdot = a.alpha_v * (T[g] - a.T_boil);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) base[c] = u[c * nn + g];
-        } else {
-            const double x[3] = {m.lox + i * 0.5 * m.hx, m.loy + j * 0.5 * m.hy, m.loz + k * 0.5 * m.hz};
-            const double dg = d[g], dl = 3.0 * a.eps - dg;
-            const double pg[3] = {x[0] - dg * n[0], x[1] - dg * n[1], x[2] - dg * n[2]};
-            const double pl[3] = {x[0] + dl * n[0], x[1] + dl * n[1], x[2] + dl * n[2]};
-            const PointLoc Lg = locate(m, pg);
-            mdot = a.alpha_v * (point_value(m, Lg, T) - a.T_boil);
-            rho = a.rho_l;
-            const PointLoc Ll = locate(m, pl);
+        for (int c = 0; c < 3; ++c) base[c] = u[c * nn + g];
+    } else {
+        const double x[3] = {m.lox + i * 0.5 * m.hx, m.loy + j * 0.5 * m.hy, m.loz + k * 0.5 * m.hz};
+        const double dg = d[g], dl = 3.0 * a.eps - dg;
+        const double pg[3] = {x[0] - dg * n[0], x[1] - dg * n[1], x[2] - dg * n[2]};
+        const double pl[3] = {x[0] + dl * n[0], x[1] + dl * n[1], x[2] + dl * n[2]};
+        const PointLoc Lg = locate(m, pg, ih);
+        mdot = a.alpha_v * (point_value(m, Lg, T) - a.T_boil);
+        irho = 1.0 / a.rho_l;
+        const PointLoc Ll = locate(m, pl, ih);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) base[c] = point_value(m, Ll, u + c * nn);
-        }
-        const double s = mdot / rho;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ug[c * nn + g] = base[c] + s * n[c];
+        for (int c = 0; c < 3; ++c) base[c] = point_value(m, Ll, u + c * nn);
     }
+    const double s = mdot * irho;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ug[c * nn + g] = base[c] + s * n[c];
 }
 
 static unsigned grid_for(int64_t n)
@@ -172,7 +189,10 @@ hipError_t transport_velocity(const KMesh &m, const TransportArgs &a, const doub
     distance_kernel<<<grid_for(nn), TNT, 0, s>>>(phi, dwork, a.eps, nn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned g = grid_for(nn);
+    const int64_t np = (int64_t)m.NX * m.NY;
+    // the row split's single-precision estimate is within one row for NY < 2^23
+    if (np > 0xFFFFFFFFll || m.NZ > 65535 || m.NY >= (1 << 23)) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((np + TNT - 1) / TNT), (unsigned)m.NZ);
     const int key = a.variant * 2 + (a.hkind ? 1 : 0);
     switch (key) {
     case 2: transport_velocity_kernel<1, 0><<<g, TNT, 0, s>>>(m, a, phi, dwork, u, T, ug); break;
