@@ -64,8 +64,10 @@ struct OseenArgs {
 // field that another workgroup of the same launch writes.
 struct CGState {
     double rz, rz_old, pAp, rr, bb, alpha, beta, thresh2;
+    double rzprev; // flexible CG: r_{k+1} . z_k
     int iter, maxit, done, breakdown, flexible;
-    int run; // set by the CG residual kernel: whether it ran this iteration
+    int run;   // set by the CG residual kernel: whether it ran this iteration
+    int xpend; // flexible CG: x still lacks the last alpha p
 };
 
 // Partial sums of one reduction: NV sets of nblocks doubles, reduced by a
@@ -166,17 +168,15 @@ hipError_t cg_resid(CGState *st, const double *dinv, double *r, const double *q,
 // beta and the convergence test from cg_resid's partials; x += alpha p, p = D^-1 r + beta p
 hipError_t cg_step(CGState *st, const double *dinv, double *x, const double *r, double *p, int64_t n,
                    const RedWS *red, hipStream_t s);
-// Flexible-CG pieces: the preconditioner output z is supplied by the caller.
-// (r32 != null: also store r rounded to FP32, the FP32 preconditioner's input)
-hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n,
-                         const RedWS *red, hipStream_t s, float *r32 = nullptr);
-hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
-                   hipStream_t s);
-hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s);
-// the same with the preconditioned residuals z and z_prev in FP32
-hipError_t fcg_dir_f32(CGState *st, const double *r, const float *z, const float *zprev, int64_t n, const RedWS *red,
-                       hipStream_t s);
-hipError_t fcg_pupdate_f32(CGState *st, const float *z, float *zprev, double *p, int64_t n, hipStream_t s);
+// Flexible-CG pieces (FP32 preconditioner output z, supplied by the caller):
+// r -= alpha q, r32 = fl32(r), r.r and r.z_old, convergence test;
+hipError_t fcg_resid(CGState *st, double *r, const double *q, const float *zold, float *r32, int64_t n,
+                     const RedWS *red, hipStream_t s);
+// beta from r.z, x += alpha p (deferred from fcg_resid), p = z + beta p;
+hipError_t fcg_direction(CGState *st, const double *r, const float *z, double *p, double *x, int64_t n,
+                         const RedWS *red, hipStream_t s);
+// after the last poll: x += alpha p if still pending.
+hipError_t fcg_finish(const CGState *st, const double *p, double *x, int64_t n, hipStream_t s);
 
 // ---- multigrid (mg.hip) ----
 hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s);

@@ -369,7 +369,6 @@ struct mf_mg {
     std::vector<MGLevel> L; // 0 = coarsest
     bool smooth_coarsest = false;          // the coarsest level is smoothed, not solved (level rule)
     double *b64 = nullptr, *x64 = nullptr; // coarse FP64 right-hand side and solution
-    float *zprev32 = nullptr;              // flexible CG: previous preconditioned residual
 };
 
 static mf_status mg_fail(mf_mg *mg, mf_status st, const char *msg)
@@ -398,7 +397,6 @@ static void mg_free(mf_mg *mg)
     for (MGLevel &l : mg->L) level_free(l);
     if (mg->b64) (void)hipFree(mg->b64);
     if (mg->x64) (void)hipFree(mg->x64);
-    if (mg->zprev32) (void)hipFree(mg->zprev32);
     delete mg;
 }
 
@@ -567,10 +565,6 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
         if (prm->lambda_min) l.lmin = prm->lambda_min[li];
         else l.lmin = coarsest_smoothed ? l.est_min / prm->eig_safety : l.lmax / prm->smoothing_range;
     }
-    if (hipMalloc((void **)&mg->zprev32, sizeof(float) * c->nn) != hipSuccess) {
-        mg_free(mg);
-        return fail(c, MF_ERR_OOM, "multigrid allocation failed");
-    }
     MGLevel &co = mg->L[0];
     if (hipMalloc((void **)&mg->b64, sizeof(double) * co.nn) != hipSuccess ||
         hipMalloc((void **)&mg->x64, sizeof(double) * co.nn) != hipSuccess) {
@@ -690,34 +684,34 @@ extern "C" mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, doubl
     if (!(rtol >= 0.0) || maxit < 0) return fail(c, MF_ERR_ARG, "invalid rtol or maxit");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = c->nn;
-    double *r, *z, *p, *q;
+    double *r, *p, *q;
     mf_status st;
-    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 1, &z)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q)))
-        return st;
+    if ((st = ws_vec(c, 0, &r)) || (st = ws_vec(c, 2, &p)) || (st = ws_vec(c, 3, &q))) return st;
     RedWS red = redws(c);
     if ((st = ensure_face(c, 1))) return st;
     const HeatArgs ha = heat_args(&mg->fine_op);
     MGLevel &top = mg->L.back();
     const int ltop = (int)mg->L.size() - 1;
+    // the flexible CG of vec.hip: z = V(r) is top.x (FP32), its input r32 is top.b
     HIPCHK(c, cg_init(c->cg, b, nullptr, x, r, p, n, rtol, maxit, 1, &red, s));
-    HIPCHK(c, vfill(mg->zprev32, 0.0, n, 1, s));
     HIPCHK(c, vcvt_d2f(b, top.b, n, s)); // r = b
     HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (!c->h_state->done) {
         if ((st = vcycle(mg, ltop, s))) return st;
-        HIPCHK(c, fcg_dir_f32(c->cg, r, top.x, mg->zprev32, n, &red, s));
-        HIPCHK(c, fcg_pupdate_f32(c->cg, top.x, mg->zprev32, p, n, s));
+        HIPCHK(c, fcg_direction(c->cg, r, top.x, p, x, n, &red, s));
         for (;;) {
             HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
-            HIPCHK(c, fcg_update_xr(c->cg, x, r, p, q, n, &red, s, top.b));
+            HIPCHK(c, fcg_resid(c->cg, r, q, top.x, top.b, n, &red, s));
             HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             if (c->h_state->done) break;
             if ((st = vcycle(mg, ltop, s))) return st;
-            HIPCHK(c, fcg_dir_f32(c->cg, r, top.x, mg->zprev32, n, &red, s));
-            HIPCHK(c, fcg_pupdate_f32(c->cg, top.x, mg->zprev32, p, n, s));
+            HIPCHK(c, fcg_direction(c->cg, r, top.x, p, x, n, &red, s));
         }
+        HIPCHK(c, fcg_finish(c->cg, p, x, n, s));
+        HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
     }
     const CGState hs = *c->h_state;
     const double bnorm = sqrt(hs.bb);

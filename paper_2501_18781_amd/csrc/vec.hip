@@ -550,7 +550,9 @@ __global__ void __launch_bounds__(FNT) cg_init_finalize_kernel(CGState *st, cons
         st->maxit = maxit;
         st->breakdown = 0;
         st->flexible = flexible;
-        st->run = 0;
+        st->run = (tot[1] == 0.0 || maxit <= 0) ? 0 : 1; // the flexible CG's first direction step runs
+        st->xpend = 0;
+        st->rzprev = 0.0;
         st->alpha = 0.0;
         st->beta = 0.0;
         st->pAp = 0.0;
@@ -717,47 +719,69 @@ hipError_t cg_step(CGState *st, const double *dinv, double *x, const double *r, 
 }
 
 // ---------------------------------------------------------------------------
-// Flexible CG (Notay): x, r update; then z = V(r) by the caller; then
-// beta = (r.z - r.z_prev) / rz_old (Polak-Ribiere), p = z + beta p.
+// Flexible CG (Notay) with an FP32 preconditioner z = V(r).  One iteration:
+//   apply     q = A p, alpha = rz / p.Ap             (CG-mode apply)
+//   resid     r -= alpha q, r32 = fl32(r); partials of r.r and r.z_old,
+//             z_old (FP32) being the last preconditioner output, still in
+//             place                                  (reads r, q, z_old;
+//                                                     writes r, r32)
+//   finalize  iteration count, r.r, r.z_old, convergence; the host polls
+//   z = V(r32)                                       (the caller)
+//   dir       partials of r.z                        (reads r, z)
+//   step      every workgroup sums dir's partials in the same order:
+//             rz_new, Polak-Ribiere beta = (rz_new - r.z_old) / rz (0 for
+//             the first direction); x += alpha p, the update the residual
+//             step deferred, and p = z + beta p      (reads z, p, x;
+//                                                     writes p, x)
+// After the last poll fcg_finish adds a still pending alpha p to x.  The
+// step kernel writes done (on breakdown), so it tests `run` (set by the
+// residual kernel or the initialization) instead.  `xpend` records whether
+// x still lacks the last alpha p.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(VNT) fcg_xr_kernel(const CGState *st, double *__restrict__ x,
-                                                     double *__restrict__ r, const double *__restrict__ p,
-                                                     const double *__restrict__ q, int64_t n, RedWS red,
-                                                     float *__restrict__ r32)
+__global__ void __launch_bounds__(VNT) fcg_resid_kernel(CGState *st, double *__restrict__ r,
+                                                        const double *__restrict__ q,
+                                                        const float *__restrict__ zold, float *__restrict__ r32,
+                                                        int64_t n, RedWS red)
 {
-    __shared__ double lds[VNT / 64];
-    if (st->done) return;
+    __shared__ double lds[2 * (VNT / 64)];
+    const int skip = st->done;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->run = !skip; // read by the step kernel only
+        if (!skip) st->xpend = 1;
+    }
+    if (skip) return;
     const double alpha = st->alpha;
-    double acc = 0.0;
-    double xv[CG_UNROLL], pv[CG_UNROLL], rv[CG_UNROLL], qv[CG_UNROLL];
+    double acc[2] = {0.0, 0.0};
+    double rv[CG_UNROLL], qv[CG_UNROLL];
+    float zv[CG_UNROLL];
     grid_stride_unrolled(
         n,
         [&](int k, int64_t i) {
-            xv[k] = x[i];
-            pv[k] = p[i];
             rv[k] = r[i];
             qv[k] = q[i];
+            zv[k] = zold[i];
         },
         [&](int k, int64_t i) {
-            x[i] = xv[k] + alpha * pv[k];
             const double ri = rv[k] - alpha * qv[k];
             r[i] = ri;
-            if (r32) r32[i] = (float)ri; // the FP32 preconditioner's input
-            acc += ri * ri;
+            r32[i] = (float)ri; // the FP32 preconditioner's input
+            acc[0] += ri * ri;
+            acc[1] += ri * (double)zv[k];
         });
-    grid_partials<1>(&acc, red, lds);
+    grid_partials<2>(acc, red, lds);
 }
 
-__global__ void __launch_bounds__(FNT) fcg_xr_finalize_kernel(CGState *st, const double *__restrict__ partials,
-                                                              unsigned nb)
+__global__ void __launch_bounds__(FNT) fcg_resid_finalize_kernel(CGState *st, const double *__restrict__ partials,
+                                                                 unsigned nb)
 {
-    __shared__ double tot[1];
+    __shared__ double tot[2];
     if (st->done) return;
-    wave_set_sums<1>(partials, nb, tot);
+    wave_set_sums<2>(partials, nb, tot);
     if (threadIdx.x == 0) {
         const double rr = tot[0];
         st->iter += 1;
         st->rr = rr;
+        st->rzprev = tot[1];
         if (!isfinite(rr)) {
             st->breakdown = 1;
             st->done = 1;
@@ -767,100 +791,34 @@ __global__ void __launch_bounds__(FNT) fcg_xr_finalize_kernel(CGState *st, const
     }
 }
 
-hipError_t fcg_update_xr(CGState *st, double *x, double *r, const double *p, double *q, int64_t n, const RedWS *red,
-                         hipStream_t s, float *r32)
+hipError_t fcg_resid(CGState *st, double *r, const double *q, const float *zold, float *r32, int64_t n,
+                     const RedWS *red, hipStream_t s)
 {
     const unsigned nb = vec_blocks(n);
-    if (red->capacity < nb) return hipErrorInvalidValue;
-    fcg_xr_kernel<<<nb, VNT, 0, s>>>(st, x, r, p, q, n, *red, r32);
+    if (red->capacity < 2 * nb) return hipErrorInvalidValue;
+    fcg_resid_kernel<<<nb, VNT, 0, s>>>(st, r, q, zold, r32, n, *red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    fcg_xr_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
+    fcg_resid_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
     return hipGetLastError();
 }
 
-template <typename Z>
 __global__ void __launch_bounds__(VNT) fcg_dir_kernel(const CGState *st, const double *__restrict__ r,
-                                                      const Z *__restrict__ z, const Z *__restrict__ zprev,
-                                                      int64_t n, RedWS red)
+                                                      const float *__restrict__ z, int64_t n, RedWS red)
 {
-    __shared__ double lds[2 * (VNT / 64)];
-    if (st->done) return;
-    double acc[2] = {0.0, 0.0};
+    __shared__ double lds[VNT / 64];
+    if (!st->run) return;
+    double acc = 0.0;
     double rv[CG_UNROLL];
-    Z zv[CG_UNROLL], wv[CG_UNROLL];
+    float zv[CG_UNROLL];
     grid_stride_unrolled(
         n,
         [&](int k, int64_t i) {
             rv[k] = r[i];
             zv[k] = z[i];
-            wv[k] = zprev[i];
         },
-        [&](int k, int64_t) {
-            acc[0] += rv[k] * (double)zv[k];
-            acc[1] += rv[k] * (double)wv[k];
-        });
-    grid_partials<2>(acc, red, lds);
-}
-
-__global__ void __launch_bounds__(FNT) fcg_dir_finalize_kernel(CGState *st, const double *__restrict__ partials,
-                                                               unsigned nb)
-{
-    __shared__ double tot[2];
-    if (st->done) return;
-    wave_set_sums<2>(partials, nb, tot);
-    if (threadIdx.x == 0) {
-        // first direction: rz == 0 marks "no previous direction"
-        st->beta = (st->rz != 0.0) ? (tot[0] - tot[1]) / st->rz : 0.0;
-        st->rz = tot[0];
-        if (!isfinite(tot[0]) || !(tot[0] > 0.0)) {
-            st->breakdown = 1;
-            st->done = 1;
-        }
-    }
-}
-
-template <typename Z>
-static hipError_t fcg_dir_t(CGState *st, const double *r, const Z *z, const Z *zprev, int64_t n, const RedWS *red,
-                            hipStream_t s)
-{
-    const unsigned nb = vec_blocks(n);
-    if (red->capacity < 2 * nb) return hipErrorInvalidValue;
-    fcg_dir_kernel<Z><<<nb, VNT, 0, s>>>(st, r, z, zprev, n, *red);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    fcg_dir_finalize_kernel<<<1, FNT, 0, s>>>(st, red->partials, nb);
-    return hipGetLastError();
-}
-hipError_t fcg_dir(CGState *st, const double *r, const double *z, const double *zprev, int64_t n, const RedWS *red,
-                   hipStream_t s)
-{
-    return fcg_dir_t<double>(st, r, z, zprev, n, red, s);
-}
-hipError_t fcg_dir_f32(CGState *st, const double *r, const float *z, const float *zprev, int64_t n, const RedWS *red,
-                       hipStream_t s)
-{
-    return fcg_dir_t<float>(st, r, z, zprev, n, red, s);
-}
-
-template <typename Z>
-__global__ void __launch_bounds__(VNT) fcg_pupdate_kernel(const CGState *st, const Z *__restrict__ z,
-                                                          Z *__restrict__ zprev, double *__restrict__ p, int64_t n)
-{
-    if (st->done) return;
-    const double beta = st->beta;
-    Z zv[CG_UNROLL];
-    double pv[CG_UNROLL];
-    grid_stride_unrolled(
-        n,
-        [&](int k, int64_t i) {
-            zv[k] = z[i];
-            pv[k] = p[i];
-        },
-        [&](int k, int64_t i) {
-            p[i] = (double)zv[k] + beta * pv[k];
-            zprev[i] = zv[k];
-        });
+        [&](int k, int64_t) { acc += rv[k] * (double)zv[k]; });
+    grid_partials<1>(&acc, red, lds);
 }
 
 static unsigned stream_blocks(int64_t n)
@@ -869,14 +827,74 @@ static unsigned stream_blocks(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, CG_STEP_BLOCKS));
 }
 
-hipError_t fcg_pupdate(CGState *st, const double *z, double *zprev, double *p, int64_t n, hipStream_t s)
+__global__ void __launch_bounds__(VNT) fcg_step_kernel(CGState *st, const double *__restrict__ partials, unsigned nb,
+                                                       const float *__restrict__ z, double *__restrict__ p,
+                                                       double *__restrict__ x, int64_t n)
 {
-    fcg_pupdate_kernel<double><<<stream_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    __shared__ double tot[1];
+    if (!st->run) return; // written by an earlier launch; this kernel may write done
+    wave_set_sums<1>(partials, nb, tot);
+    const double rz = tot[0], alpha = st->alpha;
+    const bool bad = !isfinite(rz) || !(rz > 0.0);
+    // first direction: rz == 0 marks "no previous direction"
+    const double beta = (!bad && st->rz != 0.0) ? (rz - st->rzprev) / st->rz : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->beta = beta;
+        st->xpend = 0;
+        if (bad) {
+            st->breakdown = 1;
+            st->done = 1;
+        } else {
+            st->rz = rz;
+        }
+    }
+    float zv[CG_UNROLL];
+    double pv[CG_UNROLL], xv[CG_UNROLL];
+    if (bad) { // x still takes the deferred update; p is not needed any more
+        grid_stride_unrolled(
+            n, [&](int k, int64_t i) { pv[k] = p[i]; xv[k] = x[i]; },
+            [&](int k, int64_t i) { x[i] = xv[k] + alpha * pv[k]; });
+        return;
+    }
+    grid_stride_unrolled(
+        n,
+        [&](int k, int64_t i) {
+            zv[k] = z[i];
+            pv[k] = p[i];
+            xv[k] = x[i];
+        },
+        [&](int k, int64_t i) {
+            x[i] = xv[k] + alpha * pv[k];
+            p[i] = (double)zv[k] + beta * pv[k];
+        });
+}
+
+hipError_t fcg_direction(CGState *st, const double *r, const float *z, double *p, double *x, int64_t n,
+                         const RedWS *red, hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < nb) return hipErrorInvalidValue;
+    fcg_dir_kernel<<<nb, VNT, 0, s>>>(st, r, z, n, *red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    fcg_step_kernel<<<stream_blocks(n), VNT, 0, s>>>(st, red->partials, nb, z, p, x, n);
     return hipGetLastError();
 }
-hipError_t fcg_pupdate_f32(CGState *st, const float *z, float *zprev, double *p, int64_t n, hipStream_t s)
+
+__global__ void __launch_bounds__(VNT) fcg_finish_kernel(const CGState *st, const double *__restrict__ p,
+                                                         double *__restrict__ x, int64_t n)
 {
-    fcg_pupdate_kernel<float><<<stream_blocks(n), VNT, 0, s>>>(st, z, zprev, p, n);
+    if (!st->xpend) return;
+    const double alpha = st->alpha;
+    double pv[CG_UNROLL], xv[CG_UNROLL];
+    grid_stride_unrolled(
+        n, [&](int k, int64_t i) { pv[k] = p[i]; xv[k] = x[i]; },
+        [&](int k, int64_t i) { x[i] = xv[k] + alpha * pv[k]; });
+}
+
+hipError_t fcg_finish(const CGState *st, const double *p, double *x, int64_t n, hipStream_t s)
+{
+    fcg_finish_kernel<<<stream_blocks(n), VNT, 0, s>>>(st, p, x, n);
     return hipGetLastError();
 }
 
