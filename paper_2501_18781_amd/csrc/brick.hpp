@@ -74,13 +74,21 @@ struct Brick {
     bool valid;
     bool lastx, lasty, lastz;
 
-    __device__ __forceinline__ Brick(const KMesh &m, int slot) : t(slot)
+    __device__ __forceinline__ Brick(const KMesh &m, int slot) : Brick(m, slot, xcd_index()) {}
+
+    // XCD-contiguous numbering: workgroup b runs on XCD b % 8; XCD k gets
+    // the workgroup indices [start_k, start_k + count_k).
+    static __device__ __forceinline__ int xcd_index()
     {
-        // XCD-contiguous numbering: workgroup b runs on XCD b % 8; XCD k gets
-        // bricks [start_k, start_k + count_k).
         const int G = gridDim.x, q = G / NXCD, r = G % NXCD;
         const int k = blockIdx.x % NXCD, j = blockIdx.x / NXCD;
-        brick = k * q + min(k, r) + j;
+        return k * q + min(k, r) + j;
+    }
+
+    // The brick of natural index b.
+    __device__ __forceinline__ Brick(const KMesh &m, int slot, int b) : t(slot)
+    {
+        brick = b;
         const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB;
         bx = brick % nbx;
         by = (brick / nbx) % nby;
@@ -623,6 +631,99 @@ __device__ __forceinline__ void combine_visit(const KMesh &m, const T *__restric
         for (int e = 1; e < 8; ++e) s += v[k][e];
         f(g[k], con[k], (SKIP_CONSTRAINED && con[k]) ? T(0) : s);
     }
+}
+
+// Brick-owned combine: one workgroup of BNT threads per brick (numbered like
+// the brick kernels, XCD-contiguously).  Each shared node is finished by the
+// one brick that holds it at local index 0 in every direction in which it
+// is shared: the brick's nodes on its low faces that lie on internal brick
+// planes, without its shared high faces (the next brick's low faces).  For
+// a brick with lower neighbours in x, y and z that is up to 64 + 56 + 49
+// nodes (217 for a brick at the far end of the mesh in every direction), at
+// most four per thread, enumerated in three slabs: l_z = 0 (runs along x);
+// l_y = 0 (runs along x); l_x = 0 (runs along y, where the x-face slots are
+// contiguous).  The partials are summed in the order of combine_visit (z
+// outer, then y, then x; lower brick first), so the two give bitwise the
+// same result; all loads of a thread's nodes are issued before the sums.
+template <typename T, bool SKIP_CONSTRAINED, typename F>
+__device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, int lane, const T *__restrict__ face,
+                                                    F f)
+{
+    const Brick br(m, lane, brick);
+    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
+    const bool fx = br.bx > 0, fy = br.by > 0, fz = br.bz > 0; // lower neighbour: the low face is shared
+    const int ex = 2 * br.ncx + (br.bx == nbx - 1 ? 1 : 0);     // local range without a shared high face
+    const int ey = 2 * br.ncy + (br.by == nby - 1 ? 1 : 0);
+    const int ez = 2 * br.ncz + (br.bz == nbz - 1 ? 1 : 0);
+    const int z0 = fz ? 1 : 0, y0 = fy ? 1 : 0;
+    const int nzs = fz ? ex * ey : 0, nys = fy ? ex * (ez - z0) : 0, nxs = fx ? (ey - y0) * (ez - z0) : 0;
+    const int tot = nzs + nys + nxs;
+    // small exact divisions: floor((j + 1/2) / w) for j < 256, w <= 9
+    const float iex = 1.0f / (float)ex, iw = 1.0f / (float)(ey - y0);
+    constexpr int K = 4;
+    bool has[K], con[K];
+    int64_t g[K];
+    T v[K][8];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int j = lane + BNT * k;
+        has[k] = j < tot;
+        int lx = 0, ly = 0, lz = 0;
+        if (j < nzs) {
+            ly = (int)(((float)j + 0.5f) * iex);
+            lx = j - ly * ex;
+        } else if ((j -= nzs) < nys) {
+            const int q = (int)(((float)j + 0.5f) * iex);
+            lz = z0 + q;
+            lx = j - q * ex;
+        } else {
+            j -= nys;
+            const int w = ey - y0, q = (int)(((float)j + 0.5f) * iw);
+            lz = z0 + q;
+            ly = y0 + j - q * w;
+        }
+        if (!has[k]) lx = ly = lz = 0;
+        const int gx = 2 * br.c0x + lx, gy = 2 * br.c0y + ly, gz = 2 * br.c0z + lz;
+        con[k] = has[k] && node_constrained(m, gx, gy, gz);
+        g[k] = node_index(m, gx, gy, gz);
+        const bool read = has[k] && !(SKIP_CONSTRAINED && con[k]);
+        const bool sx = lx == 0 && fx, sy = ly == 0 && fy, sz = lz == 0 && fz;
+        const int kx0 = sx ? br.bx - 1 : br.bx, lx0 = sx ? 2 * BB : lx;
+        const int ky0 = sy ? br.by - 1 : br.by, ly0 = sy ? 2 * BB : ly;
+        const int kz0 = sz ? br.bz - 1 : br.bz, lz0 = sz ? 2 * BB : lz;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int ex_ = e & 1, ey_ = (e >> 1) & 1, ez_ = e >> 2;
+            v[k][e] = T(0);
+            if (read && (!ex_ || sx) && (!ey_ || sy) && (!ez_ || sz)) {
+                const int b = (kx0 + ex_) + nbx * ((ky0 + ey_) + nby * (kz0 + ez_));
+                v[k][e] = face[(int64_t)b * BFACE + face_slot(ex_ ? 0 : lx0, ey_ ? 0 : ly0, ez_ ? 0 : lz0)];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!has[k]) continue;
+        T s = v[k][0];
+#pragma unroll
+        for (int e = 1; e < 8; ++e) s += v[k][e];
+        f(g[k], con[k], (SKIP_CONSTRAINED && con[k]) ? T(0) : s);
+    }
+}
+
+// CBW bricks per workgroup, one per wavefront.
+constexpr int CBW = 4;
+
+template <typename T, int DMODE>
+__device__ __forceinline__ void combine_brick(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
+                                              T *__restrict__ y)
+{
+    const int brick = Brick::xcd_index() * CBW + (int)threadIdx.x / BNT;
+    if (brick >= n_bricks(m)) return; // a whole wavefront; no barrier follows in it
+    combine_brick_visit<T, DMODE != 0>(m, brick, (int)threadIdx.x % BNT, face, [&](int64_t g, bool constrained, T s) {
+        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
+        else y[g] = s;
+    });
 }
 
 template <typename T, int DMODE, int NPT = 1>

@@ -449,6 +449,35 @@ __global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__r
     }
 }
 
+// The same pass with one workgroup per brick finishing the shared nodes it
+// owns (combine_brick in brick.hpp); bitwise the same result.
+template <typename T, bool CG, int DMODE = 1>
+__global__ void __launch_bounds__(BNT * CBW) face_combine_brick_kernel(KMesh m, const T *__restrict__ face,
+                                                                 const T *__restrict__ x, T *__restrict__ y,
+                                                                 CGState *cg, const double *__restrict__ partials,
+                                                                 unsigned nbricks)
+{
+    if (CG) {
+        if (cg->done) return;
+    }
+    if (CG && blockIdx.x == 0) {
+        // before the combine, which lets wavefronts without a brick leave
+        __shared__ double red[BNT * CBW];
+        const double pAp = sum_partials<BNT * CBW>(partials, nbricks, 0, red);
+        if (threadIdx.x == 0) {
+            cg->pAp = pAp;
+            if (!(pAp > 0.0) || !isfinite(pAp)) {
+                cg->breakdown = 1;
+                cg->done = 1;
+                cg->alpha = 0.0;
+            } else {
+                cg->alpha = cg->rz / pAp;
+            }
+        }
+    }
+    combine_brick<T, DMODE>(m, face, x, y);
+}
+
 constexpr int APPLY_NPT = 2; // nodes per thread in the combine pass of the applies
 
 int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
@@ -526,14 +555,14 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
         // single brick: nothing shared; alpha from the brick's partial
         return cg ? cg_alpha(cg, &r, nb, s) : hipSuccess;
     } else if (fp32)
-        face_combine_kernel<float, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(
-            m, (const float *)face, (const float *)x, (float *)y, nullptr, nullptr, 0);
+        face_combine_brick_kernel<float, false, 1><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const float *)face, (const float *)x,
+                                                                     (float *)y, nullptr, nullptr, 0);
     else if (cg)
-        face_combine_kernel<double, true, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(
-            m, (const double *)face, (const double *)x, (double *)y, cg, r.partials, nb);
+        face_combine_brick_kernel<double, true, 1><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const double *)face, (const double *)x,
+                                                                     (double *)y, cg, r.partials, nb);
     else
-        face_combine_kernel<double, false, 1, APPLY_NPT><<<rows, CNT, 0, s>>>(
-            m, (const double *)face, (const double *)x, (double *)y, nullptr, nullptr, 0);
+        face_combine_brick_kernel<double, false, 1><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const double *)face, (const double *)x,
+                                                                      (double *)y, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 
