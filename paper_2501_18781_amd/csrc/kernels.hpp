@@ -179,8 +179,12 @@ hipError_t fcg_direction(CGState *st, const double *r, const float *z, double *p
 hipError_t fcg_finish(const CGState *st, const double *p, double *x, int64_t n, hipStream_t s);
 
 // ---- multigrid (mg.hip) ----
-hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s);
-hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, hipStream_t s);
+// Separable transfers, one direction per pass; w1 (NXf NYc NZc floats) and w2
+// (NXf NYf NZc floats) are work arrays.
+hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, float *w1, float *w2,
+                       hipStream_t s);
+hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, float *w1, float *w2,
+                          hipStream_t s);
 hipError_t mg_inject(const KMesh &fine, const KMesh &coarse, const void *phif, void *phic, int fp32,
                      hipStream_t s);
 // Chebyshev pieces in FP32 (see mg.hip)

@@ -115,68 +115,85 @@ __device__ __forceinline__ void restrict_taps(int s, int NF, bool dlo, bool dhi,
     }
 }
 
-constexpr int TNT = 64; // threads per transfer workgroup (one row segment along x)
+// The transfers are separable, P = P_z P_y P_x with the 1D operators above,
+// and are applied one direction at a time, each pass a streaming kernel over
+// its output with the 1D taps of one line (coalesced along x; the y and z
+// passes read whole rows).  Prolongation: x, y, then z (adding into the fine
+// vector); restriction: z, y, then x.  The Dirichlet zeroing is per
+// direction (a tap on a Dirichlet face has weight 0), so it factors too.
+// The intermediate arrays are two fine-level work vectors.
+constexpr int XNT = 256; // threads per transfer workgroup
 
-// xf += P ec over the fine nodes; grid (ceil(NXf / TNT), NYf, NZf).
-__global__ void __launch_bounds__(TNT) prolong_add_kernel(KMesh c, KMesh f, const float *__restrict__ ec,
-                                                          float *__restrict__ xf)
+// Position of the thread in an (NX x NY) plane of a 3D array: grid
+// (ceil(NX NY / XNT), NZ); the row is split by a single-precision estimate
+// and one correction (exact for NY < 2^23).
+struct PlanePos {
+    int x, y, z;
+    bool ok;
+    __device__ __forceinline__ PlanePos(int NX, int NY)
+    {
+        const unsigned p = blockIdx.x * XNT + threadIdx.x, nx = (unsigned)NX;
+        ok = p < nx * (unsigned)NY;
+        unsigned q = (unsigned)((float)p * (1.0f / (float)nx));
+        if (q * nx > p) --q;
+        else if ((q + 1) * nx <= p) ++q;
+        x = (int)(p - q * nx);
+        y = (int)q;
+        z = blockIdx.y;
+    }
+};
+
+// Prolongation pass along direction DIR: out(.., t, ..) = sum_k w_k in(.., s0 + k, ..)
+// with t the fine index along DIR; in has NC nodes along DIR, out NF.
+// (nx, ny, nz): out's extents; the in extent along DIR is NC.
+template <int DIR, bool ADD>
+__global__ void __launch_bounds__(XNT) prolong_pass_kernel(const float *__restrict__ in, float *__restrict__ out,
+                                                           int nx, int ny, int nz, int NC, unsigned dmask,
+                                                           KMesh f)
 {
-    const int fx = blockIdx.x * TNT + threadIdx.x, fy = blockIdx.y, fz = blockIdx.z;
-    if (fx >= f.NX || node_constrained(f, fx, fy, fz)) return;
-    const unsigned D = c.dirichlet;
-    int sx, sy, sz;
-    float wx[3], wy[3], wz[3];
-    prolong_taps(fx, c.NX, D & 1u, D & 2u, sx, wx);
-    prolong_taps(fy, c.NY, D & 4u, D & 8u, sy, wy);
-    prolong_taps(fz, c.NZ, D & 16u, D & 32u, sz, wz);
-    const int ny = (fy & 1) ? 3 : 1, nz = (fz & 1) ? 3 : 1; // uniform over the workgroup
-    if (!(fy & 1)) {
-        sy = fy >> 1;
-        wy[0] = ((D & 4u) && sy == 0) || ((D & 8u) && sy == c.NY - 1) ? 0.0f : 1.0f;
-    }
-    if (!(fz & 1)) {
-        sz = fz >> 1;
-        wz[0] = ((D & 16u) && sz == 0) || ((D & 32u) && sz == c.NZ - 1) ? 0.0f : 1.0f;
-    }
-    float acc = 0.0f;
-    for (int kz = 0; kz < nz; ++kz)
-        for (int ky = 0; ky < ny; ++ky) {
-            const float *row = ec + node_index(c, sx, sy + ky, sz + kz);
-            const float wyz = wy[ky] * wz[kz];
-            acc += wyz * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
-        }
-    xf[node_index(f, fx, fy, fz)] += acc;
+    const PlanePos P(nx, ny);
+    if (!P.ok) return;
+    const int t = DIR == 0 ? P.x : (DIR == 1 ? P.y : P.z);
+    if (ADD && node_constrained(f, P.x, P.y, P.z)) return; // rows of P at Dirichlet fine nodes
+    int s0;
+    float w[3];
+    prolong_taps(t, NC, dmask & 1u, dmask & 2u, s0, w);
+    const int inx = DIR == 0 ? NC : nx, iny = DIR == 1 ? NC : ny;
+    const int64_t sd = DIR == 0 ? 1 : (DIR == 1 ? (int64_t)inx : (int64_t)inx * iny);
+    const int ix = DIR == 0 ? s0 : P.x, iy = DIR == 1 ? s0 : P.y, iz = DIR == 2 ? s0 : P.z;
+    const float *src = in + (int64_t)ix + (int64_t)inx * ((int64_t)iy + (int64_t)iny * iz);
+    const float v = w[0] * src[0] + w[1] * src[sd] + w[2] * src[2 * sd];
+    float *dst = out + (int64_t)P.x + (int64_t)nx * ((int64_t)P.y + (int64_t)ny * P.z);
+    if (ADD) *dst += v;
+    else *dst = v;
 }
 
-// rc = P^T rf over the coarse nodes; grid (ceil(NXc / TNT), NYc, NZc).
-__global__ void __launch_bounds__(TNT) restrict_kernel(KMesh f, KMesh c, const float *__restrict__ rf,
-                                                       float *__restrict__ rc)
+// Restriction pass along DIR: out(.., s, ..) = sum_k w_k in(.., t_k, ..), s the
+// coarse index along DIR; in has NF nodes along DIR.  The last pass (x)
+// writes 0 at the coarse Dirichlet nodes.
+template <int DIR, bool LAST>
+__global__ void __launch_bounds__(XNT) restrict_pass_kernel(const float *__restrict__ in, float *__restrict__ out,
+                                                            int nx, int ny, int nz, int NF, unsigned dmask,
+                                                            KMesh c)
 {
-    const int sx = blockIdx.x * TNT + threadIdx.x, sy = blockIdx.y, sz = blockIdx.z;
-    if (sx >= c.NX) return;
-    const int64_t o = node_index(c, sx, sy, sz);
-    if (node_constrained(c, sx, sy, sz)) {
-        rc[o] = 0.0f;
+    const PlanePos P(nx, ny);
+    if (!P.ok) return;
+    float *dst = out + (int64_t)P.x + (int64_t)nx * ((int64_t)P.y + (int64_t)ny * P.z);
+    if (LAST && node_constrained(c, P.x, P.y, P.z)) {
+        *dst = 0.0f;
         return;
     }
-    const unsigned D = f.dirichlet;
-    int tx[5], ty[5], tz[5];
-    float wx[5], wy[5], wz[5];
-    restrict_taps(sx, f.NX, D & 1u, D & 2u, tx, wx);
-    restrict_taps(sy, f.NY, D & 4u, D & 8u, ty, wy);
-    restrict_taps(sz, f.NZ, D & 16u, D & 32u, tz, wz);
-    const int ny = (sy & 1) ? 3 : 5, nz = (sz & 1) ? 3 : 5; // uniform over the workgroup
-    float acc = 0.0f;
-    for (int kz = 0; kz < nz; ++kz)
-        for (int ky = 0; ky < ny; ++ky) {
-            const float wyz = wy[ky] * wz[kz];
-            const float *row = rf + node_index(f, 0, ty[ky], tz[kz]);
-            float sxs = 0.0f;
+    const int sc = DIR == 0 ? P.x : (DIR == 1 ? P.y : P.z);
+    int t[5];
+    float w[5];
+    restrict_taps(sc, NF, dmask & 1u, dmask & 2u, t, w);
+    const int inx = DIR == 0 ? NF : nx, iny = DIR == 1 ? NF : ny;
+    const int64_t sd = DIR == 0 ? 1 : (DIR == 1 ? (int64_t)inx : (int64_t)inx * iny);
+    const int64_t base = (DIR == 0 ? 0 : P.x) + (int64_t)inx * ((DIR == 1 ? 0 : P.y) + (int64_t)iny * (DIR == 2 ? 0 : P.z));
+    float v = 0.0f;
 #pragma unroll
-            for (int kx = 0; kx < 5; ++kx) sxs += wx[kx] * row[tx[kx]];
-            acc += wyz * sxs;
-        }
-    rc[o] = acc;
+    for (int k = 0; k < 5; ++k) v += w[k] * in[base + sd * t[k]];
+    *dst = v;
 }
 
 template <typename T> __global__ void inject_kernel(KMesh f, KMesh c, const T *__restrict__ pf, T *__restrict__ pc)
@@ -243,17 +260,36 @@ __global__ void knuth_kernel(double *__restrict__ v, int64_t n)
 
 __global__ void sqrt_kernel(const double *__restrict__ d, double *__restrict__ s, int64_t n) { GSTRIDE(i, n) s[i] = sqrt(d[i]); }
 
-hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, hipStream_t s)
+static dim3 plane_grid(int nx, int ny, int nz)
 {
-    const dim3 g((coarse.NX + TNT - 1) / TNT, coarse.NY, coarse.NZ);
-    restrict_kernel<<<g, TNT, 0, s>>>(fine, coarse, rf, rc);
+    return dim3((unsigned)(((int64_t)nx * ny + XNT - 1) / XNT), (unsigned)nz);
+}
+
+hipError_t mg_restrict(const KMesh &fine, const KMesh &coarse, const float *rf, float *rc, float *w1, float *w2,
+                       hipStream_t s)
+{
+    const unsigned D = fine.dirichlet;
+    // z: (NXf, NYf, NZc) <- rf;  y: (NXf, NYc, NZc);  x: (NXc, NYc, NZc) = rc
+    restrict_pass_kernel<2, false><<<plane_grid(fine.NX, fine.NY, coarse.NZ), XNT, 0, s>>>(
+        rf, w2, fine.NX, fine.NY, coarse.NZ, fine.NZ, (D >> 4) & 3u, coarse);
+    restrict_pass_kernel<1, false><<<plane_grid(fine.NX, coarse.NY, coarse.NZ), XNT, 0, s>>>(
+        w2, w1, fine.NX, coarse.NY, coarse.NZ, fine.NY, (D >> 2) & 3u, coarse);
+    restrict_pass_kernel<0, true><<<plane_grid(coarse.NX, coarse.NY, coarse.NZ), XNT, 0, s>>>(
+        w1, rc, coarse.NX, coarse.NY, coarse.NZ, fine.NX, D & 3u, coarse);
     return hipGetLastError();
 }
 
-hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, hipStream_t s)
+hipError_t mg_prolong_add(const KMesh &coarse, const KMesh &fine, const float *ec, float *xf, float *w1, float *w2,
+                          hipStream_t s)
 {
-    const dim3 g((fine.NX + TNT - 1) / TNT, fine.NY, fine.NZ);
-    prolong_add_kernel<<<g, TNT, 0, s>>>(coarse, fine, ec, xf);
+    const unsigned D = coarse.dirichlet;
+    // x: (NXf, NYc, NZc) <- ec;  y: (NXf, NYf, NZc);  z: xf (NXf, NYf, NZf) +=
+    prolong_pass_kernel<0, false><<<plane_grid(fine.NX, coarse.NY, coarse.NZ), XNT, 0, s>>>(
+        ec, w1, fine.NX, coarse.NY, coarse.NZ, coarse.NX, D & 3u, fine);
+    prolong_pass_kernel<1, false><<<plane_grid(fine.NX, fine.NY, coarse.NZ), XNT, 0, s>>>(
+        w1, w2, fine.NX, fine.NY, coarse.NZ, coarse.NY, (D >> 2) & 3u, fine);
+    prolong_pass_kernel<2, true><<<plane_grid(fine.NX, fine.NY, fine.NZ), XNT, 0, s>>>(
+        w2, xf, fine.NX, fine.NY, fine.NZ, coarse.NZ, (D >> 4) & 3u, fine);
     return hipGetLastError();
 }
 
@@ -652,9 +688,9 @@ static mf_status vcycle(mf_mg *mg, int li, hipStream_t s)
     if ((st = cheb_smooth(mg, l, l.b, l.x, true, s))) return st;
     MGCHK(mg, heat_apply(l.ctx->km, heat_args(&l.op32), 1, l.x, l.t, l.ctx->face, nullptr, nullptr, s));
     MGCHK(mg, vsub_f(l.b, l.t, l.r, l.nn, s));
-    MGCHK(mg, mg_restrict(l.ctx->km, cl.ctx->km, l.r, cl.b, s));
+    MGCHK(mg, mg_restrict(l.ctx->km, cl.ctx->km, l.r, cl.b, l.d, l.t, s)); // l.d, l.t: free work vectors here
     if ((st = vcycle(mg, li - 1, s))) return st;
-    MGCHK(mg, mg_prolong_add(cl.ctx->km, l.ctx->km, cl.x, l.x, s));
+    MGCHK(mg, mg_prolong_add(cl.ctx->km, l.ctx->km, cl.x, l.x, l.d, l.t, s)); // l.d, l.t: free until smoothing
     return cheb_smooth(mg, l, l.b, l.x, false, s);
 }
 

@@ -782,6 +782,7 @@ __global__ void __launch_bounds__(FNT) fcg_resid_finalize_kernel(CGState *st, co
         st->iter += 1;
         st->rr = rr;
         st->rzprev = tot[1];
+        st->rz_old = st->rz; // read by the step kernel, which writes rz
         if (!isfinite(rr)) {
             st->breakdown = 1;
             st->done = 1;
@@ -834,10 +835,12 @@ __global__ void __launch_bounds__(VNT) fcg_step_kernel(CGState *st, const double
     __shared__ double tot[1];
     if (!st->run) return; // written by an earlier launch; this kernel may write done
     wave_set_sums<1>(partials, nb, tot);
-    const double rz = tot[0], alpha = st->alpha;
+    // fields read here are written by earlier launches only (rz_old by the
+    // residual step's finalize; rz, written below, is not read)
+    const double rz = tot[0], alpha = st->alpha, rz_old = st->rz_old;
     const bool bad = !isfinite(rz) || !(rz > 0.0);
-    // first direction: rz == 0 marks "no previous direction"
-    const double beta = (!bad && st->rz != 0.0) ? (rz - st->rzprev) / st->rz : 0.0;
+    // first direction: rz_old == 0 marks "no previous direction"
+    const double beta = (!bad && rz_old != 0.0) ? (rz - st->rzprev) / rz_old : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->beta = beta;
         st->xpend = 0;

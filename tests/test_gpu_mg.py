@@ -237,3 +237,38 @@ def test_level_rule_vcycle_and_flexible_cg(gpu, n, dt, nlev, coarsest_degree):
     print(res, ref.iters, flush=True)
     assert res.converged and res.rel_res <= 1e-8 and abs(res.iters - ref.iters) <= 1
     assert normerr(x, xr) <= 1e-6
+
+
+def test_flexible_cg_at_scale_matches_oracle_and_repeats_bitwise(gpu):
+    # The benchmark's hierarchy in the conduction-dominated regime on 64^3
+    # cells (five V-cycle levels of Chebyshev(1), 4^3 by FP64 CG): the GPU
+    # flexible CG takes the oracle's iteration count (its V-cycle in FP64 with
+    # the same bounds) within one, and three solves give bitwise the same
+    # iterate.  Every scalar of the iteration (alpha, beta, the convergence
+    # test) is formed on the device by launches whose workgroups all read the
+    # same inputs; a workgroup that saw another's update of a scalar it reads
+    # would change the direction of part of the vector, and the iteration
+    # count and bits with it.
+    wl = W.heat_sphere_workload(64, W.ALL_FACES, W.HeatParams(dt=1e3))
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=4, degree=1, auto_levels=True, smooth_degree=2))
+    info = mg.levels()
+    assert [lv[0] for lv in info] == [4, 8, 16, 32, 64] and all(lv[1] == 1 for lv in info[1:])
+    b = dev(W.uniform(5, wl.mesh.n_nodes))
+    xs, its = [], []
+    for _ in range(3):
+        x = torch.empty_like(b)
+        res = mf.mg_cg_solve(mg, b, x, 1e-8, 200)
+        assert res.converged and res.rel_res <= 1e-8
+        xs.append(x.cpu().numpy())
+        its.append(res.iters)
+    print("GPU FCG iterations", its, flush=True)
+    assert its[0] == its[1] == its[2]
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    levels, coarse = oracle_hierarchy_like(wl, mg)
+    print("oracle flexible CG at 64^3", flush=True)
+    ref = O.flexible_cg(levels[-1].A, b.cpu().numpy(), lambda v: O.vcycle(levels, v, degree=1, coarse_solve=coarse),
+                        rtol=1e-8)
+    print(its[0], ref.iters, flush=True)
+    assert abs(its[0] - ref.iters) <= 1
