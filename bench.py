@@ -361,7 +361,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (every box has one GPU); "
+        print("bench.py measures one GPU: the path has no multi-GPU code (the kernels run on one GPU); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -292,84 +292,93 @@ struct Brick {
                     if constexpr (NF == 2) l1s[l] = v1[a + 3 * b + 9 * c];
                 }
     }
-    // Node-parallel staging of NF (1 or 2) unmasked fields: lane t reads brick
-    // nodes t, t + 64, ... (at most 12 per lane), each node once, clipped to
-    // the brick's valid node range, all reads before the first LDS write.
-    // Node n = lx + 9 ly + 81 lz splits by a multiply-shift division by 9
-    // (exact for n < 768).  For FP64 fields this beats the per-cell staging
-    // (apply kernel 27.7 -> 26.4 us at 64^3); FP32 fields keep the per-cell
-    // form, whose paired reads do better there.
+    // Node-parallel staging over a workgroup of NT threads (tid = the
+    // thread's index in it) of NF fields of 8-byte entries: field f is read
+    // from src[f] into the LDS region dst[f]; with MASK, a field with bit f
+    // of maskbits set reads its Dirichlet nodes as zero.  Thread tid takes
+    // the node column l_x = tid mod 9 of the rows (l_y, l_z) = row0 + RPI k,
+    // row0 = tid div 9 and RPI = NT div 9 rows per step (the NT mod 9 threads
+    // left over idle), so each step reads RPI whole 9-node rows, contiguous
+    // along x, and the row index advances by constant steps (no per-node
+    // division or multiply).  Every brick node is read once; all reads are
+    // issued before the first LDS write.  Nodes beyond a clipped brick's valid
+    // range are staged too: their reads stay inside the array or fall beyond
+    // the buffer resource's range and read as zero, and no valid cell reads
+    // their LDS slots.  Steps past the last row write to the row padding
+    // (slot 9 of row 0), which nothing reads.
+    template <int NT, int NF, bool MASK, typename T>
+    __device__ __forceinline__ void stage_rows(const KMesh &m, int tid, const T *const (&src)[NF],
+                                               T *const (&dst)[NF], unsigned maskbits) const
+    {
+        static_assert(sizeof(T) == 8, "8-byte entries (padded LDS rows)");
+        constexpr int R = lds_row<T>(), P = lds_plane<T>();
+        static_assert(R > BP, "the padding slot of row 0 takes the writes of the idle steps");
+        constexpr int RPI = NT / BP, K = (BP * BP + RPI - 1) / RPI;
+        constexpr int DLY = RPI % BP, DLZ = RPI / BP;
+        __amdgpu_buffer_rsrc_t rs[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) rs[f] = nodal_rsrc(m, src[f]);
+        const unsigned NX = m.NX, NXY = (unsigned)m.NX * m.NY;
+        asm volatile("" : "+v"(tid)); // set up per call: nothing kept live across stagings
+        const int lx = tid % BP, row0 = tid / BP;
+        const bool active = tid < RPI * BP;
+        int ly = row0 % BP, lz = row0 / BP;
+        unsigned vofs = 8u * ((unsigned)lx + NX * (unsigned)ly + NXY * (unsigned)lz);
+        int lo = lx + R * ly + P * lz;
+        const unsigned vstep = 8u * (DLY * NX + DLZ * NXY), vcarry = 8u * (NXY - BP * NX);
+        T v[K][NF];
+        int slot[K];
+        bool con[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k > 0) {
+                ly += DLY;
+                lz += DLZ;
+                vofs += vstep;
+                lo += DLY * R + DLZ * P;
+                if (ly >= BP) {
+                    ly -= BP;
+                    lz += 1;
+                    vofs += vcarry;
+                    lo += P - BP * R;
+                }
+            }
+            const bool ok = active && lz < BP;
+            slot[k] = ok ? lo : BP; // padding slot of row 0
+            con[k] = MASK && ok && node_constrained(m, 2 * c0x + lx, 2 * c0y + ly, 2 * c0z + lz);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[k][f] = nodal_load<T>(rs[f], ok ? vofs : 0u, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) dst[f][slot[k]] = (MASK && ((maskbits >> f) & 1u) && con[k]) ? T(0) : v[k][f];
+    }
+
+    // The brick's NF (1 or 2) unmasked 8-byte fields, staged by its 64 lanes.
     template <int NF, typename T>
     __device__ __forceinline__ void stage_nodes(const KMesh &m, const T *__restrict__ g0, T *l0s,
                                                 const T *__restrict__ g1, T *l1s) const
     {
-        constexpr int R = lds_row<T>(), P = lds_plane<T>();
-        constexpr int K = (BNB + BNT - 1) / BNT;
-        const __amdgpu_buffer_rsrc_t r0 = nodal_rsrc(m, g0), r1 = nodal_rsrc(m, NF == 2 ? g1 : g0);
-        const unsigned nxn = 2 * ncx + 1, nyn = 2 * ncy + 1, nzn = 2 * ncz + 1;
-        const unsigned NX = m.NX, NXY = (unsigned)m.NX * m.NY;
-        T v0[K], v1[K];
-        int lo[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            unsigned n = (unsigned)t + (unsigned)BNT * k;
-            asm volatile("" : "+v"(n)); // decoded per call: not kept live across stagings
-            const unsigned q1 = (n * 7282u) >> 16, lx = n - 9u * q1;
-            const unsigned q2 = (q1 * 7282u) >> 16, ly = q1 - 9u * q2, lz = q2;
-            const bool ok = n < (unsigned)BNB && lx < nxn && ly < nyn && lz < nzn;
-            const unsigned vofs = ok ? (unsigned)sizeof(T) * (lx + NX * ly + NXY * lz) : 0u;
-            lo[k] = ok ? (int)(lx + R * ly + P * lz) : -1;
-            v0[k] = nodal_load<T>(r0, vofs, 0);
-            if constexpr (NF == 2) v1[k] = nodal_load<T>(r1, vofs, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (lo[k] >= 0) {
-                l0s[lo[k]] = v0[k];
-                if constexpr (NF == 2) l1s[lo[k]] = v1[k];
-            }
+        if constexpr (NF == 1) {
+            const T *src[1] = {g0};
+            T *const dst[1] = {l0s};
+            stage_rows<BNT, 1, false, T>(m, t, src, dst, 0u);
+        } else {
+            const T *src[2] = {g0, g1};
+            T *const dst[2] = {l0s, l1s};
+            stage_rows<BNT, 2, false, T>(m, t, src, dst, 0u);
         }
     }
 
-    // Node-parallel staging over a workgroup of NT threads (tid = the thread's
-    // index in it): NF FP64 fields, field f read from src[f] into the LDS
-    // region dst[f]; a field with bit f of maskbits set reads its Dirichlet
-    // nodes as zero.  Each brick node is read once per field; all reads are
-    // issued before the first LDS write.
+    // NF FP64 fields over a workgroup of NT threads; bit f of maskbits: field f
+    // reads its Dirichlet nodes as zero.
     template <int NT, int NF>
     __device__ __forceinline__ void stage_nodes_wg(const KMesh &m, int tid, const double *const (&src)[NF],
                                                    double *const (&dst)[NF], unsigned maskbits) const
     {
-        constexpr int R = lds_row<double>(), P = lds_plane<double>();
-        constexpr int K = (BNB + NT - 1) / NT;
-        __amdgpu_buffer_rsrc_t rs[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) rs[f] = nodal_rsrc(m, src[f]);
-        const unsigned nxn = 2 * ncx + 1, nyn = 2 * ncy + 1, nzn = 2 * ncz + 1;
-        const unsigned NX = m.NX, NXY = (unsigned)m.NX * m.NY;
-        double v[K][NF];
-        int lo[K];
-        bool con[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            unsigned n = (unsigned)tid + (unsigned)NT * k;
-            asm volatile("" : "+v"(n)); // decoded per call: not kept live across stagings
-            const unsigned q1 = (n * 7282u) >> 16, lx = n - 9u * q1;
-            const unsigned q2 = (q1 * 7282u) >> 16, ly = q1 - 9u * q2, lz = q2;
-            const bool ok = n < (unsigned)BNB && lx < nxn && ly < nyn && lz < nzn;
-            const unsigned vofs = ok ? 8u * (lx + NX * ly + NXY * lz) : 0u;
-            lo[k] = ok ? (int)(lx + R * ly + P * lz) : -1;
-            con[k] = ok && node_constrained(m, 2 * c0x + (int)lx, 2 * c0y + (int)ly, 2 * c0z + (int)lz);
-#pragma unroll
-            for (int f = 0; f < NF; ++f) v[k][f] = nodal_load<double>(rs[f], vofs, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (lo[k] >= 0) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) dst[f][lo[k]] = ((maskbits >> f) & 1u) && con[k] ? 0.0 : v[k][f];
-            }
-        }
+        if (maskbits) stage_rows<NT, NF, true, double>(m, tid, src, dst, maskbits);
+        else stage_rows<NT, NF, false, double>(m, tid, src, dst, 0u);
     }
 
     template <typename T> __device__ __forceinline__ void load_fields(const KMesh &m, const T *g0, T *l0s) const
