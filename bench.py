@@ -107,6 +107,8 @@ def parse():
                    help="write the SQ counter summary of --kernel from rocprofv3 --pmc output folders and exit")
     p.add_argument("--summarize-trace", metavar="DIR",
                    help="write the kernel statistics of a rocprofv3 --kernel-trace --stats folder and exit")
+    p.add_argument("--summarize-traffic-table", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="write the per-kernel HBM traffic table from two rocprofv3 --pmc output folders and exit")
     p.add_argument("--profile-leg", default="",
                    help="run only this supplementary leg (oseen, heat_convection, heat_sources, three_phase, "
                         "gradient, transport_velocity, mg_vs_cg) and print its JSON, for profiler runs")
@@ -169,6 +171,39 @@ def summarize_counters(fetch_dir, write_dir, command, kernel=APPLY_KERNEL, alg_b
         lines.append(f"traffic / algorithmic: {(fetch_b + write_b) / alg:.3f}")
     if heat:
         lines.append(f"source_hash: {kernel_source_hash()}")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_traffic_table(fetch_dir, write_dir, command, title=""):
+    """FETCH_SIZE and WRITE_SIZE per dispatch of every kernel (by name and
+    grid size) in two rocprofv3 --pmc folders, scaled like summarize_counters
+    by the calibration copy."""
+    def means(folder, counter):
+        files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+        acc, calib = {}, []
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                if CALIB_KERNEL in name and int(r["Grid_Size"]) >= (1 << 24):
+                    calib.append(float(r["Counter_Value"]))
+                    continue
+                short = name[5:] if name.startswith("void ") else name
+                short = short[:short.index(">(") + 1] if ">(" in short else short.split("(")[0]
+                acc.setdefault((short, int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
+        if not calib:
+            raise SystemExit(f"no calibration rows for {counter} in {folder}")
+        scale = CALIB_BYTES / (sum(calib) / len(calib) * 1024.0)
+        return {k: (sum(v) / len(v) * 1024.0 * scale, len(v)) for k, v in acc.items()}, scale
+    f, sf = means(fetch_dir, "FETCH_SIZE")
+    w, sw = means(write_dir, "WRITE_SIZE")
+    rows = sorted(set(f) & set(w), key=lambda k: -(f[k][0] + w[k][0]) * f[k][1])
+    lines = [title or "HBM traffic per dispatch", f"command: {command}",
+             f"calibration: {CALIB_KERNEL} over 2^26 doubles; FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f}", "",
+             " dispatches  grid size   fetch MB   write MB  kernel"]
+    for k in rows[:40]:
+        lines.append(f"{f[k][1]:11d} {k[1]:10d} {f[k][0] / 1e6:10.2f} {w[k][0] / 1e6:10.2f}  {k[0]}")
     return "\n".join(lines) + "\n"
 
 
@@ -358,6 +393,9 @@ def main():
         return
     if args.summarize_trace:
         sys.stdout.write(summarize_trace(args.summarize_trace, args.command, args.title))
+        return
+    if args.summarize_traffic_table:
+        sys.stdout.write(summarize_traffic_table(*args.summarize_traffic_table, args.command, args.title))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
