@@ -45,10 +45,7 @@ __device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, T *phq, cons
 {
     if (MODE == 0 && HK == 1) {
         // out of line and not unrolled: one transcendental evaluation per point
-        for (int q = 0; q < 27; ++q) {
-            double dH;
-            phq[q] = T(heaviside_sine(a.eps, (double)phq[q], &dH));
-        }
+        for (int q = 0; q < 27; ++q) phq[q] = T(heaviside_sine_value(a.eps, (double)phq[q]));
     }
     // The Gauss weight of point q is w[q%3] w[q/3%3] w[q/9], one of four
     // products w0^3, w0^2 w1, w0 w1^2, w1^3 (class = number of middle-point
@@ -207,10 +204,8 @@ __device__ __forceinline__ void cell_heaviside(const Brick &br, const HeatArgs &
     br.gather27(ps, H);
     interp3(H);
     if (HK == 1) {
-        for (int q = 0; q < 27; ++q) { // out of line, not unrolled (as in heat_cell_coeffs)
-            double dH;
-            H[q] = heaviside_sine(a.eps, H[q], &dH);
-        }
+        for (int q = 0; q < 27; ++q) // out of line, not unrolled (as in heat_cell_coeffs)
+            H[q] = heaviside_sine_value(a.eps, H[q]);
     } else {
 #pragma unroll
         for (int q = 0; q < 27; ++q) H[q] = heaviside_linear<double>(H[q]);

@@ -36,8 +36,7 @@ template <int HK> __device__ __forceinline__ void heaviside27(const OseenArgs &a
         if (HK == 0) {
             ph[q] = heaviside_linear<double>(ph[q]);
         } else {
-            double d;
-            ph[q] = heaviside_sine(a.eps, ph[q], &d);
+            ph[q] = heaviside_sine_value(a.eps, ph[q]);
         }
     }
 }
@@ -126,8 +125,7 @@ __device__ __forceinline__ void oseen_phase1(const Brick &br, const OseenArgs &a
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
             const int q = 9 * C + j;
-            double d;
-            const double H = HK == 0 ? heaviside_linear<double>(h[q]) : heaviside_sine(a.eps, h[q], &d);
+            const double H = HK == 0 ? heaviside_linear<double>(h[q]) : heaviside_sine_value(a.eps, h[q]);
             const double Hs = solid_indicator(solid_fraction(a, tq[q]));
             const double W = vol * gauss_weight(q);
             rwl[q * BNT + t] = W / (H / (Hs * a.rho_s + (1.0 - Hs) * a.rho_l) + (1.0 - H) / a.rho_g);
@@ -144,8 +142,7 @@ __device__ __forceinline__ void oseen_phase1(const Brick &br, const OseenArgs &a
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
             const int q = 9 * C + j;
-            double d;
-            const double H = HK == 0 ? heaviside_linear<double>(h[q]) : heaviside_sine(a.eps, h[q], &d);
+            const double H = HK == 0 ? heaviside_linear<double>(h[q]) : heaviside_sine_value(a.eps, h[q]);
             const double W = vol * gauss_weight(q);
             rwl[q * BNT + t] = W / (H / a.rho_l + (1.0 - H) / a.rho_g);
             nul[q * BNT + t] = a.av * W * (a.mu_g + H * (a.mu_l - a.mu_g));
