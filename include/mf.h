@@ -328,7 +328,8 @@ typedef struct {
  * the sine Heaviside reaches 1), and u(x_l), T(x_G) the values of the Q2
  * interpolants at those points, each moved to the nearest point of the box.
  * phi, T: n_nodes doubles; u, u_gamma: [3][n_nodes] doubles (u_gamma != u).
- * Uses one workspace vector of the context. */
+ * Uses one workspace vector of the context.  Meshes with more than 65535
+ * nodes along z or 2^23 along y are rejected (MF_ERR_ARG). */
 mf_status mf_transport_velocity(mf_ctx *ctx, const mf_transport_params *params, const double *phi, const double *u,
                                 const double *T, double *u_gamma, mf_stream stream);
 

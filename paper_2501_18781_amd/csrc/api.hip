@@ -437,6 +437,8 @@ mf_status mf_transport_velocity(mf_ctx *c, const mf_transport_params *p, const d
         return fail(c, MF_ERR_ARG, "the liquid-extension variant needs the sine Heaviside (H = 1 at d = 3 eps)");
     if (!(p->eps > 0.0)) return fail(c, MF_ERR_ARG, "eps must be positive");
     if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0)) return fail(c, MF_ERR_ARG, "densities must be positive");
+    if (c->km.NZ > 65535 || c->km.NY >= (1 << 23))
+        return fail(c, MF_ERR_ARG, "the transport velocity takes at most 65535 nodes along z and 2^23 along y");
     const double gam = p->evaporation_coefficient;
     if (!(gam > 0.0 && gam <= 1.0) || !(p->molar_mass > 0.0) || !(p->boiling_temperature > 0.0))
         return fail(c, MF_ERR_ARG, "invalid evaporation parameters");
