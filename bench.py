@@ -68,7 +68,7 @@ METRIC = "Q2 operator-apply DoFs/s + HBM GB/s; FP32-MG vs FP64 CG time to 1e-8 r
 # a copy kernel of known size).  The summary records a hash of the sources the
 # kernel is built from; once they change, the figure no longer describes the
 # kernel and traffic is reported as null.
-APPLY_KERNEL = "heat_apply_kernel<double, 0, 0, false, 0, true>"  # level set, equal cell edges
+APPLY_KERNEL = "heat_apply_kernel<double, 0, 0, false, 0, true, 4>"  # level set, equal cell edges
 CALIB_KERNEL = "neg_kernel"
 CALIB_BYTES = 8 << 26  # 2^26 doubles read and 2^26 written by the calibration copy
 KERNEL_SOURCES = ["paper_2501_18781_amd/csrc/heat.hip", "paper_2501_18781_amd/csrc/brick.hpp",

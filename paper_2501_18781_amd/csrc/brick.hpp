@@ -34,8 +34,6 @@ namespace mf {
 constexpr int BB = 4;               // cells per brick edge
 constexpr int BNT = BB * BB * BB;   // threads (cells) per brick
 constexpr int BP = 2 * BB + 1;      // nodes per brick edge
-constexpr int BNB = BP * BP * BP;   // nodes per brick
-constexpr int BFACE = BNB + 2 * BP * BP; // face-buffer slots per brick (see face_slot)
 constexpr int NXCD = 8;
 
 // LDS layout of a staged brick field: node (lx, ly, lz) at lx + R ly + R BP lz.
@@ -46,12 +44,23 @@ constexpr int NXCD = 8;
 // measured no faster there).
 template <typename T> __host__ __device__ constexpr int lds_row() { return sizeof(T) == 8 ? BP + 1 : BP; }
 template <typename T> __host__ __device__ constexpr int lds_plane() { return lds_row<T>() * BP; }
-// LDS entries of one staged field
-template <typename T> __host__ __device__ constexpr int lds_field() { return lds_plane<T>() * BP; }
+// LDS entries of one staged field of a brick BZ cells deep in z
+template <typename T, int BZ = BB> __host__ __device__ constexpr int lds_field() { return lds_plane<T>() * (2 * BZ + 1); }
 
-__host__ __device__ inline int64_t n_bricks(const KMesh &m)
+// Bricks are BB x BB x BZ cells; BZ = BB unless a kernel says otherwise.
+// Per brick: threads (cells), node planes along z, nodes, face-buffer slots.
+template <int BZ> struct BrickDims {
+    static constexpr int NT = BB * BB * BZ;
+    static constexpr int PZ = 2 * BZ + 1;
+    static constexpr int NNODES = BP * BP * PZ;
+    static constexpr int NFACE = NNODES + 2 * BP * PZ; // see face_slot
+};
+constexpr int BNB = BrickDims<BB>::NNODES;  // nodes per 4x4x4 brick
+constexpr int BFACE = BrickDims<BB>::NFACE; // its face-buffer slots
+
+template <int BZ = BB> __host__ __device__ inline int64_t n_bricks(const KMesh &m)
 {
-    return (int64_t)((m.nx + BB - 1) / BB) * ((m.ny + BB - 1) / BB) * ((m.nz + BB - 1) / BB);
+    return (int64_t)((m.nx + BB - 1) / BB) * ((m.ny + BB - 1) / BB) * ((m.nz + BZ - 1) / BZ);
 }
 
 // Face-buffer slot of a brick node (only the slots of shared surface nodes
@@ -59,12 +68,16 @@ __host__ __device__ inline int64_t n_bricks(const KMesh &m)
 // of their own, (side, ly, lz) with ly fastest, so that the combine pass
 // reads them in runs along y; every other node keeps its lexicographic brick
 // index, so that runs along x stay contiguous.
-__host__ __device__ __forceinline__ constexpr int face_slot(int lx, int ly, int lz)
+template <int BZ = BB> __host__ __device__ __forceinline__ constexpr int face_slot(int lx, int ly, int lz)
 {
-    return (lx == 0 || lx == 2 * BB) ? BNB + (lx ? BP * BP : 0) + ly + BP * lz : lx + BP * (ly + BP * lz);
+    return (lx == 0 || lx == 2 * BB) ? BrickDims<BZ>::NNODES + (lx ? BP * (2 * BZ + 1) : 0) + ly + BP * lz
+                                     : lx + BP * (ly + BP * lz);
 }
 
-struct Brick {
+template <int BZ> struct BrickT {
+    static constexpr int NT = BrickDims<BZ>::NT, PZ = BrickDims<BZ>::PZ;
+    static constexpr int NNODES = BrickDims<BZ>::NNODES, NFACE = BrickDims<BZ>::NFACE;
+
     int brick;         // natural brick index (x fastest)
     int bx, by, bz;    // brick coordinates
     int c0x, c0y, c0z; // first cell of the brick
@@ -74,7 +87,7 @@ struct Brick {
     bool valid;
     bool lastx, lasty, lastz;
 
-    __device__ __forceinline__ Brick(const KMesh &m, int slot) : Brick(m, slot, xcd_index()) {}
+    __device__ __forceinline__ BrickT(const KMesh &m, int slot) : BrickT(m, slot, xcd_index()) {}
 
     // XCD-contiguous numbering: workgroup b runs on XCD b % 8; XCD k gets
     // the workgroup indices [start_k, start_k + count_k).
@@ -86,7 +99,7 @@ struct Brick {
     }
 
     // The brick of natural index b.
-    __device__ __forceinline__ Brick(const KMesh &m, int slot, int b) : t(slot)
+    __device__ __forceinline__ BrickT(const KMesh &m, int slot, int b) : t(slot)
     {
         brick = b;
         const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB;
@@ -95,10 +108,10 @@ struct Brick {
         bz = brick / (nbx * nby);
         c0x = bx * BB;
         c0y = by * BB;
-        c0z = bz * BB;
+        c0z = bz * BZ;
         ncx = min(BB, m.nx - c0x);
         ncy = min(BB, m.ny - c0y);
-        ncz = min(BB, m.nz - c0z);
+        ncz = min(BZ, m.nz - c0z);
         tx = t & (BB - 1);
         ty = (t / BB) & (BB - 1);
         tz = t / (BB * BB);
@@ -119,7 +132,7 @@ struct Brick {
         const int lex = (2 * tx + a) + BP * ((2 * ty + b) + BP * (2 * tz + c));
         if (a == 1) return lex;
         const bool xface = a == 0 ? tx == 0 : tx == BB - 1;
-        return xface ? BNB + (a ? BP * BP : 0) + (2 * ty + b) + BP * (2 * tz + c) : lex;
+        return xface ? NNODES + (a ? BP * PZ : 0) + (2 * ty + b) + BP * (2 * tz + c) : lex;
     }
 
     __device__ __forceinline__ int64_t cell_index(const KMesh &m) const
@@ -292,12 +305,12 @@ struct Brick {
                     if constexpr (NF == 2) l1s[l] = v1[a + 3 * b + 9 * c];
                 }
     }
-    // Node-parallel staging over a workgroup of NT threads (tid = the
+    // Node-parallel staging over a workgroup of WG threads (tid = the
     // thread's index in it) of NF fields of 8-byte entries: field f is read
     // from src[f] into the LDS region dst[f]; with MASK, a field with bit f
     // of maskbits set reads its Dirichlet nodes as zero.  Thread tid takes
     // the node column l_x = tid mod 9 of the rows (l_y, l_z) = row0 + RPI k,
-    // row0 = tid div 9 and RPI = NT div 9 rows per step (the NT mod 9 threads
+    // row0 = tid div 9 and RPI = WG div 9 rows per step (the WG mod 9 threads
     // left over idle), so each step reads RPI whole 9-node rows, contiguous
     // along x, and the row index advances by constant steps (no per-node
     // division or multiply).  Every brick node is read once; all reads are
@@ -306,14 +319,14 @@ struct Brick {
     // the buffer resource's range and read as zero, and no valid cell reads
     // their LDS slots.  Steps past the last row write to the row padding
     // (slot 9 of row 0), which nothing reads.
-    template <int NT, int NF, bool MASK, typename T>
+    template <int WG, int NF, bool MASK, typename T>
     __device__ __forceinline__ void stage_rows(const KMesh &m, int tid, const T *const (&src)[NF],
                                                T *const (&dst)[NF], unsigned maskbits) const
     {
         static_assert(sizeof(T) == 8, "8-byte entries (padded LDS rows)");
         constexpr int R = lds_row<T>(), P = lds_plane<T>();
         static_assert(R > BP, "the padding slot of row 0 takes the writes of the idle steps");
-        constexpr int RPI = NT / BP, K = (BP * BP + RPI - 1) / RPI;
+        constexpr int RPI = WG / BP, K = (BP * PZ + RPI - 1) / RPI;
         constexpr int DLY = RPI % BP, DLZ = RPI / BP;
         __amdgpu_buffer_rsrc_t rs[NF];
 #pragma unroll
@@ -343,7 +356,7 @@ struct Brick {
                     lo += P - BP * R;
                 }
             }
-            const bool ok = active && lz < BP;
+            const bool ok = active && lz < PZ;
             slot[k] = ok ? lo : BP; // padding slot of row 0
             con[k] = MASK && ok && node_constrained(m, 2 * c0x + lx, 2 * c0y + ly, 2 * c0z + lz);
 #pragma unroll
@@ -355,7 +368,7 @@ struct Brick {
             for (int f = 0; f < NF; ++f) dst[f][slot[k]] = (MASK && ((maskbits >> f) & 1u) && con[k]) ? T(0) : v[k][f];
     }
 
-    // The brick's NF (1 or 2) unmasked 8-byte fields, staged by its 64 lanes.
+    // The brick's NF (1 or 2) unmasked 8-byte fields, staged by its NT lanes.
     template <int NF, typename T>
     __device__ __forceinline__ void stage_nodes(const KMesh &m, const T *__restrict__ g0, T *l0s,
                                                 const T *__restrict__ g1, T *l1s) const
@@ -363,22 +376,22 @@ struct Brick {
         if constexpr (NF == 1) {
             const T *src[1] = {g0};
             T *const dst[1] = {l0s};
-            stage_rows<BNT, 1, false, T>(m, t, src, dst, 0u);
+            stage_rows<NT, 1, false, T>(m, t, src, dst, 0u);
         } else {
             const T *src[2] = {g0, g1};
             T *const dst[2] = {l0s, l1s};
-            stage_rows<BNT, 2, false, T>(m, t, src, dst, 0u);
+            stage_rows<NT, 2, false, T>(m, t, src, dst, 0u);
         }
     }
 
-    // NF FP64 fields over a workgroup of NT threads; bit f of maskbits: field f
+    // NF FP64 fields over a workgroup of WG threads; bit f of maskbits: field f
     // reads its Dirichlet nodes as zero.
-    template <int NT, int NF>
+    template <int WG, int NF>
     __device__ __forceinline__ void stage_nodes_wg(const KMesh &m, int tid, const double *const (&src)[NF],
                                                    double *const (&dst)[NF], unsigned maskbits) const
     {
-        if (maskbits) stage_rows<NT, NF, true, double>(m, tid, src, dst, maskbits);
-        else stage_rows<NT, NF, false, double>(m, tid, src, dst, 0u);
+        if (maskbits) stage_rows<WG, NF, true, double>(m, tid, src, dst, maskbits);
+        else stage_rows<WG, NF, false, double>(m, tid, src, dst, 0u);
     }
 
     template <typename T> __device__ __forceinline__ void load_fields(const KMesh &m, const T *g0, T *l0s) const
@@ -428,13 +441,13 @@ struct Brick {
                 for (int a = 0; a < 3; ++a) v[a + 3 * b + 9 * c] = lds[l0 + a + R * b + P * c];
     }
 
-    // Cell results, node-major: E[local * BNT + thread].  A thread without a
+    // Cell results, node-major: E[local * NT + thread].  A thread without a
     // cell stores whatever it computed: node_sum reads only the lower
     // neighbours of a valid cell within the brick, and those are valid too.
     template <typename T> __device__ __forceinline__ void store_cell(T *E, const T *v) const
     {
 #pragma unroll
-        for (int i = 0; i < 27; ++i) E[i * BNT + t] = v[i];
+        for (int i = 0; i < 27; ++i) E[i * NT + t] = v[i];
     }
 
     // Lane shift within the 16-lane rows of the wavefront (DPP row_shr:S):
@@ -461,7 +474,8 @@ struct Brick {
     // and in y lane t - 4, both in the same 16-lane row (a DPP row shift;
     // the first cell of an x line is masked, the first of a y line is at a
     // row's start and takes zero), and in z lane t - 16, exchanged through
-    // LDS (xch, 9 BNT values).  The sums run x, then y, then z: a fixed order.
+    // LDS (xch, 9 NT values; with two wavefronts per brick the exchange
+    // between tz = 3 and tz = 4 crosses them).  The sums run x, then y, then z: a fixed order.
     // All lanes of the wavefront must call it.
     template <typename T> __device__ __forceinline__ void assemble27(T *u, T *xch) const
     {
@@ -475,12 +489,12 @@ struct Brick {
 #pragma unroll
             for (int a = 0; a < 3; ++a) u[a + 9 * c] += row_shr<4>(u[a + 6 + 9 * c]);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) xch[i * BNT + t] = u[18 + i];
+        for (int i = 0; i < 9; ++i) xch[i * NT + t] = u[18 + i];
         __syncthreads();
         const int src = tz > 0 ? t - BB * BB : t;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const T nb = xch[i * BNT + src];
+            const T nb = xch[i * NT + src];
             u[i] += tz > 0 ? nb : T(0);
         }
     }
@@ -491,7 +505,7 @@ struct Brick {
     // missing neighbour (brick edge) reads this cell's slot, weighted by 0.
     template <typename T> __device__ __forceinline__ T node_sum(const T *E, int a, int b, int c) const
     {
-        T s = E[(a + 3 * b + 9 * c) * BNT + t];
+        T s = E[(a + 3 * b + 9 * c) * NT + t];
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
@@ -503,11 +517,13 @@ struct Brick {
                     const bool ok = !((dx && tx == 0) || (dy && ty == 0) || (dz && tz == 0));
                     const int loc = (a + 2 * dx) + 3 * (b + 2 * dy) + 9 * (c + 2 * dz);
                     const int nb = ok ? t - dx - BB * dy - BB * BB * dz : t;
-                    s += (ok ? T(1) : T(0)) * E[loc * BNT + nb];
+                    s += (ok ? T(1) : T(0)) * E[loc * NT + nb];
                 }
         return s;
     }
 };
+
+using Brick = BrickT<BB>;
 
 // ---------------------------------------------------------------------------
 // Shared-node combine.  The nodes that several bricks touch lie on the
@@ -642,24 +658,33 @@ __device__ __forceinline__ void combine_visit(const KMesh &m, const T *__restric
     }
 }
 
-// Brick-owned combine: one workgroup of BNT threads per brick (numbered like
-// the brick kernels, XCD-contiguously).  Each shared node is finished by the
-// one brick that holds it at local index 0 in every direction in which it
-// is shared: the brick's nodes on its low faces that lie on internal brick
-// planes, without its shared high faces (the next brick's low faces).  For
-// a brick with lower neighbours in x, y and z that is up to 64 + 56 + 49
-// nodes (217 for a brick at the far end of the mesh in every direction), at
-// most four per thread, enumerated in three slabs: l_z = 0 (runs along x);
-// l_y = 0 (runs along x); l_x = 0 (runs along y, where the x-face slots are
-// contiguous).  The partials are summed in the order of combine_visit (z
-// outer, then y, then x; lower brick first), so the two give bitwise the
-// same result; all loads of a thread's nodes are issued before the sums.
-template <typename T, bool SKIP_CONSTRAINED, typename F>
+// Brick-owned combine: a wavefront per 4 cells of brick depth (numbered
+// like the brick kernels, XCD-contiguously).  Each shared node is finished
+// by the one brick that holds it at local index 0 in every direction in
+// which it is shared: the brick's nodes on its low faces that lie on
+// internal brick planes, without its shared high faces (the next brick's
+// low faces).  For a 4x4x4 brick with lower neighbours in x, y and z that is
+// up to 64 + 56 + 49 nodes (217 for a brick at the far end of the mesh in
+// every direction), at most four per lane; a 4x4x8 brick has up to
+// 81 + 144 + 128 = 353 over two wavefronts, three per lane.  They are
+// enumerated in three slabs: l_z = 0 (runs along x); l_y = 0 (runs along x);
+// l_x = 0 (runs along y, where the x-face slots are contiguous).  The
+// partials are summed in the order of combine_visit (z outer, then y, then
+// x; lower brick first), so the two give bitwise the same result for
+// BZ = BB; all loads of a lane's nodes are issued before the sums.
+// Lanes that finish one brick's shared nodes: a wavefront per 4 cells of
+// brick depth.
+template <int BZ> struct CombineLanes {
+    static constexpr int value = BNT * BZ / BB;
+};
+
+template <typename T, bool SKIP_CONSTRAINED, int BZ = BB, typename F>
 __device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, int lane, const T *__restrict__ face,
                                                     F f)
 {
-    const Brick br(m, lane, brick);
-    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
+    using BD = BrickDims<BZ>;
+    const BrickT<BZ> br(m, lane, brick);
+    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BZ - 1) / BZ;
     const bool fx = br.bx > 0, fy = br.by > 0, fz = br.bz > 0; // lower neighbour: the low face is shared
     const int ex = 2 * br.ncx + (br.bx == nbx - 1 ? 1 : 0);     // local range without a shared high face
     const int ey = 2 * br.ncy + (br.by == nby - 1 ? 1 : 0);
@@ -667,15 +692,17 @@ __device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, i
     const int z0 = fz ? 1 : 0, y0 = fy ? 1 : 0;
     const int nzs = fz ? ex * ey : 0, nys = fy ? ex * (ez - z0) : 0, nxs = fx ? (ey - y0) * (ez - z0) : 0;
     const int tot = nzs + nys + nxs;
-    // small exact divisions: floor((j + 1/2) / w) for j < 256, w <= 9
+    // small exact divisions: floor((j + 1/2) / w) for j < 512, w <= 9
     const float iex = 1.0f / (float)ex, iw = 1.0f / (float)(ey - y0);
-    constexpr int K = 4;
+    // nodes per lane: BP^2 + 2 BP (PZ - 1) at most over the brick's lanes
+    constexpr int L = CombineLanes<BZ>::value;
+    constexpr int K = (BP * BP + 2 * BP * (BD::PZ - 1) + L - 1) / L;
     bool has[K], con[K];
     int64_t g[K];
     T v[K][8];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        int j = lane + BNT * k;
+        int j = lane + L * k;
         has[k] = j < tot;
         int lx = 0, ly = 0, lz = 0;
         if (j < nzs) {
@@ -699,14 +726,14 @@ __device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, i
         const bool sx = lx == 0 && fx, sy = ly == 0 && fy, sz = lz == 0 && fz;
         const int kx0 = sx ? br.bx - 1 : br.bx, lx0 = sx ? 2 * BB : lx;
         const int ky0 = sy ? br.by - 1 : br.by, ly0 = sy ? 2 * BB : ly;
-        const int kz0 = sz ? br.bz - 1 : br.bz, lz0 = sz ? 2 * BB : lz;
+        const int kz0 = sz ? br.bz - 1 : br.bz, lz0 = sz ? 2 * BZ : lz;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int ex_ = e & 1, ey_ = (e >> 1) & 1, ez_ = e >> 2;
             v[k][e] = T(0);
             if (read && (!ex_ || sx) && (!ey_ || sy) && (!ez_ || sz)) {
                 const int b = (kx0 + ex_) + nbx * ((ky0 + ey_) + nby * (kz0 + ez_));
-                v[k][e] = face[(int64_t)b * BFACE + face_slot(ex_ ? 0 : lx0, ey_ ? 0 : ly0, ez_ ? 0 : lz0)];
+                v[k][e] = face[(int64_t)b * BD::NFACE + face_slot<BZ>(ex_ ? 0 : lx0, ey_ ? 0 : ly0, ez_ ? 0 : lz0)];
             }
         }
     }
@@ -720,16 +747,18 @@ __device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, i
     }
 }
 
-// CBW bricks per workgroup, one per wavefront.
+// Threads of a brick-combine workgroup: 4 bricks of 4x4x4 cells, 2 of 4x4x8.
 constexpr int CBW = 4;
 
-template <typename T, int DMODE>
+template <typename T, int DMODE, int BZ = BB>
 __device__ __forceinline__ void combine_brick(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
                                               T *__restrict__ y)
 {
-    const int brick = Brick::xcd_index() * CBW + (int)threadIdx.x / BNT;
-    if (brick >= n_bricks(m)) return; // a whole wavefront; no barrier follows in it
-    combine_brick_visit<T, DMODE != 0>(m, brick, (int)threadIdx.x % BNT, face, [&](int64_t g, bool constrained, T s) {
+    constexpr int L = CombineLanes<BZ>::value, BPW = BNT * CBW / L; // bricks per workgroup
+    const int brick = Brick::xcd_index() * BPW + (int)threadIdx.x / L;
+    if (brick >= n_bricks<BZ>(m)) return; // whole wavefronts; no barrier follows in them
+    combine_brick_visit<T, DMODE != 0, BZ>(m, brick, (int)threadIdx.x % L, face,
+                                           [&](int64_t g, bool constrained, T s) {
         if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
         else y[g] = s;
     });

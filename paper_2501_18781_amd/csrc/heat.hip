@@ -84,8 +84,8 @@ __device__ __forceinline__ void heat_cell_coeffs(const HeatArgs &a, T *phq, cons
 //   k, rc = H (H_s a_s + (1 - H_s) a_l) + (1 - H) a_g         (H_s = 0 without a.tc)
 //   cm_q = |J| w_q (alpha_m rc + beta H' |grad phi| rc_lg c_rcp),  ck_q = alpha_k |J| w_q k / r^2
 // with rc_lg the liquid-gas blend of eq. deltaRhoCp.
-template <int HK>
-__device__ __forceinline__ void heat_cell_coeffs3(const Brick &br, const KMesh &m, const HeatArgs &a,
+template <int HK, typename BR>
+__device__ __forceinline__ void heat_cell_coeffs3(const BR &br, const KMesh &m, const HeatArgs &a,
                                                   const double *ps, const double *ts, double *cm, double *ck,
                                                   double ck_scale = 1.0)
 {
@@ -307,34 +307,39 @@ __device__ __forceinline__ void heat_conv_cell_apply(const Brick &br, const KMes
 }
 
 // CONV: 0 plain heat operator; 1 with the convective term; 2 its transpose
-// (FP64, level-set coefficients, no CG epilogue).
-template <typename T, int MODE, int HK, bool CG, int CONV = 0, bool ISO = false>
-__global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, const T *__restrict__ x,
-                                                         T *__restrict__ y, T *__restrict__ face, CGState *cg,
-                                                         RedWS red)
+// (FP64, level-set coefficients, no CG epilogue).  Bricks of 4 x 4 x BZ
+// cells, one thread per cell (BZ = 8: two wavefronts per brick).
+template <typename T, int MODE, int HK, bool CG, int CONV = 0, bool ISO = false, int BZ = BB>
+__global__ void __launch_bounds__(BrickDims<BZ>::NT) heat_apply_kernel(KMesh m, HeatArgs a, const T *__restrict__ x,
+                                                                       T *__restrict__ y, T *__restrict__ face,
+                                                                       CGState *cg, RedWS red)
 {
     static_assert(CONV == 0 || (std::is_same<T, double>::value && MODE == 0 && !CG), "convective form: FP64 only");
     static_assert(MODE != 2 || std::is_same<T, double>::value, "three-phase coefficients: FP64 only");
+    static_assert(CONV == 0 || BZ == BB, "convective form: 4x4x4 bricks (its velocity staging)");
+    using BR = BrickT<BZ>;
+    constexpr int NT = BR::NT;
     // x stays resident (Dirichlet rows y = x and the CG epilogue read it);
     // the second region takes phi (with one velocity component at a time, or
     // the frozen temperature), then the z exchange of the node sums (for the
     // transposed convective form, the cell results).
-    constexpr int NB = lds_field<T>(); // one staged field
-    constexpr int STAGE = CONV == 2 ? 27 * BNT : ((CONV || MODE == 2) ? 2 * NB : NB);
+    constexpr int NB = lds_field<T, BZ>(); // one staged field
+    constexpr int STAGE = CONV == 2 ? 27 * NT : ((CONV || MODE == 2) ? 2 * NB : NB);
+    static_assert(STAGE >= 9 * NT, "the second region takes the z exchange of the node sums");
     constexpr int LDS_T = NB + STAGE;
     __shared__ T lds[LDS_T];
-    __shared__ double red_lds[BNT];
+    __shared__ double red_lds[NT];
     if (CG) {
         if (cg->done) return; // converged or broken down: the rest of the batch is a no-op
     }
-    const Brick br(m, threadIdx.x);
+    const BR br(m, threadIdx.x);
     T *xs = lds;
     T *ps = lds + NB;
     if constexpr (MODE == 2) {
         if (a.tc) {
             const double *src[3] = {(const double *)x, (const double *)a.phi, (const double *)a.tc};
             double *const dst[3] = {(double *)xs, (double *)ps, (double *)ps + NB};
-            br.stage_nodes_wg<BNT, 3>(m, threadIdx.x, src, dst, 0u);
+            br.template stage_nodes_wg<NT, 3>(m, threadIdx.x, src, dst, 0u);
         } else {
             br.template stage_nodes<2, T>(m, x, xs, (const T *)a.phi, ps);
         }
@@ -398,7 +403,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     // with x_i^2 for a Dirichlet node counted once, by the brick that
     // finishes it.
     double energy = 0.0;
-    T *fb = face + (int64_t)br.brick * BFACE;
+    T *fb = face + (int64_t)br.brick * BR::NFACE;
     br.template for_owned_nodes<T>(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int sh) {
         const T xv = xs[l], s = u[ai + 3 * bi + 9 * ci];
         if (CG) energy += constrained ? ((sh & 2) ? 0.0 : (double)xv * (double)xv) : (double)xv * (double)s;
@@ -407,7 +412,7 @@ __global__ void __launch_bounds__(BNT) heat_apply_kernel(KMesh m, HeatArgs a, co
     });
     if (CG) {
         // one partial per brick; the alpha kernel sums them in brick order
-        const double tot = block_sum<BNT>(energy, red_lds);
+        const double tot = block_sum<NT>(energy, red_lds);
         write_partials<1>(&tot, red.partials, gridDim.x, (unsigned)br.brick);
     }
 }
@@ -446,7 +451,7 @@ __global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__r
 
 // The same pass with one workgroup per brick finishing the shared nodes it
 // owns (combine_brick in brick.hpp); bitwise the same result.
-template <typename T, bool CG, int DMODE = 1>
+template <typename T, bool CG, int DMODE = 1, int BZ = BB>
 __global__ void __launch_bounds__(BNT * CBW) face_combine_brick_kernel(KMesh m, const T *__restrict__ face,
                                                                  const T *__restrict__ x, T *__restrict__ y,
                                                                  CGState *cg, const double *__restrict__ partials,
@@ -470,23 +475,58 @@ __global__ void __launch_bounds__(BNT * CBW) face_combine_brick_kernel(KMesh m, 
             }
         }
     }
-    combine_brick<T, DMODE>(m, face, x, y);
+    combine_brick<T, DMODE, BZ>(m, face, x, y);
 }
 
-constexpr int APPLY_NPT = 2; // nodes per thread in the combine pass of the applies
+// Brick depth of the FP32 applies (the multigrid levels): 4x4x8 cells, two
+// wavefronts per brick.  Against 4x4x4 bricks this halves the internal z
+// planes of the brick grid, and with them the face-buffer partials and the
+// combine pass's z-shared nodes (128^3 FP32 whole apply about 5 % faster).
+// The FP64 applies keep 4x4x4 bricks: there the deeper brick made the brick
+// kernel slower by as much as it made the combine faster.
+constexpr int HEAT_BZ32 = 8;
 
-int64_t face_buffer_elems(const KMesh &m) { return n_bricks(m) * BFACE; }
+int64_t face_buffer_elems(const KMesh &m)
+{
+    const int64_t b4 = n_bricks<BB>(m) * BrickDims<BB>::NFACE;
+    const int64_t b8 = n_bricks<HEAT_BZ32>(m) * BrickDims<HEAT_BZ32>::NFACE;
+    return b4 > b8 ? b4 : b8;
+}
+
+// One apply: the brick kernel, then the combine pass of its shared nodes
+// (with CG, alpha from the bricks' partials of p.Ap).  With timing on, the
+// events are attached to the brick kernel's own dispatch (they record its
+// start and end, not the neighbouring queue packets).
+template <typename T, int MODE, int HK, bool CGF, int CV, bool ISO>
+static hipError_t heat_apply_launch(const KMesh &m, const HeatArgs &a, const void *x, void *y, void *face,
+                                    CGState *cg, const RedWS &r, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    constexpr int BZ = sizeof(T) == 4 ? HEAT_BZ32 : BB;
+    constexpr int NT = BrickDims<BZ>::NT;
+    const unsigned nb = (unsigned)n_bricks<BZ>(m);
+    if (ev0)
+        hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF, CV, ISO, BZ>, dim3(nb), dim3(NT), 0, s, ev0, ev1, 0,
+                              m, a, (const T *)x, (T *)y, (T *)face, cg, r);
+    else
+        heat_apply_kernel<T, MODE, HK, CGF, CV, ISO, BZ><<<nb, NT, 0, s>>>(m, a, (const T *)x, (T *)y, (T *)face, cg, r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // a single brick shares nothing; alpha from its partial
+    if (nb == 1) return CGF ? cg_alpha(cg, &r, nb, s) : hipSuccess;
+    constexpr int BPW = BNT * CBW / CombineLanes<BZ>::value; // bricks per combine workgroup
+    face_combine_brick_kernel<T, CGF, 1, BZ><<<(nb + BPW - 1) / BPW, BNT * CBW, 0, s>>>(
+        m, (const T *)face, (const T *)x, (T *)y, CGF ? cg : nullptr, CGF ? r.partials : nullptr, CGF ? nb : 0u);
+    return hipGetLastError();
+}
 
 hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x, void *y, void *face, CGState *cg,
                       const RedWS *red, hipStream_t s, const KTiming *t)
 {
-    const unsigned nb = (unsigned)n_bricks(m);
+    const unsigned nb = (unsigned)n_bricks(m); // the most bricks of any layout
     RedWS r = red ? *red : RedWS{nullptr, 0};
     if (!face) return hipErrorInvalidValue;
     if (cg && (!red || red->capacity < nb)) return hipErrorInvalidValue;
     if (fp32 && cg) return hipErrorInvalidValue;
-    // With timing on, the events are attached to the kernel's own dispatch
-    // (they record its start and end, not the neighbouring queue packets).
     hipEvent_t ev0 = t ? t->start : nullptr, ev1 = t ? t->stop : nullptr;
     if (a.conv && (fp32 || cg || a.mode != 0 || !a.u0)) return hipErrorInvalidValue;
     if (a.mode == 2 && fp32) return hipErrorInvalidValue;
@@ -498,13 +538,7 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     switch (key) {
 #define HEAT_CASE(K, T, MODE, HK, CGF, CV, ISO)                                                               \
     case K:                                                                                                   \
-        if (ev0)                                                                                              \
-            hipExtLaunchKernelGGL(heat_apply_kernel<T, MODE, HK, CGF, CV, ISO>, dim3(nb), dim3(BNT), 0, s, ev0, \
-                                  ev1, 0, m, a, (const T *)x, (T *)y, (T *)face, cg, r);                      \
-        else                                                                                                  \
-            heat_apply_kernel<T, MODE, HK, CGF, CV, ISO><<<nb, BNT, 0, s>>>(m, a, (const T *)x, (T *)y,        \
-                                                                            (T *)face, cg, r);                \
-        break;
+        return heat_apply_launch<T, MODE, HK, CGF, CV, ISO>(m, a, x, y, face, cg, r, s, ev0, ev1);
         HEAT_CASE(0, double, 0, 0, false, 0, false)
         HEAT_CASE(1, double, 0, 0, true, 0, false)
         HEAT_CASE(2, double, 0, 1, false, 0, false)
@@ -543,22 +577,6 @@ hipError_t heat_apply(const KMesh &m, const HeatArgs &a, int fp32, const void *x
     default:
         return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const unsigned rows = combine_blocks(m, APPLY_NPT);
-    if (rows == 0) {
-        // single brick: nothing shared; alpha from the brick's partial
-        return cg ? cg_alpha(cg, &r, nb, s) : hipSuccess;
-    } else if (fp32)
-        face_combine_brick_kernel<float, false, 1><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const float *)face, (const float *)x,
-                                                                     (float *)y, nullptr, nullptr, 0);
-    else if (cg)
-        face_combine_brick_kernel<double, true, 1><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const double *)face, (const double *)x,
-                                                                     (double *)y, cg, r.partials, nb);
-    else
-        face_combine_brick_kernel<double, false, 1><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const double *)face, (const double *)x,
-                                                                      (double *)y, nullptr, nullptr, 0);
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
