@@ -136,6 +136,45 @@ def test_heat_apply_fp32(gpu, n, dirichlet):
     assert relerr(y, A @ x.astype(np.float64)) <= TOL32
 
 
+# Meshes around the 4x4x8-cell bricks of the FP32 applies: exactly one brick,
+# ragged z tails, several bricks along z, equal and unequal cell edges.
+DEEP = [((4, 4, 8), W.ALL_FACES), ((3, 2, 9), 0), ((6, 5, 19), W.FACE_ZLO | W.FACE_YHI),
+        ((12, 12, 12), W.FACE_YLO | W.FACE_ZHI), ((5, 9, 17), W.FACE_XHI)]
+
+
+@pytest.mark.parametrize("hkind", [0, 1])
+@pytest.mark.parametrize("n,dirichlet", DEEP)
+def test_heat_apply_fp32_deep_bricks(gpu, n, dirichlet, hkind):
+    mesh, p, phi = heat_case(n, dirichlet, hkind=hkind)
+    print(f"heat apply fp32 n={n} dirichlet={dirichlet} hkind={hkind}", flush=True)
+    phi32 = phi.astype(np.float32)
+    A = O.heat_matrix(mesh, p, phi=phi32.astype(np.float64))
+    x = W.uniform(4, mesh.n_nodes).astype(np.float32)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, phi=dev(phi32, torch.float32), precision=mf.MF_FP32)
+    y = torch.empty(mesh.n_nodes, dtype=torch.float32, device="cuda")
+    mf.operator_apply(op, dev(x, torch.float32), y)
+    assert relerr(y, A @ x.astype(np.float64)) <= TOL32
+
+
+@pytest.mark.parametrize("n", [(6, 6, 6), (7, 4, 13)])
+def test_heat_apply_fp32_quadrature_point_coefficients(gpu, n):
+    mesh = W.Mesh(n, dirichlet=W.FACE_ZLO | W.FACE_XHI)
+    print(f"heat apply fp32, coefficients per quadrature point, n={n}", flush=True)
+    rng = np.random.default_rng(6)
+    kq = rng.uniform(0.3, 30.0, mesh.n_cells * 27).astype(np.float32)
+    rcq = rng.uniform(5e3, 5e6, mesh.n_cells * 27).astype(np.float32)
+    p = W.HeatParams()
+    x = W.uniform(5, mesh.n_nodes).astype(np.float32)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, k_q=dev(kq, torch.float32), rc_q=dev(rcq, torch.float32), precision=mf.MF_FP32)
+    y = torch.empty(mesh.n_nodes, dtype=torch.float32, device="cuda")
+    for am in (p.alpha_m, 0.0):  # the whole operator, then the stiffness part alone
+        A = O.heat_matrix(mesh, p, kq=kq.astype(np.float64), rcq=rcq.astype(np.float64), alpha_m=am)
+        mf.operator_apply(op.with_alphas(alpha_m=am), dev(x, torch.float32), y)
+        assert relerr(y, A @ x.astype(np.float64)) <= TOL32, am
+
+
 @pytest.mark.parametrize("n,dirichlet", MESHES[1:4])
 def test_heat_diagonal(gpu, n, dirichlet):
     mesh, p, phi = heat_case(n, dirichlet)
