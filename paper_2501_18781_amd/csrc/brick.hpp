@@ -1,12 +1,15 @@
 // brick.hpp -- the cell-brick work unit shared by the operator kernels.
 //
 // A 64-thread workgroup (one wavefront) owns a brick of 4x4x4 cells, one
-// thread per cell; the brick's 9x9x9 Q2 nodes are staged in LDS.
+// thread per cell; the brick's 9x9x9 Q2 nodes are staged in LDS.  The brick
+// code is templated on the brick's depth along z (BrickT<BZ>): the FP32
+// heat applies take 4x4x8 cells, two wavefronts per workgroup and 9x9x17
+// nodes.
 //
 // Staging is per cell (each thread reads the 27 nodes of its cell and
 // writes them to LDS; nodes shared by cells of the brick are written with
-// the same value by each) or per node (each lane stages every 64th node of
-// the brick; used by the FP64 heat apply).  Finishing is by ownership: a cell owns its
+// the same value by each) or per node (the lanes stage whole 9-node rows of
+// the brick; used by the FP64 kernels).  Finishing is by ownership: a cell owns its
 // local nodes (a, b, c) with a, b, c in {0, 1}, and the last valid cell of
 // the brick in a direction also owns the local nodes with index 2 in that
 // direction, so every brick node is finished by exactly one thread, with
