@@ -188,6 +188,32 @@ template <int BZ> struct BrickT {
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
+        // A brick with neighbours on all six sides and no Dirichlet face:
+        // nothing is constrained, a low node is shared exactly on the
+        // brick's low faces and every high node is shared.  Such bricks take
+        // a copy of the visits with these flags folded in (a uniform branch;
+        // 26.1 -> 25.6 us for the FP64 apply kernel at 64^3).
+        const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BZ - 1) / BZ;
+        const bool inner = bx > 0 && by > 0 && bz > 0 && bx < nbx - 1 && by < nby - 1 && bz < nbz - 1 &&
+                           !touches_dirichlet(m);
+        auto inode = [&](auto A, auto B, auto C) {
+            constexpr int a = decltype(A)::value, b = decltype(B)::value, c = decltype(C)::value;
+            constexpr bool hi = a == 2 || b == 2 || c == 2;
+            const bool shared = hi || (a == 0 && tx == 0) || (b == 0 && ty == 0) || (c == 0 && tz == 0);
+            f(a, b, c, l0 + a + R * b + P * c, g0 + a + sy * b + sz * c, false, (shared ? 1 : 0) | (hi ? 2 : 0));
+        };
+        if (inner) {
+            inode(I0{}, I0{}, I0{}); inode(I1{}, I0{}, I0{}); inode(I0{}, I1{}, I0{}); inode(I1{}, I1{}, I0{});
+            inode(I0{}, I0{}, I1{}); inode(I1{}, I0{}, I1{}); inode(I0{}, I1{}, I1{}); inode(I1{}, I1{}, I1{});
+            if (lastx) { inode(I2{}, I0{}, I0{}); inode(I2{}, I1{}, I0{}); inode(I2{}, I0{}, I1{}); inode(I2{}, I1{}, I1{}); }
+            if (lasty) { inode(I0{}, I2{}, I0{}); inode(I1{}, I2{}, I0{}); inode(I0{}, I2{}, I1{}); inode(I1{}, I2{}, I1{}); }
+            if (lastz) { inode(I0{}, I0{}, I2{}); inode(I1{}, I0{}, I2{}); inode(I0{}, I1{}, I2{}); inode(I1{}, I1{}, I2{}); }
+            if (lastx && lasty) { inode(I2{}, I2{}, I0{}); inode(I2{}, I2{}, I1{}); }
+            if (lastx && lastz) { inode(I2{}, I0{}, I2{}); inode(I2{}, I1{}, I2{}); }
+            if (lasty && lastz) { inode(I0{}, I2{}, I2{}); inode(I1{}, I2{}, I2{}); }
+            if (lastx && lasty && lastz) inode(I2{}, I2{}, I2{});
+            return;
+        }
         node(I0{}, I0{}, I0{}); node(I1{}, I0{}, I0{}); node(I0{}, I1{}, I0{}); node(I1{}, I1{}, I0{});
         node(I0{}, I0{}, I1{}); node(I1{}, I0{}, I1{}); node(I0{}, I1{}, I1{}); node(I1{}, I1{}, I1{});
         if (lastx) { node(I2{}, I0{}, I0{}); node(I2{}, I1{}, I0{}); node(I2{}, I0{}, I1{}); node(I2{}, I1{}, I1{}); }
@@ -681,22 +707,26 @@ template <int BZ> struct CombineLanes {
     static constexpr int value = BNT * BZ / BB;
 };
 
-template <typename T, bool SKIP_CONSTRAINED, int BZ = BB, typename F>
-__device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, int lane, const T *__restrict__ face,
-                                                    F f)
+// The visit for one brick; INNER: a brick with neighbours on all six sides
+// and no Dirichlet face, for which the ranges, the sharing flags and the
+// slab divisions are compile-time constants and nothing is constrained.
+template <typename T, bool SKIP_CONSTRAINED, int BZ, bool INNER, typename F>
+__device__ __forceinline__ void combine_brick_nodes(const KMesh &m, const BrickT<BZ> &br, int nbx, int nby, int nbz,
+                                                    int lane, const T *__restrict__ face, F f)
 {
     using BD = BrickDims<BZ>;
-    const BrickT<BZ> br(m, lane, brick);
-    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BZ - 1) / BZ;
-    const bool fx = br.bx > 0, fy = br.by > 0, fz = br.bz > 0; // lower neighbour: the low face is shared
-    const int ex = 2 * br.ncx + (br.bx == nbx - 1 ? 1 : 0);     // local range without a shared high face
-    const int ey = 2 * br.ncy + (br.by == nby - 1 ? 1 : 0);
-    const int ez = 2 * br.ncz + (br.bz == nbz - 1 ? 1 : 0);
+    // lower neighbour: the low face is shared
+    const bool fx = INNER || br.bx > 0, fy = INNER || br.by > 0, fz = INNER || br.bz > 0;
+    // local range without a shared high face
+    const int ex = INNER ? 2 * BB : 2 * br.ncx + (br.bx == nbx - 1 ? 1 : 0);
+    const int ey = INNER ? 2 * BB : 2 * br.ncy + (br.by == nby - 1 ? 1 : 0);
+    const int ez = INNER ? 2 * BZ : 2 * br.ncz + (br.bz == nbz - 1 ? 1 : 0);
     const int z0 = fz ? 1 : 0, y0 = fy ? 1 : 0;
     const int nzs = fz ? ex * ey : 0, nys = fy ? ex * (ez - z0) : 0, nxs = fx ? (ey - y0) * (ez - z0) : 0;
     const int tot = nzs + nys + nxs;
     // small exact divisions: floor((j + 1/2) / w) for j < 512, w <= 9
     const float iex = 1.0f / (float)ex, iw = 1.0f / (float)(ey - y0);
+    auto div = [&](int j, int w, float iw_) { return INNER ? j / w : (int)(((float)j + 0.5f) * iw_); };
     // nodes per lane: BP^2 + 2 BP (PZ - 1) at most over the brick's lanes
     constexpr int L = CombineLanes<BZ>::value;
     constexpr int K = (BP * BP + 2 * BP * (BD::PZ - 1) + L - 1) / L;
@@ -709,21 +739,21 @@ __device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, i
         has[k] = j < tot;
         int lx = 0, ly = 0, lz = 0;
         if (j < nzs) {
-            ly = (int)(((float)j + 0.5f) * iex);
+            ly = div(j, ex, iex);
             lx = j - ly * ex;
         } else if ((j -= nzs) < nys) {
-            const int q = (int)(((float)j + 0.5f) * iex);
+            const int q = div(j, ex, iex);
             lz = z0 + q;
             lx = j - q * ex;
         } else {
             j -= nys;
-            const int w = ey - y0, q = (int)(((float)j + 0.5f) * iw);
+            const int w = ey - y0, q = div(j, w, iw);
             lz = z0 + q;
             ly = y0 + j - q * w;
         }
         if (!has[k]) lx = ly = lz = 0;
         const int gx = 2 * br.c0x + lx, gy = 2 * br.c0y + ly, gz = 2 * br.c0z + lz;
-        con[k] = has[k] && node_constrained(m, gx, gy, gz);
+        con[k] = !INNER && has[k] && node_constrained(m, gx, gy, gz);
         g[k] = node_index(m, gx, gy, gz);
         const bool read = has[k] && !(SKIP_CONSTRAINED && con[k]);
         const bool sx = lx == 0 && fx, sy = ly == 0 && fy, sz = lz == 0 && fz;
@@ -748,6 +778,18 @@ __device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, i
         for (int e = 1; e < 8; ++e) s += v[k][e];
         f(g[k], con[k], (SKIP_CONSTRAINED && con[k]) ? T(0) : s);
     }
+}
+
+template <typename T, bool SKIP_CONSTRAINED, int BZ = BB, typename F>
+__device__ __forceinline__ void combine_brick_visit(const KMesh &m, int brick, int lane, const T *__restrict__ face,
+                                                    F f)
+{
+    const BrickT<BZ> br(m, lane, brick);
+    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BZ - 1) / BZ;
+    const bool inner = br.bx > 0 && br.by > 0 && br.bz > 0 && br.bx < nbx - 1 && br.by < nby - 1 &&
+                       br.bz < nbz - 1 && !br.touches_dirichlet(m);
+    if (inner) combine_brick_nodes<T, SKIP_CONSTRAINED, BZ, true>(m, br, nbx, nby, nbz, lane, face, f);
+    else combine_brick_nodes<T, SKIP_CONSTRAINED, BZ, false>(m, br, nbx, nby, nbz, lane, face, f);
 }
 
 // Threads of a brick-combine workgroup: 4 bricks of 4x4x4 cells, 2 of 4x4x8.
