@@ -663,11 +663,18 @@ def oseen_bench(dev, applies=50):
     op = mf.oseen_operator(ctx, wl.params, dev(wl.phi), dev(wl.u0))
     xr = dev(W.uniform(1, nd))
     b = torch.empty_like(xr)
-    out = {"cells": 48, "velocity_dofs": nd}
+    # algorithmic bytes per velocity DoF: x, y, u0 (8 B each) and phi (8 B per 3 DoFs);
+    # operation estimate per velocity DoF: about 390 flops (interpolations of
+    # x, u0 and phi, the quadrature-point operator, the transposed integration)
+    bpd, fpd = 24 + 8 / 3, 390.0
+    out = {"cells": 48, "velocity_dofs": nd, "bytes_per_dof": bpd, "flops_per_dof_estimate": fpd}
     for label, fn in [("apply", mf.operator_apply), ("apply_transpose", mf.operator_apply_transpose)]:
-        us = _time_calls(lambda: fn(op, xr, b), applies) * 1e6
-        # algorithmic bytes per velocity DoF: x, y, u0 (8 B each) and phi (8 B per 3 DoFs)
-        out[label] = {"us": us, "dofs_per_s": nd / (us * 1e-6), "algorithmic_gbs": nd * (24 + 8 / 3) / (us * 1e-6) / 1e9}
+        whole, kt = _time_applies(ctx, fn, op, xr, b, applies)
+        out[label] = {"us": whole * 1e6, "dofs_per_s": nd / whole, "algorithmic_gbs": nd * bpd / whole / 1e9,
+                      "kernel_us": kt * 1e6, "kernel_algorithmic_gbs": nd * bpd / kt / 1e9,
+                      "kernel_tflops_estimate": nd * fpd / kt / 1e12,
+                      "hbm_frac": nd * bpd / kt / (PEAK_HBM_GBS * 1e9),
+                      "fp64_frac_estimate": nd * fpd / kt / (PEAK_FP64_TFLOPS * 1e12)}
     mf.operator_apply(op, xr, b)
     x = torch.empty_like(b)
     mf.gmres_solve(op, b, x, 1e-8, 3000, precond=mf.MF_PC_BLOCK_JACOBI, restart=30)  # warm
@@ -679,8 +686,8 @@ def oseen_bench(dev, applies=50):
     err = float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
     out["gmres30_block_jacobi"] = {"ms": t * 1e3, "iters": info.iters, "rel_res": info.rel_res,
                                    "converged": bool(info.converged), "rel_err_vs_x_ref": err}
-    log(f"[bench]   apply {out['apply']['us']:.1f} us, transpose {out['apply_transpose']['us']:.1f} us; "
-        f"GMRES(30) {info.iters} it {t * 1e3:.1f} ms, err {err:.1e}")
+    log(f"[bench]   apply {out['apply']['us']:.1f} us (kernel {out['apply']['kernel_us']:.1f}), transpose "
+        f"{out['apply_transpose']['us']:.1f} us; GMRES(30) {info.iters} it {t * 1e3:.1f} ms, err {err:.1e}")
     return out
 
 
