@@ -149,6 +149,7 @@ void mf_destroy(mf_ctx *c)
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
+    if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
     delete c;
 }
 
@@ -494,10 +495,11 @@ mf_status true_residual(mf_ctx *c, const mf_operator *op, int transpose, const d
 {
     const int64_t n = ndofs(c, op);
     HIPCHK(c, apply_any(c, op, transpose, x, tmp, s));
-    HIPCHK(c, vaxpby(1.0, b, -1.0, tmp, n, s));
-    double rr;
-    mf_status st = host_dot(c, tmp, tmp, n, &rr, s);
-    if (st) return st;
+    RedWS r = redws(c);
+    HIPCHK(c, vdiffnorm2(b, tmp, n, c->scal, &r, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const double rr = c->h_scal[0];
     *out = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
     return MF_OK;
 }
@@ -529,30 +531,40 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
     if ((st = ensure_face(c, 1))) return st;
     if (precond == MF_PC_JACOBI) {
         if ((st = ws_vec(c, 4, &dinv))) return st;
-        HIPCHK(c, heat_diagonal(c->km, ha, 0, dinv, c->face, s));
-        HIPCHK(c, vinv(dinv, n, s));
+        HIPCHK(c, heat_diagonal(c->km, ha, 0, dinv, c->face, s, true));
     }
     RedWS red = redws(c);
     HIPCHK(c, cg_init(c->cg, b, dinv, x, r, p, n, rtol, maxit, 0, &red, s));
-    // Iterations are launched in batches between host polls of the state;
-    // once done, the rest of a batch is a chain of no-op launches.  After
-    // the first batch the next one is sized from the residual's decay so
-    // far (geometric extrapolation to the threshold): that only sets how
-    // often the host polls, never what is computed.
-    int batch = 8;
+    // Iterations are launched in batches, each followed by a copy of the
+    // state that the host polls.  While the host waits for that copy and
+    // decides, the GPU already runs one more iteration (launched before the
+    // wait), so it does not idle through the poll; an iteration launched
+    // after convergence is a chain of no-op launches.  After the first batch
+    // the next one is sized from the residual's decay so far (geometric
+    // extrapolation to the threshold): that only sets how often the host
+    // polls, never what is computed.
+    if (!c->poll_ev) HIPCHK(c, hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming));
+    auto iterate = [&](int k) -> hipError_t {
+        for (int i = 0; i < k; ++i) {
+            hipError_t e = heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s);
+            if (e == hipSuccess) e = cg_resid(c->cg, dinv, r, q, n, &red, s);
+            if (e == hipSuccess) e = cg_step(c->cg, dinv, x, r, p, n, &red, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    int batch = 8, launched = 8;
     double rr_prev = -1.0;
     int iters_prev = 0;
-    for (int done_iters = 0;;) {
-        for (int k = 0; k < batch; ++k) {
-            HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
-            HIPCHK(c, cg_resid(c->cg, dinv, r, q, n, &red, s));
-            HIPCHK(c, cg_step(c->cg, dinv, x, r, p, n, &red, s));
-        }
-        done_iters += batch;
+    HIPCHK(c, iterate(batch));
+    for (;;) {
         HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, hipEventRecord(c->poll_ev, s));
+        HIPCHK(c, iterate(1)); // runs while the host polls
+        launched += 1;
+        HIPCHK(c, hipEventSynchronize(c->poll_ev));
         const CGState &h = *c->h_state;
-        if (h.done || done_iters >= maxit + batch) break;
+        if (h.done || launched >= maxit + 8) break;
         const double rr0 = rr_prev > 0.0 ? rr_prev : h.bb;
         const int dk = h.iter - iters_prev;
         batch = 8;
@@ -561,8 +573,18 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
             const double need = ceil(log(h.thresh2 / h.rr) / rate);
             batch = need < 1.0 ? 1 : (need > 16.0 ? 16 : (int)need);
         }
+        batch = batch > 1 ? batch - 1 : 1; // one iteration is already queued
         rr_prev = h.rr;
         iters_prev = h.iter;
+        HIPCHK(c, iterate(batch));
+        launched += batch;
+    }
+    // The state copied at the last poll is final when it says done: the
+    // iteration queued behind it only sets `run`.  Otherwise (the iteration
+    // limit guard) read the state again.
+    if (!c->h_state->done) {
+        HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
     }
     const CGState hs = *c->h_state;
     const double bnorm = sqrt(hs.bb);

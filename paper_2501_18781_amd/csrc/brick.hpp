@@ -570,7 +570,8 @@ using Brick = BrickT<BB>;
 // first).  Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
 // operator), DMODE 2 writes y = 1 (its diagonal), DMODE 3 writes 0 (a
 // right-hand side), DMODE 0 sums them like every other node (a plain nodal
-// field such as a gradient).
+// field such as a gradient).  DMODE 4 is DMODE 2 with the reciprocal of every
+// other sum stored (the inverse diagonal).
 // ---------------------------------------------------------------------------
 constexpr int CNT = 256; // threads per combine workgroup
 
@@ -804,8 +805,8 @@ __device__ __forceinline__ void combine_brick(const KMesh &m, const T *__restric
     if (brick >= n_bricks<BZ>(m)) return; // whole wavefronts; no barrier follows in them
     combine_brick_visit<T, DMODE != 0, BZ>(m, brick, (int)threadIdx.x % L, face,
                                            [&](int64_t g, bool constrained, T s) {
-        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
-        else y[g] = s;
+        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : ((DMODE == 2 || DMODE == 4) ? T(1) : T(0));
+        else y[g] = DMODE == 4 ? T(1) / s : s;
     });
 }
 
@@ -814,8 +815,8 @@ __device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restri
                                                T *__restrict__ y)
 {
     combine_visit<T, DMODE != 0, NPT>(m, face, [&](int64_t g, bool constrained, T s) {
-        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : (DMODE == 2 ? T(1) : T(0));
-        else y[g] = s;
+        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : ((DMODE == 2 || DMODE == 4) ? T(1) : T(0));
+        else y[g] = DMODE == 4 ? T(1) / s : s;
     });
 }
 

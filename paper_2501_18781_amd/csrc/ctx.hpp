@@ -28,6 +28,7 @@ struct mf_ctx {
     double *blocks = nullptr;    // Oseen block-Jacobi inverse
     double *face = nullptr;      // shared-face partial sums of the brick kernels
     int64_t face_elems = 0;      // its capacity in doubles
+    hipEvent_t poll_ev = nullptr; // marks the state copy a solve loop polls (created on first use)
     // kernel timing
     bool timing = false;
     std::vector<mf::KTiming> events;

@@ -642,7 +642,8 @@ __device__ __forceinline__ void heat_cell_conv_diag(const Brick &br, const KMesh
     }
 }
 
-template <typename T, int MODE, int HK, bool CONV = false>
+// INV: store 1 / diag (the Jacobi preconditioner) instead of diag.
+template <typename T, int MODE, int HK, bool CONV = false, bool INV = false>
 __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *__restrict__ diag, T *__restrict__ face)
 {
     static_assert(!CONV || (std::is_same<T, double>::value && MODE == 0), "convective form: FP64 only");
@@ -702,42 +703,51 @@ __global__ void __launch_bounds__(BNT) heat_diag_kernel(KMesh m, HeatArgs a, T *
     br.template for_owned_nodes<T>(m, [&](int ai, int bi, int ci, int, int64_t g, bool constrained, int sh) {
         const T v = br.node_sum(lds, ai, bi, ci);
         if (sh) fb[br.fslot(ai, bi, ci)] = v; // constrained ones: 1 in the combine
-        else diag[g] = constrained ? T(1) : v;
+        else diag[g] = constrained ? T(1) : (INV ? T(1) / v : v);
     });
 }
 
-hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s)
+template <bool INV>
+static hipError_t heat_diagonal_launch(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face,
+                                       hipStream_t s)
 {
     const unsigned nb = (unsigned)n_bricks(m);
     if (!face) return hipErrorInvalidValue;
+    float *df = (float *)diag, *ff = (float *)face;
+    double *dd = (double *)diag, *fd = (double *)face;
     if (fp32) {
-        if (a.mode == 1) heat_diag_kernel<float, 1, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
-        else if (a.hkind == 1) heat_diag_kernel<float, 0, 1><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
-        else heat_diag_kernel<float, 0, 0><<<nb, BNT, 0, s>>>(m, a, (float *)diag, (float *)face);
+        if (a.mode == 1) heat_diag_kernel<float, 1, 0, false, INV><<<nb, BNT, 0, s>>>(m, a, df, ff);
+        else if (a.hkind == 1) heat_diag_kernel<float, 0, 1, false, INV><<<nb, BNT, 0, s>>>(m, a, df, ff);
+        else heat_diag_kernel<float, 0, 0, false, INV><<<nb, BNT, 0, s>>>(m, a, df, ff);
     } else if (a.conv) {
         if (a.mode != 0 || !a.u0) return hipErrorInvalidValue;
-        if (a.hkind == 1) heat_diag_kernel<double, 0, 1, true><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
-        else heat_diag_kernel<double, 0, 0, true><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+        if (a.hkind == 1) heat_diag_kernel<double, 0, 1, true, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
+        else heat_diag_kernel<double, 0, 0, true, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
     } else {
         if (a.mode == 2) {
-            if (a.hkind == 1) heat_diag_kernel<double, 2, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
-            else heat_diag_kernel<double, 2, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+            if (a.hkind == 1) heat_diag_kernel<double, 2, 1, false, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
+            else heat_diag_kernel<double, 2, 0, false, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
         } else if (a.mode == 1)
-            heat_diag_kernel<double, 1, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
-        else if (a.hkind == 1) heat_diag_kernel<double, 0, 1><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
-        else heat_diag_kernel<double, 0, 0><<<nb, BNT, 0, s>>>(m, a, (double *)diag, (double *)face);
+            heat_diag_kernel<double, 1, 0, false, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
+        else if (a.hkind == 1) heat_diag_kernel<double, 0, 1, false, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
+        else heat_diag_kernel<double, 0, 0, false, INV><<<nb, BNT, 0, s>>>(m, a, dd, fd);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned rows = combine_blocks(m);
     if (rows == 0) return hipSuccess;
-    if (fp32)
-        face_combine_kernel<float, false, 2><<<rows, CNT, 0, s>>>(m, (const float *)face, nullptr, (float *)diag,
-                                                                  nullptr, nullptr, 0);
-    else
-        face_combine_kernel<double, false, 2><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr,
-                                                                   (double *)diag, nullptr, nullptr, 0);
+    // DMODE 2: Dirichlet rows 1; 4: the same, and the reciprocals of the others
+    constexpr int DM = INV ? 4 : 2;
+    if (fp32) face_combine_kernel<float, false, DM><<<rows, CNT, 0, s>>>(m, ff, nullptr, df, nullptr, nullptr, 0);
+    else face_combine_kernel<double, false, DM><<<rows, CNT, 0, s>>>(m, fd, nullptr, dd, nullptr, nullptr, 0);
     return hipGetLastError();
+}
+
+hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s,
+                         bool invert)
+{
+    return invert ? heat_diagonal_launch<true>(m, a, fp32, diag, face, s)
+                  : heat_diagonal_launch<false>(m, a, fp32, diag, face, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -98,7 +98,9 @@ bool heat_fits_one_brick(const KMesh &m);
 hipError_t heat_cg_one_brick(const KMesh &m, const HeatArgs &a, const float *b32, float *x32, double rtol, int maxit,
                              hipStream_t s);
 hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
-hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s);
+// diag(A) (Dirichlet rows 1); with invert its reciprocals (the Jacobi preconditioner).
+hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s,
+                         bool invert = false);
 hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const double *dT, const double *lam,
                      double *dk, double *drc, double *dphi, void *face, hipStream_t s);
 
@@ -141,9 +143,10 @@ hipError_t vinv(double *d, int64_t n, hipStream_t s);                           
 hipError_t vcvt_d2f(const double *x, float *y, int64_t n, hipStream_t s);
 hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s);
 hipError_t vmulf(const float *d, const float *x, float *y, int64_t n, hipStream_t s);
-hipError_t vinvf(float *d, int64_t n, hipStream_t s);
 // out[k] = sum_i V_k[i] w[i] for k < nv (V columns of length n, leading dim ld);
 // nv = 1 with V = x gives a plain dot product.  out is device memory.
+// out[0] = ||b - t||^2 (device scalar), the partials in red.
+hipError_t vdiffnorm2(const double *b, const double *t, int64_t n, double *out, const RedWS *red, hipStream_t s);
 hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out,
                      const RedWS *red, hipStream_t s);
 // w -= sum_k V_k h[k] (h device), optionally out_norm2 = ||w||^2 after the update.

@@ -448,8 +448,7 @@ static mf_status lanczos_bounds(mf_mg *mg, MGLevel &l, int steps, double *out_ma
     if ((st = ws_vec(c, 0, &sv)) || (st = ws_vec(c, 1, &q)) || (st = ws_vec(c, 2, &qp)) || (st = ws_vec(c, 3, &w)) ||
         (st = ws_vec(c, 4, &tmp)))
         return st;
-    MGCHK(mg, heat_diagonal(c->km, heat_args(&l.op64), 0, tmp, c->face, s));
-    MGCHK(mg, vinv(tmp, n, s));
+    MGCHK(mg, heat_diagonal(c->km, heat_args(&l.op64), 0, tmp, c->face, s, true));
     MGCHK(mg, vsqrt(tmp, sv, n, s));
     MGCHK(mg, vknuth(q, n, s));
     double nq2;
@@ -588,8 +587,7 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
             mg_free(mg);
             return st;
         }
-        MGCHK(mg, heat_diagonal(l.ctx->km, heat_args(&l.op32), 1, l.dinv, l.ctx->face, s));
-        MGCHK(mg, vinvf(l.dinv, l.nn, s));
+        MGCHK(mg, heat_diagonal(l.ctx->km, heat_args(&l.op32), 1, l.dinv, l.ctx->face, s, true));
         const bool coarsest_smoothed = li == 0 && mg->smooth_coarsest;
         const bool need_est = !prm->lambda_max || (coarsest_smoothed && !prm->lambda_min);
         if (need_est && (st = lanczos_bounds(mg, l, prm->eig_steps, &l.est_max, &l.est_min, s))) {

@@ -182,12 +182,6 @@ hipError_t vinv(double *d, int64_t n, hipStream_t s)
     inv_kernel<double><<<ew_blocks(n), VNT, 0, s>>>(d, n);
     return hipGetLastError();
 }
-hipError_t vinvf(float *d, int64_t n, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    inv_kernel<float><<<ew_blocks(n), VNT, 0, s>>>(d, n);
-    return hipGetLastError();
-}
 
 __global__ void d2f_kernel(const double *x, float *y, int64_t n) { GRID_STRIDE(i, n) y[i] = (float)x[i]; }
 __global__ void f2d_kernel(const float *x, double *y, int64_t n) { GRID_STRIDE(i, n) y[i] = (double)x[i]; }
@@ -321,6 +315,29 @@ hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64
     }
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
+}
+
+// Partials of ||b - t||^2 (the true residual of a solve, without storing it).
+__global__ void __launch_bounds__(VNT) diffnorm2_kernel(const double *__restrict__ b, const double *__restrict__ t,
+                                                        int64_t n, RedWS red)
+{
+    __shared__ double lds[VNT / 64];
+    double acc = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double d = b[i] - t[i];
+        acc += d * d;
+    }
+    grid_partials<1>(&acc, red, lds);
+}
+
+hipError_t vdiffnorm2(const double *b, const double *t, int64_t n, double *out, const RedWS *red, hipStream_t s)
+{
+    const unsigned nb = vec_blocks(n);
+    if (red->capacity < nb) return hipErrorInvalidValue;
+    diffnorm2_kernel<<<nb, VNT, 0, s>>>(b, t, n, *red);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : sum_finalize(*red, nb, 1, out, s);
 }
 
 // w -= V h; optionally ||w||^2 of the result
