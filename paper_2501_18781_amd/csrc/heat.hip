@@ -417,40 +417,15 @@ __global__ void __launch_bounds__(BrickDims<BZ>::NT) heat_apply_kernel(KMesh m, 
     }
 }
 
-// Second pass of an apply: shared nodes = sum of the bricks' face partials,
-// NPT nodes per thread (their loads in flight together).  In CG mode the
-// first workgroup then also sums the bricks' partials of p.Ap (complete
-// once the brick kernel has finished) and sets alpha = rz / p.Ap, which
-// saves a launch per iteration.  A breakdown sets done here; a workgroup
-// of this launch that then skips its nodes leaves q incomplete, which no
-// later step of the solve reads.
-template <typename T, bool CG, int DMODE = 1, int NPT = 1>
-__global__ void __launch_bounds__(CNT) face_combine_kernel(KMesh m, const T *__restrict__ face,
-                                                           const T *__restrict__ x, T *__restrict__ y, CGState *cg,
-                                                           const double *__restrict__ partials, unsigned nbricks)
-{
-    if (CG) {
-        if (cg->done) return;
-    }
-    combine_shared<T, DMODE, NPT>(m, face, x, y);
-    if (CG && blockIdx.x == 0) {
-        __shared__ double red[CNT];
-        const double pAp = sum_partials<CNT>(partials, nbricks, 0, red);
-        if (threadIdx.x == 0) {
-            cg->pAp = pAp;
-            if (!(pAp > 0.0) || !isfinite(pAp)) {
-                cg->breakdown = 1;
-                cg->done = 1;
-                cg->alpha = 0.0;
-            } else {
-                cg->alpha = cg->rz / pAp;
-            }
-        }
-    }
-}
-
-// The same pass with one workgroup per brick finishing the shared nodes it
-// owns (combine_brick in brick.hpp); bitwise the same result.
+// Second pass of an apply, a diagonal or a gradient: the shared nodes, each
+// the sum of the bricks' face partials, finished brick by brick
+// (combine_brick in brick.hpp: the same fixed sum order as the
+// node-enumerated combine_shared).  In CG mode the first workgroup first
+// sums the bricks' partials of p.Ap (complete once the brick kernel has
+// finished) and sets alpha = rz / p.Ap, which saves a launch per
+// iteration.  A breakdown sets done here; a workgroup of this launch that
+// then skips its nodes leaves q incomplete, which no later step of the
+// solve reads.
 template <typename T, bool CG, int DMODE = 1, int BZ = BB>
 __global__ void __launch_bounds__(BNT * CBW) face_combine_brick_kernel(KMesh m, const T *__restrict__ face,
                                                                  const T *__restrict__ x, T *__restrict__ y,
@@ -734,12 +709,12 @@ static hipError_t heat_diagonal_launch(const KMesh &m, const HeatArgs &a, int fp
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned rows = combine_blocks(m);
-    if (rows == 0) return hipSuccess;
+    if (nb == 1) return hipSuccess; // a single brick shares nothing
     // DMODE 2: Dirichlet rows 1; 4: the same, and the reciprocals of the others
     constexpr int DM = INV ? 4 : 2;
-    if (fp32) face_combine_kernel<float, false, DM><<<rows, CNT, 0, s>>>(m, ff, nullptr, df, nullptr, nullptr, 0);
-    else face_combine_kernel<double, false, DM><<<rows, CNT, 0, s>>>(m, fd, nullptr, dd, nullptr, nullptr, 0);
+    const unsigned wg = (nb + CBW - 1) / CBW;
+    if (fp32) face_combine_brick_kernel<float, false, DM><<<wg, BNT * CBW, 0, s>>>(m, ff, nullptr, df, nullptr, nullptr, 0);
+    else face_combine_brick_kernel<double, false, DM><<<wg, BNT * CBW, 0, s>>>(m, fd, nullptr, dd, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 
@@ -1023,10 +998,9 @@ hipError_t heat_grad(const KMesh &m, const HeatArgs &a, const double *T, const d
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !dphi || a.mode != 0) return e;
     // the level-set gradient sums over Dirichlet nodes too (DMODE 0)
-    const unsigned rows = combine_blocks(m);
-    if (rows == 0) return hipSuccess;
-    face_combine_kernel<double, false, 0><<<rows, CNT, 0, s>>>(m, (const double *)face, nullptr, dphi, nullptr,
-                                                               nullptr, 0);
+    if (nb == 1) return hipSuccess;
+    face_combine_brick_kernel<double, false, 0><<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(
+        m, (const double *)face, nullptr, dphi, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 

@@ -310,12 +310,13 @@ __global__ void __launch_bounds__(ONT) oseen_apply_kernel(KMesh m, OseenArgs a, 
     }
 }
 
-__global__ void __launch_bounds__(CNT) oseen_combine_kernel(KMesh m, const double *__restrict__ face,
-                                                            const double *__restrict__ x, double *__restrict__ y)
+// Shared nodes of component blockIdx.y, brick by brick (combine_brick).
+__global__ void __launch_bounds__(BNT * CBW) oseen_combine_kernel(KMesh m, const double *__restrict__ face,
+                                                                  const double *__restrict__ x, double *__restrict__ y)
 {
     const int comp = blockIdx.y;
     const int64_t nn = (int64_t)m.NX * m.NY * m.NZ, nb = n_bricks(m);
-    combine_shared<double, 1, 2>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn);
+    combine_brick<double, 1>(m, face + comp * nb * BFACE, x + comp * nn, y + comp * nn);
 }
 
 hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const double *x, double *y, void *face,
@@ -342,8 +343,7 @@ hipError_t oseen_apply(const KMesh &m, const OseenArgs &a, int transpose, const 
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && t && t->stop) e = hipEventRecord(t->stop, s);
     if (e != hipSuccess) return e;
-    const unsigned rows = combine_blocks(m, 2); // two nodes per thread
-    if (rows > 0) oseen_combine_kernel<<<dim3(rows, 3), CNT, 0, s>>>(m, fb, x, y);
+    if (nb > 1) oseen_combine_kernel<<<dim3((nb + CBW - 1) / CBW, 3), BNT * CBW, 0, s>>>(m, fb, x, y);
     return hipGetLastError();
 }
 

@@ -122,10 +122,11 @@ __global__ void __launch_bounds__(BNT) heat_source_kernel(KMesh m, HeatArgs a, S
     });
 }
 
-__global__ void __launch_bounds__(CNT) source_combine_kernel(KMesh m, const double *__restrict__ face,
-                                                             double *__restrict__ b)
+// Shared nodes, brick by brick (combine_brick); Dirichlet ones get 0.
+__global__ void __launch_bounds__(BNT * CBW) source_combine_kernel(KMesh m, const double *__restrict__ face,
+                                                                   double *__restrict__ b)
 {
-    combine_shared<double, 3, 2>(m, face, nullptr, b);
+    combine_brick<double, 3>(m, face, nullptr, b);
 }
 
 hipError_t heat_sources(const KMesh &m, const HeatArgs &a, const SourceArgs &sa, const double *T, double *b,
@@ -137,9 +138,8 @@ hipError_t heat_sources(const KMesh &m, const HeatArgs &a, const SourceArgs &sa,
     else heat_source_kernel<0><<<nb, BNT, 0, s>>>(m, a, sa, T, b, (double *)face);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned rows = combine_blocks(m, 2); // two nodes per thread
-    if (rows == 0) return hipSuccess;
-    source_combine_kernel<<<rows, CNT, 0, s>>>(m, (const double *)face, b);
+    if (nb == 1) return hipSuccess; // a single brick shares nothing
+    source_combine_kernel<<<(nb + CBW - 1) / CBW, BNT * CBW, 0, s>>>(m, (const double *)face, b);
     return hipGetLastError();
 }
 
