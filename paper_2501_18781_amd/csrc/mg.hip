@@ -727,26 +727,25 @@ extern "C" mf_status mf_mg_cg_solve(mf_mg *mg, const double *b, double *x, doubl
     MGLevel &top = mg->L.back();
     const int ltop = (int)mg->L.size() - 1;
     // the flexible CG of vec.hip: z = V(r) is top.x (FP32), its input r32 is top.b
+    // No poll before the first V-cycle: when the initial residual already
+    // meets the threshold (b = 0, maxit = 0) the state says done, the
+    // direction, apply and residual kernels are no-ops and the V-cycle's
+    // output is unused.  The state read at the last poll is final: the
+    // finishing kernel only adds the pending alpha p to x.
     HIPCHK(c, cg_init(c->cg, b, nullptr, x, r, p, n, rtol, maxit, 1, &red, s));
     HIPCHK(c, vcvt_d2f(b, top.b, n, s)); // r = b
-    HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (!c->h_state->done) {
-        if ((st = vcycle(mg, ltop, s))) return st;
-        HIPCHK(c, fcg_direction(c->cg, r, top.x, p, x, n, &red, s));
-        for (;;) {
-            HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
-            HIPCHK(c, fcg_resid(c->cg, r, q, top.x, top.b, n, &red, s));
-            HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipStreamSynchronize(s));
-            if (c->h_state->done) break;
-            if ((st = vcycle(mg, ltop, s))) return st;
-            HIPCHK(c, fcg_direction(c->cg, r, top.x, p, x, n, &red, s));
-        }
-        HIPCHK(c, fcg_finish(c->cg, p, x, n, s));
+    if ((st = vcycle(mg, ltop, s))) return st;
+    HIPCHK(c, fcg_direction(c->cg, r, top.x, p, x, n, &red, s));
+    for (;;) {
+        HIPCHK(c, heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s));
+        HIPCHK(c, fcg_resid(c->cg, r, q, top.x, top.b, n, &red, s));
         HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
+        if (c->h_state->done) break;
+        if ((st = vcycle(mg, ltop, s))) return st;
+        HIPCHK(c, fcg_direction(c->cg, r, top.x, p, x, n, &red, s));
     }
+    HIPCHK(c, fcg_finish(c->cg, p, x, n, s));
     const CGState hs = *c->h_state;
     const double bnorm = sqrt(hs.bb);
     info->iters = hs.iter;

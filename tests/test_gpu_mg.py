@@ -272,3 +272,24 @@ def test_flexible_cg_at_scale_matches_oracle_and_repeats_bitwise(gpu):
                         rtol=1e-8)
     print(its[0], ref.iters, flush=True)
     assert abs(its[0] - ref.iters) <= 1
+
+
+def test_flexible_cg_edge_cases(gpu):
+    # a zero right-hand side and maxit = 0 stop before the first iteration
+    # with x = 0 (the first V-cycle runs without a poll before it, on a solve
+    # that is already done); a small maxit is reported with that many
+    # iterations done
+    wl = W.heat_sphere_workload(8, W.ALL_FACES)
+    ctx = mf.Context(wl.mesh)
+    op = mf.heat_operator(ctx, wl.params, phi=dev(wl.phi))
+    mg = mf.Multigrid(op, mf.MGConfig(coarse_cells=4))
+    n = wl.mesh.n_nodes
+    x = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+    info = mf.mg_cg_solve(mg, torch.zeros(n, dtype=torch.float64, device="cuda"), x, 1e-8, 50)
+    assert info.converged and info.iters == 0 and float(x.abs().max()) == 0.0
+    b = dev(W.uniform(3, n))
+    x.fill_(7.0)
+    info = mf.mg_cg_solve(mg, b, x, 1e-8, 0)
+    assert info.status == mf.MF_NOT_CONVERGED and info.iters == 0 and float(x.abs().max()) == 0.0
+    info = mf.mg_cg_solve(mg, b, x, 1e-14, 2)
+    assert info.status == mf.MF_NOT_CONVERGED and info.iters == 2
