@@ -149,7 +149,8 @@ void mf_destroy(mf_ctx *c)
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
-    if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
+    for (hipEvent_t &e : c->poll_ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -479,6 +480,16 @@ mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, 
 // Helpers for the solvers
 // ---------------------------------------------------------------------------
 // ||v||^2 read back to the host (synchronizes the stream)
+hipError_t poll_events(mf_ctx *c)
+{
+    for (hipEvent_t &e : c->poll_ev)
+        if (!e) {
+            hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (err != hipSuccess) return err;
+        }
+    return hipSuccess;
+}
+
 mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s)
 {
     RedWS r = redws(c);
@@ -543,7 +554,7 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
     // the next one is sized from the residual's decay so far (geometric
     // extrapolation to the threshold): that only sets how often the host
     // polls, never what is computed.
-    if (!c->poll_ev) HIPCHK(c, hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming));
+    HIPCHK(c, poll_events(c));
     auto iterate = [&](int k) -> hipError_t {
         for (int i = 0; i < k; ++i) {
             hipError_t e = heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s);
@@ -559,10 +570,10 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
     HIPCHK(c, iterate(batch));
     for (;;) {
         HIPCHK(c, hipMemcpyAsync(c->h_state, c->cg, sizeof(CGState), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipEventRecord(c->poll_ev, s));
+        HIPCHK(c, hipEventRecord(c->poll_ev[0], s));
         HIPCHK(c, iterate(1)); // runs while the host polls
         launched += 1;
-        HIPCHK(c, hipEventSynchronize(c->poll_ev));
+        HIPCHK(c, hipEventSynchronize(c->poll_ev[0]));
         const CGState &h = *c->h_state;
         if (h.done || launched >= maxit + 8) break;
         const double rr0 = rr_prev > 0.0 ? rr_prev : h.bb;
@@ -699,25 +710,39 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jdone = 0;
-        bool inner = false;
+        // Arnoldi step j on the device: w = A M^{-1} v_j, two passes of
+        // classical Gram-Schmidt (the first update and the second
+        // projection share one read of V: three passes, not four), w
+        // normalized by its norm, and the Hessenberg column (both
+        // projections and the squared norm) copied to the host.  Scalars of
+        // step j go to slot j mod 2 of the device and host scalar arrays
+        // (first projection at +0, second at +32, squared norm at +64).
+        // While the host applies the Givens rotations to column j, the GPU
+        // already runs step j + 1; when column j ends the cycle, step j + 1
+        // is simply not used.
+        auto step = [&](int j) -> hipError_t {
+            double *w = V + (int64_t)(j + 1) * ld, *hd = c->scal + (j & 1) * 128;
+            hipError_t e = prec(V + (int64_t)j * ld, zt);
+            if (e == hipSuccess) e = apply_any(c, op, transpose, zt, w, s);
+            if (e == hipSuccess) e = vmultidot(V, ld, j + 1, w, n, hd, &red, s);
+            if (e == hipSuccess) e = vmultiaxpy_dot(V, ld, j + 1, hd, w, n, hd + 32, &red, s);
+            if (e == hipSuccess) e = vmultiaxpy(V, ld, j + 1, hd + 32, w, n, hd + 64, &red, s);
+            if (e == hipSuccess) e = vscale_inv_norm(w, n, hd + 64, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->h_scal + (j & 1) * 128, hd, sizeof(double) * 65, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipEventRecord(c->poll_ev[j & 1], s);
+            return e;
+        };
+        HIPCHK(c, poll_events(c));
+        HIPCHK(c, step(0));
         for (int j = 0; j < m; ++j) {
-            double *w = V + (int64_t)(j + 1) * ld;
-            HIPCHK(c, prec(V + (int64_t)j * ld, zt));
-            HIPCHK(c, apply_any(c, op, transpose, zt, w, s));
+            // the next step, unless the cycle or the iteration budget ends here
+            if (j + 1 < m && total + 1 < maxit) HIPCHK(c, step(j + 1));
+            HIPCHK(c, hipEventSynchronize(c->poll_ev[j & 1]));
             ++total;
-            // two passes of classical Gram-Schmidt: the first update and the
-            // second projection share one read of V (three passes, not four)
-            double *hd = c->scal;
-            HIPCHK(c, vmultidot(V, ld, j + 1, w, n, hd, &red, s));
-            HIPCHK(c, vmultiaxpy_dot(V, ld, j + 1, hd, w, n, hd + 64, &red, s));
-            HIPCHK(c, hipMemcpyAsync(c->h_scal, hd, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-            HIPCHK(c, vmultiaxpy(V, ld, j + 1, hd + 64, w, n, hd + 128, &red, s));
-            HIPCHK(c, hipMemcpyAsync(c->h_scal + 64, hd + 64, sizeof(double) * 65, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipStreamSynchronize(s));
-            for (int i = 0; i <= j; ++i) H[i * m + j] = c->h_scal[i] + c->h_scal[64 + i];
-            const double hn = sqrt(c->h_scal[128]);
-            H[(j + 1) * m + j] = hn;
-            if (hn > 0.0) HIPCHK(c, vaxpby(1.0 / hn, w, 0.0, w, n, s));
+            const double *hh = c->h_scal + (j & 1) * 128;
+            for (int i = 0; i <= j; ++i) H[i * m + j] = hh[i] + hh[32 + i];
+            H[(j + 1) * m + j] = sqrt(hh[64]);
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
                 H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
@@ -725,8 +750,8 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
             }
             const double den = hypot(H[j * m + j], H[(j + 1) * m + j]);
             if (!(den > 0.0) || !isfinite(den)) {
-                jdone = j;
                 info->iters = total;
+                HIPCHK(c, hipStreamSynchronize(s)); // a step launched ahead may still use the host copies
                 return fail(c, MF_BREAKDOWN, "GMRES breakdown at step %d", total);
             }
             cs[j] = H[j * m + j] / den;
@@ -737,10 +762,7 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
             g[j] = cs[j] * g[j];
             jdone = j + 1;
             info->rel_res_est = fabs(g[j + 1]) / bnorm;
-            if (info->rel_res_est <= rtol || total >= maxit) {
-                inner = info->rel_res_est <= rtol;
-                break;
-            }
+            if (info->rel_res_est <= rtol || total >= maxit) break;
         }
         // y = H^{-1} g (upper triangular), x += M^{-1} V y
         for (int i = jdone - 1; i >= 0; --i) {
@@ -753,7 +775,6 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
         HIPCHK(c, prec(tmp, zt));
         HIPCHK(c, vaxpby(1.0, zt, 1.0, x, n, s));
         HIPCHK(c, hipStreamSynchronize(s)); // h is a host vector reused by the next cycle
-        (void)inner;
     }
     info->iters = total;
     double tr;

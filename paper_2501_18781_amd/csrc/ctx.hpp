@@ -28,7 +28,9 @@ struct mf_ctx {
     double *blocks = nullptr;    // Oseen block-Jacobi inverse
     double *face = nullptr;      // shared-face partial sums of the brick kernels
     int64_t face_elems = 0;      // its capacity in doubles
-    hipEvent_t poll_ev = nullptr; // marks the state copy a solve loop polls (created on first use)
+    // mark the state copies a solve loop polls (created on first use; GMRES
+    // alternates between the two)
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
     // kernel timing
     bool timing = false;
     std::vector<mf::KTiming> events;
@@ -61,6 +63,8 @@ int64_t ndofs(const mf_ctx *c, const mf_operator *op);
 // y = A x or A^T x for any operator kind / precision; timed: record kernel events.
 hipError_t apply_any(mf_ctx *c, const mf_operator *op, int transpose, const void *x, void *y, hipStream_t s,
                      bool timed = false);
+// The two poll events of the context, created on first use.
+hipError_t poll_events(mf_ctx *c);
 // a.b read back to the host (synchronizes the stream).
 mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s);
 // ||b - A x|| / bnorm using workspace vector tmp.

@@ -145,6 +145,9 @@ hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s);
 hipError_t vmulf(const float *d, const float *x, float *y, int64_t n, hipStream_t s);
 // out[k] = sum_i V_k[i] w[i] for k < nv (V columns of length n, leading dim ld);
 // nv = 1 with V = x gives a plain dot product.  out is device memory.
+// w = w / sqrt(n2[0]) when n2[0] > 0 (n2 a device scalar: a norm formed by an
+// earlier launch), else w unchanged.
+hipError_t vscale_inv_norm(double *w, int64_t n, const double *n2, hipStream_t s);
 // out[0] = ||b - t||^2 (device scalar), the partials in red.
 hipError_t vdiffnorm2(const double *b, const double *t, int64_t n, double *out, const RedWS *red, hipStream_t s);
 hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out,

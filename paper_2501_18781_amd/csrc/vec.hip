@@ -317,6 +317,20 @@ hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64
     return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
 }
 
+__global__ void scale_inv_norm_kernel(double *__restrict__ w, int64_t n, const double *__restrict__ n2)
+{
+    const double hn = sqrt(n2[0]);
+    if (!(hn > 0.0)) return;
+    const double a = 1.0 / hn;
+    GRID_STRIDE(i, n) w[i] = a * w[i];
+}
+
+hipError_t vscale_inv_norm(double *w, int64_t n, const double *n2, hipStream_t s)
+{
+    scale_inv_norm_kernel<<<ew_blocks(n), VNT, 0, s>>>(w, n, n2);
+    return hipGetLastError();
+}
+
 // Partials of ||b - t||^2 (the true residual of a solve, without storing it).
 __global__ void __launch_bounds__(VNT) diffnorm2_kernel(const double *__restrict__ b, const double *__restrict__ t,
                                                         int64_t n, RedWS red)
