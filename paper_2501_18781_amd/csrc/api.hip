@@ -479,7 +479,6 @@ mf_status mf_heat_coeff_grad(mf_ctx *c, const mf_operator *op, const double *T, 
 // ---------------------------------------------------------------------------
 // Helpers for the solvers
 // ---------------------------------------------------------------------------
-// ||v||^2 read back to the host (synchronizes the stream)
 hipError_t poll_events(mf_ctx *c)
 {
     for (hipEvent_t &e : c->poll_ev)
@@ -490,6 +489,7 @@ hipError_t poll_events(mf_ctx *c)
     return hipSuccess;
 }
 
+// a.b read back to the host (synchronizes the stream)
 mf_status host_dot(mf_ctx *c, const double *a, const double *b, int64_t n, double *out, hipStream_t s)
 {
     RedWS r = redws(c);
