@@ -10,7 +10,8 @@
 // the test function: alpha_c rc_q x_q u_q . grad N_i.
 //
 // Work decomposition (brick.hpp): one 64-thread workgroup (one wavefront)
-// per brick of 4x4x4 cells, one thread per cell.
+// per brick of 4x4x4 cells, one thread per cell (the FP32 applies: bricks
+// of 4x4x8 cells, two wavefronts).
 //   1. the brick's nodal x and phi are staged in LDS (FP64: each node read
 //      once, node-parallel over the wavefront; FP32: each cell reads its 27
 //      nodes); Dirichlet columns read as zero when x is gathered;
@@ -18,13 +19,15 @@
 //      factorization (3x3 contractions along one direction at a time,
 //      collocation derivatives at the Gauss points, one 3-point line at a
 //      time);
-//   3. the 27 cell results go to LDS; each owned node sums the (at most 8)
-//      cells of the brick that share it in a fixed order;
+//   3. each owned node sums the (at most 8) cells of the brick that share it
+//      in a fixed order, in registers (cross-lane shifts in x and y, an LDS
+//      exchange in z);
 //   4. nodes complete within the brick are stored; nodes on a face shared
 //      with a neighbouring brick go to a face buffer, and a second kernel
 //      adds the partials of the bricks sharing each such node in a fixed
-//      order.  Every output entry is written once, without atomics, and the
-//      result is bitwise reproducible.  Dirichlet nodes get y_i = x_i.
+//      order, brick by brick.  Every output entry is written once, without
+//      atomics, and the result is bitwise reproducible.  Dirichlet nodes get
+//      y_i = x_i.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
