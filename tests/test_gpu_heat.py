@@ -253,6 +253,11 @@ def test_cg_edge_cases(gpu):
     b = A @ W.uniform(0, n)
     info = mf.cg_solve(op, dev(b), x, 1e-14, 2)
     assert info.status == mf.MF_NOT_CONVERGED and info.iters == 2
+    # iteration limits at and just past the first poll (after 8 iterations,
+    # with one more already queued behind it) stop exactly there
+    for maxit in (8, 9, 10):
+        info = mf.cg_solve(op, dev(b), x, 1e-30, maxit)
+        assert info.status == mf.MF_NOT_CONVERGED and info.iters == maxit, maxit
     # an indefinite operator (negative mass factor) is reported as a breakdown
     bad = op.with_alphas(alpha_m=-1e3, alpha_k=0.0)
     info = mf.cg_solve(bad, dev(b), x, 1e-10, 100, precond=mf.MF_PC_NONE)

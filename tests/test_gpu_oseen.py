@@ -167,6 +167,21 @@ def test_gmres_other_preconditioners_and_restarts(gpu, precond, restart):
     assert normerr(x, O.direct_solve(A, b)) <= 1e-7
 
 
+@pytest.mark.parametrize("restart,maxit", [(1, 3), (2, 3), (2, 4), (5, 7)])
+def test_gmres_iteration_limit(gpu, restart, maxit):
+    # the limit stops GMRES after exactly maxit Arnoldi steps, also when it
+    # falls inside a restart cycle (the step launched ahead is not counted)
+    mesh, p, phi, u0 = case((4, 5, 3), W.ALL_FACES)
+    A = O.oseen_matrix(mesh, p, phi, u0)
+    b = A @ W.uniform(6, 3 * mesh.n_nodes)
+    ctx = mf.Context(mesh)
+    op = mf.oseen_operator(ctx, p, dev(phi), dev(u0))
+    x = torch.empty_like(dev(b))
+    info = mf.gmres_solve(op, dev(b), x, 1e-14, maxit, precond=mf.MF_PC_JACOBI, restart=restart)
+    assert info.status == mf.MF_NOT_CONVERGED and info.iters == maxit
+    assert bool(torch.isfinite(x).all()) and 0.0 < info.rel_res <= 1.0
+
+
 def test_gmres_transposed_system_and_heat(gpu):
     mesh, p, phi, u0 = case((4, 4, 4), W.ALL_FACES)
     A = O.oseen_matrix(mesh, p, phi, u0)
