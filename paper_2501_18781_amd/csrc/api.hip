@@ -559,7 +559,7 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
         for (int i = 0; i < k; ++i) {
             hipError_t e = heat_apply(c->km, ha, 0, p, q, c->face, c->cg, &red, s);
             if (e == hipSuccess) e = cg_resid(c->cg, dinv, r, q, n, &red, s);
-            if (e == hipSuccess) e = cg_step(c->cg, dinv, x, r, p, n, &red, s);
+            if (e == hipSuccess) e = cg_step(c->cg, x, r, p, n, &red, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

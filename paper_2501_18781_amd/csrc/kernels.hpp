@@ -163,17 +163,18 @@ hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double
 hipError_t block3_invert(double *blocks, int64_t nn, hipStream_t s);
 hipError_t block3_apply(const double *binv, const double *x, double *y, int64_t nn, hipStream_t s);
 
-// x = 0, r = b, p = D^-1 b (flexible: p = 0), rz and |b|^2 into st.
+// x = 0, p = D^-1 b and r = D^-1 b (the z of cg_resid; flexible: r = b, p = 0), rz and |b|^2 into st.
 hipError_t cg_init(CGState *st, const double *b, const double *dinv, double *x, double *r, double *p, int64_t n,
                    double rtol, int maxit, int flexible, const RedWS *red, hipStream_t s);
 // alpha = rz / p.Ap from the nb per-brick partials of a CG-mode apply.
 hipError_t cg_alpha(CGState *st, const RedWS *red, unsigned nb, hipStream_t s);
-// r -= alpha q with the partials of r.D^-1 r and r.r (dinv null: no preconditioner)
+// With the diagonal preconditioner (dinv non-null) the vector r holds
+// z = D^-1 r: z -= alpha D^-1 q and the partials of r.z and r.r with
+// r = z / D^-1; without one, r -= alpha q and the partials of r.r (twice).
 hipError_t cg_resid(CGState *st, const double *dinv, double *r, const double *q, int64_t n, const RedWS *red,
                     hipStream_t s);
-// beta and the convergence test from cg_resid's partials; x += alpha p, p = D^-1 r + beta p
-hipError_t cg_step(CGState *st, const double *dinv, double *x, const double *r, double *p, int64_t n,
-                   const RedWS *red, hipStream_t s);
+// beta and the convergence test from cg_resid's partials; x += alpha p, p = z + beta p
+hipError_t cg_step(CGState *st, double *x, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s);
 // Flexible-CG pieces (FP32 preconditioner output z, supplied by the caller):
 // r -= alpha q, r32 = fl32(r), r.r and r.z_old, convergence test;
 hipError_t fcg_resid(CGState *st, double *r, const double *q, const float *zold, float *r32, int64_t n,

@@ -522,18 +522,19 @@ hipError_t block3_apply(const double *B, const double *x, double *y, int64_t nn,
 }
 
 // ---------------------------------------------------------------------------
-// CG (preconditioned with a diagonal, Saad Alg. 9.1).  One iteration is
+// CG (preconditioned with a diagonal, Saad Alg. 9.1).  With the diagonal
+// preconditioner the solver keeps z = D^-1 r in place of r (r = z / D^-1
+// where a dot product needs it), so that the direction update needs no
+// D^-1.  One iteration is
 //   apply   q = A p, per-brick partials of p.q     (heat.hip, CG mode)
 //   alpha   alpha = rz / p.q                        (one workgroup)
-//   resid   r -= alpha q; partials of r.(D^-1 r) and r.r; iteration count,
-//           rz_old = rz                              (reads r, q, D^-1; writes r)
+//   resid   z -= alpha D^-1 q; partials of r.z and r.r; iteration count,
+//           rz_old = rz                              (reads z, q, D^-1; writes z)
 //   step    every workgroup sums the residual partials in the same order:
 //           beta = rz / rz_old and the convergence test; then
-//           x += alpha p and (unless converged) p = D^-1 r + beta p
-//                                                    (reads x, p, r, D^-1;
-//                                                     writes x, p)
-// Ten vector passes per iteration; z = D^-1 r is formed where it is used
-// and never stored (the same products, rounded the same way, as storing it).
+//           x += alpha p and (unless converged) p = z + beta p
+//                                                    (reads x, p, z; writes x, p)
+// Nine vector passes per iteration (without a preconditioner z = r).
 // Each thread keeps CG_UNROLL elements of its grid-stride sequence in flight.
 //
 // The done flag: a kernel that reads it at entry must not write it (another
@@ -553,12 +554,13 @@ __global__ void __launch_bounds__(VNT) cg_init_kernel(const double *__restrict__
     {
         const double bi = b[i];
         x[i] = 0.0;
-        r[i] = bi;
         if (!flexible) {
             const double zi = dinv ? dinv[i] * bi : bi;
+            r[i] = zi; // the preconditioned CG keeps z = D^-1 r in place of r
             p[i] = zi;
             acc[0] += bi * zi;
         } else {
+            r[i] = bi;
             p[i] = 0.0;
         }
         acc[1] += bi * bi;
@@ -672,11 +674,19 @@ __global__ void __launch_bounds__(VNT) cg_resid_kernel(CGState *st, const double
             if (PC) dv[k] = dinv[i];
         },
         [&](int k, int64_t i) {
-            const double ri = rv[k] - alpha * qv[k];
-            r[i] = ri;
-            const double zi = PC ? dv[k] * ri : ri;
-            acc[0] += ri * zi;
-            acc[1] += ri * ri;
+            if (PC) {
+                // the vector holds z = D^-1 r: z -= alpha D^-1 q, r = z / D^-1
+                const double zi = rv[k] - alpha * (dv[k] * qv[k]);
+                r[i] = zi;
+                const double ri = zi / dv[k];
+                acc[0] += ri * zi;
+                acc[1] += ri * ri;
+            } else {
+                const double ri = rv[k] - alpha * qv[k];
+                r[i] = ri;
+                acc[0] += ri * ri;
+                acc[1] += ri * ri;
+            }
         });
     grid_partials<2>(acc, red, lds);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -696,10 +706,9 @@ hipError_t cg_resid(CGState *st, const double *dinv, double *r, const double *q,
     return hipGetLastError();
 }
 
-template <bool PC>
 __global__ void __launch_bounds__(VNT) cg_step_kernel(CGState *st, const double *__restrict__ partials, unsigned nb,
-                                                      const double *__restrict__ dinv, double *__restrict__ x,
-                                                      const double *__restrict__ r, double *__restrict__ p, int64_t n)
+                                                      double *__restrict__ x, const double *__restrict__ z,
+                                                      double *__restrict__ p, int64_t n)
 {
     __shared__ double tot[2];
     if (!st->run) return; // this iteration's residual update was skipped (written by an earlier launch)
@@ -715,7 +724,7 @@ __global__ void __launch_bounds__(VNT) cg_step_kernel(CGState *st, const double 
         if (bad) st->breakdown = 1;
         if (stop) st->done = 1;
     }
-    double xv[CG_UNROLL], pv[CG_UNROLL], rv[CG_UNROLL], dv[CG_UNROLL];
+    double xv[CG_UNROLL], pv[CG_UNROLL], zv[CG_UNROLL];
     if (stop) {
         // the last iteration: x only
         grid_stride_unrolled(
@@ -728,24 +737,20 @@ __global__ void __launch_bounds__(VNT) cg_step_kernel(CGState *st, const double 
         [&](int k, int64_t i) {
             xv[k] = x[i];
             pv[k] = p[i];
-            rv[k] = r[i];
-            if (PC) dv[k] = dinv[i];
+            zv[k] = z[i];
         },
         [&](int k, int64_t i) {
             x[i] = xv[k] + alpha * pv[k];
-            const double zi = PC ? dv[k] * rv[k] : rv[k];
-            p[i] = zi + beta * pv[k];
+            p[i] = zv[k] + beta * pv[k];
         });
 }
 
-hipError_t cg_step(CGState *st, const double *dinv, double *x, const double *r, double *p, int64_t n,
-                   const RedWS *red, hipStream_t s)
+hipError_t cg_step(CGState *st, double *x, const double *z, double *p, int64_t n, const RedWS *red, hipStream_t s)
 {
     unsigned nb = (unsigned)std::min<int64_t>(((n + (int64_t)VNT * CG_UNROLL - 1) / ((int64_t)VNT * CG_UNROLL)),
                                               CG_STEP_BLOCKS);
     if (nb < 1) nb = 1;
-    if (dinv) cg_step_kernel<true><<<nb, VNT, 0, s>>>(st, red->partials, cg_resid_blocks(n), dinv, x, r, p, n);
-    else cg_step_kernel<false><<<nb, VNT, 0, s>>>(st, red->partials, cg_resid_blocks(n), dinv, x, r, p, n);
+    cg_step_kernel<<<nb, VNT, 0, s>>>(st, red->partials, cg_resid_blocks(n), x, z, p, n);
     return hipGetLastError();
 }
 
