@@ -556,137 +556,15 @@ using Brick = BrickT<BB>;
 
 // ---------------------------------------------------------------------------
 // Shared-node combine.  The nodes that several bricks touch lie on the
-// internal brick planes g = 8k, 0 < g < N - 1, of some direction.  One
-// thread per shared node, enumerated in three sections so that every shared
-// node comes exactly once:
-//   Z: g_z on an internal plane; order (plane, g_y, g_x);
-//   Y: g_y on an internal plane, g_z not; order (plane, g_z, g_x);
-//   X: g_x on an internal plane, g_y and g_z not; order (g_z, plane, g_y).
-// Z and Y threads run along x, X threads along y, which is the direction in
-// which the face slots they read are contiguous; the X order keeps the
-// output entries a row's planes share (8 nodes apart) close in time.
-// A node's value is the sum of the face partials of the 2, 4 or 8 bricks
-// containing it, in a fixed order (z outer, then y, then x; lower brick
-// first).  Shared Dirichlet nodes: DMODE 1 writes y = x (identity rows of an
-// operator), DMODE 2 writes y = 1 (its diagonal), DMODE 3 writes 0 (a
-// right-hand side), DMODE 0 sums them like every other node (a plain nodal
-// field such as a gradient).  DMODE 4 is DMODE 2 with the reciprocal of every
-// other sum stored (the inverse diagonal).
+// internal brick planes of some direction.  A node's value is the sum of the
+// face partials of the 2, 4 or 8 bricks containing it, in a fixed order (z
+// outer, then y, then x; lower brick first).  Shared Dirichlet nodes: DMODE 1
+// writes y = x (identity rows of an operator), DMODE 2 writes y = 1 (its
+// diagonal), DMODE 3 writes 0 (a right-hand side), DMODE 0 sums them like
+// every other node (a plain nodal field such as a gradient).  DMODE 4 is
+// DMODE 2 with the reciprocal of every other sum stored (the inverse
+// diagonal).
 // ---------------------------------------------------------------------------
-constexpr int CNT = 256; // threads per combine workgroup
-
-__host__ __device__ inline int internal_planes(int N) { return N >= 2 ? (N - 2) / (2 * BB) : 0; }
-
-__device__ __forceinline__ bool on_internal_plane(int g, int N) { return (g & (2 * BB - 1)) == 0 && g > 0 && g < N - 1; }
-
-// Threads of the combine pass (one per enumerated node, skipped ones included).
-__host__ __device__ inline int64_t combine_nodes(const KMesh &m)
-{
-    return (int64_t)internal_planes(m.NZ) * m.NX * m.NY + (int64_t)internal_planes(m.NY) * m.NX * m.NZ +
-           (int64_t)internal_planes(m.NX) * m.NY * m.NZ;
-}
-
-// Workgroups of a combine pass with npt nodes per thread.
-__host__ inline unsigned combine_blocks(const KMesh &m, int npt = 1)
-{
-    return (unsigned)((combine_nodes(m) + (int64_t)CNT * npt - 1) / ((int64_t)CNT * npt));
-}
-
-// Bricks containing node coordinate g along a direction with N nodes and nb
-// bricks: (k0, l0) and, if two, (k0 + 1, 0).
-__device__ __forceinline__ int brick_entries(int g, int N, int nb, int &k0, int &l0)
-{
-    if (on_internal_plane(g, N)) {
-        k0 = g / (2 * BB) - 1;
-        l0 = 2 * BB;
-        return 2;
-    }
-    k0 = min(g / (2 * BB), nb - 1);
-    l0 = g - 2 * BB * k0;
-    return 1;
-}
-
-// Enumerated node j (see above); false for an index without a node of its
-// own.  Workgroups are numbered so that each XCD receives a contiguous range
-// of indices (neighbouring rows share face cache lines; combine_visit).
-__device__ __forceinline__ bool combine_node_at(const KMesh &m, unsigned j, int &gx, int &gy, int &gz)
-{
-    const unsigned NX = m.NX, NY = m.NY, NZ = m.NZ;
-    const unsigned nzp = internal_planes(m.NZ), nyp = internal_planes(m.NY), nxp = internal_planes(m.NX);
-    const unsigned sz = nzp * NX * NY, sy = nyp * NX * NZ, sx = nxp * NY * NZ;
-    if (j < sz) {
-        const unsigned p = j / (NX * NY), rr = j - p * NX * NY, y = rr / NX;
-        gz = 2 * BB * (p + 1);
-        gy = y;
-        gx = rr - y * NX;
-        return true;
-    }
-    j -= sz;
-    if (j < sy) {
-        const unsigned p = j / (NX * NZ), rr = j - p * NX * NZ, z = rr / NX;
-        gy = 2 * BB * (p + 1);
-        gz = z;
-        gx = rr - z * NX;
-        return !on_internal_plane(gz, m.NZ);
-    }
-    j -= sy;
-    if (j < sx) {
-        const unsigned z = j / (nxp * NY), rr = j - z * nxp * NY, p = rr / NY;
-        gx = 2 * BB * (p + 1);
-        gz = z;
-        gy = rr - p * NY;
-        return !on_internal_plane(gy, m.NY) && !on_internal_plane(gz, m.NZ);
-    }
-    return false;
-}
-
-// The combine thread's shared nodes (NPT of them, one from each of NPT
-// sweeps of gridDim.x * CNT enumerated nodes), each with its partials summed
-// in the fixed order: f(g, constrained, sum).  All loads of the thread's
-// nodes are issued before the first sum.  With SKIP_CONSTRAINED a Dirichlet
-// node's partials are not read and f gets a zero sum.
-template <typename T, bool SKIP_CONSTRAINED, int NPT = 1, typename F>
-__device__ __forceinline__ void combine_visit(const KMesh &m, const T *__restrict__ face, F f)
-{
-    const unsigned G = gridDim.x, q = G / NXCD, r = G % NXCD;
-    const unsigned xk = blockIdx.x % NXCD, jb = blockIdx.x / NXCD;
-    const unsigned j0 = (xk * q + min(xk, r) + jb) * CNT + threadIdx.x;
-    const int nbx = (m.nx + BB - 1) / BB, nby = (m.ny + BB - 1) / BB, nbz = (m.nz + BB - 1) / BB;
-    bool has[NPT], con[NPT];
-    int64_t g[NPT];
-    T v[NPT][8];
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        int gx, gy, gz;
-        has[k] = combine_node_at(m, j0 + (unsigned)k * G * CNT, gx, gy, gz);
-        con[k] = has[k] && node_constrained(m, gx, gy, gz);
-        g[k] = has[k] ? node_index(m, gx, gy, gz) : 0;
-        const bool read = has[k] && !(SKIP_CONSTRAINED && con[k]);
-        int kx0 = 0, lx0 = 0, ky0 = 0, ly0 = 0, kz0 = 0, lz0 = 0, nxe = 0, nye = 0, nze = 0;
-        if (read) {
-            nxe = brick_entries(gx, m.NX, nbx, kx0, lx0);
-            nye = brick_entries(gy, m.NY, nby, ky0, ly0);
-            nze = brick_entries(gz, m.NZ, nbz, kz0, lz0);
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-            v[k][e] = T(0);
-            if (ex < nxe && ey < nye && ez < nze) {
-                const int b = (kx0 + ex) + nbx * ((ky0 + ey) + nby * (kz0 + ez));
-                v[k][e] = face[(int64_t)b * BFACE + face_slot(ex ? 0 : lx0, ey ? 0 : ly0, ez ? 0 : lz0)];
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        if (!has[k]) continue;
-        T s = v[k][0];
-#pragma unroll
-        for (int e = 1; e < 8; ++e) s += v[k][e];
-        f(g[k], con[k], (SKIP_CONSTRAINED && con[k]) ? T(0) : s);
-    }
-}
 
 // Brick-owned combine: a wavefront per 4 cells of brick depth (numbered
 // like the brick kernels, XCD-contiguously).  Each shared node is finished
@@ -699,9 +577,10 @@ __device__ __forceinline__ void combine_visit(const KMesh &m, const T *__restric
 // 81 + 144 + 128 = 353 over two wavefronts, three per lane.  They are
 // enumerated in three slabs: l_z = 0 (runs along x); l_y = 0 (runs along x);
 // l_x = 0 (runs along y, where the x-face slots are contiguous).  The
-// partials are summed in the order of combine_visit (z outer, then y, then
-// x; lower brick first), so the two give bitwise the same result for
-// BZ = BB; all loads of a lane's nodes are issued before the sums.
+// partials are summed in the fixed order above (the same order as a pass
+// that enumerates the shared nodes flat, which this pass replaced with
+// bitwise the same results); all loads of a lane's nodes are issued before
+// the sums.
 // Lanes that finish one brick's shared nodes: a wavefront per 4 cells of
 // brick depth.
 template <int BZ> struct CombineLanes {
@@ -805,16 +684,6 @@ __device__ __forceinline__ void combine_brick(const KMesh &m, const T *__restric
     if (brick >= n_bricks<BZ>(m)) return; // whole wavefronts; no barrier follows in them
     combine_brick_visit<T, DMODE != 0, BZ>(m, brick, (int)threadIdx.x % L, face,
                                            [&](int64_t g, bool constrained, T s) {
-        if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : ((DMODE == 2 || DMODE == 4) ? T(1) : T(0));
-        else y[g] = DMODE == 4 ? T(1) / s : s;
-    });
-}
-
-template <typename T, int DMODE, int NPT = 1>
-__device__ __forceinline__ void combine_shared(const KMesh &m, const T *__restrict__ face, const T *__restrict__ x,
-                                               T *__restrict__ y)
-{
-    combine_visit<T, DMODE != 0, NPT>(m, face, [&](int64_t g, bool constrained, T s) {
         if (DMODE != 0 && constrained) y[g] = DMODE == 1 ? x[g] : ((DMODE == 2 || DMODE == 4) ? T(1) : T(0));
         else y[g] = DMODE == 4 ? T(1) / s : s;
     });

@@ -421,9 +421,8 @@ __global__ void __launch_bounds__(BrickDims<BZ>::NT) heat_apply_kernel(KMesh m, 
 }
 
 // Second pass of an apply, a diagonal or a gradient: the shared nodes, each
-// the sum of the bricks' face partials, finished brick by brick
-// (combine_brick in brick.hpp: the same fixed sum order as the
-// node-enumerated combine_shared).  In CG mode the first workgroup first
+// the sum of the bricks' face partials in a fixed order, finished brick by
+// brick (combine_brick in brick.hpp).  In CG mode the first workgroup first
 // sums the bricks' partials of p.Ap (complete once the brick kernel has
 // finished) and sets alpha = rz / p.Ap, which saves a launch per
 // iteration.  A breakdown sets done here; a workgroup of this launch that

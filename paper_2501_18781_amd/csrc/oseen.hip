@@ -480,19 +480,23 @@ __global__ void __launch_bounds__(BNT) oseen_block_kernel(KMesh m, OseenArgs a, 
 }
 
 // Shared nodes of the 3x3 blocks: entry e = blockIdx.y of the face sheets,
-// summed in the fixed order, written to both symmetric positions; Dirichlet
-// nodes get the identity.
-__global__ void __launch_bounds__(CNT) oseen_block_combine_kernel(KMesh m, const double *__restrict__ face,
-                                                                  double *__restrict__ blocks)
+// summed in the fixed order brick by brick (combine_brick_visit), written to
+// both symmetric positions; Dirichlet nodes get the identity.
+__global__ void __launch_bounds__(BNT * CBW) oseen_block_combine_kernel(KMesh m, const double *__restrict__ face,
+                                                                        double *__restrict__ blocks)
 {
     const int e = blockIdx.y;
     const int c = e < 3 ? e : (e == 5 ? 1 : 0), cp = e < 3 ? e : (e == 3 ? 1 : 2);
-    combine_visit<double, true>(m, face + (int64_t)e * n_bricks(m) * BFACE, [&](int64_t g, bool constrained, double v) {
-        double *B = blocks + 9 * g;
-        const double s = constrained ? (c == cp ? 1.0 : 0.0) : v;
-        B[3 * c + cp] = s;
-        B[3 * cp + c] = s;
-    });
+    const int64_t nb = n_bricks(m);
+    const int brick = Brick::xcd_index() * CBW + (int)threadIdx.x / BNT;
+    if (brick >= nb) return; // a whole wavefront; no barrier follows in it
+    combine_brick_visit<double, true>(m, brick, (int)threadIdx.x % BNT, face + (int64_t)e * nb * BFACE,
+                                      [&](int64_t g, bool constrained, double v) {
+                                          double *B = blocks + 9 * g;
+                                          const double s = constrained ? (c == cp ? 1.0 : 0.0) : v;
+                                          B[3 * c + cp] = s;
+                                          B[3 * cp + c] = s;
+                                      });
 }
 
 hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *blocks, void *face, hipStream_t s)
@@ -509,9 +513,8 @@ hipError_t oseen_block_diagonal(const KMesh &m, const OseenArgs &a, double *bloc
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned rows = combine_blocks(m);
-    if (rows == 0) return hipSuccess; // single brick: nothing shared
-    oseen_block_combine_kernel<<<dim3(rows, 6), CNT, 0, s>>>(m, fc, blocks);
+    if (nb == 1) return hipSuccess; // single brick: nothing shared
+    oseen_block_combine_kernel<<<dim3((nb + CBW - 1) / CBW, 6), BNT * CBW, 0, s>>>(m, fc, blocks);
     return hipGetLastError();
 }
 
