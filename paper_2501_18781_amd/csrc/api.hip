@@ -628,14 +628,16 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = ndofs(c, op);
     const int m = restart;
+    // basis columns start on 512-byte boundaries (the Gram-Schmidt passes
+    // take 16-byte element pairs)
+    const int64_t ld = (3 * c->nn + 63) / 64 * 64;
     if (!c->V || c->V_cols < m + 1) {
         if (c->V) (void)hipFree(c->V);
         c->V = nullptr;
-        if (hipMalloc((void **)&c->V, sizeof(double) * (int64_t)(m + 1) * 3 * c->nn) != hipSuccess)
+        if (hipMalloc((void **)&c->V, sizeof(double) * (int64_t)(m + 1) * ld) != hipSuccess)
             return fail(c, MF_ERR_OOM, "GMRES basis allocation failed");
         c->V_cols = m + 1;
     }
-    const int64_t ld = 3 * c->nn;
     double *V = c->V;
     double *tmp, *pc = nullptr;
     if ((st = ws_vec(c, 0, &tmp))) return st;
