@@ -20,8 +20,8 @@ constexpr int VNT = 256;   // threads per block of the vector kernels
 constexpr int VMAXB = 1024; // max blocks of a reduction kernel
 constexpr int MAXV = 32;   // max vectors in a multi-dot
 constexpr int FNT = 1024;  // threads of the single-workgroup finalize kernels
-constexpr unsigned CG_RESID_BLOCKS = 1024; // partials the CG step kernel reduces in every workgroup
-constexpr int64_t CG_STEP_BLOCKS = 2048;
+constexpr unsigned CG_RESID_BLOCKS = 512; // partials the CG step kernels reduce in every workgroup
+constexpr int64_t CG_STEP_BLOCKS = 1024;
 
 static unsigned vec_blocks(int64_t n)
 {
@@ -756,6 +756,36 @@ template <typename L, typename U> __device__ __forceinline__ void grid_stride_un
     }
 }
 
+// The same visit, with the first step's loads issued before mid(), which
+// every thread calls once (a workgroup reduction with a barrier): the loads
+// are in flight while the workgroup sums the partials that use() needs.
+template <typename L, typename M, typename U>
+__device__ __forceinline__ void grid_stride_early(int64_t n, L load, M mid, U use)
+{
+    const int64_t S = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool full = i + (CG_UNROLL - 1) * S < n;
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < CG_UNROLL; ++k) load(k, i + k * S);
+    }
+    mid();
+    while (full) {
+#pragma unroll
+        for (int k = 0; k < CG_UNROLL; ++k) use(k, i + k * S);
+        i += CG_UNROLL * S;
+        full = i + (CG_UNROLL - 1) * S < n;
+        if (full) {
+#pragma unroll
+            for (int k = 0; k < CG_UNROLL; ++k) load(k, i + k * S);
+        }
+    }
+    for (; i < n; i += S) {
+        load(0, i);
+        use(0, i);
+    }
+}
+
 template <bool PC>
 __global__ void __launch_bounds__(VNT) cg_resid_kernel(CGState *st, const double *__restrict__ dinv,
                                                        double *__restrict__ r, const double *__restrict__ q,
@@ -814,36 +844,34 @@ __global__ void __launch_bounds__(VNT) cg_step_kernel(CGState *st, const double 
 {
     __shared__ double tot[2];
     if (!st->run) return; // this iteration's residual update was skipped (written by an earlier launch)
-    wave_set_sums<2>(partials, nb, tot);
-    const double rz = tot[0], rr = tot[1];
-    const bool bad = !isfinite(rz) || !isfinite(rr);
-    const bool stop = bad || rr <= st->thresh2 || st->iter >= st->maxit;
-    const double beta = rz / st->rz_old, alpha = st->alpha;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->rr = rr;
-        st->rz = rz;
-        st->beta = beta;
-        if (bad) st->breakdown = 1;
-        if (stop) st->done = 1;
-    }
     double xv[CG_UNROLL], pv[CG_UNROLL], zv[CG_UNROLL];
-    if (stop) {
-        // the last iteration: x only
-        grid_stride_unrolled(
-            n, [&](int k, int64_t i) { xv[k] = x[i]; pv[k] = p[i]; },
-            [&](int k, int64_t i) { x[i] = xv[k] + alpha * pv[k]; });
-        return;
-    }
-    grid_stride_unrolled(
+    double alpha = 0.0, beta = 0.0;
+    bool stop = false;
+    grid_stride_early(
         n,
         [&](int k, int64_t i) {
             xv[k] = x[i];
             pv[k] = p[i];
             zv[k] = z[i];
         },
+        [&] {
+            wave_set_sums<2>(partials, nb, tot);
+            const double rz = tot[0], rr = tot[1];
+            const bool bad = !isfinite(rz) || !isfinite(rr);
+            stop = bad || rr <= st->thresh2 || st->iter >= st->maxit;
+            beta = rz / st->rz_old;
+            alpha = st->alpha;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->rr = rr;
+                st->rz = rz;
+                st->beta = beta;
+                if (bad) st->breakdown = 1;
+                if (stop) st->done = 1;
+            }
+        },
         [&](int k, int64_t i) {
             x[i] = xv[k] + alpha * pv[k];
-            p[i] = zv[k] + beta * pv[k];
+            if (!stop) p[i] = zv[k] + beta * pv[k]; // the last iteration updates x only
         });
 }
 
@@ -972,48 +1000,48 @@ __global__ void __launch_bounds__(VNT) fcg_step_kernel(CGState *st, const double
 {
     __shared__ double tot[1];
     if (!st->run) return; // written by an earlier launch; this kernel may write done
-    wave_set_sums<1>(partials, nb, tot);
-    // fields read here are written by earlier launches only (rz_old by the
-    // residual step's finalize; rz, written below, is not read)
-    const double rz = tot[0], alpha = st->alpha, rz_old = st->rz_old;
-    const bool bad = !isfinite(rz) || !(rz > 0.0);
-    // first direction: rz_old == 0 marks "no previous direction"
-    const double beta = (!bad && rz_old != 0.0) ? (rz - st->rzprev) / rz_old : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->beta = beta;
-        st->xpend = 0;
-        if (bad) {
-            st->breakdown = 1;
-            st->done = 1;
-        } else {
-            st->rz = rz;
-        }
-    }
     float zv[CG_UNROLL];
     double pv[CG_UNROLL], xv[CG_UNROLL];
-    if (bad) { // x still takes the deferred update; p is not needed any more
-        grid_stride_unrolled(
-            n, [&](int k, int64_t i) { pv[k] = p[i]; xv[k] = x[i]; },
-            [&](int k, int64_t i) { x[i] = xv[k] + alpha * pv[k]; });
-        return;
-    }
-    grid_stride_unrolled(
+    double alpha = 0.0, beta = 0.0;
+    bool bad = false;
+    grid_stride_early(
         n,
         [&](int k, int64_t i) {
             zv[k] = z[i];
             pv[k] = p[i];
             xv[k] = x[i];
         },
+        [&] {
+            wave_set_sums<1>(partials, nb, tot);
+            // fields read here are written by earlier launches only (rz_old by
+            // the residual step's finalize; rz, written below, is not read)
+            const double rz = tot[0], rz_old = st->rz_old;
+            alpha = st->alpha;
+            bad = !isfinite(rz) || !(rz > 0.0);
+            // first direction: rz_old == 0 marks "no previous direction"
+            beta = (!bad && rz_old != 0.0) ? (rz - st->rzprev) / rz_old : 0.0;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->beta = beta;
+                st->xpend = 0;
+                if (bad) {
+                    st->breakdown = 1;
+                    st->done = 1;
+                } else {
+                    st->rz = rz;
+                }
+            }
+        },
         [&](int k, int64_t i) {
             x[i] = xv[k] + alpha * pv[k];
-            p[i] = (double)zv[k] + beta * pv[k];
+            // on a breakdown x still takes the deferred update; p is not needed any more
+            if (!bad) p[i] = (double)zv[k] + beta * pv[k];
         });
 }
 
 hipError_t fcg_direction(CGState *st, const double *r, const float *z, double *p, double *x, int64_t n,
                          const RedWS *red, hipStream_t s)
 {
-    const unsigned nb = vec_blocks(n);
+    const unsigned nb = cg_resid_blocks(n);
     if (red->capacity < nb) return hipErrorInvalidValue;
     fcg_dir_kernel<<<nb, VNT, 0, s>>>(st, r, z, n, *red);
     hipError_t e = hipGetLastError();
