@@ -196,7 +196,10 @@ mf_status mf_cg_solve(mf_ctx *ctx, const mf_operator *op, int32_t precond, const
  * Gram-Schmidt and one re-orthogonalization pass and Givens rotations.
  * precond: MF_PC_NONE, MF_PC_JACOBI, or MF_PC_BLOCK_JACOBI (inverse 3x3 nodal
  * blocks, Oseen).  transpose != 0 solves A^T x = b.  Stops when the residual
- * estimate is <= rtol ||b|| and the true residual confirms it. */
+ * estimate is <= rtol ||b|| and the true residual confirms it.  restart is
+ * 1..31 (MF_ERR_ARG otherwise).  The context keeps the Krylov basis (restart
+ * + 1 columns of 3 n_nodes doubles, each rounded up to a multiple of 64)
+ * until it is destroyed; a later call with a larger restart reallocates it. */
 mf_status mf_gmres_solve(mf_ctx *ctx, const mf_operator *op, int32_t precond, int32_t restart, int32_t transpose,
                          const double *b, double *x, double rtol, int32_t maxit, mf_solve_info *info,
                          mf_stream stream);
