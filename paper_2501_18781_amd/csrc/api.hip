@@ -115,13 +115,13 @@ mf_status mf_create(const mf_mesh *mesh, mf_ctx **out)
         delete c;
         return MF_ERR_HIP;
     }
-    // reduction workspace: enough for one partial per heat brick and 32 sets of 1024 blocks
+    // reduction workspace: enough for one partial per heat brick and 64 sets of 1024 blocks
     const int64_t nbricks = ((k.nx + 3) / 4) * (int64_t)((k.ny + 3) / 4) * ((k.nz + 3) / 4);
-    int64_t cap = nbricks > 32 * 1024 ? nbricks : 32 * 1024;
+    int64_t cap = nbricks > 64 * 1024 ? nbricks : 64 * 1024;
     c->cap = (unsigned)cap;
     bool ok = hipMalloc((void **)&c->partials, sizeof(double) * cap) == hipSuccess &&
               hipMalloc((void **)&c->cg, sizeof(CGState)) == hipSuccess &&
-              hipMalloc((void **)&c->scal, sizeof(double) * 256) == hipSuccess &&
+              hipMalloc((void **)&c->scal, sizeof(double) * 2048) == hipSuccess &&
               hipHostMalloc((void **)&c->h_state, sizeof(CGState), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void **)&c->h_scal, sizeof(double) * 256, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -609,7 +609,8 @@ mf_status cg_solve(mf_ctx *c, const mf_operator *op, int precond, const double *
 }
 
 // ---------------------------------------------------------------------------
-// GMRES(m), right preconditioned, CGS2 Arnoldi, Givens rotations (Saad Alg. 9.5)
+// GMRES(m), right preconditioned, Arnoldi by classical Gram-Schmidt applied twice
+// (the second pass delayed by one step), Givens rotations (Saad Alg. 9.5)
 // ---------------------------------------------------------------------------
 extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t precond, int32_t restart,
                                     int32_t transpose, const double *b, double *x, double rtol, int32_t maxit,
@@ -628,8 +629,8 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = ndofs(c, op);
     const int m = restart;
-    // basis columns start on 512-byte boundaries (the Gram-Schmidt passes
-    // take 16-byte element pairs)
+    // basis columns start on 512-byte boundaries (every wavefront's loads of
+    // a column cover whole 128-byte lines)
     const int64_t ld = (3 * c->nn + 63) / 64 * 64;
     if (!c->V || c->V_cols < m + 1) {
         if (c->V) (void)hipFree(c->V);
@@ -712,39 +713,43 @@ extern "C" mf_status mf_gmres_solve(mf_ctx *c, const mf_operator *op, int32_t pr
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jdone = 0;
-        // Arnoldi step j on the device: w = A M^{-1} v_j, two passes of
-        // classical Gram-Schmidt (the first update and the second
-        // projection share one read of V: three passes, not four), w
-        // normalized by its norm, and the Hessenberg column (both
-        // projections and the squared norm) copied to the host.  Scalars of
-        // step j go to slot j mod 2 of the device and host scalar arrays
-        // (first projection at +0, second at +32, squared norm at +64).
-        // While the host applies the Givens rotations to column j, the GPU
-        // already runs step j + 1; when column j ends the cycle, step j + 1
-        // is simply not used.
+        // Arnoldi with delayed re-orthogonalization on the device: step j
+        // forms w = A M^-1 u_j from the once-orthogonalized candidate u_j,
+        // completes column j - 1 of the Hessenberg matrix with one pass
+        // over the basis, and with a second pass writes q_j and the next
+        // candidate (two passes per step).  The closing step of a cycle
+        // only completes the last column.  Column j - 1 is copied to slot
+        // j mod 2 of the host scalars; while the host applies the Givens
+        // rotations to it, the GPU already runs step j + 1 (a step launched
+        // past the end of the cycle is not used).
+        const int mc = std::min(m, maxit - total); // columns of this cycle at most
+        double *Hd = c->scal + 512;
+        HIPCHK(c, vfill(Hd, 0.0, DGS_LDH * DGS_LDH, 0, s));
         auto step = [&](int j) -> hipError_t {
-            double *w = V + (int64_t)(j + 1) * ld, *hd = c->scal + (j & 1) * 128;
-            hipError_t e = prec(V + (int64_t)j * ld, zt);
-            if (e == hipSuccess) e = apply_any(c, op, transpose, zt, w, s);
-            if (e == hipSuccess) e = vmultidot(V, ld, j + 1, w, n, hd, &red, s);
-            if (e == hipSuccess) e = vmultiaxpy_dot(V, ld, j + 1, hd, w, n, hd + 32, &red, s);
-            if (e == hipSuccess) e = vmultiaxpy(V, ld, j + 1, hd + 32, w, n, hd + 64, &red, s);
-            if (e == hipSuccess) e = vscale_inv_norm(w, n, hd + 64, s);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(c->h_scal + (j & 1) * 128, hd, sizeof(double) * 65, hipMemcpyDeviceToHost, s);
+            const bool full = j < mc;
+            double *u = V + (int64_t)j * ld, *w = full ? V + (int64_t)(j + 1) * ld : u;
+            double *coef = c->scal + 1536 + (j & 1) * 128, *col = c->scal + 1792 + (j & 1) * 64;
+            hipError_t e = hipSuccess;
+            if (full) {
+                e = prec(u, zt);
+                if (e == hipSuccess) e = apply_any(c, op, transpose, zt, w, s);
+            }
+            if (e == hipSuccess) e = dgs_step(V, ld, j, full, u, w, n, Hd, coef, col, &red, s);
+            if (e == hipSuccess && j > 0)
+                e = hipMemcpyAsync(c->h_scal + (j & 1) * 64, col, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipEventRecord(c->poll_ev[j & 1], s);
             return e;
         };
         HIPCHK(c, poll_events(c));
         HIPCHK(c, step(0));
-        for (int j = 0; j < m; ++j) {
-            // the next step, unless the cycle or the iteration budget ends here
-            if (j + 1 < m && total + 1 < maxit) HIPCHK(c, step(j + 1));
-            HIPCHK(c, hipEventSynchronize(c->poll_ev[j & 1]));
+        HIPCHK(c, step(1));
+        for (int j = 0; j < mc; ++j) {
+            // column j is completed by step j + 1, launched already; queue step j + 2
+            if (j + 2 <= mc) HIPCHK(c, step(j + 2));
+            HIPCHK(c, hipEventSynchronize(c->poll_ev[(j + 1) & 1]));
             ++total;
-            const double *hh = c->h_scal + (j & 1) * 128;
-            for (int i = 0; i <= j; ++i) H[i * m + j] = hh[i] + hh[32 + i];
-            H[(j + 1) * m + j] = sqrt(hh[64]);
+            const double *hh = c->h_scal + ((j + 1) & 1) * 64;
+            for (int i = 0; i <= j + 1; ++i) H[i * m + j] = hh[i];
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
                 H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];

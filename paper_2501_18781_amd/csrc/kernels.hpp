@@ -143,23 +143,23 @@ hipError_t vinv(double *d, int64_t n, hipStream_t s);                           
 hipError_t vcvt_d2f(const double *x, float *y, int64_t n, hipStream_t s);
 hipError_t vcvt_f2d(const float *x, double *y, int64_t n, hipStream_t s);
 hipError_t vmulf(const float *d, const float *x, float *y, int64_t n, hipStream_t s);
-// out[k] = sum_i V_k[i] w[i] for k < nv (V columns of length n, leading dim ld);
-// nv = 1 with V = x gives a plain dot product.  out is device memory.
-// w = w / sqrt(n2[0]) when n2[0] > 0 (n2 a device scalar: a norm formed by an
-// earlier launch), else w unchanged.
-hipError_t vscale_inv_norm(double *w, int64_t n, const double *n2, hipStream_t s);
 // out[0] = ||b - t||^2 (device scalar), the partials in red.
 hipError_t vdiffnorm2(const double *b, const double *t, int64_t n, double *out, const RedWS *red, hipStream_t s);
+// out[k] = sum_i V_k[i] w[i] for k < nv (V columns of length n, leading dim ld);
+// nv = 1 with V = x gives a plain dot product.  out is device memory.
 hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out,
                      const RedWS *red, hipStream_t s);
-// w -= sum_k V_k h[k] (h device), optionally out_norm2 = ||w||^2 after the update.
-hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n,
-                      double *out_norm2, const RedWS *red, hipStream_t s);
-// w -= V h, then out = V^T w (nv <= 32), in one pass over V.
-hipError_t vmultiaxpy_dot(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out,
-                          const RedWS *red, hipStream_t s);
 // y = sum_k V_k h[k] (h device)
 hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double *y, int64_t n, hipStream_t s);
+// Arnoldi step j with delayed re-orthogonalization (vec.hip).  V holds the
+// final q_0 .. q_{j-1}; u = column j (once orthogonalized), w = column j + 1
+// (A M^-1 u on entry when full).  Completes column j - 1 of the unrotated
+// Hessenberg matrix H (device, row stride DGS_LDH) and copies it to col;
+// when full, also writes q_j into u, the next candidate into w, and column
+// j's first projection into H.  j <= DGS_MAXJ (a closing step: full = false).
+constexpr int DGS_MAXJ = 31, DGS_LDH = 32, DGS_INV = 32, DGS_C = 33;
+hipError_t dgs_step(const double *V, int64_t ld, int j, bool full, double *u, double *w, int64_t n, double *H,
+                    double *coef, double *col, const RedWS *red, hipStream_t s);
 hipError_t block3_invert(double *blocks, int64_t nn, hipStream_t s);
 hipError_t block3_apply(const double *binv, const double *x, double *y, int64_t nn, hipStream_t s);
 

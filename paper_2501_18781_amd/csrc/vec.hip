@@ -49,6 +49,22 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Sum NV per-thread values over the block; results valid in thread 0 (out[]).
+// One lane's share of a set of nb partials: entries lane, lane + 64, ...,
+// in four interleaved sums so that four loads are in flight at a time.
+__device__ __forceinline__ double lane_partial_sum(const double *p, unsigned nb, int lane)
+{
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    unsigned b = lane;
+    for (; b + 192 < nb; b += 256) {
+        v0 += p[b];
+        v1 += p[b + 64];
+        v2 += p[b + 128];
+        v3 += p[b + 192];
+    }
+    for (; b < nb; b += 64) v0 += p[b];
+    return (v0 + v1) + (v2 + v3);
+}
+
 template <int NV> __device__ __forceinline__ void block_sum_n(double *v, double *lds /*[NV][VNT/64]*/)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -83,10 +99,7 @@ __device__ __forceinline__ void wave_set_sums(const double *partials, unsigned n
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (w < NV) {
-        const double *p = partials + (size_t)w * nb;
-        double s = 0.0;
-        for (unsigned b = lane; b < nb; b += 64) s += p[b];
-        s = wave_sum(s);
+        const double s = wave_sum(lane_partial_sum(partials + (size_t)w * nb, nb, lane));
         if (lane == 0) out_lds[w] = s;
     }
     __syncthreads();
@@ -98,10 +111,7 @@ __global__ void __launch_bounds__(FNT) sum_finalize_kernel(const double *__restr
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int k = w; k < nv; k += FNT / 64) {
-        const double *p = partials + (size_t)k * nb;
-        double s = 0.0;
-        for (unsigned b = lane; b < nb; b += 64) s += p[b];
-        s = wave_sum(s);
+        const double s = wave_sum(lane_partial_sum(partials + (size_t)k * nb, nb, lane));
         if (lane == 0) out[k] = s;
     }
 }
@@ -265,22 +275,12 @@ hipError_t picard_update(const double *T_old, const double *dT, double *T, int64
 }
 
 // ---------------------------------------------------------------------------
-// Multi-dot, multi-axpy, combination (GMRES Gram-Schmidt).  The number of
-// vectors NV is a template parameter (1..32, chosen by a switch), so that
-// every loop over the vectors is unrolled without conditions and all NV
-// loads of an element are in flight together.  From PAIR_MIN vectors on,
-// the multi-dot and the multi-update take two consecutive elements per
-// thread (16-byte loads) when the stride and the pointers allow it: with
-// one element the compiler's batching of 20 or more loads dropped these
-// passes to about 4 TB/s at some widths, with pairs they stream at about
-// 5.5 TB/s for every width.
+// Multi-dot and combination of basis vectors.  The number of vectors NV is
+// a template parameter (1..32, chosen by a switch), so that every loop over
+// the vectors is unrolled without conditions and all NV loads of an element
+// are in flight together.
 // ---------------------------------------------------------------------------
-constexpr int PAIR_MIN = 20;
 
-static bool pairable(const double *V, int64_t ld, const double *w)
-{
-    return (ld & 1) == 0 && ((uintptr_t)V & 15) == 0 && ((uintptr_t)w & 15) == 0;
-}
 #define MF_NV_CASES(X)                                                                                      \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
         X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
@@ -313,73 +313,20 @@ __global__ void __launch_bounds__(VNT) multidot_kernel(const double *__restrict_
     store_block_partials<NV>(acc, lds, red);
 }
 
-// The same sums over element pairs (2i, 2i + 1); ld even, V and w 16-byte
-// aligned.  The last element of an odd n goes to thread 0 of block 0.
-template <int NV>
-__global__ void __launch_bounds__(VNT) multidot_pair_kernel(const double *__restrict__ V, int64_t ld,
-                                                            const double *__restrict__ w, int64_t n, RedWS red)
-{
-    __shared__ double lds[NV * (VNT / 64)];
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    GRID_STRIDE(i, n / 2)
-    {
-        const double2 wi = ((const double2 *)w)[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const double2 v = ((const double2 *)(V + (int64_t)k * ld))[i];
-            acc[k] += v.x * wi.x + v.y * wi.y;
-        }
-    }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) acc[k] += V[(int64_t)k * ld + n - 1] * w[n - 1];
-    }
-    store_block_partials<NV>(acc, lds, red);
-}
-
-template <int NV> static void launch_multidot(bool pair, unsigned nb, const double *V, int64_t ld, const double *w,
-                                              int64_t n, const RedWS &red, hipStream_t s)
-{
-    if constexpr (NV >= PAIR_MIN) {
-        if (pair) {
-            multidot_pair_kernel<NV><<<nb, VNT, 0, s>>>(V, ld, w, n, red);
-            return;
-        }
-    }
-    multidot_kernel<NV><<<nb, VNT, 0, s>>>(V, ld, w, n, red);
-}
-
 hipError_t vmultidot(const double *V, int64_t ld, int nv, const double *w, int64_t n, double *out, const RedWS *red,
                      hipStream_t s)
 {
     if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
     const unsigned nb = vec_blocks(n);
     if (red->capacity < nb * MAXV) return hipErrorInvalidValue;
-    const bool pair = pairable(V, ld, w);
     switch (nv) {
 #define MF_CASE(N)                                                                                            \
-    case N: launch_multidot<N>(pair, nb, V, ld, w, n, *red, s); break;
+    case N: multidot_kernel<N><<<nb, VNT, 0, s>>>(V, ld, w, n, *red); break;
         MF_NV_CASES(MF_CASE)
 #undef MF_CASE
     }
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
-}
-
-__global__ void scale_inv_norm_kernel(double *__restrict__ w, int64_t n, const double *__restrict__ n2)
-{
-    const double hn = sqrt(n2[0]);
-    if (!(hn > 0.0)) return;
-    const double a = 1.0 / hn;
-    GRID_STRIDE(i, n) w[i] = a * w[i];
-}
-
-hipError_t vscale_inv_norm(double *w, int64_t n, const double *n2, hipStream_t s)
-{
-    scale_inv_norm_kernel<<<ew_blocks(n), VNT, 0, s>>>(w, n, n2);
-    return hipGetLastError();
 }
 
 // Partials of ||b - t||^2 (the true residual of a solve, without storing it).
@@ -403,147 +350,6 @@ hipError_t vdiffnorm2(const double *b, const double *t, int64_t n, double *out, 
     diffnorm2_kernel<<<nb, VNT, 0, s>>>(b, t, n, *red);
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : sum_finalize(*red, nb, 1, out, s);
-}
-
-// w -= V h; optionally ||w||^2 of the result
-template <int NV>
-__global__ void __launch_bounds__(VNT) multiaxpy_kernel(const double *__restrict__ V, int64_t ld,
-                                                        const double *__restrict__ h, double *__restrict__ w,
-                                                        int64_t n, bool norm, RedWS red)
-{
-    __shared__ double lds[VNT / 64];
-    __shared__ double hs[NV];
-    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
-    __syncthreads();
-    double acc = 0.0;
-    GRID_STRIDE(i, n)
-    {
-        double vk[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) vk[k] = V[(int64_t)k * ld + i];
-        double v = w[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v -= vk[k] * hs[k];
-        w[i] = v;
-        acc += v * v;
-    }
-    if (norm) grid_partials<1>(&acc, red, lds);
-}
-
-// The same update over element pairs (2i, 2i + 1); ld even, V and w 16-byte
-// aligned.  Each element takes the same operations in the same order as in
-// the one-element kernel; only the norm's partial sums are grouped
-// differently.
-template <int NV>
-__global__ void __launch_bounds__(VNT) multiaxpy_pair_kernel(const double *__restrict__ V, int64_t ld,
-                                                             const double *__restrict__ h, double *__restrict__ w,
-                                                             int64_t n, bool norm, RedWS red)
-{
-    __shared__ double lds[VNT / 64];
-    __shared__ double hs[NV];
-    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
-    __syncthreads();
-    double acc = 0.0;
-    GRID_STRIDE(i, n / 2)
-    {
-        double2 vk[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) vk[k] = ((const double2 *)(V + (int64_t)k * ld))[i];
-        double2 v = ((double2 *)w)[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            v.x -= vk[k].x * hs[k];
-            v.y -= vk[k].y * hs[k];
-        }
-        ((double2 *)w)[i] = v;
-        acc += v.x * v.x + v.y * v.y;
-    }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-        double v = w[n - 1];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v -= V[(int64_t)k * ld + n - 1] * hs[k];
-        w[n - 1] = v;
-        acc += v * v;
-    }
-    if (norm) grid_partials<1>(&acc, red, lds);
-}
-
-template <int NV> static void launch_multiaxpy(bool pair, unsigned nb, const double *V, int64_t ld, const double *h,
-                                               double *w, int64_t n, bool norm, const RedWS &red, hipStream_t s)
-{
-    if constexpr (NV >= PAIR_MIN) {
-        if (pair) {
-            multiaxpy_pair_kernel<NV><<<nb, VNT, 0, s>>>(V, ld, h, w, n, norm, red);
-            return;
-        }
-    }
-    multiaxpy_kernel<NV><<<nb, VNT, 0, s>>>(V, ld, h, w, n, norm, red);
-}
-
-hipError_t vmultiaxpy(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out_norm2,
-                      const RedWS *red, hipStream_t s)
-{
-    if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
-    const unsigned nb = vec_blocks(n);
-    if (out_norm2 && red->capacity < nb) return hipErrorInvalidValue;
-    const RedWS r = red ? *red : RedWS{nullptr, 0};
-    const bool norm = out_norm2 != nullptr;
-    const bool pair = pairable(V, ld, w);
-    switch (nv) {
-#define MF_CASE(N)                                                                                            \
-    case N: launch_multiaxpy<N>(pair, nb, V, ld, h, w, n, norm, r, s); break;
-        MF_NV_CASES(MF_CASE)
-#undef MF_CASE
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !norm) return e;
-    return sum_finalize(*red, nb, 1, out_norm2, s);
-}
-
-// w -= V h and, in the same pass, g = V^T w (the new w): the first update
-// and the second projection of classical Gram-Schmidt applied twice share
-// one read of V.
-template <int NV>
-__global__ void __launch_bounds__(VNT) multiaxpy_dot_kernel(const double *__restrict__ V, int64_t ld,
-                                                            const double *__restrict__ h, double *__restrict__ w,
-                                                            int64_t n, RedWS red)
-{
-    __shared__ double lds[NV * (VNT / 64)];
-    __shared__ double hs[NV];
-    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
-    __syncthreads();
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    GRID_STRIDE(i, n)
-    {
-        double vk[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) vk[k] = V[(int64_t)k * ld + i];
-        double v = w[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v -= vk[k] * hs[k];
-        w[i] = v;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) acc[k] += vk[k] * v;
-    }
-    store_block_partials<NV>(acc, lds, red);
-}
-
-hipError_t vmultiaxpy_dot(const double *V, int64_t ld, int nv, const double *h, double *w, int64_t n, double *out,
-                          const RedWS *red, hipStream_t s)
-{
-    if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
-    const unsigned nb = vec_blocks(n);
-    if (red->capacity < nb * MAXV) return hipErrorInvalidValue;
-    switch (nv) {
-#define MF_CASE(N)                                                                                            \
-    case N: multiaxpy_dot_kernel<N><<<nb, VNT, 0, s>>>(V, ld, h, w, n, *red); break;
-        MF_NV_CASES(MF_CASE)
-#undef MF_CASE
-    }
-    hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : sum_finalize(*red, nb, nv, out, s);
 }
 
 // y = V h
@@ -579,6 +385,301 @@ hipError_t vcombine(const double *V, int64_t ld, int nv, const double *h, double
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Arnoldi with delayed re-orthogonalization (classical Gram-Schmidt applied
+// twice, the second pass of a vector taken one step later; the low-synchro-
+// nization form of Swirydowicz, Langou, Ananthan, Yang and Thomas, 2020).
+// Step j of a cycle starts from the final q_0 .. q_{j-1} and u_j, the j-th
+// candidate orthogonalized once, and from w = A M^-1 u_j.  One pass over the
+// basis forms a = Q^T u_j, b = Q^T w, u_j.u_j and u_j.w.  Then
+//   s = a, nu = sqrt(u_j.u_j - s.s), q_j = (u_j - Q s) / nu
+// completes column j-1 of the Hessenberg matrix (the first projection of
+// the previous step plus s, and nu).  Since A M^-1 Q = Q_j H (Arnoldi), the
+// product with q_j is (w - Q_j H s) / nu: with t = H s its first projection
+// is h = ((Q^T w, q_j.w) - t) / nu, where q_j.w = (u_j.w - s.b) / nu, and
+//   u_{j+1} = w / nu - Q_j (t / nu + h)
+// is the next candidate.  A second pass over the basis writes q_j and
+// u_{j+1}: two passes per step instead of three, and the normalization is
+// part of the second.  The device keeps the (unrotated) Hessenberg matrix.
+// ---------------------------------------------------------------------------
+#define MF_NV0_CASES(X)                                                                                     \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) \
+        X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
+
+// partial sets: 0..NV-1 q_k.u, NV..2NV-1 q_k.w, 2NV u.u, 2NV+1 u.w
+template <int NV>
+__global__ void __launch_bounds__(VNT) dgs_dot_kernel(const double *__restrict__ V, int64_t ld,
+                                                      const double *__restrict__ u, const double *__restrict__ w,
+                                                      int64_t n, RedWS red)
+{
+    constexpr int NS = 2 * NV + 2;
+    __shared__ double lds[NS * (VNT / 64)];
+    double acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double ui = u[i], wi = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double v = V[(int64_t)k * ld + i];
+            acc[k] += v * ui;
+            acc[NV + k] += v * wi;
+        }
+        acc[2 * NV] += ui * ui;
+        acc[2 * NV + 1] += ui * wi;
+    }
+    store_block_partials<NS>(acc, lds, red);
+}
+
+// The same over element pairs (2i, 2i + 1) with 16-byte loads; V, u and w
+// 16-byte aligned and ld even.  The last element of an odd n goes to thread
+// 0 of block 0.
+template <int NV>
+__global__ void __launch_bounds__(VNT) dgs_dot_pair_kernel(const double *__restrict__ V, int64_t ld,
+                                                           const double *__restrict__ u,
+                                                           const double *__restrict__ w, int64_t n, RedWS red)
+{
+    constexpr int NS = 2 * NV + 2;
+    __shared__ double lds[NS * (VNT / 64)];
+    double acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    GRID_STRIDE(i, n / 2)
+    {
+        const double2 ui = ((const double2 *)u)[i], wi = ((const double2 *)w)[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double2 v = ((const double2 *)(V + (int64_t)k * ld))[i];
+            acc[k] += v.x * ui.x + v.y * ui.y;
+            acc[NV + k] += v.x * wi.x + v.y * wi.y;
+        }
+        acc[2 * NV] += ui.x * ui.x + ui.y * ui.y;
+        acc[2 * NV + 1] += ui.x * wi.x + ui.y * wi.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double ui = u[n - 1], wi = w[n - 1];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double v = V[(int64_t)k * ld + n - 1];
+            acc[k] += v * ui;
+            acc[NV + k] += v * wi;
+        }
+        acc[2 * NV] += ui * ui;
+        acc[2 * NV + 1] += ui * wi;
+    }
+    store_block_partials<NS>(acc, lds, red);
+}
+
+// One workgroup: totals of the dot pass, then the scalars of step j.
+// H: unrotated Hessenberg matrix, row i at i * DGS_LDH; column j-1 holds the
+// first projection of the previous step until this kernel completes it.
+// coef: s at 0..j-1, 1 / nu at DGS_INV, t / nu + h at DGS_C + 0..j.
+// col: the completed column j-1 (rows 0..j), for the host.
+__global__ void __launch_bounds__(FNT) dgs_scalars_kernel(const double *__restrict__ partials, unsigned nb, int j,
+                                                          int full, double *__restrict__ H,
+                                                          double *__restrict__ coef, double *__restrict__ col)
+{
+    __shared__ double sums[2 * DGS_MAXJ + 2];
+    __shared__ double cprev[DGS_MAXJ + 1];
+    __shared__ double sh[3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, t = threadIdx.x;
+    const int ns = 2 * j + 2;
+    for (int k = wv; k < ns; k += FNT / 64) {
+        const double v = wave_sum(lane_partial_sum(partials + (size_t)k * nb, nb, lane));
+        if (lane == 0) sums[k] = v;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        double ss = 0.0, sb = 0.0;
+        if (lane < j) {
+            ss = sums[lane] * sums[lane];
+            sb = sums[lane] * sums[j + lane];
+        }
+        ss = wave_sum(ss);
+        sb = wave_sum(sb);
+        if (lane == 0) {
+            // q_0 is r / ||r||: it is final as it stands
+            const double nu = j == 0 ? 1.0 : sqrt(fmax(sums[2 * j] - ss, 0.0));
+            sh[0] = nu;
+            sh[1] = 1.0 / nu;
+            sh[2] = sb;
+        }
+    }
+    __syncthreads();
+    const double inv = sh[1];
+    if (j > 0 && t <= j) {
+        const double v = t < j ? H[t * DGS_LDH + (j - 1)] + sums[t] : sh[0];
+        cprev[t] = v;
+        H[t * DGS_LDH + (j - 1)] = v;
+        col[t] = v;
+    }
+    __syncthreads();
+    if (full && t <= j) {
+        // t_i = (H s)_i over the completed columns 0 .. j-1 (zero below the subdiagonal)
+        double tt = 0.0;
+        for (int k = 0; k + 1 < j; ++k) tt += H[t * DGS_LDH + k] * sums[k];
+        if (j > 0) tt += cprev[t] * sums[j - 1];
+        const double qw = t < j ? sums[j + t] : (sums[2 * j + 1] - sh[2]) * inv;
+        const double h = (qw - tt) * inv;
+        H[t * DGS_LDH + j] = h;
+        coef[DGS_C + t] = tt * inv + h;
+        if (t < j) coef[t] = sums[t];
+    }
+    if (t == 0) coef[DGS_INV] = inv;
+}
+
+// q_j = (u - Q s) / nu into u, u_{j+1} = w / nu - Q c - q_j c_j into w
+template <int NV>
+__global__ void __launch_bounds__(VNT) dgs_update_kernel(const double *__restrict__ V, int64_t ld,
+                                                         double *__restrict__ u, double *__restrict__ w, int64_t n,
+                                                         const double *__restrict__ coef)
+{
+    __shared__ double cs[2 * NV + 2];
+    if (threadIdx.x < NV) cs[threadIdx.x] = coef[threadIdx.x];
+    if (threadIdx.x <= NV) cs[NV + threadIdx.x] = coef[DGS_C + threadIdx.x];
+    if (threadIdx.x == 0) cs[2 * NV + 1] = coef[DGS_INV];
+    __syncthreads();
+    const double inv = cs[2 * NV + 1];
+    GRID_STRIDE(i, n)
+    {
+        double vk[NV > 0 ? NV : 1];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vk[k] = V[(int64_t)k * ld + i];
+        double q = u[i], y = w[i] * inv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) q -= vk[k] * cs[k];
+        q *= inv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) y -= vk[k] * cs[NV + k];
+        y -= q * cs[2 * NV];
+        u[i] = q;
+        w[i] = y;
+    }
+}
+
+// the same over element pairs (see dgs_dot_pair_kernel)
+template <int NV>
+__global__ void __launch_bounds__(VNT) dgs_update_pair_kernel(const double *__restrict__ V, int64_t ld,
+                                                              double *__restrict__ u, double *__restrict__ w,
+                                                              int64_t n, const double *__restrict__ coef)
+{
+    __shared__ double cs[2 * NV + 2];
+    if (threadIdx.x < NV) cs[threadIdx.x] = coef[threadIdx.x];
+    if (threadIdx.x <= NV) cs[NV + threadIdx.x] = coef[DGS_C + threadIdx.x];
+    if (threadIdx.x == 0) cs[2 * NV + 1] = coef[DGS_INV];
+    __syncthreads();
+    const double inv = cs[2 * NV + 1];
+    GRID_STRIDE(i, n / 2)
+    {
+        double2 vk[NV > 0 ? NV : 1];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vk[k] = ((const double2 *)(V + (int64_t)k * ld))[i];
+        double2 q = ((const double2 *)u)[i], y = ((const double2 *)w)[i];
+        y.x *= inv;
+        y.y *= inv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            q.x -= vk[k].x * cs[k];
+            q.y -= vk[k].y * cs[k];
+        }
+        q.x *= inv;
+        q.y *= inv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            y.x -= vk[k].x * cs[NV + k];
+            y.y -= vk[k].y * cs[NV + k];
+        }
+        y.x -= q.x * cs[2 * NV];
+        y.y -= q.y * cs[2 * NV];
+        ((double2 *)u)[i] = q;
+        ((double2 *)w)[i] = y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t i = n - 1;
+        double q = u[i], y = w[i] * inv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) q -= V[(int64_t)k * ld + i] * cs[k];
+        q *= inv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) y -= V[(int64_t)k * ld + i] * cs[NV + k];
+        y -= q * cs[2 * NV];
+        u[i] = q;
+        w[i] = y;
+    }
+}
+
+constexpr int DGS_PAIR_MIN = 10; // basis widths from which the passes take element pairs
+
+// Workgroups of VNT threads of `kernel` that the device holds at once (its
+// occupancy times the compute units), cached by the caller per kernel.  The
+// wide passes use 60-170 VGPRs: a grid of exactly one resident round avoids
+// a second, partly filled round that runs alone.
+template <typename K> static unsigned resident_blocks(K kernel, int *cache)
+{
+    static int cus = 0;
+    if (cus <= 0) {
+        int dev = 0, v = 0;
+        cus = (hipGetDevice(&dev) == hipSuccess &&
+               hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                  ? v
+                  : 256;
+    }
+    if (*cache <= 0) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, VNT, 0) != hipSuccess || b < 1) b = 1;
+        *cache = b;
+    }
+    return (unsigned)(*cache * cus);
+}
+
+
+hipError_t dgs_step(const double *V, int64_t ld, int j, bool full, double *u, double *w, int64_t n, double *H,
+                    double *coef, double *col, const RedWS *red, hipStream_t s)
+{
+    if (j < 0 || j > DGS_MAXJ || (full && j >= DGS_MAXJ)) return hipErrorInvalidValue;
+    const int ns = 2 * j + 2;
+    unsigned nb = vec_blocks(n);
+    if (nb * (unsigned)ns > red->capacity) nb = (unsigned)(red->capacity / (unsigned)ns);
+    if (nb < 1) return hipErrorInvalidValue;
+    const double *wd = full ? w : u; // a closing step has no new product
+    const bool pair = j >= DGS_PAIR_MIN && (ld & 1) == 0 && ((uintptr_t)V & 15) == 0 && ((uintptr_t)u & 15) == 0 &&
+                      ((uintptr_t)w & 15) == 0;
+    static int occ[4][DGS_MAXJ + 1]; // resident workgroups per CU: dot, dot pairs, update, update pairs
+    switch (j) {
+#define MF_CASE(N)                                                                                            \
+    case N:                                                                                                   \
+        if (pair) nb = std::min(nb, resident_blocks(dgs_dot_pair_kernel<N>, &occ[1][N]));                      \
+        else nb = std::min(nb, resident_blocks(dgs_dot_kernel<N>, &occ[0][N]));                                \
+        if (pair) dgs_dot_pair_kernel<N><<<nb, VNT, 0, s>>>(V, ld, u, wd, n, *red);                           \
+        else dgs_dot_kernel<N><<<nb, VNT, 0, s>>>(V, ld, u, wd, n, *red);                                     \
+        break;
+        MF_NV0_CASES(MF_CASE)
+#undef MF_CASE
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dgs_scalars_kernel<<<1, FNT, 0, s>>>(red->partials, nb, j, full ? 1 : 0, H, coef, col);
+    e = hipGetLastError();
+    if (e != hipSuccess || !full) return e;
+    const unsigned g = ew_blocks(n) < VMAXB ? ew_blocks(n) : VMAXB;
+    switch (j) {
+#define MF_CASE(N)                                                                                            \
+    case N:                                                                                                   \
+        if (pair)                                                                                             \
+            dgs_update_pair_kernel<N><<<std::min(g, resident_blocks(dgs_update_pair_kernel<N>, &occ[3][N])), VNT, \
+                                        0, s>>>(V, ld, u, w, n, coef);                                        \
+        else                                                                                                  \
+            dgs_update_kernel<N><<<std::min(g, resident_blocks(dgs_update_kernel<N>, &occ[2][N])), VNT, 0, s>>>( \
+                V, ld, u, w, n, coef);                                                                        \
+        break;
+        MF_NV0_CASES(MF_CASE)
+#undef MF_CASE
+    }
+    return hipGetLastError();
+}
+
+#undef MF_NV0_CASES
 #undef MF_NV_CASES
 
 // ---------------------------------------------------------------------------
