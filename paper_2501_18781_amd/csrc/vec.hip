@@ -10,6 +10,7 @@
 // and become no-ops once the solve is done, so the host only synchronizes to
 // poll convergence.
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -615,22 +616,28 @@ constexpr int DGS_PAIR_MIN = 10; // basis widths from which the passes take elem
 // occupancy times the compute units), cached by the caller per kernel.  The
 // wide passes use 60-170 VGPRs: a grid of exactly one resident round avoids
 // a second, partly filled round that runs alone.
-template <typename K> static unsigned resident_blocks(K kernel, int *cache)
+static int compute_units()
 {
-    static int cus = 0;
-    if (cus <= 0) {
-        int dev = 0, v = 0;
-        cus = (hipGetDevice(&dev) == hipSuccess &&
-               hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-                  ? v
-                  : 256;
+    static std::atomic<int> cus{0};
+    int v = cus.load(std::memory_order_relaxed);
+    if (v <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cus.store(v, std::memory_order_relaxed);
     }
-    if (*cache <= 0) {
-        int b = 0;
+    return v;
+}
+
+template <typename K> static unsigned resident_blocks(K kernel, std::atomic<int> *cache)
+{
+    int b = cache->load(std::memory_order_relaxed);
+    if (b <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, VNT, 0) != hipSuccess || b < 1) b = 1;
-        *cache = b;
+        cache->store(b, std::memory_order_relaxed);
     }
-    return (unsigned)(*cache * cus);
+    return (unsigned)(b * compute_units());
 }
 
 
@@ -645,7 +652,7 @@ hipError_t dgs_step(const double *V, int64_t ld, int j, bool full, double *u, do
     const double *wd = full ? w : u; // a closing step has no new product
     const bool pair = j >= DGS_PAIR_MIN && (ld & 1) == 0 && ((uintptr_t)V & 15) == 0 && ((uintptr_t)u & 15) == 0 &&
                       ((uintptr_t)w & 15) == 0;
-    static int occ[4][DGS_MAXJ + 1]; // resident workgroups per CU: dot, dot pairs, update, update pairs
+    static std::atomic<int> occ[4][DGS_MAXJ + 1]; // resident workgroups per CU: dot, dot pairs, update, update pairs
     switch (j) {
 #define MF_CASE(N)                                                                                            \
     case N:                                                                                                   \
