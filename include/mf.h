@@ -213,7 +213,8 @@ typedef struct {
     int32_t eig_steps;        /* Lanczos steps for lambda_max of D^{-1} A per level */
     double eig_safety;        /* lambda_max = eig_safety * Lanczos estimate */
     const double *lambda_max; /* optional host array, one per level (coarsest first), overriding the estimate */
-    double coarse_rtol;       /* FP64 CG tolerance of the coarse solve */
+    double coarse_rtol;       /* FP64 CG tolerance of the coarse solve (a coarsest level of at most 4 cells
+                                 per direction: of the columns of its inverse, formed at setup) */
     int32_t coarse_maxit;
     int32_t auto_levels;      /* 0: levels down to coarse_cells.  1: level rule -- the first level, from the
                                  finest down, on which the mass term dominates the diagonal,

@@ -743,14 +743,17 @@ __device__ __forceinline__ double wave_total(double v)
     return __shfl(v, 0, 64);
 }
 
-template <int HK>
+// INV: workgroup c solves A x = e_c and writes x as column c of inv (FP64,
+// column-major, n_nodes rows): the columns of A^-1, all solved at once.
+template <int HK, bool INV = false>
 __global__ void __launch_bounds__(BNT) heat_cg_brick_kernel(KMesh m, HeatArgs a, const float *__restrict__ b32,
-                                                            float *__restrict__ x32, double rtol, int maxit)
+                                                            float *__restrict__ x32, double rtol, int maxit,
+                                                            double *__restrict__ inv)
 {
     constexpr int NB = lds_field<double>();
     __shared__ double X[NB], R[NB], P[NB], Q[NB], S[NB], Dv[NB];
     __shared__ double E[27 * BNT];
-    const Brick br(m, threadIdx.x);
+    const Brick br(m, threadIdx.x, 0); // the mesh is one brick, whatever the workgroup (INV: one per column)
     br.stage_nodes<1, double>(m, (const double *)a.phi, S, nullptr, nullptr);
     __syncthreads();
     const double vol = m.hx * m.hy * m.hz;
@@ -773,7 +776,7 @@ __global__ void __launch_bounds__(BNT) heat_cg_brick_kernel(KMesh m, HeatArgs a,
     br.for_owned_nodes(m, [&](int ai, int bi, int ci, int l, int64_t g, bool constrained, int) {
         const double dv = br.node_sum(E, ai, bi, ci);
         const double di = constrained ? 1.0 : 1.0 / dv;
-        const double bv = (double)b32[g];
+        const double bv = INV ? (g == (int64_t)blockIdx.x ? 1.0 : 0.0) : (double)b32[g];
         Dv[l] = di;
         X[l] = 0.0;
         R[l] = bv;
@@ -821,7 +824,10 @@ __global__ void __launch_bounds__(BNT) heat_cg_brick_kernel(KMesh m, HeatArgs a,
         rz = rzn;
         br.for_owned_nodes(m, [&](int, int, int, int l, int64_t, bool, int) { P[l] = Q[l] + beta * P[l]; });
     }
-    br.for_owned_nodes(m, [&](int, int, int, int l, int64_t g, bool, int) { x32[g] = (float)X[l]; });
+    br.for_owned_nodes(m, [&](int, int, int, int l, int64_t g, bool, int) {
+        if constexpr (INV) inv[(int64_t)blockIdx.x * m.NX * m.NY * m.NZ + g] = X[l];
+        else x32[g] = (float)X[l];
+    });
 }
 
 bool heat_fits_one_brick(const KMesh &m) { return m.nx <= BB && m.ny <= BB && m.nz <= BB; }
@@ -830,8 +836,17 @@ hipError_t heat_cg_one_brick(const KMesh &m, const HeatArgs &a, const float *b32
                              hipStream_t s)
 {
     if (!heat_fits_one_brick(m) || a.mode != 0) return hipErrorInvalidValue;
-    if (a.hkind == 1) heat_cg_brick_kernel<1><<<1, BNT, 0, s>>>(m, a, b32, x32, rtol, maxit);
-    else heat_cg_brick_kernel<0><<<1, BNT, 0, s>>>(m, a, b32, x32, rtol, maxit);
+    if (a.hkind == 1) heat_cg_brick_kernel<1><<<1, BNT, 0, s>>>(m, a, b32, x32, rtol, maxit, nullptr);
+    else heat_cg_brick_kernel<0><<<1, BNT, 0, s>>>(m, a, b32, x32, rtol, maxit, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t heat_inverse_one_brick(const KMesh &m, const HeatArgs &a, double *inv, double rtol, int maxit, hipStream_t s)
+{
+    if (!heat_fits_one_brick(m) || a.mode != 0) return hipErrorInvalidValue;
+    const unsigned nn = (unsigned)(m.NX * m.NY * m.NZ);
+    if (a.hkind == 1) heat_cg_brick_kernel<1, true><<<nn, BNT, 0, s>>>(m, a, nullptr, nullptr, rtol, maxit, inv);
+    else heat_cg_brick_kernel<0, true><<<nn, BNT, 0, s>>>(m, a, nullptr, nullptr, rtol, maxit, inv);
     return hipGetLastError();
 }
 

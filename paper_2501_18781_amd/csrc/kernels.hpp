@@ -97,6 +97,11 @@ hipError_t heat_qp_coeffs(const KMesh &m, const HeatArgs &a, double *kq, double 
 bool heat_fits_one_brick(const KMesh &m);
 hipError_t heat_cg_one_brick(const KMesh &m, const HeatArgs &a, const float *b32, float *x32, double rtol, int maxit,
                              hipStream_t s);
+// A^-1 of a one-brick heat operator (the coarsest multigrid level): column c
+// solved by the same CG from e_c, all columns in one launch; inv is FP64,
+// n_nodes x n_nodes, column-major.
+hipError_t heat_inverse_one_brick(const KMesh &m, const HeatArgs &a, double *inv, double rtol, int maxit,
+                                  hipStream_t s);
 hipError_t quad_points(const KMesh &m, double *xq, hipStream_t s);
 // diag(A) (Dirichlet rows 1); with invert its reciprocals (the Jacobi preconditioner).
 hipError_t heat_diagonal(const KMesh &m, const HeatArgs &a, int fp32, void *diag, void *face, hipStream_t s,

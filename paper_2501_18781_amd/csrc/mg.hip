@@ -405,6 +405,7 @@ struct mf_mg {
     std::vector<MGLevel> L; // 0 = coarsest
     bool smooth_coarsest = false;          // the coarsest level is smoothed, not solved (level rule)
     double *b64 = nullptr, *x64 = nullptr; // coarse FP64 right-hand side and solution
+    double *cinv = nullptr;                // A^-1 of a one-brick coarsest level (FP64, column-major)
 };
 
 static mf_status mg_fail(mf_mg *mg, mf_status st, const char *msg)
@@ -427,12 +428,49 @@ static void level_free(MGLevel &l)
     l = MGLevel();
 }
 
+// x = A^-1 b on a one-brick coarsest level (n <= 729 nodes): workgroup r0
+// takes rows r0 .. r0 + 63; its 16 wavefronts split the columns (every
+// 16th), each reading 64 consecutive entries of a column per load and
+// keeping four loads in flight.
+constexpr int CINV_MAXN = 729, CINV_WAVES = 16;
+__global__ void __launch_bounds__(64 * CINV_WAVES) coarse_inverse_apply_kernel(const double *__restrict__ inv, int n,
+                                                                               const float *__restrict__ b,
+                                                                               float *__restrict__ x)
+{
+    constexpr int S = CINV_WAVES;
+    __shared__ double bs[CINV_MAXN];
+    __shared__ double part[S][64];
+    for (int c = threadIdx.x; c < n; c += 64 * S) bs[c] = (double)b[c];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = blockIdx.x * 64 + lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (r < n) {
+        const double *col = inv + r;
+        int c = w;
+        for (; c + 3 * S < n; c += 4 * S) {
+            a0 += col[(int64_t)c * n] * bs[c];
+            a1 += col[(int64_t)(c + S) * n] * bs[c + S];
+            a2 += col[(int64_t)(c + 2 * S) * n] * bs[c + 2 * S];
+            a3 += col[(int64_t)(c + 3 * S) * n] * bs[c + 3 * S];
+        }
+        for (; c < n; c += S) a0 += col[(int64_t)c * n] * bs[c];
+    }
+    part[w][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (w == 0 && r < n) {
+        double v = 0.0;
+        for (int k = 0; k < S; ++k) v += part[k][lane];
+        x[r] = (float)v;
+    }
+}
+
 static void mg_free(mf_mg *mg)
 {
     if (!mg) return;
     for (MGLevel &l : mg->L) level_free(l);
     if (mg->b64) (void)hipFree(mg->b64);
     if (mg->x64) (void)hipFree(mg->x64);
+    if (mg->cinv) (void)hipFree(mg->cinv);
     delete mg;
 }
 
@@ -605,6 +643,22 @@ mf_status mf_mg_create(mf_ctx *c, const mf_operator *op, const mf_mg_params *prm
         mg_free(mg);
         return fail(c, MF_ERR_OOM, "multigrid allocation failed");
     }
+    // A one-brick coarsest level that is solved, not smoothed, keeps A^-1:
+    // its columns are solved once here by the coarse CG to coarse_rtol, and
+    // every coarse solve is then one dense product (a few microseconds
+    // instead of a CG of tens of iterations in one workgroup).
+    if (!mg->smooth_coarsest && heat_fits_one_brick(co.ctx->km) && co.nn <= CINV_MAXN) {
+        if (hipMalloc((void **)&mg->cinv, sizeof(double) * co.nn * co.nn) != hipSuccess) {
+            mg_free(mg);
+            return fail(c, MF_ERR_OOM, "multigrid allocation failed");
+        }
+        const hipError_t e = heat_inverse_one_brick(co.ctx->km, heat_args(&co.op64), mg->cinv, prm->coarse_rtol,
+                                                    prm->coarse_maxit, s);
+        if (e != hipSuccess) {
+            mg_free(mg);
+            return fail(c, MF_ERR_HIP, "coarse inverse: %s", hipGetErrorString(e));
+        }
+    }
     if (hipStreamSynchronize(s) != hipSuccess) {
         mg_free(mg);
         return fail(c, MF_ERR_HIP, "multigrid setup failed");
@@ -662,13 +716,20 @@ static mf_status cheb_smooth(mf_mg *mg, MGLevel &l, const float *b, float *x, bo
     return MF_OK;
 }
 
-// x_l = V_l(b_l): recursive V-cycle, level 0 solved by FP64 CG.
+// x_l = V_l(b_l): recursive V-cycle, level 0 solved by FP64 CG (a one-brick
+// level by its inverse, formed by that CG at setup).
 static mf_status vcycle(mf_mg *mg, int li, hipStream_t s)
 {
     MGLevel &l = mg->L[li];
     mf_status st;
     if (li == 0 && mg->smooth_coarsest) return cheb_smooth(mg, l, l.b, l.x, true, s);
     if (li == 0) {
+        if (mg->cinv) {
+            coarse_inverse_apply_kernel<<<(unsigned)((l.nn + 63) / 64), 64 * CINV_WAVES, 0, s>>>(mg->cinv, (int)l.nn,
+                                                                                            l.b, l.x);
+            MGCHK(mg, hipGetLastError());
+            return MF_OK;
+        }
         if (heat_fits_one_brick(l.ctx->km)) {
             MGCHK(mg, heat_cg_one_brick(l.ctx->km, heat_args(&l.op64), l.b, l.x, mg->prm.coarse_rtol,
                                         mg->prm.coarse_maxit, s));
