@@ -146,6 +146,27 @@ def test_conv_gmres_jacobi_matches_oracle(gpu):
     assert info.converged and relerr(x, O.direct_solve(A.T.tocsr(), bt)) <= 1e-10
 
 
+@pytest.mark.parametrize("restart", [3, 5])
+def test_conv_gmres_short_restarts_match_oracle(gpu, restart):
+    # 28-50 restart cycles, each ended by a closing Arnoldi step that only
+    # completes the cycle's last Hessenberg column; the oracle takes modified
+    # Gram-Schmidt, so the counts agree up to rounding near the threshold
+    mesh, p, phi, u0 = conv_case((5, 4, 6), W.ALL_FACES, dt=1e-1)
+    A = O.heat_matrix(mesh, p, phi=phi, u0=u0)
+    b = A @ W.uniform(11, mesh.n_nodes)
+    dinv = 1.0 / A.diagonal()
+    ref = O.gmres(A, b, lambda v: dinv * v, restart, 1e-10)
+    ctx = mf.Context(mesh)
+    op = mf.heat_operator(ctx, p, phi=dev(phi), u0=dev(u0))
+    x = torch.empty_like(dev(b))
+    info = mf.gmres_solve(op, dev(b), x, 1e-10, 5000, precond=mf.MF_PC_JACOBI, restart=restart)
+    print(info, ref.iters, flush=True)
+    assert info.converged and info.rel_res <= 1e-10 and abs(info.iters - ref.iters) <= 3
+    # the oracle's own iterate is 7.1e-10 (restart 3) and 7.2e-10 (restart 5) from the direct solution
+    xs = O.direct_solve(A, b)
+    assert float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)) <= 1e-8
+
+
 def test_conv_operator_argument_errors(gpu):
     mesh, p, phi, u0 = conv_case((4, 4, 4), W.ALL_FACES)
     ctx = mf.Context(mesh)

@@ -186,6 +186,24 @@ def test_gmres_full_cycles_unpreconditioned(gpu):
     assert normerr(x, O.direct_solve(A, b)) <= 1e-5
 
 
+@pytest.mark.parametrize("restart", [4, 7])
+def test_gmres_block_jacobi_short_restarts_match_oracle(gpu, restart):
+    # 6-11 restart cycles with point-block Jacobi; each cycle ends with a
+    # closing Arnoldi step that only completes its last Hessenberg column
+    mesh, p, phi, u0 = case((5, 5, 4), W.ALL_FACES)
+    A = O.oseen_matrix(mesh, p, phi, u0)
+    b = A @ W.uniform(12, 3 * mesh.n_nodes)
+    ref = O.gmres(A, b, O.block_jacobi(A, mesh.n_nodes), restart, 1e-10)
+    ctx = mf.Context(mesh)
+    op = mf.oseen_operator(ctx, p, dev(phi), dev(u0))
+    x = torch.empty_like(dev(b))
+    info = mf.gmres_solve(op, dev(b), x, 1e-10, 5000, precond=mf.MF_PC_BLOCK_JACOBI, restart=restart)
+    print(info, ref.iters, flush=True)
+    assert info.converged and info.rel_res <= 1e-10 and abs(info.iters - ref.iters) <= 3
+    # the oracle's own iterate is 8.3e-10 (restart 4) and 4.2e-10 (restart 7) from the direct solution
+    assert normerr(x, O.direct_solve(A, b)) <= 1e-8
+
+
 @pytest.mark.parametrize("restart,maxit", [(1, 3), (2, 3), (2, 4), (5, 7)])
 def test_gmres_iteration_limit(gpu, restart, maxit):
     # the limit stops GMRES after exactly maxit Arnoldi steps, also when it
