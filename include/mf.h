@@ -193,7 +193,8 @@ mf_status mf_cg_solve(mf_ctx *ctx, const mf_operator *op, int32_t precond, const
                       double rtol, int32_t maxit, mf_solve_info *info, mf_stream stream);
 
 /* Right-preconditioned restarted GMRES(restart), x0 = 0, with classical
- * Gram-Schmidt and one re-orthogonalization pass and Givens rotations.
+ * Gram-Schmidt and one re-orthogonalization pass (taken one Arnoldi step
+ * late, two passes over the basis per step) and Givens rotations.
  * precond: MF_PC_NONE, MF_PC_JACOBI, or MF_PC_BLOCK_JACOBI (inverse 3x3 nodal
  * blocks, Oseen).  transpose != 0 solves A^T x = b.  Stops when the residual
  * estimate is <= rtol ||b|| and the true residual confirms it.  restart is
